@@ -1,0 +1,108 @@
+"""Static RPA polarizability as a brute-force band-pair sum (oracle; test infrastructure).
+
+Definition used (Eq. chi1 with the k-discretised Green's function of Sec. VI.D,
+N_k^-1 per g, spin sum -> factor s):
+
+    chi0(r, r') = -(2 s / N_k^2) sum_{k,k'} sum_{n occ} sum_{m unocc}
+                  Re[ psi_nk*(r) psi_mk'(r) psi_mk'*(r') psi_nk(r') ] * K_{nk,mk'}
+
+with K = 1/(e_mk' - e_nk) (the exact result of the imaginary-axis integral for
+one band pair; pairs on the same side of mu integrate to zero) or a quadrature
+kernel K = sum_l c_l alpha_l(nk) beta_l(mk') from ``oracle.quadrature``.
+
+Pair densities rho_nm(p) = psi_n*(p) psi_m(p) make the sum a product of
+(rows x pairs) and (pairs x cols) matrices; nothing is factored further.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import quadrature as q
+
+
+def exact_kernel(E, nocc, mu=None, delta=0.0):
+    """Returns kernel(k, kp) -> [nocc, nunocc] array of 1/(x_nk + y_mkp)."""
+    if mu is None:
+        mu = q.mid_gap(E, nocc)
+    x, y = q.offsets(E, nocc, mu, delta)
+
+    def K(k, kp):
+        return 1.0 / (x[k][:, None] + y[kp][None, :])
+    return K
+
+
+def quad_kernel(c, alpha, beta):
+    def K(k, kp):
+        return q.kernel(c, alpha, beta, k, kp)
+    return K
+
+
+def pair_sum(psi_rows, psi_cols, nocc, spin, kern, nblock=16):
+    """chi0 over all rows x cols.  psi_*: complex [nk, nb, npts]; returns float64 [nrows, ncols].
+
+    Also returns the largest |Im| of the same sum taken without the real part; it
+    vanishes for time-reversal-symmetric orbitals on k-sets closed under k -> -k,
+    where the full band sum is real before the real part is taken."""
+    nk = psi_rows.shape[0]
+    nr, nc = psi_rows.shape[2], psi_cols.shape[2]
+    acc = np.zeros((nr, nc), dtype=np.complex128)
+    for k in range(nk):
+        for kp in range(nk):
+            Kmat = kern(k, kp)                                   # [nocc, nu]
+            for n0 in range(0, nocc, nblock):
+                n1 = min(nocc, n0 + nblock)
+                # rho[r, n, m] = conj(psi_nk(r)) psi_mkp(r)
+                rr = np.conj(psi_rows[k, n0:n1, :])[:, None, :] * psi_rows[kp, None, nocc:, :]
+                rc = np.conj(psi_cols[k, n0:n1, :])[:, None, :] * psi_cols[kp, None, nocc:, :]
+                rr = rr * Kmat[n0:n1, :, None]
+                nu = rr.shape[1]
+                acc += rr.reshape((n1 - n0) * nu, nr).T @ np.conj(rc.reshape((n1 - n0) * nu, nc))
+    pref = -2.0 * spin / nk ** 2
+    return pref * acc.real, float(np.abs(acc.imag).max() * abs(pref))
+
+
+def chi0_exact(psi_rows, psi_cols, E, nocc, spin=2, mu=None, delta=0.0):
+    return pair_sum(psi_rows, psi_cols, nocc, spin, exact_kernel(E, nocc, mu, delta))[0]
+
+
+def chi0_quad(psi_rows, psi_cols, nocc, spin, c, alpha, beta):
+    return pair_sum(psi_rows, psi_cols, nocc, spin, quad_kernel(c, alpha, beta))[0]
+
+
+def pair_sum_entries(psi_r, psi_c, nocc, spin, kern):
+    """chi0 at individual entries: psi_r, psi_c complex [nk, nb, E] hold the orbitals at the
+    row point and the column point of each entry; returns float64 [E]."""
+    nk = psi_r.shape[0]
+    out = np.zeros(psi_r.shape[2], dtype=np.complex128)
+    for k in range(nk):
+        a = np.conj(psi_r[k, :nocc]) * psi_c[k, :nocc]               # [nocc, E]
+        for kp in range(nk):
+            b = psi_r[kp, nocc:] * np.conj(psi_c[kp, nocc:])         # [nu, E]
+            Kmat = kern(k, kp)
+            out += np.einsum("ne,ne->e", a, Kmat @ b)
+    return -2.0 * spin / nk ** 2 * out.real
+
+
+def chi0_exact_entries(psi_r, psi_c, E, nocc, spin=2, mu=None, delta=0.0):
+    return pair_sum_entries(psi_r, psi_c, nocc, spin, exact_kernel(E, nocc, mu, delta))
+
+
+def chi0_quad_entries(psi_r, psi_c, nocc, spin, c, alpha, beta):
+    return pair_sum_entries(psi_r, psi_c, nocc, spin, quad_kernel(c, alpha, beta))
+
+
+def terms_for(E, nocc, kind, n, scale=None, mu=None, delta=0.0):
+    """Quadrature terms for band energies E: kind 'time' (imaginary time) or 'freq' (paper)."""
+    if mu is None:
+        mu = q.mid_gap(E, nocc)
+    x, y = q.offsets(E, nocc, mu, delta)
+    if kind == "time":
+        if scale is None or scale <= 0:
+            scale = q.auto_scale(x, y, n)
+        c, al, be, _ = q.imag_time_terms(x, y, n, scale)
+        return c, al, be
+    if kind == "freq":
+        z = q.zeta(E, mu, metallic=delta > 0) if scale is None or scale <= 0 else scale
+        c, al, be, _ = q.freq_terms(x, y, n, z)
+        return c, al, be
+    raise ValueError(kind)

@@ -1,0 +1,105 @@
+"""Reference gradients of the test-charge loss (oracle; test infrastructure).
+
+Loss: L = sum_sites rho_L^T D W D rho_L with W from the site x site chi0 block
+(``oracle.screen``).  Back through the solve, dL/dX = D W^T Gbar W^T D with
+Gbar = (D rho_L)(D rho_L)^T, so on the site points the sensitivity
+Lambda = dL/dchi0 = P^T (dL/dX) P is the rank-one g g^T with
+g = P^T D W D rho_L (W symmetric).
+
+With P_f = -2 s / N_k^2 and, per site, the band-pair matrix element
+    M_{nk,mk'} = sum_p g(p) psi_nk*(p) psi_mk'(p),
+the loss's dependence on chi0 is Q = P_f sum |M|^2 K_{nk,mk'} and
+    dL/de_nk  = P_f sum_{m,k'} |M|^2 dK/de_nk
+    dL/de_mk' = P_f sum_{n,k}  |M|^2 dK/de_mk'
+    grad psi_nk(p)  = 2 P_f g(p) sum_{m,k'} conj(M) K psi_mk'(p)
+    grad psi_mk'(p) = 2 P_f g(p) sum_{n,k}  M K psi_nk(p)
+(complex gradients as dL/dRe + i dL/dIm).  Exact denominators: K = 1/Delta,
+dK/de_n = 1/Delta^2, dK/de_m = -1/Delta^2.  Imaginary-time terms with mu and
+the nodes held fixed: dK/de_n = sum_l c_l tau_l alpha beta, dK/de_m = -that.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import chi0 as cz
+from . import quadrature as q
+from . import screen as sc
+
+
+def site_slices(sites):
+    o, out = 0, []
+    for s in sites:
+        out.append(slice(o, o + s.npts))
+        o += s.npts
+    return out
+
+
+def loss(psi_site, E, nocc, spin, sites, rho, kern, lmax=2):
+    """Test-charge loss and the per-site W; kern as in oracle.chi0."""
+    total, Ws = 0.0, []
+    for s, sl in zip(sites, site_slices(sites)):
+        ps = psi_site[:, :, sl]
+        chi = cz.pair_sum(ps, ps, nocc, spin, kern)[0]
+        W = sc.screen_W(chi, s, lmax)
+        Ws.append(W)
+        total += sc.test_charge_loss(W, rho[sl], s, lmax)
+    return total, Ws
+
+
+def _kernels_exact(E, nocc, mu, delta):
+    x, y = q.offsets(E, nocc, mu, delta)
+    if delta > 0:
+        raise NotImplementedError("reference gradient with delta > 0")
+
+    def K(k, kp):
+        d = x[k][:, None] + y[kp][None, :]
+        return 1.0 / d, 1.0 / d ** 2, -1.0 / d ** 2
+    return K
+
+
+def _kernels_time(E, nocc, mu, n, scale):
+    x, y = q.offsets(E, nocc, mu)
+    c, al, be, tau = q.imag_time_terms(x, y, n, scale)
+
+    def K(k, kp):
+        base = np.einsum("l,ln,lm->nm", c, al[:, k], be[:, kp])
+        d = np.einsum("l,ln,lm->nm", c * tau, al[:, k], be[:, kp])
+        return base, d, -d
+    return K
+
+
+def loss_and_grads(psi_site, E, nocc, spin, sites, rho, kind="exact", n_terms=None,
+                   scale=None, lmax=2):
+    """Returns (loss, dL/dE [nk, nb], dL/dpsi_site complex [nk, nb, npts])."""
+    mu = q.mid_gap(E, nocc)
+    if kind == "exact":
+        kfun = _kernels_exact(E, nocc, mu, 0.0)
+        kern = cz.exact_kernel(E, nocc, mu)
+    elif kind == "time":
+        kfun = _kernels_time(E, nocc, mu, n_terms, scale)
+        c, al, be = cz.terms_for(E, nocc, "time", n_terms, scale, mu)
+        kern = cz.quad_kernel(c, al, be)
+    else:
+        raise ValueError(kind)
+    L, Ws = loss(psi_site, E, nocc, spin, sites, rho, kern, lmax)
+    nk = E.shape[0]
+    Pf = -2.0 * spin / nk ** 2
+    dE = np.zeros_like(E)
+    dpsi = np.zeros_like(psi_site)
+    for s, sl, W in zip(sites, site_slices(sites), Ws):
+        Wsym = 0.5 * (W + W.T)
+        d = sc.radial_weights(s, lmax)
+        rl = sc.charge_moments(rho[sl], s, lmax)
+        g = sc.projector(s, lmax).T @ (d * (Wsym @ (d * rl)))
+        po = psi_site[:, :nocc, sl]
+        pu = psi_site[:, nocc:, sl]
+        for k in range(nk):
+            for kp in range(nk):
+                M = (np.conj(po[k]) * g[None, :]) @ pu[kp].T          # [nocc, nu]
+                Km, dKn, dKm = kfun(k, kp)
+                M2 = (M * np.conj(M)).real
+                dE[k, :nocc] += Pf * (M2 * dKn).sum(1)
+                dE[kp, nocc:] += Pf * (M2 * dKm).sum(0)
+                dpsi[k, :nocc, sl] += 2 * Pf * g[None, :] * ((np.conj(M) * Km) @ pu[kp])
+                dpsi[kp, nocc:, sl] += 2 * Pf * g[None, :] * ((M * Km).T @ po[k])
+    return L, dE, dpsi

@@ -1,0 +1,336 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: adaptive
+numerical integration, a plane-wave closed form, brute-force loops, exact
+invariants of the static RPA polarizability (symmetry, sign, sum rule, gauge,
+translation, k-set replication), the push-through identity between the two
+forms of W in the paper, and finite differences of the loss.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy import integrate
+
+from oracle import chi0 as cz
+from oracle import grads as gr
+from oracle import quadrature as q
+from oracle import screen as sc
+from tests.conftest import workload
+from workloads import configs, sites as sx
+
+
+# --------------------------------------------------------------------------- quadrature
+@pytest.mark.parametrize("x,y", [(0.02, 0.03), (0.3, 1.7), (1.0, 0.05)])
+def test_pair_identity_adaptive_integration(x, y):
+    """Per band pair, the imaginary-axis integral of Eq. chi1 gives -1/(x+y); both separable
+    integrands used by the rules integrate to 1/(x+y) (scipy adaptive quadrature)."""
+    full = integrate.quad(lambda t: ((x * y + t * t) / ((x * x + t * t) * (y * y + t * t))),
+                          0, np.inf, epsabs=0, epsrel=1e-13, limit=500)[0] / math.pi
+    time = integrate.quad(lambda s: math.exp(-(x + y) * s), 0, np.inf, epsabs=0, epsrel=1e-13)[0]
+    # the complex integrand of Eq. chi1 over the whole imaginary axis, integrated numerically
+    re = integrate.quad(lambda t: (1.0 / ((x + 1j * t) * (-y + 1j * t))).real, -np.inf, np.inf,
+                        epsabs=0, epsrel=1e-13, limit=500)[0] / (2 * math.pi)
+    im = integrate.quad(lambda t: (1.0 / ((x + 1j * t) * (-y + 1j * t))).imag, -np.inf, np.inf,
+                        epsabs=1e-14, limit=500)[0]
+    assert abs(full * (x + y) - 1) < 1e-11
+    assert abs(time * (x + y) - 1) < 1e-11
+    assert abs(re * (x + y) + 1) < 1e-10
+    assert abs(im) < 1e-10
+    # same-sign pairs integrate to zero
+    same = integrate.quad(lambda t: (1.0 / ((x + 1j * t) * (y + 1j * t))).real, -np.inf, np.inf,
+                          epsabs=1e-13, limit=500)[0]
+    assert abs(same) < 1e-9
+
+
+@pytest.mark.parametrize("kind", ["time", "freq"])
+def test_rules_converge_to_adaptive_integral(kind):
+    """The oracle's separable rules approach the adaptively integrated 1/(x+y), with the
+    error shrinking as nodes are added, at R = Dmax/Dmin = 50."""
+    xs = np.array([[0.025, 0.1, 0.6]])
+    ys = np.array([[0.025, 0.3, 0.65]])
+    ref = np.array([[integrate.quad(lambda s: math.exp(-(a + b) * s), 0, np.inf, epsrel=1e-14)[0]
+                     for b in ys[0]] for a in xs[0]])
+    errs = []
+    for n in (8, 16, 32):
+        if kind == "time":
+            c, al, be, _ = q.imag_time_terms(xs, ys, n, q.auto_scale(xs, ys, n))
+        else:
+            E = np.concatenate([-xs, ys], 1)
+            c, al, be, _ = q.freq_terms(xs, ys, n, q.zeta(E, 0.0))
+        K = q.kernel(c, al, be, 0, 0)
+        assert np.all(c >= 0) and np.all(al >= 0) and np.all(be >= 0)
+        errs.append(np.abs(K / ref - 1).max())
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 1e-9
+
+
+def test_gauss_legendre_01_exact_for_polynomials():
+    a, w = q.gauss_legendre_01(8)
+    for p in range(16):
+        assert abs((w * a ** p).sum() - 1.0 / (p + 1)) < 1e-14
+
+
+def test_time_rule_scale_choice_is_optimal_on_scan():
+    x = np.array([[0.03, 0.2, 0.9]])
+    y = np.array([[0.02, 0.5, 1.1]])
+    s = q.auto_scale(x, y, 16)
+    e0 = q.imag_time_error(s, 16, 0.05, 2.0)
+    for f in (0.5, 0.8, 1.25, 2.0):
+        assert q.imag_time_error(s * f, 16, 0.05, 2.0) >= e0 * 0.999
+
+
+# --------------------------------------------------------------------------- chi0 structure
+def _brute_chi0(psi_r, psi_c, E, nocc, spin):
+    """Six nested loops over the definition (tiny sizes only)."""
+    nk, nb, nr = psi_r.shape
+    nc = psi_c.shape[2]
+    mu = 0.5 * (E[:, :nocc].max() + E[:, nocc:].min())
+    out = np.zeros((nr, nc))
+    for i in range(nr):
+        for j in range(nc):
+            s = 0.0
+            for k in range(nk):
+                for kp in range(nk):
+                    for n in range(nocc):
+                        for m in range(nocc, nb):
+                            v = (np.conj(psi_r[k, n, i]) * psi_r[kp, m, i]
+                                 * np.conj(psi_c[kp, m, j]) * psi_c[k, n, j])
+                            s += v.real / (E[kp, m] - E[k, n])
+            out[i, j] = -2 * spin / nk ** 2 * s
+    assert mu is not None
+    return out
+
+
+def test_pair_sum_matches_brute_force_loops():
+    rng = np.random.default_rng(7)
+    nk, nb, nocc, nr, nc = 2, 6, 2, 3, 4
+    pr = rng.normal(size=(nk, nb, nr)) + 1j * rng.normal(size=(nk, nb, nr))
+    pc = rng.normal(size=(nk, nb, nc)) + 1j * rng.normal(size=(nk, nb, nc))
+    E = np.sort(rng.uniform(-1, 1, size=(nk, nb)), axis=1)
+    E[:, nocc:] += 2.0
+    got = cz.chi0_exact(pr, pc, E, nocc, spin=2)
+    ref = _brute_chi0(pr, pc, E, nocc, 2)
+    assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+    # and the entry-wise form
+    ent = cz.chi0_exact_entries(pr[:, :, [0, 2, 1]], pc[:, :, [3, 0, 1]], E, nocc, 2)
+    assert np.abs(ent - ref[[0, 2, 1], [3, 0, 1]]).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_free_electron_closed_form():
+    """V = 0 at Gamma: psi = e^{iG.r}/sqrt(Omega), e = |G|^2/2, closed shells on both sides;
+    chi0(r,r') = -(2s/Omega^2) sum_{G occ, G' unocc} cos((G'-G).(r-r')) / (e' - e)."""
+    fe = configs.free_electron()
+    G, E, nocc, omega = fe["G"], fe["E"], fe["nocc"], fe["omega"]
+    pts, gp = fe["pts"], fe["grid_pts"][::37]
+    got = cz.chi0_exact(fe["psi_site"], fe["psi_site"][:, :, :], E, nocc)
+    got_g = cz.chi0_exact(fe["psi_site"], fe["psi_grid"][:, :, ::37], E, nocc)
+    dG = G[None, nocc:, :] - G[:nocc, None, :]                       # [occ, unocc, 3]
+    den = E[0, nocc:][None, :] - E[0, :nocc][:, None]
+
+    def closed(r, rp):
+        d = r[:, None, :] - rp[None, :, :]
+        ph = np.einsum("nmx,ijx->ijnm", dG, d)
+        return -4.0 / omega ** 2 * (np.cos(ph) / den).sum((2, 3))
+    ref = closed(pts, pts)
+    ref_g = closed(pts, gp)
+    assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+    assert np.abs(got_g - ref_g).max() < 1e-12 * np.abs(ref_g).max()
+
+
+def test_replicated_kset_invariance(tiny):
+    """Passing the same k-point twice must leave chi0 unchanged: pins the N_k^-2 factor of the
+    double k-sum (one power per Green's function)."""
+    w = tiny
+    ps = w.psi_site.numpy()[:, :, :40]
+    a = cz.chi0_exact(ps, ps, w.energies, w.nocc)
+    ps2 = np.concatenate([ps, ps])
+    E2 = np.concatenate([w.energies, w.energies])
+    b = cz.chi0_exact(ps2, ps2, E2, w.nocc)
+    assert np.abs(a - b).max() < 1e-13 * np.abs(a).max()
+
+
+def test_structure_tiny(tiny):
+    """Symmetry, vanishing imaginary part, negative semidefiniteness, gauge invariance and
+    the charge sum rule on the cell grid at Gamma."""
+    w = tiny
+    ps = w.psi_site.numpy()
+    pg = w.psi_grid.numpy()
+    kern = cz.exact_kernel(w.energies, w.nocc)
+    ss, im = cz.pair_sum(ps, ps, w.nocc, 2, kern)
+    scale = np.abs(ss).max()
+    assert np.abs(ss - ss.T).max() < 1e-14 * scale
+    assert im < 1e-14 * scale
+    lam = np.linalg.eigvalsh(ss)
+    assert lam.max() <= 1e-12 * abs(lam.min())
+    # gauge: psi_n -> e^{i theta_n} psi_n
+    th = np.random.default_rng(3).uniform(0, 2 * np.pi, size=(1, w.nb, 1))
+    g = cz.chi0_exact(ps * np.exp(1j * th), ps * np.exp(1j * th), w.energies, w.nocc)
+    assert np.abs(g - ss).max() < 1e-13 * scale
+    # sum rule: sum_r' chi0(r, r') dV = 0 (orbitals orthonormal on the alias-free grid)
+    sg = cz.chi0_exact(ps, pg, w.energies, w.nocc)
+    rowsum = sg.sum(1) * w.grid_dV
+    assert np.abs(rowsum).max() < 1e-12 * np.abs(sg).max() * pg.shape[2] * w.grid_dV
+    # NSD of the grid x grid block
+    gg = cz.chi0_exact(pg[:, :, ::5], pg[:, :, ::5], w.energies, w.nocc)
+    lg = np.linalg.eigvalsh(gg)
+    assert lg.max() <= 1e-12 * abs(lg.min())
+
+
+def test_translation_and_mu_independence():
+    """chi0(r+R, r'+R) = chi0(r, r') for a lattice vector R with k-points; the
+    imaginary-time quadrature is independent of mu inside the gap."""
+    w = workload("production", with_grid=False)
+    cr = w.bands.crystal
+    from workloads import crystal as cx
+    pts = w.sites[0].points()[::53]
+    shift = np.array([cr.a, -cr.a, 2 * cr.a])
+    pa = torch.stack([cx.psi_at_points(w.bands, pts, k) for k in range(w.nk)]).numpy()
+    pb = torch.stack([cx.psi_at_points(w.bands, pts + shift, k) for k in range(w.nk)]).numpy()
+    E, nocc = w.energies, w.nocc
+    a = cz.chi0_exact(pa, pa, E, nocc)
+    b = cz.chi0_exact(pb, pb, E, nocc)
+    assert np.abs(a - b).max() < 1e-12 * np.abs(a).max()
+    mu0 = q.mid_gap(E, nocc)
+    gap = E[:, nocc:].min() - E[:, :nocc].max()
+    c1 = cz.chi0_quad(pa, pa, nocc, 2, *cz.terms_for(E, nocc, "time", 16, scale=3.0, mu=mu0))
+    c2 = cz.chi0_quad(pa, pa, nocc, 2, *cz.terms_for(E, nocc, "time", 16, scale=3.0,
+                                                     mu=mu0 + 0.3 * gap))
+    assert np.abs(c1 - c2).max() < 1e-13 * np.abs(c1).max()
+
+
+@pytest.mark.parametrize("kind,n,tol", [("time", 16, 2e-6), ("time", 32, 1e-9), ("freq", 32, 1e-8)])
+def test_quadrature_chi0_converges_to_exact(tiny, kind, n, tol):
+    w = tiny
+    ps = w.psi_site.numpy()
+    ex = cz.chi0_exact(ps, ps, w.energies, w.nocc)
+    c, al, be = cz.terms_for(w.energies, w.nocc, kind, n)
+    qu = cz.chi0_quad(ps, ps, w.nocc, 2, c, al, be)
+    assert np.abs(qu - ex).max() < tol * np.abs(ex).max()
+    lam = np.linalg.eigvalsh(qu)
+    assert lam.max() <= 1e-12 * abs(lam.min())
+
+
+# --------------------------------------------------------------------------- W
+def test_real_ylm_orthonormal_under_lebedev():
+    for n in (26, 50, 110):
+        x, wgt = sx.angular_rule(n)
+        Y = sc.real_ylm(x)
+        S = (Y * wgt[None, :]) @ Y.T
+        assert np.abs(S - np.eye(9)).max() < 1e-13
+
+
+def test_real_ylm_values_against_scipy():
+    from scipy.special import sph_harm_y
+    rng = np.random.default_rng(1)
+    v = rng.normal(size=(5, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    theta = np.arccos(v[:, 2])
+    phi = np.arctan2(v[:, 1], v[:, 0])
+    Y = sc.real_ylm(v)
+    for l in range(3):
+        for m in range(-l, l + 1):
+            c = sph_harm_y(l, abs(m), theta, phi)
+            if m == 0:
+                ref = c.real
+            elif m > 0:
+                ref = math.sqrt(2) * (-1) ** m * c.real
+            else:
+                ref = math.sqrt(2) * (-1) ** m * c.imag
+            assert np.abs(Y[l * l + l + m] - ref).max() < 1e-13
+
+
+def test_W_special_cases(tiny):
+    site = tiny.sites[0]
+    n = site.npts
+    V = sc.coulomb(site)
+    assert np.abs(sc.screen_W(np.zeros((n, n)), site) - V).max() == 0.0
+    # one shell, isotropic chi0: only the L = 00 channel is non-zero -> scalar solve
+    one = sx.make_site(np.zeros(3), 1, 26, r_max=1.5)
+    chi = -0.3 * np.ones((26, 26))
+    W = sc.screen_W(chi, one, lmax=2)
+    x00 = (one.ang_w.sum() / (2 * math.sqrt(math.pi))) ** 2 * -0.3
+    v00 = 4 * math.pi / 1.5
+    u = one.rad_w[0]
+    assert abs(W[0, 0] - v00 / (1 - v00 * u * x00 * u)) < 1e-13 * v00
+    assert np.abs(W[1:, 1:] - V[1:, 1:] if False else W[1:, 1:] - sc.coulomb(one)[1:, 1:]).max() < 1e-13
+
+
+def test_W_push_through_and_screening_bound(tiny):
+    w = tiny
+    ps = w.psi_site.numpy()
+    site = w.sites[0]
+    chi = cz.chi0_exact(ps, ps, w.energies, w.nocc)
+    W1 = sc.screen_W(chi, site)
+    W2 = sc.screen_W_via_chi(chi, site)
+    assert np.abs(W1 - W2).max() < 1e-12 * np.abs(W1).max()
+    assert np.abs(W1 - W1.T).max() < 1e-12 * np.abs(W1).max()
+    rho = w.rho_test
+    Lw = sc.test_charge_loss(W1, rho, site)
+    Lv = sc.test_charge_loss(sc.coulomb(site), rho, site)
+    assert 0 < Lw <= Lv
+
+
+def test_gaussian_self_energy_converges():
+    """A unit Gaussian (sigma 0.5) at the site centre: rho^T D V D rho -> 1/(sigma sqrt(pi))."""
+    sig = 0.5
+    errs = []
+    for nr in (40, 160):
+        s = sx.make_site(np.zeros(3), nr, 26, r_max=4.0)
+        r2 = (s.points() ** 2).sum(1)
+        rho = (2 * math.pi * sig ** 2) ** -1.5 * np.exp(-r2 / (2 * sig ** 2))
+        e = sc.test_charge_loss(sc.coulomb(s), rho, s)
+        errs.append(abs(e - 1 / (sig * math.sqrt(math.pi))))
+    assert errs[1] < errs[0] and errs[1] < 5e-3
+
+
+# --------------------------------------------------------------------------- gradients
+def test_reference_gradients_finite_differences():
+    """Exact-denominator reference gradients vs central differences of the oracle loss
+    (h = 1e-5 Ha for energies; a directional derivative for the orbitals)."""
+    w = workload("tiny")
+    nb = 40
+    E = w.energies[:, :nb].copy()
+    ps = w.psi_site.numpy()[:, :nb, :].copy()
+    sites, rho, nocc = w.sites, w.rho_test, w.nocc
+    kern = lambda EE: cz.exact_kernel(EE, nocc)
+    L, dE, dpsi = gr.loss_and_grads(ps, E, nocc, 2, sites, rho, "exact")
+    h = 1e-5
+    for (k, b) in [(0, 0), (0, 5), (0, 7), (0, 8), (0, 20), (0, 39)]:
+        Ep, Em = E.copy(), E.copy()
+        Ep[k, b] += h
+        Em[k, b] -= h
+        fd = (gr.loss(ps, Ep, nocc, 2, sites, rho, kern(Ep))[0]
+              - gr.loss(ps, Em, nocc, 2, sites, rho, kern(Em))[0]) / (2 * h)
+        assert abs(fd - dE[k, b]) < 1e-6 * np.abs(dE).max() + 1e-9 * abs(L)
+    rng = np.random.default_rng(5)
+    Vd = rng.normal(size=ps.shape) + 1j * rng.normal(size=ps.shape)
+    Vd /= np.abs(Vd).max()
+    hp = 1e-5 * np.abs(ps).max()
+    Lp = gr.loss(ps + hp * Vd, E, nocc, 2, sites, rho, kern(E))[0]
+    Lm = gr.loss(ps - hp * Vd, E, nocc, 2, sites, rho, kern(E))[0]
+    fd = (Lp - Lm) / (2 * hp)
+    an = float(np.real(np.conj(dpsi) * Vd).sum())
+    assert abs(fd - an) < 1e-6 * abs(an)
+
+
+def test_quadrature_gradients_finite_differences():
+    w = workload("tiny")
+    nb = 40
+    E = w.energies[:, :nb].copy()
+    ps = w.psi_site.numpy()[:, :nb, :].copy()
+    sites, rho, nocc = w.sites, w.rho_test, w.nocc
+    n, scale = 16, 4.0
+
+    def Lq(EE, pp):
+        c, al, be = cz.terms_for(EE, nocc, "time", n, scale, mu=q.mid_gap(E, nocc))
+        return gr.loss(pp, EE, nocc, 2, sites, rho, cz.quad_kernel(c, al, be))[0]
+    L, dE, dpsi = gr.loss_and_grads(ps, E, nocc, 2, sites, rho, "time", n, scale)
+    h = 1e-5
+    for (k, b) in [(0, 1), (0, 7), (0, 8), (0, 30)]:
+        Ep, Em = E.copy(), E.copy()
+        Ep[k, b] += h
+        Em[k, b] -= h
+        fd = (Lq(Ep, ps) - Lq(Em, ps)) / (2 * h)
+        assert abs(fd - dE[k, b]) < 1e-6 * np.abs(dE).max()
