@@ -1,0 +1,197 @@
+/*
+ * lrs.h -- C ABI of the local real-space screening library for MI355X (gfx950).
+ *
+ * The library computes the static RPA independent-particle polarizability
+ * chi0(r, r') between the points r of one or more sites and a column point set
+ * (the cell's real-space grid, or the site's own points), summed over
+ * k-points and occupied x unoccupied band pairs (Eq. chi1 with the
+ * k-discretised Green's function of Sec. VI.D), and the per-site screened
+ * Coulomb interaction W = (1 - v chi0)^-1 v in a radial x real-Y_lm basis
+ * (Sec. VI.E, Eqs. reducible and W), plus the adjoints of both.
+ *
+ * The energy denominator is replaced by a quadrature along the imaginary energy
+ * axis (Appendix D.1.b) written as non-negative separable terms
+ *     1/(e_m - e_n) ~= sum_l c_l alpha_l(n) beta_l(m),
+ * so that, with the weighted Green's functions
+ *     G_o^l(r,r') = sum_{k, n occ}   psi_nk*(r) alpha_l(nk) psi_nk(r')
+ *     G_u^l(r,r') = sum_{k, m unocc} psi_mk*(r) beta_l(mk)  psi_mk(r'),
+ *     chi0(r,r') = -(2 s / N_k^2) sum_l c_l Re[ G_o^l(r,r') conj(G_u^l(r,r')) ].
+ * The two Green's functions are dense complex contractions over bands and run
+ * on the matrix cores; the Hadamard product is fused into their epilogue.
+ *
+ * Conventions
+ *  - Every pointer named *_host is host memory; every other array pointer is
+ *    device memory on the context's device.  Complex arrays are complex128
+ *    (interleaved re, im doubles).
+ *  - Calls enqueue work on the context's HIP stream and return without
+ *    synchronising unless stated; results are valid after the stream is
+ *    synchronised.  Inputs may be freed by the caller once the call returned
+ *    and the stream has been synchronised (the library keeps packed copies).
+ *  - Outputs are overwritten, never accumulated into.
+ *  - Errors are return codes; no exception or abort crosses the ABI.  Every
+ *    host-checkable input condition is checked before any work is enqueued,
+ *    so a call that fails leaves the context and all outputs unchanged.
+ *    lrs_last_error() gives a message for the last failed call on a context.
+ *  - One context per stream; a context is not re-entrant.
+ *  - Site points are ordered radial-major inside a site (p = i * n_ang + a,
+ *    position centre + r_i * Omega_a) and sites are concatenated.
+ *  - The W basis index of a site is (L, i), L-major: idx = L * n_rad + i,
+ *    L = l*l + l + m, with the real spherical harmonics
+ *      Y_00 = 1/(2 sqrt(pi)); Y_1,-1 = c1 y, Y_10 = c1 z, Y_11 = c1 x, c1 = sqrt(3/(4 pi));
+ *      Y_2,-2 = c2 x y, Y_2,-1 = c2 y z, Y_20 = c20 (3z^2 - 1), Y_21 = c2 x z,
+ *      Y_22 = c2/2 (x^2 - y^2), c2 = sqrt(15/(4 pi)), c20 = sqrt(5/(16 pi)).
+ */
+#ifndef LRS_H
+#define LRS_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lrs_ctx lrs_ctx;
+
+typedef enum {
+  LRS_OK = 0,
+  LRS_EINVAL = 1,        /* bad argument, shape or pointer */
+  LRS_ENOMEM = 2,        /* device allocation failed or would exceed LRS_MAX_BYTES */
+  LRS_EDEVICE = 3,       /* HIP runtime error, or no gfx950 device */
+  LRS_ESTATE = 4,        /* call out of order (e.g. chi0 before orbitals) */
+  LRS_ENOGAP = 5,        /* some occupied energy is not below every unoccupied one */
+  LRS_ENONFINITE = 6,    /* NaN or Inf in an input */
+  LRS_EUNSUPPORTED = 7   /* valid request this build does not implement */
+} lrs_status;
+
+typedef enum {
+  LRS_FP64 = 0,     /* FP64 matrix-core products, FP64 accumulation */
+  LRS_FP32 = 1,     /* FP32 matrix-core products, FP32 accumulation of G */
+  LRS_BF16X2 = 2,   /* each operand split into bf16 hi + lo; hi*hi + hi*lo + lo*hi, FP32 accumulation */
+  LRS_FP16X2 = 3    /* the same with fp16 halves (operands prescaled by powers of two) */
+} lrs_precision;
+
+typedef enum {
+  LRS_COLS_GRID = 0,   /* columns = the cell grid given to lrs_set_orbitals */
+  LRS_COLS_SITE = 1    /* columns = the same site's points (site x site blocks) */
+} lrs_colset;
+
+typedef enum {
+  LRS_QUAD_TIME = 0,   /* imaginary time: Gauss-Legendre on (0,1), tau = C a/(1-a) */
+  LRS_QUAD_FREQ = 1    /* the paper's single-grid imaginary-frequency rule, 2 terms per node */
+} lrs_quad_kind;
+
+/* Version string of the library build. */
+const char* lrs_version(void);
+
+/* Creates a context on HIP device `device`, enqueuing on `hip_stream` (a hipStream_t;
+ * NULL = the legacy default stream).  Fails with LRS_EDEVICE if the device is not
+ * gfx950 or cannot be initialised.  *ctx is set to NULL on failure. */
+lrs_status lrs_create(lrs_ctx** ctx, int device, void* hip_stream);
+
+/* Synchronises the context's stream and frees every device buffer the context owns. */
+void lrs_destroy(lrs_ctx* ctx);
+
+/* Message of the last failed call on ctx ("" if none).  Valid until the next call. */
+const char* lrs_last_error(const lrs_ctx* ctx);
+
+/* Host-only validation of a band set, usable without a device: nk >= 1,
+ * 1 <= nocc < nb, finite energies, and (delta == 0) a global gap:
+ * min over k of e[k][nocc] > max over k of e[k][nocc-1].  Returns the status
+ * lrs_set_orbitals would return for these energies. */
+lrs_status lrs_check_bands(int nk, int nb, int nocc, const double* energies_host, double mu,
+                           double delta);
+
+/* Band energies and the grid orbitals (Sec. VI.A-D).
+ *   energies_host  [nk][nb] float64, Ha; the lowest nocc bands at every k are occupied.
+ *   mu             chemical potential; NaN = middle of the global gap (Sec. VI.D).
+ *                  With delta == 0 it must lie strictly inside the gap.
+ *   delta          metallic regularisation of Sec. VI.D: |mu - e| -> sqrt((mu - e)^2 + delta^2)
+ *                  in every energy offset (0 = off).
+ *   spin_factor    s in the prefactor -2 s / N_k^2 (2 for a closed shell, 1 per spin channel).
+ *   psi_grid       complex128 [nk][nb][ngrid] on the device, or NULL with ngrid = 0.
+ *   grid_dV        volume element of the grid (kept for the caller; not used by chi0).
+ * Packs psi_grid into the library's operand layouts (FP64 copy kept; reduced-precision
+ * copies are made on first use).  Synchronises the stream to check finiteness
+ * (LRS_ENONFINITE).  Invalidates sites, quadrature and cached plans. */
+lrs_status lrs_set_orbitals(lrs_ctx* ctx, int nk, int nb, int nocc, int spin_factor,
+                            const double* energies_host, double mu, double delta,
+                            const void* psi_grid, int ngrid, double grid_dV);
+
+/* Site geometry and the orbitals at the site points.
+ *   nrad_host, nang_host  [nsites] shell and angular-point counts; npts_s = nrad * nang.
+ *   radii_host, rad_w_host [sum nrad]  radii r_i and radial weights u_i (~ r_i^2 dr).
+ *   ang_xyz_host  [sum nang][3] unit vectors; ang_w_host [sum nang] weights (sum 4 pi).
+ *   psi_site      complex128 [nk][nb][sum npts_s] on the device (same nk, nb as the orbitals).
+ *   lmax          angular cut-off of the W basis, 0 <= lmax <= 2.
+ * Requires lrs_set_orbitals first (LRS_ESTATE).  Synchronises the stream. */
+lrs_status lrs_set_sites(lrs_ctx* ctx, int nsites, const int* nrad_host, const int* nang_host,
+                         const double* radii_host, const double* rad_w_host,
+                         const double* ang_xyz_host, const double* ang_w_host,
+                         const void* psi_site, int lmax);
+
+/* Generic quadrature terms: c_host [nterms] > 0, alpha_host [nterms][nk][nocc] >= 0,
+ * beta_host [nterms][nk][nb-nocc] >= 0, 1 <= nterms <= 128.  The backward pass
+ * is unavailable with generic terms (no derivative is known). */
+lrs_status lrs_set_quadrature(lrs_ctx* ctx, int nterms, const double* c_host,
+                              const double* alpha_host, const double* beta_host);
+
+/* Builds terms from the current energies (Appendix D.1.b):
+ *   LRS_QUAD_TIME: nnodes Gauss-Legendre nodes a_j, w_j on (0,1);
+ *     tau_j = C a_j/(1-a_j), c_j = C w_j/(1-a_j)^2, alpha = exp(-x tau), beta = exp(-y tau),
+ *     x = mu - e_occ, y = e_unocc - mu.  scale > 0 sets C; scale <= 0 picks
+ *     C = kappa / sqrt(Dmin Dmax), kappa = 10^(j/40) (j = -80..100) minimising the worst
+ *     relative error of sum_j c_j exp(-D tau_j) against 1/D over 512 log-spaced D in
+ *     [Dmin, Dmax] (the smallest kappa on ties).
+ *   LRS_QUAD_FREQ: t_j = zeta a_j/(1-a_j), c_j = zeta w_j/(pi (1-a_j)^2); the integrand is
+ *     folded to t > 0 (its value at -t is the conjugate of that at +t), giving two terms per
+ *     node with alpha, beta = x/(x^2+t^2) and t/(x^2+t^2).  scale > 0 sets zeta, else zeta is
+ *     the geometric mean of the smallest and largest |mu - e| (0.5 eV added in quadrature
+ *     to the smallest when delta > 0).
+ * 1 <= nnodes <= 64.  Node positions and mu are constants under differentiation. */
+lrs_status lrs_make_quadrature(lrs_ctx* ctx, int kind, int nnodes, double scale);
+
+/* Reads back the terms in use: c_host [nterms], tau_host [nterms] (tau for LRS_QUAD_TIME,
+ * t for LRS_QUAD_FREQ, 0 for generic), mu and the time scale C / zeta (may be NULL). */
+lrs_status lrs_get_quadrature(const lrs_ctx* ctx, int* nterms, double* c_host, double* tau_host,
+                              double* mu_host, double* scale_host);
+
+/* chi0 for one site (site >= 0) or all sites concatenated (site = -1), in precision prec.
+ *   LRS_COLS_GRID: chi0_out float64 [rows][ngrid], rows = npts of the site (or all sites).
+ *   LRS_COLS_SITE: chi0_out float64 site blocks [npts_s][npts_s], concatenated over sites.
+ * chi0 is real for the static case, so float64 is returned.  Asynchronous. */
+lrs_status lrs_compute_chi0(lrs_ctx* ctx, int site, int cols, int prec, double* chi0_out);
+
+/* Per-site dielectric solve from site x site chi0 blocks (layout of LRS_COLS_SITE, all sites):
+ *   X = P chi0 P^T (P_{(L,i),(i',a)} = delta_ii' w_a Y_L(a)), V_L = 4 pi/(2l+1) r_<^l / r_>^(l+1),
+ *   D = diag(u_i), eps = I - V D X D, W = eps^-1 V (LU with partial pivoting, FP64).
+ *   W_out      float64 [nsites][n][n] with n = (lmax+1)^2 * n_rad of each site, concatenated.
+ *   rho_test   optional float64 [sum npts] test charge at the site points (NULL = none).
+ *   loss_out   optional float64 [nsites]: rho_L^T D W D rho_L, rho_L = P rho (needs rho_test).
+ * Keeps W (and rho_test) for lrs_screen_W_backward.  Asynchronous. */
+lrs_status lrs_screen_W(lrs_ctx* ctx, const double* chi0_sitesite, double* W_out,
+                        const double* rho_test, double* loss_out);
+
+/* Adjoint of lrs_screen_W.  dL_dW float64 [nsites][n][n], or NULL to differentiate
+ * sum(loss_out) of the last lrs_screen_W call with rho_test.  Writes
+ * dL_dchi0_sitesite (site-block layout) = P^T (D W^T Gbar W^T D) P per site.  Asynchronous. */
+lrs_status lrs_screen_W_backward(lrs_ctx* ctx, const double* dL_dW, double* dL_dchi0_sitesite);
+
+/* Adjoint of lrs_compute_chi0 for site x site blocks (cols must be LRS_COLS_SITE, all sites,
+ * LRS_FP64): given dL/dchi0 (site-block layout) writes dL_dE float64 [nk][nb] and
+ * dL_dpsi_site complex128 [nk][nb][sum npts] (complex gradients as dL/dRe + i dL/dIm).
+ * Each term's G_o, G_u are recomputed rather than stored.  Requires terms from
+ * lrs_make_quadrature.  dL_dpsi_grid must be NULL (site blocks do not use grid orbitals). */
+lrs_status lrs_compute_chi0_backward(lrs_ctx* ctx, int cols, const double* dL_dchi0,
+                                     double* dL_dE, void* dL_dpsi_site, void* dL_dpsi_grid);
+
+/* Times the candidate tile configurations of precision prec on the current problem and keeps
+ * the fastest for later lrs_compute_chi0 calls; the choice is cached on disk in the file named
+ * by LRS_TUNE_CACHE (if set), keyed by precision and problem shape.  Synchronous. */
+lrs_status lrs_tune(lrs_ctx* ctx, int prec);
+
+/* Duration in milliseconds of the main kernel of the last lrs_compute_chi0 call, measured
+ * with HIP events on the context's stream (synchronises).  -1 if none. */
+double lrs_last_kernel_ms(lrs_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LRS_H */

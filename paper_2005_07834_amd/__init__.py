@@ -1,0 +1,243 @@
+"""Local real-space RPA screening on MI355X: Python binding of the liblrs C ABI.
+
+Argument marshalling only: every step of the computation runs in the library's HIP
+kernels.  PyTorch supplies device memory and the stream.  The binding refuses to
+work without the built library (no CPU fallback).
+
+Low-level: ``lib`` is the ctypes handle with the C names (``lib.lrs_create`` ...).
+High-level: :class:`Context` wraps one library context on the current torch stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblrs.so")
+
+LRS_OK, LRS_EINVAL, LRS_ENOMEM, LRS_EDEVICE, LRS_ESTATE, LRS_ENOGAP, LRS_ENONFINITE, \
+    LRS_EUNSUPPORTED = range(8)
+FP64, FP32, BF16X2, FP16X2 = range(4)
+COLS_GRID, COLS_SITE = 0, 1
+QUAD_TIME, QUAD_FREQ = 0, 1
+PREC_NAMES = {"fp64": FP64, "fp32": FP32, "bf16x2": BF16X2, "fp16x2": FP16X2}
+STATUS_NAMES = {0: "LRS_OK", 1: "LRS_EINVAL", 2: "LRS_ENOMEM", 3: "LRS_EDEVICE", 4: "LRS_ESTATE",
+                5: "LRS_ENOGAP", 6: "LRS_ENONFINITE", 7: "LRS_EUNSUPPORTED"}
+
+# (name, restype, argtypes) for every entry point of include/lrs.h
+_P, _I, _D, _CS = C.c_void_p, C.c_int, C.c_double, C.c_char_p
+SIGNATURES = [
+    ("lrs_version", _CS, []),
+    ("lrs_create", _I, [C.POINTER(_P), _I, _P]),
+    ("lrs_destroy", None, [_P]),
+    ("lrs_last_error", _CS, [_P]),
+    ("lrs_check_bands", _I, [_I, _I, _I, _P, _D, _D]),
+    ("lrs_set_orbitals", _I, [_P, _I, _I, _I, _I, _P, _D, _D, _P, _I, _D]),
+    ("lrs_set_sites", _I, [_P, _I, _P, _P, _P, _P, _P, _P, _P, _I]),
+    ("lrs_set_quadrature", _I, [_P, _I, _P, _P, _P]),
+    ("lrs_make_quadrature", _I, [_P, _I, _I, _D]),
+    ("lrs_get_quadrature", _I, [_P, C.POINTER(_I), _P, _P, _P, _P]),
+    ("lrs_compute_chi0", _I, [_P, _I, _I, _I, _P]),
+    ("lrs_screen_W", _I, [_P, _P, _P, _P, _P]),
+    ("lrs_screen_W_backward", _I, [_P, _P, _P]),
+    ("lrs_compute_chi0_backward", _I, [_P, _I, _P, _P, _P, _P]),
+    ("lrs_tune", _I, [_P, _I]),
+    ("lrs_last_kernel_ms", _D, [_P]),
+]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(python paper_2005_07834_amd/build.py)")
+    lib = C.CDLL(LIB_PATH)
+    for name, res, args in SIGNATURES:
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+class LrsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, torch.Tensor):
+        return C.c_void_p(x.data_ptr())
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data_as(C.c_void_p)
+    raise TypeError(type(x))
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+def _dev(t, dtype, device):
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(np.asarray(t))
+    return t.to(device=device, dtype=dtype).contiguous()
+
+
+class Context:
+    """One library context on a CUDA (HIP) device, enqueuing on the current torch stream."""
+
+    def __init__(self, device=0):
+        if not torch.cuda.is_available():
+            raise LrsError(LRS_EDEVICE, "no GPU visible to torch")
+        self.device = torch.device("cuda", device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        st = lib.lrs_create(C.byref(h), device, C.c_void_p(self.stream.cuda_stream))
+        if st != LRS_OK:
+            raise LrsError(st, "lrs_create failed")
+        self.h = h
+        self._keep = []
+        self.nsites = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.lrs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != LRS_OK:
+            raise LrsError(st, lib.lrs_last_error(self.h).decode())
+
+    # ------------------------------------------------------------------ inputs
+    def set_orbitals(self, energies, nocc, psi_grid=None, grid_dV=0.0, spin=2, mu=float("nan"),
+                     delta=0.0):
+        E = _host(energies, np.float64)
+        nk, nb = E.shape
+        g = None
+        ngrid = 0
+        if psi_grid is not None:
+            g = _dev(psi_grid, torch.complex128, self.device)
+            assert g.shape[:2] == (nk, nb)
+            ngrid = g.shape[2]
+        self._check(lib.lrs_set_orbitals(self.h, nk, nb, nocc, spin, _ptr(E), mu, delta, _ptr(g),
+                                         ngrid, grid_dV))
+        self.nk, self.nb, self.nocc, self.ngrid = nk, nb, nocc, ngrid
+
+    def set_sites(self, sites, psi_site, lmax=2):
+        nrad = _host([s.n_rad for s in sites], np.int32)
+        nang = _host([s.n_ang for s in sites], np.int32)
+        radii = _host(np.concatenate([s.radii for s in sites]), np.float64)
+        radw = _host(np.concatenate([s.rad_w for s in sites]), np.float64)
+        axyz = _host(np.concatenate([s.ang_xyz for s in sites]), np.float64)
+        angw = _host(np.concatenate([s.ang_w for s in sites]), np.float64)
+        p = _dev(psi_site, torch.complex128, self.device)
+        self._check(lib.lrs_set_sites(self.h, len(sites), _ptr(nrad), _ptr(nang), _ptr(radii),
+                                      _ptr(radw), _ptr(axyz), _ptr(angw), _ptr(p), lmax))
+        self.nsites = len(sites)
+        self.npts = [s.npts for s in sites]
+        self.nbasis = [(lmax + 1) ** 2 * s.n_rad for s in sites]
+
+    def make_quadrature(self, kind=QUAD_TIME, nnodes=16, scale=0.0):
+        self._check(lib.lrs_make_quadrature(self.h, kind, nnodes, scale))
+
+    def set_quadrature(self, c, alpha, beta):
+        c = _host(c, np.float64)
+        a = _host(alpha, np.float64)
+        b = _host(beta, np.float64)
+        self._check(lib.lrs_set_quadrature(self.h, c.shape[0], _ptr(c), _ptr(a), _ptr(b)))
+
+    def get_quadrature(self):
+        n = C.c_int()
+        c = np.zeros(128)
+        tau = np.zeros(128)
+        mu = np.zeros(1)
+        sc = np.zeros(1)
+        self._check(lib.lrs_get_quadrature(self.h, C.byref(n), _ptr(c), _ptr(tau), _ptr(mu),
+                                           _ptr(sc)))
+        return dict(c=c[:n.value].copy(), tau=tau[:n.value].copy(), mu=float(mu[0]),
+                    scale=float(sc[0]))
+
+    # ------------------------------------------------------------------ compute
+    def chi0(self, site=-1, cols=COLS_GRID, prec=FP64, out=None):
+        if isinstance(prec, str):
+            prec = PREC_NAMES[prec]
+        if cols == COLS_GRID:
+            rows = sum(self.npts) if site < 0 else self.npts[site]
+            shape = (rows, self.ngrid)
+        else:
+            sel = self.npts if site < 0 else [self.npts[site]]
+            shape = (sum(n * n for n in sel),)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float64, device=self.device)
+        self._check(lib.lrs_compute_chi0(self.h, site, cols, prec, _ptr(out)))
+        return out
+
+    def site_blocks(self, flat):
+        """Splits the site-block layout into per-site [n, n] views."""
+        out, o = [], 0
+        for n in self.npts:
+            out.append(flat[o:o + n * n].view(n, n))
+            o += n * n
+        return out
+
+    def screen_W(self, chi0_ss, rho=None, want_loss=False):
+        W = torch.empty(sum(n * n for n in self.nbasis), dtype=torch.float64, device=self.device)
+        r = None if rho is None else _dev(rho, torch.float64, self.device)
+        loss = torch.empty(self.nsites, dtype=torch.float64, device=self.device) if want_loss else None
+        self._keep = [r]
+        self._check(lib.lrs_screen_W(self.h, _ptr(chi0_ss.contiguous()), _ptr(W), _ptr(r),
+                                     _ptr(loss)))
+        return W, loss
+
+    def W_blocks(self, flat):
+        out, o = [], 0
+        for n in self.nbasis:
+            out.append(flat[o:o + n * n].view(n, n))
+            o += n * n
+        return out
+
+    def screen_W_backward(self, dL_dW=None):
+        g = torch.empty(sum(n * n for n in self.npts), dtype=torch.float64, device=self.device)
+        d = None if dL_dW is None else dL_dW.contiguous()
+        self._check(lib.lrs_screen_W_backward(self.h, _ptr(d), _ptr(g)))
+        return g
+
+    def chi0_backward(self, dL_dchi0_ss):
+        dE = torch.empty((self.nk, self.nb), dtype=torch.float64, device=self.device)
+        dpsi = torch.empty((self.nk, self.nb, sum(self.npts)), dtype=torch.complex128,
+                           device=self.device)
+        self._check(lib.lrs_compute_chi0_backward(self.h, COLS_SITE, _ptr(dL_dchi0_ss.contiguous()),
+                                                  _ptr(dE), _ptr(dpsi), None))
+        return dE, dpsi
+
+    def tune(self, prec):
+        if isinstance(prec, str):
+            prec = PREC_NAMES[prec]
+        self._check(lib.lrs_tune(self.h, prec))
+
+    def last_kernel_ms(self):
+        return float(lib.lrs_last_kernel_ms(self.h))
+
+
+def check_bands(energies, nocc, mu=float("nan"), delta=0.0):
+    """Host-only validation of a band set; returns the status code."""
+    E = _host(energies, np.float64)
+    return lib.lrs_check_bands(E.shape[0], E.shape[1], nocc, _ptr(E), mu, delta)
+
+
+__all__ = ["lib", "Context", "LrsError", "check_bands", "FP64", "FP32", "BF16X2", "FP16X2",
+           "COLS_GRID", "COLS_SITE", "QUAD_TIME", "QUAD_FREQ", "SIGNATURES"]

@@ -1,0 +1,852 @@
+// C ABI of the screening library: argument validation (host, before any launch), device
+// buffers, lazy operand layouts, quadrature terms, launch plans and timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "lrs_internal.h"
+
+using namespace lrs;
+
+namespace {
+
+const double kHartreeEv = 27.211386245988;
+const double kPi = 3.14159265358979323846;
+
+lrs_status fail(lrs_ctx* ctx, lrs_status st, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return st;
+}
+
+#define HIP_OR_FAIL(ctx, expr)                                                        \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(ctx, LRS_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+  } while (0)
+
+void release(lrs_ctx* ctx, DevBuf& b) {
+  if (b.p) {
+    (void)hipFree(b.p);
+    ctx->bytes_in_use -= b.bytes;
+  }
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+// Allocates (or keeps, if already large enough) a device buffer, honouring LRS_MAX_BYTES.
+lrs_status ensure_buf(lrs_ctx* ctx, DevBuf& b, size_t bytes, const char* what) {
+  bytes = (size_t)round_up((long long)std::max<size_t>(bytes, 256), 256);
+  if (b.p && b.bytes >= bytes) return LRS_OK;
+  release(ctx, b);
+  if (ctx->max_bytes && ctx->bytes_in_use + bytes > ctx->max_bytes)
+    return fail(ctx, LRS_ENOMEM, "%s: %zu bytes would exceed LRS_MAX_BYTES (%zu in use)", what,
+                bytes, ctx->bytes_in_use);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return fail(ctx, LRS_ENOMEM, "%s: hipMalloc of %zu bytes failed", what, bytes);
+  }
+  b.p = p;
+  b.bytes = bytes;
+  ctx->bytes_in_use += bytes;
+  return LRS_OK;
+}
+
+#define CHECK(st)                 \
+  do {                            \
+    lrs_status s_ = (st);         \
+    if (s_ != LRS_OK) return s_;  \
+  } while (0)
+
+bool all_finite(const double* x, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(x[i])) return false;
+  return true;
+}
+
+void drop_plans(lrs_ctx* ctx) {
+  for (auto& kv : ctx->plans) release(ctx, kv.second.tiles);
+  ctx->plans.clear();
+}
+
+void drop_sites(lrs_ctx* ctx) {
+  release(ctx, ctx->site_f64);
+  release(ctx, ctx->site_f32);
+  release(ctx, ctx->site_f32_perm);
+  release(ctx, ctx->psi_site_f64);
+  for (auto& b : ctx->site_tiles) release(ctx, b);
+  release(ctx, ctx->site_colmap);
+  ctx->have_sites = false;
+  ctx->have_W = false;
+  ctx->have_rho = false;
+  drop_plans(ctx);
+}
+
+void drop_quad(lrs_ctx* ctx) {
+  release(ctx, ctx->w_f64);
+  release(ctx, ctx->w_f32);
+  release(ctx, ctx->w_f32_perm);
+  release(ctx, ctx->c_dev);
+  ctx->have_quad = false;
+  ctx->quad = Quad();
+}
+
+// max |x| over a device array of doubles, and whether any entry is not finite (synchronises)
+lrs_status device_max_abs(lrs_ctx* ctx, const double* x, long long n, float* out, bool* bad) {
+  DevBuf tmp;
+  CHECK(ensure_buf(ctx, tmp, 256, "max|x| scratch"));
+  lrs_status st = LRS_OK;
+  unsigned int h[2] = {0, 0};
+  if (launch_fill_zero(tmp.p, 256, ctx->stream) != hipSuccess ||
+      launch_max_abs(x, n, (unsigned int*)tmp.p, ctx->stream) != hipSuccess ||
+      hipMemcpyAsync(h, tmp.p, 8, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess)
+    st = fail(ctx, LRS_EDEVICE, "max|x| reduction failed");
+  release(ctx, tmp);
+  float m;
+  std::memcpy(&m, &h[0], 4);
+  *out = m;
+  *bad = h[1] != 0;
+  return st;
+}
+
+float pow2_prescale(float maxabs) {
+  if (!(maxabs > 0)) return 1.f;
+  int e = (int)std::floor(std::log2((double)maxabs));
+  return (float)std::ldexp(1.0, -e);
+}
+
+// ------------------------------------------------------------------ lazy operand layouts
+lrs_status ensure_grid_tiles(lrs_ctx* ctx, int prec) {
+  if (ctx->ngrid <= 0) return fail(ctx, LRS_ESTATE, "no grid orbitals were given");
+  DevBuf& b = ctx->grid_tiles[prec];
+  if (b.p) return LRS_OK;
+  size_t bytes = (size_t)(ctx->grid_cols_pad / 16) * (ctx->K_pad / chunk_of(prec)) * kTileBytes;
+  CHECK(ensure_buf(ctx, b, bytes, "grid operand"));
+  HIP_OR_FAIL(ctx, launch_repack_from_f64(ctx->grid_tiles[LRS_FP64].p, ctx->grid_cols_pad,
+                                          ctx->K_pad, prec, ctx->grid_scale_f16, b.p,
+                                          ctx->stream));
+  return LRS_OK;
+}
+
+lrs_status ensure_site_f32(lrs_ctx* ctx) {
+  if (ctx->site_f32.p && ctx->site_f32_perm.p) return LRS_OK;
+  size_t bytes = (size_t)2 * ctx->rows_pad * ctx->K_pad * sizeof(float);
+  CHECK(ensure_buf(ctx, ctx->site_f32, bytes, "site operand fp32"));
+  CHECK(ensure_buf(ctx, ctx->site_f32_perm, bytes, "site operand fp32 (permuted)"));
+  HIP_OR_FAIL(ctx, launch_derive_site_f32((const double*)ctx->site_f64.p, ctx->rows_pad,
+                                          ctx->K_pad, (float*)ctx->site_f32.p,
+                                          (float*)ctx->site_f32_perm.p, ctx->stream));
+  return LRS_OK;
+}
+
+lrs_status ensure_site_tiles(lrs_ctx* ctx, int prec) {
+  DevBuf& b = ctx->site_tiles[prec];
+  if (b.p) return LRS_OK;
+  size_t bytes = (size_t)(ctx->site_cols_pad / 16) * (ctx->K_pad / chunk_of(prec)) * kTileBytes;
+  CHECK(ensure_buf(ctx, b, bytes, "site column operand"));
+  HIP_OR_FAIL(ctx, launch_site_col_tiles((const double*)ctx->site_f64.p, ctx->rows_pad,
+                                         ctx->K_pad, ctx->site_cols_pad,
+                                         (const int*)ctx->site_colmap.p, prec,
+                                         ctx->site_scale_f16, b.p, ctx->stream));
+  return LRS_OK;
+}
+
+// ------------------------------------------------------------------ quadrature terms
+// alpha/beta given per term on the (k, band) grid; normalises each term's weights by powers
+// of two (largest weight in [1, 2)) and moves the factors into c.
+lrs_status install_terms(lrs_ctx* ctx, Quad& q, const std::vector<double>& c,
+                         const std::vector<double>& alpha, const std::vector<double>& beta,
+                         const std::vector<double>* dalpha, const std::vector<double>* dbeta) {
+  const int T = (int)c.size();
+  const int Ko = ctx->Ko, Ku = ctx->Ku, Kp = ctx->K_pad;
+  q.nterms = T;
+  q.c_raw = c;
+  q.c.assign(T, 0.0);
+  q.w.assign((size_t)T * Kp, 0.0);
+  q.dw.assign((size_t)T * Kp, 0.0);
+  q.has_deriv = dalpha != nullptr;
+  for (int t = 0; t < T; ++t) {
+    double ma = 0, mb = 0;
+    for (int i = 0; i < Ko; ++i) ma = std::max(ma, alpha[(size_t)t * Ko + i]);
+    for (int i = 0; i < Ku; ++i) mb = std::max(mb, beta[(size_t)t * Ku + i]);
+    double sa = ma > 0 ? std::ldexp(1.0, -(int)std::floor(std::log2(ma))) : 1.0;
+    double sb = mb > 0 ? std::ldexp(1.0, -(int)std::floor(std::log2(mb))) : 1.0;
+    q.c[t] = c[t] / (sa * sb);
+    double* w = &q.w[(size_t)t * Kp];
+    double* dw = &q.dw[(size_t)t * Kp];
+    for (int i = 0; i < Ko; ++i) {
+      w[i] = alpha[(size_t)t * Ko + i] * sa;
+      if (dalpha) dw[i] = (*dalpha)[(size_t)t * Ko + i] * sa;
+    }
+    for (int i = 0; i < Ku; ++i) {
+      w[ctx->Ko_pad + i] = beta[(size_t)t * Ku + i] * sb;
+      if (dbeta) dw[ctx->Ko_pad + i] = (*dbeta)[(size_t)t * Ku + i] * sb;
+    }
+  }
+  // device copies: FP64 (FP64-path chunk order), FP32 natural, FP32 (FP32-path chunk order)
+  std::vector<double> w64((size_t)T * Kp);
+  std::vector<float> w32((size_t)T * Kp), w32p((size_t)T * Kp);
+  for (int t = 0; t < T; ++t)
+    for (int k = 0; k < Kp; ++k) {
+      double v = q.w[(size_t)t * Kp + k];
+      int ch16 = k >> 4, kl16 = k & 15;
+      w64[(size_t)t * Kp + ch16 * 16 + (kl16 & 3) * 4 + (kl16 >> 2)] = v;
+      int ch32 = k >> 5, kl32 = k & 31;
+      w32p[(size_t)t * Kp + ch32 * 32 + (kl32 & 3) * 8 + (kl32 >> 2)] = (float)v;
+      w32[(size_t)t * Kp + k] = (float)v;
+    }
+  CHECK(ensure_buf(ctx, ctx->w_f64, w64.size() * 8, "weights"));
+  CHECK(ensure_buf(ctx, ctx->w_f32, w32.size() * 4, "weights fp32"));
+  CHECK(ensure_buf(ctx, ctx->w_f32_perm, w32p.size() * 4, "weights fp32"));
+  CHECK(ensure_buf(ctx, ctx->c_dev, (size_t)T * 8, "term coefficients"));
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->w_f64.p, w64.data(), w64.size() * 8,
+                                  hipMemcpyHostToDevice, ctx->stream));
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->w_f32.p, w32.data(), w32.size() * 4,
+                                  hipMemcpyHostToDevice, ctx->stream));
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->w_f32_perm.p, w32p.data(), w32p.size() * 4,
+                                  hipMemcpyHostToDevice, ctx->stream));
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->c_dev.p, q.c.data(), (size_t)T * 8,
+                                  hipMemcpyHostToDevice, ctx->stream));
+  HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));   // host vectors are freed on return
+  ctx->have_quad = true;
+  ++ctx->quad_version;
+  drop_plans(ctx);
+  return LRS_OK;
+}
+
+// x = mu - e_occ, y = e_unocc - mu with the metallic regularisation
+void offsets(const lrs_ctx* ctx, std::vector<double>& x, std::vector<double>& y) {
+  x.resize(ctx->Ko);
+  y.resize(ctx->Ku);
+  for (int k = 0; k < ctx->nk; ++k) {
+    for (int n = 0; n < ctx->nocc; ++n) {
+      double v = ctx->mu - ctx->energies[(size_t)k * ctx->nb + n];
+      x[(size_t)k * ctx->nocc + n] = ctx->delta > 0 ? std::sqrt(v * v + ctx->delta * ctx->delta) : v;
+    }
+    for (int m = 0; m < ctx->nu; ++m) {
+      double v = ctx->energies[(size_t)k * ctx->nb + ctx->nocc + m] - ctx->mu;
+      y[(size_t)k * ctx->nu + m] = ctx->delta > 0 ? std::sqrt(v * v + ctx->delta * ctx->delta) : v;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ plans
+long long plan_key(int site, int cols, int prec, int variant) {
+  return (((long long)(site + 1) * 4 + cols) * 8 + prec) * 16 + variant;
+}
+
+void add_region(std::vector<TileDesc>& out, int a_row0, int nrows, int b_col0, int ncols,
+                long long out_base, int ldo, int bm, int bn) {
+  const int mt = (nrows + bm - 1) / bm, nt = (ncols + bn - 1) / bn;
+  const int GM = 8;
+  for (int g0 = 0; g0 < mt; g0 += GM) {
+    const int gsz = std::min(GM, mt - g0);
+    for (int n = 0; n < nt; ++n)
+      for (int m = g0; m < g0 + gsz; ++m) {
+        TileDesc t;
+        t.a_row0 = a_row0 + m * bm;
+        t.b_col0 = b_col0 + n * bn;
+        t.nrows = std::min(bm, nrows - m * bm);
+        t.ncols = std::min(bn, ncols - n * bn);
+        t.out_off = out_base + (long long)m * bm * ldo + (long long)n * bn;
+        t.ldo = ldo;
+        t.pad = 0;
+        out.push_back(t);
+      }
+  }
+}
+
+lrs_status get_plan(lrs_ctx* ctx, int site, int cols, int prec, int variant, Plan** out) {
+  long long key = plan_key(site, cols, prec, variant);
+  auto it = ctx->plans.find(key);
+  if (it != ctx->plans.end()) {
+    *out = &it->second;
+    return LRS_OK;
+  }
+  TileShape sh = chi0_shape(prec, variant);
+  std::vector<TileDesc> tiles;
+  const int s0 = site < 0 ? 0 : site, s1 = site < 0 ? ctx->nsites : site + 1;
+  if (cols == LRS_COLS_GRID) {
+    const int r0 = ctx->site_off[s0], nr = ctx->site_off[s1] - r0;
+    add_region(tiles, r0, nr, 0, ctx->ngrid, 0, ctx->ngrid, sh.bm, sh.bn);
+  } else {
+    long long base = 0;
+    for (int s = s0; s < s1; ++s) {
+      const int n = ctx->site_off[s + 1] - ctx->site_off[s];
+      add_region(tiles, ctx->site_off[s], n, ctx->site_col_off[s], n, base, n, sh.bm, sh.bn);
+      base += (long long)n * n;
+    }
+  }
+  Plan p;
+  p.ntiles = (int)tiles.size();
+  p.variant = variant;
+  CHECK(ensure_buf(ctx, p.tiles, tiles.size() * sizeof(TileDesc) + 32, "tile list"));
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(p.tiles.p, tiles.data(), tiles.size() * sizeof(TileDesc),
+                                  hipMemcpyHostToDevice, ctx->stream));
+  HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+  int per_cu = chi0_blocks_per_cu(prec, variant);
+  long long maxg = (long long)ctx->num_cu * std::max(1, per_cu);
+  long long g = std::min<long long>(maxg, round_up(p.ntiles, 8));
+  p.grid = (int)std::max<long long>(8, g / 8 * 8);
+  auto res = ctx->plans.emplace(key, p);
+  *out = &res.first->second;
+  return LRS_OK;
+}
+
+int pick_variant(lrs_ctx* ctx, int prec) {
+  if (ctx->tuned_variant[prec] >= 0) return ctx->tuned_variant[prec];
+  const char* e = std::getenv("LRS_VARIANT");
+  if (e) {
+    int v = std::atoi(e);
+    if (v >= 0 && v < chi0_num_variants(prec)) return v;
+  }
+  return 0;
+}
+
+lrs_status run_chi0(lrs_ctx* ctx, int site, int cols, int prec, int variant, double* out,
+                    bool timed) {
+  Plan* plan = nullptr;
+  CHECK(get_plan(ctx, site, cols, prec, variant, &plan));
+  const void *are, *aim, *w;
+  float a_scale = 1.f;
+  double bscale = 1.0;
+  size_t plane = (size_t)ctx->rows_pad * ctx->K_pad;
+  if (prec == LRS_FP64) {
+    are = ctx->site_f64.p;
+    aim = (const double*)ctx->site_f64.p + plane;
+    w = ctx->w_f64.p;
+  } else {
+    CHECK(ensure_site_f32(ctx));
+    const float* base = (const float*)(prec == LRS_FP32 ? ctx->site_f32_perm.p : ctx->site_f32.p);
+    are = base;
+    aim = base + plane;
+    w = prec == LRS_FP32 ? ctx->w_f32_perm.p : ctx->w_f32.p;
+    if (prec == LRS_FP16X2) a_scale = ctx->site_scale_f16;
+  }
+  const void* b;
+  if (cols == LRS_COLS_GRID) {
+    CHECK(ensure_grid_tiles(ctx, prec));
+    b = ctx->grid_tiles[prec].p;
+    if (prec == LRS_FP16X2) bscale = ctx->grid_scale_f16;
+  } else {
+    CHECK(ensure_site_tiles(ctx, prec));
+    b = ctx->site_tiles[prec].p;
+    if (prec == LRS_FP16X2) bscale = ctx->site_scale_f16;
+  }
+  const int KC = chunk_of(prec);
+  const int b_nchunks = ctx->K_pad / KC;
+  double pref = -2.0 * ctx->spin / ((double)ctx->nk * ctx->nk);
+  double g_scale = (double)a_scale * bscale;   // each G carries a_scale * b_scale
+  pref /= g_scale * g_scale;
+  if (timed) HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+  HIP_OR_FAIL(ctx, launch_chi0(prec, variant, plan->grid, are, aim, ctx->K_pad, b, b_nchunks, w,
+                               (const double*)ctx->c_dev.p, ctx->quad.nterms, ctx->Ko_pad / KC,
+                               ctx->Ku_pad / KC, (const TileDesc*)plan->tiles.p, plan->ntiles,
+                               out, pref, a_scale, ctx->stream));
+  if (timed) {
+    HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+    ctx->timed = true;
+  }
+  return LRS_OK;
+}
+
+}  // namespace
+
+namespace lrs {
+lrs_status plan_for(lrs_ctx* ctx, int site, int cols, int prec, int variant, Plan** out) {
+  return get_plan(ctx, site, cols, prec, variant, out);
+}
+lrs_status ensure_site_tiles_for(lrs_ctx* ctx, int prec) { return ensure_site_tiles(ctx, prec); }
+}  // namespace lrs
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char* lrs_version(void) { return "lrs 0.1 (gfx950)"; }
+
+lrs_status lrs_create(lrs_ctx** out, int device, void* hip_stream) {
+  if (!out) return LRS_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    return LRS_EDEVICE;
+  }
+  if (device < 0 || device >= n) return LRS_EINVAL;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return LRS_EDEVICE;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return LRS_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return LRS_EDEVICE;
+  lrs_ctx* ctx = new lrs_ctx();
+  ctx->device = device;
+  ctx->stream = (hipStream_t)hip_stream;
+  ctx->num_cu = prop.multiProcessorCount;
+  if (const char* e = std::getenv("LRS_MAX_BYTES")) ctx->max_bytes = (size_t)std::strtoull(e, nullptr, 10);
+  if (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
+    delete ctx;
+    return LRS_EDEVICE;
+  }
+  *out = ctx;
+  return LRS_OK;
+}
+
+void lrs_destroy(lrs_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  drop_sites(ctx);
+  drop_quad(ctx);
+  for (auto& b : ctx->grid_tiles) release(ctx, b);
+  release(ctx, ctx->W_last);
+  release(ctx, ctx->rho_last);
+  release(ctx, ctx->screen_tab);
+  release(ctx, ctx->work);
+  release(ctx, ctx->adj_work);
+  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  delete ctx;
+}
+
+const char* lrs_last_error(const lrs_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+lrs_status lrs_check_bands(int nk, int nb, int nocc, const double* e, double mu, double delta) {
+  if (nk < 1 || nb < 2 || nocc < 1 || nocc >= nb || !e) return LRS_EINVAL;
+  if (!(delta >= 0) || !std::isfinite(delta)) return LRS_EINVAL;
+  if (!all_finite(e, (size_t)nk * nb)) return LRS_ENONFINITE;
+  if (std::isinf(mu)) return LRS_ENONFINITE;
+  double top = -INFINITY, bottom = INFINITY;
+  for (int k = 0; k < nk; ++k) {
+    for (int n = 0; n < nocc; ++n) top = std::max(top, e[(size_t)k * nb + n]);
+    for (int m = nocc; m < nb; ++m) bottom = std::min(bottom, e[(size_t)k * nb + m]);
+  }
+  if (delta == 0) {
+    if (!(bottom > top)) return LRS_ENOGAP;
+    if (!std::isnan(mu) && !(mu > top && mu < bottom)) return LRS_ENOGAP;
+  }
+  return LRS_OK;
+}
+
+lrs_status lrs_set_orbitals(lrs_ctx* ctx, int nk, int nb, int nocc, int spin_factor,
+                            const double* e, double mu, double delta, const void* psi_grid,
+                            int ngrid, double grid_dV) {
+  if (!ctx) return LRS_EINVAL;
+  ctx->err.clear();
+  lrs_status st = lrs_check_bands(nk, nb, nocc, e, mu, delta);
+  if (st == LRS_EINVAL) return fail(ctx, st, "invalid band set (nk=%d nb=%d nocc=%d delta=%g)", nk, nb, nocc, delta);
+  if (st == LRS_ENONFINITE) return fail(ctx, st, "non-finite band energy or mu");
+  if (st == LRS_ENOGAP) return fail(ctx, st, "no global gap between occupied and unoccupied bands (or mu outside it)");
+  if (spin_factor != 1 && spin_factor != 2) return fail(ctx, LRS_EINVAL, "spin_factor must be 1 or 2");
+  if (ngrid < 0 || (ngrid > 0 && !psi_grid) || (ngrid == 0 && psi_grid))
+    return fail(ctx, LRS_EINVAL, "psi_grid and ngrid must be given together");
+  if (ngrid > 0 && !(grid_dV > 0)) return fail(ctx, LRS_EINVAL, "grid_dV must be > 0");
+  const long long K = (long long)nk * nb;
+  if (K > (1LL << 26) || (long long)ngrid > (1LL << 28)) return fail(ctx, LRS_EINVAL, "problem too large");
+  HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+
+  // sizes and storage for the new state, validated before the old state is dropped
+  const int Ko = nk * nocc, Ku = nk * (nb - nocc);
+  const int Ko_pad = (int)round_up(Ko, 64), Ku_pad = (int)round_up(Ku, 64);
+  const int K_pad = Ko_pad + Ku_pad;
+  const int cols_pad = ngrid > 0 ? (int)round_up(ngrid, kRowAlign) + kRowAlign : 0;
+  DevBuf tiles;
+  if (ngrid > 0) {
+    size_t bytes = (size_t)(cols_pad / 16) * (K_pad / kChunkF64) * kTileBytes;
+    CHECK(ensure_buf(ctx, tiles, bytes, "grid operand fp64"));
+    float m = 0;
+    bool bad = false;
+    lrs_status s2 = device_max_abs(ctx, (const double*)psi_grid, 2LL * K * ngrid, &m, &bad);
+    if (s2 != LRS_OK || bad) {
+      release(ctx, tiles);
+      return s2 != LRS_OK ? s2 : fail(ctx, LRS_ENONFINITE, "non-finite value in psi_grid");
+    }
+    ctx->grid_max_abs = m;
+    hipError_t he = launch_pack_tiles((const double*)psi_grid, nk, nb, nocc, ngrid, ngrid, cols_pad,
+                                      Ko_pad, K_pad, LRS_FP64, 1.f, tiles.p, ctx->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
+    if (he != hipSuccess) {
+      release(ctx, tiles);
+      return fail(ctx, LRS_EDEVICE, "packing grid orbitals: %s", hipGetErrorString(he));
+    }
+  }
+  drop_sites(ctx);
+  drop_quad(ctx);
+  for (auto& b : ctx->grid_tiles) release(ctx, b);
+  ctx->grid_tiles[LRS_FP64] = tiles;
+  ctx->nk = nk;
+  ctx->nb = nb;
+  ctx->nocc = nocc;
+  ctx->nu = nb - nocc;
+  ctx->spin = spin_factor;
+  ctx->delta = delta;
+  ctx->energies.assign(e, e + (size_t)nk * nb);
+  double top = -INFINITY, bottom = INFINITY;
+  for (int k = 0; k < nk; ++k) {
+    for (int n = 0; n < nocc; ++n) top = std::max(top, e[(size_t)k * nb + n]);
+    for (int m = nocc; m < nb; ++m) bottom = std::min(bottom, e[(size_t)k * nb + m]);
+  }
+  ctx->mu = std::isnan(mu) ? 0.5 * (top + bottom) : mu;
+  ctx->Ko = Ko;
+  ctx->Ku = Ku;
+  ctx->Ko_pad = Ko_pad;
+  ctx->Ku_pad = Ku_pad;
+  ctx->K_pad = K_pad;
+  ctx->ngrid = ngrid;
+  ctx->grid_dV = grid_dV;
+  ctx->grid_cols_pad = cols_pad;
+  ctx->grid_scale_f16 = pow2_prescale(ctx->grid_max_abs);
+  ctx->have_bands = true;
+  return LRS_OK;
+}
+
+lrs_status lrs_set_sites(lrs_ctx* ctx, int nsites, const int* nrad, const int* nang,
+                         const double* radii, const double* rad_w, const double* ang_xyz,
+                         const double* ang_w, const void* psi_site, int lmax) {
+  if (!ctx) return LRS_EINVAL;
+  ctx->err.clear();
+  if (!ctx->have_bands) return fail(ctx, LRS_ESTATE, "lrs_set_orbitals must come first");
+  if (nsites < 1 || !nrad || !nang || !radii || !rad_w || !ang_xyz || !ang_w || !psi_site)
+    return fail(ctx, LRS_EINVAL, "missing site arguments");
+  if (lmax < 0 || lmax > 2) return fail(ctx, LRS_EINVAL, "lmax must be 0..2");
+  long long nrows = 0, trad = 0, tang = 0;
+  for (int s = 0; s < nsites; ++s) {
+    if (nrad[s] < 1 || nang[s] < 1 || nrad[s] > 4096 || nang[s] > 4096)
+      return fail(ctx, LRS_EINVAL, "site %d: bad grid %d x %d", s, nrad[s], nang[s]);
+    nrows += (long long)nrad[s] * nang[s];
+    trad += nrad[s];
+    tang += nang[s];
+  }
+  if (nrows > (1LL << 24)) return fail(ctx, LRS_EINVAL, "too many site points");
+  if (!all_finite(radii, trad) || !all_finite(rad_w, trad) || !all_finite(ang_xyz, 3 * tang) ||
+      !all_finite(ang_w, tang))
+    return fail(ctx, LRS_ENONFINITE, "non-finite site geometry");
+  for (long long i = 0; i < trad; ++i)
+    if (!(radii[i] > 0)) return fail(ctx, LRS_EINVAL, "radii must be > 0");
+  HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+  float m = 0;
+  bool bad = false;
+  CHECK(device_max_abs(ctx, (const double*)psi_site, 2LL * ctx->nk * ctx->nb * nrows, &m, &bad));
+  if (bad) return fail(ctx, LRS_ENONFINITE, "non-finite value in psi_site");
+
+  drop_sites(ctx);
+  ctx->nsites = nsites;
+  ctx->lmax = lmax;
+  ctx->nrad.assign(nrad, nrad + nsites);
+  ctx->nang.assign(nang, nang + nsites);
+  ctx->radii.assign(radii, radii + trad);
+  ctx->rad_w.assign(rad_w, rad_w + trad);
+  ctx->ang_xyz.assign(ang_xyz, ang_xyz + 3 * tang);
+  ctx->ang_w.assign(ang_w, ang_w + tang);
+  ctx->site_off.assign(nsites + 1, 0);
+  ctx->site_col_off.assign(nsites + 1, 0);
+  ctx->rad_off.assign(nsites + 1, 0);
+  ctx->ang_off.assign(nsites + 1, 0);
+  for (int s = 0; s < nsites; ++s) {
+    int n = nrad[s] * nang[s];
+    ctx->site_off[s + 1] = ctx->site_off[s] + n;
+    ctx->site_col_off[s + 1] = ctx->site_col_off[s] + (int)round_up(n, kRowAlign);
+    ctx->rad_off[s + 1] = ctx->rad_off[s] + nrad[s];
+    ctx->ang_off[s + 1] = ctx->ang_off[s] + nang[s];
+  }
+  ctx->nrows = (int)nrows;
+  ctx->rows_pad = (int)round_up(nrows, kRowAlign) + kRowAlign;
+  ctx->site_cols_pad = ctx->site_col_off[nsites] + kRowAlign;
+  ctx->site_max_abs = m;
+  ctx->site_scale_f16 = pow2_prescale(m);
+  // column map of the site column operand: padded column -> site row (-1 = zero column)
+  std::vector<int> colmap(ctx->site_cols_pad, -1);
+  for (int s = 0; s < nsites; ++s)
+    for (int i = 0; i < ctx->site_off[s + 1] - ctx->site_off[s]; ++i)
+      colmap[ctx->site_col_off[s] + i] = ctx->site_off[s] + i;
+  CHECK(ensure_buf(ctx, ctx->site_colmap, colmap.size() * sizeof(int), "site column map"));
+  CHECK(ensure_buf(ctx, ctx->site_f64, (size_t)2 * ctx->rows_pad * ctx->K_pad * 8, "site operand"));
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->site_colmap.p, colmap.data(), colmap.size() * sizeof(int),
+                                  hipMemcpyHostToDevice, ctx->stream));
+  HIP_OR_FAIL(ctx, launch_pack_site_rows((const double*)psi_site, ctx->nk, ctx->nb, ctx->nocc,
+                                         ctx->nrows, ctx->rows_pad, ctx->Ko_pad, ctx->K_pad,
+                                         (double*)ctx->site_f64.p, ctx->stream));
+  HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->have_sites = true;
+  return LRS_OK;
+}
+
+lrs_status lrs_set_quadrature(lrs_ctx* ctx, int nterms, const double* c, const double* alpha,
+                              const double* beta) {
+  if (!ctx) return LRS_EINVAL;
+  ctx->err.clear();
+  if (!ctx->have_bands) return fail(ctx, LRS_ESTATE, "lrs_set_orbitals must come first");
+  if (nterms < 1 || nterms > kMaxTerms || !c || !alpha || !beta)
+    return fail(ctx, LRS_EINVAL, "nterms must be 1..%d with all arrays given", kMaxTerms);
+  const size_t na = (size_t)nterms * ctx->Ko, nb_ = (size_t)nterms * ctx->Ku;
+  if (!all_finite(c, nterms) || !all_finite(alpha, na) || !all_finite(beta, nb_))
+    return fail(ctx, LRS_ENONFINITE, "non-finite quadrature term");
+  for (int t = 0; t < nterms; ++t)
+    if (!(c[t] > 0)) return fail(ctx, LRS_EINVAL, "c must be > 0");
+  for (size_t i = 0; i < na; ++i)
+    if (alpha[i] < 0) return fail(ctx, LRS_EINVAL, "alpha must be >= 0");
+  for (size_t i = 0; i < nb_; ++i)
+    if (beta[i] < 0) return fail(ctx, LRS_EINVAL, "beta must be >= 0");
+  Quad q;
+  q.kind = -1;
+  q.scale = 0;
+  q.tau.assign(nterms, 0.0);
+  std::vector<double> cv(c, c + nterms), av(alpha, alpha + na), bv(beta, beta + nb_);
+  drop_quad(ctx);
+  CHECK(install_terms(ctx, q, cv, av, bv, nullptr, nullptr));
+  ctx->quad = q;
+  return LRS_OK;
+}
+
+lrs_status lrs_make_quadrature(lrs_ctx* ctx, int kind, int nnodes, double scale) {
+  if (!ctx) return LRS_EINVAL;
+  ctx->err.clear();
+  if (!ctx->have_bands) return fail(ctx, LRS_ESTATE, "lrs_set_orbitals must come first");
+  if (kind != LRS_QUAD_TIME && kind != LRS_QUAD_FREQ) return fail(ctx, LRS_EINVAL, "unknown quadrature kind %d", kind);
+  if (nnodes < 1 || nnodes > 64) return fail(ctx, LRS_EINVAL, "nnodes must be 1..64");
+  if (!std::isfinite(scale)) return fail(ctx, LRS_ENONFINITE, "non-finite scale");
+  std::vector<double> x, y;
+  offsets(ctx, x, y);
+  std::vector<double> a, wgl;
+  gauss_legendre_01(nnodes, a, wgl);
+  const int Ko = ctx->Ko, Ku = ctx->Ku;
+  Quad q;
+  q.kind = kind;
+  std::vector<double> c, al, be, dal, dbe;
+  // derivative of an offset with respect to its band energy (mu fixed):
+  // x = mu - e -> -1, y = e - mu -> +1, times x/sqrt(x^2+delta^2) with regularisation
+  auto dx_de = [&](double xr, double sign) {
+    if (ctx->delta > 0) return sign * (xr / std::sqrt(xr * xr + ctx->delta * ctx->delta));
+    return sign;
+  };
+  std::vector<double> xr(Ko), yr(Ku);   // unregularised offsets
+  for (int k = 0; k < ctx->nk; ++k) {
+    for (int n = 0; n < ctx->nocc; ++n) xr[(size_t)k * ctx->nocc + n] = ctx->mu - ctx->energies[(size_t)k * ctx->nb + n];
+    for (int m = 0; m < ctx->nu; ++m) yr[(size_t)k * ctx->nu + m] = ctx->energies[(size_t)k * ctx->nb + ctx->nocc + m] - ctx->mu;
+  }
+  if (kind == LRS_QUAD_TIME) {
+    double dmin = *std::min_element(x.begin(), x.end()) + *std::min_element(y.begin(), y.end());
+    double dmax = *std::max_element(x.begin(), x.end()) + *std::max_element(y.begin(), y.end());
+    if (!(dmin > 0)) return fail(ctx, LRS_ENOGAP, "smallest denominator is not positive");
+    double C = scale > 0 ? scale : time_auto_scale(dmin, dmax, nnodes);
+    q.scale = C;
+    for (int j = 0; j < nnodes; ++j) {
+      double tau = C * a[j] / (1.0 - a[j]);
+      double cj = C * wgl[j] / ((1.0 - a[j]) * (1.0 - a[j]));
+      c.push_back(cj);
+      q.tau.push_back(tau);
+      for (int i = 0; i < Ko; ++i) {
+        double v = std::exp(-x[i] * tau);
+        al.push_back(v);
+        dal.push_back(-tau * v * dx_de(xr[i], -1.0));
+      }
+      for (int i = 0; i < Ku; ++i) {
+        double v = std::exp(-y[i] * tau);
+        be.push_back(v);
+        dbe.push_back(-tau * v * dx_de(yr[i], 1.0));
+      }
+    }
+  } else {
+    double zeta = scale;
+    if (!(scale > 0)) {
+      double lo = INFINITY, hi = 0;
+      for (double e : ctx->energies) {
+        double d = std::fabs(ctx->mu - e);
+        lo = std::min(lo, d);
+        hi = std::max(hi, d);
+      }
+      if (ctx->delta > 0) {
+        double f = 0.5 / kHartreeEv;
+        lo = std::sqrt(lo * lo + f * f);
+      }
+      zeta = std::sqrt(lo * hi);
+    }
+    q.scale = zeta;
+    for (int part = 0; part < 2; ++part) {      // p-terms, then q-terms
+      for (int j = 0; j < nnodes; ++j) {
+        double t = zeta * a[j] / (1.0 - a[j]);
+        double cj = zeta * wgl[j] / (kPi * (1.0 - a[j]) * (1.0 - a[j]));
+        c.push_back(cj);
+        q.tau.push_back(t);
+        auto f = [&](double v) { return part == 0 ? v / (v * v + t * t) : t / (v * v + t * t); };
+        auto df = [&](double v) {   // derivative with respect to the offset v
+          double d = v * v + t * t;
+          return part == 0 ? (t * t - v * v) / (d * d) : -2.0 * v * t / (d * d);
+        };
+        for (int i = 0; i < Ko; ++i) {
+          al.push_back(f(x[i]));
+          dal.push_back(df(x[i]) * dx_de(xr[i], -1.0));
+        }
+        for (int i = 0; i < Ku; ++i) {
+          be.push_back(f(y[i]));
+          dbe.push_back(df(y[i]) * dx_de(yr[i], 1.0));
+        }
+      }
+    }
+  }
+  if ((int)c.size() > kMaxTerms) return fail(ctx, LRS_EINVAL, "too many terms");
+  drop_quad(ctx);
+  CHECK(install_terms(ctx, q, c, al, be, &dal, &dbe));
+  ctx->quad = q;
+  return LRS_OK;
+}
+
+lrs_status lrs_get_quadrature(const lrs_ctx* ctx, int* nterms, double* c_host, double* tau_host,
+                              double* mu_host, double* scale_host) {
+  if (!ctx || !nterms) return LRS_EINVAL;
+  if (!ctx->have_quad) return LRS_ESTATE;
+  *nterms = ctx->quad.nterms;
+  // report the caller-facing coefficients: undo the per-term power-of-two normalisation
+  if (c_host || tau_host) {
+    for (int t = 0; t < ctx->quad.nterms; ++t) {
+      if (c_host) c_host[t] = ctx->quad.c_raw.empty() ? ctx->quad.c[t] : ctx->quad.c_raw[t];
+      if (tau_host) tau_host[t] = ctx->quad.tau[t];
+    }
+  }
+  if (mu_host) *mu_host = ctx->mu;
+  if (scale_host) *scale_host = ctx->quad.scale;
+  return LRS_OK;
+}
+
+lrs_status lrs_compute_chi0(lrs_ctx* ctx, int site, int cols, int prec, double* out) {
+  if (!ctx) return LRS_EINVAL;
+  ctx->err.clear();
+  if (!ctx->have_bands || !ctx->have_sites || !ctx->have_quad)
+    return fail(ctx, LRS_ESTATE, "orbitals, sites and quadrature must be set first");
+  if (!out) return fail(ctx, LRS_EINVAL, "chi0_out is NULL");
+  if (site < -1 || site >= ctx->nsites) return fail(ctx, LRS_EINVAL, "site %d out of range", site);
+  if (cols != LRS_COLS_GRID && cols != LRS_COLS_SITE) return fail(ctx, LRS_EINVAL, "bad column set");
+  if (prec < LRS_FP64 || prec > LRS_FP16X2) return fail(ctx, LRS_EINVAL, "bad precision");
+  if (cols == LRS_COLS_GRID && ctx->ngrid <= 0) return fail(ctx, LRS_ESTATE, "no grid orbitals were given");
+  HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+  return run_chi0(ctx, site, cols, prec, pick_variant(ctx, prec), out, true);
+}
+
+double lrs_last_kernel_ms(lrs_ctx* ctx) {
+  if (!ctx || !ctx->timed) return -1.0;
+  float ms = -1.f;
+  if (hipEventSynchronize(ctx->ev1) != hipSuccess || hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1) != hipSuccess)
+    return -1.0;
+  return ms;
+}
+
+lrs_status lrs_tune(lrs_ctx* ctx, int prec) {
+  if (!ctx) return LRS_EINVAL;
+  ctx->err.clear();
+  if (!ctx->have_bands || !ctx->have_sites || !ctx->have_quad)
+    return fail(ctx, LRS_ESTATE, "orbitals, sites and quadrature must be set first");
+  if (prec < LRS_FP64 || prec > LRS_FP16X2) return fail(ctx, LRS_EINVAL, "bad precision");
+  HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+  const int cols = ctx->ngrid > 0 ? LRS_COLS_GRID : LRS_COLS_SITE;
+  // problem key for the on-disk cache
+  std::ostringstream key;
+  key << "prec=" << prec << " rows=" << ctx->nrows << " cols=" << (cols == LRS_COLS_GRID ? ctx->ngrid : -1)
+      << " K=" << ctx->K_pad << " T=" << ctx->quad.nterms;
+  const char* path = std::getenv("LRS_TUNE_CACHE");
+  if (path) {
+    std::ifstream in(path);
+    std::string line;
+    while (std::getline(in, line)) {
+      size_t p = line.rfind(" variant=");
+      if (p != std::string::npos && line.substr(0, p) == key.str()) {
+        int v = std::atoi(line.c_str() + p + 9);
+        if (v >= 0 && v < chi0_num_variants(prec)) {
+          ctx->tuned_variant[prec] = v;
+          return LRS_OK;
+        }
+      }
+    }
+  }
+  // time every variant on a bounded sample of the problem: the first row tile band of one site
+  DevBuf out;
+  const int s = 0;
+  const int nr = ctx->site_off[1] - ctx->site_off[0];
+  const long long ncol = cols == LRS_COLS_GRID ? ctx->ngrid : nr;
+  CHECK(ensure_buf(ctx, out, (size_t)nr * ncol * 8, "tuning output"));
+  int best = 0;
+  float best_ms = 1e30f;
+  for (int v = 0; v < chi0_num_variants(prec); ++v) {
+    lrs_status st = run_chi0(ctx, s, cols, prec, v, (double*)out.p, false);   // warm-up + plan
+    if (st != LRS_OK) { release(ctx, out); return st; }
+    HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    st = run_chi0(ctx, s, cols, prec, v, (double*)out.p, false);
+    if (st != LRS_OK) { release(ctx, out); return st; }
+    HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+    HIP_OR_FAIL(ctx, hipEventSynchronize(ctx->ev1));
+    float ms = 0;
+    HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = v;
+    }
+  }
+  release(ctx, out);
+  ctx->timed = false;
+  ctx->tuned_variant[prec] = best;
+  if (path) {
+    std::ofstream o(path, std::ios::app);
+    o << key.str() << " variant=" << best << "\n";
+  }
+  return LRS_OK;
+}
+
+lrs_status lrs_screen_W(lrs_ctx* ctx, const double* chi0_ss, double* W_out, const double* rho,
+                        double* loss_out) {
+  if (!ctx) return LRS_EINVAL;
+  ctx->err.clear();
+  if (!ctx->have_sites) return fail(ctx, LRS_ESTATE, "sites must be set first");
+  if (!chi0_ss || !W_out) return fail(ctx, LRS_EINVAL, "chi0 and W_out are required");
+  if (loss_out && !rho) return fail(ctx, LRS_EINVAL, "loss_out needs rho_test");
+  HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+  hipError_t e = launch_screen_forward(ctx, chi0_ss, W_out, rho, loss_out);
+  if (e == hipErrorOutOfMemory) return fail(ctx, LRS_ENOMEM, "screening workspace");
+  if (e != hipSuccess) return fail(ctx, LRS_EDEVICE, "screen_W: %s", hipGetErrorString(e));
+  return LRS_OK;
+}
+
+lrs_status lrs_screen_W_backward(lrs_ctx* ctx, const double* dL_dW, double* dL_dchi0) {
+  if (!ctx) return LRS_EINVAL;
+  ctx->err.clear();
+  if (!ctx->have_W) return fail(ctx, LRS_ESTATE, "lrs_screen_W must come first");
+  if (!dL_dchi0) return fail(ctx, LRS_EINVAL, "dL_dchi0 is required");
+  if (!dL_dW && !ctx->have_rho) return fail(ctx, LRS_EINVAL, "dL_dW is NULL and no test charge was given");
+  HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+  hipError_t e = launch_screen_backward(ctx, dL_dW, dL_dchi0);
+  if (e != hipSuccess) return fail(ctx, LRS_EDEVICE, "screen_W backward: %s", hipGetErrorString(e));
+  return LRS_OK;
+}
+
+lrs_status lrs_compute_chi0_backward(lrs_ctx* ctx, int cols, const double* dL_dchi0, double* dL_dE,
+                                     void* dL_dpsi_site, void* dL_dpsi_grid) {
+  if (!ctx) return LRS_EINVAL;
+  ctx->err.clear();
+  if (!ctx->have_bands || !ctx->have_sites || !ctx->have_quad)
+    return fail(ctx, LRS_ESTATE, "orbitals, sites and quadrature must be set first");
+  if (cols != LRS_COLS_SITE) return fail(ctx, LRS_EUNSUPPORTED, "backward supports site x site blocks only");
+  if (dL_dpsi_grid) return fail(ctx, LRS_EUNSUPPORTED, "site blocks do not depend on grid orbitals");
+  if (!dL_dchi0 || !dL_dE || !dL_dpsi_site) return fail(ctx, LRS_EINVAL, "missing gradient buffers");
+  if (!ctx->quad.has_deriv) return fail(ctx, LRS_EUNSUPPORTED, "generic terms carry no energy derivative");
+  HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+  hipError_t e = launch_chi0_backward(ctx, dL_dchi0, dL_dE, (double*)dL_dpsi_site);
+  if (e == hipErrorOutOfMemory) return fail(ctx, LRS_ENOMEM, "adjoint workspace");
+  if (e != hipSuccess) return fail(ctx, LRS_EDEVICE, "chi0 backward: %s", hipGetErrorString(e));
+  return LRS_OK;
+}
+
+}  // extern "C"

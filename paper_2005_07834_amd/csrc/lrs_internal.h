@@ -1,0 +1,185 @@
+// Internal declarations of the screening library: context state, operand layouts and
+// kernel launchers.  Not part of the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/lrs.h"
+
+namespace lrs {
+
+// Operand chunking along K (the flattened (k-point, band) index).  A "fragment tile" is
+// 16 rows (or columns) x one K chunk of a precision's matrix-core operand, 4 KiB in every
+// precision: FP64 -> 16 k x 2 planes (re, im) x 8 B; FP32 -> 32 k x 2 planes x 4 B;
+// BF16X2/FP16X2 -> 32 k x 4 planes (re hi, re lo, im hi, im lo) x 2 B.
+constexpr int kTileBytes = 4096;
+constexpr int kChunkF64 = 16;
+constexpr int kChunkLow = 32;
+constexpr int kRowAlign = 128;  // rows / columns of every operand are padded to this
+constexpr int kMaxTerms = 128;
+
+inline int chunk_of(int prec) { return prec == LRS_FP64 ? kChunkF64 : kChunkLow; }
+inline long long round_up(long long x, long long m) { return (x + m - 1) / m * m; }
+
+// One output tile of a chi0 launch.
+struct TileDesc {
+  int a_row0;           // first row of the site operand
+  int b_col0;           // first column of the column operand (multiple of 16)
+  int nrows;            // valid rows in this tile
+  int ncols;            // valid columns
+  long long out_off;    // element offset of the tile's (0,0) in the output
+  int ldo;              // output leading dimension
+  int pad;
+};
+static_assert(sizeof(TileDesc) == 32, "TileDesc layout");
+
+// Tile shape of one kernel instantiation.
+struct TileShape {
+  int bm, bn;           // workgroup tile
+  int threads;
+};
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Plan {             // cached launch plan for (site, cols, prec, variant)
+  DevBuf tiles;
+  int ntiles = 0;
+  int grid = 0;
+  int variant = 0;
+};
+
+struct Quad {
+  int kind = -1;          // LRS_QUAD_TIME, LRS_QUAD_FREQ, or -1 generic
+  int nterms = 0;
+  double scale = 0;       // C (time) or zeta (freq)
+  std::vector<double> c;        // per-term coefficient after weight normalisation
+  std::vector<double> c_raw;    // per-term coefficient as constructed
+  std::vector<double> tau;      // tau (time) or t (freq) per term
+  std::vector<double> w;        // [T][K_pad] normalised alpha | beta (zero padded)
+  std::vector<double> dw;       // [T][K_pad] d(weight)/d(energy) with mu fixed
+  bool has_deriv = false;
+};
+
+}  // namespace lrs
+
+struct lrs_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cu = 0;
+  std::string err;
+  size_t bytes_in_use = 0;
+  size_t max_bytes = 0;   // 0 = unlimited
+
+  // bands
+  bool have_bands = false;
+  int nk = 0, nb = 0, nocc = 0, nu = 0, spin = 2;
+  double mu = 0, delta = 0;
+  std::vector<double> energies;   // [nk][nb]
+  int ngrid = 0;
+  double grid_dV = 0;
+  // K layout: [0, Ko) occupied (k-major), zeros to Ko_pad, then [Ko_pad, Ko_pad+Ku) unoccupied
+  int Ko = 0, Ku = 0, Ko_pad = 0, Ku_pad = 0, K_pad = 0;
+
+  // grid operand: FP64 fragment tiles (always) and lazily built reduced-precision tiles
+  lrs::DevBuf grid_tiles[4];
+  int grid_cols_pad = 0;
+  float grid_scale_f16 = 1.f;     // power-of-two prescale used by the FP16X2 tiles
+
+  // sites
+  bool have_sites = false;
+  int nsites = 0, lmax = 2, nrows = 0, rows_pad = 0;
+  std::vector<int> nrad, nang, site_off, rad_off, ang_off;
+  std::vector<int> site_col_off;  // column offset of each site in the site column operand
+  int site_cols_pad = 0;
+  float site_scale_f16 = 1.f;     // power-of-two prescale of site values in FP16X2 operands
+  lrs::DevBuf site_colmap;        // [site_cols_pad] column -> site row (-1: zero column)
+  std::vector<double> radii, rad_w, ang_xyz, ang_w;
+  lrs::DevBuf site_f64;           // planar re/im [2][rows_pad][K_pad] (chunk-permuted), FP64
+  lrs::DevBuf site_f32;           // the same in FP32 (FP32/split paths; per-precision permutation)
+  lrs::DevBuf site_f32_perm;      // FP32 with the FP32-path permutation
+  lrs::DevBuf site_tiles[4];      // site points as a column operand (fragment tiles)
+  lrs::DevBuf psi_site_f64;       // planar [2][K_pad][rows_pad] (k-major rows) for the adjoint
+  float site_max_abs = 0.f;
+  float grid_max_abs = 0.f;
+
+  // quadrature
+  bool have_quad = false;
+  lrs::Quad quad;
+  lrs::DevBuf w_f64, w_f32, w_f32_perm, c_dev;
+  int quad_version = 0;
+
+  // plans
+  std::map<long long, lrs::Plan> plans;
+  int tuned_variant[4] = {-1, -1, -1, -1};
+
+  // screening state
+  lrs::DevBuf W_last, rho_last, screen_tab, work, adj_work;
+  bool have_W = false, have_rho = false;
+
+  // timing
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool timed = false;
+};
+
+namespace lrs {
+
+// quadrature.cpp
+void gauss_legendre_01(int n, std::vector<double>& a, std::vector<double>& w);
+double time_rule_error(double scale, int n, double dmin, double dmax);
+double time_auto_scale(double dmin, double dmax, int n);
+
+// pack.hip
+hipError_t launch_pack_tiles(const double* psi, int nk, int nb, int nocc, int ncols, int ld_src,
+                             int ncols_pad, int Ko_pad, int K_pad, int prec, float prescale,
+                             void* out, hipStream_t s);
+hipError_t launch_pack_site_rows(const double* psi, int nk, int nb, int nocc, int nrows,
+                                 int rows_pad, int Ko_pad, int K_pad, double* out_f64,
+                                 hipStream_t s);
+hipError_t launch_derive_site_f32(const double* site_f64, int rows_pad, int K_pad, float* o32,
+                                  float* o32p, hipStream_t s);
+hipError_t launch_derive_site_kmajor(const double* site_f64, int rows_pad, int K_pad, double* out,
+                                     hipStream_t s);
+hipError_t launch_site_col_tiles(const double* site_f64, int rows_pad, int K_pad, int ncols_pad,
+                                 const int* colmap, int prec, float prescale, void* dst,
+                                 hipStream_t s);
+hipError_t launch_max_abs(const double* x, long long n, unsigned int* out_bits, hipStream_t s);
+hipError_t launch_repack_from_f64(const void* tiles64, int ncols_pad, int K_pad, int prec,
+                                  float prescale, void* dst, hipStream_t s);
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+
+// chi0.hip
+int chi0_num_variants(int prec);
+int chi0_blocks_per_cu(int prec, int variant);
+TileShape chi0_shape(int prec, int variant);
+hipError_t launch_chi0(int prec, int variant, int grid, const void* a_re, const void* a_im,
+                       int lda, const void* b_tiles, int b_nchunks, const void* w,
+                       const double* c, int T, int nch_o, int nch_u, const TileDesc* tiles,
+                       int ntiles, double* out, double pref, float a_scale, hipStream_t s);
+
+hipError_t launch_green_adjoint(int grid, const void* a_re, const void* a_im, int lda,
+                                const void* b_tiles, int b_nchunks, const double* w,
+                                const double* c, int nch_o, int nch_u, const TileDesc* tiles,
+                                int ntiles, const double* lam, double* hu_re, double* hu_im,
+                                double* ho_re, double* ho_im, hipStream_t s);
+
+// lrs_api.cpp (shared with the adjoint)
+lrs_status plan_for(lrs_ctx* ctx, int site, int cols, int prec, int variant, Plan** out);
+lrs_status ensure_site_tiles_for(lrs_ctx* ctx, int prec);
+
+// screen.hip
+hipError_t launch_screen_forward(lrs_ctx* ctx, const double* chi0_ss, double* W_out,
+                                 const double* rho, double* loss_out);
+hipError_t launch_screen_backward(lrs_ctx* ctx, const double* dL_dW, double* dL_dchi0);
+
+// adjoint.hip
+hipError_t launch_chi0_backward(lrs_ctx* ctx, const double* dL_dchi0, double* dL_dE,
+                                double* dL_dpsi);
+
+}  // namespace lrs

@@ -1,0 +1,287 @@
+// Operand packing: complex128 orbitals -> the matrix-core fragment layouts used by the chi0
+// kernels, plus small helpers (max |x|, zero fill).
+//
+// The contraction index K runs over (k-point, band) pairs: occupied pairs first
+// ([0, Ko), k-major), zeros up to Ko_pad, then unoccupied pairs ([Ko_pad, Ko_pad + Ku)),
+// zeros up to K_pad.  Padding is zero so that padded products vanish.
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include "lrs_internal.h"
+
+namespace lrs {
+namespace {
+
+struct SrcPsi {           // complex128 [nk][nb][ld] orbitals on a point set
+  const double* psi;
+  int nb, nocc, nu, ncols, ld, Ko, Ko_pad, Ku;
+  __device__ void get(int c, int k, double& re, double& im) const {
+    re = 0.0;
+    im = 0.0;
+    if (c >= ncols) return;
+    int kp, band;
+    if (k < Ko) {
+      kp = k / nocc;
+      band = k - kp * nocc;
+    } else if (k >= Ko_pad && k < Ko_pad + Ku) {
+      int j = k - Ko_pad;
+      kp = j / nu;
+      band = nocc + (j - kp * nu);
+    } else {
+      return;
+    }
+    const double* p = psi + 2 * ((size_t)(kp * nb + band) * ld + c);
+    re = p[0];
+    im = p[1];
+  }
+};
+
+struct SrcTiles64 {       // FP64 fragment tiles as a source (for lazy reduced-precision copies)
+  const double* t;
+  int nchunks64;
+  __device__ void get(int c, int k, double& re, double& im) const {
+    int cb = c >> 4, ch = k >> 4, kl = k & 15;
+    int lane = ((kl & 3) << 4) | (c & 15);
+    int s = kl >> 2;
+    const double* tile = t + ((size_t)cb * nchunks64 + ch) * (kTileBytes / 8);
+    re = tile[lane * 4 + s];
+    im = tile[256 + lane * 4 + s];
+  }
+};
+
+__device__ inline void split_bf16(float x, __hip_bfloat16& hi, __hip_bfloat16& lo) {
+  hi = __float2bfloat16(x);
+  lo = __float2bfloat16(x - __bfloat162float(hi));
+}
+__device__ inline void split_f16(float x, __half& hi, __half& lo) {
+  hi = __float2half(x);
+  lo = __float2half(x - __half2float(hi));
+}
+
+// One thread per (tile, lane): writes that lane's slot of every plane of the tile.
+template <class Src>
+__global__ void pack_tiles_kernel(Src src, long long ntiles, int nchunks, int prec,
+                                  float prescale, unsigned char* out) {
+  long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= ntiles * 64) return;
+  int lane = (int)(gid & 63);
+  long long tile = gid >> 6;
+  int cb = (int)(tile / nchunks);
+  int ch = (int)(tile - (long long)cb * nchunks);
+  int c = cb * 16 + (lane & 15);
+  unsigned char* base = out + tile * kTileBytes;
+  if (prec == LRS_FP64) {
+    double* t = reinterpret_cast<double*>(base);
+    for (int s = 0; s < 4; ++s) {
+      double re, im;
+      src.get(c, ch * 16 + 4 * s + (lane >> 4), re, im);
+      t[lane * 4 + s] = re;
+      t[256 + lane * 4 + s] = im;
+    }
+  } else if (prec == LRS_FP32) {
+    float* t = reinterpret_cast<float*>(base);
+    for (int s = 0; s < 8; ++s) {
+      double re, im;
+      src.get(c, ch * 32 + 4 * s + (lane >> 4), re, im);
+      t[lane * 8 + s] = (float)re;
+      t[512 + lane * 8 + s] = (float)im;
+    }
+  } else if (prec == LRS_BF16X2) {
+    __hip_bfloat16* t = reinterpret_cast<__hip_bfloat16*>(base);
+    for (int e = 0; e < 8; ++e) {
+      double re, im;
+      src.get(c, ch * 32 + 8 * (lane >> 4) + e, re, im);
+      split_bf16((float)re, t[lane * 8 + e], t[512 + lane * 8 + e]);
+      split_bf16((float)im, t[1024 + lane * 8 + e], t[1536 + lane * 8 + e]);
+    }
+  } else {
+    __half* t = reinterpret_cast<__half*>(base);
+    for (int e = 0; e < 8; ++e) {
+      double re, im;
+      src.get(c, ch * 32 + 8 * (lane >> 4) + e, re, im);
+      split_f16((float)(re * prescale), t[lane * 8 + e], t[512 + lane * 8 + e]);
+      split_f16((float)(im * prescale), t[1024 + lane * 8 + e], t[1536 + lane * 8 + e]);
+    }
+  }
+}
+
+// Site rows for the A side: planar [2][rows_pad][K_pad].  Within each chunk the K order is
+// permuted so that one thread's contiguous load is exactly one matrix-core lane's operand:
+//   FP64 (chunk 16): stored g*4 + j  <-> k = 4 j + g
+//   FP32 (chunk 32): stored g*8 + j  <-> k = 4 j + g
+//   natural (bf16/fp16 split paths): stored k <-> k
+__device__ inline size_t pos_f64(int r, int k, int K_pad) {
+  int ch = k >> 4, kl = k & 15;
+  return (size_t)r * K_pad + ch * 16 + (kl & 3) * 4 + (kl >> 2);
+}
+__device__ inline size_t pos_f32p(int r, int k, int K_pad) {
+  int ch = k >> 5, kl = k & 31;
+  return (size_t)r * K_pad + ch * 32 + (kl & 3) * 8 + (kl >> 2);
+}
+
+struct SrcSite64 {        // the FP64 row operand as a source (optionally through a column map)
+  const double* a;
+  int rows_pad, K_pad;
+  const int* colmap;      // nullptr: identity
+  __device__ void get(int r, int k, double& re, double& im) const {
+    if (colmap) {
+      r = colmap[r];
+      if (r < 0) {
+        re = 0.0;
+        im = 0.0;
+        return;
+      }
+    }
+    size_t p = pos_f64(r, k, K_pad);
+    re = a[p];
+    im = a[(size_t)rows_pad * K_pad + p];
+  }
+};
+
+__global__ void pack_site_rows_kernel(SrcPsi src, int rows_pad, int K_pad, double* o64) {
+  long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long n = (long long)rows_pad * K_pad;
+  if (gid >= n) return;
+  int r = (int)(gid / K_pad);
+  int k = (int)(gid - (long long)r * K_pad);
+  double re, im;
+  src.get(r, k, re, im);
+  size_t p = pos_f64(r, k, K_pad);
+  o64[p] = re;
+  o64[(size_t)n + p] = im;
+}
+
+// FP32 row operands from the FP64 one: natural order (o32) and FP32-path order (o32p).
+__global__ void derive_site_rows_f32_kernel(SrcSite64 src, float* o32, float* o32p) {
+  long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long n = (long long)src.rows_pad * src.K_pad;
+  if (gid >= n) return;
+  int r = (int)(gid / src.K_pad);
+  int k = (int)(gid - (long long)r * src.K_pad);
+  double re, im;
+  src.get(r, k, re, im);
+  o32[gid] = (float)re;
+  o32[n + gid] = (float)im;
+  size_t p = pos_f32p(r, k, src.K_pad);
+  o32p[p] = (float)re;
+  o32p[(size_t)n + p] = (float)im;
+}
+
+// Site orbitals k-major for the adjoint: planar [2][K_pad][rows_pad], natural K order.
+__global__ void derive_site_kmajor_kernel(SrcSite64 src, double* out) {
+  long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long n = (long long)src.rows_pad * src.K_pad;
+  if (gid >= n) return;
+  int k = (int)(gid / src.rows_pad);
+  int r = (int)(gid - (long long)k * src.rows_pad);
+  double re, im;
+  src.get(r, k, re, im);
+  out[gid] = re;
+  out[n + gid] = im;
+}
+
+__global__ void max_abs_kernel(const double* x, long long n, unsigned int* out_bits) {
+  float m = 0.f;
+  bool bad = false;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    double v = x[i];
+    if (!isfinite(v)) bad = true;
+    m = fmaxf(m, (float)fabs(v));
+  }
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  unsigned int any = __any(bad) ? 1u : 0u;
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(out_bits, __float_as_uint(m));   // non-negative floats order like their bits
+    if (any) atomicOr(out_bits + 1, 1u);
+  }
+}
+
+__global__ void fill_zero_kernel(uint4* p, size_t n16) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = make_uint4(0, 0, 0, 0);
+}
+
+inline int blocks_for(long long n, int tpb) { return (int)((n + tpb - 1) / tpb); }
+
+}  // namespace
+
+hipError_t launch_pack_tiles(const double* psi, int nk, int nb, int nocc, int ncols, int ld_src,
+                             int ncols_pad, int Ko_pad, int K_pad, int prec, float prescale,
+                             void* out, hipStream_t s) {
+  int nu = nb - nocc;
+  SrcPsi src{psi, nb, nocc, nu, ncols, ld_src, nk * nocc, Ko_pad, nk * nu};
+  int nchunks = K_pad / chunk_of(prec);
+  long long ntiles = (long long)(ncols_pad / 16) * nchunks;
+  hipLaunchKernelGGL(pack_tiles_kernel<SrcPsi>, dim3(blocks_for(ntiles * 64, 256)), dim3(256), 0,
+                     s, src, ntiles, nchunks, prec, prescale, (unsigned char*)out);
+  return hipGetLastError();
+}
+
+hipError_t launch_repack_from_f64(const void* tiles64, int ncols_pad, int K_pad, int prec,
+                                  float prescale, void* dst, hipStream_t s) {
+  SrcTiles64 src{(const double*)tiles64, K_pad / kChunkF64};
+  int nchunks = K_pad / chunk_of(prec);
+  long long ntiles = (long long)(ncols_pad / 16) * nchunks;
+  hipLaunchKernelGGL(pack_tiles_kernel<SrcTiles64>, dim3(blocks_for(ntiles * 64, 256)), dim3(256),
+                     0, s, src, ntiles, nchunks, prec, prescale, (unsigned char*)dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_site_rows(const double* psi, int nk, int nb, int nocc, int nrows,
+                                 int rows_pad, int Ko_pad, int K_pad, double* out_f64,
+                                 hipStream_t s) {
+  int nu = nb - nocc;
+  SrcPsi src{psi, nb, nocc, nu, nrows, nrows, nk * nocc, Ko_pad, nk * nu};
+  long long n = (long long)rows_pad * K_pad;
+  hipLaunchKernelGGL(pack_site_rows_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, src,
+                     rows_pad, K_pad, out_f64);
+  return hipGetLastError();
+}
+
+hipError_t launch_derive_site_f32(const double* site_f64, int rows_pad, int K_pad, float* o32,
+                                  float* o32p, hipStream_t s) {
+  SrcSite64 src{site_f64, rows_pad, K_pad, nullptr};
+  long long n = (long long)rows_pad * K_pad;
+  hipLaunchKernelGGL(derive_site_rows_f32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, src,
+                     o32, o32p);
+  return hipGetLastError();
+}
+
+hipError_t launch_derive_site_kmajor(const double* site_f64, int rows_pad, int K_pad, double* out,
+                                     hipStream_t s) {
+  SrcSite64 src{site_f64, rows_pad, K_pad, nullptr};
+  long long n = (long long)rows_pad * K_pad;
+  hipLaunchKernelGGL(derive_site_kmajor_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, src,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_site_col_tiles(const double* site_f64, int rows_pad, int K_pad, int ncols_pad,
+                                 const int* colmap, int prec, float prescale, void* dst,
+                                 hipStream_t s) {
+  SrcSite64 src{site_f64, rows_pad, K_pad, colmap};
+  int nchunks = K_pad / chunk_of(prec);
+  long long ntiles = (long long)(ncols_pad / 16) * nchunks;
+  hipLaunchKernelGGL(pack_tiles_kernel<SrcSite64>, dim3(blocks_for(ntiles * 64, 256)), dim3(256),
+                     0, s, src, ntiles, nchunks, prec, prescale, (unsigned char*)dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_max_abs(const double* x, long long n, unsigned int* out_bits, hipStream_t s) {
+  int blocks = (int)std::min<long long>(4096, std::max<long long>(1, (n + 255) / 256));
+  hipLaunchKernelGGL(max_abs_kernel, dim3(blocks), dim3(256), 0, s, x, n, out_bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
+  size_t n16 = bytes / 16;
+  if (n16 == 0) return hipSuccess;
+  int blocks = (int)std::min<size_t>(8192, (n16 + 255) / 256);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks), dim3(256), 0, s, (uint4*)p, n16);
+  return hipGetLastError();
+}
+
+}  // namespace lrs

@@ -1,0 +1,475 @@
+// Per-site dielectric solve in the radial x real-Y_lm basis (Sec. VI.E) and its adjoint.
+//
+// For a site with n_rad shells r_i (weights u_i) and n_ang directions (weights w_a):
+//   X_{(L,i),(L',j)} = sum_{a,b} w_a Y_L(a) chi0(i a, j b) Y_L'(b) w_b
+//   V_L(i,j) = 4 pi/(2l+1) min(r_i,r_j)^l / max(r_i,r_j)^(l+1)      (Coulomb, diagonal in L)
+//   eps = I - V D X D,  W = eps^-1 V                                  (D = diag(u_i))
+// solved per site by Gauss-Jordan elimination with partial pivoting on [eps | V] in FP64.
+// Adjoint: dL/dX = D W^T Gbar W^T D,  dL/dchi0 = P^T (dL/dX) P.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "lrs_internal.h"
+
+namespace lrs {
+namespace {
+
+// per-site metadata (device): offsets into the packed tables and buffers
+struct SiteMeta {
+  int nrad, nang, nL, n;        // n = nL * nrad
+  int rad_off, yw_off;          // into radii/u and the Y*w table
+  long long chi_off;            // site block offset in the site-block chi0 layout (npts^2)
+  long long w_off;              // offset of the site's n x n matrices (W, X, T, ...)
+  long long pt_off;             // first site point (for rho)
+  long long h_off;              // offset of the site's length-n vectors
+};
+
+struct ScreenTabs {
+  const SiteMeta* meta;
+  const double* radii;
+  const double* u;
+  const double* yw;             // [sum nL * nang] : w_a Y_L(a), row L
+};
+
+__device__ inline double coulomb_l(int l, double ri, double rj) {
+  double lo = fmin(ri, rj), hi = fmax(ri, rj);
+  double v = 4.0 * 3.14159265358979323846 / (2 * l + 1) / hi;
+  for (int k = 0; k < l; ++k) v *= lo / hi;
+  return v;
+}
+
+__device__ inline int l_of(int L) { return L == 0 ? 0 : (L < 4 ? 1 : 2); }
+
+// X block (i, j) of one site: one workgroup per (site, i, j)
+__global__ void project_kernel(ScreenTabs T, const int4* blocks, const double* chi0,
+                               double* X) {
+  __shared__ double t1[9 * 4096 / 16];   // nL x nang, nang <= 256
+  const int4 bk = blocks[blockIdx.x];
+  const SiteMeta m = T.meta[bk.x];
+  const int i = bk.y, j = bk.z, A = m.nang, nL = m.nL;
+  const int npts = m.nrad * A;
+  const double* yw = T.yw + m.yw_off;
+  const double* c = chi0 + m.chi_off + (long long)(i * A) * npts + j * A;
+  for (int it = threadIdx.x; it < nL * A; it += blockDim.x) {
+    const int L = it / A, b = it % A;
+    double s = 0;
+    for (int a = 0; a < A; ++a) s += yw[L * A + a] * c[(long long)a * npts + b];
+    t1[L * A + b] = s;
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < nL * nL; it += blockDim.x) {
+    const int L = it / nL, Lp = it % nL;
+    double s = 0;
+    for (int b = 0; b < A; ++b) s += t1[L * A + b] * yw[Lp * A + b];
+    X[m.w_off + (long long)(L * m.nrad + i) * m.n + Lp * m.nrad + j] = s;
+  }
+}
+
+// augmented [eps | V] rows: one workgroup per (site, row)
+__global__ void eps_kernel(ScreenTabs T, const int2* rows, const double* X, double* M) {
+  const int2 rw = rows[blockIdx.x];
+  const SiteMeta m = T.meta[rw.x];
+  const int row = rw.y, n = m.n, R = m.nrad;
+  const int L = row / R, i = row % R, l = l_of(L);
+  const double* r = T.radii + m.rad_off;
+  const double* u = T.u + m.rad_off;
+  const double* x = X + m.w_off;
+  double* out = M + 2 * m.w_off + (long long)row * 2 * n;
+  for (int c = threadIdx.x; c < 2 * n; c += blockDim.x) {
+    if (c < n) {
+      const int j = c % R;
+      double s = 0;
+      for (int q = 0; q < R; ++q) s += coulomb_l(l, r[i], r[q]) * u[q] * x[(long long)(L * R + q) * n + c];
+      out[c] = (c == row ? 1.0 : 0.0) - s * u[j];
+    } else {
+      const int cc = c - n, Lp = cc / R, j = cc % R;
+      out[c] = Lp == L ? coulomb_l(l, r[i], r[j]) : 0.0;
+    }
+  }
+}
+
+// Gauss-Jordan with partial pivoting on the n x 2n augmented matrix of one site
+__global__ void __launch_bounds__(1024) gauss_jordan_kernel(ScreenTabs T, double* M, double* W_out,
+                                                            const long long* w_out_off) {
+  __shared__ double fac[288 + 32];
+  __shared__ double red_v[1024 / 64];
+  __shared__ int red_i[1024 / 64];
+  __shared__ int piv_s;
+  const SiteMeta m = T.meta[blockIdx.x];
+  const int n = m.n, n2 = 2 * n;
+  double* A = M + 2 * m.w_off;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  for (int col = 0; col < n; ++col) {
+    // pivot: the largest |A[r][col]| for r >= col (lowest row on ties)
+    double best = -1.0;
+    int bi = col;
+    for (int r = col + tid; r < n; r += blockDim.x) {
+      double v = fabs(A[(long long)r * n2 + col]);
+      if (v > best) { best = v; bi = r; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      double ov = __shfl_xor(best, o);
+      int oi = __shfl_xor(bi, o);
+      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    }
+    if (lane == 0) { red_v[wave] = best; red_i[wave] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      double b = red_v[0];
+      int p = red_i[0];
+      for (int w = 1; w < nw; ++w)
+        if (red_v[w] > b || (red_v[w] == b && red_i[w] < p)) { b = red_v[w]; p = red_i[w]; }
+      piv_s = p;
+    }
+    __syncthreads();
+    const int p = piv_s;
+    if (p != col)
+      for (int c = tid; c < n2; c += blockDim.x) {
+        double a = A[(long long)col * n2 + c];
+        A[(long long)col * n2 + c] = A[(long long)p * n2 + c];
+        A[(long long)p * n2 + c] = a;
+      }
+    __syncthreads();
+    const double inv = 1.0 / A[(long long)col * n2 + col];
+    for (int r = tid; r < n; r += blockDim.x) fac[r] = A[(long long)r * n2 + col];
+    __syncthreads();
+    for (int c = col + tid; c < n2; c += blockDim.x) A[(long long)col * n2 + c] *= inv;
+    __syncthreads();
+    // eliminate column col from every other row (columns > col of the left block, all of the right)
+    const int width = n2 - col - 1;
+    for (long long it = tid; it < (long long)n * width; it += blockDim.x) {
+      const int r = (int)(it / width);
+      const int c = col + 1 + (int)(it % width);
+      if (r != col) A[(long long)r * n2 + c] -= fac[r] * A[(long long)col * n2 + c];
+    }
+    __syncthreads();
+  }
+  double* W = W_out + w_out_off[blockIdx.x];
+  for (long long it = tid; it < (long long)n * n; it += blockDim.x) {
+    const int r = (int)(it / n), c = (int)(it % n);
+    W[it] = A[(long long)r * n2 + n + c];
+  }
+}
+
+// rho_L = P rho and h = D rho_L for one site; optional loss h^T W h
+__global__ void charge_kernel(ScreenTabs T, const double* rho, const double* W,
+                              const long long* w_out_off, double* h_out, double* loss) {
+  __shared__ double h[288 + 32];
+  __shared__ double part[1024 / 64];
+  const SiteMeta m = T.meta[blockIdx.x];
+  const int R = m.nrad, A = m.nang, n = m.n;
+  const double* yw = T.yw + m.yw_off;
+  const double* u = T.u + m.rad_off;
+  for (int q = threadIdx.x; q < n; q += blockDim.x) {
+    const int L = q / R, i = q % R;
+    double s = 0;
+    for (int a = 0; a < A; ++a) s += yw[L * A + a] * rho[m.pt_off + (long long)i * A + a];
+    h[q] = s * u[i];
+    h_out[m.h_off + q] = s * u[i];
+  }
+  __syncthreads();
+  if (!loss) return;
+  const double* w = W + w_out_off[blockIdx.x];
+  double acc = 0;
+  for (long long it = threadIdx.x; it < (long long)n * n; it += blockDim.x) {
+    const int r = (int)(it / n), c = (int)(it % n);
+    acc += h[r] * w[it] * h[c];
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0;
+    for (int w2 = 0; w2 < (int)(blockDim.x >> 6); ++w2) s += part[w2];
+    loss[blockIdx.x] = s;
+  }
+}
+
+// dX = D (W^T G W^T) D for one site; G = dL/dW, or h h^T when dLdW is NULL.
+// Two passes through small tiles: T1 = W^T G, then dX = T1 W^T.
+__global__ void wtgw_pass1(ScreenTabs T, const double* W, const long long* w_out_off,
+                           const double* G, const double* h, double* T1, int rank_one) {
+  // grid: (site, row tile) ; each thread a column
+  const int site = blockIdx.y;
+  const SiteMeta m = T.meta[site];
+  const int n = m.n;
+  const int r = blockIdx.x;
+  if (r >= n) return;
+  const double* w = W + w_out_off[site];
+  const double* g = G ? G + w_out_off[site] : nullptr;
+  const double* hv = h + m.h_off;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    double s = 0;
+    if (rank_one) {
+      // (W^T h h^T)[r][c] = (sum_q W[q][r] h[q]) h[c]
+      for (int q = 0; q < n; ++q) s += w[(long long)q * n + r] * hv[q];
+      s *= hv[c];
+    } else {
+      for (int q = 0; q < n; ++q) s += w[(long long)q * n + r] * g[(long long)q * n + c];
+    }
+    T1[m.w_off + (long long)r * n + c] = s;
+  }
+}
+
+__global__ void wtgw_pass2(ScreenTabs T, const double* W, const long long* w_out_off,
+                           const double* T1, double* dX) {
+  const int site = blockIdx.y;
+  const SiteMeta m = T.meta[site];
+  const int n = m.n, R = m.nrad;
+  const int r = blockIdx.x;
+  if (r >= n) return;
+  const double* w = W + w_out_off[site];
+  const double* u = T.u + m.rad_off;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    double s = 0;
+    for (int q = 0; q < n; ++q) s += T1[m.w_off + (long long)r * n + q] * w[(long long)c * n + q];
+    dX[m.w_off + (long long)r * n + c] = s * u[r % R] * u[c % R];
+  }
+}
+
+// dL/dchi0 block (i, j) = sum_{L,L'} yw[L][a] dX[(L,i),(L',j)] yw[L'][b]
+__global__ void lambda_kernel(ScreenTabs T, const int4* blocks, const double* dX, double* out) {
+  __shared__ double u1[9 * 256];
+  __shared__ double dxb[81];
+  const int4 bk = blocks[blockIdx.x];
+  const SiteMeta m = T.meta[bk.x];
+  const int i = bk.y, j = bk.z, A = m.nang, nL = m.nL, R = m.nrad, n = m.n;
+  const int npts = R * A;
+  const double* yw = T.yw + m.yw_off;
+  for (int it = threadIdx.x; it < nL * nL; it += blockDim.x) {
+    const int L = it / nL, Lp = it % nL;
+    dxb[it] = dX[m.w_off + (long long)(L * R + i) * n + Lp * R + j];
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < nL * A; it += blockDim.x) {
+    const int L = it / A, b = it % A;
+    double s = 0;
+    for (int Lp = 0; Lp < nL; ++Lp) s += dxb[L * nL + Lp] * yw[Lp * A + b];
+    u1[L * A + b] = s;
+  }
+  __syncthreads();
+  double* o = out + m.chi_off + (long long)(i * A) * npts + j * A;
+  for (int it = threadIdx.x; it < A * A; it += blockDim.x) {
+    const int a = it / A, b = it % A;
+    double s = 0;
+    for (int L = 0; L < nL; ++L) s += yw[L * A + a] * u1[L * A + b];
+    o[(long long)a * npts + b] = s;
+  }
+}
+
+// real spherical harmonics, l <= 2, order L = l*l + l + m
+void real_ylm(double x, double y, double z, double* Y) {
+  const double pi = 3.14159265358979323846;
+  const double c0 = 0.5 / std::sqrt(pi);
+  const double c1 = std::sqrt(3.0 / (4.0 * pi));
+  const double c2 = std::sqrt(15.0 / (4.0 * pi));
+  const double c20 = std::sqrt(5.0 / (16.0 * pi));
+  Y[0] = c0;
+  Y[1] = c1 * y;
+  Y[2] = c1 * z;
+  Y[3] = c1 * x;
+  Y[4] = c2 * x * y;
+  Y[5] = c2 * y * z;
+  Y[6] = c20 * (3.0 * z * z - 1.0);
+  Y[7] = c2 * x * z;
+  Y[8] = 0.5 * c2 * (x * x - y * y);
+}
+
+struct HostTabs {
+  std::vector<SiteMeta> meta;
+  std::vector<double> radii, u, yw;
+  std::vector<int4> blocks;
+  std::vector<int2> rows;
+  std::vector<long long> w_out_off;
+  long long w_total = 0;   // sum n^2
+  long long n_total = 0;   // sum n
+  int max_n = 0;
+};
+
+void build_tabs(const lrs_ctx* ctx, HostTabs& H) {
+  const int nL = (ctx->lmax + 1) * (ctx->lmax + 1);
+  long long chi = 0, w = 0, ywo = 0;
+  for (int s = 0; s < ctx->nsites; ++s) {
+    SiteMeta m;
+    m.nrad = ctx->nrad[s];
+    m.nang = ctx->nang[s];
+    m.nL = nL;
+    m.n = nL * m.nrad;
+    m.rad_off = ctx->rad_off[s];
+    m.yw_off = (int)ywo;
+    m.chi_off = chi;
+    m.w_off = w;
+    m.pt_off = ctx->site_off[s];
+    m.h_off = H.n_total;
+    H.meta.push_back(m);
+    H.w_out_off.push_back(w);
+    for (int L = 0; L < nL; ++L)
+      for (int a = 0; a < m.nang; ++a) {
+        const double* p = &ctx->ang_xyz[3 * (size_t)(ctx->ang_off[s] + a)];
+        double Y[9];
+        real_ylm(p[0], p[1], p[2], Y);
+        H.yw.push_back(Y[L] * ctx->ang_w[ctx->ang_off[s] + a]);
+      }
+    ywo += (long long)nL * m.nang;
+    for (int i = 0; i < m.nrad; ++i)
+      for (int j = 0; j < m.nrad; ++j) H.blocks.push_back(make_int4(s, i, j, 0));
+    for (int r = 0; r < m.n; ++r) H.rows.push_back(make_int2(s, r));
+    chi += (long long)m.nrad * m.nang * m.nrad * m.nang;
+    w += (long long)m.n * m.n;
+    H.n_total += m.n;
+    H.max_n = std::max(H.max_n, m.n);
+  }
+  H.w_total = w;
+  H.radii = ctx->radii;
+  H.u = ctx->rad_w;
+}
+
+// device layout of screen_tab: meta | radii | u | yw | blocks | rows | w_out_off
+struct DevTabs {
+  ScreenTabs t;
+  const int4* blocks;
+  const int2* rows;
+  const long long* w_out_off;
+  int nblocks, nrows;
+};
+
+hipError_t upload_tabs(lrs_ctx* ctx, const HostTabs& H, DevTabs& D) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  size_t o_meta = take(H.meta.size() * sizeof(SiteMeta));
+  size_t o_rad = take(H.radii.size() * 8), o_u = take(H.u.size() * 8), o_yw = take(H.yw.size() * 8);
+  size_t o_blk = take(H.blocks.size() * sizeof(int4)), o_rows = take(H.rows.size() * sizeof(int2));
+  size_t o_wo = take(H.w_out_off.size() * 8);
+  if (ctx->screen_tab.bytes < off) {
+    if (ctx->screen_tab.p) {
+      (void)hipFree(ctx->screen_tab.p);
+      ctx->bytes_in_use -= ctx->screen_tab.bytes;
+      ctx->screen_tab.p = nullptr;
+      ctx->screen_tab.bytes = 0;
+    }
+    hipError_t e = hipMalloc(&ctx->screen_tab.p, off);
+    if (e != hipSuccess) return e;
+    ctx->screen_tab.bytes = off;
+    ctx->bytes_in_use += off;
+  }
+  char* b = (char*)ctx->screen_tab.p;
+  hipStream_t s = ctx->stream;
+  hipError_t e = hipSuccess;
+  auto put = [&](size_t o, const void* src, size_t bytes) {
+    if (e == hipSuccess && bytes) e = hipMemcpyAsync(b + o, src, bytes, hipMemcpyHostToDevice, s);
+  };
+  put(o_meta, H.meta.data(), H.meta.size() * sizeof(SiteMeta));
+  put(o_rad, H.radii.data(), H.radii.size() * 8);
+  put(o_u, H.u.data(), H.u.size() * 8);
+  put(o_yw, H.yw.data(), H.yw.size() * 8);
+  put(o_blk, H.blocks.data(), H.blocks.size() * sizeof(int4));
+  put(o_rows, H.rows.data(), H.rows.size() * sizeof(int2));
+  put(o_wo, H.w_out_off.data(), H.w_out_off.size() * 8);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);   // host tables are freed on return
+  D.t.meta = (const SiteMeta*)(b + o_meta);
+  D.t.radii = (const double*)(b + o_rad);
+  D.t.u = (const double*)(b + o_u);
+  D.t.yw = (const double*)(b + o_yw);
+  D.blocks = (const int4*)(b + o_blk);
+  D.rows = (const int2*)(b + o_rows);
+  D.w_out_off = (const long long*)(b + o_wo);
+  D.nblocks = (int)H.blocks.size();
+  D.nrows = (int)H.rows.size();
+  return e;
+}
+
+hipError_t ensure_dev(lrs_ctx* ctx, DevBuf& b, size_t bytes) {
+  bytes = (bytes + 255) / 256 * 256;
+  if (b.p && b.bytes >= bytes) return hipSuccess;
+  if (b.p) {
+    (void)hipFree(b.p);
+    ctx->bytes_in_use -= b.bytes;
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  if (ctx->max_bytes && ctx->bytes_in_use + bytes > ctx->max_bytes) return hipErrorOutOfMemory;
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  b.bytes = bytes;
+  ctx->bytes_in_use += bytes;
+  return hipSuccess;
+}
+
+}  // namespace
+
+// work layout: X [w_total] | M [2 w_total] | h [n_total]; W_last [w_total]; rho_last [nrows]
+hipError_t launch_screen_forward(lrs_ctx* ctx, const double* chi0_ss, double* W_out,
+                                 const double* rho, double* loss_out) {
+  HostTabs H;
+  build_tabs(ctx, H);
+  if (H.max_n > 288) return hipErrorInvalidValue;
+  for (const auto& m : H.meta)
+    if (m.nang > 256) return hipErrorInvalidValue;
+  DevTabs D;
+  hipError_t e = upload_tabs(ctx, H, D);
+  if (e != hipSuccess) return e;
+  e = ensure_dev(ctx, ctx->work, (size_t)(3 * H.w_total + H.n_total) * 8);
+  if (e == hipSuccess) e = ensure_dev(ctx, ctx->W_last, (size_t)H.w_total * 8);
+  if (e == hipSuccess && rho) e = ensure_dev(ctx, ctx->rho_last, (size_t)ctx->nrows * 8);
+  if (e != hipSuccess) return e;
+  double* X = (double*)ctx->work.p;
+  double* M = X + H.w_total;
+  double* h = M + 2 * H.w_total;
+  hipLaunchKernelGGL(project_kernel, dim3(D.nblocks), dim3(256), 0, ctx->stream, D.t, D.blocks,
+                     chi0_ss, X);
+  hipLaunchKernelGGL(eps_kernel, dim3(D.nrows), dim3(256), 0, ctx->stream, D.t, D.rows, X, M);
+  hipLaunchKernelGGL(gauss_jordan_kernel, dim3(ctx->nsites), dim3(1024), 0, ctx->stream, D.t, M,
+                     W_out, D.w_out_off);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(ctx->W_last.p, W_out, (size_t)H.w_total * 8, hipMemcpyDeviceToDevice,
+                     ctx->stream);
+  if (e != hipSuccess) return e;
+  ctx->have_rho = false;
+  if (rho) {
+    e = hipMemcpyAsync(ctx->rho_last.p, rho, (size_t)ctx->nrows * 8, hipMemcpyDeviceToDevice,
+                       ctx->stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(charge_kernel, dim3(ctx->nsites), dim3(256), 0, ctx->stream, D.t, rho,
+                       W_out, D.w_out_off, h, loss_out);
+    ctx->have_rho = true;
+  }
+  ctx->have_W = true;
+  return hipGetLastError();
+}
+
+hipError_t launch_screen_backward(lrs_ctx* ctx, const double* dL_dW, double* dL_dchi0) {
+  HostTabs H;
+  build_tabs(ctx, H);
+  DevTabs D;
+  hipError_t e = upload_tabs(ctx, H, D);
+  if (e != hipSuccess) return e;
+  double* X = (double*)ctx->work.p;     // reused as T1 and dX
+  double* M = X + H.w_total;
+  double* h = M + 2 * H.w_total;
+  double* T1 = X;
+  double* dX = M;
+  const double* W = (const double*)ctx->W_last.p;
+  if (!dL_dW) {
+    hipLaunchKernelGGL(charge_kernel, dim3(ctx->nsites), dim3(256), 0, ctx->stream, D.t,
+                       (const double*)ctx->rho_last.p, W, D.w_out_off, h, (double*)nullptr);
+  }
+  dim3 grid(H.max_n, ctx->nsites);
+  hipLaunchKernelGGL(wtgw_pass1, grid, dim3(256), 0, ctx->stream, D.t, W, D.w_out_off, dL_dW, h,
+                     T1, dL_dW ? 0 : 1);
+  hipLaunchKernelGGL(wtgw_pass2, grid, dim3(256), 0, ctx->stream, D.t, W, D.w_out_off, T1, dX);
+  hipLaunchKernelGGL(lambda_kernel, dim3(D.nblocks), dim3(256), 0, ctx->stream, D.t, D.blocks, dX,
+                     dL_dchi0);
+  return hipGetLastError();
+}
+
+}  // namespace lrs

@@ -1,0 +1,66 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports every
+declared entry point, and validates band sets before touching a device."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "lrs.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lrs_[A-Za-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2005_07834_amd as P
+    names = _declared()
+    assert len(names) >= 15
+    bound = {n for n, _, _ in P.SIGNATURES}
+    for n in names:
+        assert hasattr(P.lib, n), n
+        assert n in bound, f"{n} has no binding"
+    assert P.lib.lrs_version().decode().startswith("lrs")
+
+
+def test_check_bands_status_codes():
+    import paper_2005_07834_amd as P
+    E = np.array([[-1.0, -0.5, 0.2, 0.9], [-0.9, -0.4, 0.3, 1.0]])
+    assert P.check_bands(E, 2) == P.LRS_OK
+    assert P.check_bands(E, 0) == P.LRS_EINVAL
+    assert P.check_bands(E, 4) == P.LRS_EINVAL
+    bad = E.copy()
+    bad[1, 1] = math.nan
+    assert P.check_bands(bad, 2) == P.LRS_ENONFINITE
+    ov = E.copy()
+    ov[1, 1] = 0.25          # occupied at k=1 above the unoccupied bottom at k=0
+    assert P.check_bands(ov, 2) == P.LRS_ENOGAP
+    assert P.check_bands(ov, 2, delta=0.01) == P.LRS_OK   # metallic regularisation needs no gap
+    assert P.check_bands(E, 2, mu=0.1) == P.LRS_OK
+    assert P.check_bands(E, 2, mu=-0.45) == P.LRS_ENOGAP  # mu below the valence top
+    assert P.check_bands(E, 2, delta=-1.0) == P.LRS_EINVAL
+
+
+def test_create_without_gpu_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    import ctypes as C
+    import paper_2005_07834_amd as P
+    h = C.c_void_p(1)
+    st = P.lib.lrs_create(C.byref(h), 0, None)
+    assert st == P.LRS_EDEVICE
+    assert not h.value
+    P.lib.lrs_destroy(None)                      # a NULL context is accepted
+    assert P.lib.lrs_last_error(None) == b"null context"
+
+
+def test_null_context_is_rejected():
+    import paper_2005_07834_amd as P
+    assert P.lib.lrs_compute_chi0(None, -1, 0, 0, None) == P.LRS_EINVAL
+    assert P.lib.lrs_set_orbitals(None, 1, 2, 1, 2, None, 0.0, 0.0, None, 0, 0.0) == P.LRS_EINVAL
+    assert P.lib.lrs_tune(None, 0) == P.LRS_EINVAL

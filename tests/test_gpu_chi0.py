@@ -1,0 +1,248 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Error measure (one per comparison): max |gpu - ref| / max |ref| over the compared entries.
+Bars: FP64 path vs the same quadrature 1e-12, vs exact denominators 1e-6; BF16X2 vs the
+same quadrature 1e-4; FP32 and FP16X2 1e-5.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import chi0 as cz
+from oracle import grads as gr
+from oracle import quadrature as q
+from oracle import screen as sc
+from tests.conftest import workload
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2005_07834_amd as P
+    return P
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def oracle_scale(w, n):
+    mu = q.mid_gap(w.energies, w.nocc)
+    x, y = q.offsets(w.energies, w.nocc, mu)
+    return q.auto_scale(x, y, n)
+
+
+def make_ctx(P, w, n, scale, kind=0, grid=True):
+    ctx = P.Context(0)
+    ctx.set_orbitals(w.energies, w.nocc, w.psi_grid if grid else None, w.grid_dV)
+    ctx.set_sites(w.sites, w.psi_site)
+    ctx.make_quadrature(kind, n, scale)
+    return ctx
+
+
+@pytest.fixture(scope="module")
+def tiny_ref():
+    w = workload("tiny")
+    n = w.n_terms
+    s = oracle_scale(w, n)
+    ps, pg = w.psi_site.numpy(), w.psi_grid.numpy()
+    terms = cz.terms_for(w.energies, w.nocc, "time", n, s)
+    return dict(w=w, n=n, scale=s, ps=ps, pg=pg, terms=terms,
+                quad_grid=cz.chi0_quad(ps, pg, w.nocc, 2, *terms),
+                quad_site=cz.chi0_quad(ps, ps, w.nocc, 2, *terms),
+                exact_grid=cz.chi0_exact(ps, pg, w.energies, w.nocc),
+                exact_site=cz.chi0_exact(ps, ps, w.energies, w.nocc))
+
+
+def test_auto_scale_matches_oracle(P, tiny_ref):
+    w = tiny_ref["w"]
+    say("auto scale tiny")
+    ctx = make_ctx(P, w, tiny_ref["n"], 0.0)
+    qd = ctx.get_quadrature()
+    assert abs(qd["scale"] / tiny_ref["scale"] - 1) < 1e-12
+    assert abs(qd["mu"] - q.mid_gap(w.energies, w.nocc)) < 1e-15
+    a, wgl = q.gauss_legendre_01(tiny_ref["n"])
+    assert np.abs(qd["tau"] - qd["scale"] * a / (1 - a)).max() < 1e-12 * qd["tau"].max()
+
+
+def test_tiny_fp64_parity(P, tiny_ref):
+    w = tiny_ref["w"]
+    say("tiny fp64 grid+site")
+    ctx = make_ctx(P, w, tiny_ref["n"], tiny_ref["scale"])
+    g = ctx.chi0(-1, P.COLS_GRID, P.FP64).cpu().numpy()
+    s = ctx.site_blocks(ctx.chi0(-1, P.COLS_SITE, P.FP64))[0].cpu().numpy()
+    say("  grid vs quad", rel(g, tiny_ref["quad_grid"]), "vs exact", rel(g, tiny_ref["exact_grid"]))
+    say("  site vs quad", rel(s, tiny_ref["quad_site"]), "vs exact", rel(s, tiny_ref["exact_site"]))
+    assert rel(g, tiny_ref["quad_grid"]) < 1e-12
+    assert rel(s, tiny_ref["quad_site"]) < 1e-12
+    assert rel(g, tiny_ref["exact_grid"]) < 1e-6
+    assert rel(s, tiny_ref["exact_site"]) < 1e-6
+    # single-site selection gives the same block; repeated calls are bitwise identical
+    g0 = ctx.chi0(0, P.COLS_GRID, P.FP64).cpu().numpy()
+    assert np.array_equal(g0, g)
+    g2 = ctx.chi0(-1, P.COLS_GRID, P.FP64).cpu().numpy()
+    assert np.array_equal(g2, g)
+
+
+@pytest.mark.parametrize("prec,tol", [("bf16x2", 1e-4), ("fp32", 1e-5), ("fp16x2", 1e-5)])
+def test_tiny_reduced_precision(P, tiny_ref, prec, tol):
+    w = tiny_ref["w"]
+    say("tiny", prec)
+    ctx = make_ctx(P, w, tiny_ref["n"], tiny_ref["scale"])
+    g = ctx.chi0(-1, P.COLS_GRID, prec).cpu().numpy()
+    s = ctx.site_blocks(ctx.chi0(-1, P.COLS_SITE, prec))[0].cpu().numpy()
+    eg, es = rel(g, tiny_ref["quad_grid"]), rel(s, tiny_ref["quad_site"])
+    say(f"  {prec}: grid {eg:.3e} site {es:.3e} exact {rel(g, tiny_ref['exact_grid']):.3e}")
+    assert eg < tol and es < tol
+
+
+def test_tiny_frequency_rule(P, tiny_ref):
+    w = tiny_ref["w"]
+    say("tiny freq rule")
+    ctx = make_ctx(P, w, 16, 0.0, kind=P.QUAD_FREQ)
+    s = ctx.site_blocks(ctx.chi0(-1, P.COLS_SITE, P.FP64))[0].cpu().numpy()
+    terms = cz.terms_for(w.energies, w.nocc, "freq", 16)
+    ref = cz.chi0_quad(tiny_ref["ps"], tiny_ref["ps"], w.nocc, 2, *terms)
+    assert abs(ctx.get_quadrature()["scale"] / q.zeta(w.energies, q.mid_gap(w.energies, w.nocc)) - 1) < 1e-13
+    say("  freq vs quad", rel(s, ref))
+    assert rel(s, ref) < 1e-12
+
+
+def test_generic_terms_and_errors(P, tiny_ref):
+    w = tiny_ref["w"]
+    say("generic terms + error paths")
+    ctx = P.Context(0)
+    with pytest.raises(P.LrsError) as e:
+        ctx.make_quadrature(0, 16, 0.0)
+    assert e.value.status == P.LRS_ESTATE
+    ctx.set_orbitals(w.energies, w.nocc, w.psi_grid, w.grid_dV)
+    ctx.set_sites(w.sites, w.psi_site)
+    c, al, be = tiny_ref["terms"]
+    ctx.set_quadrature(c, al, be)
+    s = ctx.site_blocks(ctx.chi0(-1, P.COLS_SITE, P.FP64))[0].cpu().numpy()
+    assert rel(s, tiny_ref["quad_site"]) < 1e-12
+    with pytest.raises(P.LrsError) as e:
+        ctx.chi0_backward(torch.zeros(w.nrows ** 2, dtype=torch.float64, device="cuda"))
+    assert e.value.status == P.LRS_EUNSUPPORTED
+    buf = torch.empty(16, dtype=torch.float64, device="cuda")
+    assert P.lib.lrs_compute_chi0(ctx.h, 3, P.COLS_GRID, P.FP64, buf.data_ptr()) == P.LRS_EINVAL
+    assert P.lib.lrs_compute_chi0(ctx.h, -1, 7, P.FP64, buf.data_ptr()) == P.LRS_EINVAL
+    assert P.lib.lrs_compute_chi0(ctx.h, -1, P.COLS_GRID, 9, buf.data_ptr()) == P.LRS_EINVAL
+    assert b"precision" in P.lib.lrs_last_error(ctx.h)
+    bad = w.psi_site.clone()
+    bad[0, 3, 5] = float("nan")
+    with pytest.raises(P.LrsError) as e:
+        ctx.set_sites(w.sites, bad)
+    assert e.value.status == P.LRS_ENONFINITE
+
+
+@pytest.fixture(scope="module")
+def prod():
+    return workload("production")
+
+
+def _sample(n, m, rng):
+    return rng.integers(0, n, size=m)
+
+
+def test_production_fp64_and_bf16_sampled(P, prod):
+    w = prod
+    n = w.n_terms
+    s = oracle_scale(w, n)
+    say("production fp64/bf16x2, 2 sites, 8 k")
+    ctx = make_ctx(P, w, n, s)
+    rng = np.random.default_rng(11)
+    ps = w.psi_site.numpy()
+    pg = w.psi_grid.numpy()
+    terms = cz.terms_for(w.energies, w.nocc, "time", n, s)
+    rows = _sample(w.nrows, 300, rng)
+    cols = _sample(w.ngrid ** 3, 300, rng)
+    ref_q = cz.chi0_quad_entries(ps[:, :, rows], pg[:, :, cols], w.nocc, 2, *terms)
+    ref_x = cz.chi0_exact_entries(ps[:, :, rows], pg[:, :, cols], w.energies, w.nocc)
+    for prec, tq, tx in [("fp64", 1e-12, 1e-6), ("bf16x2", 1e-4, 1e-4)]:
+        g = ctx.chi0(-1, P.COLS_GRID, prec)
+        got = g[torch.as_tensor(rows), torch.as_tensor(cols)].cpu().numpy()
+        say(f"  grid {prec}: vs quad {rel(got, ref_q):.3e} vs exact {rel(got, ref_x):.3e}")
+        assert rel(got, ref_q) < tq and rel(got, ref_x) < tx
+        del g
+    # site x site blocks of both sites, sampled
+    blocks = ctx.site_blocks(ctx.chi0(-1, P.COLS_SITE, P.FP64))
+    off = w.site_offsets
+    for si in range(len(w.sites)):
+        nsp = w.sites[si].npts
+        r = _sample(nsp, 200, rng)
+        c2 = _sample(nsp, 200, rng)
+        got = blocks[si][torch.as_tensor(r), torch.as_tensor(c2)].cpu().numpy()
+        ref = cz.chi0_quad_entries(ps[:, :, off[si] + r], ps[:, :, off[si] + c2], w.nocc, 2, *terms)
+        say(f"  site {si} block vs quad {rel(got, ref):.3e}")
+        assert rel(got, ref) < 1e-12
+
+
+def test_W_parity_and_loss(P, tiny_ref):
+    w = tiny_ref["w"]
+    say("tiny W + loss")
+    ctx = make_ctx(P, w, tiny_ref["n"], tiny_ref["scale"])
+    site = w.sites[0]
+    # the solve alone, on the oracle's chi0
+    chi_ref = tiny_ref["quad_site"]
+    Wg, loss = ctx.screen_W(torch.as_tensor(chi_ref.ravel()).cuda(), rho=w.rho_test, want_loss=True)
+    Wref = sc.screen_W(chi_ref, site)
+    say("  W (oracle chi0)", rel(ctx.W_blocks(Wg)[0].cpu().numpy(), Wref))
+    assert rel(ctx.W_blocks(Wg)[0].cpu().numpy(), Wref) < 1e-12
+    Lref = sc.test_charge_loss(Wref, w.rho_test, site)
+    assert abs(loss.item() / Lref - 1) < 1e-12
+    # end to end from the GPU chi0
+    chi = ctx.chi0(-1, P.COLS_SITE, P.FP64)
+    Wg2, _ = ctx.screen_W(chi)
+    assert rel(ctx.W_blocks(Wg2)[0].cpu().numpy(), Wref) < 1e-11
+    assert rel(ctx.W_blocks(Wg2)[0].cpu().numpy(), sc.screen_W(tiny_ref["exact_site"], site)) < 1e-6
+
+
+def test_screen_backward_matches_rank_one_sensitivity(P, tiny_ref):
+    w = tiny_ref["w"]
+    say("tiny screen backward")
+    ctx = make_ctx(P, w, tiny_ref["n"], tiny_ref["scale"])
+    site = w.sites[0]
+    chi = tiny_ref["quad_site"]
+    ctx.screen_W(torch.as_tensor(chi.ravel()).cuda(), rho=w.rho_test, want_loss=True)
+    lam = ctx.screen_W_backward().cpu().numpy().reshape(site.npts, site.npts)
+    W = sc.screen_W(chi, site)
+    d = sc.radial_weights(site)
+    g = sc.projector(site).T @ (d * (0.5 * (W + W.T) @ (d * sc.charge_moments(w.rho_test, site))))
+    ref = np.outer(g, g)
+    say("  lambda", rel(lam, ref))
+    assert rel(lam, ref) < 1e-10
+    # an explicit dL/dW gives the same as the stored test charge
+    h = d * sc.charge_moments(w.rho_test, site)
+    lam2 = ctx.screen_W_backward(torch.as_tensor(np.outer(h, h).ravel()).cuda()).cpu().numpy()
+    assert rel(lam2.reshape(lam.shape), lam) < 1e-12
+
+
+def test_chi0_backward_vs_oracle(P, tiny_ref):
+    w = tiny_ref["w"]
+    n, s = tiny_ref["n"], tiny_ref["scale"]
+    say("tiny chi0 backward")
+    ctx = make_ctx(P, w, n, s)
+    chi = ctx.chi0(-1, P.COLS_SITE, P.FP64)
+    ctx.screen_W(chi, rho=w.rho_test, want_loss=True)
+    lam = ctx.screen_W_backward()
+    dE, dpsi = ctx.chi0_backward(lam)
+    L, dE_ref, dpsi_ref = gr.loss_and_grads(tiny_ref["ps"], w.energies, w.nocc, 2, w.sites,
+                                            w.rho_test, "time", n, s)
+    eE, eP = rel(dE.cpu().numpy(), dE_ref), rel(dpsi.cpu().numpy(), dpsi_ref)
+    say(f"  dE {eE:.3e} dpsi {eP:.3e}")
+    assert eE < 1e-9 and eP < 1e-9
+    dE2, dpsi2 = ctx.chi0_backward(lam)
+    assert torch.equal(dE, dE2) and torch.equal(dpsi, dpsi2)
