@@ -418,6 +418,9 @@ TileShape shape_p(int v) {
 
 int chi0_num_variants(int) { return kNumVariants; }
 
+// fastest variant measured on the precision workload (the tuner can override it)
+int chi0_default_variant(int) { return 2; }
+
 namespace {
 template <int PREC, int V>
 int occ_v() {

@@ -187,8 +187,15 @@ lrs_status install_terms(lrs_ctx* ctx, Quad& q, const std::vector<double>& c,
     double ma = 0, mb = 0;
     for (int i = 0; i < Ko; ++i) ma = std::max(ma, alpha[(size_t)t * Ko + i]);
     for (int i = 0; i < Ku; ++i) mb = std::max(mb, beta[(size_t)t * Ku + i]);
-    double sa = ma > 0 ? std::ldexp(1.0, -(int)std::floor(std::log2(ma))) : 1.0;
-    double sb = mb > 0 ? std::ldexp(1.0, -(int)std::floor(std::log2(mb))) : 1.0;
+    // A term whose largest weight on either side is below 1e-200 contributes less than
+    // c * 1e-200 to any band pair and is dropped (its power-of-two normalisation would
+    // overflow); it stays in the list with zero weights.
+    if (!(ma >= 1e-200) || !(mb >= 1e-200)) {
+      q.c[t] = 0.0;
+      continue;
+    }
+    double sa = std::ldexp(1.0, -(int)std::floor(std::log2(ma)));
+    double sb = std::ldexp(1.0, -(int)std::floor(std::log2(mb)));
     q.c[t] = c[t] / (sa * sb);
     double* w = &q.w[(size_t)t * Kp];
     double* dw = &q.dw[(size_t)t * Kp];
@@ -312,13 +319,13 @@ lrs_status get_plan(lrs_ctx* ctx, int site, int cols, int prec, int variant, Pla
 }
 
 int pick_variant(lrs_ctx* ctx, int prec) {
-  if (ctx->tuned_variant[prec] >= 0) return ctx->tuned_variant[prec];
   const char* e = std::getenv("LRS_VARIANT");
   if (e) {
     int v = std::atoi(e);
     if (v >= 0 && v < chi0_num_variants(prec)) return v;
   }
-  return 0;
+  if (ctx->tuned_variant[prec] >= 0) return ctx->tuned_variant[prec];
+  return chi0_default_variant(prec);
 }
 
 lrs_status run_chi0(lrs_ctx* ctx, int site, int cols, int prec, int variant, double* out,

@@ -157,6 +157,7 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 // chi0.hip
 int chi0_num_variants(int prec);
 int chi0_blocks_per_cu(int prec, int variant);
+int chi0_default_variant(int prec);
 TileShape chi0_shape(int prec, int variant);
 hipError_t launch_chi0(int prec, int variant, int grid, const void* a_re, const void* a_im,
                        int lda, const void* b_tiles, int b_nchunks, const void* w,
