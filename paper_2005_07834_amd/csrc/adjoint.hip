@@ -229,7 +229,7 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, const double* dL_dchi0, double* dL
   // operands: site rows (FP64), site columns (FP64 tiles), k-major orbitals
   if (ensure_site_tiles_for(ctx, LRS_FP64) != LRS_OK) return hipErrorOutOfMemory;
   Plan* plan = nullptr;
-  if (plan_for(ctx, -1, LRS_COLS_SITE, LRS_FP64, 0, &plan) != LRS_OK) return hipErrorOutOfMemory;
+  if (plan_for(ctx, -1, LRS_COLS_SITE, LRS_FP64, 0, 1, &plan) != LRS_OK) return hipErrorOutOfMemory;
   hipError_t e = ensure(ctx, ctx->psi_site_f64, (size_t)2 * ctx->K_pad * ctx->rows_pad * 8);
   if (e != hipSuccess) return e;
   e = launch_derive_site_kmajor((const double*)ctx->site_f64.p, ctx->rows_pad, ctx->K_pad,
@@ -292,7 +292,6 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, const double* dL_dchi0, double* dL
       (e = launch_fill_zero(dL_dpsi, (size_t)2 * ctx->nk * ctx->nb * ctx->nrows * 8, st)))
     return e;
 
-  const size_t plane = (size_t)ctx->rows_pad * ctx->K_pad;
   BwdParams B;
   B.hu_re = hu_re;
   B.hu_im = hu_im;
@@ -313,13 +312,16 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, const double* dL_dchi0, double* dL
   B.grad = dL_dpsi;
   B.part = part;
   for (int t = 0; t < T; ++t) {
-    e = launch_green_adjoint(plan->grid, ctx->site_f64.p, (const double*)ctx->site_f64.p + plane,
-                             ctx->K_pad, ctx->site_tiles[LRS_FP64].p, ctx->K_pad / kChunkF64,
-                             (const double*)ctx->w_f64.p + (size_t)t * Kp,
-                             (const double*)ctx->c_dev.p + t, ctx->Ko_pad / kChunkF64,
-                             ctx->Ku_pad / kChunkF64, (const TileDesc*)plan->tiles.p,
-                             plan->ntiles, lam, hu_re, hu_im, ho_re, ho_im, st);
-    if (e != hipSuccess) return e;
+    for (const Batch& bt : plan->batches) {
+      if (bt.ntiles == 0) continue;
+      if (ensure_site_operand(ctx, LRS_FP64, bt, t, 1) != LRS_OK) return hipErrorOutOfMemory;
+      if (ensure_park(ctx, LRS_FP64, 0, bt.grid) != LRS_OK) return hipErrorOutOfMemory;
+      e = launch_green_adjoint(bt.grid, ctx->a_tiles.p, bt.nrb, ctx->site_tiles[LRS_FP64].p,
+                               ctx->site_cols_pad / 16, ctx->K_pad / kChunkF64, (const double*)ctx->c_dev.p + t,
+                               ctx->Ko_pad / kChunkF64, (const TileDesc*)plan->tiles.p + bt.tile0,
+                               bt.ntiles, lam, hu_re, hu_im, ho_re, ho_im, ctx->park.p, st);
+      if (e != hipSuccess) return e;
+    }
     B.w = wn + (size_t)t * Kp;
     B.dw = dwn + (size_t)t * Kp;
     B.ct = ctx->quad.c[t];

@@ -7,12 +7,20 @@
 // as complex GEMMs in the real 4M form (G_r = p b_r + q b_i, G_i = p b_i - q b_r with
 // p + i q = weight * psi(r)) on MFMA, then accumulates
 //     chi(r,r') += c_l (Re G_o Re G_u + Im G_o Im G_u)
-// in FP64 registers.  After the last term the tile is scaled by -2 s / N_k^2 and stored.
+// in FP64 (read-modify-write of the tile's own output entries once per term).  The last
+// term applies the prefactor -2 s / N_k^2.
 //
-// The per-term weight is applied to the small site operand while it is staged into LDS, so
-// the large column operand is identical for every term.  BF16X2 / FP16X2 split the weighted
-// site value into hi + lo halves on the fly; the column operand is pre-split.  Each real
-// product takes hi*hi + hi*lo + lo*hi (lo*lo dropped) with FP32 accumulation.
+// Operands.  Both sides arrive as 4 KiB fragment tiles (16 rows or columns x one K chunk,
+// every lane's matrix-core operand contiguous): the column operand is packed once per set of
+// orbitals; the weighted site operand of every term is built once per call by
+// prep_site_kernel (the per-term weight lives on the small site side, so the large column
+// operand is the same for every term).  BF16X2 / FP16X2 carry hi + lo halves of each value;
+// each real product takes hi*hi + hi*lo + lo*hi (lo*lo dropped) with FP32 accumulation.
+//
+// Pipeline.  The chunks of a tile (term-major, then K) stream through a two-slot LDS ring
+// filled by 16-byte direct-to-LDS loads, with two register sets of operand fragments: while
+// the matrix cores work on chunk q, chunk q+1's fragments are read from LDS and chunk q+2's
+// tiles travel from global memory into the slot chunk q came from (see chi0_kernel).
 //
 // Persistent launch: gridDim.x workgroups walk a host-built tile list; workgroup b handles
 // tiles b' + i * gridDim.x with b' = (b % 8) * (gridDim.x / 8) + b / 8, so that the
@@ -29,23 +37,23 @@ namespace {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 typedef __attribute__((__vector_size__(4 * sizeof(double)))) double f64x4;
 typedef __attribute__((__vector_size__(4 * sizeof(unsigned int)))) unsigned int u32x4;
 
 struct Chi0Params {
-  const void* a_re;
-  const void* a_im;
-  int lda;                      // = K_pad (row stride of the site operand and of the weights)
-  const unsigned char* b;       // column operand fragment tiles [colblock][chunk][4 KiB]
-  int b_nchunks;
-  const void* w;                // weights [T][K_pad]
+  const unsigned char* a;       // weighted site operand tiles [term][chunk][rowblock][tile]
+  int a_nrb;                    // row blocks per term in a
+  const unsigned char* b;       // column operand tiles [chunk][colblock][tile]
+  int b_ncb;                    // column blocks in b
+  int nch;                      // chunks per term (= K_pad / chunk)
   const double* c;              // [T]
-  int T, nch_o, nch_u;
+  int T, nch_o;
   const TileDesc* tiles;
   int ntiles;
   double* out;
   double pref;
-  float a_scale;                // power-of-two prescale of the site operand (FP16X2)
+  unsigned char* park;          // per-workgroup space for G_o between the two phases
   // adjoint mode (FP64 only): with T = 1, write lam * conj(G_u) and lam * conj(G_o)
   const double* lam;
   double* hu_re;
@@ -54,308 +62,478 @@ struct Chi0Params {
   double* ho_im;
 };
 
+// Matrix-core shape per precision.  FP64 and FP32 use 16 x 16 accumulator blocks (4 values
+// per lane); the split 16-bit paths use the 32 x 32 x 16 instructions (16 values per lane),
+// which sustain twice the rate of the 16 x 16 x 32 form on gfx950.
+//   KC  K values per chunk, TB bytes per fragment tile (16 rows x KC x planes).
 template <int PREC>
 struct Prec;
 template <>
 struct Prec<LRS_FP64> {
   using acc_t = f64x4;
-  using site_t = double;
-  static constexpr int KC = 16;
+  static constexpr int KC = 16, TB = 4096, BLK = 16, ELEMS = 4;
 };
 template <>
 struct Prec<LRS_FP32> {
   using acc_t = f32x4;
-  using site_t = float;
-  static constexpr int KC = 32;
+  static constexpr int KC = 32, TB = 4096, BLK = 16, ELEMS = 4;
 };
 template <>
 struct Prec<LRS_BF16X2> {
-  using acc_t = f32x4;
-  using site_t = float;
-  static constexpr int KC = 32;
+  using acc_t = f32x16;
+  static constexpr int KC = 16, TB = 2048, BLK = 32, ELEMS = 16;
 };
 template <>
 struct Prec<LRS_FP16X2> {
-  using acc_t = f32x4;
-  using site_t = float;
-  static constexpr int KC = 32;
+  using acc_t = f32x16;
+  static constexpr int KC = 16, TB = 2048, BLK = 32, ELEMS = 16;
 };
 
-// ----------------------------------------------------------------------------- staging
-// Site operand: item (row r, lane group g) covers the K values one lane of the 16-row block
-// holds; the row operand's chunk-local order makes them contiguous (see pack.hip).
+// Row and column (inside a BLK x BLK accumulator block) of element e of a lane:
+//   f32 16x16:   (4 (lane/16) + e, lane%16)
+//   f64 16x16x4: (4 e + lane/16, lane%16)
+//   f32 32x32:   (8 (e/4) + 4 (lane/32) + e%4, lane%32)
 template <int PREC>
-__device__ __forceinline__ void stage_a_item(const Chi0Params& P, unsigned char* lds_a, int r,
-                                             int g, int a_row, int t, int kbase) {
-  const int blk = r >> 4;
-  const int slot = g * 16 + (r & 15);
-  unsigned char* base = lds_a + blk * kTileBytes;
+__device__ __forceinline__ void elem_rc(int lane, int e, int& r, int& c) {
   if constexpr (PREC == LRS_FP64) {
-    const double* are = (const double*)P.a_re + (size_t)a_row * P.lda + kbase + g * 4;
-    const double* aim = (const double*)P.a_im + (size_t)a_row * P.lda + kbase + g * 4;
-    const double* wt = (const double*)P.w + (size_t)t * P.lda + kbase + g * 4;
-    f64x4 re = *(const f64x4*)are, im = *(const f64x4*)aim, w = *(const f64x4*)wt;
-    *(f64x4*)(base + slot * 32) = re * w;
-    *(f64x4*)(base + 2048 + slot * 32) = im * w;
+    r = 4 * e + (lane >> 4);
+    c = lane & 15;
   } else if constexpr (PREC == LRS_FP32) {
-    const float* are = (const float*)P.a_re + (size_t)a_row * P.lda + kbase + g * 8;
-    const float* aim = (const float*)P.a_im + (size_t)a_row * P.lda + kbase + g * 8;
-    const float* wt = (const float*)P.w + (size_t)t * P.lda + kbase + g * 8;
+    r = 4 * (lane >> 4) + e;
+    c = lane & 15;
+  } else {
+    r = 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+    c = lane & 31;
+  }
+}
+
+template <class T>
+__device__ __forceinline__ T zero_acc() {
+  T v;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      f32x4 re = *(const f32x4*)(are + 4 * h), im = *(const f32x4*)(aim + 4 * h),
-            w = *(const f32x4*)(wt + 4 * h);
-      *(f32x4*)(base + slot * 32 + 16 * h) = re * w;
-      *(f32x4*)(base + 2048 + slot * 32 + 16 * h) = im * w;
+  for (int e = 0; e < (int)(sizeof(T) / sizeof(v[0])); ++e) v[e] = 0;
+  return v;
+}
+
+// ----------------------------------------------------------------------------- site prep
+// Weighted site operand for terms [t0, t0 + nt) and row blocks [rb0, rb0 + nrb) of the slot
+// layout, with p + i q = w_t(k) * psi_k(row) * a_scale.  One thread per (term, row block,
+// chunk, lane slot) writes that slot of every plane:
+//   FP64 (chunk 16, 64 slots):  slot l holds row l%16, k = 4 s + l/16, s = 0..3, planes p, q
+//   FP32 (chunk 32, 64 slots):  slot l holds row l%16, k = 4 s + l/16, s = 0..7, planes p, q
+//   split (chunk 16, 32 slots): slot l holds row l%16, k = 8 (l/16) + e, e = 0..7,
+//                               planes p_hi, p_lo, q_hi, q_lo
+__device__ inline size_t site_pos(int r, int k, int K_pad) {
+  int ch = k >> 4, kl = k & 15;
+  return (size_t)r * K_pad + ch * 16 + (kl & 3) * 4 + (kl >> 2);
+}
+
+template <int PREC>
+__global__ void prep_site_kernel(const double* site, int rows_pad, int K_pad, const int* slot_row,
+                                 int rb0, int nrb, const double* w, int t0, int nt, double a_scale,
+                                 unsigned char* out) {
+  constexpr int KC = Prec<PREC>::KC, TB = Prec<PREC>::TB;
+  constexpr int SLOTS = (PREC == LRS_BF16X2 || PREC == LRS_FP16X2) ? 32 : 64;
+  const int nch = K_pad / KC;
+  long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long long)nt * nrb * nch * SLOTS) return;
+  const int lane = (int)(gid % SLOTS);
+  long long tile = gid / SLOTS;              // ((t * nch + ch) * nrb + rb): chunk-major
+  const int rb = (int)(tile % nrb);
+  tile /= nrb;
+  const int ch = (int)(tile % nch);
+  const int t = (int)(tile / nch);
+  const int row = slot_row[(rb0 + rb) * 16 + (lane & 15)];
+  const size_t plane = (size_t)rows_pad * K_pad;
+  const double* wt = w + (size_t)(t0 + t) * K_pad;
+  unsigned char* base = out + (((size_t)t * nch + ch) * nrb + rb) * TB;
+  auto val = [&](int k, double& p, double& q) {
+    if (row < 0) {
+      p = 0.0;
+      q = 0.0;
+      return;
+    }
+    const size_t o = site_pos(row, k, K_pad);
+    const double f = wt[k] * a_scale;
+    p = site[o] * f;
+    q = site[plane + o] * f;
+  };
+  if constexpr (PREC == LRS_FP64) {
+    double* d = (double*)base;
+    for (int s = 0; s < 4; ++s) {
+      double p, q;
+      val(ch * 16 + 4 * s + (lane >> 4), p, q);
+      d[lane * 4 + s] = p;
+      d[256 + lane * 4 + s] = q;
+    }
+  } else if constexpr (PREC == LRS_FP32) {
+    float* d = (float*)base;
+    for (int s = 0; s < 8; ++s) {
+      double p, q;
+      val(ch * 32 + 4 * s + (lane >> 4), p, q);
+      d[lane * 8 + s] = (float)p;
+      d[512 + lane * 8 + s] = (float)q;
     }
   } else {
-    const float* are = (const float*)P.a_re + (size_t)a_row * P.lda + kbase + g * 8;
-    const float* aim = (const float*)P.a_im + (size_t)a_row * P.lda + kbase + g * 8;
-    const float* wt = (const float*)P.w + (size_t)t * P.lda + kbase + g * 8;
-    using half_t = typename std::conditional<PREC == LRS_BF16X2, bf16x8, f16x8>::type;
     using elem_t = typename std::conditional<PREC == LRS_BF16X2, __bf16, _Float16>::type;
-    half_t ph, pl, qh, ql;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      f32x4 re = *(const f32x4*)(are + 4 * h), im = *(const f32x4*)(aim + 4 * h),
-            w = *(const f32x4*)(wt + 4 * h);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        float p = re[e] * w[e] * P.a_scale;
-        float q = im[e] * w[e] * P.a_scale;
-        elem_t phe = (elem_t)p, qhe = (elem_t)q;
-        ph[4 * h + e] = phe;
-        qh[4 * h + e] = qhe;
-        pl[4 * h + e] = (elem_t)(p - (float)phe);
-        ql[4 * h + e] = (elem_t)(q - (float)qhe);
-      }
+    elem_t* d = (elem_t*)base;
+    for (int e = 0; e < 8; ++e) {
+      double p, q;
+      val(ch * 16 + 8 * (lane >> 4) + e, p, q);
+      const elem_t ph = (elem_t)(float)p, qh = (elem_t)(float)q;
+      d[lane * 8 + e] = ph;
+      d[256 + lane * 8 + e] = (elem_t)(float)(p - (double)(float)ph);
+      d[512 + lane * 8 + e] = qh;
+      d[768 + lane * 8 + e] = (elem_t)(float)(q - (double)(float)qh);
     }
-    *(half_t*)(base + slot * 16) = ph;
-    *(half_t*)(base + 1024 + slot * 16) = pl;
-    *(half_t*)(base + 2048 + slot * 16) = qh;
-    *(half_t*)(base + 3072 + slot * 16) = ql;
   }
 }
 
 // ----------------------------------------------------------------------------- MFMA step
+// One chunk of the wave's MB x NB tiles of 16 rows, in two parts: load_frags() reads every
+// operand fragment the chunk needs from LDS into registers, mma_frags() runs the matrix-core
+// instructions on them.
 template <int PREC, int MB, int NB>
-__device__ __forceinline__ void mma_chunk(const unsigned char* lds_a, const unsigned char* lds_b,
-                                          int lane,
-                                          typename Prec<PREC>::acc_t (&gr)[MB][NB],
-                                          typename Prec<PREC>::acc_t (&gi)[MB][NB]) {
+struct Frags;
+
+template <int MB, int NB>
+struct Frags<LRS_FP64, MB, NB> {
+  f64x4 p[MB], q[MB], br[NB], bi[NB];   // element s <-> k = 4 s + lane/16
+};
+template <int MB, int NB>
+struct Frags<LRS_FP32, MB, NB> {
+  f32x4 p[MB][2], q[MB][2], br[NB][2], bi[NB][2];   // [h][e] <-> k = 4 (4 h + e) + lane/16
+};
+// split paths: one 32-row block per two 16-row tiles; lane l reads row l%32 of the block at
+// k = 8 (l/32) + e, which sits in tile (l%32)/16 at slot (l/32) * 16 + l%16.
+template <int MB, int NB>
+struct Frags<LRS_BF16X2, MB, NB> {
+  bf16x8 ph[MB / 2], pl[MB / 2], qh[MB / 2], ql[MB / 2];
+  bf16x8 rh[NB / 2], rl[NB / 2], ih[NB / 2], il[NB / 2];
+};
+template <int MB, int NB>
+struct Frags<LRS_FP16X2, MB, NB> {
+  f16x8 ph[MB / 2], pl[MB / 2], qh[MB / 2], ql[MB / 2];
+  f16x8 rh[NB / 2], rl[NB / 2], ih[NB / 2], il[NB / 2];
+};
+
+template <int PREC, int MB, int NB>
+__device__ __forceinline__ void load_frags(const unsigned char* lds_a, const unsigned char* lds_b,
+                                           int lane, Frags<PREC, MB, NB>& f) {
+  constexpr int TB = Prec<PREC>::TB;
   if constexpr (PREC == LRS_FP64) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      double p[MB], q[MB];
+    for (int i = 0; i < MB; ++i) {
+      f.p[i] = *(const f64x4*)(lds_a + i * TB + lane * 32);
+      f.q[i] = *(const f64x4*)(lds_a + i * TB + 2048 + lane * 32);
+    }
 #pragma unroll
-      for (int i = 0; i < MB; ++i) {
-        p[i] = ((const double*)(lds_a + i * kTileBytes))[lane * 4 + s];
-        q[i] = ((const double*)(lds_a + i * kTileBytes + 2048))[lane * 4 + s];
-      }
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        double br = ((const double*)(lds_b + j * kTileBytes))[lane * 4 + s];
-        double bi = ((const double*)(lds_b + j * kTileBytes + 2048))[lane * 4 + s];
-#pragma unroll
-        for (int i = 0; i < MB; ++i) {
-          gr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(p[i], br, gr[i][j], 0, 0, 0);
-          gr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(q[i], bi, gr[i][j], 0, 0, 0);
-          gi[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(p[i], bi, gi[i][j], 0, 0, 0);
-          gi[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-q[i], br, gi[i][j], 0, 0, 0);
-        }
-      }
+    for (int j = 0; j < NB; ++j) {
+      f.br[j] = *(const f64x4*)(lds_b + j * TB + lane * 32);
+      f.bi[j] = *(const f64x4*)(lds_b + j * TB + 2048 + lane * 32);
     }
   } else if constexpr (PREC == LRS_FP32) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      f32x4 p[MB], q[MB];
 #pragma unroll
       for (int i = 0; i < MB; ++i) {
-        p[i] = *(const f32x4*)(lds_a + i * kTileBytes + lane * 32 + 16 * h);
-        q[i] = *(const f32x4*)(lds_a + i * kTileBytes + 2048 + lane * 32 + 16 * h);
+        f.p[i][h] = *(const f32x4*)(lds_a + i * TB + lane * 32 + 16 * h);
+        f.q[i][h] = *(const f32x4*)(lds_a + i * TB + 2048 + lane * 32 + 16 * h);
       }
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
-        f32x4 br = *(const f32x4*)(lds_b + j * kTileBytes + lane * 32 + 16 * h);
-        f32x4 bi = *(const f32x4*)(lds_b + j * kTileBytes + 2048 + lane * 32 + 16 * h);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-#pragma unroll
-          for (int i = 0; i < MB; ++i) {
-            gr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(p[i][e], br[e], gr[i][j], 0, 0, 0);
-            gr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(q[i][e], bi[e], gr[i][j], 0, 0, 0);
-            gi[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(p[i][e], bi[e], gi[i][j], 0, 0, 0);
-            gi[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(-q[i][e], br[e], gi[i][j], 0, 0, 0);
-          }
-        }
+        f.br[j][h] = *(const f32x4*)(lds_b + j * TB + lane * 32 + 16 * h);
+        f.bi[j][h] = *(const f32x4*)(lds_b + j * TB + 2048 + lane * 32 + 16 * h);
       }
     }
   } else {
     using half_t = typename std::conditional<PREC == LRS_BF16X2, bf16x8, f16x8>::type;
-    half_t ph[MB], pl[MB], qh[MB], ql[MB], nqh[MB], nql[MB];
+    const int lofs = ((lane & 31) >> 4) * TB + (lane >> 5) * 256 + (lane & 15) * 16;
 #pragma unroll
-    for (int i = 0; i < MB; ++i) {
-      const unsigned char* a = lds_a + i * kTileBytes + lane * 16;
-      ph[i] = *(const half_t*)(a);
-      pl[i] = *(const half_t*)(a + 1024);
-      qh[i] = *(const half_t*)(a + 2048);
-      ql[i] = *(const half_t*)(a + 3072);
-      // negation flips the sign bit of every 16-bit element
-      u32x4 m = {0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
-      nqh[i] = (half_t)((u32x4)qh[i] ^ m);
-      nql[i] = (half_t)((u32x4)ql[i] ^ m);
+    for (int i = 0; i < MB / 2; ++i) {
+      const unsigned char* a = lds_a + i * 2 * TB + lofs;
+      f.ph[i] = *(const half_t*)(a);
+      f.pl[i] = *(const half_t*)(a + 512);
+      f.qh[i] = *(const half_t*)(a + 1024);
+      f.ql[i] = *(const half_t*)(a + 1536);
     }
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const unsigned char* b = lds_b + j * kTileBytes + lane * 16;
-      half_t rh = *(const half_t*)(b), rl = *(const half_t*)(b + 1024);
-      half_t ih = *(const half_t*)(b + 2048), il = *(const half_t*)(b + 3072);
+    for (int j = 0; j < NB / 2; ++j) {
+      const unsigned char* b = lds_b + j * 2 * TB + lofs;
+      f.rh[j] = *(const half_t*)(b);
+      f.rl[j] = *(const half_t*)(b + 512);
+      f.ih[j] = *(const half_t*)(b + 1024);
+      f.il[j] = *(const half_t*)(b + 1536);
+    }
+  }
+}
+
+template <int PREC, int MB, int NB>
+__device__ __forceinline__ void mma_frags(
+    const Frags<PREC, MB, NB>& f,
+    typename Prec<PREC>::acc_t (&gr)[MB * 16 / Prec<PREC>::BLK][NB * 16 / Prec<PREC>::BLK],
+    typename Prec<PREC>::acc_t (&gi)[MB * 16 / Prec<PREC>::BLK][NB * 16 / Prec<PREC>::BLK]) {
+  if constexpr (PREC == LRS_FP64) {
 #pragma unroll
-      for (int i = 0; i < MB; ++i) {
-        if constexpr (PREC == LRS_BF16X2) {
-          gr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ph[i], rh, gr[i][j], 0, 0, 0);
-          gr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ph[i], rl, gr[i][j], 0, 0, 0);
-          gr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pl[i], rh, gr[i][j], 0, 0, 0);
-          gr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qh[i], ih, gr[i][j], 0, 0, 0);
-          gr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qh[i], il, gr[i][j], 0, 0, 0);
-          gr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ql[i], ih, gr[i][j], 0, 0, 0);
-          gi[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ph[i], ih, gi[i][j], 0, 0, 0);
-          gi[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ph[i], il, gi[i][j], 0, 0, 0);
-          gi[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pl[i], ih, gi[i][j], 0, 0, 0);
-          gi[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nqh[i], rh, gi[i][j], 0, 0, 0);
-          gi[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nqh[i], rl, gi[i][j], 0, 0, 0);
-          gi[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nql[i], rh, gi[i][j], 0, 0, 0);
-        } else {
-          gr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ph[i], rh, gr[i][j], 0, 0, 0);
-          gr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ph[i], rl, gr[i][j], 0, 0, 0);
-          gr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(pl[i], rh, gr[i][j], 0, 0, 0);
-          gr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(qh[i], ih, gr[i][j], 0, 0, 0);
-          gr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(qh[i], il, gr[i][j], 0, 0, 0);
-          gr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ql[i], ih, gr[i][j], 0, 0, 0);
-          gi[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ph[i], ih, gi[i][j], 0, 0, 0);
-          gi[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ph[i], il, gi[i][j], 0, 0, 0);
-          gi[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(pl[i], ih, gi[i][j], 0, 0, 0);
-          gi[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(nqh[i], rh, gi[i][j], 0, 0, 0);
-          gi[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(nqh[i], rl, gi[i][j], 0, 0, 0);
-          gi[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(nql[i], rh, gi[i][j], 0, 0, 0);
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          gr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.p[i][s], f.br[j][s], gr[i][j], 0, 0, 0);
+          gi[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.p[i][s], f.bi[j][s], gi[i][j], 0, 0, 0);
+          gr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.q[i][s], f.bi[j][s], gr[i][j], 0, 0, 0);
+          gi[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-f.q[i][s], f.br[j][s], gi[i][j], 0, 0, 0);
         }
+  } else if constexpr (PREC == LRS_FP32) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            const float p = f.p[i][h][e], q = f.q[i][h][e];
+            const float br = f.br[j][h][e], bi = f.bi[j][h][e];
+            gr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(p, br, gr[i][j], 0, 0, 0);
+            gi[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(p, bi, gi[i][j], 0, 0, 0);
+            gr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(q, bi, gr[i][j], 0, 0, 0);
+            gi[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(-q, br, gi[i][j], 0, 0, 0);
+          }
+  } else {
+    using half_t = typename std::conditional<PREC == LRS_BF16X2, bf16x8, f16x8>::type;
+    // negation flips the sign bit of every 16-bit element
+    const u32x4 m = {0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+    auto mf = [](half_t a, half_t b, f32x16 c) {
+      if constexpr (PREC == LRS_BF16X2)
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+      else
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    };
+#pragma unroll
+    for (int i = 0; i < MB / 2; ++i) {
+      const half_t ph = f.ph[i], pl = f.pl[i], qh = f.qh[i], ql = f.ql[i];
+      const half_t nqh = (half_t)((u32x4)qh ^ m);
+      const half_t nql = (half_t)((u32x4)ql ^ m);
+      // G_r += p b_r + q b_i, G_i += p b_i - q b_r; consecutive instructions update
+      // different accumulators
+#pragma unroll
+      for (int j = 0; j < NB / 2; ++j) {
+        gr[i][j] = mf(ph, f.rh[j], gr[i][j]);
+        gi[i][j] = mf(ph, f.ih[j], gi[i][j]);
+      }
+#pragma unroll
+      for (int j = 0; j < NB / 2; ++j) {
+        gr[i][j] = mf(ph, f.rl[j], gr[i][j]);
+        gi[i][j] = mf(ph, f.il[j], gi[i][j]);
+      }
+#pragma unroll
+      for (int j = 0; j < NB / 2; ++j) {
+        gr[i][j] = mf(pl, f.rh[j], gr[i][j]);
+        gi[i][j] = mf(pl, f.ih[j], gi[i][j]);
+      }
+#pragma unroll
+      for (int j = 0; j < NB / 2; ++j) {
+        gr[i][j] = mf(qh, f.ih[j], gr[i][j]);
+        gi[i][j] = mf(nqh, f.rh[j], gi[i][j]);
+      }
+#pragma unroll
+      for (int j = 0; j < NB / 2; ++j) {
+        gr[i][j] = mf(qh, f.il[j], gr[i][j]);
+        gi[i][j] = mf(nqh, f.rl[j], gi[i][j]);
+      }
+#pragma unroll
+      for (int j = 0; j < NB / 2; ++j) {
+        gr[i][j] = mf(ql, f.ih[j], gr[i][j]);
+        gi[i][j] = mf(nql, f.rh[j], gi[i][j]);
       }
     }
   }
 }
 
 // ----------------------------------------------------------------------------- kernel
+// Per chunk q of a tile (term-major, then K), with chunk q's fragments already in registers:
+//   wait for chunk q+1's global->LDS loads and barrier (which also retires chunk q's LDS reads)
+//   read chunk q+1's fragments into the other register set
+//   start chunk q+2's loads into the LDS slot chunk q occupied (its data is in registers)
+//   run chunk q's matrix-core instructions
+// so the LDS reads and the global loads of later chunks overlap the matrix-core work.  The
+// chunks of one term run in two phases (occupied then unoccupied K), each an even number of
+// chunks, so the two register sets alternate in a fixed pattern.
 template <int PREC, int WMW, int WNW, int MB, int NB, int MODE>
 __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
   using acc_t = typename Prec<PREC>::acc_t;
-  constexpr int KC = Prec<PREC>::KC;
+  using frag_t = Frags<PREC, MB, NB>;
+  constexpr int TB = Prec<PREC>::TB;
+  constexpr int BLK = Prec<PREC>::BLK, ELEMS = Prec<PREC>::ELEMS;
+  constexpr int AM = MB * 16 / BLK, AN = NB * 16 / BLK;   // accumulator blocks per wave
+  static_assert(AM * BLK == MB * 16 && AN * BLK == NB * 16, "wave tile vs block size");
   constexpr int BM = WMW * MB * 16;
   constexpr int BN = WNW * NB * 16;
-  constexpr int THREADS = WMW * WNW * 64;
-  constexpr int A_BYTES = (BM / 16) * kTileBytes;
-  constexpr int B_BYTES = (BN / 16) * kTileBytes;
-  __shared__ __attribute__((aligned(16))) unsigned char lds[A_BYTES + B_BYTES];
-  unsigned char* lds_a = lds;
-  unsigned char* lds_b = lds + A_BYTES;
+  constexpr int A_BYTES = (BM / 16) * TB;
+  constexpr int B_BYTES = (BN / 16) * TB;
+  constexpr int STAGE = A_BYTES + B_BYTES;
+  constexpr int NWAVES = WMW * WNW;
+  constexpr int NLOAD = STAGE / 1024;   // 1 KiB wave-wide loads per stage
+  static_assert(NLOAD % NWAVES == 0, "stage split");
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WNW, wn = wave % WNW;
   const int G = gridDim.x;
   const int bslot = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
-  const int nch = P.nch_o + P.nch_u;
+  const int nch = P.nch;
+  const int nseq = P.T * nch;
+  const size_t a_term = (size_t)P.a_nrb * nch * TB;
+
+  // global -> LDS slot for chunk q: the stage's A tiles and B tiles are each one contiguous
+  // run; the wave's share of its 1 KiB pieces goes straight into LDS (lane l's 16 bytes at
+  // +16 l).
+  auto issue = [&](const TileDesc& td, int q, int slot) {
+    const int t = q / nch, ch = q - t * nch;
+    const unsigned char* ab =
+        P.a + t * a_term + ((size_t)ch * P.a_nrb + (td.a_row0 >> 4)) * TB + lane * 16;
+    const unsigned char* bb = P.b + ((size_t)ch * P.b_ncb + (td.b_col0 >> 4)) * TB + lane * 16;
+    unsigned char* dst = lds + slot * STAGE;
+#pragma unroll
+    for (int k = 0; k < NLOAD / NWAVES; ++k) {
+      const int j = k * NWAVES + wave;
+      const unsigned char* src = j < A_BYTES / 1024 ? ab + j * 1024 : bb + (j - A_BYTES / 1024) * 1024;
+      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)src,
+                                       (void __attribute__((address_space(3)))*)(dst + j * 1024),
+                                       16, 0, 0);
+    }
+  };
+
+  // G_o of the current term waits here (one slot per workgroup) while G_u accumulates.
+  // Addresses used once per term are rebuilt from opaque copies of their inputs inside the term
+  // loop, so that the compiler does not hoist them and keep them live across the chunk loop.
+  // A workgroup barrier does not wait for the vector-memory counter, so each wave drains its
+  // own global->LDS loads before the barrier that hands their bytes to the other waves.
+  auto dma_wait = [] { __builtin_amdgcn_s_waitcnt(0x0F70); };  // vmcnt(0)
+  auto opaque = [](int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+  };
+  auto park_at = [&](int ln, int i, int j, int comp) -> acc_t* {
+    acc_t* park = (acc_t*)(P.park + (size_t)blockIdx.x * NWAVES * AM * AN * 2 * 64 * sizeof(acc_t));
+    return park + (((size_t)(wave * AM + i) * AN + j) * 2 + comp) * 64 + ln;
+  };
 
   for (long long tau = bslot; tau < P.ntiles; tau += G) {
     const TileDesc td = P.tiles[tau];
-    double chi[MB][NB][4];
-#pragma unroll
-    for (int i = 0; i < MB; ++i)
-#pragma unroll
-      for (int j = 0; j < NB; ++j)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) chi[i][j][e] = 0.0;
+    acc_t gr[AM][AN], gi[AM][AN];
+    frag_t fa, fb;
 
-    for (int t = 0; t < P.T; ++t) {
-      acc_t go_r[MB][NB], go_i[MB][NB], gu_r[MB][NB], gu_i[MB][NB];
-#pragma unroll
-      for (int i = 0; i < MB; ++i)
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          go_r[i][j] = acc_t{0, 0, 0, 0};
-          go_i[i][j] = acc_t{0, 0, 0, 0};
-          gu_r[i][j] = acc_t{0, 0, 0, 0};
-          gu_i[i][j] = acc_t{0, 0, 0, 0};
-        }
-      for (int ch = 0; ch < nch; ++ch) {
-        const int kbase = ch * KC;
-        __syncthreads();
-        // site operand, weighted by this term
-        for (int it = tid; it < BM * 4; it += THREADS)
-          stage_a_item<PREC>(P, lds_a, it >> 2, it & 3, td.a_row0 + (it >> 2), t, kbase);
-        // column operand: straight copy of BN/16 fragment tiles
-        const unsigned char* bsrc =
-            P.b + ((size_t)(td.b_col0 >> 4) * P.b_nchunks + ch) * kTileBytes;
-        for (int it = tid; it < (BN / 16) * (kTileBytes / 16); it += THREADS) {
-          const int blk = it / (kTileBytes / 16), off = it % (kTileBytes / 16);
-          *(u32x4*)(lds_b + blk * kTileBytes + off * 16) =
-              *(const u32x4*)(bsrc + (size_t)blk * P.b_nchunks * kTileBytes + off * 16);
-        }
-        __syncthreads();
-        const unsigned char* wa = lds_a + wm * MB * kTileBytes;
-        const unsigned char* wb = lds_b + wn * NB * kTileBytes;
-        if (ch < P.nch_o)
-          mma_chunk<PREC, MB, NB>(wa, wb, lane, go_r, go_i);
-        else
-          mma_chunk<PREC, MB, NB>(wa, wb, lane, gu_r, gu_i);
+    __syncthreads();                 // the previous tile is done with both slots
+    issue(td, 0, 0);
+    if (nseq > 1) issue(td, 1, 1);
+    dma_wait();
+    __syncthreads();                 // both slots landed
+    load_frags<PREC, MB, NB>(lds + wm * MB * TB, lds + A_BYTES + wn * NB * TB, lane, fa);
+    int q = 0;
+    // chunk q with its fragments in `cur`; the next chunk's fragments go to `nxt`
+    auto step = [&](frag_t& cur, frag_t& nxt) {
+      dma_wait();
+      __syncthreads();               // chunk q+1 landed (every wave waited on its loads);
+                                     // chunk q's LDS reads are complete
+      if (q + 1 < nseq) {
+        const unsigned char* s = lds + ((q + 1) & 1) * STAGE;
+        load_frags<PREC, MB, NB>(s + wm * MB * TB, s + A_BYTES + wn * NB * TB, lane, nxt);
       }
+      if (q + 2 < nseq) issue(td, q + 2, q & 1);
+      __builtin_amdgcn_sched_barrier(0);
+      mma_frags<PREC, MB, NB>(cur, gr, gi);
+      __builtin_amdgcn_sched_barrier(0);
+      ++q;
+    };
+    auto zero = [&] {
+#pragma unroll
+      for (int i = 0; i < AM; ++i)
+#pragma unroll
+        for (int j = 0; j < AN; ++j) {
+          gr[i][j] = zero_acc<acc_t>();
+          gi[i][j] = zero_acc<acc_t>();
+        }
+    };
+    for (int t = 0; t < P.T; ++t) {
+      zero();
+      for (int ch = 0; ch < P.nch_o; ch += 2) {
+        step(fa, fb);
+        step(fb, fa);
+      }
+      {
+        const int ln = opaque(lane);
+#pragma unroll
+        for (int i = 0; i < AM; ++i)
+#pragma unroll
+          for (int j = 0; j < AN; ++j) {
+            *park_at(ln, i, j, 0) = gr[i][j];
+            *park_at(ln, i, j, 1) = gi[i][j];
+          }
+      }
+      zero();
+      for (int ch = P.nch_o; ch < nch; ch += 2) {
+        step(fa, fb);
+        step(fb, fa);
+      }
+      // here gr, gi hold G_u; G_o comes back block by block
+      const int ln = opaque(lane);
+      const long long obase = td.out_off + opaque(0);
       if constexpr (MODE == 1) {
         // adjoint: Hu = lam * conj(G_u), Ho = lam * conj(G_o) on this tile (single term)
 #pragma unroll
-        for (int i = 0; i < MB; ++i)
+        for (int i = 0; i < AM; ++i)
 #pragma unroll
-          for (int j = 0; j < NB; ++j)
+          for (int j = 0; j < AN; ++j) {
+            const acc_t or_ = *park_at(ln, i, j, 0), oi_ = *park_at(ln, i, j, 1);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const int rr = (PREC == LRS_FP64) ? (4 * e + (lane >> 4)) : (4 * (lane >> 4) + e);
-              const int row = (wm * MB + i) * 16 + rr;
-              const int col = (wn * NB + j) * 16 + (lane & 15);
+            for (int e = 0; e < ELEMS; ++e) {
+              int rr, cc;
+              elem_rc<PREC>(ln, e, rr, cc);
+              const int row = wm * MB * 16 + i * BLK + rr;
+              const int col = wn * NB * 16 + j * BLK + cc;
               if (row < td.nrows && col < td.ncols) {
-                const long long o = td.out_off + (long long)row * td.ldo + col;
+                const long long o = obase + (long long)row * td.ldo + col;
                 const double l = P.lam[o];
-                P.hu_re[o] = l * (double)gu_r[i][j][e];
-                P.hu_im[o] = -l * (double)gu_i[i][j][e];
-                P.ho_re[o] = l * (double)go_r[i][j][e];
-                P.ho_im[o] = -l * (double)go_i[i][j][e];
+                P.hu_re[o] = l * (double)gr[i][j][e];
+                P.hu_im[o] = -l * (double)gi[i][j][e];
+                P.ho_re[o] = l * (double)or_[e];
+                P.ho_im[o] = -l * (double)oi_[e];
               }
             }
+          }
       } else {
+        // chi accumulates across terms in FP64 in the output itself (this tile's entries
+        // belong to this workgroup only); the last term applies the prefactor
         const double ct = P.c[t];
+        const bool first = t == 0, last = t == P.T - 1;
 #pragma unroll
-        for (int i = 0; i < MB; ++i)
+        for (int i = 0; i < AM; ++i)
 #pragma unroll
-          for (int j = 0; j < NB; ++j)
+          for (int j = 0; j < AN; ++j) {
+            const acc_t or_ = *park_at(ln, i, j, 0), oi_ = *park_at(ln, i, j, 1);
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-              chi[i][j][e] += ct * ((double)go_r[i][j][e] * (double)gu_r[i][j][e] +
-                                    (double)go_i[i][j][e] * (double)gu_i[i][j][e]);
+            for (int e = 0; e < ELEMS; ++e) {
+              int rr, cc;
+              elem_rc<PREC>(ln, e, rr, cc);
+              const int row = wm * MB * 16 + i * BLK + rr;
+              const int col = wn * NB * 16 + j * BLK + cc;
+              if (row < td.nrows && col < td.ncols) {
+                double* o = P.out + obase + (long long)row * td.ldo + col;
+                double v = ct * ((double)or_[e] * (double)gr[i][j][e] +
+                                 (double)oi_[e] * (double)gi[i][j][e]);
+                if (!first) v += *o;
+                if (last) v *= P.pref;
+                *o = v;
+              }
+            }
+          }
       }
     }
-    if constexpr (MODE == 1) continue;
-    // store: f32 16x16 accumulators hold (row 4*(lane/16)+e, col lane%16); the f64 16x16x4
-    // accumulator holds (row 4*e + lane/16, col lane%16)
-#pragma unroll
-    for (int i = 0; i < MB; ++i)
-#pragma unroll
-      for (int j = 0; j < NB; ++j)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int rr = (PREC == LRS_FP64) ? (4 * e + (lane >> 4)) : (4 * (lane >> 4) + e);
-          const int row = (wm * MB + i) * 16 + rr;
-          const int col = (wn * NB + j) * 16 + (lane & 15);
-          if (row < td.nrows && col < td.ncols)
-            P.out[td.out_off + (long long)row * td.ldo + col] = P.pref * chi[i][j][e];
-        }
   }
 }
 
@@ -368,34 +546,55 @@ struct Variant;
     static constexpr int WMW = A, WNW = B, MB = C, NB = D;             \
   };
 LRS_VARIANT(LRS_FP64, 0, 2, 2, 2, 2)
-LRS_VARIANT(LRS_FP64, 1, 2, 2, 2, 1)
-LRS_VARIANT(LRS_FP64, 2, 4, 2, 1, 2)
+LRS_VARIANT(LRS_FP64, 1, 2, 2, 2, 4)
+LRS_VARIANT(LRS_FP64, 2, 2, 2, 4, 2)
 LRS_VARIANT(LRS_FP32, 0, 2, 2, 2, 4)
 LRS_VARIANT(LRS_FP32, 1, 2, 2, 2, 2)
-LRS_VARIANT(LRS_FP32, 2, 4, 2, 1, 4)
-LRS_VARIANT(LRS_BF16X2, 0, 2, 2, 2, 4)
-LRS_VARIANT(LRS_BF16X2, 1, 2, 2, 2, 2)
-LRS_VARIANT(LRS_BF16X2, 2, 4, 2, 1, 4)
-LRS_VARIANT(LRS_FP16X2, 0, 2, 2, 2, 4)
-LRS_VARIANT(LRS_FP16X2, 1, 2, 2, 2, 2)
-LRS_VARIANT(LRS_FP16X2, 2, 4, 2, 1, 4)
+LRS_VARIANT(LRS_FP32, 2, 2, 2, 4, 2)
+LRS_VARIANT(LRS_BF16X2, 0, 2, 2, 4, 4)
+LRS_VARIANT(LRS_BF16X2, 1, 2, 2, 2, 4)
+LRS_VARIANT(LRS_BF16X2, 2, 2, 2, 4, 2)
+LRS_VARIANT(LRS_FP16X2, 0, 2, 2, 4, 4)
+LRS_VARIANT(LRS_FP16X2, 1, 2, 2, 2, 4)
+LRS_VARIANT(LRS_FP16X2, 2, 2, 2, 4, 2)
 #undef LRS_VARIANT
 constexpr int kNumVariants = 3;
 
 template <int PREC, int V>
+constexpr int lds_bytes_v() {
+  using Vt = Variant<PREC, V>;
+  return 2 * (Vt::WMW * Vt::MB + Vt::WNW * Vt::NB) * Prec<PREC>::TB;
+}
+
+template <int PREC, int V>
+constexpr size_t park_bytes_v() {
+  using Vt = Variant<PREC, V>;
+  return (size_t)Vt::WMW * Vt::WNW * (Vt::MB * 16 / Prec<PREC>::BLK) *
+         (Vt::NB * 16 / Prec<PREC>::BLK) * 2 * 64 * sizeof(typename Prec<PREC>::acc_t);
+}
+
+template <int PREC, int V, int MODE>
 hipError_t launch_v(int grid, const Chi0Params& P, hipStream_t s) {
   using Vt = Variant<PREC, V>;
-  hipLaunchKernelGGL((chi0_kernel<PREC, Vt::WMW, Vt::WNW, Vt::MB, Vt::NB, 0>), dim3(grid),
-                     dim3(Vt::WMW * Vt::WNW * 64), 0, s, P);
+  auto k = chi0_kernel<PREC, Vt::WMW, Vt::WNW, Vt::MB, Vt::NB, MODE>;
+  constexpr int lds = lds_bytes_v<PREC, V>();
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(k, dim3(grid), dim3(Vt::WMW * Vt::WNW * 64), lds, s, P);
   return hipGetLastError();
 }
 
 template <int PREC>
 hipError_t launch_p(int variant, int grid, const Chi0Params& P, hipStream_t s) {
   switch (variant) {
-    case 0: return launch_v<PREC, 0>(grid, P, s);
-    case 1: return launch_v<PREC, 1>(grid, P, s);
-    case 2: return launch_v<PREC, 2>(grid, P, s);
+    case 0: return launch_v<PREC, 0, 0>(grid, P, s);
+    case 1: return launch_v<PREC, 1, 0>(grid, P, s);
+    case 2: return launch_v<PREC, 2, 0>(grid, P, s);
   }
   return hipErrorInvalidValue;
 }
@@ -403,7 +602,8 @@ hipError_t launch_p(int variant, int grid, const Chi0Params& P, hipStream_t s) {
 template <int PREC, int V>
 TileShape shape_v() {
   using Vt = Variant<PREC, V>;
-  return TileShape{Vt::WMW * Vt::MB * 16, Vt::WNW * Vt::NB * 16, Vt::WMW * Vt::WNW * 64};
+  return TileShape{Vt::WMW * Vt::MB * 16, Vt::WNW * Vt::NB * 16, Vt::WMW * Vt::WNW * 64,
+                   park_bytes_v<PREC, V>()};
 }
 template <int PREC>
 TileShape shape_p(int v) {
@@ -414,21 +614,13 @@ TileShape shape_p(int v) {
   }
 }
 
-}  // namespace
-
-int chi0_num_variants(int) { return kNumVariants; }
-
-// fastest variant measured on the precision workload (the tuner can override it)
-int chi0_default_variant(int) { return 2; }
-
-namespace {
 template <int PREC, int V>
 int occ_v() {
   using Vt = Variant<PREC, V>;
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
           &n, reinterpret_cast<const void*>(&chi0_kernel<PREC, Vt::WMW, Vt::WNW, Vt::MB, Vt::NB, 0>),
-          Vt::WMW * Vt::WNW * 64, 0) != hipSuccess)
+          Vt::WMW * Vt::WNW * 64, lds_bytes_v<PREC, V>()) != hipSuccess)
     return 1;
   return n;
 }
@@ -440,7 +632,26 @@ int occ_p(int v) {
     default: return occ_v<PREC, 2>();
   }
 }
+
+template <int PREC>
+hipError_t prep_p(const double* site, int rows_pad, int K_pad, const int* slot_row, int rb0,
+                  int nrb, const double* w, int t0, int nt, double a_scale, void* out,
+                  hipStream_t s) {
+  const int nch = K_pad / Prec<PREC>::KC;
+  const int slots = (PREC == LRS_BF16X2 || PREC == LRS_FP16X2) ? 32 : 64;
+  const long long n = (long long)nt * nrb * nch * slots;
+  hipLaunchKernelGGL(prep_site_kernel<PREC>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     site, rows_pad, K_pad, slot_row, rb0, nrb, w, t0, nt, a_scale,
+                     (unsigned char*)out);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+int chi0_num_variants(int) { return kNumVariants; }
+
+// fastest variant measured on the precision workload (the tuner can override it)
+int chi0_default_variant(int) { return 0; }
 
 int chi0_blocks_per_cu(int prec, int variant) {
   switch (prec) {
@@ -460,26 +671,36 @@ TileShape chi0_shape(int prec, int variant) {
   }
 }
 
-hipError_t launch_chi0(int prec, int variant, int grid, const void* a_re, const void* a_im,
-                       int lda, const void* b_tiles, int b_nchunks, const void* w,
-                       const double* c, int T, int nch_o, int nch_u, const TileDesc* tiles,
-                       int ntiles, double* out, double pref, float a_scale, hipStream_t s) {
+hipError_t launch_prep_site(int prec, const double* site, int rows_pad, int K_pad,
+                            const int* slot_row, int rb0, int nrb, const double* w, int t0,
+                            int nt, double a_scale, void* out, hipStream_t s) {
+  switch (prec) {
+    case LRS_FP64: return prep_p<LRS_FP64>(site, rows_pad, K_pad, slot_row, rb0, nrb, w, t0, nt, a_scale, out, s);
+    case LRS_FP32: return prep_p<LRS_FP32>(site, rows_pad, K_pad, slot_row, rb0, nrb, w, t0, nt, a_scale, out, s);
+    case LRS_BF16X2: return prep_p<LRS_BF16X2>(site, rows_pad, K_pad, slot_row, rb0, nrb, w, t0, nt, a_scale, out, s);
+    case LRS_FP16X2: return prep_p<LRS_FP16X2>(site, rows_pad, K_pad, slot_row, rb0, nrb, w, t0, nt, a_scale, out, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int a_nrb,
+                       const void* b_tiles, int b_ncb, int nch, const double* c, int T,
+                       int nch_o, const TileDesc* tiles, int ntiles, double* out, double pref,
+                       void* park, hipStream_t s) {
   Chi0Params P;
-  P.a_re = a_re;
-  P.a_im = a_im;
-  P.lda = lda;
+  P.park = (unsigned char*)park;
+  P.a = (const unsigned char*)a_tiles;
+  P.a_nrb = a_nrb;
   P.b = (const unsigned char*)b_tiles;
-  P.b_nchunks = b_nchunks;
-  P.w = w;
+  P.b_ncb = b_ncb;
+  P.nch = nch;
   P.c = c;
   P.T = T;
   P.nch_o = nch_o;
-  P.nch_u = nch_u;
   P.tiles = tiles;
   P.ntiles = ntiles;
   P.out = out;
   P.pref = pref;
-  P.a_scale = a_scale;
   P.lam = nullptr;
   P.hu_re = P.hu_im = P.ho_re = P.ho_im = nullptr;
   switch (prec) {
@@ -491,36 +712,31 @@ hipError_t launch_chi0(int prec, int variant, int grid, const void* a_re, const 
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_green_adjoint(int grid, const void* a_re, const void* a_im, int lda,
-                                const void* b_tiles, int b_nchunks, const double* w,
-                                const double* c, int nch_o, int nch_u, const TileDesc* tiles,
-                                int ntiles, const double* lam, double* hu_re, double* hu_im,
-                                double* ho_re, double* ho_im, hipStream_t s) {
+hipError_t launch_green_adjoint(int grid, const void* a_tiles, int a_nrb, const void* b_tiles,
+                                int b_ncb, int nch, const double* c, int nch_o,
+                                const TileDesc* tiles, int ntiles, const double* lam,
+                                double* hu_re, double* hu_im, double* ho_re, double* ho_im,
+                                void* park, hipStream_t s) {
   Chi0Params P;
-  P.a_re = a_re;
-  P.a_im = a_im;
-  P.lda = lda;
+  P.park = (unsigned char*)park;
+  P.a = (const unsigned char*)a_tiles;
+  P.a_nrb = a_nrb;
   P.b = (const unsigned char*)b_tiles;
-  P.b_nchunks = b_nchunks;
-  P.w = w;
+  P.b_ncb = b_ncb;
+  P.nch = nch;
   P.c = c;
   P.T = 1;
   P.nch_o = nch_o;
-  P.nch_u = nch_u;
   P.tiles = tiles;
   P.ntiles = ntiles;
   P.out = nullptr;
   P.pref = 1.0;
-  P.a_scale = 1.f;
   P.lam = lam;
   P.hu_re = hu_re;
   P.hu_im = hu_im;
   P.ho_re = ho_re;
   P.ho_im = ho_im;
-  using Vt = Variant<LRS_FP64, 0>;
-  hipLaunchKernelGGL((chi0_kernel<LRS_FP64, Vt::WMW, Vt::WNW, Vt::MB, Vt::NB, 1>), dim3(grid),
-                     dim3(Vt::WMW * Vt::WNW * 64), 0, s, P);
-  return hipGetLastError();
+  return launch_v<LRS_FP64, 0, 1>(grid, P, s);
 }
 
 }  // namespace lrs

@@ -88,8 +88,8 @@ void drop_plans(lrs_ctx* ctx) {
 
 void drop_sites(lrs_ctx* ctx) {
   release(ctx, ctx->site_f64);
-  release(ctx, ctx->site_f32);
-  release(ctx, ctx->site_f32_perm);
+  release(ctx, ctx->a_tiles);
+  ctx->a_prec = -1;
   release(ctx, ctx->psi_site_f64);
   for (auto& b : ctx->site_tiles) release(ctx, b);
   release(ctx, ctx->site_colmap);
@@ -100,10 +100,9 @@ void drop_sites(lrs_ctx* ctx) {
 }
 
 void drop_quad(lrs_ctx* ctx) {
-  release(ctx, ctx->w_f64);
-  release(ctx, ctx->w_f32);
-  release(ctx, ctx->w_f32_perm);
+  release(ctx, ctx->w_nat);
   release(ctx, ctx->c_dev);
+  ctx->a_prec = -1;
   ctx->have_quad = false;
   ctx->quad = Quad();
 }
@@ -138,7 +137,7 @@ lrs_status ensure_grid_tiles(lrs_ctx* ctx, int prec) {
   if (ctx->ngrid <= 0) return fail(ctx, LRS_ESTATE, "no grid orbitals were given");
   DevBuf& b = ctx->grid_tiles[prec];
   if (b.p) return LRS_OK;
-  size_t bytes = (size_t)(ctx->grid_cols_pad / 16) * (ctx->K_pad / chunk_of(prec)) * kTileBytes;
+  size_t bytes = (size_t)(ctx->grid_cols_pad / 16) * (ctx->K_pad / chunk_of(prec)) * tile_bytes(prec);
   CHECK(ensure_buf(ctx, b, bytes, "grid operand"));
   HIP_OR_FAIL(ctx, launch_repack_from_f64(ctx->grid_tiles[LRS_FP64].p, ctx->grid_cols_pad,
                                           ctx->K_pad, prec, ctx->grid_scale_f16, b.p,
@@ -146,21 +145,10 @@ lrs_status ensure_grid_tiles(lrs_ctx* ctx, int prec) {
   return LRS_OK;
 }
 
-lrs_status ensure_site_f32(lrs_ctx* ctx) {
-  if (ctx->site_f32.p && ctx->site_f32_perm.p) return LRS_OK;
-  size_t bytes = (size_t)2 * ctx->rows_pad * ctx->K_pad * sizeof(float);
-  CHECK(ensure_buf(ctx, ctx->site_f32, bytes, "site operand fp32"));
-  CHECK(ensure_buf(ctx, ctx->site_f32_perm, bytes, "site operand fp32 (permuted)"));
-  HIP_OR_FAIL(ctx, launch_derive_site_f32((const double*)ctx->site_f64.p, ctx->rows_pad,
-                                          ctx->K_pad, (float*)ctx->site_f32.p,
-                                          (float*)ctx->site_f32_perm.p, ctx->stream));
-  return LRS_OK;
-}
-
 lrs_status ensure_site_tiles(lrs_ctx* ctx, int prec) {
   DevBuf& b = ctx->site_tiles[prec];
   if (b.p) return LRS_OK;
-  size_t bytes = (size_t)(ctx->site_cols_pad / 16) * (ctx->K_pad / chunk_of(prec)) * kTileBytes;
+  size_t bytes = (size_t)(ctx->site_cols_pad / 16) * (ctx->K_pad / chunk_of(prec)) * tile_bytes(prec);
   CHECK(ensure_buf(ctx, b, bytes, "site column operand"));
   HIP_OR_FAIL(ctx, launch_site_col_tiles((const double*)ctx->site_f64.p, ctx->rows_pad,
                                          ctx->K_pad, ctx->site_cols_pad,
@@ -208,27 +196,10 @@ lrs_status install_terms(lrs_ctx* ctx, Quad& q, const std::vector<double>& c,
       if (dbeta) dw[ctx->Ko_pad + i] = (*dbeta)[(size_t)t * Ku + i] * sb;
     }
   }
-  // device copies: FP64 (FP64-path chunk order), FP32 natural, FP32 (FP32-path chunk order)
-  std::vector<double> w64((size_t)T * Kp);
-  std::vector<float> w32((size_t)T * Kp), w32p((size_t)T * Kp);
-  for (int t = 0; t < T; ++t)
-    for (int k = 0; k < Kp; ++k) {
-      double v = q.w[(size_t)t * Kp + k];
-      int ch16 = k >> 4, kl16 = k & 15;
-      w64[(size_t)t * Kp + ch16 * 16 + (kl16 & 3) * 4 + (kl16 >> 2)] = v;
-      int ch32 = k >> 5, kl32 = k & 31;
-      w32p[(size_t)t * Kp + ch32 * 32 + (kl32 & 3) * 8 + (kl32 >> 2)] = (float)v;
-      w32[(size_t)t * Kp + k] = (float)v;
-    }
-  CHECK(ensure_buf(ctx, ctx->w_f64, w64.size() * 8, "weights"));
-  CHECK(ensure_buf(ctx, ctx->w_f32, w32.size() * 4, "weights fp32"));
-  CHECK(ensure_buf(ctx, ctx->w_f32_perm, w32p.size() * 4, "weights fp32"));
+  // device copies: weights in natural K order (FP64) and the coefficients
+  CHECK(ensure_buf(ctx, ctx->w_nat, q.w.size() * 8, "weights"));
   CHECK(ensure_buf(ctx, ctx->c_dev, (size_t)T * 8, "term coefficients"));
-  HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->w_f64.p, w64.data(), w64.size() * 8,
-                                  hipMemcpyHostToDevice, ctx->stream));
-  HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->w_f32.p, w32.data(), w32.size() * 4,
-                                  hipMemcpyHostToDevice, ctx->stream));
-  HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->w_f32_perm.p, w32p.data(), w32p.size() * 4,
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->w_nat.p, q.w.data(), q.w.size() * 8,
                                   hipMemcpyHostToDevice, ctx->stream));
   HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->c_dev.p, q.c.data(), (size_t)T * 8,
                                   hipMemcpyHostToDevice, ctx->stream));
@@ -256,10 +227,12 @@ void offsets(const lrs_ctx* ctx, std::vector<double>& x, std::vector<double>& y)
 }
 
 // ------------------------------------------------------------------ plans
-long long plan_key(int site, int cols, int prec, int variant) {
-  return (((long long)(site + 1) * 4 + cols) * 8 + prec) * 16 + variant;
+long long plan_key(int site, int cols, int prec, int variant, int mode) {
+  return ((((long long)(site + 1) * 4 + cols) * 8 + prec) * 16 + variant) * 2 + mode;
 }
 
+// Tiles of one site's rows [m0, m1) (site-local, BM-aligned) against its columns, 8 x 8
+// grouped (row tiles fastest inside a group of 8).
 void add_region(std::vector<TileDesc>& out, int a_row0, int nrows, int b_col0, int ncols,
                 long long out_base, int ldo, int bm, int bn) {
   const int mt = (nrows + bm - 1) / bm, nt = (ncols + bn - 1) / bn;
@@ -281,41 +254,107 @@ void add_region(std::vector<TileDesc>& out, int a_row0, int nrows, int b_col0, i
   }
 }
 
-lrs_status get_plan(lrs_ctx* ctx, int site, int cols, int prec, int variant, Plan** out) {
-  long long key = plan_key(site, cols, prec, variant);
+// Bytes of weighted site operand per 16-row block for nt terms.
+size_t a_bytes_per_rb(const lrs_ctx* ctx, int prec, int nt) {
+  return (size_t)nt * (ctx->K_pad / chunk_of(prec)) * tile_bytes(prec);
+}
+
+size_t a_budget() {
+  if (const char* e = std::getenv("LRS_SITE_OPERAND_BYTES")) return (size_t)std::strtoull(e, nullptr, 10);
+  return (size_t)24 << 30;
+}
+
+lrs_status get_plan(lrs_ctx* ctx, int site, int cols, int prec, int variant, int mode,
+                    Plan** out) {
+  long long key = plan_key(site, cols, prec, variant, mode);
   auto it = ctx->plans.find(key);
   if (it != ctx->plans.end()) {
     *out = &it->second;
     return LRS_OK;
   }
   TileShape sh = chi0_shape(prec, variant);
-  std::vector<TileDesc> tiles;
+  if (kRowAlign % sh.bm != 0) return fail(ctx, LRS_EINVAL, "tile rows must divide %d", kRowAlign);
+  const int nt = mode == 1 ? 1 : ctx->quad.nterms;
+  const size_t per_rb = a_bytes_per_rb(ctx, prec, nt);
+  int max_rb = (int)std::min<size_t>(1 << 20, a_budget() / std::max<size_t>(per_rb, 1));
+  max_rb = std::max(kRowAlign / 16, max_rb / (kRowAlign / 16) * (kRowAlign / 16));
   const int s0 = site < 0 ? 0 : site, s1 = site < 0 ? ctx->nsites : site + 1;
-  if (cols == LRS_COLS_GRID) {
-    const int r0 = ctx->site_off[s0], nr = ctx->site_off[s1] - r0;
-    add_region(tiles, r0, nr, 0, ctx->ngrid, 0, ctx->ngrid, sh.bm, sh.bn);
-  } else {
-    long long base = 0;
-    for (int s = s0; s < s1; ++s) {
-      const int n = ctx->site_off[s + 1] - ctx->site_off[s];
-      add_region(tiles, ctx->site_off[s], n, ctx->site_col_off[s], n, base, n, sh.bm, sh.bn);
-      base += (long long)n * n;
-    }
-  }
+  // walk the sites' 128-row slot chunks, cutting batches at max_rb row blocks
+  std::vector<TileDesc> tiles;
   Plan p;
-  p.ntiles = (int)tiles.size();
   p.variant = variant;
+  Batch cur;
+  cur.rb0 = ctx->site_col_off[s0] / 16;
+  long long base_site = 0;     // site-block output offset (SITE)
+  for (int s = s0; s < s1; ++s) {
+    const int n = ctx->site_off[s + 1] - ctx->site_off[s];
+    const int slot0 = ctx->site_col_off[s];
+    for (int m0 = 0; m0 < n; m0 += kRowAlign) {
+      const int rb = (slot0 + m0) / 16;
+      if (rb + kRowAlign / 16 - cur.rb0 > max_rb && rb > cur.rb0) {
+        cur.nrb = rb - cur.rb0;
+        cur.ntiles = (int)tiles.size() - cur.tile0;
+        p.batches.push_back(cur);
+        cur = Batch();
+        cur.rb0 = rb;
+        cur.tile0 = (int)tiles.size();
+      }
+      const int rows = std::min(kRowAlign, n - m0);
+      const int a_row0 = slot0 + m0 - cur.rb0 * 16;
+      if (cols == LRS_COLS_GRID) {
+        const long long orow = ctx->site_off[s] - ctx->site_off[s0] + m0;
+        add_region(tiles, a_row0, rows, 0, ctx->ngrid, orow * ctx->ngrid, ctx->ngrid, sh.bm, sh.bn);
+      } else {
+        add_region(tiles, a_row0, rows, slot0, n, base_site + (long long)m0 * n, n, sh.bm, sh.bn);
+      }
+    }
+    base_site += (long long)n * n;
+  }
+  const int last_slot = ctx->site_col_off[s1 - 1] +
+                        (int)round_up(ctx->site_off[s1] - ctx->site_off[s1 - 1], kRowAlign);
+  cur.nrb = last_slot / 16 - cur.rb0;
+  cur.ntiles = (int)tiles.size() - cur.tile0;
+  p.batches.push_back(cur);
+  p.ntiles = (int)tiles.size();
+  int per_cu = chi0_blocks_per_cu(prec, variant);
+  long long maxg = (long long)ctx->num_cu * std::max(1, per_cu);
+  for (auto& b : p.batches) {
+    long long g = std::min<long long>(maxg, round_up(std::max(b.ntiles, 1), 8));
+    b.grid = (int)std::max<long long>(8, g / 8 * 8);
+  }
   CHECK(ensure_buf(ctx, p.tiles, tiles.size() * sizeof(TileDesc) + 32, "tile list"));
   HIP_OR_FAIL(ctx, hipMemcpyAsync(p.tiles.p, tiles.data(), tiles.size() * sizeof(TileDesc),
                                   hipMemcpyHostToDevice, ctx->stream));
   HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
-  int per_cu = chi0_blocks_per_cu(prec, variant);
-  long long maxg = (long long)ctx->num_cu * std::max(1, per_cu);
-  long long g = std::min<long long>(maxg, round_up(p.ntiles, 8));
-  p.grid = (int)std::max<long long>(8, g / 8 * 8);
   auto res = ctx->plans.emplace(key, p);
   *out = &res.first->second;
   return LRS_OK;
+}
+
+// Weighted site operand of terms [t0, t0+nt) for one batch (kept while nothing changes).
+lrs_status site_operand(lrs_ctx* ctx, int prec, const Batch& b, int t0, int nt) {
+  if (ctx->a_prec == prec && ctx->a_version == ctx->quad_version && ctx->a_rb0 == b.rb0 &&
+      ctx->a_nrb == b.nrb && ctx->a_t0 == t0 && ctx->a_nt == nt && ctx->a_tiles.p)
+    return LRS_OK;
+  ctx->a_prec = -1;
+  CHECK(ensure_buf(ctx, ctx->a_tiles, a_bytes_per_rb(ctx, prec, nt) * b.nrb, "weighted site operand"));
+  const double a_scale = prec == LRS_FP16X2 ? ctx->site_scale_f16 : 1.0;
+  HIP_OR_FAIL(ctx, launch_prep_site(prec, (const double*)ctx->site_f64.p, ctx->rows_pad,
+                                    ctx->K_pad, (const int*)ctx->site_colmap.p, b.rb0, b.nrb,
+                                    (const double*)ctx->w_nat.p, t0, nt, a_scale,
+                                    ctx->a_tiles.p, ctx->stream));
+  ctx->a_prec = prec;
+  ctx->a_version = ctx->quad_version;
+  ctx->a_rb0 = b.rb0;
+  ctx->a_nrb = b.nrb;
+  ctx->a_t0 = t0;
+  ctx->a_nt = nt;
+  return LRS_OK;
+}
+
+lrs_status park_for(lrs_ctx* ctx, int prec, int variant, int grid) {
+  const size_t bytes = chi0_shape(prec, variant).park_bytes * (size_t)grid;
+  return ensure_buf(ctx, ctx->park, bytes, "G_o scratch");
 }
 
 int pick_variant(lrs_ctx* ctx, int prec) {
@@ -328,27 +367,14 @@ int pick_variant(lrs_ctx* ctx, int prec) {
   return chi0_default_variant(prec);
 }
 
+// max_tiles > 0 limits the launch to the first tiles of the first batch (tuning samples)
 lrs_status run_chi0(lrs_ctx* ctx, int site, int cols, int prec, int variant, double* out,
-                    bool timed) {
+                    bool timed, int max_tiles = 0) {
   Plan* plan = nullptr;
-  CHECK(get_plan(ctx, site, cols, prec, variant, &plan));
-  const void *are, *aim, *w;
-  float a_scale = 1.f;
+  CHECK(get_plan(ctx, site, cols, prec, variant, 0, &plan));
   double bscale = 1.0;
-  size_t plane = (size_t)ctx->rows_pad * ctx->K_pad;
-  if (prec == LRS_FP64) {
-    are = ctx->site_f64.p;
-    aim = (const double*)ctx->site_f64.p + plane;
-    w = ctx->w_f64.p;
-  } else {
-    CHECK(ensure_site_f32(ctx));
-    const float* base = (const float*)(prec == LRS_FP32 ? ctx->site_f32_perm.p : ctx->site_f32.p);
-    are = base;
-    aim = base + plane;
-    w = prec == LRS_FP32 ? ctx->w_f32_perm.p : ctx->w_f32.p;
-    if (prec == LRS_FP16X2) a_scale = ctx->site_scale_f16;
-  }
   const void* b;
+  const int b_ncb = (cols == LRS_COLS_GRID ? ctx->grid_cols_pad : ctx->site_cols_pad) / 16;
   if (cols == LRS_COLS_GRID) {
     CHECK(ensure_grid_tiles(ctx, prec));
     b = ctx->grid_tiles[prec].p;
@@ -358,17 +384,32 @@ lrs_status run_chi0(lrs_ctx* ctx, int site, int cols, int prec, int variant, dou
     b = ctx->site_tiles[prec].p;
     if (prec == LRS_FP16X2) bscale = ctx->site_scale_f16;
   }
+  const double a_scale = prec == LRS_FP16X2 ? ctx->site_scale_f16 : 1.0;
   const int KC = chunk_of(prec);
-  const int b_nchunks = ctx->K_pad / KC;
+  const int nch = ctx->K_pad / KC;
   double pref = -2.0 * ctx->spin / ((double)ctx->nk * ctx->nk);
-  double g_scale = (double)a_scale * bscale;   // each G carries a_scale * b_scale
+  const double g_scale = a_scale * bscale;   // each G carries a_scale * b_scale
   pref /= g_scale * g_scale;
-  if (timed) HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-  HIP_OR_FAIL(ctx, launch_chi0(prec, variant, plan->grid, are, aim, ctx->K_pad, b, b_nchunks, w,
-                               (const double*)ctx->c_dev.p, ctx->quad.nterms, ctx->Ko_pad / KC,
-                               ctx->Ku_pad / KC, (const TileDesc*)plan->tiles.p, plan->ntiles,
-                               out, pref, a_scale, ctx->stream));
-  if (timed) {
+  const int T = ctx->quad.nterms;
+  bool first = true;
+  for (const Batch& bt : plan->batches) {
+    if (bt.ntiles == 0) continue;
+    CHECK(site_operand(ctx, prec, bt, 0, T));
+    int nt = bt.ntiles, grid = bt.grid;
+    if (max_tiles > 0) {
+      nt = std::min(nt, max_tiles);
+      grid = (int)std::max<long long>(8, std::min<long long>(grid, round_up(nt, 8)));
+    }
+    CHECK(park_for(ctx, prec, variant, grid));
+    if (timed && first) HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    first = false;
+    HIP_OR_FAIL(ctx, launch_chi0(prec, variant, grid, ctx->a_tiles.p, bt.nrb, b, b_ncb, nch,
+                                 (const double*)ctx->c_dev.p, T, ctx->Ko_pad / KC,
+                                 (const TileDesc*)plan->tiles.p + bt.tile0, nt, out, pref,
+                                 ctx->park.p, ctx->stream));
+    if (max_tiles > 0) break;
+  }
+  if (timed && !first) {
     HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev1, ctx->stream));
     ctx->timed = true;
   }
@@ -378,10 +419,17 @@ lrs_status run_chi0(lrs_ctx* ctx, int site, int cols, int prec, int variant, dou
 }  // namespace
 
 namespace lrs {
-lrs_status plan_for(lrs_ctx* ctx, int site, int cols, int prec, int variant, Plan** out) {
-  return get_plan(ctx, site, cols, prec, variant, out);
+lrs_status plan_for(lrs_ctx* ctx, int site, int cols, int prec, int variant, int mode,
+                    Plan** out) {
+  return get_plan(ctx, site, cols, prec, variant, mode, out);
 }
 lrs_status ensure_site_tiles_for(lrs_ctx* ctx, int prec) { return ensure_site_tiles(ctx, prec); }
+lrs_status ensure_site_operand(lrs_ctx* ctx, int prec, const Batch& b, int t0, int nt) {
+  return site_operand(ctx, prec, b, t0, nt);
+}
+lrs_status ensure_park(lrs_ctx* ctx, int prec, int variant, int grid) {
+  return park_for(ctx, prec, variant, grid);
+}
 }  // namespace lrs
 
 // ====================================================================== C ABI
@@ -427,6 +475,8 @@ void lrs_destroy(lrs_ctx* ctx) {
   release(ctx, ctx->screen_tab);
   release(ctx, ctx->work);
   release(ctx, ctx->adj_work);
+  release(ctx, ctx->a_tiles);
+  release(ctx, ctx->park);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   delete ctx;
@@ -780,7 +830,7 @@ lrs_status lrs_tune(lrs_ctx* ctx, int prec) {
       }
     }
   }
-  // time every variant on a bounded sample of the problem: the first row tile band of one site
+  // time every variant on a bounded sample: the first tiles of the first batch of site 0
   DevBuf out;
   const int s = 0;
   const int nr = ctx->site_off[1] - ctx->site_off[0];
@@ -788,16 +838,20 @@ lrs_status lrs_tune(lrs_ctx* ctx, int prec) {
   CHECK(ensure_buf(ctx, out, (size_t)nr * ncol * 8, "tuning output"));
   int best = 0;
   float best_ms = 1e30f;
+  const int sample = 2 * ctx->num_cu * 2;
   for (int v = 0; v < chi0_num_variants(prec); ++v) {
-    lrs_status st = run_chi0(ctx, s, cols, prec, v, (double*)out.p, false);   // warm-up + plan
+    lrs_status st = run_chi0(ctx, s, cols, prec, v, (double*)out.p, false, sample);   // warm-up
     if (st != LRS_OK) { release(ctx, out); return st; }
     HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-    st = run_chi0(ctx, s, cols, prec, v, (double*)out.p, false);
+    st = run_chi0(ctx, s, cols, prec, v, (double*)out.p, false, sample);
     if (st != LRS_OK) { release(ctx, out); return st; }
     HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev1, ctx->stream));
     HIP_OR_FAIL(ctx, hipEventSynchronize(ctx->ev1));
     float ms = 0;
     HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    // normalise by the tile area so that variants with different tile shapes compare fairly
+    TileShape sh = chi0_shape(prec, v);
+    ms /= (float)(sh.bm * sh.bn);
     if (ms < best_ms) {
       best_ms = ms;
       best = v;

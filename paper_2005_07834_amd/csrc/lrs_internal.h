@@ -13,16 +13,19 @@
 namespace lrs {
 
 // Operand chunking along K (the flattened (k-point, band) index).  A "fragment tile" is
-// 16 rows (or columns) x one K chunk of a precision's matrix-core operand, 4 KiB in every
-// precision: FP64 -> 16 k x 2 planes (re, im) x 8 B; FP32 -> 32 k x 2 planes x 4 B;
-// BF16X2/FP16X2 -> 32 k x 4 planes (re hi, re lo, im hi, im lo) x 2 B.
-constexpr int kTileBytes = 4096;
+// 16 rows (or columns) x one K chunk of a precision's matrix-core operand, every lane's operand
+// contiguous: FP64 -> 16 k x 2 planes (re, im) x 8 B = 4 KiB; FP32 -> 32 k x 2 planes x 4 B
+// = 4 KiB; BF16X2/FP16X2 -> 16 k x 4 planes (re hi, re lo, im hi, im lo) x 2 B = 2 KiB.
+// Operands are stored chunk-major ([chunk][block][tile]).
+constexpr int kTileBytes = 4096;   // FP64 and FP32 tiles
 constexpr int kChunkF64 = 16;
-constexpr int kChunkLow = 32;
 constexpr int kRowAlign = 128;  // rows / columns of every operand are padded to this
 constexpr int kMaxTerms = 128;
 
-inline int chunk_of(int prec) { return prec == LRS_FP64 ? kChunkF64 : kChunkLow; }
+inline bool is_split(int prec) { return prec == LRS_BF16X2 || prec == LRS_FP16X2; }
+// K values per chunk and bytes per fragment tile (16 rows x chunk x planes)
+inline int chunk_of(int prec) { return prec == LRS_FP32 ? 32 : 16; }
+inline int tile_bytes(int prec) { return is_split(prec) ? 2048 : 4096; }
 inline long long round_up(long long x, long long m) { return (x + m - 1) / m * m; }
 
 // One output tile of a chi0 launch.
@@ -41,6 +44,7 @@ static_assert(sizeof(TileDesc) == 32, "TileDesc layout");
 struct TileShape {
   int bm, bn;           // workgroup tile
   int threads;
+  size_t park_bytes;    // per-workgroup scratch for G_o
 };
 
 struct DevBuf {
@@ -48,11 +52,17 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
-struct Plan {             // cached launch plan for (site, cols, prec, variant)
+struct Batch {            // a contiguous range of site row blocks and its tiles
+  int rb0 = 0, nrb = 0;   // row blocks (16 slot rows each) of the weighted site operand
+  int tile0 = 0, ntiles = 0;
+  int grid = 0;
+};
+
+struct Plan {             // cached launch plan for (site, cols, prec, variant, mode)
   DevBuf tiles;
   int ntiles = 0;
-  int grid = 0;
   int variant = 0;
+  std::vector<Batch> batches;
 };
 
 struct Quad {
@@ -102,9 +112,10 @@ struct lrs_ctx {
   lrs::DevBuf site_colmap;        // [site_cols_pad] column -> site row (-1: zero column)
   std::vector<double> radii, rad_w, ang_xyz, ang_w;
   lrs::DevBuf site_f64;           // planar re/im [2][rows_pad][K_pad] (chunk-permuted), FP64
-  lrs::DevBuf site_f32;           // the same in FP32 (FP32/split paths; per-precision permutation)
-  lrs::DevBuf site_f32_perm;      // FP32 with the FP32-path permutation
   lrs::DevBuf site_tiles[4];      // site points as a column operand (fragment tiles)
+  lrs::DevBuf a_tiles;            // weighted site operand tiles of the current batch
+  lrs::DevBuf park;               // per-workgroup G_o scratch of the chi0 launches
+  int a_prec = -1, a_version = -1, a_rb0 = -1, a_nrb = -1, a_t0 = -1, a_nt = -1;
   lrs::DevBuf psi_site_f64;       // planar [2][K_pad][rows_pad] (k-major rows) for the adjoint
   float site_max_abs = 0.f;
   float grid_max_abs = 0.f;
@@ -112,7 +123,7 @@ struct lrs_ctx {
   // quadrature
   bool have_quad = false;
   lrs::Quad quad;
-  lrs::DevBuf w_f64, w_f32, w_f32_perm, c_dev;
+  lrs::DevBuf w_nat, c_dev;       // weights [T][K_pad] (natural K order), coefficients [T]
   int quad_version = 0;
 
   // plans
@@ -142,8 +153,6 @@ hipError_t launch_pack_tiles(const double* psi, int nk, int nb, int nocc, int nc
 hipError_t launch_pack_site_rows(const double* psi, int nk, int nb, int nocc, int nrows,
                                  int rows_pad, int Ko_pad, int K_pad, double* out_f64,
                                  hipStream_t s);
-hipError_t launch_derive_site_f32(const double* site_f64, int rows_pad, int K_pad, float* o32,
-                                  float* o32p, hipStream_t s);
 hipError_t launch_derive_site_kmajor(const double* site_f64, int rows_pad, int K_pad, double* out,
                                      hipStream_t s);
 hipError_t launch_site_col_tiles(const double* site_f64, int rows_pad, int K_pad, int ncols_pad,
@@ -159,20 +168,25 @@ int chi0_num_variants(int prec);
 int chi0_blocks_per_cu(int prec, int variant);
 int chi0_default_variant(int prec);
 TileShape chi0_shape(int prec, int variant);
-hipError_t launch_chi0(int prec, int variant, int grid, const void* a_re, const void* a_im,
-                       int lda, const void* b_tiles, int b_nchunks, const void* w,
-                       const double* c, int T, int nch_o, int nch_u, const TileDesc* tiles,
-                       int ntiles, double* out, double pref, float a_scale, hipStream_t s);
-
-hipError_t launch_green_adjoint(int grid, const void* a_re, const void* a_im, int lda,
-                                const void* b_tiles, int b_nchunks, const double* w,
-                                const double* c, int nch_o, int nch_u, const TileDesc* tiles,
-                                int ntiles, const double* lam, double* hu_re, double* hu_im,
-                                double* ho_re, double* ho_im, hipStream_t s);
+hipError_t launch_prep_site(int prec, const double* site, int rows_pad, int K_pad,
+                            const int* slot_row, int rb0, int nrb, const double* w, int t0,
+                            int nt, double a_scale, void* out, hipStream_t s);
+hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int a_nrb,
+                       const void* b_tiles, int b_ncb, int nch, const double* c, int T,
+                       int nch_o, const TileDesc* tiles, int ntiles, double* out, double pref,
+                       void* park, hipStream_t s);
+hipError_t launch_green_adjoint(int grid, const void* a_tiles, int a_nrb, const void* b_tiles,
+                                int b_ncb, int nch, const double* c, int nch_o,
+                                const TileDesc* tiles, int ntiles, const double* lam,
+                                double* hu_re, double* hu_im, double* ho_re, double* ho_im,
+                                void* park, hipStream_t s);
 
 // lrs_api.cpp (shared with the adjoint)
-lrs_status plan_for(lrs_ctx* ctx, int site, int cols, int prec, int variant, Plan** out);
+lrs_status plan_for(lrs_ctx* ctx, int site, int cols, int prec, int variant, int mode,
+                    Plan** out);
 lrs_status ensure_site_tiles_for(lrs_ctx* ctx, int prec);
+lrs_status ensure_site_operand(lrs_ctx* ctx, int prec, const Batch& b, int t0, int nt);
+lrs_status ensure_park(lrs_ctx* ctx, int prec, int variant, int grid);
 
 // screen.hip
 hipError_t launch_screen_forward(lrs_ctx* ctx, const double* chi0_ss, double* W_out,

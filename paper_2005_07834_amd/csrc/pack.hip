@@ -39,12 +39,12 @@ struct SrcPsi {           // complex128 [nk][nb][ld] orbitals on a point set
 
 struct SrcTiles64 {       // FP64 fragment tiles as a source (for lazy reduced-precision copies)
   const double* t;
-  int nchunks64;
+  int ncb;                // column blocks
   __device__ void get(int c, int k, double& re, double& im) const {
     int cb = c >> 4, ch = k >> 4, kl = k & 15;
     int lane = ((kl & 3) << 4) | (c & 15);
     int s = kl >> 2;
-    const double* tile = t + ((size_t)cb * nchunks64 + ch) * (kTileBytes / 8);
+    const double* tile = t + ((size_t)ch * ncb + cb) * (kTileBytes / 8);
     re = tile[lane * 4 + s];
     im = tile[256 + lane * 4 + s];
   }
@@ -59,18 +59,26 @@ __device__ inline void split_f16(float x, __half& hi, __half& lo) {
   lo = __float2half(x - __half2float(hi));
 }
 
-// One thread per (tile, lane): writes that lane's slot of every plane of the tile.
+// One thread per (tile, lane slot): writes that slot of every plane of the tile.  Tiles are
+// stored chunk-major: tile (column block cb, chunk ch) at index ch * ncb + cb, so that the
+// blocks one workgroup needs for one chunk are contiguous.
+//   FP64  (4 KiB, 64 slots):  slot l holds column l%16, k = 16 ch + 4 s + l/16, s = 0..3
+//   FP32  (4 KiB, 64 slots):  slot l holds column l%16, k = 32 ch + 4 s + l/16, s = 0..7
+//   split (2 KiB, 32 slots):  slot l holds column l%16, k = 16 ch + 8 (l/16) + e, e = 0..7,
+//                             planes re hi, re lo, im hi, im lo
 template <class Src>
-__global__ void pack_tiles_kernel(Src src, long long ntiles, int nchunks, int prec,
+__global__ void pack_tiles_kernel(Src src, long long ntiles, int ncb, int prec,
                                   float prescale, unsigned char* out) {
+  const bool split = prec == LRS_BF16X2 || prec == LRS_FP16X2;
+  const int slots = split ? 32 : 64;
   long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= ntiles * 64) return;
-  int lane = (int)(gid & 63);
-  long long tile = gid >> 6;
-  int cb = (int)(tile / nchunks);
-  int ch = (int)(tile - (long long)cb * nchunks);
+  if (gid >= ntiles * slots) return;
+  int lane = (int)(gid % slots);
+  long long tile = gid / slots;
+  int ch = (int)(tile / ncb);
+  int cb = (int)(tile - (long long)ch * ncb);
   int c = cb * 16 + (lane & 15);
-  unsigned char* base = out + tile * kTileBytes;
+  unsigned char* base = out + tile * (split ? 2048 : 4096);
   if (prec == LRS_FP64) {
     double* t = reinterpret_cast<double*>(base);
     for (int s = 0; s < 4; ++s) {
@@ -91,33 +99,27 @@ __global__ void pack_tiles_kernel(Src src, long long ntiles, int nchunks, int pr
     __hip_bfloat16* t = reinterpret_cast<__hip_bfloat16*>(base);
     for (int e = 0; e < 8; ++e) {
       double re, im;
-      src.get(c, ch * 32 + 8 * (lane >> 4) + e, re, im);
-      split_bf16((float)re, t[lane * 8 + e], t[512 + lane * 8 + e]);
-      split_bf16((float)im, t[1024 + lane * 8 + e], t[1536 + lane * 8 + e]);
+      src.get(c, ch * 16 + 8 * (lane >> 4) + e, re, im);
+      split_bf16((float)re, t[lane * 8 + e], t[256 + lane * 8 + e]);
+      split_bf16((float)im, t[512 + lane * 8 + e], t[768 + lane * 8 + e]);
     }
   } else {
     __half* t = reinterpret_cast<__half*>(base);
     for (int e = 0; e < 8; ++e) {
       double re, im;
-      src.get(c, ch * 32 + 8 * (lane >> 4) + e, re, im);
-      split_f16((float)(re * prescale), t[lane * 8 + e], t[512 + lane * 8 + e]);
-      split_f16((float)(im * prescale), t[1024 + lane * 8 + e], t[1536 + lane * 8 + e]);
+      src.get(c, ch * 16 + 8 * (lane >> 4) + e, re, im);
+      split_f16((float)(re * prescale), t[lane * 8 + e], t[256 + lane * 8 + e]);
+      split_f16((float)(im * prescale), t[512 + lane * 8 + e], t[768 + lane * 8 + e]);
     }
   }
 }
 
-// Site rows for the A side: planar [2][rows_pad][K_pad].  Within each chunk the K order is
-// permuted so that one thread's contiguous load is exactly one matrix-core lane's operand:
-//   FP64 (chunk 16): stored g*4 + j  <-> k = 4 j + g
-//   FP32 (chunk 32): stored g*8 + j  <-> k = 4 j + g
-//   natural (bf16/fp16 split paths): stored k <-> k
+// Site rows: planar [2][rows_pad][K_pad] FP64.  Within each 16-chunk of K the order is
+// permuted (stored g*4 + j <-> k = 4 j + g) so that a lane's four FP64 matrix-core operands
+// are contiguous.
 __device__ inline size_t pos_f64(int r, int k, int K_pad) {
   int ch = k >> 4, kl = k & 15;
   return (size_t)r * K_pad + ch * 16 + (kl & 3) * 4 + (kl >> 2);
-}
-__device__ inline size_t pos_f32p(int r, int k, int K_pad) {
-  int ch = k >> 5, kl = k & 31;
-  return (size_t)r * K_pad + ch * 32 + (kl & 3) * 8 + (kl >> 2);
 }
 
 struct SrcSite64 {        // the FP64 row operand as a source (optionally through a column map)
@@ -150,22 +152,6 @@ __global__ void pack_site_rows_kernel(SrcPsi src, int rows_pad, int K_pad, doubl
   size_t p = pos_f64(r, k, K_pad);
   o64[p] = re;
   o64[(size_t)n + p] = im;
-}
-
-// FP32 row operands from the FP64 one: natural order (o32) and FP32-path order (o32p).
-__global__ void derive_site_rows_f32_kernel(SrcSite64 src, float* o32, float* o32p) {
-  long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  long long n = (long long)src.rows_pad * src.K_pad;
-  if (gid >= n) return;
-  int r = (int)(gid / src.K_pad);
-  int k = (int)(gid - (long long)r * src.K_pad);
-  double re, im;
-  src.get(r, k, re, im);
-  o32[gid] = (float)re;
-  o32[n + gid] = (float)im;
-  size_t p = pos_f32p(r, k, src.K_pad);
-  o32p[p] = (float)re;
-  o32p[(size_t)n + p] = (float)im;
 }
 
 // Site orbitals k-major for the adjoint: planar [2][K_pad][rows_pad], natural K order.
@@ -216,17 +202,17 @@ hipError_t launch_pack_tiles(const double* psi, int nk, int nb, int nocc, int nc
   int nchunks = K_pad / chunk_of(prec);
   long long ntiles = (long long)(ncols_pad / 16) * nchunks;
   hipLaunchKernelGGL(pack_tiles_kernel<SrcPsi>, dim3(blocks_for(ntiles * 64, 256)), dim3(256), 0,
-                     s, src, ntiles, nchunks, prec, prescale, (unsigned char*)out);
+                     s, src, ntiles, ncols_pad / 16, prec, prescale, (unsigned char*)out);
   return hipGetLastError();
 }
 
 hipError_t launch_repack_from_f64(const void* tiles64, int ncols_pad, int K_pad, int prec,
                                   float prescale, void* dst, hipStream_t s) {
-  SrcTiles64 src{(const double*)tiles64, K_pad / kChunkF64};
+  SrcTiles64 src{(const double*)tiles64, ncols_pad / 16};
   int nchunks = K_pad / chunk_of(prec);
   long long ntiles = (long long)(ncols_pad / 16) * nchunks;
   hipLaunchKernelGGL(pack_tiles_kernel<SrcTiles64>, dim3(blocks_for(ntiles * 64, 256)), dim3(256),
-                     0, s, src, ntiles, nchunks, prec, prescale, (unsigned char*)dst);
+                     0, s, src, ntiles, ncols_pad / 16, prec, prescale, (unsigned char*)dst);
   return hipGetLastError();
 }
 
@@ -238,15 +224,6 @@ hipError_t launch_pack_site_rows(const double* psi, int nk, int nb, int nocc, in
   long long n = (long long)rows_pad * K_pad;
   hipLaunchKernelGGL(pack_site_rows_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, src,
                      rows_pad, K_pad, out_f64);
-  return hipGetLastError();
-}
-
-hipError_t launch_derive_site_f32(const double* site_f64, int rows_pad, int K_pad, float* o32,
-                                  float* o32p, hipStream_t s) {
-  SrcSite64 src{site_f64, rows_pad, K_pad, nullptr};
-  long long n = (long long)rows_pad * K_pad;
-  hipLaunchKernelGGL(derive_site_rows_f32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, src,
-                     o32, o32p);
   return hipGetLastError();
 }
 
@@ -266,7 +243,7 @@ hipError_t launch_site_col_tiles(const double* site_f64, int rows_pad, int K_pad
   int nchunks = K_pad / chunk_of(prec);
   long long ntiles = (long long)(ncols_pad / 16) * nchunks;
   hipLaunchKernelGGL(pack_tiles_kernel<SrcSite64>, dim3(blocks_for(ntiles * 64, 256)), dim3(256),
-                     0, s, src, ntiles, nchunks, prec, prescale, (unsigned char*)dst);
+                     0, s, src, ntiles, ncols_pad / 16, prec, prescale, (unsigned char*)dst);
   return hipGetLastError();
 }
 
