@@ -53,6 +53,22 @@ def traffic_for(workload, prec, ms_unused=None):
     return d.get("hbm_bytes_per_launch")
 
 
+def copy_calibration(mib):
+    """A plain streaming kernel of known traffic: reads and writes `mib` MiB, three launches.
+    Hardware byte counters read on it give the scale between counter units and bytes."""
+    import torch
+    n = (mib << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_kernel": "neg (float32)", "bytes_read": n * 4, "bytes_written": n * 4,
+                      "launches": 3}), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,11 +81,16 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU layout is described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the path is "
+              "built and measured for a single device; sharding over sites or grid columns "
+              "is not implemented", file=sys.stderr)
         return 2
+    if args.copy_mib:
+        return copy_calibration(args.copy_mib)
 
     import torch
     import paper_2005_07834_amd as P
