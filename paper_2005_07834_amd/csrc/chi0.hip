@@ -352,19 +352,189 @@ __device__ __forceinline__ void mma_frags(
   }
 }
 
+// Split paths with rotating B fragments: the A fragments of a chunk are double-buffered, the B
+// fragments are single-buffered and refilled block column by block column: once the matrix-core
+// instructions of B block j have issued, block j is read again from the next chunk's slot.  This
+// keeps a 64 x 128 wave tile (256 accumulator registers) within the register file.
+template <int PREC, int MB>
+struct FragsA {
+  using half_t = typename std::conditional<PREC == LRS_BF16X2, bf16x8, f16x8>::type;
+  half_t ph[MB / 2], pl[MB / 2], qh[MB / 2], ql[MB / 2];
+};
+template <int PREC, int NB>
+struct FragsB {
+  using half_t = typename std::conditional<PREC == LRS_BF16X2, bf16x8, f16x8>::type;
+  half_t rh[NB / 2], rl[NB / 2], ih[NB / 2], il[NB / 2];
+};
+
+__device__ __forceinline__ int split_lane_ofs(int lane, int tb) {
+  return ((lane & 31) >> 4) * tb + (lane >> 5) * 256 + (lane & 15) * 16;
+}
+
+template <int PREC, int MB>
+__device__ __forceinline__ void load_a_split(const unsigned char* lds_a, int lane,
+                                             FragsA<PREC, MB>& f) {
+  using half_t = typename FragsA<PREC, MB>::half_t;
+  constexpr int TB = Prec<PREC>::TB;
+  const int lofs = split_lane_ofs(lane, TB);
+#pragma unroll
+  for (int i = 0; i < MB / 2; ++i) {
+    const unsigned char* a = lds_a + i * 2 * TB + lofs;
+    f.ph[i] = *(const half_t*)(a);
+    f.pl[i] = *(const half_t*)(a + 512);
+    f.qh[i] = *(const half_t*)(a + 1024);
+    f.ql[i] = *(const half_t*)(a + 1536);
+  }
+}
+
+template <int PREC, int NB>
+__device__ __forceinline__ void load_b_split(const unsigned char* lds_b, int lane, int j,
+                                             FragsB<PREC, NB>& f) {
+  using half_t = typename FragsB<PREC, NB>::half_t;
+  constexpr int TB = Prec<PREC>::TB;
+  const unsigned char* b = lds_b + j * 2 * TB + split_lane_ofs(lane, TB);
+  f.rh[j] = *(const half_t*)(b);
+  f.rl[j] = *(const half_t*)(b + 512);
+  f.ih[j] = *(const half_t*)(b + 1024);
+  f.il[j] = *(const half_t*)(b + 1536);
+}
+
+// the matrix-core instructions of B block column j: per product, the A blocks in turn, G_r
+// and G_i alternating, so that consecutive instructions update different accumulators
+template <int PREC, int MB, int NB>
+__device__ __forceinline__ void mma_col_split(const FragsA<PREC, MB>& a, const FragsB<PREC, NB>& b,
+                                              int j, f32x16 (&gr)[MB / 2][NB / 2],
+                                              f32x16 (&gi)[MB / 2][NB / 2]) {
+  using half_t = typename FragsA<PREC, MB>::half_t;
+  const u32x4 m = {0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+  auto mf = [](half_t x, half_t y, f32x16 c) {
+    if constexpr (PREC == LRS_BF16X2)
+      return __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, c, 0, 0, 0);
+    else
+      return __builtin_amdgcn_mfma_f32_32x32x16_f16(x, y, c, 0, 0, 0);
+  };
+  half_t nqh[MB / 2], nql[MB / 2];
+#pragma unroll
+  for (int i = 0; i < MB / 2; ++i) {
+    nqh[i] = (half_t)((u32x4)a.qh[i] ^ m);
+    nql[i] = (half_t)((u32x4)a.ql[i] ^ m);
+  }
+#pragma unroll
+  for (int i = 0; i < MB / 2; ++i) {
+    gr[i][j] = mf(a.ph[i], b.rh[j], gr[i][j]);
+    gi[i][j] = mf(a.ph[i], b.ih[j], gi[i][j]);
+  }
+#pragma unroll
+  for (int i = 0; i < MB / 2; ++i) {
+    gr[i][j] = mf(a.ph[i], b.rl[j], gr[i][j]);
+    gi[i][j] = mf(a.ph[i], b.il[j], gi[i][j]);
+  }
+#pragma unroll
+  for (int i = 0; i < MB / 2; ++i) {
+    gr[i][j] = mf(a.pl[i], b.rh[j], gr[i][j]);
+    gi[i][j] = mf(a.pl[i], b.ih[j], gi[i][j]);
+  }
+#pragma unroll
+  for (int i = 0; i < MB / 2; ++i) {
+    gr[i][j] = mf(a.qh[i], b.ih[j], gr[i][j]);
+    gi[i][j] = mf(nqh[i], b.rh[j], gi[i][j]);
+  }
+#pragma unroll
+  for (int i = 0; i < MB / 2; ++i) {
+    gr[i][j] = mf(a.qh[i], b.il[j], gr[i][j]);
+    gi[i][j] = mf(nqh[i], b.rl[j], gi[i][j]);
+  }
+#pragma unroll
+  for (int i = 0; i < MB / 2; ++i) {
+    gr[i][j] = mf(a.ql[i], b.ih[j], gr[i][j]);
+    gi[i][j] = mf(nql[i], b.rh[j], gi[i][j]);
+  }
+}
+
+// Scheduling groups for one pipeline step: the next chunk's LDS reads, one per matrix-core
+// instruction, then the global->LDS loads spread over the following ones, then the rest.
+template <int N, int M1, int S1, int M2, int S2>
+__device__ __forceinline__ void sched_pairs() {
+  if constexpr (N > 0) {
+    __builtin_amdgcn_sched_group_barrier(M1, S1, 0);
+    __builtin_amdgcn_sched_group_barrier(M2, S2, 0);
+    sched_pairs<N - 1, M1, S1, M2, S2>();
+  }
+}
+template <int PREC, int MB, int NB, int NVM>
+__device__ __forceinline__ void interleave() {
+  constexpr int kMFMA = 0x008, kVMEM = 0x010, kDSREAD = 0x100;
+  constexpr bool split = PREC == LRS_BF16X2 || PREC == LRS_FP16X2;
+  // instructions per step: LDS reads of 16 bytes, matrix-core instructions
+  constexpr int NDS = split ? 2 * (MB + NB) : (PREC == LRS_FP64 ? 4 * (MB + NB) : 4 * (MB + NB));
+  constexpr int NMF = split ? 3 * MB * NB : (PREC == LRS_FP64 ? 16 * MB * NB : 32 * MB * NB);
+  constexpr int R = (NMF - NDS) / NVM > 0 ? (NMF - NDS) / NVM : 1;
+  sched_pairs<NDS, kMFMA, 1, kDSREAD, 1>();
+  sched_pairs<NVM, kMFMA, R, kVMEM, 1>();
+  __builtin_amdgcn_sched_group_barrier(kMFMA, NMF, 0);
+}
+
+// Scheduling groups of a rotating step: the next chunk's A reads one per matrix-core
+// instruction, the global->LDS loads spread over the rest of block column 0, then per block
+// column its matrix-core instructions followed by the refill of its B fragments.
+template <int NJ, int NMFJ>
+__device__ __forceinline__ void sched_cols() {
+  if constexpr (NJ > 0) {
+    __builtin_amdgcn_sched_group_barrier(0x008, NMFJ, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+    sched_cols<NJ - 1, NMFJ>();
+  }
+}
+template <int MB, int NB, int NVM>
+__device__ __forceinline__ void interleave_rot() {
+  constexpr int kMFMA = 0x008, kVMEM = 0x010, kDSREAD = 0x100;
+  constexpr int NAR = 2 * MB;          // A reads (16 bytes each)
+  constexpr int NMFJ = 6 * MB;         // matrix-core instructions per B block column
+  constexpr int R = (NMFJ - NAR) / NVM > 0 ? (NMFJ - NAR) / NVM : 1;
+  constexpr int REST = NMFJ - NAR - R * NVM > 0 ? NMFJ - NAR - R * NVM : 0;
+  sched_pairs<NAR, kMFMA, 1, kDSREAD, 1>();
+  sched_pairs<NVM, kMFMA, R, kVMEM, 1>();
+  if constexpr (REST > 0) __builtin_amdgcn_sched_group_barrier(kMFMA, REST, 0);
+  __builtin_amdgcn_sched_group_barrier(kDSREAD, 4, 0);
+  sched_cols<NB / 2 - 1, NMFJ>();
+}
+
+// Workgroup barrier of the LDS ring.  __syncthreads() carries a release fence, for which the
+// compiler drains every direct-to-LDS load in flight; here each wave retires exactly what the
+// next step needs instead: its own LDS reads (so a slot may be refilled) and its global->LDS
+// loads up to the last KEEP (loads complete in order, so with only loads in flight this means
+// every load but the last KEEP has landed).  The empty asm statements with a memory clobber
+// keep the compiler from moving memory accesses across the barrier.
+template <int KEEP>
+__device__ __forceinline__ void ring_barrier() {
+  static_assert(KEEP >= 0 && KEEP <= 63, "vector-memory counter range");
+  // s_waitcnt vmcnt(KEEP) expcnt(7) lgkmcnt(0): vmcnt bits [3:0] and [15:14]
+  constexpr int imm = (KEEP & 15) | ((KEEP >> 4) << 14) | (7 << 4);
+  __builtin_amdgcn_s_waitcnt(imm);
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // ----------------------------------------------------------------------------- kernel
-// Per chunk q of a tile (term-major, then K), with chunk q's fragments already in registers:
-//   wait for chunk q+1's global->LDS loads and barrier (which also retires chunk q's LDS reads)
+// The chunks of a tile (term-major, then K) stream through a ring of S LDS slots, each a
+// separate __shared__ array so that the compiler can tell the slots' direct-to-LDS loads
+// apart and wait only for the slot it reads.  Chunk q lives in slot q % S.  Per chunk q,
+// with chunk q's fragments already in registers:
+//   wait for chunk q+1's global->LDS loads and barrier (which also retires chunk q's LDS
+//   reads, so slot q % S is free)
 //   read chunk q+1's fragments into the other register set
-//   start chunk q+2's loads into the LDS slot chunk q occupied (its data is in registers)
+//   start chunk q+S's loads into slot q % S
 //   run chunk q's matrix-core instructions
-// so the LDS reads and the global loads of later chunks overlap the matrix-core work.  The
-// chunks of one term run in two phases (occupied then unoccupied K), each an even number of
-// chunks, so the two register sets alternate in a fixed pattern.
-template <int PREC, int WMW, int WNW, int MB, int NB, int MODE>
+// so the LDS reads of the next chunk and the global loads of the following S-1 chunks overlap
+// the matrix-core work.  The chunks of one term run in two phases (occupied then unoccupied
+// K), each a multiple of S chunks, so slots and register sets follow a fixed pattern.
+template <int PREC, int WMW, int WNW, int MB, int NB, int S, int IL, int ROT, int MODE>
 __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
   using acc_t = typename Prec<PREC>::acc_t;
-  using frag_t = Frags<PREC, MB, NB>;
+  static_assert(!ROT || PREC == LRS_BF16X2 || PREC == LRS_FP16X2, "rotating B: split paths");
+  // with ROT the register sets hold A fragments only; the B fragments live in `bfr`
+  using frag_t = typename std::conditional<ROT != 0, FragsA<PREC, MB>, Frags<PREC, MB, NB>>::type;
   constexpr int TB = Prec<PREC>::TB;
   constexpr int BLK = Prec<PREC>::BLK, ELEMS = Prec<PREC>::ELEMS;
   constexpr int AM = MB * 16 / BLK, AN = NB * 16 / BLK;   // accumulator blocks per wave
@@ -376,8 +546,21 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
   constexpr int STAGE = A_BYTES + B_BYTES;
   constexpr int NWAVES = WMW * WNW;
   constexpr int NLOAD = STAGE / 1024;   // 1 KiB wave-wide loads per stage
+  constexpr int LPW = NLOAD / NWAVES;   // loads per wave per chunk
   static_assert(NLOAD % NWAVES == 0, "stage split");
-  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  static_assert(S == 2 || S == 4, "ring depth");
+  static_assert((S - 2) * LPW <= 63, "vector-memory counter range");
+  __shared__ __attribute__((aligned(1024))) unsigned char lds0[STAGE];
+  __shared__ __attribute__((aligned(1024))) unsigned char lds1[STAGE];
+  __shared__ __attribute__((aligned(1024))) unsigned char lds2[S > 2 ? STAGE : 1024];
+  __shared__ __attribute__((aligned(1024))) unsigned char lds3[S > 2 ? STAGE : 1024];
+  auto slot = [&](auto I) -> unsigned char* {
+    constexpr int i = decltype(I)::value;
+    if constexpr (i == 0) return lds0;
+    else if constexpr (i == 1) return lds1;
+    else if constexpr (i == 2) return lds2;
+    else return lds3;
+  };
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -389,31 +572,45 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
   const int nseq = P.T * nch;
   const size_t a_term = (size_t)P.a_nrb * nch * TB;
 
-  // global -> LDS slot for chunk q: the stage's A tiles and B tiles are each one contiguous
-  // run; the wave's share of its 1 KiB pieces goes straight into LDS (lane l's 16 bytes at
-  // +16 l).
-  auto issue = [&](const TileDesc& td, int q, int slot) {
-    const int t = q / nch, ch = q - t * nch;
-    const unsigned char* ab =
-        P.a + t * a_term + ((size_t)ch * P.a_nrb + (td.a_row0 >> 4)) * TB + lane * 16;
-    const unsigned char* bb = P.b + ((size_t)ch * P.b_ncb + (td.b_col0 >> 4)) * TB + lane * 16;
-    unsigned char* dst = lds + slot * STAGE;
+  // global -> LDS: the next chunk to load has its A tiles at `an` and its B tiles at `bn`; the
+  // stage's A tiles and B tiles are each one contiguous run, and the wave's share of its 1 KiB
+  // pieces goes straight into LDS (lane l's 16 bytes at +16 l).  The A operand is stored
+  // [term][chunk][row block], so its chunks follow each other across terms; the B operand has
+  // one term's worth of chunks and starts over at each term.
+  constexpr int NA = A_BYTES / 1024;
+  static_assert(NA % NWAVES == 0, "A pieces per wave");
+  const size_t a_step = (size_t)P.a_nrb * TB, b_step = (size_t)P.b_ncb * TB;
+  const unsigned char* an = nullptr;
+  const unsigned char* bn = nullptr;
+  const unsigned char* b0 = nullptr;
+  int cn = 0;
+  // `more` false (no chunk left in the tile): load the last chunk again, so that every step
+  // issues the same loads from in-bounds addresses; the slot it lands in is not read again in
+  // this tile, and the next tile's loads into it are issued later, so they land later.
+  auto issue_next = [&](unsigned char* dst, bool more) {
+    const unsigned char* a = more ? an : an - a_step;
+    const unsigned char* b = more ? bn : (cn == 0 ? b0 + (size_t)(nch - 1) * b_step : bn - b_step);
 #pragma unroll
-    for (int k = 0; k < NLOAD / NWAVES; ++k) {
+    for (int k = 0; k < LPW; ++k) {
       const int j = k * NWAVES + wave;
-      const unsigned char* src = j < A_BYTES / 1024 ? ab + j * 1024 : bb + (j - A_BYTES / 1024) * 1024;
+      const unsigned char* src = k * NWAVES < NA ? a + j * 1024 : b + (j - NA) * 1024;
       __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)src,
                                        (void __attribute__((address_space(3)))*)(dst + j * 1024),
                                        16, 0, 0);
     }
+    // advance without a branch, so that the step stays one basic block
+    const int c1 = cn + 1;
+    const bool wrap = more && c1 == nch;
+    an = more ? an + a_step : an;
+    bn = wrap ? b0 : (more ? bn + b_step : bn);
+    cn = wrap ? 0 : (more ? c1 : cn);
   };
+  // in steady state the loads of chunks q+2 .. q+S-1 may still be in flight at step q
+  constexpr int kKeep = (S - 2) * LPW;
 
   // G_o of the current term waits here (one slot per workgroup) while G_u accumulates.
   // Addresses used once per term are rebuilt from opaque copies of their inputs inside the term
   // loop, so that the compiler does not hoist them and keep them live across the chunk loop.
-  // A workgroup barrier does not wait for the vector-memory counter, so each wave drains its
-  // own global->LDS loads before the barrier that hands their bytes to the other waves.
-  auto dma_wait = [] { __builtin_amdgcn_s_waitcnt(0x0F70); };  // vmcnt(0)
   auto opaque = [](int x) {
     asm volatile("" : "+v"(x));
     return x;
@@ -427,28 +624,77 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
     const TileDesc td = P.tiles[tau];
     acc_t gr[AM][AN], gi[AM][AN];
     frag_t fa, fb;
+    FragsB<PREC, NB> bfr;
 
-    __syncthreads();                 // the previous tile is done with both slots
-    issue(td, 0, 0);
-    if (nseq > 1) issue(td, 1, 1);
-    dma_wait();
-    __syncthreads();                 // both slots landed
-    load_frags<PREC, MB, NB>(lds + wm * MB * TB, lds + A_BYTES + wn * NB * TB, lane, fa);
-    int q = 0;
-    // chunk q with its fragments in `cur`; the next chunk's fragments go to `nxt`
-    auto step = [&](frag_t& cur, frag_t& nxt) {
-      dma_wait();
-      __syncthreads();               // chunk q+1 landed (every wave waited on its loads);
-                                     // chunk q's LDS reads are complete
-      if (q + 1 < nseq) {
-        const unsigned char* s = lds + ((q + 1) & 1) * STAGE;
-        load_frags<PREC, MB, NB>(s + wm * MB * TB, s + A_BYTES + wn * NB * TB, lane, nxt);
+    ring_barrier<63>();              // the previous tile is done reading every slot
+    an = P.a + (size_t)(td.a_row0 >> 4) * TB + lane * 16;
+    b0 = P.b + (size_t)(td.b_col0 >> 4) * TB + lane * 16;
+    bn = b0;
+    cn = 0;
+    // every phase holds a multiple of S chunks, so the tile has at least S
+    issue_next(slot(std::integral_constant<int, 0>{}), true);
+    issue_next(slot(std::integral_constant<int, 1>{}), true);
+    if constexpr (S > 2) {
+      issue_next(slot(std::integral_constant<int, 2>{}), true);
+      issue_next(slot(std::integral_constant<int, 3>{}), true);
+    }
+    ring_barrier<0>();
+    {
+      const unsigned char* s0 = slot(std::integral_constant<int, 0>{});
+      if constexpr (ROT) {
+        load_a_split<PREC, MB>(s0 + wm * MB * TB, lane, fa);
+#pragma unroll
+        for (int j = 0; j < NB / 2; ++j)
+          load_b_split<PREC, NB>(s0 + A_BYTES + wn * NB * TB, lane, j, bfr);
+      } else {
+        load_frags<PREC, MB, NB>(s0 + wm * MB * TB, s0 + A_BYTES + wn * NB * TB, lane, fa);
       }
-      if (q + 2 < nseq) issue(td, q + 2, q & 1);
-      __builtin_amdgcn_sched_barrier(0);
-      mma_frags<PREC, MB, NB>(cur, gr, gi);
+    }
+    int q = 0;
+    // chunk q (in slot I = q % S) with its fragments in `cur`; the next chunk's fragments go
+    // to `nxt`.  Every step issues LPW loads per wave, so at step q the loads of chunks
+    // q+2 .. q+S-1 are the last kKeep; `full` asks for a complete drain instead (first chunk of
+    // a phase, after the previous phase's global stores).
+    auto step = [&](auto I, frag_t& cur, frag_t& nxt, bool full) {
+      constexpr int i = decltype(I)::value;
+      constexpr int inext = (i + 1) % S;
+      if (full) ring_barrier<0>();
+      else ring_barrier<kKeep>();
+      // (after the tile's last chunk these fragments are read but not used)
+      const unsigned char* sn = slot(std::integral_constant<int, inext>{});
+      if constexpr (ROT) {
+        load_a_split<PREC, MB>(sn + wm * MB * TB, lane, nxt);
+        issue_next(slot(I), q + S < nseq);
+#pragma unroll
+        for (int j = 0; j < NB / 2; ++j) {
+          mma_col_split<PREC, MB, NB>(cur, bfr, j, gr, gi);
+          load_b_split<PREC, NB>(sn + A_BYTES + wn * NB * TB, lane, j, bfr);
+        }
+        interleave_rot<MB, NB, LPW>();
+      } else {
+        load_frags<PREC, MB, NB>(sn + wm * MB * TB, sn + A_BYTES + wn * NB * TB, lane, nxt);
+        issue_next(slot(I), q + S < nseq);
+        if constexpr (IL == 0) {
+          // LDS reads and loads first, then the matrix-core block
+          __builtin_amdgcn_sched_barrier(0);
+          mma_frags<PREC, MB, NB>(cur, gr, gi);
+        } else {
+          // LDS reads and loads spread between the matrix-core instructions
+          mma_frags<PREC, MB, NB>(cur, gr, gi);
+          interleave<PREC, MB, NB, LPW>();
+        }
+      }
       __builtin_amdgcn_sched_barrier(0);
       ++q;
+    };
+    // one ring cycle: S chunks starting at slot 0
+    auto cycle = [&](bool first) {
+      step(std::integral_constant<int, 0>{}, fa, fb, first);
+      step(std::integral_constant<int, 1>{}, fb, fa, false);
+      if constexpr (S > 2) {
+        step(std::integral_constant<int, 2 % S>{}, fa, fb, false);
+        step(std::integral_constant<int, 3 % S>{}, fb, fa, false);
+      }
     };
     auto zero = [&] {
 #pragma unroll
@@ -461,10 +707,7 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
     };
     for (int t = 0; t < P.T; ++t) {
       zero();
-      for (int ch = 0; ch < P.nch_o; ch += 2) {
-        step(fa, fb);
-        step(fb, fa);
-      }
+      for (int ch = 0; ch < P.nch_o; ch += S) cycle(ch == 0);
       {
         const int ln = opaque(lane);
 #pragma unroll
@@ -476,94 +719,100 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
           }
       }
       zero();
-      for (int ch = P.nch_o; ch < nch; ch += 2) {
-        step(fa, fb);
-        step(fb, fa);
-      }
-      // here gr, gi hold G_u; G_o comes back block by block
+      for (int ch = P.nch_o; ch < nch; ch += S) cycle(ch == P.nch_o);
+      // here gr, gi hold G_u; G_o comes back block by block.  Per accumulator block every
+      // global load is issued before the first use (elements outside the output take the
+      // tile origin's address and skip the store), so the block costs one memory latency.
       const int ln = opaque(lane);
       const long long obase = td.out_off + opaque(0);
-      if constexpr (MODE == 1) {
-        // adjoint: Hu = lam * conj(G_u), Ho = lam * conj(G_o) on this tile (single term)
 #pragma unroll
-        for (int i = 0; i < AM; ++i)
+      for (int i = 0; i < AM; ++i)
 #pragma unroll
-          for (int j = 0; j < AN; ++j) {
-            const acc_t or_ = *park_at(ln, i, j, 0), oi_ = *park_at(ln, i, j, 1);
+        for (int j = 0; j < AN; ++j) {
+          const acc_t or_ = *park_at(ln, i, j, 0), oi_ = *park_at(ln, i, j, 1);
+          int off[ELEMS];
+          bool in[ELEMS];
+#pragma unroll
+          for (int e = 0; e < ELEMS; ++e) {
+            int rr, cc;
+            elem_rc<PREC>(ln, e, rr, cc);
+            const int row = wm * MB * 16 + i * BLK + rr;
+            const int col = wn * NB * 16 + j * BLK + cc;
+            in[e] = row < td.nrows && col < td.ncols;
+            off[e] = in[e] ? row * td.ldo + col : 0;
+          }
+          if constexpr (MODE == 1) {
+            // adjoint: Hu = lam * conj(G_u), Ho = lam * conj(G_o) on this tile (single term)
+            double l[ELEMS];
+#pragma unroll
+            for (int e = 0; e < ELEMS; ++e) l[e] = P.lam[obase + off[e]];
+#pragma unroll
+            for (int e = 0; e < ELEMS; ++e)
+              if (in[e]) {
+                const long long o = obase + off[e];
+                P.hu_re[o] = l[e] * (double)gr[i][j][e];
+                P.hu_im[o] = -l[e] * (double)gi[i][j][e];
+                P.ho_re[o] = l[e] * (double)or_[e];
+                P.ho_im[o] = -l[e] * (double)oi_[e];
+              }
+          } else {
+            // chi accumulates across terms in FP64 in the output itself (this tile's entries
+            // belong to this workgroup only); the last term applies the prefactor
+            const double ct = P.c[t];
+            const double scale = t == P.T - 1 ? P.pref : 1.0;
+            double old[ELEMS];
+            if (t > 0) {
+#pragma unroll
+              for (int e = 0; e < ELEMS; ++e) old[e] = P.out[obase + off[e]];
+            } else {
+#pragma unroll
+              for (int e = 0; e < ELEMS; ++e) old[e] = 0.0;
+            }
 #pragma unroll
             for (int e = 0; e < ELEMS; ++e) {
-              int rr, cc;
-              elem_rc<PREC>(ln, e, rr, cc);
-              const int row = wm * MB * 16 + i * BLK + rr;
-              const int col = wn * NB * 16 + j * BLK + cc;
-              if (row < td.nrows && col < td.ncols) {
-                const long long o = obase + (long long)row * td.ldo + col;
-                const double l = P.lam[o];
-                P.hu_re[o] = l * (double)gr[i][j][e];
-                P.hu_im[o] = -l * (double)gi[i][j][e];
-                P.ho_re[o] = l * (double)or_[e];
-                P.ho_im[o] = -l * (double)oi_[e];
-              }
+              const double v = ct * ((double)or_[e] * (double)gr[i][j][e] +
+                                     (double)oi_[e] * (double)gi[i][j][e]);
+              if (in[e]) P.out[obase + off[e]] = (v + old[e]) * scale;
             }
           }
-      } else {
-        // chi accumulates across terms in FP64 in the output itself (this tile's entries
-        // belong to this workgroup only); the last term applies the prefactor
-        const double ct = P.c[t];
-        const bool first = t == 0, last = t == P.T - 1;
-#pragma unroll
-        for (int i = 0; i < AM; ++i)
-#pragma unroll
-          for (int j = 0; j < AN; ++j) {
-            const acc_t or_ = *park_at(ln, i, j, 0), oi_ = *park_at(ln, i, j, 1);
-#pragma unroll
-            for (int e = 0; e < ELEMS; ++e) {
-              int rr, cc;
-              elem_rc<PREC>(ln, e, rr, cc);
-              const int row = wm * MB * 16 + i * BLK + rr;
-              const int col = wn * NB * 16 + j * BLK + cc;
-              if (row < td.nrows && col < td.ncols) {
-                double* o = P.out + obase + (long long)row * td.ldo + col;
-                double v = ct * ((double)or_[e] * (double)gr[i][j][e] +
-                                 (double)oi_[e] * (double)gi[i][j][e]);
-                if (!first) v += *o;
-                if (last) v *= P.pref;
-                *o = v;
-              }
-            }
-          }
-      }
+        }
     }
   }
 }
 
-// variant table: {WMW, WNW, MB, NB}
+// variant table: {WMW, WNW, MB, NB, S, IL, ROT}; S = LDS ring slots, IL = 1 interleaves the LDS
+// reads and loads with the matrix-core instructions, ROT = 1 rotates the B fragments (split
+// paths; allows the 64 x 128 and 128 x 64 wave tiles)
 template <int PREC, int V>
 struct Variant;
-#define LRS_VARIANT(PR, V, A, B, C, D)                                  \
+#define LRS_VARIANT(PR, V, A, B, C, D, E, F, G)                         \
   template <>                                                          \
   struct Variant<PR, V> {                                              \
-    static constexpr int WMW = A, WNW = B, MB = C, NB = D;             \
+    static constexpr int WMW = A, WNW = B, MB = C, NB = D, S = E, IL = F, ROT = G; \
   };
-LRS_VARIANT(LRS_FP64, 0, 2, 2, 2, 2)
-LRS_VARIANT(LRS_FP64, 1, 2, 2, 2, 4)
-LRS_VARIANT(LRS_FP64, 2, 2, 2, 4, 2)
-LRS_VARIANT(LRS_FP32, 0, 2, 2, 2, 4)
-LRS_VARIANT(LRS_FP32, 1, 2, 2, 2, 2)
-LRS_VARIANT(LRS_FP32, 2, 2, 2, 4, 2)
-LRS_VARIANT(LRS_BF16X2, 0, 2, 2, 4, 4)
-LRS_VARIANT(LRS_BF16X2, 1, 2, 2, 2, 4)
-LRS_VARIANT(LRS_BF16X2, 2, 2, 2, 4, 2)
-LRS_VARIANT(LRS_FP16X2, 0, 2, 2, 4, 4)
-LRS_VARIANT(LRS_FP16X2, 1, 2, 2, 2, 4)
-LRS_VARIANT(LRS_FP16X2, 2, 2, 2, 4, 2)
+LRS_VARIANT(LRS_FP64, 0, 2, 2, 2, 4, 2, 1, 0)
+LRS_VARIANT(LRS_FP64, 1, 2, 2, 2, 2, 4, 1, 0)
+LRS_VARIANT(LRS_FP64, 2, 2, 2, 2, 2, 4, 0, 0)
+LRS_VARIANT(LRS_FP64, 3, 2, 2, 2, 4, 2, 0, 0)
+LRS_VARIANT(LRS_FP32, 0, 2, 2, 2, 2, 4, 1, 0)
+LRS_VARIANT(LRS_FP32, 1, 2, 2, 2, 4, 2, 1, 0)
+LRS_VARIANT(LRS_FP32, 2, 2, 2, 2, 4, 2, 0, 0)
+LRS_VARIANT(LRS_FP32, 3, 2, 2, 2, 2, 4, 0, 0)
+LRS_VARIANT(LRS_BF16X2, 0, 2, 2, 4, 4, 4, 1, 0)
+LRS_VARIANT(LRS_BF16X2, 1, 2, 2, 4, 8, 2, 1, 1)
+LRS_VARIANT(LRS_BF16X2, 2, 1, 4, 8, 4, 2, 1, 1)
+LRS_VARIANT(LRS_BF16X2, 3, 2, 2, 4, 4, 4, 0, 0)
+LRS_VARIANT(LRS_FP16X2, 0, 2, 2, 4, 4, 4, 1, 0)
+LRS_VARIANT(LRS_FP16X2, 1, 2, 2, 4, 8, 2, 1, 1)
+LRS_VARIANT(LRS_FP16X2, 2, 1, 4, 8, 4, 2, 1, 1)
+LRS_VARIANT(LRS_FP16X2, 3, 2, 2, 4, 4, 4, 0, 0)
 #undef LRS_VARIANT
-constexpr int kNumVariants = 3;
+constexpr int kNumVariants = 4;
 
 template <int PREC, int V>
 constexpr int lds_bytes_v() {
   using Vt = Variant<PREC, V>;
-  return 2 * (Vt::WMW * Vt::MB + Vt::WNW * Vt::NB) * Prec<PREC>::TB;
+  return Vt::S * (Vt::WMW * Vt::MB + Vt::WNW * Vt::NB) * Prec<PREC>::TB;
 }
 
 template <int PREC, int V>
@@ -574,18 +823,17 @@ constexpr size_t park_bytes_v() {
 }
 
 template <int PREC, int V, int MODE>
+constexpr auto kernel_v() {
+  using Vt = Variant<PREC, V>;
+  static_assert(lds_bytes_v<PREC, V>() <= 160 * 1024, "LDS ring too large");
+  return &chi0_kernel<PREC, Vt::WMW, Vt::WNW, Vt::MB, Vt::NB, Vt::S, Vt::IL, Vt::ROT, MODE>;
+}
+
+template <int PREC, int V, int MODE>
 hipError_t launch_v(int grid, const Chi0Params& P, hipStream_t s) {
   using Vt = Variant<PREC, V>;
-  auto k = chi0_kernel<PREC, Vt::WMW, Vt::WNW, Vt::MB, Vt::NB, MODE>;
-  constexpr int lds = lds_bytes_v<PREC, V>();
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
-  hipLaunchKernelGGL(k, dim3(grid), dim3(Vt::WMW * Vt::WNW * 64), lds, s, P);
+  constexpr auto k = kernel_v<PREC, V, MODE>();
+  hipLaunchKernelGGL(k, dim3(grid), dim3(Vt::WMW * Vt::WNW * 64), 0, s, P);
   return hipGetLastError();
 }
 
@@ -595,6 +843,7 @@ hipError_t launch_p(int variant, int grid, const Chi0Params& P, hipStream_t s) {
     case 0: return launch_v<PREC, 0, 0>(grid, P, s);
     case 1: return launch_v<PREC, 1, 0>(grid, P, s);
     case 2: return launch_v<PREC, 2, 0>(grid, P, s);
+    case 3: return launch_v<PREC, 3, 0>(grid, P, s);
   }
   return hipErrorInvalidValue;
 }
@@ -610,7 +859,8 @@ TileShape shape_p(int v) {
   switch (v) {
     case 0: return shape_v<PREC, 0>();
     case 1: return shape_v<PREC, 1>();
-    default: return shape_v<PREC, 2>();
+    case 2: return shape_v<PREC, 2>();
+    default: return shape_v<PREC, 3>();
   }
 }
 
@@ -619,8 +869,8 @@ int occ_v() {
   using Vt = Variant<PREC, V>;
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &n, reinterpret_cast<const void*>(&chi0_kernel<PREC, Vt::WMW, Vt::WNW, Vt::MB, Vt::NB, 0>),
-          Vt::WMW * Vt::WNW * 64, lds_bytes_v<PREC, V>()) != hipSuccess)
+          &n, reinterpret_cast<const void*>(kernel_v<PREC, V, 0>()), Vt::WMW * Vt::WNW * 64, 0) !=
+      hipSuccess)
     return 1;
   return n;
 }
@@ -629,7 +879,8 @@ int occ_p(int v) {
   switch (v) {
     case 0: return occ_v<PREC, 0>();
     case 1: return occ_v<PREC, 1>();
-    default: return occ_v<PREC, 2>();
+    case 2: return occ_v<PREC, 2>();
+    default: return occ_v<PREC, 3>();
   }
 }
 

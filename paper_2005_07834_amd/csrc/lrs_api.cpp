@@ -316,6 +316,18 @@ lrs_status get_plan(lrs_ctx* ctx, int site, int cols, int prec, int variant, int
   cur.ntiles = (int)tiles.size() - cur.tile0;
   p.batches.push_back(cur);
   p.ntiles = (int)tiles.size();
+  // every tile's operand reads (bm rows of its batch's A, bn columns of B) stay inside the
+  // operands; the kernel does not check them
+  {
+    const int b_cols = cols == LRS_COLS_GRID ? ctx->grid_cols_pad : ctx->site_cols_pad;
+    for (const Batch& b : p.batches)
+      for (int i = b.tile0; i < b.tile0 + b.ntiles; ++i) {
+        const TileDesc& t = tiles[i];
+        if (t.a_row0 < 0 || t.a_row0 % 16 || t.a_row0 + sh.bm > b.nrb * 16 || t.b_col0 < 0 ||
+            t.b_col0 % 16 || t.b_col0 + sh.bn > b_cols || t.nrows <= 0 || t.ncols <= 0)
+          return fail(ctx, LRS_EINVAL, "internal: tile %d exceeds its operands", i);
+      }
+  }
   int per_cu = chi0_blocks_per_cu(prec, variant);
   long long maxg = (long long)ctx->num_cu * std::max(1, per_cu);
   for (auto& b : p.batches) {
@@ -520,9 +532,9 @@ lrs_status lrs_set_orbitals(lrs_ctx* ctx, int nk, int nb, int nocc, int spin_fac
 
   // sizes and storage for the new state, validated before the old state is dropped
   const int Ko = nk * nocc, Ku = nk * (nb - nocc);
-  const int Ko_pad = (int)round_up(Ko, 64), Ku_pad = (int)round_up(Ku, 64);
+  const int Ko_pad = (int)round_up(Ko, kPhaseAlign), Ku_pad = (int)round_up(Ku, kPhaseAlign);
   const int K_pad = Ko_pad + Ku_pad;
-  const int cols_pad = ngrid > 0 ? (int)round_up(ngrid, kRowAlign) + kRowAlign : 0;
+  const int cols_pad = ngrid > 0 ? (int)round_up(ngrid, kRowAlign) + kMaxTileCols : 0;
   DevBuf tiles;
   if (ngrid > 0) {
     size_t bytes = (size_t)(cols_pad / 16) * (K_pad / kChunkF64) * kTileBytes;
@@ -624,7 +636,7 @@ lrs_status lrs_set_sites(lrs_ctx* ctx, int nsites, const int* nrad, const int* n
   }
   ctx->nrows = (int)nrows;
   ctx->rows_pad = (int)round_up(nrows, kRowAlign) + kRowAlign;
-  ctx->site_cols_pad = ctx->site_col_off[nsites] + kRowAlign;
+  ctx->site_cols_pad = ctx->site_col_off[nsites] + kMaxTileCols;
   ctx->site_max_abs = m;
   ctx->site_scale_f16 = pow2_prescale(m);
   // column map of the site column operand: padded column -> site row (-1 = zero column)

@@ -20,6 +20,12 @@ namespace lrs {
 constexpr int kTileBytes = 4096;   // FP64 and FP32 tiles
 constexpr int kChunkF64 = 16;
 constexpr int kRowAlign = 128;  // rows / columns of every operand are padded to this
+// widest output tile of any kernel variant: column operands carry this much slack past their
+// last 128-column slot, so a full-width last tile reads inside the operand
+constexpr int kMaxTileCols = 256;
+// each K phase (occupied, unoccupied) is padded to this: a multiple of four chunks of every
+// precision, so the kernel's four-slot LDS ring starts every phase at slot 0
+constexpr int kPhaseAlign = 128;
 constexpr int kMaxTerms = 128;
 
 inline bool is_split(int prec) { return prec == LRS_BF16X2 || prec == LRS_FP16X2; }
