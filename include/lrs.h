@@ -156,7 +156,13 @@ lrs_status lrs_get_quadrature(const lrs_ctx* ctx, int* nterms, double* c_host, d
 /* chi0 for one site (site >= 0) or all sites concatenated (site = -1), in precision prec.
  *   LRS_COLS_GRID: chi0_out float64 [rows][ngrid], rows = npts of the site (or all sites).
  *   LRS_COLS_SITE: chi0_out float64 site blocks [npts_s][npts_s], concatenated over sites.
- * chi0 is real for the static case, so float64 is returned.  Asynchronous. */
+ * chi0 is real for the static case, so float64 is returned.  Asynchronous.
+ * All sites and terms go into one persistent launch per operand batch (a batch holds as many
+ * sites' weighted operands as fit LRS_SITE_OPERAND_BYTES, default 24 GiB).
+ * Graph capture: once a call has run on a problem (same site, column set and precision), the
+ * same call may be captured on the context's stream (e.g. into a HIP graph); under capture it
+ * records kernels only, records no timing event, and returns LRS_ESTATE instead of
+ * allocating or building a plan. */
 lrs_status lrs_compute_chi0(lrs_ctx* ctx, int site, int cols, int prec, double* chi0_out);
 
 /* Per-site dielectric solve from site x site chi0 blocks (layout of LRS_COLS_SITE, all sites):

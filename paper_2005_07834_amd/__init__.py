@@ -82,6 +82,8 @@ def _ptr(x):
 
 
 def _host(a, dtype):
+    if isinstance(a, torch.Tensor):
+        a = a.detach().cpu().numpy()
     return np.ascontiguousarray(np.asarray(a, dtype=dtype))
 
 
@@ -106,6 +108,10 @@ class Context:
         self.h = h
         self._keep = []
         self.nsites = 0
+        # bumped by every call that changes the state a backward pass reads: orbitals, sites
+        # and quadrature (chi0 adjoint), and the last W solve (W adjoint)
+        self.orb_version = 0
+        self.screen_version = 0
 
     def close(self):
         if getattr(self, "h", None):
@@ -133,6 +139,7 @@ class Context:
             g = _dev(psi_grid, torch.complex128, self.device)
             assert g.shape[:2] == (nk, nb)
             ngrid = g.shape[2]
+        self.orb_version += 1
         self._check(lib.lrs_set_orbitals(self.h, nk, nb, nocc, spin, _ptr(E), mu, delta, _ptr(g),
                                          ngrid, grid_dV))
         self.nk, self.nb, self.nocc, self.ngrid = nk, nb, nocc, ngrid
@@ -145,6 +152,7 @@ class Context:
         axyz = _host(np.concatenate([s.ang_xyz for s in sites]), np.float64)
         angw = _host(np.concatenate([s.ang_w for s in sites]), np.float64)
         p = _dev(psi_site, torch.complex128, self.device)
+        self.orb_version += 1
         self._check(lib.lrs_set_sites(self.h, len(sites), _ptr(nrad), _ptr(nang), _ptr(radii),
                                       _ptr(radw), _ptr(axyz), _ptr(angw), _ptr(p), lmax))
         self.nsites = len(sites)
@@ -152,12 +160,14 @@ class Context:
         self.nbasis = [(lmax + 1) ** 2 * s.n_rad for s in sites]
 
     def make_quadrature(self, kind=QUAD_TIME, nnodes=16, scale=0.0):
+        self.orb_version += 1
         self._check(lib.lrs_make_quadrature(self.h, kind, nnodes, scale))
 
     def set_quadrature(self, c, alpha, beta):
         c = _host(c, np.float64)
         a = _host(alpha, np.float64)
         b = _host(beta, np.float64)
+        self.orb_version += 1
         self._check(lib.lrs_set_quadrature(self.h, c.shape[0], _ptr(c), _ptr(a), _ptr(b)))
 
     def get_quadrature(self):
@@ -199,6 +209,7 @@ class Context:
         r = None if rho is None else _dev(rho, torch.float64, self.device)
         loss = torch.empty(self.nsites, dtype=torch.float64, device=self.device) if want_loss else None
         self._keep = [r]
+        self.screen_version += 1
         self._check(lib.lrs_screen_W(self.h, _ptr(chi0_ss.contiguous()), _ptr(W), _ptr(r),
                                      _ptr(loss)))
         return W, loss
@@ -233,11 +244,101 @@ class Context:
         return float(lib.lrs_last_kernel_ms(self.h))
 
 
+class Chi0Fn(torch.autograd.Function):
+    """chi0 on the site x site blocks (FP64 path) as a differentiable function of the band
+    energies and the site orbitals: Eq. chi1 with the imaginary-time quadrature.
+
+    ``Chi0Fn.apply(energies, psi_site, ctx, nocc, sites, nnodes, scale)`` sets the context's
+    orbitals (no grid), sites and quadrature, and returns the flat site-block layout.  The
+    backward pass runs the library's adjoint (Green's functions recomputed per term) and
+    returns dL/de [nk, nb] and dL/dpsi_site (complex, dL/dRe + i dL/dIm).  The nodes and mu
+    are held fixed: pass ``scale > 0`` so the node set does not depend on the energies.  If
+    the context was given other inputs since the forward pass, the backward pass sets the
+    forward's inputs again first.
+    """
+
+    @staticmethod
+    def _setup(lctx, energies, psi_site, nocc, sites, nnodes, scale):
+        lctx.set_orbitals(energies, nocc)
+        lctx.set_sites(sites, psi_site)
+        lctx.make_quadrature(QUAD_TIME, nnodes, scale)
+
+    @staticmethod
+    def forward(fctx, energies, psi_site, lctx, nocc, sites, nnodes, scale):
+        args = (energies.detach() if isinstance(energies, torch.Tensor) else energies,
+                psi_site.detach(), nocc, sites, nnodes, scale)
+        Chi0Fn._setup(lctx, *args)
+        out = lctx.chi0(-1, COLS_SITE, FP64)
+        fctx.lctx = lctx
+        fctx.args = args
+        fctx.version = lctx.orb_version
+        fctx.e_like = (energies.device, energies.dtype) if isinstance(energies, torch.Tensor) \
+            else (torch.device("cpu"), torch.float64)
+        return out
+
+    @staticmethod
+    def backward(fctx, g):
+        lctx = fctx.lctx
+        if lctx.orb_version != fctx.version:
+            Chi0Fn._setup(lctx, *fctx.args)
+            fctx.version = lctx.orb_version
+        dE, dpsi = lctx.chi0_backward(g)
+        return (dE.to(device=fctx.e_like[0], dtype=fctx.e_like[1]), dpsi,
+                None, None, None, None, None)
+
+
+class ScreenWFn(torch.autograd.Function):
+    """The per-site solve W = (1 - v chi0)^-1 v of Sec. VI.E as a differentiable function of
+    the site-block chi0, with the test-charge loss L_s = rho^T D W D rho per site.
+
+    ``W, loss = ScreenWFn.apply(chi0_ss, ctx, rho)`` (rho may be None: loss is then zero and
+    not differentiable).  The backward pass combines dL/dW and dL/dloss through the library's
+    adjoint; if the context solved another problem since the forward pass, the forward's solve
+    is run again first (with the context's sites, which must be the forward's).
+    """
+
+    @staticmethod
+    def forward(fctx, chi0_ss, lctx, rho):
+        chi = chi0_ss.detach()
+        W, loss = lctx.screen_W(chi, rho=rho, want_loss=rho is not None)
+        fctx.lctx = lctx
+        fctx.saved = (chi, rho)
+        # new sites drop the kept W too, so both counters are watched
+        fctx.version = (lctx.orb_version, lctx.screen_version)
+        fctx.has_loss = rho is not None
+        if loss is None:
+            loss = torch.zeros(lctx.nsites, dtype=torch.float64, device=lctx.device)
+        if rho is None:
+            fctx.mark_non_differentiable(loss)
+        return W, loss
+
+    @staticmethod
+    def backward(fctx, gW, gloss):
+        lctx = fctx.lctx
+        if (lctx.orb_version, lctx.screen_version) != fctx.version:
+            chi, rho = fctx.saved
+            lctx.screen_W(chi, rho=rho, want_loss=rho is not None)
+            fctx.version = (lctx.orb_version, lctx.screen_version)
+        total = None
+        if fctx.has_loss and gloss is not None and bool((gloss != 0).any()):
+            # each site's loss depends on its own block only: scale the blocks of d(sum L)/dchi0
+            total = lctx.screen_W_backward(None)
+            for s, b in enumerate(lctx.site_blocks(total)):
+                b.mul_(gloss[s])
+        if gW is not None and bool((gW != 0).any()):
+            g2 = lctx.screen_W_backward(gW)
+            total = g2 if total is None else total + g2
+        if total is None:
+            total = torch.zeros(sum(n * n for n in lctx.npts), dtype=torch.float64,
+                                device=lctx.device)
+        return total, None, None
+
+
 def check_bands(energies, nocc, mu=float("nan"), delta=0.0):
     """Host-only validation of a band set; returns the status code."""
     E = _host(energies, np.float64)
     return lib.lrs_check_bands(E.shape[0], E.shape[1], nocc, _ptr(E), mu, delta)
 
 
-__all__ = ["lib", "Context", "LrsError", "check_bands", "FP64", "FP32", "BF16X2", "FP16X2",
+__all__ = ["lib", "Context", "LrsError", "check_bands", "Chi0Fn", "ScreenWFn", "FP64", "FP32", "BF16X2", "FP16X2",
            "COLS_GRID", "COLS_SITE", "QUAD_TIME", "QUAD_FREQ", "SIGNATURES"]

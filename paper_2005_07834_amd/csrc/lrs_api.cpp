@@ -54,6 +54,9 @@ void release(lrs_ctx* ctx, DevBuf& b) {
 lrs_status ensure_buf(lrs_ctx* ctx, DevBuf& b, size_t bytes, const char* what) {
   bytes = (size_t)round_up((long long)std::max<size_t>(bytes, 256), 256);
   if (b.p && b.bytes >= bytes) return LRS_OK;
+  if (ctx->capturing)
+    return fail(ctx, LRS_ESTATE, "%s: the call would allocate during stream capture; run it "
+                "once on the same problem before capturing", what);
   release(ctx, b);
   if (ctx->max_bytes && ctx->bytes_in_use + bytes > ctx->max_bytes)
     return fail(ctx, LRS_ENOMEM, "%s: %zu bytes would exceed LRS_MAX_BYTES (%zu in use)", what,
@@ -272,6 +275,9 @@ lrs_status get_plan(lrs_ctx* ctx, int site, int cols, int prec, int variant, int
     *out = &it->second;
     return LRS_OK;
   }
+  if (ctx->capturing)
+    return fail(ctx, LRS_ESTATE, "the tile plan would be built during stream capture; run the "
+                "call once on the same problem before capturing");
   TileShape sh = chi0_shape(prec, variant);
   if (kRowAlign % sh.bm != 0) return fail(ctx, LRS_EINVAL, "tile rows must divide %d", kRowAlign);
   const int nt = mode == 1 ? 1 : ctx->quad.nterms;
@@ -803,8 +809,18 @@ lrs_status lrs_compute_chi0(lrs_ctx* ctx, int site, int cols, int prec, double* 
   if (cols != LRS_COLS_GRID && cols != LRS_COLS_SITE) return fail(ctx, LRS_EINVAL, "bad column set");
   if (prec < LRS_FP64 || prec > LRS_FP16X2) return fail(ctx, LRS_EINVAL, "bad precision");
   if (cols == LRS_COLS_GRID && ctx->ngrid <= 0) return fail(ctx, LRS_ESTATE, "no grid orbitals were given");
-  HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
-  return run_chi0(ctx, site, cols, prec, pick_variant(ctx, prec), out, true);
+  int cur = -1;
+  HIP_OR_FAIL(ctx, hipGetDevice(&cur));
+  if (cur != ctx->device) HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+  // under stream capture the call records its kernels only: no timing events, and anything
+  // that would allocate or build a plan is refused
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_OR_FAIL(ctx, hipStreamIsCapturing(ctx->stream, &cs));
+  ctx->capturing = cs != hipStreamCaptureStatusNone;
+  if (ctx->capturing) ctx->timed = false;
+  const lrs_status st = run_chi0(ctx, site, cols, prec, pick_variant(ctx, prec), out, !ctx->capturing);
+  ctx->capturing = false;
+  return st;
 }
 
 double lrs_last_kernel_ms(lrs_ctx* ctx) {

@@ -143,6 +143,9 @@ struct lrs_ctx {
   // timing
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool timed = false;
+  // set while a call runs on a stream that is being captured into a graph: nothing may
+  // allocate, copy from the host or synchronise then
+  bool capturing = false;
 };
 
 namespace lrs {
