@@ -285,13 +285,16 @@ lrs_status get_plan(lrs_ctx* ctx, int site, int cols, int prec, int variant, int
   int max_rb = (int)std::min<size_t>(1 << 20, a_budget() / std::max<size_t>(per_rb, 1));
   max_rb = std::max(kRowAlign / 16, max_rb / (kRowAlign / 16) * (kRowAlign / 16));
   const int s0 = site < 0 ? 0 : site, s1 = site < 0 ? ctx->nsites : site + 1;
-  // walk the sites' 128-row slot chunks, cutting batches at max_rb row blocks
-  std::vector<TileDesc> tiles;
+  // 1. the sites' rows in tiles of bm rows (128-row slots hold 128/bm of them), cut into
+  //    batches at max_rb row blocks of weighted site operand
+  struct RowTile {
+    int site, slot_row, rows, m0;   // m0: first row within the site
+  };
+  std::vector<std::vector<RowTile>> brows(1);
   Plan p;
   p.variant = variant;
   Batch cur;
   cur.rb0 = ctx->site_col_off[s0] / 16;
-  long long base_site = 0;     // site-block output offset (SITE)
   for (int s = s0; s < s1; ++s) {
     const int n = ctx->site_off[s + 1] - ctx->site_off[s];
     const int slot0 = ctx->site_col_off[s];
@@ -299,28 +302,86 @@ lrs_status get_plan(lrs_ctx* ctx, int site, int cols, int prec, int variant, int
       const int rb = (slot0 + m0) / 16;
       if (rb + kRowAlign / 16 - cur.rb0 > max_rb && rb > cur.rb0) {
         cur.nrb = rb - cur.rb0;
-        cur.ntiles = (int)tiles.size() - cur.tile0;
         p.batches.push_back(cur);
+        brows.emplace_back();
         cur = Batch();
         cur.rb0 = rb;
-        cur.tile0 = (int)tiles.size();
       }
-      const int rows = std::min(kRowAlign, n - m0);
-      const int a_row0 = slot0 + m0 - cur.rb0 * 16;
-      if (cols == LRS_COLS_GRID) {
-        const long long orow = ctx->site_off[s] - ctx->site_off[s0] + m0;
-        add_region(tiles, a_row0, rows, 0, ctx->ngrid, orow * ctx->ngrid, ctx->ngrid, sh.bm, sh.bn);
-      } else {
-        add_region(tiles, a_row0, rows, slot0, n, base_site + (long long)m0 * n, n, sh.bm, sh.bn);
-      }
+      for (int r = m0; r < std::min(n, m0 + kRowAlign); r += sh.bm)
+        brows.back().push_back(RowTile{s, slot0 + r, std::min(sh.bm, n - r), r});
     }
-    base_site += (long long)n * n;
   }
   const int last_slot = ctx->site_col_off[s1 - 1] +
                         (int)round_up(ctx->site_off[s1] - ctx->site_off[s1 - 1], kRowAlign);
   cur.nrb = last_slot / 16 - cur.rb0;
-  cur.ntiles = (int)tiles.size() - cur.tile0;
   p.batches.push_back(cur);
+  // 2. tiles in 2-D blocks: the workgroups of one XCD run 32 consecutive tiles of the list
+  //    at a time and the whole grid runs 256, so the list goes in 16 x 16 blocks of
+  //    (row tile, column tile), each made of eight 4 x 8 blocks: the concurrent tiles of an
+  //    XCD then share 4 A and 8 B panels in its L2, and those of the grid 16 + 16 in the
+  //    memory-side cache, instead of one row against hundreds of columns.
+  std::vector<TileDesc> tiles;
+  auto emit_blocked = [&](int nr, int nc, auto&& make) {
+    constexpr int SR = 16, SC = 16, BR = 4, BC = 8;
+    for (int R0 = 0; R0 < nr; R0 += SR)
+      for (int C0 = 0; C0 < nc; C0 += SC) {
+        const int R1 = std::min(nr, R0 + SR), C1 = std::min(nc, C0 + SC);
+        for (int r1 = R0; r1 < R1; r1 += BR)
+          for (int c1 = C0; c1 < C1; c1 += BC)
+            for (int r = r1; r < std::min(R1, r1 + BR); ++r)
+              for (int c = c1; c < std::min(C1, c1 + BC); ++c) make(r, c);
+      }
+  };
+  std::vector<long long> site_base(ctx->nsites + 1, 0);   // site-block output offsets
+  for (int s = s0; s < s1; ++s) {
+    const long long n = ctx->site_off[s + 1] - ctx->site_off[s];
+    site_base[s + 1] = site_base[s] + n * n;
+  }
+  for (size_t bi = 0; bi < p.batches.size(); ++bi) {
+    Batch& bt = p.batches[bi];
+    const std::vector<RowTile>& rt = brows[bi];
+    bt.tile0 = (int)tiles.size();
+    if (cols == LRS_COLS_GRID) {
+      const int ng = ctx->ngrid, nc = (ng + sh.bn - 1) / sh.bn;
+      emit_blocked((int)rt.size(), nc, [&](int r, int c) {
+        const RowTile& x = rt[r];
+        const long long orow = ctx->site_off[x.site] - ctx->site_off[s0] + x.m0;
+        TileDesc t;
+        t.a_row0 = x.slot_row - bt.rb0 * 16;
+        t.b_col0 = c * sh.bn;
+        t.nrows = x.rows;
+        t.ncols = std::min(sh.bn, ng - c * sh.bn);
+        t.out_off = orow * ng + (long long)c * sh.bn;
+        t.ldo = ng;
+        t.pad = 0;
+        tiles.push_back(t);
+      });
+    } else {
+      // each site's square block on its own (its columns are its own points)
+      for (size_t i = 0; i < rt.size();) {
+        size_t j = i;
+        while (j < rt.size() && rt[j].site == rt[i].site) ++j;
+        const int s = rt[i].site;
+        const int n = ctx->site_off[s + 1] - ctx->site_off[s];
+        const int slot0 = ctx->site_col_off[s];
+        const int nc = (n + sh.bn - 1) / sh.bn;
+        emit_blocked((int)(j - i), nc, [&](int r, int c) {
+          const RowTile& x = rt[i + r];
+          TileDesc t;
+          t.a_row0 = x.slot_row - bt.rb0 * 16;
+          t.b_col0 = slot0 + c * sh.bn;
+          t.nrows = x.rows;
+          t.ncols = std::min(sh.bn, n - c * sh.bn);
+          t.out_off = site_base[s] - site_base[s0] + (long long)x.m0 * n + (long long)c * sh.bn;
+          t.ldo = n;
+          t.pad = 0;
+          tiles.push_back(t);
+        });
+        i = j;
+      }
+    }
+    bt.ntiles = (int)tiles.size() - bt.tile0;
+  }
   p.ntiles = (int)tiles.size();
   // every tile's operand reads (bm rows of its batch's A, bn columns of B) stay inside the
   // operands; the kernel does not check them
