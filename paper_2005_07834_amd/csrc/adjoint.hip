@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "lrs_internal.h"
+#include "ring.h"
 
 namespace lrs {
 namespace {
@@ -27,9 +28,9 @@ struct BwdTile {
   int r0;              // first local row of this tile
   int ns;              // points of the site
   int k0;              // first K column of this tile
-  long long h_off;     // offset of the site's block in the H arrays
+  long long h_off;     // offset of the site's block in the H arrays (row stride npad)
   int part_row;        // row-tile index for the energy partials
-  int pad;
+  int npad;            // ns rounded up to 16: row stride of the H block, contraction length
 };
 
 struct BwdParams {
@@ -47,83 +48,125 @@ struct BwdParams {
   double* part;          // [nparts][K_pad]
 };
 
-constexpr int BM = 64, BN = 64, BK = 16;
+// Y = H psi for one site: rows p of H (64 per workgroup) x K columns (128 per workgroup),
+// contracted over the site's points r' in chunks of 16, as a complex FP64 GEMM on
+// v_mfma_f64_16x16x4.  The contraction order is free, so lane l of matrix-core step s takes
+// r' = 4 (l/16) + s: its four values of a chunk are then four consecutive r' of one row of H
+// (row-major, stride npad) and of one K's orbital row (planar [K][rows]), and each lane's
+// 32 bytes per plane come straight from those natural layouts as two 16-byte direct-to-LDS
+// loads.  A 16-row (or 16-column) tile of a chunk takes 4 KiB of LDS: [plane][half][lane][16 B],
+// so each fragment read is a conflict-free 16-byte read per lane.  Chunks stream through a
+// two-slot ring (one __shared__ array per slot).
+constexpr int BM = 64, BN = 128, BKC = 16;
+constexpr int BW_WN = 2;                      // waves: 2 (rows) x 2 (columns)
+constexpr int BW_MB = 2, BW_NB = 4;           // 16 x 16 accumulator blocks per wave
+constexpr int BW_AT = BM / 16, BW_BT = BN / 16;
+constexpr int BW_STAGE = (BW_AT + BW_BT) * 4096;
+constexpr int BW_LPW = (BW_AT + BW_BT);       // loads per wave per chunk (one per tile)
 
 __global__ __launch_bounds__(256) void bwd_gemm_kernel(BwdParams P) {
-  __shared__ __attribute__((aligned(16))) unsigned char lds[(BM / 16 + BN / 16) * kTileBytes];
+  __shared__ __attribute__((aligned(1024))) unsigned char slot0[BW_STAGE];
+  __shared__ __attribute__((aligned(1024))) unsigned char slot1[BW_STAGE];
   __shared__ double red[2][BN];
-  unsigned char* la = lds;
-  unsigned char* lb = lds + (BM / 16) * kTileBytes;
   const BwdTile tl = P.tiles[blockIdx.x];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave / BW_WN, wn = wave % BW_WN;
   const bool occ = tl.k0 < P.Ko_pad;
-  const double* hre = (occ ? P.hu_re : P.ho_re) + tl.h_off;
-  const double* him = (occ ? P.hu_im : P.ho_im) + tl.h_off;
   const size_t plane = (size_t)P.K_pad * P.rows_pad;
-  f64x4 cr[2][2], ci[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) {
+  // this wave loads plane (wave / 2), half (wave % 2) of every tile of a chunk
+  const int pl = wave >> 1, hf = wave & 1;
+  const double* hsrc = (pl == 0 ? (occ ? P.hu_re : P.ho_re) : (occ ? P.hu_im : P.ho_im)) + tl.h_off;
+  const int lr = lane & 15, lg = lane >> 4;
+  const double* asrc[BW_AT];
+#pragma unroll
+  for (int t = 0; t < BW_AT; ++t) {
+    // rows past the block read its last row (their results are not stored)
+    const int row = min(tl.r0 + 16 * t + lr, tl.npad - 1);
+    asrc[t] = hsrc + (size_t)row * tl.npad + 4 * lg + 2 * hf;
+  }
+  const double* bsrc[BW_BT];
+#pragma unroll
+  for (int t = 0; t < BW_BT; ++t)
+    bsrc[t] = P.psi + pl * plane + (size_t)(tl.k0 + 16 * t + lr) * P.rows_pad + tl.site_row0 +
+              4 * lg + 2 * hf;
+  const int dofs = pl * 2048 + hf * 1024;
+  auto issue = [&](int c, unsigned char* dst) {
+#pragma unroll
+    for (int t = 0; t < BW_AT; ++t)
+      __builtin_amdgcn_global_load_lds(
+          (const void __attribute__((address_space(1)))*)(asrc[t] + c * BKC),
+          (void __attribute__((address_space(3)))*)(dst + t * 4096 + dofs), 16, 0, 0);
+#pragma unroll
+    for (int t = 0; t < BW_BT; ++t)
+      __builtin_amdgcn_global_load_lds(
+          (const void __attribute__((address_space(1)))*)(bsrc[t] + c * BKC),
+          (void __attribute__((address_space(3)))*)(dst + (BW_AT + t) * 4096 + dofs), 16, 0, 0);
+  };
+  f64x4 cr[BW_MB][BW_NB], ci[BW_MB][BW_NB];
+#pragma unroll
+  for (int i = 0; i < BW_MB; ++i)
+#pragma unroll
+    for (int j = 0; j < BW_NB; ++j) {
       cr[i][j] = f64x4{0, 0, 0, 0};
       ci[i][j] = f64x4{0, 0, 0, 0};
     }
-  for (int kc = 0; kc < tl.ns; kc += BK) {
-    __syncthreads();
-    for (int it = tid; it < BM * BK; it += 256) {
-      const int m = it / BK, kk = it % BK;
-      const int row = tl.r0 + m, k = kc + kk;
-      double ar = 0, ai = 0;
-      if (row < tl.ns && k < tl.ns) {
-        ar = hre[(long long)row * tl.ns + k];
-        ai = him[(long long)row * tl.ns + k];
-      }
-      const int ln = (kk & 3) * 16 + (m & 15), s = kk >> 2;
-      double* dst = (double*)(la + (m >> 4) * kTileBytes);
-      dst[ln * 4 + s] = ar;
-      dst[256 + ln * 4 + s] = ai;
+  // fragments of one chunk: value s of a lane is r' = 4 (lane/16) + s
+  auto mma = [&](const unsigned char* sl) {
+    f64x4 ar[BW_MB], ai[BW_MB], br[BW_NB], bi[BW_NB];
+#pragma unroll
+    for (int i = 0; i < BW_MB; ++i) {
+      const unsigned char* t = sl + (wm * BW_MB + i) * 4096 + lane * 16;
+      const double2 r0 = *(const double2*)(t), r1 = *(const double2*)(t + 1024);
+      const double2 i0 = *(const double2*)(t + 2048), i1 = *(const double2*)(t + 3072);
+      ar[i] = f64x4{r0.x, r0.y, r1.x, r1.y};
+      ai[i] = f64x4{i0.x, i0.y, i1.x, i1.y};
     }
-    for (int it = tid; it < BN * BK; it += 256) {
-      const int n = it / BK, kk = it % BK;
-      const int k = kc + kk;
-      double br = 0, bi = 0;
-      if (k < tl.ns) {
-        const size_t o = (size_t)(tl.k0 + n) * P.rows_pad + tl.site_row0 + k;
-        br = P.psi[o];
-        bi = P.psi[plane + o];
-      }
-      const int ln = (kk & 3) * 16 + (n & 15), s = kk >> 2;
-      double* dst = (double*)(lb + (n >> 4) * kTileBytes);
-      dst[ln * 4 + s] = br;
-      dst[256 + ln * 4 + s] = bi;
+#pragma unroll
+    for (int j = 0; j < BW_NB; ++j) {
+      const unsigned char* t = sl + (BW_AT + wn * BW_NB + j) * 4096 + lane * 16;
+      const double2 r0 = *(const double2*)(t), r1 = *(const double2*)(t + 1024);
+      const double2 i0 = *(const double2*)(t + 2048), i1 = *(const double2*)(t + 3072);
+      br[j] = f64x4{r0.x, r0.y, r1.x, r1.y};
+      bi[j] = f64x4{i0.x, i0.y, i1.x, i1.y};
     }
-    __syncthreads();
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      double ar[2], ai[2], br[2], bi[2];
+    for (int s = 0; s < 4; ++s)
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const double* a = (const double*)(la + (wm * 2 + i) * kTileBytes);
-        ar[i] = a[lane * 4 + s];
-        ai[i] = a[256 + lane * 4 + s];
-        const double* b = (const double*)(lb + (wn * 2 + i) * kTileBytes);
-        br[i] = b[lane * 4 + s];
-        bi[i] = b[256 + lane * 4 + s];
-      }
+      for (int i = 0; i < BW_MB; ++i)
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], cr[i][j], 0, 0, 0);
-          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], bi[j], cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], ci[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], ci[i][j], 0, 0, 0);
+        for (int j = 0; j < BW_NB; ++j) {
+          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i][s], br[j][s], cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i][s], bi[j][s], ci[i][j], 0, 0, 0);
+          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i][s], bi[j][s], cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i][s], br[j][s], ci[i][j], 0, 0, 0);
         }
+  };
+  const int nch = tl.npad / BKC;
+  issue(0, slot0);
+  ring_barrier<0>();
+  for (int c = 0; c < nch; c += 2) {
+    if (c + 1 < nch) issue(c + 1, slot1);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(slot0);
+    __builtin_amdgcn_sched_barrier(0);
+    ring_barrier<0>();            // chunk c+1 landed; slot 0 is free
+    if (c + 1 < nch) {
+      if (c + 2 < nch) issue(c + 2, slot0);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(slot1);
+      __builtin_amdgcn_sched_barrier(0);
+      ring_barrier<0>();
     }
   }
-  // epilogue: f64 accumulator element e of lane holds (row 4e + lane/16, col lane%16)
-  double colsum[2] = {0.0, 0.0};
+  // epilogue: f64 accumulator element e of lane holds (row 4e + lane/16, col lane%16).  Per
+  // accumulator block all loads are issued before the first use (entries outside the site or
+  // in K padding read a valid address and store nothing).
+  double colsum[BW_NB];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int K = tl.k0 + (wn * 2 + j) * 16 + (lane & 15);
+  for (int j = 0; j < BW_NB; ++j) {
+    colsum[j] = 0.0;
+    const int K = tl.k0 + (wn * BW_NB + j) * 16 + (lane & 15);
     int kp = -1, band = 0;
     if (occ && K < P.Ko) {
       kp = K / P.nocc;
@@ -135,32 +178,46 @@ __global__ __launch_bounds__(256) void bwd_gemm_kernel(BwdParams P) {
     }
     const double gw = 2.0 * P.pf * P.ct * P.w[K];
     const double ew = P.pf * P.ct * P.dw[K];
+    const size_t gbase = (size_t)(max(kp, 0) * P.nb + band) * P.nrows;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < BW_MB; ++i) {
+      bool ok[4];
+      size_t gidx[4], o[4];
+      double gre[4], gim[4], pre[4], pim[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int row = tl.r0 + (wm * 2 + i) * 16 + 4 * e + (lane >> 4);
-        if (kp < 0 || row >= tl.ns) continue;
-        const int grow = tl.site_row0 + row;
-        const double yr = cr[i][j][e], yi = ci[i][j][e];
-        double* g = P.grad + 2 * ((size_t)(kp * P.nb + band) * P.nrows + grow);
-        g[0] += gw * yr;
-        g[1] += gw * yi;
-        const size_t o = (size_t)K * P.rows_pad + grow;
-        colsum[j] += ew * (P.psi[o] * yr + P.psi[plane + o] * yi);
+        const int row = tl.r0 + (wm * BW_MB + i) * 16 + 4 * e + (lane >> 4);
+        ok[e] = kp >= 0 && row < tl.ns;
+        const int grow = tl.site_row0 + min(row, tl.ns - 1);
+        gidx[e] = 2 * (gbase + grow);
+        o[e] = (size_t)K * P.rows_pad + grow;
+        gre[e] = P.grad[gidx[e]];
+        gim[e] = P.grad[gidx[e] + 1];
+        pre[e] = P.psi[o[e]];
+        pim[e] = P.psi[plane + o[e]];
       }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double yr = cr[i][j][e], yi = ci[i][j][e];
+        if (ok[e]) {
+          P.grad[gidx[e]] = gre[e] + gw * yr;
+          P.grad[gidx[e] + 1] = gim[e] + gw * yi;
+          colsum[j] += ew * (pre[e] * yr + pim[e] * yi);
+        }
+      }
+    }
   }
   // reduce the energy partials over the tile's rows
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
+  for (int j = 0; j < BW_NB; ++j) {
     double v = colsum[j];
     v += __shfl_xor(v, 16);
     v += __shfl_xor(v, 32);
     colsum[j] = v;
   }
   if (lane < 16) {
-    red[wm][(wn * 2 + 0) * 16 + lane] = colsum[0];
-    red[wm][(wn * 2 + 1) * 16 + lane] = colsum[1];
+#pragma unroll
+    for (int j = 0; j < BW_NB; ++j) red[wm][(wn * BW_NB + j) * 16 + lane] = colsum[j];
   }
   __syncthreads();
   if (tid < BN) {
@@ -169,17 +226,20 @@ __global__ __launch_bounds__(256) void bwd_gemm_kernel(BwdParams P) {
   }
 }
 
-__global__ void symmetrise_kernel(const double* lam, const long long* blk_off, const int* blk_n,
-                                  int nsites, double* out) {
+// lam = (A + A^T) / 2 per site, from the caller's n x n blocks (offsets blk_off) into blocks
+// with row stride npad (offsets pblk_off); the padding rows and columns are zero
+__global__ void symmetrise_kernel(const double* lam, const long long* blk_off,
+                                  const long long* pblk_off, const int* blk_n, int nsites,
+                                  double* out) {
   const int s = blockIdx.y;
   if (s >= nsites) return;
-  const int n = blk_n[s];
+  const int n = blk_n[s], np = (n + 15) / 16 * 16;
   const double* a = lam + blk_off[s];
-  double* o = out + blk_off[s];
-  for (long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x; it < (long long)n * n;
+  double* o = out + pblk_off[s];
+  for (long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x; it < (long long)np * np;
        it += (long long)gridDim.x * blockDim.x) {
-    const int r = (int)(it / n), c = (int)(it % n);
-    o[it] = 0.5 * (a[it] + a[(long long)c * n + r]);
+    const int r = (int)(it / np), c = (int)(it % np);
+    o[it] = (r < n && c < n) ? 0.5 * (a[(long long)r * n + c] + a[(long long)c * n + r]) : 0.0;
   }
 }
 
@@ -236,29 +296,35 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, const double* dL_dchi0, double* dL
                                 (double*)ctx->psi_site_f64.p, st);
   if (e != hipSuccess) return e;
 
-  // site blocks and the GEMM tile list
+  // site blocks (the caller's n x n layout, and the padded one of the H arrays) and the GEMM
+  // tile list
   const int S = ctx->nsites;
-  std::vector<long long> blk_off(S);
+  std::vector<long long> blk_off(S), pblk_off(S);
   std::vector<int> blk_n(S);
   std::vector<BwdTile> tiles;
-  long long tot = 0;
+  long long tot = 0, ptot = 0;
   int nparts = 0;
   for (int s = 0; s < S; ++s) {
     const int n = ctx->site_off[s + 1] - ctx->site_off[s];
+    const int np = site_block_ld(n, 1);
     blk_off[s] = tot;
+    pblk_off[s] = ptot;
     blk_n[s] = n;
     for (int r0 = 0; r0 < n; r0 += BM) {
       for (int k0 = 0; k0 < ctx->K_pad; k0 += BN)
-        tiles.push_back(BwdTile{ctx->site_off[s], r0, n, k0, tot, nparts, 0});
+        tiles.push_back(BwdTile{ctx->site_off[s], r0, n, k0, ptot, nparts, np});
       ++nparts;
     }
     tot += (long long)n * n;
+    ptot += (long long)np * np;
   }
+  if (ctx->K_pad % BN) return hipErrorInvalidValue;
   const int T = ctx->quad.nterms;
   const size_t Kp = ctx->K_pad;
-  // workspace: lam | hu_re | hu_im | ho_re | ho_im | part | w | dw | tiles | blk_off | blk_n
-  size_t bytes = (size_t)5 * tot * 8 + (size_t)nparts * Kp * 8 + 2 * (size_t)T * Kp * 8 +
-                 tiles.size() * sizeof(BwdTile) + S * 8 + S * 4 + 4096;
+  // workspace: lam | hu_re | hu_im | ho_re | ho_im (padded blocks) | part | w | dw | tiles |
+  // blk_off | pblk_off | blk_n
+  size_t bytes = (size_t)5 * ptot * 8 + (size_t)nparts * Kp * 8 + 2 * (size_t)T * Kp * 8 +
+                 tiles.size() * sizeof(BwdTile) + S * 16 + S * 4 + 4096;
   e = ensure(ctx, ctx->adj_work, bytes);
   if (e != hipSuccess) return e;
   char* p = (char*)ctx->adj_work.p;
@@ -267,16 +333,17 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, const double* dL_dchi0, double* dL
     p += (b + 255) / 256 * 256;
     return q;
   };
-  double* lam = (double*)take(tot * 8);
-  double* hu_re = (double*)take(tot * 8);
-  double* hu_im = (double*)take(tot * 8);
-  double* ho_re = (double*)take(tot * 8);
-  double* ho_im = (double*)take(tot * 8);
+  double* lam = (double*)take(ptot * 8);
+  double* hu_re = (double*)take(ptot * 8);
+  double* hu_im = (double*)take(ptot * 8);
+  double* ho_re = (double*)take(ptot * 8);
+  double* ho_im = (double*)take(ptot * 8);
   double* part = (double*)take((size_t)nparts * Kp * 8);
   double* wn = (double*)take((size_t)T * Kp * 8);
   double* dwn = (double*)take((size_t)T * Kp * 8);
   BwdTile* dtiles = (BwdTile*)take(tiles.size() * sizeof(BwdTile));
   long long* dblk_off = (long long*)take(S * 8);
+  long long* dpblk_off = (long long*)take(S * 8);
   int* dblk_n = (int*)take(S * 4);
   if ((size_t)(p - (char*)ctx->adj_work.p) > ctx->adj_work.bytes) return hipErrorOutOfMemory;
 
@@ -284,11 +351,15 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, const double* dL_dchi0, double* dL
       (e = hipMemcpyAsync(dwn, ctx->quad.dw.data(), (size_t)T * Kp * 8, hipMemcpyHostToDevice, st)) ||
       (e = hipMemcpyAsync(dtiles, tiles.data(), tiles.size() * sizeof(BwdTile), hipMemcpyHostToDevice, st)) ||
       (e = hipMemcpyAsync(dblk_off, blk_off.data(), S * 8, hipMemcpyHostToDevice, st)) ||
+      (e = hipMemcpyAsync(dpblk_off, pblk_off.data(), S * 8, hipMemcpyHostToDevice, st)) ||
       (e = hipMemcpyAsync(dblk_n, blk_n.data(), S * 4, hipMemcpyHostToDevice, st)))
     return e;
-  hipLaunchKernelGGL(symmetrise_kernel, dim3(256, S), dim3(256), 0, st, dL_dchi0, dblk_off, dblk_n,
-                     S, lam);
-  if ((e = launch_fill_zero(part, (size_t)nparts * Kp * 8, st)) ||
+  hipLaunchKernelGGL(symmetrise_kernel, dim3(256, S), dim3(256), 0, st, dL_dchi0, dblk_off,
+                     dpblk_off, dblk_n, S, lam);
+  // the adjoint Green's-function launches write the blocks' valid entries only: the padding
+  // of the H arrays must read as zero in the contraction
+  if ((e = launch_fill_zero(hu_re, (size_t)((char*)(ho_im + ptot) - (char*)hu_re), st)) ||
+      (e = launch_fill_zero(part, (size_t)nparts * Kp * 8, st)) ||
       (e = launch_fill_zero(dL_dpsi, (size_t)2 * ctx->nk * ctx->nb * ctx->nrows * 8, st)))
     return e;
 

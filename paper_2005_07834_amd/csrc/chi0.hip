@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 
 #include "lrs_internal.h"
+#include "ring.h"
 
 namespace lrs {
 namespace {
@@ -497,23 +498,6 @@ __device__ __forceinline__ void interleave_rot() {
   if constexpr (REST > 0) __builtin_amdgcn_sched_group_barrier(kMFMA, REST, 0);
   __builtin_amdgcn_sched_group_barrier(kDSREAD, 4, 0);
   sched_cols<NB / 2 - 1, NMFJ>();
-}
-
-// Workgroup barrier of the LDS ring.  __syncthreads() carries a release fence, for which the
-// compiler drains every direct-to-LDS load in flight; here each wave retires exactly what the
-// next step needs instead: its own LDS reads (so a slot may be refilled) and its global->LDS
-// loads up to the last KEEP (loads complete in order, so with only loads in flight this means
-// every load but the last KEEP has landed).  The empty asm statements with a memory clobber
-// keep the compiler from moving memory accesses across the barrier.
-template <int KEEP>
-__device__ __forceinline__ void ring_barrier() {
-  static_assert(KEEP >= 0 && KEEP <= 63, "vector-memory counter range");
-  // s_waitcnt vmcnt(KEEP) expcnt(7) lgkmcnt(0): vmcnt bits [3:0] and [15:14]
-  constexpr int imm = (KEEP & 15) | ((KEEP >> 4) << 14) | (7 << 4);
-  __builtin_amdgcn_s_waitcnt(imm);
-  asm volatile("" ::: "memory");
-  __builtin_amdgcn_s_barrier();
-  asm volatile("" ::: "memory");
 }
 
 // ----------------------------------------------------------------------------- kernel

@@ -332,10 +332,12 @@ lrs_status get_plan(lrs_ctx* ctx, int site, int cols, int prec, int variant, int
               for (int c = c1; c < std::min(C1, c1 + BC); ++c) make(r, c);
       }
   };
-  std::vector<long long> site_base(ctx->nsites + 1, 0);   // site-block output offsets
+  // site-block output offsets; the adjoint mode (1) writes blocks with rows padded to a
+  // multiple of 16 (site_block_ld), the layout its GEMM reads
+  std::vector<long long> site_base(ctx->nsites + 1, 0);
   for (int s = s0; s < s1; ++s) {
-    const long long n = ctx->site_off[s + 1] - ctx->site_off[s];
-    site_base[s + 1] = site_base[s] + n * n;
+    const long long ld = site_block_ld(ctx->site_off[s + 1] - ctx->site_off[s], mode);
+    site_base[s + 1] = site_base[s] + ld * ld;
   }
   for (size_t bi = 0; bi < p.batches.size(); ++bi) {
     Batch& bt = p.batches[bi];
@@ -365,6 +367,7 @@ lrs_status get_plan(lrs_ctx* ctx, int site, int cols, int prec, int variant, int
         const int n = ctx->site_off[s + 1] - ctx->site_off[s];
         const int slot0 = ctx->site_col_off[s];
         const int nc = (n + sh.bn - 1) / sh.bn;
+        const int ld = site_block_ld(n, mode);
         emit_blocked((int)(j - i), nc, [&](int r, int c) {
           const RowTile& x = rt[i + r];
           TileDesc t;
@@ -372,8 +375,8 @@ lrs_status get_plan(lrs_ctx* ctx, int site, int cols, int prec, int variant, int
           t.b_col0 = slot0 + c * sh.bn;
           t.nrows = x.rows;
           t.ncols = std::min(sh.bn, n - c * sh.bn);
-          t.out_off = site_base[s] - site_base[s0] + (long long)x.m0 * n + (long long)c * sh.bn;
-          t.ldo = n;
+          t.out_off = site_base[s] - site_base[s0] + (long long)x.m0 * ld + (long long)c * sh.bn;
+          t.ldo = ld;
           t.pad = 0;
           tiles.push_back(t);
         });

@@ -29,6 +29,9 @@ constexpr int kPhaseAlign = 128;
 constexpr int kMaxTerms = 128;
 
 inline bool is_split(int prec) { return prec == LRS_BF16X2 || prec == LRS_FP16X2; }
+// leading dimension of a site's n x n block: n for chi0 outputs, n rounded up to 16 for the
+// adjoint's internal site blocks (plan mode 1)
+inline int site_block_ld(int n, int mode) { return mode == 1 ? (n + 15) / 16 * 16 : n; }
 // K values per chunk and bytes per fragment tile (16 rows x chunk x planes)
 inline int chunk_of(int prec) { return prec == LRS_FP32 ? 32 : 16; }
 inline int tile_bytes(int prec) { return is_split(prec) ? 2048 : 4096; }
