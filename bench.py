@@ -43,8 +43,10 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def traffic_for(workload, prec, ms_unused=None):
-    """HBM bytes per launch from committed counter runs, if taken on the current kernel."""
+def counters_for(workload, prec):
+    """HBM bytes per launch and MFMA busy fraction from the committed counter runs
+    (profiles/chi0_<prec>_<workload>_traffic.json), only if they were taken on the current
+    kernel, layout and planner sources."""
     path = os.path.join(ROOT, "profiles", f"chi0_{prec}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -52,7 +54,7 @@ def traffic_for(workload, prec, ms_unused=None):
         d = json.load(fh)
     if d.get("kernel_sha") != kernel_source_sha():
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d
 
 
 def copy_calibration(mib):
@@ -204,7 +206,8 @@ def main():
     achieved = entries * flop_per_entry / (kern_ms / 1e3) / 1e12
     peak = PEAKS_TFLOPS[prec]
     exec_factor = 3.0 if prec in ("bf16x2", "fp16x2") else 1.0
-    traffic = traffic_for(w.name + ("_gamma" if args.gamma else ""), prec)
+    ctr = counters_for(w.name + ("_gamma" if args.gamma else ""), prec)
+    traffic = ctr.get("hbm_bytes_per_launch") if ctr else None
 
     # oracle: timed exact pair sum on the baseline block (cpu_baseline), and the sampled
     # entries of the GPU results against the exact sum and against the same quadrature
@@ -261,7 +264,8 @@ def main():
                      "executed_mfma_tflops": achieved * exec_factor,
                      "executed_frac": achieved * exec_factor / peak,
                      "kernel": "chi0_kernel (site x grid)", "kernel_ms": kern_ms,
-                     "flop_per_entry": flop_per_entry},
+                     "flop_per_entry": flop_per_entry,
+                     "mfma_busy": ctr.get("mfma_busy_frac") if ctr else None},
         "cpu_baseline": cpu,
         "chi0_kernel_entries_per_s": entries / (kern_ms / 1e3),
         "fp64_path": fp64,
