@@ -714,7 +714,7 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
 #pragma unroll
         for (int j = 0; j < AN; ++j) {
           const acc_t or_ = *park_at(ln, i, j, 0), oi_ = *park_at(ln, i, j, 1);
-          int off[ELEMS];
+          int off[ELEMS], dg[ELEMS];
           bool in[ELEMS];
 #pragma unroll
           for (int e = 0; e < ELEMS; ++e) {
@@ -724,20 +724,34 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
             const int col = wn * NB * 16 + j * BLK + cc;
             in[e] = row < td.nrows && col < td.ncols;
             off[e] = in[e] ? row * td.ldo + col : 0;
+            dg[e] = col - row - td.pad;   // (site column) - (site row), adjoint mode
           }
           if constexpr (MODE == 1) {
-            // adjoint: Hu = lam * conj(G_u), Ho = lam * conj(G_o) on this tile (single term)
+            // adjoint: Hu = lam * conj(G_u), Ho = lam * conj(G_o) on a site block.  lam is
+            // symmetric and G Hermitian there, so H(c, r) = conj(H(r, c)): the host lists only
+            // tiles that reach the upper triangle, each element on or above the diagonal is
+            // stored with its conjugate at the transposed place, and each place is written
+            // once.
             double l[ELEMS];
 #pragma unroll
             for (int e = 0; e < ELEMS; ++e) l[e] = P.lam[obase + off[e]];
 #pragma unroll
             for (int e = 0; e < ELEMS; ++e)
-              if (in[e]) {
+              if (in[e] && dg[e] >= 0) {
                 const long long o = obase + off[e];
-                P.hu_re[o] = l[e] * (double)gr[i][j][e];
-                P.hu_im[o] = -l[e] * (double)gi[i][j][e];
-                P.ho_re[o] = l[e] * (double)or_[e];
-                P.ho_im[o] = -l[e] * (double)oi_[e];
+                const double hur = l[e] * (double)gr[i][j][e], hui = -l[e] * (double)gi[i][j][e];
+                const double hor = l[e] * (double)or_[e], hoi = -l[e] * (double)oi_[e];
+                P.hu_re[o] = hur;
+                P.hu_im[o] = hui;
+                P.ho_re[o] = hor;
+                P.ho_im[o] = hoi;
+                if (dg[e] > 0) {
+                  const long long ot = o + (long long)dg[e] * (td.ldo - 1);
+                  P.hu_re[ot] = hur;
+                  P.hu_im[ot] = -hui;
+                  P.ho_re[ot] = hor;
+                  P.ho_im[ot] = -hoi;
+                }
               }
           } else {
             // chi accumulates across terms in FP64 in the output itself (this tile's entries

@@ -370,6 +370,9 @@ lrs_status get_plan(lrs_ctx* ctx, int site, int cols, int prec, int variant, int
         const int ld = site_block_ld(n, mode);
         emit_blocked((int)(j - i), nc, [&](int r, int c) {
           const RowTile& x = rt[i + r];
+          // the adjoint mode stores Hermitian blocks from their upper triangle: tiles wholly
+          // below the diagonal are not needed, and pad carries (first row - first column)
+          if (mode == 1 && c * sh.bn + sh.bn - 1 < x.m0) return;
           TileDesc t;
           t.a_row0 = x.slot_row - bt.rb0 * 16;
           t.b_col0 = slot0 + c * sh.bn;
@@ -377,7 +380,7 @@ lrs_status get_plan(lrs_ctx* ctx, int site, int cols, int prec, int variant, int
           t.ncols = std::min(sh.bn, n - c * sh.bn);
           t.out_off = site_base[s] - site_base[s0] + (long long)x.m0 * ld + (long long)c * sh.bn;
           t.ldo = ld;
-          t.pad = 0;
+          t.pad = mode == 1 ? x.m0 - c * sh.bn : 0;
           tiles.push_back(t);
         });
         i = j;

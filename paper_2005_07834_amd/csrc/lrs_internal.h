@@ -45,7 +45,7 @@ struct TileDesc {
   int ncols;            // valid columns
   long long out_off;    // element offset of the tile's (0,0) in the output
   int ldo;              // output leading dimension
-  int pad;
+  int pad;              // adjoint mode: first site row - first site column (else 0)
 };
 static_assert(sizeof(TileDesc) == 32, "TileDesc layout");
 
