@@ -1,0 +1,146 @@
+"""GPU edge cases against the FP64 CPU oracle: minimal band sets, ragged grid and site sizes,
+single-node quadrature, tiny sites in the W solve, and rejected inputs.
+
+Error measure: max |gpu - ref| / max |ref|.  Bars as in the other parity tests: FP64 path vs
+the same quadrature 1e-12, FP32 and FP16X2 1e-5, BF16X2 1e-4.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import chi0 as cz
+from oracle import quadrature as q
+from oracle import screen as sc
+from tests.conftest import workload
+from workloads import crystal as cx
+from workloads import sites as sx
+
+pytestmark = pytest.mark.gpu
+
+BARS = [("fp64", 1e-12), ("fp32", 1e-5), ("bf16x2", 1e-4), ("fp16x2", 1e-5)]
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2005_07834_amd as P
+    return P
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def scale_for(E, nocc, n):
+    mu = q.mid_gap(E, nocc)
+    x, y = q.offsets(E, nocc, mu)
+    return q.auto_scale(x, y, n)
+
+
+def check_all_precisions(P, ctx, npts, ref_grid, ref_site, label):
+    for prec, tol in BARS:
+        g = ctx.chi0(-1, P.COLS_GRID, prec).cpu().numpy()
+        s = ctx.chi0(-1, P.COLS_SITE, prec).cpu().numpy()
+        o, es = 0, 0.0
+        for k, n in enumerate(npts):
+            es = max(es, rel(s[o:o + n * n].reshape(n, n), ref_site[k]))
+            o += n * n
+        eg = rel(g, ref_grid)
+        say(f"  {label} {prec}: grid {eg:.2e} site {es:.2e}")
+        assert eg < tol and es < tol
+
+
+@pytest.mark.parametrize("nb,nocc", [(2, 1), (9, 1), (128, 127)])
+def test_minimal_band_sets(P, nb, nocc):
+    """One unoccupied or one occupied band (K phases of a single pair per k), on a ragged
+    column count (3001 grid points)."""
+    w = workload("tiny", nb=nb, nocc=nocc)
+    n = 16
+    s = scale_for(w.energies, nocc, n)
+    ng = 3001
+    pg = w.psi_grid[:, :, :ng].contiguous()
+    ps = w.psi_site.numpy()
+    terms = cz.terms_for(w.energies, nocc, "time", n, s)
+    ref_g = cz.chi0_quad(ps, pg.numpy(), nocc, 2, *terms)
+    ref_s = cz.chi0_quad(ps, ps, nocc, 2, *terms)
+    ctx = P.Context(0)
+    ctx.set_orbitals(w.energies, nocc, pg, w.grid_dV)
+    ctx.set_sites(w.sites, w.psi_site)
+    ctx.make_quadrature(P.QUAD_TIME, n, s)
+    check_all_precisions(P, ctx, [w.nrows], ref_g, [ref_s], f"nb={nb} nocc={nocc}")
+    ctx.close()
+
+
+def test_small_sites_ragged_grids_few_terms(P):
+    """Sites of 26, 150 and 208 points (a single 26-point shell included) in one call; grid
+    column counts 1, 17 and 129; 1 and 3 imaginary-time terms; W of every site."""
+    w = workload("tiny")
+    c0 = w.sites[0].centre
+    sites = [sx.make_site(c0 + 0.3, 1, 26, r_max=1.0),
+             sx.make_site(c0 - 0.2, 3, 50, r_max=2.0),
+             w.sites[0]]
+    pts = np.concatenate([x.points() for x in sites])
+    psi_site = torch.stack([cx.psi_at_points(w.bands, pts, k) for k in range(w.nk)])
+    ps = psi_site.numpy()
+    npts = [x.npts for x in sites]
+    offs = np.cumsum([0] + npts)
+    for nterms in (1, 3):
+        s = scale_for(w.energies, w.nocc, nterms)
+        terms = cz.terms_for(w.energies, w.nocc, "time", nterms, s)
+        ref_s = [cz.chi0_quad(ps[:, :, offs[k]:offs[k + 1]], ps[:, :, offs[k]:offs[k + 1]],
+                              w.nocc, 2, *terms) for k in range(len(sites))]
+        for ng in (1, 17, 129):
+            pg = w.psi_grid[:, :, :ng].contiguous()
+            ref_g = cz.chi0_quad(ps, pg.numpy(), w.nocc, 2, *terms)
+            ctx = P.Context(0)
+            ctx.set_orbitals(w.energies, w.nocc, pg, w.grid_dV)
+            ctx.set_sites(sites, psi_site)
+            ctx.make_quadrature(P.QUAD_TIME, nterms, s)
+            check_all_precisions(P, ctx, npts, ref_g, ref_s, f"terms={nterms} ngrid={ng}")
+            if ng == 17:
+                chi = ctx.chi0(-1, P.COLS_SITE, P.FP64)
+                W, _ = ctx.screen_W(chi)
+                for k, Wk in enumerate(ctx.W_blocks(W)):
+                    eW = rel(Wk.cpu().numpy(), sc.screen_W(ref_s[k], sites[k]))
+                    say(f"  terms={nterms} W site {k} ({npts[k]} points): {eW:.2e}")
+                    assert eW < 1e-11
+            ctx.close()
+
+
+def test_rejected_inputs(P):
+    """Invalid band sets, a closed gap, bad node counts and calls out of order are refused
+    with their status and leave the context usable."""
+    w = workload("tiny")
+    ctx = P.Context(0)
+    buf = torch.empty(16, dtype=torch.float64, device="cuda")
+    assert P.lib.lrs_compute_chi0(ctx.h, -1, P.COLS_SITE, P.FP64, buf.data_ptr()) == P.LRS_ESTATE
+    for nocc in (0, w.nb):
+        with pytest.raises(P.LrsError) as e:
+            ctx.set_orbitals(w.energies, nocc, w.psi_grid, w.grid_dV)
+        assert e.value.status == P.LRS_EINVAL
+    E = w.energies.copy()
+    E[0, w.nocc] = E[0, w.nocc - 1] - 0.01          # an unoccupied band below the top occupied
+    with pytest.raises(P.LrsError) as e:
+        ctx.set_orbitals(E, w.nocc, w.psi_grid, w.grid_dV)
+    assert e.value.status == P.LRS_ENOGAP
+    ctx.set_orbitals(w.energies, w.nocc, w.psi_grid, w.grid_dV)
+    ctx.set_sites(w.sites, w.psi_site)
+    for nn in (0, 65):
+        with pytest.raises(P.LrsError) as e:
+            ctx.make_quadrature(P.QUAD_TIME, nn, 0.0)
+        assert e.value.status == P.LRS_EINVAL
+    ctx.make_quadrature(P.QUAD_TIME, 16, 0.0)
+    got = ctx.chi0(-1, P.COLS_SITE, P.FP64)
+    assert torch.isfinite(got).all()
+    say("  rejected inputs: statuses as documented, context still usable")
+    ctx.close()
