@@ -306,3 +306,49 @@ def test_tune_and_determinism(P):
         say(f"  {prec}: repeat equal, tuned vs default rel diff {d:.2e}")
         assert d < (1e-6 if prec == "bf16x2" else 1e-13)
     ctx.close()
+
+
+def test_single_site_calls_match_all_sites(P):
+    """chi0 for one site (site >= 0) equals that site's rows of the all-sites call (grid
+    columns) and its block of the site-block layout, bit for bit."""
+    w = workload("production")
+    n = w.n_terms
+    s = oracle_scale(w, n)
+    ctx = make_ctx(P, w, n, s)
+    offs = w.site_offsets
+    for prec in ["bf16x2", "fp64"]:
+        allg = ctx.chi0(-1, P.COLS_GRID, prec)
+        alls = ctx.site_blocks(ctx.chi0(-1, P.COLS_SITE, prec))
+        for k in range(len(w.sites)):
+            g = ctx.chi0(k, P.COLS_GRID, prec)
+            b = ctx.chi0(k, P.COLS_SITE, prec).view(w.sites[k].npts, w.sites[k].npts)
+            assert torch.equal(g, allg[offs[k]:offs[k + 1]])
+            assert torch.equal(b, alls[k])
+        say(f"  {prec}: single-site calls equal the all-sites call")
+    ctx.close()
+
+
+def test_size_limits_refused(P):
+    """Inputs beyond the documented limits are refused on the host before any launch."""
+    import ctypes as C
+    w = workload("tiny")
+    ctx = P.Context(0)
+    ctx.set_orbitals(w.energies, w.nocc, w.psi_grid, w.grid_dV)
+    psi = w.psi_site.to("cuda")
+    one = np.ones(8, dtype=np.float64)
+    xyz = np.zeros((8, 3), dtype=np.float64)
+    for nrad, nang in [(4097, 1), (1, 4097), (0, 26)]:
+        st = P.lib.lrs_set_sites(ctx.h, 1, np.array([nrad], np.int32).ctypes.data_as(C.c_void_p),
+                                 np.array([nang], np.int32).ctypes.data_as(C.c_void_p),
+                                 one.ctypes.data_as(C.c_void_p), one.ctypes.data_as(C.c_void_p),
+                                 xyz.ctypes.data_as(C.c_void_p), one.ctypes.data_as(C.c_void_p),
+                                 C.c_void_p(psi.data_ptr()), 2)
+        assert st == P.LRS_EINVAL, (nrad, nang, st)
+    st = P.lib.lrs_set_sites(ctx.h, 1, np.array([8], np.int32).ctypes.data_as(C.c_void_p),
+                             np.array([26], np.int32).ctypes.data_as(C.c_void_p),
+                             one.ctypes.data_as(C.c_void_p), one.ctypes.data_as(C.c_void_p),
+                             xyz.ctypes.data_as(C.c_void_p), one.ctypes.data_as(C.c_void_p),
+                             C.c_void_p(psi.data_ptr()), 3)
+    assert st == P.LRS_EINVAL                     # lmax above 2
+    say("  size limits refused")
+    ctx.close()
