@@ -780,7 +780,9 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
 
 // variant table: {WMW, WNW, MB, NB, S, IL, ROT}; S = LDS ring slots, IL = 1 interleaves the LDS
 // reads and loads with the matrix-core instructions, ROT = 1 rotates the B fragments (split
-// paths; allows the 64 x 128 and 128 x 64 wave tiles)
+// paths; allows the 128 x 64 wave tile).  Split paths: 128 x 128 workgroup tiles with four
+// slots (default), 128 x 256 with two slots, 128 x 256 from 128 x 64 wave tiles, and
+// 128 x 192 (four 40 KiB slots fill the 160 KiB of LDS).
 template <int PREC, int V>
 struct Variant;
 #define LRS_VARIANT(PR, V, A, B, C, D, E, F, G)                         \
@@ -797,13 +799,13 @@ LRS_VARIANT(LRS_FP32, 1, 2, 2, 2, 4, 2, 1, 0)
 LRS_VARIANT(LRS_FP32, 2, 2, 2, 2, 4, 2, 0, 0)
 LRS_VARIANT(LRS_FP32, 3, 2, 2, 2, 2, 4, 0, 0)
 LRS_VARIANT(LRS_BF16X2, 0, 2, 2, 4, 4, 4, 1, 0)
-LRS_VARIANT(LRS_BF16X2, 1, 2, 2, 4, 8, 2, 1, 1)
+LRS_VARIANT(LRS_BF16X2, 1, 2, 2, 4, 8, 2, 1, 0)
 LRS_VARIANT(LRS_BF16X2, 2, 1, 4, 8, 4, 2, 1, 1)
-LRS_VARIANT(LRS_BF16X2, 3, 2, 2, 4, 4, 4, 0, 0)
+LRS_VARIANT(LRS_BF16X2, 3, 2, 2, 4, 6, 4, 1, 0)
 LRS_VARIANT(LRS_FP16X2, 0, 2, 2, 4, 4, 4, 1, 0)
-LRS_VARIANT(LRS_FP16X2, 1, 2, 2, 4, 8, 2, 1, 1)
+LRS_VARIANT(LRS_FP16X2, 1, 2, 2, 4, 8, 2, 1, 0)
 LRS_VARIANT(LRS_FP16X2, 2, 1, 4, 8, 4, 2, 1, 1)
-LRS_VARIANT(LRS_FP16X2, 3, 2, 2, 4, 4, 4, 0, 0)
+LRS_VARIANT(LRS_FP16X2, 3, 2, 2, 4, 6, 4, 1, 0)
 #undef LRS_VARIANT
 constexpr int kNumVariants = 4;
 
