@@ -112,53 +112,74 @@ __global__ __launch_bounds__(256) void bwd_gemm_kernel(BwdParams P) {
       ci[i][j] = f64x4{0, 0, 0, 0};
     }
   // fragments of one chunk: value s of a lane is r' = 4 (lane/16) + s
-  auto mma = [&](const unsigned char* sl) {
+  struct Frag {
     f64x4 ar[BW_MB], ai[BW_MB], br[BW_NB], bi[BW_NB];
+  };
+  auto load = [&](const unsigned char* sl, Frag& f) {
 #pragma unroll
     for (int i = 0; i < BW_MB; ++i) {
       const unsigned char* t = sl + (wm * BW_MB + i) * 4096 + lane * 16;
       const double2 r0 = *(const double2*)(t), r1 = *(const double2*)(t + 1024);
       const double2 i0 = *(const double2*)(t + 2048), i1 = *(const double2*)(t + 3072);
-      ar[i] = f64x4{r0.x, r0.y, r1.x, r1.y};
-      ai[i] = f64x4{i0.x, i0.y, i1.x, i1.y};
+      f.ar[i] = f64x4{r0.x, r0.y, r1.x, r1.y};
+      f.ai[i] = f64x4{i0.x, i0.y, i1.x, i1.y};
     }
 #pragma unroll
     for (int j = 0; j < BW_NB; ++j) {
       const unsigned char* t = sl + (BW_AT + wn * BW_NB + j) * 4096 + lane * 16;
       const double2 r0 = *(const double2*)(t), r1 = *(const double2*)(t + 1024);
       const double2 i0 = *(const double2*)(t + 2048), i1 = *(const double2*)(t + 3072);
-      br[j] = f64x4{r0.x, r0.y, r1.x, r1.y};
-      bi[j] = f64x4{i0.x, i0.y, i1.x, i1.y};
+      f.br[j] = f64x4{r0.x, r0.y, r1.x, r1.y};
+      f.bi[j] = f64x4{i0.x, i0.y, i1.x, i1.y};
     }
+  };
+  auto mma = [&](const Frag& f) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int i = 0; i < BW_MB; ++i)
 #pragma unroll
         for (int j = 0; j < BW_NB; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i][s], br[j][s], cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i][s], bi[j][s], ci[i][j], 0, 0, 0);
-          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i][s], bi[j][s], cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i][s], br[j][s], ci[i][j], 0, 0, 0);
+          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.ar[i][s], f.br[j][s], cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.ar[i][s], f.bi[j][s], ci[i][j], 0, 0, 0);
+          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-f.ai[i][s], f.bi[j][s], cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.ai[i][s], f.br[j][s], ci[i][j], 0, 0, 0);
         }
   };
+  // Chunk c sits in slot c % 2 with its fragments in register set c % 2.  Per step: barrier
+  // (chunk c+1 landed, chunk c's slot read out), read chunk c+1's fragments, load chunk c+2
+  // into chunk c's slot, matrix-core instructions of chunk c, with the reads and loads
+  // interleaved between them.  Loads past the last chunk repeat it, so every step is one
+  // basic block; an odd chunk count ends with the last chunk's instructions alone.
+  constexpr int kMFMA = 0x008, kVMEM = 0x010, kDSREAD = 0x100;
+  constexpr int NMF = 16 * BW_MB * BW_NB, NDS = 4 * (BW_MB + BW_NB), NVM = BW_LPW;
+  constexpr int R = (NMF - NDS) / (NVM + 1), REST = NMF - NDS - R * NVM;
+  auto sched = [] {
+    sched_pairs<NDS, kMFMA, 1, kDSREAD, 1>();
+    sched_pairs<NVM, kMFMA, R, kVMEM, 1>();
+    __builtin_amdgcn_sched_group_barrier(kMFMA, REST, 0);
+  };
   const int nch = tl.npad / BKC;
+  Frag fa, fb;
   issue(0, slot0);
+  issue(min(1, nch - 1), slot1);
   ring_barrier<0>();
-  for (int c = 0; c < nch; c += 2) {
-    if (c + 1 < nch) issue(c + 1, slot1);
-    __builtin_amdgcn_sched_barrier(0);
-    mma(slot0);
-    __builtin_amdgcn_sched_barrier(0);
-    ring_barrier<0>();            // chunk c+1 landed; slot 0 is free
-    if (c + 1 < nch) {
-      if (c + 2 < nch) issue(c + 2, slot0);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(slot1);
-      __builtin_amdgcn_sched_barrier(0);
-      ring_barrier<0>();
-    }
+  load(slot0, fa);
+  int c = 0;
+  for (; c + 2 <= nch; c += 2) {
+    ring_barrier<0>();
+    load(slot1, fb);
+    issue(min(c + 2, nch - 1), slot0);
+    mma(fa);
+    sched();
+    ring_barrier<0>();
+    load(slot0, fa);
+    issue(min(c + 3, nch - 1), slot1);
+    mma(fb);
+    sched();
   }
+  if (c < nch) mma(fa);
+  ring_barrier<0>();
   // epilogue: f64 accumulator element e of lane holds (row 4e + lane/16, col lane%16).  Per
   // accumulator block all loads are issued before the first use (entries outside the site or
   // in K padding read a valid address and store nothing).

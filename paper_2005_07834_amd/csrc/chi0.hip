@@ -454,14 +454,6 @@ __device__ __forceinline__ void mma_col_split(const FragsA<PREC, MB>& a, const F
 
 // Scheduling groups for one pipeline step: the next chunk's LDS reads, one per matrix-core
 // instruction, then the global->LDS loads spread over the following ones, then the rest.
-template <int N, int M1, int S1, int M2, int S2>
-__device__ __forceinline__ void sched_pairs() {
-  if constexpr (N > 0) {
-    __builtin_amdgcn_sched_group_barrier(M1, S1, 0);
-    __builtin_amdgcn_sched_group_barrier(M2, S2, 0);
-    sched_pairs<N - 1, M1, S1, M2, S2>();
-  }
-}
 template <int PREC, int MB, int NB, int NVM>
 __device__ __forceinline__ void interleave() {
   constexpr int kMFMA = 0x008, kVMEM = 0x010, kDSREAD = 0x100;

@@ -22,4 +22,16 @@ __device__ __forceinline__ void ring_barrier() {
   asm volatile("" ::: "memory");
 }
 
+// Pairs of scheduling groups, N times: S1 instructions of class M1, then S2 of class M2
+// (classes as in __builtin_amdgcn_sched_group_barrier: 0x008 matrix core, 0x010 vector
+// memory, 0x100 LDS read).
+template <int N, int M1, int S1, int M2, int S2>
+__device__ __forceinline__ void sched_pairs() {
+  if constexpr (N > 0) {
+    __builtin_amdgcn_sched_group_barrier(M1, S1, 0);
+    __builtin_amdgcn_sched_group_barrier(M2, S2, 0);
+    sched_pairs<N - 1, M1, S1, M2, S2>();
+  }
+}
+
 }  // namespace lrs
