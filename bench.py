@@ -84,6 +84,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-prec", default="auto", choices=["auto", "fp64", "bf16x2"],
+                    help="precision of the adjoint's products (auto: bf16x2 with --prec bf16x2, "
+                         "else fp64)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
@@ -148,6 +151,9 @@ def main():
     rho = torch.as_tensor(w.rho_test, device=dev)
     out_grid = torch.empty((nrows, ncols), dtype=torch.float64, device=dev)
     prec = args.prec
+    adj_prec = args.adjoint_prec
+    if adj_prec == "auto":
+        adj_prec = "bf16x2" if prec == "bf16x2" else "fp64"
 
     comp = {}
 
@@ -161,11 +167,13 @@ def main():
         if not args.no_adjoint:
             lam = ctx.screen_W_backward()
             ctx.make_quadrature(P.QUAD_TIME, w.n_terms, 0.0)
-            dE, dpsi = ctx.chi0_backward(lam)
+            dE, dpsi = ctx.chi0_backward(lam, adj_prec)
         torch.cuda.synchronize()
         if record:
             comp.setdefault("kernel_ms", []).append(kms)
             comp.setdefault("step_ms", []).append((time.time() - tq) * 1e3)
+            if not args.no_adjoint:
+                comp["adjoint"] = (lam, dE, dpsi)
         return loss
 
     for _ in range(args.warmup):
@@ -194,6 +202,19 @@ def main():
         log(f"fp64 chi0 kernel {ms64:.1f} ms")
     else:
         got64 = got_low if prec == "fp64" else None
+    # the split adjoint against the FP64 adjoint on the last step's dL/dchi0
+    adjoint = None
+    if not args.no_adjoint:
+        adjoint = {"precision": adj_prec}
+        if adj_prec != "fp64" and not args.no_fp64:
+            lam, dE, dpsi = comp.pop("adjoint")
+            ctx.make_quadrature(P.QUAD_TIME, w.n_terms, 0.0)
+            dE64, dpsi64 = ctx.chi0_backward(lam, "fp64")
+            adjoint["dE_rel_vs_fp64"] = float((dE - dE64).abs().max() / dE64.abs().max())
+            adjoint["dpsi_rel_vs_fp64"] = float((dpsi - dpsi64).abs().max() / dpsi64.abs().max())
+            del dE64, dpsi64
+            log("adjoint", adjoint)
+        comp.pop("adjoint", None)
     qd = ctx.get_quadrature()
     ctx.close()
     del out_grid
@@ -258,7 +279,8 @@ def main():
                    "rows": nrows, "grid_columns": ncols, "kpoints": nk, "bands": nb,
                    "occupied": w.nocc, "terms": w.n_terms,
                    "step": "quadrature + chi0 site x grid + chi0 site x site + W + loss + "
-                           + ("adjoints" if not args.no_adjoint else "no adjoint")},
+                           + (f"adjoints ({adj_prec} products)" if not args.no_adjoint
+                              else "no adjoint")},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "executed_mfma_tflops": achieved * exec_factor,
@@ -271,6 +293,7 @@ def main():
         "fp64_path": fp64,
         "speedup_vs_fp64": (fp64["kernel_ms"] / kern_ms) if fp64 else None,
         "rel_err": errs,
+        "adjoint": adjoint,
         "pack_ms": pack_ms,
         "loss": float(loss.sum().item()),
     }

@@ -180,12 +180,15 @@ lrs_status lrs_screen_W(lrs_ctx* ctx, const double* chi0_sitesite, double* W_out
  * dL_dchi0_sitesite (site-block layout) = P^T (D W^T Gbar W^T D) P per site.  Asynchronous. */
 lrs_status lrs_screen_W_backward(lrs_ctx* ctx, const double* dL_dW, double* dL_dchi0_sitesite);
 
-/* Adjoint of lrs_compute_chi0 for site x site blocks (cols must be LRS_COLS_SITE, all sites,
- * LRS_FP64): given dL/dchi0 (site-block layout) writes dL_dE float64 [nk][nb] and
+/* Adjoint of lrs_compute_chi0 for site x site blocks (cols must be LRS_COLS_SITE, all sites):
+ * given dL/dchi0 (site-block layout) writes dL_dE float64 [nk][nb] and
  * dL_dpsi_site complex128 [nk][nb][sum npts] (complex gradients as dL/dRe + i dL/dIm).
- * Each term's G_o, G_u are recomputed rather than stored.  Requires terms from
- * lrs_make_quadrature.  dL_dpsi_grid must be NULL (site blocks do not use grid orbitals). */
-lrs_status lrs_compute_chi0_backward(lrs_ctx* ctx, int cols, const double* dL_dchi0,
+ * Each term's G_o, G_u are recomputed rather than stored.  prec LRS_FP64 runs every product
+ * in FP64; LRS_BF16X2 recomputes G and forms the products with psi in split bfloat16 (hi + lo,
+ * FP32 accumulation; relative error of order 1e-5), with the gradient accumulation in FP64.
+ * Other precisions: LRS_EUNSUPPORTED.  Requires terms from lrs_make_quadrature.
+ * dL_dpsi_grid must be NULL (site blocks do not use grid orbitals).  Synchronous. */
+lrs_status lrs_compute_chi0_backward(lrs_ctx* ctx, int cols, int prec, const double* dL_dchi0,
                                      double* dL_dE, void* dL_dpsi_site, void* dL_dpsi_grid);
 
 /* Times the candidate tile configurations of precision prec on the current problem and keeps

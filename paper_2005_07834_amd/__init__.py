@@ -44,7 +44,7 @@ SIGNATURES = [
     ("lrs_compute_chi0", _I, [_P, _I, _I, _I, _P]),
     ("lrs_screen_W", _I, [_P, _P, _P, _P, _P]),
     ("lrs_screen_W_backward", _I, [_P, _P, _P]),
-    ("lrs_compute_chi0_backward", _I, [_P, _I, _P, _P, _P, _P]),
+    ("lrs_compute_chi0_backward", _I, [_P, _I, _I, _P, _P, _P, _P]),
     ("lrs_tune", _I, [_P, _I]),
     ("lrs_last_kernel_ms", _D, [_P]),
 ]
@@ -227,12 +227,15 @@ class Context:
         self._check(lib.lrs_screen_W_backward(self.h, _ptr(d), _ptr(g)))
         return g
 
-    def chi0_backward(self, dL_dchi0_ss):
+    def chi0_backward(self, dL_dchi0_ss, prec=FP64):
+        if isinstance(prec, str):
+            prec = PREC_NAMES[prec]
         dE = torch.empty((self.nk, self.nb), dtype=torch.float64, device=self.device)
         dpsi = torch.empty((self.nk, self.nb, sum(self.npts)), dtype=torch.complex128,
                            device=self.device)
-        self._check(lib.lrs_compute_chi0_backward(self.h, COLS_SITE, _ptr(dL_dchi0_ss.contiguous()),
-                                                  _ptr(dE), _ptr(dpsi), None))
+        self._check(lib.lrs_compute_chi0_backward(self.h, COLS_SITE, prec,
+                                                  _ptr(dL_dchi0_ss.contiguous()), _ptr(dE),
+                                                  _ptr(dpsi), None))
         return dE, dpsi
 
     def tune(self, prec):

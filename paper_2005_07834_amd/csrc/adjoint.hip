@@ -13,6 +13,7 @@
 // reproducible.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "lrs_internal.h"
@@ -30,7 +31,8 @@ struct BwdTile {
   int k0;              // first K column of this tile
   long long h_off;     // offset of the site's block in the H arrays (row stride npad)
   int part_row;        // row-tile index for the energy partials
-  int npad;            // ns rounded up to 16: row stride of the H block, contraction length
+  int npad;            // ns rounded up to 64: row stride of the H block, contraction length
+  int srow0;           // split GEMM: first row of the site in the split psi planes
 };
 
 struct BwdParams {
@@ -46,6 +48,13 @@ struct BwdParams {
   const BwdTile* tiles;
   double* grad;          // complex128 [nk][nb][nrows]
   double* part;          // [nparts][K_pad]
+  // split GEMM only
+  const __bf16* hs_u;    // Hu, Ho: four planes (re hi, re lo, im hi, im lo), blocks as above
+  const __bf16* hs_o;
+  long long hs_plane;
+  const __bf16* psis;    // four planes of psi, each [K_pad][srows], sites in 64-row slots
+  int srows;
+  int ntiles, per;       // tiles, and tiles per eighth of the grid
 };
 
 // Y = H psi for one site: rows p of H (64 per workgroup) x K columns (128 per workgroup),
@@ -247,6 +256,239 @@ __global__ __launch_bounds__(256) void bwd_gemm_kernel(BwdParams P) {
   }
 }
 
+// The same product in split precision: Y = H psi with H = H_hi + H_lo and psi = psi_hi +
+// psi_lo in bfloat16, each real product taken as hi*hi + hi*lo + lo*hi on
+// v_mfma_f32_32x32x16_bf16 with FP32 accumulation.  Lane l of an instruction holds row (or
+// column) l%32 and r' = 8 (l/32) + e, e = 0..7: sixteen consecutive bytes of one row of an H
+// plane (row stride npad) and of one K row of a psi plane, so every operand again comes from
+// its natural layout by 16-byte direct-to-LDS loads.  A 32-row block of one plane and one
+// chunk of 16 r' is 1 KiB of LDS ([lane][16 B]): conflict-free 16-byte fragment reads.
+// 128 x 128 workgroup tiles (2 x 2 waves of 64 x 64), a four-slot ring, and the epilogue of
+// the FP64 GEMM with Y converted to FP64.  Workgroup b takes tile (b % 8) * per + b / 8, so
+// the workgroups resident on one XCD run a contiguous stretch of the tile list, which the host
+// orders in blocks of 4 row tiles x 8 column tiles.
+constexpr int SM = 128, SN = 128;
+constexpr int S_AB = SM / 32, S_BB = SN / 32;     // 32-row (column) blocks per tile
+constexpr int S_PIECES = (S_AB + S_BB) * 4;       // 1 KiB pieces per chunk: blocks x 4 planes
+constexpr int S_STAGE = S_PIECES * 1024;
+constexpr int S_LPW = S_PIECES / 4;               // loads per wave per chunk
+constexpr int S_KEEP = 2 * S_LPW;                 // loads of chunks q+2, q+3 in flight at step q
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+typedef __attribute__((__vector_size__(4 * sizeof(unsigned int)))) unsigned int u32x4;
+
+__global__ __launch_bounds__(256) void bwd_split_kernel(BwdParams P) {
+  __shared__ __attribute__((aligned(1024))) unsigned char s0[S_STAGE];
+  __shared__ __attribute__((aligned(1024))) unsigned char s1[S_STAGE];
+  __shared__ __attribute__((aligned(1024))) unsigned char s2[S_STAGE];
+  __shared__ __attribute__((aligned(1024))) unsigned char s3[S_STAGE];
+  __shared__ double red[2][SN];
+  const int ti = (blockIdx.x & 7) * P.per + (blockIdx.x >> 3);
+  if (ti >= P.ntiles) return;
+  const BwdTile tl = P.tiles[ti];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave >> 1, wn = wave & 1;
+  const bool occ = tl.k0 < P.Ko_pad;
+  // wave w loads plane w of every block of a chunk: piece j = 4 t + w of the A blocks, then of
+  // the B blocks
+  const int lr = lane & 31, lh = lane >> 5;
+  const __bf16* hsrc = (occ ? P.hs_u : P.hs_o) + wave * P.hs_plane + tl.h_off;
+  const __bf16* asrc[S_AB];
+#pragma unroll
+  for (int t = 0; t < S_AB; ++t) {
+    // rows past the block read its last row (their results are not stored)
+    const int row = min(tl.r0 + 32 * t + lr, tl.npad - 1);
+    asrc[t] = hsrc + (size_t)row * tl.npad + 8 * lh;
+  }
+  const size_t plane = (size_t)P.K_pad * P.rows_pad;
+  const __bf16* bsrc[S_BB];
+#pragma unroll
+  for (int t = 0; t < S_BB; ++t)
+    bsrc[t] = P.psis + (size_t)wave * P.K_pad * P.srows + (size_t)(tl.k0 + 32 * t + lr) * P.srows +
+              tl.srow0 + 8 * lh;
+  const int nch = tl.npad / 16;   // a multiple of 4
+  auto issue = [&](int c, unsigned char* dst) {
+    c = min(c, nch - 1);          // past the end: the last chunk again, never read
+#pragma unroll
+    for (int t = 0; t < S_AB; ++t)
+      __builtin_amdgcn_global_load_lds(
+          (const void __attribute__((address_space(1)))*)(asrc[t] + c * 16),
+          (void __attribute__((address_space(3)))*)(dst + (4 * t + wave) * 1024), 16, 0, 0);
+#pragma unroll
+    for (int t = 0; t < S_BB; ++t)
+      __builtin_amdgcn_global_load_lds(
+          (const void __attribute__((address_space(1)))*)(bsrc[t] + c * 16),
+          (void __attribute__((address_space(3)))*)(dst + (4 * (S_AB + t) + wave) * 1024), 16, 0,
+          0);
+  };
+  struct Frag {
+    bf16x8 a[2][4], b[2][4];   // [block][plane]
+  };
+  auto load = [&](const unsigned char* sl, Frag& f) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        f.a[i][p] = *(const bf16x8*)(sl + (4 * (2 * wm + i) + p) * 1024 + lane * 16);
+        f.b[i][p] = *(const bf16x8*)(sl + (4 * (S_AB + 2 * wn + i) + p) * 1024 + lane * 16);
+      }
+  };
+  f32x16 yr[2][2], yi[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        yr[i][j][e] = 0.f;
+        yi[i][j][e] = 0.f;
+      }
+  // Yr += Hr psi_r - Hi psi_i, Yi += Hr psi_i + Hi psi_r (planes 0, 1 = re hi, lo; 2, 3 = im)
+  auto mma = [&](const Frag& f) {
+    const u32x4 m = {0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+    auto mf = [](bf16x8 a, bf16x8 b, f32x16 c) {
+      return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    };
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const bf16x8 nih = (bf16x8)((u32x4)f.a[i][2] ^ m), nil = (bf16x8)((u32x4)f.a[i][3] ^ m);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        yr[i][j] = mf(f.a[i][0], f.b[j][0], yr[i][j]);
+        yi[i][j] = mf(f.a[i][0], f.b[j][2], yi[i][j]);
+        yr[i][j] = mf(f.a[i][0], f.b[j][1], yr[i][j]);
+        yi[i][j] = mf(f.a[i][0], f.b[j][3], yi[i][j]);
+        yr[i][j] = mf(f.a[i][1], f.b[j][0], yr[i][j]);
+        yi[i][j] = mf(f.a[i][1], f.b[j][2], yi[i][j]);
+        yr[i][j] = mf(nih, f.b[j][2], yr[i][j]);
+        yi[i][j] = mf(f.a[i][2], f.b[j][0], yi[i][j]);
+        yr[i][j] = mf(nih, f.b[j][3], yr[i][j]);
+        yi[i][j] = mf(f.a[i][2], f.b[j][1], yi[i][j]);
+        yr[i][j] = mf(nil, f.b[j][2], yr[i][j]);
+        yi[i][j] = mf(f.a[i][3], f.b[j][0], yi[i][j]);
+      }
+    }
+  };
+  constexpr int kMFMA = 0x008, kVMEM = 0x010, kDSREAD = 0x100;
+  constexpr int NMF = 48, NDS = 16, NVM = S_LPW;
+  constexpr int R = (NMF - NDS) / (NVM + 1), REST = NMF - NDS - R * NVM;
+  auto sched = [] {
+    sched_pairs<NDS, kMFMA, 1, kDSREAD, 1>();
+    sched_pairs<NVM, kMFMA, R, kVMEM, 1>();
+    __builtin_amdgcn_sched_group_barrier(kMFMA, REST, 0);
+  };
+  // step q: chunk q+1 has landed (the loads of q+2 and q+3 may be in flight) and every wave
+  // has read chunk q's slot out; read chunk q+1's fragments, load chunk q+4 into chunk q's
+  // slot, matrix-core instructions of chunk q
+  Frag fa, fb;
+  int q = 0;
+  auto step = [&](const unsigned char* next, unsigned char* mine, Frag& cur, Frag& nxt) {
+    ring_barrier<S_KEEP>();
+    load(next, nxt);
+    issue(q + 4, mine);
+    mma(cur);
+    sched();
+    __builtin_amdgcn_sched_barrier(0);
+    ++q;
+  };
+  issue(0, s0);
+  issue(1, s1);
+  issue(2, s2);
+  issue(3, s3);
+  ring_barrier<3 * S_LPW>();
+  load(s0, fa);
+  while (q < nch) {
+    step(s1, s0, fa, fb);
+    step(s2, s1, fb, fa);
+    step(s3, s2, fa, fb);
+    step(s0, s3, fb, fa);
+  }
+  ring_barrier<0>();
+  // epilogue: element e of a lane's 32 x 32 block is (row 8 (e/4) + 4 (lane/32) + e%4, column
+  // lane%32); per group of four elements every load is issued before the first use
+  double colsum[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    colsum[j] = 0.0;
+    const int K = tl.k0 + wn * 64 + 32 * j + lr;
+    int kp = -1, band = 0;
+    if (occ && K < P.Ko) {
+      kp = K / P.nocc;
+      band = K - kp * P.nocc;
+    } else if (!occ && K - P.Ko_pad < P.Ku) {
+      const int qq = K - P.Ko_pad;
+      kp = qq / P.nu;
+      band = P.nocc + (qq - kp * P.nu);
+    }
+    const double gw = 2.0 * P.pf * P.ct * P.w[K];
+    const double ew = P.pf * P.ct * P.dw[K];
+    const size_t gbase = (size_t)(max(kp, 0) * P.nb + band) * P.nrows;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        bool ok[4];
+        size_t gidx[4], o[4];
+        double gre[4], gim[4], pre[4], pim[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = tl.r0 + wm * 64 + 32 * i + 8 * g + 4 * lh + e;
+          ok[e] = kp >= 0 && row < tl.ns;
+          const int grow = tl.site_row0 + min(row, tl.ns - 1);
+          gidx[e] = 2 * (gbase + grow);
+          o[e] = (size_t)K * P.rows_pad + grow;
+          gre[e] = P.grad[gidx[e]];
+          gim[e] = P.grad[gidx[e] + 1];
+          pre[e] = P.psi[o[e]];
+          pim[e] = P.psi[plane + o[e]];
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const double vr = (double)yr[i][j][4 * g + e], vi = (double)yi[i][j][4 * g + e];
+          if (ok[e]) {
+            P.grad[gidx[e]] = gre[e] + gw * vr;
+            P.grad[gidx[e] + 1] = gim[e] + gw * vi;
+            colsum[j] += ew * (pre[e] * vr + pim[e] * vi);
+          }
+        }
+      }
+  }
+  // reduce the energy partials over the tile's rows (lanes l and l + 32 share a column)
+#pragma unroll
+  for (int j = 0; j < 2; ++j) colsum[j] += __shfl_xor(colsum[j], 32);
+  if (lane < 32) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) red[wm][wn * 64 + 32 * j + lane] = colsum[j];
+  }
+  __syncthreads();
+  if (tid < SN) {
+    double* p = P.part + (size_t)tl.part_row * P.K_pad + tl.k0 + tid;
+    *p += red[0][tid] + red[1][tid];
+  }
+}
+
+// psi planes [2][K_pad][rows_pad] (FP64, compact site rows) -> bfloat16 planes [4][K_pad][srows]
+// (re hi, re lo, im hi, im lo; site rows in 64-row slots, rowmap[slot row] = compact row or -1)
+__global__ void split_psi_kernel(const double* psi, int rows_pad, long long K_pad,
+                                 const int* rowmap, int srows, __bf16* out) {
+  const long long n = K_pad * srows;
+  const size_t pin = (size_t)K_pad * rows_pad;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long K = i / srows;
+    const int r = rowmap[i - K * srows];
+    const double re = r >= 0 ? psi[K * rows_pad + r] : 0.0;
+    const double im = r >= 0 ? psi[pin + K * rows_pad + r] : 0.0;
+    const __bf16 rh = (__bf16)(float)re, ih = (__bf16)(float)im;
+    out[i] = rh;
+    out[n + i] = (__bf16)(float)(re - (double)(float)rh);
+    out[2 * n + i] = ih;
+    out[3 * n + i] = (__bf16)(float)(im - (double)(float)ih);
+  }
+}
+
 // lam = (A + A^T) / 2 per site, from the caller's n x n blocks (offsets blk_off) into blocks
 // with row stride npad (offsets pblk_off); the padding rows and columns are zero
 __global__ void symmetrise_kernel(const double* lam, const long long* blk_off,
@@ -254,7 +496,7 @@ __global__ void symmetrise_kernel(const double* lam, const long long* blk_off,
                                   double* out) {
   const int s = blockIdx.y;
   if (s >= nsites) return;
-  const int n = blk_n[s], np = (n + 15) / 16 * 16;
+  const int n = blk_n[s], np = (n + kAdjAlign - 1) / kAdjAlign * kAdjAlign;
   const double* a = lam + blk_off[s];
   double* o = out + pblk_off[s];
   for (long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x; it < (long long)np * np;
@@ -304,50 +546,71 @@ hipError_t ensure(lrs_ctx* ctx, DevBuf& b, size_t bytes) {
 
 }  // namespace
 
-hipError_t launch_chi0_backward(lrs_ctx* ctx, const double* dL_dchi0, double* dL_dE,
+hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, double* dL_dE,
                                 double* dL_dpsi) {
   hipStream_t st = ctx->stream;
-  // operands: site rows (FP64), site columns (FP64 tiles), k-major orbitals
-  if (ensure_site_tiles_for(ctx, LRS_FP64) != LRS_OK) return hipErrorOutOfMemory;
+  const bool split = prec == LRS_BF16X2;
+  // operands: site rows and site columns of the precision, k-major orbitals (FP64, and split)
+  if (ensure_site_tiles_for(ctx, prec) != LRS_OK) return hipErrorOutOfMemory;
   Plan* plan = nullptr;
-  if (plan_for(ctx, -1, LRS_COLS_SITE, LRS_FP64, 0, 1, &plan) != LRS_OK) return hipErrorOutOfMemory;
+  if (plan_for(ctx, -1, LRS_COLS_SITE, prec, 0, 1, &plan) != LRS_OK) return hipErrorOutOfMemory;
   hipError_t e = ensure(ctx, ctx->psi_site_f64, (size_t)2 * ctx->K_pad * ctx->rows_pad * 8);
   if (e != hipSuccess) return e;
   e = launch_derive_site_kmajor((const double*)ctx->site_f64.p, ctx->rows_pad, ctx->K_pad,
                                 (double*)ctx->psi_site_f64.p, st);
   if (e != hipSuccess) return e;
 
-  // site blocks (the caller's n x n layout, and the padded one of the H arrays) and the GEMM
-  // tile list
+  // site blocks (the caller's n x n layout, and the padded one of the H arrays), the split
+  // orbital rows (64-row slot per site) and the GEMM tile list
   const int S = ctx->nsites;
+  const int tm = split ? SM : BM, tn = split ? SN : BN;
   std::vector<long long> blk_off(S), pblk_off(S);
-  std::vector<int> blk_n(S);
+  std::vector<int> blk_n(S), rowmap;
   std::vector<BwdTile> tiles;
   long long tot = 0, ptot = 0;
-  int nparts = 0;
+  int nparts = 0, srows = 0;
+  if (ctx->K_pad % tn) return hipErrorInvalidValue;
+  const int nkt = ctx->K_pad / tn;
   for (int s = 0; s < S; ++s) {
     const int n = ctx->site_off[s + 1] - ctx->site_off[s];
     const int np = site_block_ld(n, 1);
     blk_off[s] = tot;
     pblk_off[s] = ptot;
     blk_n[s] = n;
-    for (int r0 = 0; r0 < n; r0 += BM) {
-      for (int k0 = 0; k0 < ctx->K_pad; k0 += BN)
-        tiles.push_back(BwdTile{ctx->site_off[s], r0, n, k0, ptot, nparts, np});
-      ++nparts;
+    const int nrt = (n + tm - 1) / tm;
+    auto add = [&](int rt, int kt) {
+      tiles.push_back(BwdTile{ctx->site_off[s], rt * tm, n, kt * tn, ptot, nparts + rt, np, srows});
+    };
+    if (split) {
+      // blocks of 4 row tiles x 8 column tiles
+      for (int r0 = 0; r0 < nrt; r0 += 4)
+        for (int k0 = 0; k0 < nkt; k0 += 8)
+          for (int r = r0; r < std::min(r0 + 4, nrt); ++r)
+            for (int k = k0; k < std::min(k0 + 8, nkt); ++k) add(r, k);
+      for (int i = 0; i < np; ++i) rowmap.push_back(i < n ? ctx->site_off[s] + i : -1);
+      srows += np;
+    } else {
+      for (int r = 0; r < nrt; ++r)
+        for (int k = 0; k < nkt; ++k) add(r, k);
     }
+    nparts += nrt;
     tot += (long long)n * n;
     ptot += (long long)np * np;
   }
-  if (ctx->K_pad % BN) return hipErrorInvalidValue;
   const int T = ctx->quad.nterms;
   const size_t Kp = ctx->K_pad;
-  // workspace: lam | hu_re | hu_im | ho_re | ho_im (padded blocks) | part | w | dw | tiles |
-  // blk_off | pblk_off | blk_n
-  size_t bytes = (size_t)5 * ptot * 8 + (size_t)nparts * Kp * 8 + 2 * (size_t)T * Kp * 8 +
-                 tiles.size() * sizeof(BwdTile) + S * 16 + S * 4 + 4096;
+  // workspace: lam | H (FP64: hu_re | hu_im | ho_re | ho_im; split: hs_u | hs_o, four bfloat16
+  // planes each) over the padded blocks | part | w | dw | tiles | blk_off | pblk_off | blk_n |
+  // rowmap (split)
+  const size_t hbytes = split ? (size_t)16 * ptot : (size_t)32 * ptot;
+  size_t bytes = (size_t)ptot * 8 + hbytes + (size_t)nparts * Kp * 8 + 2 * (size_t)T * Kp * 8 +
+                 tiles.size() * sizeof(BwdTile) + S * 16 + S * 4 + rowmap.size() * 4 + 4096;
   e = ensure(ctx, ctx->adj_work, bytes);
   if (e != hipSuccess) return e;
+  if (split) {
+    e = ensure(ctx, ctx->psi_site_bf16, (size_t)8 * Kp * srows);
+    if (e != hipSuccess) return e;
+  }
   char* p = (char*)ctx->adj_work.p;
   auto take = [&](size_t b) {
     char* q = p;
@@ -355,10 +618,7 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, const double* dL_dchi0, double* dL
     return q;
   };
   double* lam = (double*)take(ptot * 8);
-  double* hu_re = (double*)take(ptot * 8);
-  double* hu_im = (double*)take(ptot * 8);
-  double* ho_re = (double*)take(ptot * 8);
-  double* ho_im = (double*)take(ptot * 8);
+  char* hbuf = take(hbytes);
   double* part = (double*)take((size_t)nparts * Kp * 8);
   double* wn = (double*)take((size_t)T * Kp * 8);
   double* dwn = (double*)take((size_t)T * Kp * 8);
@@ -366,7 +626,14 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, const double* dL_dchi0, double* dL
   long long* dblk_off = (long long*)take(S * 8);
   long long* dpblk_off = (long long*)take(S * 8);
   int* dblk_n = (int*)take(S * 4);
+  int* drowmap = (int*)take(rowmap.size() * 4);
   if ((size_t)(p - (char*)ctx->adj_work.p) > ctx->adj_work.bytes) return hipErrorOutOfMemory;
+  double* hu_re = split ? nullptr : (double*)hbuf;
+  double* hu_im = split ? nullptr : hu_re + ptot;
+  double* ho_re = split ? nullptr : hu_re + 2 * ptot;
+  double* ho_im = split ? nullptr : hu_re + 3 * ptot;
+  __bf16* hs_u = split ? (__bf16*)hbuf : nullptr;
+  __bf16* hs_o = split ? hs_u + 4 * ptot : nullptr;
 
   if ((e = hipMemcpyAsync(wn, ctx->quad.w.data(), (size_t)T * Kp * 8, hipMemcpyHostToDevice, st)) ||
       (e = hipMemcpyAsync(dwn, ctx->quad.dw.data(), (size_t)T * Kp * 8, hipMemcpyHostToDevice, st)) ||
@@ -375,11 +642,19 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, const double* dL_dchi0, double* dL
       (e = hipMemcpyAsync(dpblk_off, pblk_off.data(), S * 8, hipMemcpyHostToDevice, st)) ||
       (e = hipMemcpyAsync(dblk_n, blk_n.data(), S * 4, hipMemcpyHostToDevice, st)))
     return e;
+  if (split) {
+    if ((e = hipMemcpyAsync(drowmap, rowmap.data(), rowmap.size() * 4, hipMemcpyHostToDevice, st)))
+      return e;
+    hipLaunchKernelGGL(split_psi_kernel, dim3(4096), dim3(256), 0, st,
+                       (const double*)ctx->psi_site_f64.p, ctx->rows_pad, (long long)Kp, drowmap,
+                       srows, (__bf16*)ctx->psi_site_bf16.p);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(symmetrise_kernel, dim3(256, S), dim3(256), 0, st, dL_dchi0, dblk_off,
                      dpblk_off, dblk_n, S, lam);
   // the adjoint Green's-function launches write the blocks' valid entries only: the padding
   // of the H arrays must read as zero in the contraction
-  if ((e = launch_fill_zero(hu_re, (size_t)((char*)(ho_im + ptot) - (char*)hu_re), st)) ||
+  if ((e = launch_fill_zero(hbuf, hbytes, st)) ||
       (e = launch_fill_zero(part, (size_t)nparts * Kp * 8, st)) ||
       (e = launch_fill_zero(dL_dpsi, (size_t)2 * ctx->nk * ctx->nb * ctx->nrows * 8, st)))
     return e;
@@ -403,21 +678,33 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, const double* dL_dchi0, double* dL
   B.tiles = dtiles;
   B.grad = dL_dpsi;
   B.part = part;
+  B.hs_u = hs_u;
+  B.hs_o = hs_o;
+  B.hs_plane = ptot;
+  B.psis = split ? (const __bf16*)ctx->psi_site_bf16.p : nullptr;
+  B.srows = srows;
+  B.ntiles = (int)tiles.size();
+  B.per = (B.ntiles + 7) / 8;
+  const int chunk = chunk_of(prec);
   for (int t = 0; t < T; ++t) {
     for (const Batch& bt : plan->batches) {
       if (bt.ntiles == 0) continue;
-      if (ensure_site_operand(ctx, LRS_FP64, bt, t, 1) != LRS_OK) return hipErrorOutOfMemory;
-      if (ensure_park(ctx, LRS_FP64, 0, bt.grid) != LRS_OK) return hipErrorOutOfMemory;
-      e = launch_green_adjoint(bt.grid, ctx->a_tiles.p, bt.nrb, ctx->site_tiles[LRS_FP64].p,
-                               ctx->site_cols_pad / 16, ctx->K_pad / kChunkF64, (const double*)ctx->c_dev.p + t,
-                               ctx->Ko_pad / kChunkF64, (const TileDesc*)plan->tiles.p + bt.tile0,
-                               bt.ntiles, lam, hu_re, hu_im, ho_re, ho_im, ctx->park.p, st);
+      if (ensure_site_operand(ctx, prec, bt, t, 1) != LRS_OK) return hipErrorOutOfMemory;
+      if (ensure_park(ctx, prec, 0, bt.grid) != LRS_OK) return hipErrorOutOfMemory;
+      e = launch_green_adjoint(prec, bt.grid, ctx->a_tiles.p, bt.nrb, ctx->site_tiles[prec].p,
+                               ctx->site_cols_pad / 16, ctx->K_pad / chunk,
+                               (const double*)ctx->c_dev.p + t, ctx->Ko_pad / chunk,
+                               (const TileDesc*)plan->tiles.p + bt.tile0, bt.ntiles, lam, hu_re,
+                               hu_im, ho_re, ho_im, hs_u, hs_o, ptot, ctx->park.p, st);
       if (e != hipSuccess) return e;
     }
     B.w = wn + (size_t)t * Kp;
     B.dw = dwn + (size_t)t * Kp;
     B.ct = ctx->quad.c[t];
-    hipLaunchKernelGGL(bwd_gemm_kernel, dim3((unsigned)tiles.size()), dim3(256), 0, st, B);
+    if (split)
+      hipLaunchKernelGGL(bwd_split_kernel, dim3((unsigned)(8 * B.per)), dim3(256), 0, st, B);
+    else
+      hipLaunchKernelGGL(bwd_gemm_kernel, dim3((unsigned)tiles.size()), dim3(256), 0, st, B);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   hipLaunchKernelGGL(reduce_energy_kernel, dim3((ctx->K_pad + 255) / 256), dim3(256), 0, st, part,

@@ -55,13 +55,28 @@ struct Chi0Params {
   double* out;
   double pref;
   unsigned char* park;          // per-workgroup space for G_o between the two phases
-  // adjoint mode (FP64 only): with T = 1, write lam * conj(G_u) and lam * conj(G_o)
+  // adjoint modes: with T = 1, write lam * conj(G_u) and lam * conj(G_o), as FP64 planes
+  // (mode 1) or as bfloat16 hi/lo planes re hi, re lo, im hi, im lo (mode 2)
   const double* lam;
   double* hu_re;
   double* hu_im;
   double* ho_re;
   double* ho_im;
+  __bf16* hs_u;
+  __bf16* hs_o;
+  long long hs_plane;
 };
+
+// x = hi + lo in bfloat16 (hi rounded from x, lo from the remainder), re and im of one
+// element into four planes
+__device__ __forceinline__ void put_split(__bf16* base, long long plane, long long o, double re,
+                                          double im) {
+  const __bf16 rh = (__bf16)(float)re, ih = (__bf16)(float)im;
+  base[o] = rh;
+  base[plane + o] = (__bf16)(float)(re - (double)(float)rh);
+  base[2 * plane + o] = ih;
+  base[3 * plane + o] = (__bf16)(float)(im - (double)(float)ih);
+}
 
 // Matrix-core shape per precision.  FP64 and FP32 use 16 x 16 accumulator blocks (4 values
 // per lane); the split 16-bit paths use the 32 x 32 x 16 instructions (16 values per lane),
@@ -718,7 +733,7 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
             off[e] = in[e] ? row * td.ldo + col : 0;
             dg[e] = col - row - td.pad;   // (site column) - (site row), adjoint mode
           }
-          if constexpr (MODE == 1) {
+          if constexpr (MODE >= 1) {
             // adjoint: Hu = lam * conj(G_u), Ho = lam * conj(G_o) on a site block.  lam is
             // symmetric and G Hermitian there, so H(c, r) = conj(H(r, c)): the host lists only
             // tiles that reach the upper triangle, each element on or above the diagonal is
@@ -733,16 +748,25 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
                 const long long o = obase + off[e];
                 const double hur = l[e] * (double)gr[i][j][e], hui = -l[e] * (double)gi[i][j][e];
                 const double hor = l[e] * (double)or_[e], hoi = -l[e] * (double)oi_[e];
-                P.hu_re[o] = hur;
-                P.hu_im[o] = hui;
-                P.ho_re[o] = hor;
-                P.ho_im[o] = hoi;
-                if (dg[e] > 0) {
-                  const long long ot = o + (long long)dg[e] * (td.ldo - 1);
-                  P.hu_re[ot] = hur;
-                  P.hu_im[ot] = -hui;
-                  P.ho_re[ot] = hor;
-                  P.ho_im[ot] = -hoi;
+                const long long ot = o + (long long)dg[e] * (td.ldo - 1);
+                if constexpr (MODE == 1) {
+                  P.hu_re[o] = hur;
+                  P.hu_im[o] = hui;
+                  P.ho_re[o] = hor;
+                  P.ho_im[o] = hoi;
+                  if (dg[e] > 0) {
+                    P.hu_re[ot] = hur;
+                    P.hu_im[ot] = -hui;
+                    P.ho_re[ot] = hor;
+                    P.ho_im[ot] = -hoi;
+                  }
+                } else {
+                  put_split(P.hs_u, P.hs_plane, o, hur, hui);
+                  put_split(P.hs_o, P.hs_plane, o, hor, hoi);
+                  if (dg[e] > 0) {
+                    put_split(P.hs_u, P.hs_plane, ot, hur, -hui);
+                    put_split(P.hs_o, P.hs_plane, ot, hor, -hoi);
+                  }
                 }
               }
           } else {
@@ -946,6 +970,8 @@ hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int
   P.pref = pref;
   P.lam = nullptr;
   P.hu_re = P.hu_im = P.ho_re = P.ho_im = nullptr;
+  P.hs_u = P.hs_o = nullptr;
+  P.hs_plane = 0;
   switch (prec) {
     case LRS_FP64: return launch_p<LRS_FP64>(variant, grid, P, s);
     case LRS_FP32: return launch_p<LRS_FP32>(variant, grid, P, s);
@@ -955,11 +981,12 @@ hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_green_adjoint(int grid, const void* a_tiles, int a_nrb, const void* b_tiles,
-                                int b_ncb, int nch, const double* c, int nch_o,
-                                const TileDesc* tiles, int ntiles, const double* lam,
+hipError_t launch_green_adjoint(int prec, int grid, const void* a_tiles, int a_nrb,
+                                const void* b_tiles, int b_ncb, int nch, const double* c,
+                                int nch_o, const TileDesc* tiles, int ntiles, const double* lam,
                                 double* hu_re, double* hu_im, double* ho_re, double* ho_im,
-                                void* park, hipStream_t s) {
+                                void* hs_u, void* hs_o, long long hs_plane, void* park,
+                                hipStream_t s) {
   Chi0Params P;
   P.park = (unsigned char*)park;
   P.a = (const unsigned char*)a_tiles;
@@ -979,7 +1006,14 @@ hipError_t launch_green_adjoint(int grid, const void* a_tiles, int a_nrb, const 
   P.hu_im = hu_im;
   P.ho_re = ho_re;
   P.ho_im = ho_im;
-  return launch_v<LRS_FP64, 0, 1>(grid, P, s);
+  P.hs_u = (__bf16*)hs_u;
+  P.hs_o = (__bf16*)hs_o;
+  P.hs_plane = hs_plane;
+  switch (prec) {
+    case LRS_FP64: return launch_v<LRS_FP64, 0, 1>(grid, P, s);
+    case LRS_BF16X2: return launch_v<LRS_BF16X2, 0, 2>(grid, P, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace lrs

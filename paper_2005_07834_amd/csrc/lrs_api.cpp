@@ -94,6 +94,7 @@ void drop_sites(lrs_ctx* ctx) {
   release(ctx, ctx->a_tiles);
   ctx->a_prec = -1;
   release(ctx, ctx->psi_site_f64);
+  release(ctx, ctx->psi_site_bf16);
   for (auto& b : ctx->site_tiles) release(ctx, b);
   release(ctx, ctx->site_colmap);
   ctx->have_sites = false;
@@ -988,18 +989,20 @@ lrs_status lrs_screen_W_backward(lrs_ctx* ctx, const double* dL_dW, double* dL_d
   return LRS_OK;
 }
 
-lrs_status lrs_compute_chi0_backward(lrs_ctx* ctx, int cols, const double* dL_dchi0, double* dL_dE,
-                                     void* dL_dpsi_site, void* dL_dpsi_grid) {
+lrs_status lrs_compute_chi0_backward(lrs_ctx* ctx, int cols, int prec, const double* dL_dchi0,
+                                     double* dL_dE, void* dL_dpsi_site, void* dL_dpsi_grid) {
   if (!ctx) return LRS_EINVAL;
   ctx->err.clear();
   if (!ctx->have_bands || !ctx->have_sites || !ctx->have_quad)
     return fail(ctx, LRS_ESTATE, "orbitals, sites and quadrature must be set first");
   if (cols != LRS_COLS_SITE) return fail(ctx, LRS_EUNSUPPORTED, "backward supports site x site blocks only");
+  if (prec != LRS_FP64 && prec != LRS_BF16X2)
+    return fail(ctx, LRS_EUNSUPPORTED, "backward precision must be LRS_FP64 or LRS_BF16X2");
   if (dL_dpsi_grid) return fail(ctx, LRS_EUNSUPPORTED, "site blocks do not depend on grid orbitals");
   if (!dL_dchi0 || !dL_dE || !dL_dpsi_site) return fail(ctx, LRS_EINVAL, "missing gradient buffers");
   if (!ctx->quad.has_deriv) return fail(ctx, LRS_EUNSUPPORTED, "generic terms carry no energy derivative");
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
-  hipError_t e = launch_chi0_backward(ctx, dL_dchi0, dL_dE, (double*)dL_dpsi_site);
+  hipError_t e = launch_chi0_backward(ctx, prec, dL_dchi0, dL_dE, (double*)dL_dpsi_site);
   if (e == hipErrorOutOfMemory) return fail(ctx, LRS_ENOMEM, "adjoint workspace");
   if (e != hipSuccess) return fail(ctx, LRS_EDEVICE, "chi0 backward: %s", hipGetErrorString(e));
   return LRS_OK;

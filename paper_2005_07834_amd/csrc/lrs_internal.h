@@ -29,9 +29,13 @@ constexpr int kPhaseAlign = 128;
 constexpr int kMaxTerms = 128;
 
 inline bool is_split(int prec) { return prec == LRS_BF16X2 || prec == LRS_FP16X2; }
-// leading dimension of a site's n x n block: n for chi0 outputs, n rounded up to 16 for the
-// adjoint's internal site blocks (plan mode 1)
-inline int site_block_ld(int n, int mode) { return mode == 1 ? (n + 15) / 16 * 16 : n; }
+// leading dimension of a site's n x n block: n for chi0 outputs, n rounded up to kAdjAlign for
+// the adjoint's internal site blocks (plan mode 1): a whole number of four-chunk ring cycles
+// of the adjoint GEMMs' contraction, whose padding is zero
+constexpr int kAdjAlign = 64;
+inline int site_block_ld(int n, int mode) {
+  return mode == 1 ? (n + kAdjAlign - 1) / kAdjAlign * kAdjAlign : n;
+}
 // K values per chunk and bytes per fragment tile (16 rows x chunk x planes)
 inline int chunk_of(int prec) { return prec == LRS_FP32 ? 32 : 16; }
 inline int tile_bytes(int prec) { return is_split(prec) ? 2048 : 4096; }
@@ -126,6 +130,8 @@ struct lrs_ctx {
   lrs::DevBuf park;               // per-workgroup G_o scratch of the chi0 launches
   int a_prec = -1, a_version = -1, a_rb0 = -1, a_nrb = -1, a_t0 = -1, a_nt = -1;
   lrs::DevBuf psi_site_f64;       // planar [2][K_pad][rows_pad] (k-major rows) for the adjoint
+  lrs::DevBuf psi_site_bf16;      // the same split: bfloat16 [4][K_pad][rows_pad] (re hi, re lo,
+                                  // im hi, im lo) for the split adjoint
   float site_max_abs = 0.f;
   float grid_max_abs = 0.f;
 
@@ -187,11 +193,15 @@ hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int
                        const void* b_tiles, int b_ncb, int nch, const double* c, int T,
                        int nch_o, const TileDesc* tiles, int ntiles, double* out, double pref,
                        void* park, hipStream_t s);
-hipError_t launch_green_adjoint(int grid, const void* a_tiles, int a_nrb, const void* b_tiles,
-                                int b_ncb, int nch, const double* c, int nch_o,
-                                const TileDesc* tiles, int ntiles, const double* lam,
+// adjoint Green's functions of one term on site blocks: prec LRS_FP64 writes Hu, Ho as FP64
+// planes (hu_re, hu_im, ho_re, ho_im); LRS_BF16X2 writes each as four bfloat16 planes
+// (re hi, re lo, im hi, im lo; plane stride hs_plane elements) at hs_u, hs_o
+hipError_t launch_green_adjoint(int prec, int grid, const void* a_tiles, int a_nrb,
+                                const void* b_tiles, int b_ncb, int nch, const double* c,
+                                int nch_o, const TileDesc* tiles, int ntiles, const double* lam,
                                 double* hu_re, double* hu_im, double* ho_re, double* ho_im,
-                                void* park, hipStream_t s);
+                                void* hs_u, void* hs_o, long long hs_plane, void* park,
+                                hipStream_t s);
 
 // lrs_api.cpp (shared with the adjoint)
 lrs_status plan_for(lrs_ctx* ctx, int site, int cols, int prec, int variant, int mode,
@@ -206,7 +216,7 @@ hipError_t launch_screen_forward(lrs_ctx* ctx, const double* chi0_ss, double* W_
 hipError_t launch_screen_backward(lrs_ctx* ctx, const double* dL_dW, double* dL_dchi0);
 
 // adjoint.hip
-hipError_t launch_chi0_backward(lrs_ctx* ctx, const double* dL_dchi0, double* dL_dE,
+hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, double* dL_dE,
                                 double* dL_dpsi);
 
 }  // namespace lrs

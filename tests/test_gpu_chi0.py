@@ -230,19 +230,26 @@ def test_screen_backward_matches_rank_one_sensitivity(P, tiny_ref):
     assert rel(lam2.reshape(lam.shape), lam) < 1e-12
 
 
-def test_chi0_backward_vs_oracle(P, tiny_ref):
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("bf16x2", 1e-4)])
+def test_chi0_backward_vs_oracle(P, tiny_ref, prec, tol):
+    """The adjoint (FP64, or with the split products) against the oracle's gradient of the
+    test-charge loss; a second call gives the same bits."""
     w = tiny_ref["w"]
     n, s = tiny_ref["n"], tiny_ref["scale"]
-    say("tiny chi0 backward")
+    say(f"tiny chi0 backward ({prec})")
     ctx = make_ctx(P, w, n, s)
     chi = ctx.chi0(-1, P.COLS_SITE, P.FP64)
     ctx.screen_W(chi, rho=w.rho_test, want_loss=True)
     lam = ctx.screen_W_backward()
-    dE, dpsi = ctx.chi0_backward(lam)
+    dE, dpsi = ctx.chi0_backward(lam, prec)
     L, dE_ref, dpsi_ref = gr.loss_and_grads(tiny_ref["ps"], w.energies, w.nocc, 2, w.sites,
                                             w.rho_test, "time", n, s)
     eE, eP = rel(dE.cpu().numpy(), dE_ref), rel(dpsi.cpu().numpy(), dpsi_ref)
     say(f"  dE {eE:.3e} dpsi {eP:.3e}")
-    assert eE < 1e-9 and eP < 1e-9
-    dE2, dpsi2 = ctx.chi0_backward(lam)
+    assert eE < tol and eP < tol
+    dE2, dpsi2 = ctx.chi0_backward(lam, prec)
     assert torch.equal(dE, dE2) and torch.equal(dpsi, dpsi2)
+    for bad in (P.FP32, P.FP16X2):
+        with pytest.raises(P.LrsError) as e:
+            ctx.chi0_backward(lam, bad)
+        assert e.value.status == P.LRS_EUNSUPPORTED

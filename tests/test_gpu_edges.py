@@ -83,7 +83,8 @@ def test_minimal_band_sets(P, nb, nocc):
 
 def test_small_sites_ragged_grids_few_terms(P):
     """Sites of 26, 150 and 208 points (a single 26-point shell included) in one call; grid
-    column counts 1, 17 and 129; 1 and 3 imaginary-time terms; W of every site."""
+    column counts 1, 17 and 129; 1 and 3 imaginary-time terms; W of every site; the split
+    adjoint against the FP64 adjoint."""
     w = workload("tiny")
     c0 = w.sites[0].centre
     sites = [sx.make_site(c0 + 0.3, 1, 26, r_max=1.0),
@@ -114,6 +115,17 @@ def test_small_sites_ragged_grids_few_terms(P):
                     eW = rel(Wk.cpu().numpy(), sc.screen_W(ref_s[k], sites[k]))
                     say(f"  terms={nterms} W site {k} ({npts[k]} points): {eW:.2e}")
                     assert eW < 1e-11
+                # adjoint on these sizes (one 64-row slot for the 26-point site, rows past
+                # each site in the split layout): split products against FP64
+                g = torch.Generator(device="cpu").manual_seed(11)
+                lam = torch.randn(sum(m * m for m in npts), generator=g,
+                                  dtype=torch.float64).cuda()
+                dE64, dp64 = ctx.chi0_backward(lam, P.FP64)
+                dEs, dps = ctx.chi0_backward(lam, P.BF16X2)
+                eE = rel(dEs.cpu().numpy(), dE64.cpu().numpy())
+                eP = rel(dps.cpu().numpy(), dp64.cpu().numpy())
+                say(f"  terms={nterms} split adjoint vs FP64: dE {eE:.2e} dpsi {eP:.2e}")
+                assert eE < 1e-4 and eP < 1e-4
             ctx.close()
 
 
