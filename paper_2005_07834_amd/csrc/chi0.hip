@@ -54,6 +54,7 @@ struct Chi0Params {
   int ntiles;
   double* out;
   double pref;
+  int sym;                      // site blocks from their upper triangle (mode 0)
   unsigned char* park;          // per-workgroup space for G_o between the two phases
   // adjoint modes: with T = 1, write lam * conj(G_u) and lam * conj(G_o), as FP64 planes
   // (mode 1) or as bfloat16 hi/lo planes re hi, re lo, im hi, im lo (mode 2)
@@ -771,7 +772,10 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
               }
           } else {
             // chi accumulates across terms in FP64 in the output itself (this tile's entries
-            // belong to this workgroup only); the last term applies the prefactor
+            // belong to this workgroup only); the last term applies the prefactor.  On a site
+            // block chi0 is symmetric (G Hermitian, so Re[G_o conj(G_u)] is the same at (r, c)
+            // and (c, r)): the host lists only tiles that reach the upper triangle, and each
+            // element on or above the diagonal is stored at both places
             const double ct = P.c[t];
             const double scale = t == P.T - 1 ? P.pref : 1.0;
             double old[ELEMS];
@@ -786,7 +790,11 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
             for (int e = 0; e < ELEMS; ++e) {
               const double v = ct * ((double)or_[e] * (double)gr[i][j][e] +
                                      (double)oi_[e] * (double)gi[i][j][e]);
-              if (in[e]) P.out[obase + off[e]] = (v + old[e]) * scale;
+              const double r = (v + old[e]) * scale;
+              if (in[e] && (!P.sym || dg[e] >= 0)) {
+                P.out[obase + off[e]] = r;
+                if (P.sym && dg[e] > 0) P.out[obase + off[e] + (long long)dg[e] * (td.ldo - 1)] = r;
+              }
             }
           }
         }
@@ -953,8 +961,9 @@ hipError_t launch_prep_site(int prec, const double* site, int rows_pad, int K_pa
 hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int a_nrb,
                        const void* b_tiles, int b_ncb, int nch, const double* c, int T,
                        int nch_o, const TileDesc* tiles, int ntiles, double* out, double pref,
-                       void* park, hipStream_t s) {
+                       int sym, void* park, hipStream_t s) {
   Chi0Params P;
+  P.sym = sym;
   P.park = (unsigned char*)park;
   P.a = (const unsigned char*)a_tiles;
   P.a_nrb = a_nrb;
@@ -1001,6 +1010,7 @@ hipError_t launch_green_adjoint(int prec, int grid, const void* a_tiles, int a_n
   P.ntiles = ntiles;
   P.out = nullptr;
   P.pref = 1.0;
+  P.sym = 0;
   P.lam = lam;
   P.hu_re = hu_re;
   P.hu_im = hu_im;

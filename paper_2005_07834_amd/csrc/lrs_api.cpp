@@ -334,7 +334,7 @@ lrs_status get_plan(lrs_ctx* ctx, int site, int cols, int prec, int variant, int
       }
   };
   // site-block output offsets; the adjoint mode (1) writes blocks with rows padded to a
-  // multiple of 16 (site_block_ld), the layout its GEMM reads
+  // multiple of kAdjAlign (site_block_ld), the layout its GEMMs read
   std::vector<long long> site_base(ctx->nsites + 1, 0);
   for (int s = s0; s < s1; ++s) {
     const long long ld = site_block_ld(ctx->site_off[s + 1] - ctx->site_off[s], mode);
@@ -371,9 +371,10 @@ lrs_status get_plan(lrs_ctx* ctx, int site, int cols, int prec, int variant, int
         const int ld = site_block_ld(n, mode);
         emit_blocked((int)(j - i), nc, [&](int r, int c) {
           const RowTile& x = rt[i + r];
-          // the adjoint mode stores Hermitian blocks from their upper triangle: tiles wholly
-          // below the diagonal are not needed, and pad carries (first row - first column)
-          if (mode == 1 && c * sh.bn + sh.bn - 1 < x.m0) return;
+          // chi0 (symmetric) and the adjoint's H (Hermitian) blocks are stored from their
+          // upper triangle: tiles wholly below the diagonal are not needed, and pad carries
+          // (first row - first column)
+          if (c * sh.bn + sh.bn - 1 < x.m0) return;
           TileDesc t;
           t.a_row0 = x.slot_row - bt.rb0 * 16;
           t.b_col0 = slot0 + c * sh.bn;
@@ -381,7 +382,7 @@ lrs_status get_plan(lrs_ctx* ctx, int site, int cols, int prec, int variant, int
           t.ncols = std::min(sh.bn, n - c * sh.bn);
           t.out_off = site_base[s] - site_base[s0] + (long long)x.m0 * ld + (long long)c * sh.bn;
           t.ldo = ld;
-          t.pad = mode == 1 ? x.m0 - c * sh.bn : 0;
+          t.pad = x.m0 - c * sh.bn;
           tiles.push_back(t);
         });
         i = j;
@@ -492,7 +493,7 @@ lrs_status run_chi0(lrs_ctx* ctx, int site, int cols, int prec, int variant, dou
     HIP_OR_FAIL(ctx, launch_chi0(prec, variant, grid, ctx->a_tiles.p, bt.nrb, b, b_ncb, nch,
                                  (const double*)ctx->c_dev.p, T, ctx->Ko_pad / KC,
                                  (const TileDesc*)plan->tiles.p + bt.tile0, nt, out, pref,
-                                 ctx->park.p, ctx->stream));
+                                 cols == LRS_COLS_SITE, ctx->park.p, ctx->stream));
     if (max_tiles > 0) break;
   }
   if (timed && !first) {

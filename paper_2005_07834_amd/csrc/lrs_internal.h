@@ -49,7 +49,7 @@ struct TileDesc {
   int ncols;            // valid columns
   long long out_off;    // element offset of the tile's (0,0) in the output
   int ldo;              // output leading dimension
-  int pad;              // adjoint mode: first site row - first site column (else 0)
+  int pad;              // site blocks: first site row - first site column (else 0)
 };
 static_assert(sizeof(TileDesc) == 32, "TileDesc layout");
 
@@ -189,10 +189,12 @@ TileShape chi0_shape(int prec, int variant);
 hipError_t launch_prep_site(int prec, const double* site, int rows_pad, int K_pad,
                             const int* slot_row, int rb0, int nrb, const double* w, int t0,
                             int nt, double a_scale, void* out, hipStream_t s);
+// sym: site x site blocks, listed from their upper triangle (TileDesc.pad set): each element
+// on or above the diagonal is also stored at its transposed place
 hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int a_nrb,
                        const void* b_tiles, int b_ncb, int nch, const double* c, int T,
                        int nch_o, const TileDesc* tiles, int ntiles, double* out, double pref,
-                       void* park, hipStream_t s);
+                       int sym, void* park, hipStream_t s);
 // adjoint Green's functions of one term on site blocks: prec LRS_FP64 writes Hu, Ho as FP64
 // planes (hu_re, hu_im, ho_re, ho_im); LRS_BF16X2 writes each as four bfloat16 planes
 // (re hi, re lo, im hi, im lo; plane stride hs_plane elements) at hs_u, hs_o
