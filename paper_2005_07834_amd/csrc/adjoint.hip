@@ -29,10 +29,11 @@ struct BwdTile {
   int r0;              // first local row of this tile
   int ns;              // points of the site
   int k0;              // first K column of this tile
-  long long h_off;     // offset of the site's block in the H arrays (row stride npad)
+  long long h_off;     // offset of the site's block in the H arrays (FP64: row stride npad; split:
+                       // operand tiles, four values per element)
   int part_row;        // row-tile index for the energy partials
   int npad;            // ns rounded up to 64: row stride of the H block, contraction length
-  int srow0;           // split GEMM: first row of the site in the split psi planes
+  int srow0;           // split GEMM: first slot row of the site in the split psi operand
 };
 
 struct BwdParams {
@@ -49,10 +50,10 @@ struct BwdParams {
   double* grad;          // complex128 [nk][nb][nrows]
   double* part;          // [nparts][K_pad]
   // split GEMM only
-  const __bf16* hs_u;    // Hu, Ho: four planes (re hi, re lo, im hi, im lo), blocks as above
+  const __bf16* hs_u;    // Hu, Ho in operand tiles (h_tile_offset), blocks at h_off
   const __bf16* hs_o;
-  long long hs_plane;
-  const __bf16* psis;    // four planes of psi, each [K_pad][srows], sites in 64-row slots
+  const __bf16* psis;    // psi in operand tiles: 4 KiB groups [srows / 16][K_pad / 32], sites
+                         // in 64-row slots (rows: K, contraction: site rows)
   int srows;
   int ntiles, per;       // tiles, and tiles per eighth of the grid
 };
@@ -259,14 +260,14 @@ __global__ __launch_bounds__(256) void bwd_gemm_kernel(BwdParams P) {
 // The same product in split precision: Y = H psi with H = H_hi + H_lo and psi = psi_hi +
 // psi_lo in bfloat16, each real product taken as hi*hi + hi*lo + lo*hi on
 // v_mfma_f32_32x32x16_bf16 with FP32 accumulation.  Lane l of an instruction holds row (or
-// column) l%32 and r' = 8 (l/32) + e, e = 0..7: sixteen consecutive bytes of one row of an H
-// plane (row stride npad) and of one K row of a psi plane, so every operand again comes from
-// its natural layout by 16-byte direct-to-LDS loads.  A 32-row block of one plane and one
-// chunk of 16 r' is 1 KiB of LDS ([lane][16 B]): conflict-free 16-byte fragment reads.
-// 128 x 128 workgroup tiles (2 x 2 waves of 64 x 64), a four-slot ring, and the epilogue of
-// the FP64 GEMM with Y converted to FP64.  Workgroup b takes tile (b % 8) * per + b / 8, so
-// the workgroups resident on one XCD run a contiguous stretch of the tile list, which the host
-// orders in blocks of 4 row tiles x 8 column tiles.
+// column) l%32 and r' = 8 (l/32) + e, e = 0..7.  Both operands are stored in that order
+// (h_tile_offset: 1 KiB per 32 rows x 16 r' x plane, planes of a piece adjacent, chunks of r'
+// outermost), so every wave-wide direct-to-LDS load moves one contiguous KiB and every
+// fragment read is a conflict-free 16-byte LDS read.  128 x 128 workgroup tiles (2 x 2 waves
+// of 64 x 64), a four-slot ring, and the epilogue of the FP64 GEMM with Y converted to FP64.
+// Workgroup b takes tile (b % 8) * per + b / 8, so the workgroups resident on one XCD run a
+// contiguous stretch of the tile list, which the host orders in blocks of 4 row tiles x 8
+// column tiles.
 constexpr int SM = 128, SN = 128;
 constexpr int S_AB = SM / 32, S_BB = SN / 32;     // 32-row (column) blocks per tile
 constexpr int S_PIECES = (S_AB + S_BB) * 4;       // 1 KiB pieces per chunk: blocks x 4 planes
@@ -294,32 +295,34 @@ __global__ __launch_bounds__(256) void bwd_split_kernel(BwdParams P) {
   // wave w loads plane w of every block of a chunk: piece j = 4 t + w of the A blocks, then of
   // the B blocks
   const int lr = lane & 31, lh = lane >> 5;
-  const __bf16* hsrc = (occ ? P.hs_u : P.hs_o) + wave * P.hs_plane + tl.h_off;
+  const int hb = tl.npad >> 5;    // 32-row blocks of the H block
   const __bf16* asrc[S_AB];
 #pragma unroll
   for (int t = 0; t < S_AB; ++t) {
-    // rows past the block read its last row (their results are not stored)
-    const int row = min(tl.r0 + 32 * t + lr, tl.npad - 1);
-    asrc[t] = hsrc + (size_t)row * tl.npad + 8 * lh;
+    // blocks past the H block read its last one (their results are not stored)
+    const int rb = min((tl.r0 >> 5) + t, hb - 1);
+    asrc[t] = (occ ? P.hs_u : P.hs_o) + tl.h_off + ((size_t)(4 * rb + wave) << 9) + lane * 8;
   }
-  const size_t plane = (size_t)P.K_pad * P.rows_pad;
+  const size_t a_chunk = (size_t)hb << 11;
   const __bf16* bsrc[S_BB];
+  const size_t b_chunk = (size_t)(P.K_pad >> 5) << 11;
 #pragma unroll
   for (int t = 0; t < S_BB; ++t)
-    bsrc[t] = P.psis + (size_t)wave * P.K_pad * P.srows + (size_t)(tl.k0 + 32 * t + lr) * P.srows +
-              tl.srow0 + 8 * lh;
+    bsrc[t] = P.psis + (size_t)(tl.srow0 >> 4) * b_chunk +
+              ((size_t)(4 * ((tl.k0 >> 5) + t) + wave) << 9) + lane * 8;
+  const size_t plane = (size_t)P.K_pad * P.rows_pad;
   const int nch = tl.npad / 16;   // a multiple of 4
   auto issue = [&](int c, unsigned char* dst) {
     c = min(c, nch - 1);          // past the end: the last chunk again, never read
 #pragma unroll
     for (int t = 0; t < S_AB; ++t)
       __builtin_amdgcn_global_load_lds(
-          (const void __attribute__((address_space(1)))*)(asrc[t] + c * 16),
+          (const void __attribute__((address_space(1)))*)(asrc[t] + c * a_chunk),
           (void __attribute__((address_space(3)))*)(dst + (4 * t + wave) * 1024), 16, 0, 0);
 #pragma unroll
     for (int t = 0; t < S_BB; ++t)
       __builtin_amdgcn_global_load_lds(
-          (const void __attribute__((address_space(1)))*)(bsrc[t] + c * 16),
+          (const void __attribute__((address_space(1)))*)(bsrc[t] + c * b_chunk),
           (void __attribute__((address_space(3)))*)(dst + (4 * (S_AB + t) + wave) * 1024), 16, 0,
           0);
   };
@@ -345,31 +348,33 @@ __global__ __launch_bounds__(256) void bwd_split_kernel(BwdParams P) {
         yr[i][j][e] = 0.f;
         yi[i][j][e] = 0.f;
       }
-  // Yr += Hr psi_r - Hi psi_i, Yi += Hr psi_i + Hi psi_r (planes 0, 1 = re hi, lo; 2, 3 = im)
+  // Yr += Hr psi_r - Hi psi_i, Yi += Hr psi_i + Hi psi_r (planes 0, 1 = re hi, lo; 2, 3 = im),
+  // each real product as hi*hi + hi*lo + lo*hi.  Products go in the outer loop, so that the
+  // four blocks' accumulators take turns and consecutive instructions never depend on each
+  // other.
   auto mma = [&](const Frag& f) {
     const u32x4 m = {0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
-    auto mf = [](bf16x8 a, bf16x8 b, f32x16 c) {
-      return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
-    };
+    bf16x8 ni[2][2];   // -Hi hi, -Hi lo per block
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      const bf16x8 nih = (bf16x8)((u32x4)f.a[i][2] ^ m), nil = (bf16x8)((u32x4)f.a[i][3] ^ m);
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        yr[i][j] = mf(f.a[i][0], f.b[j][0], yr[i][j]);
-        yi[i][j] = mf(f.a[i][0], f.b[j][2], yi[i][j]);
-        yr[i][j] = mf(f.a[i][0], f.b[j][1], yr[i][j]);
-        yi[i][j] = mf(f.a[i][0], f.b[j][3], yi[i][j]);
-        yr[i][j] = mf(f.a[i][1], f.b[j][0], yr[i][j]);
-        yi[i][j] = mf(f.a[i][1], f.b[j][2], yi[i][j]);
-        yr[i][j] = mf(nih, f.b[j][2], yr[i][j]);
-        yi[i][j] = mf(f.a[i][2], f.b[j][0], yi[i][j]);
-        yr[i][j] = mf(nih, f.b[j][3], yr[i][j]);
-        yi[i][j] = mf(f.a[i][2], f.b[j][1], yi[i][j]);
-        yr[i][j] = mf(nil, f.b[j][2], yr[i][j]);
-        yi[i][j] = mf(f.a[i][3], f.b[j][0], yi[i][j]);
-      }
+      ni[i][0] = (bf16x8)((u32x4)f.a[i][2] ^ m);
+      ni[i][1] = (bf16x8)((u32x4)f.a[i][3] ^ m);
     }
+    // {A plane (4, 5: -Hi hi, -Hi lo), B plane, target (0: Yr, 1: Yi)}
+    constexpr int prod[12][3] = {{0, 0, 0}, {0, 2, 1}, {0, 1, 0}, {0, 3, 1},
+                                 {1, 0, 0}, {1, 2, 1}, {4, 2, 0}, {2, 0, 1},
+                                 {4, 3, 0}, {2, 1, 1}, {5, 2, 0}, {3, 0, 1}};
+#pragma unroll
+    for (int p = 0; p < 12; ++p)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const bf16x8 a = prod[p][0] >= 4 ? ni[i][prod[p][0] - 4] : f.a[i][prod[p][0]];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          f32x16& acc = prod[p][2] ? yi[i][j] : yr[i][j];
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, f.b[j][prod[p][1]], acc, 0, 0, 0);
+        }
+      }
   };
   constexpr int kMFMA = 0x008, kVMEM = 0x010, kDSREAD = 0x100;
   constexpr int NMF = 48, NDS = 16, NVM = S_LPW;
@@ -407,7 +412,8 @@ __global__ __launch_bounds__(256) void bwd_split_kernel(BwdParams P) {
   }
   ring_barrier<0>();
   // epilogue: element e of a lane's 32 x 32 block is (row 8 (e/4) + 4 (lane/32) + e%4, column
-  // lane%32); per group of four elements every load is issued before the first use
+  // lane%32); per block every load is issued before the first use (the stores may alias
+  // the next block's loads, so each block costs one memory latency)
   double colsum[2];
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
@@ -426,34 +432,31 @@ __global__ __launch_bounds__(256) void bwd_split_kernel(BwdParams P) {
     const double ew = P.pf * P.ct * P.dw[K];
     const size_t gbase = (size_t)(max(kp, 0) * P.nb + band) * P.nrows;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i) {
+      double gre[16], gim[16], pre[16], pim[16];
+      const int row0 = tl.r0 + wm * 64 + 32 * i + 4 * lh;
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        bool ok[4];
-        size_t gidx[4], o[4];
-        double gre[4], gim[4], pre[4], pim[4];
+      for (int e = 0; e < 16; ++e) {
+        const int grow = tl.site_row0 + min(row0 + 8 * (e >> 2) + (e & 3), tl.ns - 1);
+        const size_t gidx = 2 * (gbase + grow), o = (size_t)K * P.rows_pad + grow;
+        gre[e] = P.grad[gidx];
+        gim[e] = P.grad[gidx + 1];
+        pre[e] = P.psi[o];
+        pim[e] = P.psi[plane + o];
+      }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int row = tl.r0 + wm * 64 + 32 * i + 8 * g + 4 * lh + e;
-          ok[e] = kp >= 0 && row < tl.ns;
-          const int grow = tl.site_row0 + min(row, tl.ns - 1);
-          gidx[e] = 2 * (gbase + grow);
-          o[e] = (size_t)K * P.rows_pad + grow;
-          gre[e] = P.grad[gidx[e]];
-          gim[e] = P.grad[gidx[e] + 1];
-          pre[e] = P.psi[o[e]];
-          pim[e] = P.psi[plane + o[e]];
-        }
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const double vr = (double)yr[i][j][4 * g + e], vi = (double)yi[i][j][4 * g + e];
-          if (ok[e]) {
-            P.grad[gidx[e]] = gre[e] + gw * vr;
-            P.grad[gidx[e] + 1] = gim[e] + gw * vi;
-            colsum[j] += ew * (pre[e] * vr + pim[e] * vi);
-          }
+      for (int e = 0; e < 16; ++e) {
+        const int row = row0 + 8 * (e >> 2) + (e & 3);
+        const int grow = tl.site_row0 + min(row, tl.ns - 1);
+        const size_t gidx = 2 * (gbase + grow);
+        const double vr = (double)yr[i][j][e], vi = (double)yi[i][j][e];
+        if (kp >= 0 && row < tl.ns) {
+          P.grad[gidx] = gre[e] + gw * vr;
+          P.grad[gidx + 1] = gim[e] + gw * vi;
+          colsum[j] += ew * (pre[e] * vr + pim[e] * vi);
         }
       }
+    }
   }
   // reduce the energy partials over the tile's rows (lanes l and l + 32 share a column)
 #pragma unroll
@@ -469,23 +472,25 @@ __global__ __launch_bounds__(256) void bwd_split_kernel(BwdParams P) {
   }
 }
 
-// psi planes [2][K_pad][rows_pad] (FP64, compact site rows) -> bfloat16 planes [4][K_pad][srows]
-// (re hi, re lo, im hi, im lo; site rows in 64-row slots, rowmap[slot row] = compact row or -1)
-__global__ void split_psi_kernel(const double* psi, int rows_pad, long long K_pad,
-                                 const int* rowmap, int srows, __bf16* out) {
-  const long long n = K_pad * srows;
+// psi planes [2][K_pad][rows_pad] (FP64, compact site rows) -> the split GEMM's B operand:
+// bfloat16 hi/lo of re and im in operand tiles with K as the row and the site row (in 64-row
+// slots, rowmap[slot row] = compact row or -1) as the contraction index
+__global__ void split_psi_kernel(const double* psi, int rows_pad, int K_pad, const int* rowmap,
+                                 int srows, __bf16* out) {
+  const long long n = (long long)K_pad * srows;
   const size_t pin = (size_t)K_pad * rows_pad;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
-    const long long K = i / srows;
-    const int r = rowmap[i - K * srows];
-    const double re = r >= 0 ? psi[K * rows_pad + r] : 0.0;
-    const double im = r >= 0 ? psi[pin + K * rows_pad + r] : 0.0;
+    const int K = (int)(i / srows), sr = (int)(i - (long long)K * srows);
+    const int r = rowmap[sr];
+    const double re = r >= 0 ? psi[(size_t)K * rows_pad + r] : 0.0;
+    const double im = r >= 0 ? psi[pin + (size_t)K * rows_pad + r] : 0.0;
     const __bf16 rh = (__bf16)(float)re, ih = (__bf16)(float)im;
-    out[i] = rh;
-    out[n + i] = (__bf16)(float)(re - (double)(float)rh);
-    out[2 * n + i] = ih;
-    out[3 * n + i] = (__bf16)(float)(im - (double)(float)ih);
+    const long long o = h_tile_offset(K, sr, K_pad);
+    out[o] = rh;
+    out[o + 512] = (__bf16)(float)(re - (double)(float)rh);
+    out[o + 1024] = ih;
+    out[o + 1536] = (__bf16)(float)(im - (double)(float)ih);
   }
 }
 
@@ -579,7 +584,9 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
     blk_n[s] = n;
     const int nrt = (n + tm - 1) / tm;
     auto add = [&](int rt, int kt) {
-      tiles.push_back(BwdTile{ctx->site_off[s], rt * tm, n, kt * tn, ptot, nparts + rt, np, srows});
+      // (the split H holds four planes per block element)
+      tiles.push_back(BwdTile{ctx->site_off[s], rt * tm, n, kt * tn, split ? 4 * ptot : ptot,
+                              nparts + rt, np, srows});
     };
     if (split) {
       // blocks of 4 row tiles x 8 column tiles
@@ -646,7 +653,7 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
     if ((e = hipMemcpyAsync(drowmap, rowmap.data(), rowmap.size() * 4, hipMemcpyHostToDevice, st)))
       return e;
     hipLaunchKernelGGL(split_psi_kernel, dim3(4096), dim3(256), 0, st,
-                       (const double*)ctx->psi_site_f64.p, ctx->rows_pad, (long long)Kp, drowmap,
+                       (const double*)ctx->psi_site_f64.p, ctx->rows_pad, ctx->K_pad, drowmap,
                        srows, (__bf16*)ctx->psi_site_bf16.p);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
@@ -680,7 +687,6 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
   B.part = part;
   B.hs_u = hs_u;
   B.hs_o = hs_o;
-  B.hs_plane = ptot;
   B.psis = split ? (const __bf16*)ctx->psi_site_bf16.p : nullptr;
   B.srows = srows;
   B.ntiles = (int)tiles.size();
@@ -695,7 +701,7 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
                                ctx->site_cols_pad / 16, ctx->K_pad / chunk,
                                (const double*)ctx->c_dev.p + t, ctx->Ko_pad / chunk,
                                (const TileDesc*)plan->tiles.p + bt.tile0, bt.ntiles, lam, hu_re,
-                               hu_im, ho_re, ho_im, hs_u, hs_o, ptot, ctx->park.p, st);
+                               hu_im, ho_re, ho_im, hs_u, hs_o, ctx->park.p, st);
       if (e != hipSuccess) return e;
     }
     B.w = wn + (size_t)t * Kp;

@@ -56,8 +56,9 @@ struct Chi0Params {
   double pref;
   int sym;                      // site blocks from their upper triangle (mode 0)
   unsigned char* park;          // per-workgroup space for G_o between the two phases
-  // adjoint modes: with T = 1, write lam * conj(G_u) and lam * conj(G_o), as FP64 planes
-  // (mode 1) or as bfloat16 hi/lo planes re hi, re lo, im hi, im lo (mode 2)
+  // adjoint modes: with T = 1, write lam * conj(G_u) and lam * conj(G_o), as FP64 planes with
+  // the block's row stride (mode 1) or as bfloat16 hi/lo in operand tiles (mode 2,
+  // h_tile_offset)
   const double* lam;
   double* hu_re;
   double* hu_im;
@@ -65,7 +66,6 @@ struct Chi0Params {
   double* ho_im;
   __bf16* hs_u;
   __bf16* hs_o;
-  long long hs_plane;
 };
 
 // x = hi + lo in bfloat16 (hi rounded from x, lo from the remainder), re and im of one
@@ -176,13 +176,17 @@ __global__ void prep_site_kernel(const double* site, int rows_pad, int K_pad, co
     q = site[plane + o] * f;
   };
   if constexpr (PREC == LRS_FP64) {
-    double* d = (double*)base;
+    f64x4 vp, vq;
+#pragma unroll
     for (int s = 0; s < 4; ++s) {
       double p, q;
       val(ch * 16 + 4 * s + (lane >> 4), p, q);
-      d[lane * 4 + s] = p;
-      d[256 + lane * 4 + s] = q;
+      vp[s] = p;
+      vq[s] = q;
     }
+    f64x4* d = (f64x4*)base;
+    d[lane] = vp;
+    d[64 + lane] = vq;
   } else if constexpr (PREC == LRS_FP32) {
     float* d = (float*)base;
     for (int s = 0; s < 8; ++s) {
@@ -193,16 +197,24 @@ __global__ void prep_site_kernel(const double* site, int rows_pad, int K_pad, co
     }
   } else {
     using elem_t = typename std::conditional<PREC == LRS_BF16X2, __bf16, _Float16>::type;
-    elem_t* d = (elem_t*)base;
+    using vec_t = typename std::conditional<PREC == LRS_BF16X2, bf16x8, f16x8>::type;
+    // the slot's 8 values of each plane are 16 contiguous bytes: one store per plane
+    vec_t vph, vpl, vqh, vql;
+#pragma unroll
     for (int e = 0; e < 8; ++e) {
       double p, q;
       val(ch * 16 + 8 * (lane >> 4) + e, p, q);
       const elem_t ph = (elem_t)(float)p, qh = (elem_t)(float)q;
-      d[lane * 8 + e] = ph;
-      d[256 + lane * 8 + e] = (elem_t)(float)(p - (double)(float)ph);
-      d[512 + lane * 8 + e] = qh;
-      d[768 + lane * 8 + e] = (elem_t)(float)(q - (double)(float)qh);
+      vph[e] = ph;
+      vpl[e] = (elem_t)(float)(p - (double)(float)ph);
+      vqh[e] = qh;
+      vql[e] = (elem_t)(float)(q - (double)(float)qh);
     }
+    vec_t* d = (vec_t*)base;
+    d[lane] = vph;
+    d[32 + lane] = vpl;
+    d[64 + lane] = vqh;
+    d[96 + lane] = vql;
   }
 }
 
@@ -749,8 +761,8 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
                 const long long o = obase + off[e];
                 const double hur = l[e] * (double)gr[i][j][e], hui = -l[e] * (double)gi[i][j][e];
                 const double hor = l[e] * (double)or_[e], hoi = -l[e] * (double)oi_[e];
-                const long long ot = o + (long long)dg[e] * (td.ldo - 1);
                 if constexpr (MODE == 1) {
+                  const long long ot = o + (long long)dg[e] * (td.ldo - 1);
                   P.hu_re[o] = hur;
                   P.hu_im[o] = hui;
                   P.ho_re[o] = hor;
@@ -762,11 +774,20 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
                     P.ho_im[ot] = -hoi;
                   }
                 } else {
-                  put_split(P.hs_u, P.hs_plane, o, hur, hui);
-                  put_split(P.hs_o, P.hs_plane, o, hor, hoi);
+                  // (p, r) in the block: row and column offsets of the tile plus the element's
+                  int rr, cc;
+                  elem_rc<PREC>(ln, e, rr, cc);
+                  const int pr = td.m0 + wm * MB * 16 + i * BLK + rr;
+                  const int pc = td.c0 + wn * NB * 16 + j * BLK + cc;
+                  // (block base: out_off counts one value per element, the tiles four)
+                  const long long hb = 4 * (td.out_off - ((long long)td.m0 * td.ldo + td.c0));
+                  const long long ht = hb + h_tile_offset(pr, pc, td.ldo);
+                  put_split(P.hs_u, 512, ht, hur, hui);
+                  put_split(P.hs_o, 512, ht, hor, hoi);
                   if (dg[e] > 0) {
-                    put_split(P.hs_u, P.hs_plane, ot, hur, -hui);
-                    put_split(P.hs_o, P.hs_plane, ot, hor, -hoi);
+                    const long long htt = hb + h_tile_offset(pc, pr, td.ldo);
+                    put_split(P.hs_u, 512, htt, hur, -hui);
+                    put_split(P.hs_o, 512, htt, hor, -hoi);
                   }
                 }
               }
@@ -980,7 +1001,6 @@ hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int
   P.lam = nullptr;
   P.hu_re = P.hu_im = P.ho_re = P.ho_im = nullptr;
   P.hs_u = P.hs_o = nullptr;
-  P.hs_plane = 0;
   switch (prec) {
     case LRS_FP64: return launch_p<LRS_FP64>(variant, grid, P, s);
     case LRS_FP32: return launch_p<LRS_FP32>(variant, grid, P, s);
@@ -994,8 +1014,7 @@ hipError_t launch_green_adjoint(int prec, int grid, const void* a_tiles, int a_n
                                 const void* b_tiles, int b_ncb, int nch, const double* c,
                                 int nch_o, const TileDesc* tiles, int ntiles, const double* lam,
                                 double* hu_re, double* hu_im, double* ho_re, double* ho_im,
-                                void* hs_u, void* hs_o, long long hs_plane, void* park,
-                                hipStream_t s) {
+                                void* hs_u, void* hs_o, void* park, hipStream_t s) {
   Chi0Params P;
   P.park = (unsigned char*)park;
   P.a = (const unsigned char*)a_tiles;
@@ -1018,7 +1037,6 @@ hipError_t launch_green_adjoint(int prec, int grid, const void* a_tiles, int a_n
   P.ho_im = ho_im;
   P.hs_u = (__bf16*)hs_u;
   P.hs_o = (__bf16*)hs_o;
-  P.hs_plane = hs_plane;
   switch (prec) {
     case LRS_FP64: return launch_v<LRS_FP64, 0, 1>(grid, P, s);
     case LRS_BF16X2: return launch_v<LRS_BF16X2, 0, 2>(grid, P, s);

@@ -235,29 +235,6 @@ long long plan_key(int site, int cols, int prec, int variant, int mode) {
   return ((((long long)(site + 1) * 4 + cols) * 8 + prec) * 16 + variant) * 2 + mode;
 }
 
-// Tiles of one site's rows [m0, m1) (site-local, BM-aligned) against its columns, 8 x 8
-// grouped (row tiles fastest inside a group of 8).
-void add_region(std::vector<TileDesc>& out, int a_row0, int nrows, int b_col0, int ncols,
-                long long out_base, int ldo, int bm, int bn) {
-  const int mt = (nrows + bm - 1) / bm, nt = (ncols + bn - 1) / bn;
-  const int GM = 8;
-  for (int g0 = 0; g0 < mt; g0 += GM) {
-    const int gsz = std::min(GM, mt - g0);
-    for (int n = 0; n < nt; ++n)
-      for (int m = g0; m < g0 + gsz; ++m) {
-        TileDesc t;
-        t.a_row0 = a_row0 + m * bm;
-        t.b_col0 = b_col0 + n * bn;
-        t.nrows = std::min(bm, nrows - m * bm);
-        t.ncols = std::min(bn, ncols - n * bn);
-        t.out_off = out_base + (long long)m * bm * ldo + (long long)n * bn;
-        t.ldo = ldo;
-        t.pad = 0;
-        out.push_back(t);
-      }
-  }
-}
-
 // Bytes of weighted site operand per 16-row block for nt terms.
 size_t a_bytes_per_rb(const lrs_ctx* ctx, int prec, int nt) {
   return (size_t)nt * (ctx->K_pad / chunk_of(prec)) * tile_bytes(prec);
@@ -357,6 +334,7 @@ lrs_status get_plan(lrs_ctx* ctx, int site, int cols, int prec, int variant, int
         t.out_off = orow * ng + (long long)c * sh.bn;
         t.ldo = ng;
         t.pad = 0;
+        t.m0 = t.c0 = 0;
         tiles.push_back(t);
       });
     } else {
@@ -383,6 +361,8 @@ lrs_status get_plan(lrs_ctx* ctx, int site, int cols, int prec, int variant, int
           t.out_off = site_base[s] - site_base[s0] + (long long)x.m0 * ld + (long long)c * sh.bn;
           t.ldo = ld;
           t.pad = x.m0 - c * sh.bn;
+          t.m0 = x.m0;
+          t.c0 = c * sh.bn;
           tiles.push_back(t);
         });
         i = j;

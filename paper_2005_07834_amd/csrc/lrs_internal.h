@@ -40,6 +40,15 @@ inline int site_block_ld(int n, int mode) {
 inline int chunk_of(int prec) { return prec == LRS_FP32 ? 32 : 16; }
 inline int tile_bytes(int prec) { return is_split(prec) ? 2048 : 4096; }
 inline long long round_up(long long x, long long m) { return (x + m - 1) / m * m; }
+// Split adjoint operand tiles (bfloat16).  A 1 KiB piece holds 32 rows x 16 contraction
+// indices of one plane, lane l's 16 bytes at 16 l being row l%32, indices 8 (l/32) .. +7; the
+// four planes (re hi, re lo, im hi, im lo) of a piece follow each other (4 KiB groups), and
+// groups go contraction-chunk-major.  Element offset of (row p, index r) in a site block of
+// H (ld = the block's padded size, a multiple of 64), plane 0:
+__host__ __device__ inline long long h_tile_offset(int p, int r, int ld) {
+  return (((long long)(r >> 4) * (ld >> 5) + (p >> 5)) << 11) +
+         (((p & 31) + ((r >> 3) & 1) * 32) << 3) + (r & 7);
+}
 
 // One output tile of a chi0 launch.
 struct TileDesc {
@@ -50,8 +59,9 @@ struct TileDesc {
   long long out_off;    // element offset of the tile's (0,0) in the output
   int ldo;              // output leading dimension
   int pad;              // site blocks: first site row - first site column (else 0)
+  int m0, c0;           // site blocks: first row and first column within the block (else 0)
 };
-static_assert(sizeof(TileDesc) == 32, "TileDesc layout");
+static_assert(sizeof(TileDesc) == 40, "TileDesc layout");
 
 // Tile shape of one kernel instantiation.
 struct TileShape {
@@ -196,14 +206,13 @@ hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int
                        int nch_o, const TileDesc* tiles, int ntiles, double* out, double pref,
                        int sym, void* park, hipStream_t s);
 // adjoint Green's functions of one term on site blocks: prec LRS_FP64 writes Hu, Ho as FP64
-// planes (hu_re, hu_im, ho_re, ho_im); LRS_BF16X2 writes each as four bfloat16 planes
-// (re hi, re lo, im hi, im lo; plane stride hs_plane elements) at hs_u, hs_o
+// planes (hu_re, hu_im, ho_re, ho_im; row stride ld); LRS_BF16X2 writes each at hs_u, hs_o
+// as bfloat16 hi/lo in the split adjoint GEMM's operand tiles (h_tile_offset)
 hipError_t launch_green_adjoint(int prec, int grid, const void* a_tiles, int a_nrb,
                                 const void* b_tiles, int b_ncb, int nch, const double* c,
                                 int nch_o, const TileDesc* tiles, int ntiles, const double* lam,
                                 double* hu_re, double* hu_im, double* ho_re, double* ho_im,
-                                void* hs_u, void* hs_o, long long hs_plane, void* park,
-                                hipStream_t s);
+                                void* hs_u, void* hs_o, void* park, hipStream_t s);
 
 // lrs_api.cpp (shared with the adjoint)
 lrs_status plan_for(lrs_ctx* ctx, int site, int cols, int prec, int variant, int mode,
