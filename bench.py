@@ -37,7 +37,7 @@ def kernel_source_sha():
     """Hash of the sources that fix the chi0 launch's memory traffic (kernel, operand layout,
     tile order)."""
     h = hashlib.sha256()
-    for f in ("chi0.hip", "pack.hip", "lrs_api.cpp", "lrs_internal.h"):
+    for f in ("chi0.hip", "ring.h", "pack.hip", "lrs_api.cpp", "lrs_internal.h"):
         with open(os.path.join(ROOT, "paper_2005_07834_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
