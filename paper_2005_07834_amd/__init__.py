@@ -228,6 +228,8 @@ class Context:
         return g
 
     def chi0_backward(self, dL_dchi0_ss, prec=FP64):
+        """dL/dE [nk, nb] and dL/dpsi_site (complex) from dL/dchi0 on the site blocks; prec
+        FP64 or BF16X2 (split products, relative error of order 1e-5)."""
         if isinstance(prec, str):
             prec = PREC_NAMES[prec]
         dE = torch.empty((self.nk, self.nb), dtype=torch.float64, device=self.device)

@@ -1,4 +1,4 @@
-// Adjoint of chi0 on site x site blocks (FP64).
+// Adjoint of chi0 on site x site blocks, in FP64 or with split bfloat16 products.
 //
 // With P_f = -2 s / N_k^2, Lambda = dL/dchi0 (symmetrised: chi0 on a square block is symmetric)
 // and per term l the weighted Green's functions G_o^l, G_u^l of the forward pass,
@@ -6,11 +6,11 @@
 //   dL/dpsi_K (K unoccupied) = 2 P_f sum_l c_l beta_l(K)  [ (Lambda o conj(G_o^l)) psi_K ]
 //   dL/de_K = P_f sum_l c_l (d weight_l(K)/d e_K) Re[ psi_K^H (Lambda o conj(G^l)) psi_K ]
 // (complex gradients as dL/dRe + i dL/dIm; mu and the nodes held fixed).  Each term's G's are
-// recomputed on the matrix cores (the chi0 kernel in its adjoint mode writes
-// Lambda o conj(G) directly); the products with psi run as a complex FP64 MFMA GEMM whose
-// epilogue accumulates the orbital gradient and per-row-tile energy partials.  Every output
-// element has one owner per launch and launches are ordered, so results are bitwise
-// reproducible.
+// recomputed on the matrix cores (the chi0 kernel in an adjoint mode writes
+// Lambda o conj(G) directly); the products with psi run as a complex MFMA GEMM (FP64, or
+// bfloat16 hi + lo with FP32 accumulation) whose epilogue accumulates the orbital gradient and
+// per-row-tile energy partials in FP64.  Every output element has one owner per launch and
+// launches are ordered, so results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
