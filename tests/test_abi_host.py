@@ -64,3 +64,16 @@ def test_null_context_is_rejected():
     assert P.lib.lrs_compute_chi0(None, -1, 0, 0, None) == P.LRS_EINVAL
     assert P.lib.lrs_set_orbitals(None, 1, 2, 1, 2, None, 0.0, 0.0, None, 0, 0.0) == P.LRS_EINVAL
     assert P.lib.lrs_tune(None, 0) == P.LRS_EINVAL
+
+
+def test_binding_argument_counts_match_header():
+    """Every binding's argument list has as many entries as the header declaration."""
+    import paper_2005_07834_amd as P
+    src = open(os.path.join(ROOT, "include", "lrs.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    decls = dict(re.findall(r"\b(lrs_[A-Za-z0-9_]+)\s*\(([^)]*)\)\s*;", src))
+    for name, _, args in P.SIGNATURES:
+        assert name in decls, name
+        params = decls[name].strip()
+        n = 0 if params in ("", "void") else params.count(",") + 1
+        assert n == len(args), f"{name}: header {n} arguments, binding {len(args)}"
