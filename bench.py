@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--gamma", action="store_true", help="Gamma-only k-set (precision workload)")
     ap.add_argument("--prec", default="bf16x2", choices=list(PEAKS_TFLOPS))
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-fp16", action="store_true",
+                    help="skip the one FP16X2 launch run beside a BF16X2 bench")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-prec", default="auto", choices=["auto", "fp64", "bf16x2"],
@@ -202,6 +204,16 @@ def main():
         log(f"fp64 chi0 kernel {ms64:.1f} ms")
     else:
         got64 = got_low if prec == "fp64" else None
+    # the FP16 split variant once on the same launch, for comparison with BF16
+    fp16 = {}
+    got16 = None
+    if prec == "bf16x2" and not args.no_fp16:
+        ctx.make_quadrature(P.QUAD_TIME, w.n_terms, 0.0)
+        ctx.chi0(-1, P.COLS_GRID, "fp16x2", out=out_grid)
+        ms16 = ctx.last_kernel_ms()
+        got16 = out_grid[torch.as_tensor(rows, device=dev), torch.as_tensor(cols, device=dev)].cpu().numpy()
+        fp16 = dict(kernel_ms=ms16, entries_per_s=entries / (ms16 / 1e3))
+        log(f"fp16x2 chi0 kernel {ms16:.1f} ms")
     # the split adjoint against the FP64 adjoint on the last step's dL/dchi0
     adjoint = None
     if not args.no_adjoint:
@@ -258,6 +270,8 @@ def main():
         if got64 is not None:
             errs["fp64_vs_exact"] = rel(got64, ex)
             errs["fp64_vs_same_quadrature"] = rel(got64, qq)
+        if got16 is not None:
+            errs["fp16x2_vs_exact"] = rel(got16, ex)
         errs["quadrature_vs_exact"] = rel(qq, ex)
         errs["entries_compared"] = int(ns)
         log("errors", errs)
@@ -291,6 +305,7 @@ def main():
         "cpu_baseline": cpu,
         "chi0_kernel_entries_per_s": entries / (kern_ms / 1e3),
         "fp64_path": fp64,
+        "fp16x2_path": fp16,
         "speedup_vs_fp64": (fp64["kernel_ms"] / kern_ms) if fp64 else None,
         "rel_err": errs,
         "adjoint": adjoint,

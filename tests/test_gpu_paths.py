@@ -246,6 +246,41 @@ def test_batching_uneven_sites(P):
             os.environ["LRS_SITE_OPERAND_BYTES"] = old
 
 
+def test_batching_adjoint(P):
+    """The adjoint over 64 uneven sites (6 terms, a seeded dL/dchi0): split products against
+    FP64, and the split result unchanged bit for bit when a small operand budget cuts the
+    Green's-function launches into many batches."""
+    w = workload("batching", with_grid=False, device="cuda")
+    n = 6
+    s = oracle_scale(w, n)
+    ctx = make_ctx(P, w, n, s, grid=False)
+    tot = sum(x.npts ** 2 for x in w.sites)
+    g = torch.Generator(device="cuda").manual_seed(29)
+    lam = torch.randn(tot, generator=g, dtype=torch.float64, device="cuda")
+    say(f"batching adjoint: {len(w.sites)} sites, {tot} block entries")
+    dE64, dp64 = ctx.chi0_backward(lam, P.FP64)
+    dEs, dps = ctx.chi0_backward(lam, P.BF16X2)
+    eE = (dEs - dE64).abs().max().item() / dE64.abs().max().item()
+    eP = (dps - dp64).abs().max().item() / dp64.abs().max().item()
+    say(f"  split vs FP64: dE {eE:.2e} dpsi {eP:.2e}")
+    assert eE < 1e-4 and eP < 1e-4
+    ctx.close()
+    old = os.environ.get("LRS_SITE_OPERAND_BYTES")
+    os.environ["LRS_SITE_OPERAND_BYTES"] = str(64 << 20)
+    try:
+        ctx2 = make_ctx(P, w, n, s, grid=False)
+        dEb, dpb = ctx2.chi0_backward(lam, P.BF16X2)
+        say(f"  64 MiB operand budget: max diff dE {(dEb - dEs).abs().max().item():.1e} "
+            f"dpsi {(dpb - dps).abs().max().item():.1e}")
+        assert torch.equal(dEb, dEs) and torch.equal(dpb, dps)
+        ctx2.close()
+    finally:
+        if old is None:
+            os.environ.pop("LRS_SITE_OPERAND_BYTES")
+        else:
+            os.environ["LRS_SITE_OPERAND_BYTES"] = old
+
+
 # ------------------------------------------------------------------ graph capture, tuning
 def test_graph_capture_replay(P):
     """chi0 site x grid (BF16X2) and site x site (FP64) captured into one graph: every
