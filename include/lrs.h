@@ -158,7 +158,9 @@ lrs_status lrs_get_quadrature(const lrs_ctx* ctx, int* nterms, double* c_host, d
  *   LRS_COLS_SITE: chi0_out float64 site blocks [npts_s][npts_s], concatenated over sites.
  * chi0 is real for the static case, so float64 is returned.  Asynchronous.
  * All sites and terms go into one persistent launch per operand batch (a batch holds as many
- * sites' weighted operands as fit LRS_SITE_OPERAND_BYTES, default 24 GiB).
+ * sites' weighted operands as fit LRS_SITE_OPERAND_BYTES, default 24 GiB).  The workgroups of
+ * each XCD wait for each other at every term start (bounded wait; LRS_XCD_SYNC=0 turns it
+ * off), so that they share operand panels in that XCD's L2.
  * Graph capture: once a call has run on a problem (same site, column set and precision), the
  * same call may be captured on the context's stream (e.g. into a HIP graph); under capture it
  * records kernels only, records no timing event, and returns LRS_ESTATE instead of

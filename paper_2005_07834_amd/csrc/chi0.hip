@@ -55,6 +55,7 @@ struct Chi0Params {
   double* out;
   double pref;
   int sym;                      // site blocks from their upper triangle (mode 0)
+  unsigned int* sync;           // per-XCD term counters (stride 16), zero at launch; or null
   unsigned char* park;          // per-workgroup space for G_o between the two phases
   // adjoint modes: with T = 1, write lam * conj(G_u) and lam * conj(G_o), as FP64 planes with
   // the block's row stride (mode 1) or as bfloat16 hi/lo in operand tiles (mode 2,
@@ -624,8 +625,18 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
     return park + (((size_t)(wave * AM + i) * AN + j) * 2 + comp) * 64 + ln;
   };
 
+  // The workgroups of one XCD (b % 8) share their tiles' operand panels in that XCD's L2 only
+  // while they run the same stretch of K.  Left alone they drift apart over the launch, and
+  // the panels are fetched again; with P.sync they meet at every term start: each adds one to
+  // its group's counter and waits (a bounded spin, so a group member that never arrives
+  // delays but cannot stall the launch) until every member with a tile in this round has
+  // arrived.  Member count of a round: the group's tiles that exist.
+  const int grp = blockIdx.x & 7, gsz = G >> 3;
+  unsigned int done = 0;          // this group's term starts before the current tile
   for (long long tau = bslot; tau < P.ntiles; tau += G) {
     const TileDesc td = P.tiles[tau];
+    const long long base = tau - (blockIdx.x >> 3);   // the group's first tile this round
+    const unsigned int members = (unsigned int)max(0LL, min((long long)gsz, P.ntiles - base));
     acc_t gr[AM][AN], gi[AM][AN];
     frag_t fa, fb;
     FragsB<PREC, NB> bfr;
@@ -710,6 +721,18 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
         }
     };
     for (int t = 0; t < P.T; ++t) {
+      if (P.sync) {
+        if (tid == 0) {
+          unsigned int* ctr = P.sync + grp * 16;
+          const unsigned int target = done + (unsigned int)(t + 1) * members;
+          __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          for (int it = 0; it < 4096; ++it) {
+            if (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+            __builtin_amdgcn_s_sleep(4);
+          }
+        }
+        __builtin_amdgcn_s_barrier();
+      }
       zero();
       for (int ch = 0; ch < P.nch_o; ch += S) cycle(ch == 0);
       {
@@ -820,6 +843,7 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
           }
         }
     }
+    done += (unsigned int)P.T * members;
   }
 }
 
@@ -982,9 +1006,10 @@ hipError_t launch_prep_site(int prec, const double* site, int rows_pad, int K_pa
 hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int a_nrb,
                        const void* b_tiles, int b_ncb, int nch, const double* c, int T,
                        int nch_o, const TileDesc* tiles, int ntiles, double* out, double pref,
-                       int sym, void* park, hipStream_t s) {
+                       int sym, unsigned int* sync, void* park, hipStream_t s) {
   Chi0Params P;
   P.sym = sym;
+  P.sync = sync;
   P.park = (unsigned char*)park;
   P.a = (const unsigned char*)a_tiles;
   P.a_nrb = a_nrb;
@@ -1030,6 +1055,7 @@ hipError_t launch_green_adjoint(int prec, int grid, const void* a_tiles, int a_n
   P.out = nullptr;
   P.pref = 1.0;
   P.sym = 0;
+  P.sync = nullptr;
   P.lam = lam;
   P.hu_re = hu_re;
   P.hu_im = hu_im;

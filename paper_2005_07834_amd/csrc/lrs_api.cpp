@@ -468,12 +468,21 @@ lrs_status run_chi0(lrs_ctx* ctx, int site, int cols, int prec, int variant, dou
       grid = (int)std::max<long long>(8, std::min<long long>(grid, round_up(nt, 8)));
     }
     CHECK(park_for(ctx, prec, variant, grid));
+    // the workgroups of each XCD meet at every term start (LRS_XCD_SYNC=0 turns this off);
+    // the counters start from zero in every launch
+    unsigned int* sync = nullptr;
+    const char* se = std::getenv("LRS_XCD_SYNC");
+    if (!se || std::atoi(se) != 0) {
+      CHECK(ensure_buf(ctx, ctx->xcd_sync, 8 * 64, "XCD counters"));
+      sync = (unsigned int*)ctx->xcd_sync.p;
+      HIP_OR_FAIL(ctx, launch_fill_zero(sync, 8 * 64, ctx->stream));
+    }
     if (timed && first) HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev0, ctx->stream));
     first = false;
     HIP_OR_FAIL(ctx, launch_chi0(prec, variant, grid, ctx->a_tiles.p, bt.nrb, b, b_ncb, nch,
                                  (const double*)ctx->c_dev.p, T, ctx->Ko_pad / KC,
                                  (const TileDesc*)plan->tiles.p + bt.tile0, nt, out, pref,
-                                 cols == LRS_COLS_SITE, ctx->park.p, ctx->stream));
+                                 cols == LRS_COLS_SITE, sync, ctx->park.p, ctx->stream));
     if (max_tiles > 0) break;
   }
   if (timed && !first) {
@@ -544,6 +553,7 @@ void lrs_destroy(lrs_ctx* ctx) {
   release(ctx, ctx->adj_work);
   release(ctx, ctx->a_tiles);
   release(ctx, ctx->park);
+  release(ctx, ctx->xcd_sync);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   delete ctx;

@@ -138,6 +138,7 @@ struct lrs_ctx {
   lrs::DevBuf site_tiles[4];      // site points as a column operand (fragment tiles)
   lrs::DevBuf a_tiles;            // weighted site operand tiles of the current batch
   lrs::DevBuf park;               // per-workgroup G_o scratch of the chi0 launches
+  lrs::DevBuf xcd_sync;           // per-XCD term counters of the chi0 launches
   int a_prec = -1, a_version = -1, a_rb0 = -1, a_nrb = -1, a_t0 = -1, a_nt = -1;
   lrs::DevBuf psi_site_f64;       // planar [2][K_pad][rows_pad] (k-major rows) for the adjoint
   lrs::DevBuf psi_site_bf16;      // the same split: bfloat16 [4][K_pad][rows_pad] (re hi, re lo,
@@ -204,7 +205,7 @@ hipError_t launch_prep_site(int prec, const double* site, int rows_pad, int K_pa
 hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int a_nrb,
                        const void* b_tiles, int b_ncb, int nch, const double* c, int T,
                        int nch_o, const TileDesc* tiles, int ntiles, double* out, double pref,
-                       int sym, void* park, hipStream_t s);
+                       int sym, unsigned int* sync, void* park, hipStream_t s);
 // adjoint Green's functions of one term on site blocks: prec LRS_FP64 writes Hu, Ho as FP64
 // planes (hu_re, hu_im, ho_re, ho_im; row stride ld); LRS_BF16X2 writes each at hs_u, hs_o
 // as bfloat16 hi/lo in the split adjoint GEMM's operand tiles (h_tile_offset)
