@@ -168,7 +168,6 @@ def main():
         W, loss = ctx.screen_W(chi_ss, rho=rho, want_loss=True)
         if not args.no_adjoint:
             lam = ctx.screen_W_backward()
-            ctx.make_quadrature(P.QUAD_TIME, w.n_terms, 0.0)
             dE, dpsi = ctx.chi0_backward(lam, adj_prec)
         torch.cuda.synchronize()
         if record:

@@ -48,37 +48,67 @@ void gauss_legendre_01(int n, std::vector<double>& a, std::vector<double>& w) {
   }
 }
 
-// Worst relative error max_D |D * sum_j c_j exp(-D tau_j) - 1| over 512 log-spaced D.
-double time_rule_error(double scale, int n, double dmin, double dmax) {
-  std::vector<double> a, w;
-  gauss_legendre_01(n, a, w);
+// Worst relative error max_D |D * sum_j c_j exp(-D tau_j) - 1| over 512 log-spaced D of the
+// time rule with scale C (tau_j = C a_j / (1 - a_j), c_j = C w_j / (1 - a_j)^2).  The samples
+// are visited extremes first, and the scan stops once the error reaches `stop` (the worst
+// error is a maximum, so the order does not change it).
+namespace {
+constexpr int kGapSamples = 512;
+
+double rule_error(double scale, const std::vector<double>& a, const std::vector<double>& w,
+                  double dmin, double dmax, double stop) {
+  const int n = (int)a.size();
+  std::vector<double> tau(n), c(n);
+  for (int j = 0; j < n; ++j) {
+    tau[j] = scale * a[j] / (1.0 - a[j]);
+    c[j] = scale * w[j] / ((1.0 - a[j]) * (1.0 - a[j]));
+  }
   double worst = 0;
-  const int ns = 512;
-  for (int s = 0; s < ns; ++s) {
-    double d = std::exp(std::log(dmin) + (std::log(dmax) - std::log(dmin)) * s / (ns - 1));
+  for (int i = 0; i < kGapSamples; ++i) {
+    const int smp = i == 0 ? 0 : (i == 1 ? kGapSamples - 1 : i - 1);
+    const double d = std::exp(std::log(dmin) + (std::log(dmax) - std::log(dmin)) * smp /
+                                                   (kGapSamples - 1));
     double k = 0;
-    for (int j = 0; j < n; ++j) {
-      double tau = scale * a[j] / (1.0 - a[j]);
-      double c = scale * w[j] / ((1.0 - a[j]) * (1.0 - a[j]));
-      k += c * std::exp(-d * tau);
-    }
+    for (int j = 0; j < n; ++j) k += c[j] * std::exp(-d * tau[j]);
     worst = std::fmax(worst, std::fabs(d * k - 1.0));
+    if (worst >= stop) break;
   }
   return worst;
 }
+}  // namespace
 
+double time_rule_error(double scale, int n, double dmin, double dmax) {
+  std::vector<double> a, w;
+  gauss_legendre_01(n, a, w);
+  return rule_error(scale, a, w, dmin, dmax, HUGE_VAL);
+}
+
+// Scale C = 10^(j/40) / sqrt(dmin dmax), j = -80..100, with the smallest worst error (ties to
+// the smallest C).  Every tenth j is tried first, so that a good bound is known early; a
+// candidate is dropped as soon as its error passes the best so far (reaches it, for a larger
+// j than the best's), which leaves the choice unchanged.
 double time_auto_scale(double dmin, double dmax, int n) {
-  double g = std::sqrt(dmin * dmax);
-  double best = -1, best_s = 1.0 / g;
-  for (int j = -80; j <= 100; ++j) {
-    double s = std::pow(10.0, j / 40.0) / g;
-    double e = time_rule_error(s, n, dmin, dmax);
-    if (best < 0 || e < best) {
+  std::vector<double> a, w;
+  gauss_legendre_01(n, a, w);
+  const double g = std::sqrt(dmin * dmax);
+  double best = HUGE_VAL;
+  int best_j = 0;
+  bool have = false;
+  auto consider = [&](int j) {
+    const double s = std::pow(10.0, j / 40.0) / g;
+    // a smaller j wins a tie, so it is kept going until it exceeds the best
+    const double stop = !have ? HUGE_VAL : (j < best_j ? std::nextafter(best, HUGE_VAL) : best);
+    const double e = rule_error(s, a, w, dmin, dmax, stop);
+    if (!have || e < best || (e == best && j < best_j)) {
       best = e;
-      best_s = s;
+      best_j = j;
+      have = true;
     }
-  }
-  return best_s;
+  };
+  for (int j = -80; j <= 100; j += 10) consider(j);
+  for (int j = -80; j <= 100; ++j)
+    if ((j + 80) % 10 != 0) consider(j);
+  return std::pow(10.0, best_j / 40.0) / g;
 }
 
 }  // namespace lrs
