@@ -159,8 +159,9 @@ lrs_status lrs_get_quadrature(const lrs_ctx* ctx, int* nterms, double* c_host, d
  * chi0 is real for the static case, so float64 is returned.  Asynchronous.
  * All sites and terms go into one persistent launch per operand batch (a batch holds as many
  * sites' weighted operands as fit LRS_SITE_OPERAND_BYTES, default 24 GiB).  The workgroups of
- * each XCD wait for each other at every term start (bounded wait; LRS_XCD_SYNC=0 turns it
- * off), so that they share operand panels in that XCD's L2.
+ * each XCD wait for each other at every term start (a bounded wait of at most about 0.5 ms),
+ * so that they share operand panels in that XCD's L2; LRS_XCD_SYNC=0 turns this off, which
+ * suits launches that share the GPU with other kernels.
  * Graph capture: once a call has run on a problem (same site, column set and precision), the
  * same call may be captured on the context's stream (e.g. into a HIP graph); under capture it
  * records kernels only, records no timing event, and returns LRS_ESTATE instead of
@@ -189,7 +190,8 @@ lrs_status lrs_screen_W_backward(lrs_ctx* ctx, const double* dL_dW, double* dL_d
  * in FP64; LRS_BF16X2 recomputes G and forms the products with psi in split bfloat16 (hi + lo,
  * FP32 accumulation; relative error of order 1e-5), with the gradient accumulation in FP64.
  * Other precisions: LRS_EUNSUPPORTED.  Requires terms from lrs_make_quadrature.
- * dL_dpsi_grid must be NULL (site blocks do not use grid orbitals).  Synchronous. */
+ * dL_dpsi_grid must be NULL (site blocks do not use grid orbitals).  Synchronous; under stream
+ * capture it returns LRS_ESTATE. */
 lrs_status lrs_compute_chi0_backward(lrs_ctx* ctx, int cols, int prec, const double* dL_dchi0,
                                      double* dL_dE, void* dL_dpsi_site, void* dL_dpsi_grid);
 

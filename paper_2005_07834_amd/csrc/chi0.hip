@@ -726,7 +726,7 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
           unsigned int* ctr = P.sync + grp * 16;
           const unsigned int target = done + (unsigned int)(t + 1) * members;
           __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          for (int it = 0; it < 4096; ++it) {
+          for (int it = 0; it < 512; ++it) {   // at most about half a millisecond
             if (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
             __builtin_amdgcn_s_sleep(4);
           }

@@ -993,6 +993,11 @@ lrs_status lrs_compute_chi0_backward(lrs_ctx* ctx, int cols, int prec, const dou
   if (!dL_dchi0 || !dL_dE || !dL_dpsi_site) return fail(ctx, LRS_EINVAL, "missing gradient buffers");
   if (!ctx->quad.has_deriv) return fail(ctx, LRS_EUNSUPPORTED, "generic terms carry no energy derivative");
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_OR_FAIL(ctx, hipStreamIsCapturing(ctx->stream, &cs));
+  if (cs != hipStreamCaptureStatusNone)
+    return fail(ctx, LRS_ESTATE, "the backward pass copies host tables and synchronises; it "
+                "cannot be captured");
   hipError_t e = launch_chi0_backward(ctx, prec, dL_dchi0, dL_dE, (double*)dL_dpsi_site);
   if (e == hipErrorOutOfMemory) return fail(ctx, LRS_ENOMEM, "adjoint workspace");
   if (e != hipSuccess) return fail(ctx, LRS_EDEVICE, "chi0 backward: %s", hipGetErrorString(e));

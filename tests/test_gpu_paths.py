@@ -323,7 +323,8 @@ def test_graph_capture_replay(P):
 
 def test_capture_without_warmup_is_refused(P):
     """Capturing a call whose plan is not built yet returns LRS_ESTATE (nothing is allocated
-    or launched under capture)."""
+    or launched under capture); so does capturing the backward pass, which copies host tables
+    and synchronises."""
     w = workload("tiny")
     n = w.n_terms
     s = oracle_scale(w, n)
@@ -331,21 +332,23 @@ def test_capture_without_warmup_is_refused(P):
     with torch.cuda.stream(st):
         ctx = make_ctx(P, w, n, s)
         out = torch.empty((w.nrows, w.ngrid ** 3), dtype=torch.float64, device="cuda")
+        lam = torch.zeros(w.nrows ** 2, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    err = None
-    with torch.cuda.stream(st):
-        g.capture_begin()
-        try:
-            ctx.chi0(-1, P.COLS_GRID, "fp32", out=out)
-        except P.LrsError as e:
-            err = e
-        finally:
-            g.capture_end()
-    assert err is not None and err.status == P.LRS_ESTATE
-    ei = type("E", (), {"value": err})
-    say(f"  refused: {ei.value}")
-    torch.cuda.synchronize()
+    for what, call in [("chi0 without a plan", lambda: ctx.chi0(-1, P.COLS_GRID, "fp32", out=out)),
+                       ("chi0 backward", lambda: ctx.chi0_backward(lam))]:
+        g = torch.cuda.CUDAGraph()
+        err = None
+        with torch.cuda.stream(st):
+            g.capture_begin()
+            try:
+                call()
+            except P.LrsError as e:
+                err = e
+            finally:
+                g.capture_end()
+        assert err is not None and err.status == P.LRS_ESTATE
+        say(f"  {what} refused: {err}")
+        torch.cuda.synchronize()
     ctx.close()
 
 
