@@ -208,7 +208,8 @@ def test_split_adjoint_matches_fp64(P):
 def test_batching_uneven_sites(P):
     """64 sites with uneven radial x angular grids, 2x2x2 k, 28 terms: all site x site blocks
     in one call (persistent launches over operand batches), sampled against the oracle in
-    BF16X2 and FP64; a much smaller operand budget (more batches) gives the same result."""
+    BF16X2, FP32 and FP64; the BF16X2 call captured into a HIP graph replays to the same bits;
+    a much smaller operand budget (more batches) gives the same result."""
     w = workload("batching", with_grid=False, device="cuda")
     n = w.n_terms
     s = oracle_scale(w, n)
@@ -220,16 +221,32 @@ def test_batching_uneven_sites(P):
     ps_c = w.psi_site[:, :, torch.as_tensor(cols, device="cuda")].cpu().numpy()
     terms = cz.terms_for(w.energies, w.nocc, "time", n, s)
     ref = cz.chi0_quad_entries(ps_r, ps_c, w.nocc, 2, *terms)
-    ctx = make_ctx(P, w, n, s, grid=False)
-    fidx = torch.as_tensor(flat, device="cuda")
-    for prec, tol in [("bf16x2", 1e-4), ("fp64", 1e-12)]:
-        out = ctx.chi0(-1, P.COLS_SITE, prec)
-        got = out[fidx].cpu().numpy()
-        say(f"  {prec}: {ctx.last_kernel_ms():.1f} ms, rel err {rel(got, ref):.3e}")
-        assert rel(got, ref) < tol
-        if prec == "bf16x2":
-            base = out.clone()
-    del out
+    st = torch.cuda.Stream()   # the context enqueues on st, which the graph captures
+    with torch.cuda.stream(st):
+        ctx = make_ctx(P, w, n, s, grid=False)
+        fidx = torch.as_tensor(flat, device="cuda")
+        for prec, tol in [("bf16x2", 1e-4), ("fp32", 1e-5), ("fp64", 1e-12)]:
+            out = ctx.chi0(-1, P.COLS_SITE, prec)
+            got = out[fidx].cpu().numpy()
+            say(f"  {prec}: {ctx.last_kernel_ms():.1f} ms, rel err {rel(got, ref):.3e}")
+            assert rel(got, ref) < tol
+            if prec == "bf16x2":
+                base = out.clone()
+        del out
+        gout = torch.empty_like(base)
+    torch.cuda.synchronize()
+    # the whole batched BF16X2 call in a graph
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=st):
+        ctx.chi0(-1, P.COLS_SITE, "bf16x2", out=gout)
+    for i in range(2):
+        gout.fill_(3.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        say(f"  graph replay {i}: equal {torch.equal(gout, base)}")
+        assert torch.equal(gout, base)
+    del g, gout
     ctx.close()
     old = os.environ.get("LRS_SITE_OPERAND_BYTES")
     os.environ["LRS_SITE_OPERAND_BYTES"] = str(1 << 30)
