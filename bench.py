@@ -266,6 +266,7 @@ def main():
             return float(np.abs(a - b).max() / np.abs(b).max())
         errs[f"{prec}_vs_exact"] = rel(got_low, ex)
         errs[f"{prec}_vs_same_quadrature"] = rel(got_low, qq)
+        errs[f"{prec}_vs_exact_frobenius"] = float(np.linalg.norm(got_low - ex) / np.linalg.norm(ex))
         if got64 is not None:
             errs["fp64_vs_exact"] = rel(got64, ex)
             errs["fp64_vs_same_quadrature"] = rel(got64, qq)
@@ -296,6 +297,7 @@ def main():
                               else "no adjoint")},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
+                     "traffic_gb_per_s": traffic / (kern_ms / 1e3) / 1e9 if traffic else None,
                      "executed_mfma_tflops": achieved * exec_factor,
                      "executed_frac": achieved * exec_factor / peak,
                      "kernel": "chi0_kernel (site x grid)", "kernel_ms": kern_ms,
