@@ -250,16 +250,17 @@ class Context:
 
 
 class Chi0Fn(torch.autograd.Function):
-    """chi0 on the site x site blocks (FP64 path) as a differentiable function of the band
-    energies and the site orbitals: Eq. chi1 with the imaginary-time quadrature.
+    """chi0 on the site x site blocks as a differentiable function of the band energies and
+    the site orbitals: Eq. chi1 with the imaginary-time quadrature.
 
-    ``Chi0Fn.apply(energies, psi_site, ctx, nocc, sites, nnodes, scale)`` sets the context's
-    orbitals (no grid), sites and quadrature, and returns the flat site-block layout.  The
-    backward pass runs the library's adjoint (Green's functions recomputed per term) and
-    returns dL/de [nk, nb] and dL/dpsi_site (complex, dL/dRe + i dL/dIm).  The nodes and mu
-    are held fixed: pass ``scale > 0`` so the node set does not depend on the energies.  If
-    the context was given other inputs since the forward pass, the backward pass sets the
-    forward's inputs again first.
+    ``Chi0Fn.apply(energies, psi_site, ctx, nocc, sites, nnodes, scale[, prec])`` sets the
+    context's orbitals (no grid), sites and quadrature, and returns the flat site-block layout
+    computed in ``prec`` (FP64 by default).  The backward pass runs the library's adjoint
+    (Green's functions recomputed per term; split products when ``prec`` is BF16X2, FP64
+    otherwise) and returns dL/de [nk, nb] and dL/dpsi_site (complex, dL/dRe + i dL/dIm).  The
+    nodes and mu are held fixed: pass ``scale > 0`` so the node set does not depend on the
+    energies.  If the context was given other inputs since the forward pass, the backward pass
+    sets the forward's inputs again first.
     """
 
     @staticmethod
@@ -269,13 +270,17 @@ class Chi0Fn(torch.autograd.Function):
         lctx.make_quadrature(QUAD_TIME, nnodes, scale)
 
     @staticmethod
-    def forward(fctx, energies, psi_site, lctx, nocc, sites, nnodes, scale):
+    def forward(fctx, energies, psi_site, lctx, nocc, sites, nnodes, scale, *prec):
+        p = prec[0] if prec else FP64
+        p = PREC_NAMES[p] if isinstance(p, str) else p
         args = (energies.detach() if isinstance(energies, torch.Tensor) else energies,
                 psi_site.detach(), nocc, sites, nnodes, scale)
         Chi0Fn._setup(lctx, *args)
-        out = lctx.chi0(-1, COLS_SITE, FP64)
+        out = lctx.chi0(-1, COLS_SITE, p)
         fctx.lctx = lctx
         fctx.args = args
+        fctx.prec = BF16X2 if p == BF16X2 else FP64
+        fctx.nextra = len(prec)
         fctx.version = lctx.orb_version
         fctx.e_like = (energies.device, energies.dtype) if isinstance(energies, torch.Tensor) \
             else (torch.device("cpu"), torch.float64)
@@ -287,9 +292,9 @@ class Chi0Fn(torch.autograd.Function):
         if lctx.orb_version != fctx.version:
             Chi0Fn._setup(lctx, *fctx.args)
             fctx.version = lctx.orb_version
-        dE, dpsi = lctx.chi0_backward(g)
+        dE, dpsi = lctx.chi0_backward(g, fctx.prec)
         return (dE.to(device=fctx.e_like[0], dtype=fctx.e_like[1]), dpsi,
-                None, None, None, None, None)
+                None, None, None, None, None) + (None,) * fctx.nextra
 
 
 class ScreenWFn(torch.autograd.Function):

@@ -89,16 +89,20 @@ def test_autograd_gradcheck_tiny(P):
                                     fast_mode=True)
 
 
-def test_autograd_matches_oracle_tiny(P):
+@pytest.mark.parametrize("prec,tol_l,tol_g", [(None, 1e-12, 1e-9), ("bf16x2", 1e-4, 1e-4)])
+def test_autograd_matches_oracle_tiny(P, prec, tol_l, tol_g):
+    """Loss and gradients through Chi0Fn and ScreenWFn against the oracle: the FP64 path (the
+    default), and the split path (BF16X2 forward and adjoint products)."""
     w = workload("tiny")
     n = w.n_terms
     s = oracle_scale(w, n)
-    say("autograd gradients vs oracle, tiny")
+    say(f"autograd gradients vs oracle, tiny ({prec or 'fp64'})")
     ctx = P.Context(0)
     E = torch.tensor(w.energies, dtype=torch.float64, requires_grad=True)
     psi = w.psi_site.to("cuda").clone().requires_grad_(True)
     rho = torch.as_tensor(w.rho_test, device="cuda")
-    chi = P.Chi0Fn.apply(E, psi, ctx, w.nocc, w.sites, n, s)
+    extra = () if prec is None else (prec,)
+    chi = P.Chi0Fn.apply(E, psi, ctx, w.nocc, w.sites, n, s, *extra)
     W, loss = P.ScreenWFn.apply(chi, ctx, rho)
     loss.sum().backward()
     L_ref, dE_ref, dpsi_ref = gr.loss_and_grads(w.psi_site.numpy(), w.energies, w.nocc, 2,
@@ -107,7 +111,7 @@ def test_autograd_matches_oracle_tiny(P):
     eE = rel(E.grad.numpy(), dE_ref)
     ep = rel(psi.grad.cpu().numpy(), dpsi_ref)
     say(f"  loss {eL:.2e} dE {eE:.2e} dpsi {ep:.2e}")
-    assert eL < 1e-12 and eE < 1e-9 and ep < 1e-9
+    assert eL < tol_l and eE < tol_g and ep < tol_g
 
 
 def test_differentiation_workload_fd_and_oracle(P):
