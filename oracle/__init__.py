@@ -18,6 +18,8 @@ screen      spherical-basis projection, Coulomb matrix and the dielectric solve
             W = (1 - v chi0)^-1 v of Sec. VI.E, and a test-charge loss.
 grads       reference gradients of that loss with respect to band energies and
             site orbitals (exact denominators or quadrature kernel).
+project     orbitals at arbitrary points from plane-wave coefficients by the phase
+            matrix (Eq. bloch, the direct method of Sec. VI's projection step).
 
 Parity status: every function here is pinned by tests in
 ``tests/test_oracle_*.py`` (closed forms, invariants, brute force, finite

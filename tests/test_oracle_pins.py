@@ -334,3 +334,74 @@ def test_quadrature_gradients_finite_differences():
         Em[k, b] -= h
         fd = (Lq(Ep, ps) - Lq(Em, ps)) / (2 * h)
         assert abs(fd - dE[k, b]) < 1e-6 * np.abs(dE).max()
+
+
+# ------------------------------------------------------------------ orbital projection
+from oracle import project as pj  # noqa: E402
+
+
+def _random_pw(rng, a, nmax, nb, nk=1):
+    n = np.stack(np.meshgrid(*[np.arange(-nmax, nmax + 1)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    gvec = n * (2 * np.pi / a)
+    coef = rng.normal(size=(nk, nb, len(n))) + 1j * rng.normal(size=(nk, nb, len(n)))
+    coef /= np.linalg.norm(coef, axis=2, keepdims=True)       # unit norm over the cell
+    return n, gvec, coef
+
+
+def test_projection_matches_inverse_fft_on_grid_points():
+    """At the points of an N^3 grid, sum_G C(G) e^{i(k+G).x} is N^3 e^{ik.x} times the inverse
+    FFT of C placed at G mod N (numpy.fft), for k off Gamma too."""
+    rng = np.random.default_rng(31)
+    a, N, nmax = 7.0, 12, 3
+    n, gvec, coef = _random_pw(rng, a, nmax, nb=3, nk=2)
+    kpts = np.array([[0.0, 0.0, 0.0], [0.5, -0.25, 0.5]]) * (2 * np.pi / a)
+    j = np.stack(np.meshgrid(*[np.arange(N)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    x = j * (a / N)
+    psi = pj.project(coef, kpts, gvec, x, a ** 3)
+    for ik in range(2):
+        for b in range(3):
+            box = np.zeros((N, N, N), dtype=np.complex128)
+            box[n[:, 0] % N, n[:, 1] % N, n[:, 2] % N] = coef[ik, b]
+            ref = np.fft.ifftn(box).reshape(-1) * N ** 3 * np.exp(1j * (x @ kpts[ik]))
+            ref /= np.sqrt(a ** 3)
+            assert np.abs(psi[ik, b] - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_projection_bloch_and_parseval():
+    """psi(r + a e_d) = e^{i k_d a} psi(r) for each lattice direction, and the grid sum of
+    |psi|^2 dV equals sum_G |C|^2 = 1 when the grid resolves every G."""
+    rng = np.random.default_rng(32)
+    a, nmax = 6.5, 2
+    n, gvec, coef = _random_pw(rng, a, nmax, nb=2)
+    k = np.array([0.3, -0.2, 0.45]) * (2 * np.pi / a)
+    r = rng.uniform(-3, 9, size=(17, 3))
+    psi = pj.project(coef, k[None], gvec, r, a ** 3)[0]
+    for d in range(3):
+        sh = r.copy()
+        sh[:, d] += a
+        psi_t = pj.project(coef, k[None], gvec, sh, a ** 3)[0]
+        assert np.abs(psi_t - np.exp(1j * k[d] * a) * psi).max() < 1e-12
+    N = 2 * nmax + 2
+    j = np.stack(np.meshgrid(*[np.arange(N)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    pg = pj.project(coef, k[None], gvec, j * (a / N), a ** 3)[0]
+    norm = (np.abs(pg) ** 2).sum(1) * (a / N) ** 3
+    assert np.abs(norm - 1.0).max() < 1e-12
+
+
+def test_projection_explicit_loops():
+    """Two bands, a handful of plane waves and points, by explicit loops over G."""
+    import cmath
+    rng = np.random.default_rng(33)
+    gvec = rng.normal(size=(5, 3))
+    k = rng.normal(size=3) * 0.1
+    pts = rng.normal(size=(3, 3)) * 2
+    coef = rng.normal(size=(1, 2, 5)) + 1j * rng.normal(size=(1, 2, 5))
+    omega = 11.0
+    got = pj.project(coef, k[None], gvec, pts, omega)
+    for b in range(2):
+        for p in range(3):
+            s = 0j
+            for g in range(5):
+                ph = sum((k[c] + gvec[g, c]) * pts[p, c] for c in range(3))
+                s += coef[0, b, g] * cmath.exp(1j * ph)
+            assert abs(got[0, b, p] - s / math.sqrt(omega)) < 1e-13
