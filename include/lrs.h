@@ -153,6 +153,24 @@ lrs_status lrs_make_quadrature(lrs_ctx* ctx, int kind, int nnodes, double scale)
 lrs_status lrs_get_quadrature(const lrs_ctx* ctx, int* nterms, double* c_host, double* tau_host,
                               double* mu_host, double* scale_host);
 
+/* Orbitals at arbitrary points from plane-wave coefficients (Sec. VI, projecting the wave
+ * functions; Eq. bloch): psi_bk(r) = Omega^-1/2 sum_G C_bk(G) exp(i (k+G).r), by the direct
+ * method: per k the phase matrix P_k(r, G) = exp(i (k+G).r), then psi_k = C_k P_k^T as a
+ * complex FP64 GEMM on the matrix cores.
+ *   kpts_host    float64 [nk][3], Cartesian k (bohr^-1)
+ *   gvec_host    float64 [npw][3], Cartesian G (bohr^-1)
+ *   coef         complex128 [nk][nb][npw] on the device: C_bk(G), unit norm over the cell
+ *   omega        cell volume (bohr^3)
+ *   points_host  float64 [npts][3], Cartesian (bohr)
+ *   psi_out      complex128 [nk][nb][npts] on the device, the layout lrs_set_sites takes.
+ * Uses only the context's device and stream (no orbitals, sites or terms need be set).
+ * Allocates its workspace for the call and synchronises: LRS_ESTATE under stream capture.
+ * LRS_EINVAL for non-positive sizes or omega, LRS_ENONFINITE for non-finite k, G or points,
+ * LRS_ENOMEM if the workspace (16 B x (nb + npts) x npw, padded) does not fit. */
+lrs_status lrs_project_orbitals(lrs_ctx* ctx, int nk, int nb, int npw, const double* kpts_host,
+                                const double* gvec_host, const void* coef, double omega,
+                                int npts, const double* points_host, void* psi_out);
+
 /* chi0 for one site (site >= 0) or all sites concatenated (site = -1), in precision prec.
  *   LRS_COLS_GRID: chi0_out float64 [rows][ngrid], rows = npts of the site (or all sites).
  *   LRS_COLS_SITE: chi0_out float64 site blocks [npts_s][npts_s], concatenated over sites.

@@ -46,6 +46,7 @@ SIGNATURES = [
     ("lrs_screen_W_backward", _I, [_P, _P, _P]),
     ("lrs_compute_chi0_backward", _I, [_P, _I, _I, _P, _P, _P, _P]),
     ("lrs_tune", _I, [_P, _I]),
+    ("lrs_project_orbitals", _I, [_P, _I, _I, _I, _P, _P, _P, _D, _I, _P, _P]),
     ("lrs_last_kernel_ms", _D, [_P]),
 ]
 
@@ -239,6 +240,22 @@ class Context:
                                                   _ptr(dL_dchi0_ss.contiguous()), _ptr(dE),
                                                   _ptr(dpsi), None))
         return dE, dpsi
+
+    def project_orbitals(self, kpts, gvec, coef, omega, points):
+        """Orbitals at `points` (float64 [npts, 3], bohr) from plane-wave coefficients `coef`
+        (complex128 [nk, nb, npw] on this device) with k-points `kpts` [nk, 3] and G vectors
+        `gvec` [npw, 3] (Cartesian, bohr^-1): complex128 [nk, nb, npts] (Eq. bloch)."""
+        kp = _host(kpts, np.float64).reshape(-1, 3)
+        gv = _host(gvec, np.float64).reshape(-1, 3)
+        pt = _host(points, np.float64).reshape(-1, 3)
+        c = _dev(coef, torch.complex128, self.device)
+        nk, nb, npw = c.shape
+        if kp.shape[0] != nk or gv.shape[0] != npw:
+            raise ValueError("kpts and gvec must match coef's [nk, nb, npw]")
+        out = torch.empty((nk, nb, pt.shape[0]), dtype=torch.complex128, device=self.device)
+        self._check(lib.lrs_project_orbitals(self.h, nk, nb, npw, _ptr(kp), _ptr(gv), _ptr(c),
+                                             float(omega), pt.shape[0], _ptr(pt), _ptr(out)))
+        return out
 
     def tune(self, prec):
         if isinstance(prec, str):

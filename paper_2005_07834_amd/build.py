@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(os.path.dirname(HERE), "_build", "obj")
 LIB = os.path.join(HERE, "liblrs.so")
-SOURCES = ["lrs_api.cpp", "quadrature.cpp", "pack.hip", "chi0.hip", "screen.hip", "adjoint.hip"]
+SOURCES = ["lrs_api.cpp", "quadrature.cpp", "pack.hip", "chi0.hip", "screen.hip", "adjoint.hip",
+           "project.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

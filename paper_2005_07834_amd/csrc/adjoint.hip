@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "lrs_internal.h"
+#include "cgemm64.h"
 #include "ring.h"
 
 namespace lrs {
@@ -59,60 +60,38 @@ struct BwdParams {
 };
 
 // Y = H psi for one site: rows p of H (64 per workgroup) x K columns (128 per workgroup),
-// contracted over the site's points r' in chunks of 16, as a complex FP64 GEMM on
-// v_mfma_f64_16x16x4.  The contraction order is free, so lane l of matrix-core step s takes
-// r' = 4 (l/16) + s: its four values of a chunk are then four consecutive r' of one row of H
-// (row-major, stride npad) and of one K's orbital row (planar [K][rows]), and each lane's
-// 32 bytes per plane come straight from those natural layouts as two 16-byte direct-to-LDS
-// loads.  A 16-row (or 16-column) tile of a chunk takes 4 KiB of LDS: [plane][half][lane][16 B],
-// so each fragment read is a conflict-free 16-byte read per lane.  Chunks stream through a
-// two-slot ring (one __shared__ array per slot).
-constexpr int BM = 64, BN = 128, BKC = 16;
-constexpr int BW_WN = 2;                      // waves: 2 (rows) x 2 (columns)
-constexpr int BW_MB = 2, BW_NB = 4;           // 16 x 16 accumulator blocks per wave
-constexpr int BW_AT = BM / 16, BW_BT = BN / 16;
-constexpr int BW_STAGE = (BW_AT + BW_BT) * 4096;
-constexpr int BW_LPW = (BW_AT + BW_BT);       // loads per wave per chunk (one per tile)
+// contracted over the site's points r' in chunks of 16, as a complex FP64 GEMM (cgemm64.h):
+// lane l of matrix-core step s takes r' = 4 (l/16) + s, so both operands come from their
+// natural layouts, H row-major (row stride npad) and psi planar [K][rows].
+constexpr int BM = CG_BM, BN = CG_BN;
+constexpr int BW_MB = CG_MB, BW_NB = CG_NB;
 
 __global__ __launch_bounds__(256) void bwd_gemm_kernel(BwdParams P) {
-  __shared__ __attribute__((aligned(1024))) unsigned char slot0[BW_STAGE];
-  __shared__ __attribute__((aligned(1024))) unsigned char slot1[BW_STAGE];
+  __shared__ __attribute__((aligned(1024))) unsigned char slot0[CG_STAGE];
+  __shared__ __attribute__((aligned(1024))) unsigned char slot1[CG_STAGE];
   __shared__ double red[2][BN];
   const BwdTile tl = P.tiles[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wm = wave / BW_WN, wn = wave % BW_WN;
+  const int wm = wave / CG_WN, wn = wave % CG_WN;
   const bool occ = tl.k0 < P.Ko_pad;
   const size_t plane = (size_t)P.K_pad * P.rows_pad;
   // this wave loads plane (wave / 2), half (wave % 2) of every tile of a chunk
   const int pl = wave >> 1, hf = wave & 1;
   const double* hsrc = (pl == 0 ? (occ ? P.hu_re : P.ho_re) : (occ ? P.hu_im : P.ho_im)) + tl.h_off;
   const int lr = lane & 15, lg = lane >> 4;
-  const double* asrc[BW_AT];
+  const double* asrc[CG_AT];
 #pragma unroll
-  for (int t = 0; t < BW_AT; ++t) {
+  for (int t = 0; t < CG_AT; ++t) {
     // rows past the block read its last row (their results are not stored)
     const int row = min(tl.r0 + 16 * t + lr, tl.npad - 1);
     asrc[t] = hsrc + (size_t)row * tl.npad + 4 * lg + 2 * hf;
   }
-  const double* bsrc[BW_BT];
+  const double* bsrc[CG_BT];
 #pragma unroll
-  for (int t = 0; t < BW_BT; ++t)
+  for (int t = 0; t < CG_BT; ++t)
     bsrc[t] = P.psi + pl * plane + (size_t)(tl.k0 + 16 * t + lr) * P.rows_pad + tl.site_row0 +
               4 * lg + 2 * hf;
-  const int dofs = pl * 2048 + hf * 1024;
-  auto issue = [&](int c, unsigned char* dst) {
-#pragma unroll
-    for (int t = 0; t < BW_AT; ++t)
-      __builtin_amdgcn_global_load_lds(
-          (const void __attribute__((address_space(1)))*)(asrc[t] + c * BKC),
-          (void __attribute__((address_space(3)))*)(dst + t * 4096 + dofs), 16, 0, 0);
-#pragma unroll
-    for (int t = 0; t < BW_BT; ++t)
-      __builtin_amdgcn_global_load_lds(
-          (const void __attribute__((address_space(1)))*)(bsrc[t] + c * BKC),
-          (void __attribute__((address_space(3)))*)(dst + (BW_AT + t) * 4096 + dofs), 16, 0, 0);
-  };
   f64x4 cr[BW_MB][BW_NB], ci[BW_MB][BW_NB];
 #pragma unroll
   for (int i = 0; i < BW_MB; ++i)
@@ -121,75 +100,7 @@ __global__ __launch_bounds__(256) void bwd_gemm_kernel(BwdParams P) {
       cr[i][j] = f64x4{0, 0, 0, 0};
       ci[i][j] = f64x4{0, 0, 0, 0};
     }
-  // fragments of one chunk: value s of a lane is r' = 4 (lane/16) + s
-  struct Frag {
-    f64x4 ar[BW_MB], ai[BW_MB], br[BW_NB], bi[BW_NB];
-  };
-  auto load = [&](const unsigned char* sl, Frag& f) {
-#pragma unroll
-    for (int i = 0; i < BW_MB; ++i) {
-      const unsigned char* t = sl + (wm * BW_MB + i) * 4096 + lane * 16;
-      const double2 r0 = *(const double2*)(t), r1 = *(const double2*)(t + 1024);
-      const double2 i0 = *(const double2*)(t + 2048), i1 = *(const double2*)(t + 3072);
-      f.ar[i] = f64x4{r0.x, r0.y, r1.x, r1.y};
-      f.ai[i] = f64x4{i0.x, i0.y, i1.x, i1.y};
-    }
-#pragma unroll
-    for (int j = 0; j < BW_NB; ++j) {
-      const unsigned char* t = sl + (BW_AT + wn * BW_NB + j) * 4096 + lane * 16;
-      const double2 r0 = *(const double2*)(t), r1 = *(const double2*)(t + 1024);
-      const double2 i0 = *(const double2*)(t + 2048), i1 = *(const double2*)(t + 3072);
-      f.br[j] = f64x4{r0.x, r0.y, r1.x, r1.y};
-      f.bi[j] = f64x4{i0.x, i0.y, i1.x, i1.y};
-    }
-  };
-  auto mma = [&](const Frag& f) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int i = 0; i < BW_MB; ++i)
-#pragma unroll
-        for (int j = 0; j < BW_NB; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.ar[i][s], f.br[j][s], cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.ar[i][s], f.bi[j][s], ci[i][j], 0, 0, 0);
-          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-f.ai[i][s], f.bi[j][s], cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.ai[i][s], f.br[j][s], ci[i][j], 0, 0, 0);
-        }
-  };
-  // Chunk c sits in slot c % 2 with its fragments in register set c % 2.  Per step: barrier
-  // (chunk c+1 landed, chunk c's slot read out), read chunk c+1's fragments, load chunk c+2
-  // into chunk c's slot, matrix-core instructions of chunk c, with the reads and loads
-  // interleaved between them.  Loads past the last chunk repeat it, so every step is one
-  // basic block; an odd chunk count ends with the last chunk's instructions alone.
-  constexpr int kMFMA = 0x008, kVMEM = 0x010, kDSREAD = 0x100;
-  constexpr int NMF = 16 * BW_MB * BW_NB, NDS = 4 * (BW_MB + BW_NB), NVM = BW_LPW;
-  constexpr int R = (NMF - NDS) / (NVM + 1), REST = NMF - NDS - R * NVM;
-  auto sched = [] {
-    sched_pairs<NDS, kMFMA, 1, kDSREAD, 1>();
-    sched_pairs<NVM, kMFMA, R, kVMEM, 1>();
-    __builtin_amdgcn_sched_group_barrier(kMFMA, REST, 0);
-  };
-  const int nch = tl.npad / BKC;
-  Frag fa, fb;
-  issue(0, slot0);
-  issue(min(1, nch - 1), slot1);
-  ring_barrier<0>();
-  load(slot0, fa);
-  int c = 0;
-  for (; c + 2 <= nch; c += 2) {
-    ring_barrier<0>();
-    load(slot1, fb);
-    issue(min(c + 2, nch - 1), slot0);
-    mma(fa);
-    sched();
-    ring_barrier<0>();
-    load(slot0, fa);
-    issue(min(c + 3, nch - 1), slot1);
-    mma(fb);
-    sched();
-  }
-  if (c < nch) mma(fa);
-  ring_barrier<0>();
+  cgemm64_tile(asrc, bsrc, tl.npad / CG_KC, wave, lane, slot0, slot1, cr, ci);
   // epilogue: f64 accumulator element e of lane holds (row 4e + lane/16, col lane%16).  Per
   // accumulator block all loads are issued before the first use (entries outside the site or
   // in K padding read a valid address and store nothing).
