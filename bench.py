@@ -86,6 +86,8 @@ def main():
                     help="skip the one FP16X2 launch run beside a BF16X2 bench")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-projection", action="store_true",
+                    help="skip the plane-wave -> site-point projection timed after the steps")
     ap.add_argument("--adjoint-prec", default="auto", choices=["auto", "fp64", "bf16x2"],
                     help="precision of the adjoint's products (auto: bf16x2 with --prec bf16x2, "
                          "else fp64)")
@@ -226,6 +228,29 @@ def main():
             del dE64, dpsi64
             log("adjoint", adjoint)
         comp.pop("adjoint", None)
+    # the projection of the plane-wave orbitals onto the site points (the step before the
+    # packing), once, outside the timed steps
+    proj = None
+    if not args.no_projection:
+        bd = w.bands
+        coef = torch.stack([c.T for c in bd.coef]).contiguous()
+        gcart = bd.gvec * (2.0 * np.pi / bd.crystal.a)
+        pts = np.concatenate([st.points() for st in w.sites])
+        ctx.project_orbitals(bd.kpts, gcart, coef, bd.crystal.omega, pts)   # warm-up
+        torch.cuda.synchronize()
+        tp = time.time()
+        psi_p = ctx.project_orbitals(bd.kpts, gcart, coef, bd.crystal.omega, pts)
+        torch.cuda.synchronize()
+        pms = (time.time() - tp) * 1e3
+        nk_, nb_, npw_ = coef.shape
+        fl = 8.0 * nk_ * nb_ * npw_ * len(pts)
+        proj = {"call_ms": pms, "nk": nk_, "bands": nb_, "plane_waves": npw_, "points": len(pts),
+                "algorithmic_tflops": fl / (pms / 1e3) / 1e12,
+                "frac_of_fp64_peak": fl / (pms / 1e3) / 1e12 / PEAKS_TFLOPS["fp64"],
+                "rel_err_vs_workload_orbitals":
+                    float((psi_p - w.psi_site).abs().max() / w.psi_site.abs().max())}
+        del psi_p, coef
+        log("projection", proj)
     qd = ctx.get_quadrature()
     ctx.close()
     del out_grid
@@ -310,6 +335,7 @@ def main():
         "speedup_vs_fp64": (fp64["kernel_ms"] / kern_ms) if fp64 else None,
         "rel_err": errs,
         "adjoint": adjoint,
+        "projection": proj,
         "pack_ms": pack_ms,
         "loss": float(loss.sum().item()),
     }
