@@ -14,6 +14,9 @@ Discretised (basis index (L, i), L-major: idx = L * n_rad + i):
     D = diag(u_i)
     W = solve(I - V D X D, V)
 Test-charge loss: rho_L(r_i) = sum_a w_a Y_L(a) rho(r_i a); L = rho_L^T D W D rho_L.
+Induced density and potential of a spherical perturbation (the short-range part of a
+potential partitioned by a shell of charge, Eq. partition):
+    rho = (I - X D V D)^-1 X D v1,   v_ind = V D rho,   v1 in the L = 00 channel.
 
 Real spherical harmonics, orthonormal on the unit sphere, in the order
 L = l^2 + l + m:
@@ -107,3 +110,38 @@ def charge_moments(rho, site, lmax=2):
 def test_charge_loss(W, rho, site, lmax=2) -> float:
     rl = charge_moments(rho, site, lmax) * radial_weights(site, lmax)
     return float(rl @ W @ rl)
+
+
+def shell_potential(radii, q, r_shell):
+    """The short-range part v1 = v_ext - v2 of the partition by a shell of charge
+    (Eq. partition), for v_ext = q / x centred on the site: q (1/r - 1/R_S) inside the shell
+    and zero outside."""
+    r = np.asarray(radii, dtype=np.float64)
+    return np.where(r < r_shell, q * (1.0 / r - 1.0 / r_shell), 0.0)
+
+
+def induced(chi0_ss, site, v1, lmax=2, l0_only=False):
+    """Induced density and potential of a spherical perturbation v1(r_i) (Sec. VI,
+    construction of chi and W):
+        chi = S^-1 chi0 with S = 1 - chi0 v          (discretised chi = (I - X D V D)^-1 X)
+        rho_L(r_i) = sum_j chi_{(L,i),(00,j)} u_j v1_00(r_j),   v1_00 = sqrt(4 pi) v1
+        v_L(r_i)   = sum_j V_L(r_i, r_j) u_j rho_L(r_j)
+    (v1_00 is the Y_00 coefficient of the spherical v1).  l0_only: the paper's default,
+    chi restricted to its 00;00 block.  Returns rho, v as [(L,i)] vectors, L-major (zero
+    outside L = 00 when l0_only)."""
+    X = project(chi0_ss, site, lmax)
+    V = coulomb(site, lmax)
+    d = radial_weights(site, lmax)
+    nr = site.n_rad
+    n = X.shape[0]
+    m = nr if l0_only else n
+    X, V, d = X[:m, :m], V[:m, :m], d[:m]
+    D = np.diag(d)
+    chi = np.linalg.solve(np.eye(m) - X @ D @ V @ D, X)
+    v1vec = np.zeros(m)
+    v1vec[:nr] = math.sqrt(4.0 * math.pi) * np.asarray(v1, dtype=np.float64)
+    rho = chi @ D @ v1vec
+    vind = V @ D @ rho
+    rho_out, v_out = np.zeros(n), np.zeros(n)
+    rho_out[:m], v_out[:m] = rho, vind
+    return rho_out, v_out

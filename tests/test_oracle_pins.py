@@ -405,3 +405,56 @@ def test_projection_explicit_loops():
                 ph = sum((k[c] + gvec[g, c]) * pts[p, c] for c in range(3))
                 s += coef[0, b, g] * cmath.exp(1j * ph)
             assert abs(got[0, b, p] - s / math.sqrt(omega)) < 1e-13
+
+
+# ------------------------------------------------------------------ induced potential
+def test_shell_partition_potential():
+    """v1 + v2 = q / x (Eq. partition): v2 = q/R_S inside the shell, q/x outside."""
+    r = np.array([0.1, 0.5, 1.0, 1.49, 1.5, 2.0, 3.7])
+    q, rs = 1.3, 1.5
+    v1 = sc.shell_potential(r, q, rs)
+    v2 = np.where(r < rs, q / rs, q / r)
+    assert np.abs(v1 + v2 - q / r).max() < 1e-14 * q / r.min()
+    assert np.all(v1[r >= rs] == 0.0) and np.all(v1[r < rs] > 0.0)
+
+
+def test_induced_pins(tiny):
+    """Induced density and potential of a spherical perturbation:
+    - no response (chi0 = 0) gives zero;
+    - v1 + v_ind equals eps^-1 v1, solved with eps = I - V D X D instead of through chi;
+    - a weak response agrees with the Dyson iteration rho = X D (v1 + V D rho);
+    - v1^T D rho <= 0 (chi is negative semidefinite);
+    - an isotropic chi0 responds in L = 00 only, where the l = 0 solve is exact."""
+    w = tiny
+    ps = w.psi_site.numpy()
+    site = w.sites[0]
+    chi = cz.chi0_exact(ps, ps, w.energies, w.nocc)
+    v1 = sc.shell_potential(site.radii, 1.0, 1.2)
+    n = (site.n_rad) * 9
+    r0, z0 = sc.induced(np.zeros_like(chi), site, v1)
+    assert np.abs(r0).max() == 0.0 and np.abs(z0).max() == 0.0
+    rho, vind = sc.induced(chi, site, v1)
+    X = sc.project(chi, site)
+    V = sc.coulomb(site)
+    D = np.diag(sc.radial_weights(site))
+    v1vec = np.zeros(n)
+    v1vec[:site.n_rad] = math.sqrt(4 * math.pi) * v1
+    tot = np.linalg.solve(np.eye(n) - V @ D @ X @ D, v1vec)
+    assert np.abs(v1vec + vind - tot).max() < 1e-12 * np.abs(tot).max()
+    assert v1vec @ D @ rho <= 0.0
+    # weak response: the Dyson series converges
+    small = 0.05 * chi
+    rs_, _ = sc.induced(small, site, v1)
+    Xs = sc.project(small, site)
+    it = np.zeros(n)
+    for _ in range(200):
+        it = Xs @ D @ (v1vec + V @ D @ it)
+    assert np.abs(it - rs_).max() < 1e-12 * np.abs(rs_).max()
+    # isotropic response: only L = 00
+    rr = np.repeat(np.arange(site.n_rad), site.n_ang)
+    iso = -0.2 * np.exp(-np.abs(rr[:, None] - rr[None, :]))
+    full, vf = sc.induced(iso, site, v1)
+    l0, vl0 = sc.induced(iso, site, v1, l0_only=True)
+    assert np.abs(full[site.n_rad:]).max() < 1e-12 * np.abs(full).max()
+    assert np.abs(full - l0).max() < 1e-12 * np.abs(full).max()
+    assert np.abs(vf - vl0).max() < 1e-12 * np.abs(vf).max()
