@@ -196,6 +196,25 @@ lrs_status lrs_compute_chi0(lrs_ctx* ctx, int site, int cols, int prec, double* 
 lrs_status lrs_screen_W(lrs_ctx* ctx, const double* chi0_sitesite, double* W_out,
                         const double* rho_test, double* loss_out);
 
+/* Induced density and potential of a spherical perturbation at every site (Sec. VI,
+ * construction of chi and W; the perturbation is the short-range part of a potential split by
+ * a shell of charge, Eq. partition).  With X, V, D of lrs_screen_W and v1 in the L = 00
+ * channel (its Y_00 coefficient sqrt(4 pi) v1(r_i)):
+ *   rho = (I - X D V D)^-1 X D v1 (= chi v1),   v_ind = V D rho,
+ * computed per site as y = (I - V D X D)^-1 v1 (Gauss-Jordan, FP64), rho = X D y,
+ * v_ind = y - v1.  l0_only != 0 keeps the 00;00 block alone (the paper's default l = 0
+ * response); rho and v_ind are then zero outside L = 00.
+ *   chi0_sitesite  site blocks (layout of LRS_COLS_SITE, all sites), device
+ *   v1_host        float64 [sum n_rad], each site's radial values in site order; or NULL for
+ *                  the short-range part of q/|r - centre| split at the shell radius r_shell:
+ *                  q (1/r - 1/r_shell) for r < r_shell, 0 beyond
+ *   rho_out, v_out float64 [sum n], n = (lmax+1)^2 n_rad per site, L-major, device.
+ * Requires lrs_set_sites.  Synchronous in its host part; LRS_ESTATE under stream capture,
+ * LRS_EUNSUPPORTED when a site has more than 288 basis functions or 256 directions. */
+lrs_status lrs_induced_potential(lrs_ctx* ctx, const double* chi0_sitesite, const double* v1_host,
+                                 double q, double r_shell, int l0_only, double* rho_out,
+                                 double* v_out);
+
 /* Adjoint of lrs_screen_W.  dL_dW float64 [nsites][n][n], or NULL to differentiate
  * sum(loss_out) of the last lrs_screen_W call with rho_test.  Writes
  * dL_dchi0_sitesite (site-block layout) = P^T (D W^T Gbar W^T D) P per site.  Asynchronous. */

@@ -47,6 +47,7 @@ SIGNATURES = [
     ("lrs_compute_chi0_backward", _I, [_P, _I, _I, _P, _P, _P, _P]),
     ("lrs_tune", _I, [_P, _I]),
     ("lrs_project_orbitals", _I, [_P, _I, _I, _I, _P, _P, _P, _D, _I, _P, _P]),
+    ("lrs_induced_potential", _I, [_P, _P, _P, _D, _D, _I, _P, _P]),
     ("lrs_last_kernel_ms", _D, [_P]),
 ]
 
@@ -240,6 +241,18 @@ class Context:
                                                   _ptr(dL_dchi0_ss.contiguous()), _ptr(dE),
                                                   _ptr(dpsi), None))
         return dE, dpsi
+
+    def induced_potential(self, chi0_ss, v1=None, q=1.0, r_shell=1.0, l0_only=False):
+        """(rho_ind, v_ind) [sum n] of a spherical perturbation: `v1` [sum n_rad] radial
+        values, or the short-range part of q/r split at `r_shell` (Eq. partition)."""
+        n = sum(self.nbasis)
+        rho = torch.empty(n, dtype=torch.float64, device=self.device)
+        v = torch.empty(n, dtype=torch.float64, device=self.device)
+        v1h = None if v1 is None else _host(v1, np.float64).reshape(-1)
+        self._check(lib.lrs_induced_potential(self.h, _ptr(chi0_ss.contiguous()), _ptr(v1h),
+                                              float(q), float(r_shell), int(bool(l0_only)),
+                                              _ptr(rho), _ptr(v)))
+        return rho, v
 
     def project_orbitals(self, kpts, gvec, coef, omega, points):
         """Orbitals at `points` (float64 [npts, 3], bohr) from plane-wave coefficients `coef`

@@ -6,6 +6,10 @@
 //   eps = I - V D X D,  W = eps^-1 V                                  (D = diag(u_i))
 // solved per site by Gauss-Jordan elimination with partial pivoting on [eps | V] in FP64.
 // Adjoint: dL/dX = D W^T Gbar W^T D,  dL/dchi0 = P^T (dL/dX) P.
+// Induced density and potential of a spherical perturbation v1 (in the L = 00 channel):
+//   y = (I - V D X D)^-1 v1 (the total potential),  rho = X D y,  v_ind = y - v1,
+// which equal rho = (I - X D V D)^-1 X D v1 = chi D v1 and v_ind = V D rho (push-through);
+// optionally with the 00;00 block alone (the l = 0 response).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -90,15 +94,19 @@ __global__ void eps_kernel(ScreenTabs T, const int2* rows, const double* X, doub
   }
 }
 
-// Gauss-Jordan with partial pivoting on the n x 2n augmented matrix of one site
-__global__ void __launch_bounds__(1024) gauss_jordan_kernel(ScreenTabs T, double* M, double* W_out,
+// Gauss-Jordan with partial pivoting on the augmented matrix of one site (at M + 2 w_off):
+//   mode 0: [eps | V], n x 2n, the right block (W) goes to out + w_out_off[site]
+//   mode 1: [eps | v1], n x (n + 1), the last column (y) goes to out + h_off
+//   mode 2: as 1 on the 00;00 block, n_rad x (n_rad + 1)
+__global__ void __launch_bounds__(1024) gauss_jordan_kernel(ScreenTabs T, double* M, int mode,
+                                                            double* out,
                                                             const long long* w_out_off) {
   __shared__ double fac[288 + 32];
   __shared__ double red_v[1024 / 64];
   __shared__ int red_i[1024 / 64];
   __shared__ int piv_s;
   const SiteMeta m = T.meta[blockIdx.x];
-  const int n = m.n, n2 = 2 * n;
+  const int n = mode == 2 ? m.nrad : m.n, n2 = n + (mode == 0 ? n : 1);
   double* A = M + 2 * m.w_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   for (int col = 0; col < n; ++col) {
@@ -146,10 +154,61 @@ __global__ void __launch_bounds__(1024) gauss_jordan_kernel(ScreenTabs T, double
     }
     __syncthreads();
   }
-  double* W = W_out + w_out_off[blockIdx.x];
-  for (long long it = tid; it < (long long)n * n; it += blockDim.x) {
-    const int r = (int)(it / n), c = (int)(it % n);
-    W[it] = A[(long long)r * n2 + n + c];
+  if (mode == 0) {
+    double* W = out + w_out_off[blockIdx.x];
+    for (long long it = tid; it < (long long)n * n; it += blockDim.x) {
+      const int r = (int)(it / n), c = (int)(it % n);
+      W[it] = A[(long long)r * n2 + n + c];
+    }
+  } else {
+    for (int r = tid; r < n; r += blockDim.x) out[m.h_off + r] = A[(long long)r * n2 + n];
+  }
+}
+
+// augmented [eps | v1] rows of the induced-potential solve: one workgroup per (site, row);
+// l0: the 00;00 block only (rows and columns L = 00).  v1 [sum n_rad]: the radial values.
+__global__ void induced_rows_kernel(ScreenTabs T, const int2* rows, const double* X,
+                                    const double* v1, int l0, double* M) {
+  const int2 rw = rows[blockIdx.x];
+  const SiteMeta m = T.meta[rw.x];
+  const int row = rw.y, R = m.nrad, n = m.n;
+  const int sz = l0 ? R : n;
+  if (row >= sz) return;
+  const int L = row / R, i = row % R, l = l_of(L);
+  const double* r = T.radii + m.rad_off;
+  const double* u = T.u + m.rad_off;
+  const double* x = X + m.w_off;
+  double* out = M + 2 * m.w_off + (long long)row * (sz + 1);
+  for (int c = threadIdx.x; c <= sz; c += blockDim.x) {
+    if (c < sz) {
+      const int j = c % R;
+      double acc = 0;
+      for (int q = 0; q < R; ++q) acc += coulomb_l(l, r[i], r[q]) * u[q] * x[(long long)(L * R + q) * n + c];
+      out[c] = (c == row ? 1.0 : 0.0) - acc * u[j];
+    } else {
+      // the Y_00 coefficient of the spherical v1
+      out[c] = L == 0 ? 2.0 * sqrt(3.14159265358979323846) * v1[m.rad_off + i] : 0.0;
+    }
+  }
+}
+
+// rho = X D y and v_ind = y - v1 for one site (one workgroup per site)
+__global__ void induced_out_kernel(ScreenTabs T, const double* X, const double* y,
+                                   const double* v1, int l0, double* rho, double* vind) {
+  const SiteMeta m = T.meta[blockIdx.x];
+  const int R = m.nrad, n = m.n, sz = l0 ? R : n;
+  const double* x = X + m.w_off;
+  const double* u = T.u + m.rad_off;
+  const double* yy = y + m.h_off;
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    double rr = 0.0, vv = 0.0;
+    if (r < sz) {
+      for (int c = 0; c < sz; ++c) rr += x[(long long)r * n + c] * u[c % R] * yy[c];
+      const double v1r = r < R ? 2.0 * sqrt(3.14159265358979323846) * v1[m.rad_off + r] : 0.0;
+      vv = yy[r] - v1r;
+    }
+    rho[m.h_off + r] = rr;
+    vind[m.h_off + r] = vv;
   }
 }
 
@@ -428,7 +487,7 @@ hipError_t launch_screen_forward(lrs_ctx* ctx, const double* chi0_ss, double* W_
                      chi0_ss, X);
   hipLaunchKernelGGL(eps_kernel, dim3(D.nrows), dim3(256), 0, ctx->stream, D.t, D.rows, X, M);
   hipLaunchKernelGGL(gauss_jordan_kernel, dim3(ctx->nsites), dim3(1024), 0, ctx->stream, D.t, M,
-                     W_out, D.w_out_off);
+                     0, W_out, D.w_out_off);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = hipMemcpyAsync(ctx->W_last.p, W_out, (size_t)H.w_total * 8, hipMemcpyDeviceToDevice,
@@ -472,4 +531,97 @@ hipError_t launch_screen_backward(lrs_ctx* ctx, const double* dL_dW, double* dL_
   return hipGetLastError();
 }
 
+// work layout: X [w_total] | M [2 w_total] | y [n_total] | v1 [sum n_rad]
+static hipError_t launch_induced(lrs_ctx* ctx, const double* chi0_ss, const double* v1_host, int l0,
+                          double* rho_out, double* v_out) {
+  HostTabs H;
+  build_tabs(ctx, H);
+  if (H.max_n > 288) return hipErrorInvalidValue;
+  for (const auto& m : H.meta)
+    if (m.nang > 256) return hipErrorInvalidValue;
+  DevTabs D;
+  hipError_t e = upload_tabs(ctx, H, D);
+  if (e != hipSuccess) return e;
+  const size_t nrad_total = H.radii.size();
+  e = ensure_dev(ctx, ctx->work, (size_t)(3 * H.w_total + H.n_total + nrad_total) * 8);
+  if (e != hipSuccess) return e;
+  double* X = (double*)ctx->work.p;
+  double* M = X + H.w_total;
+  double* y = M + 2 * H.w_total;
+  double* v1 = y + H.n_total;
+  e = hipMemcpyAsync(v1, v1_host, nrad_total * 8, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);   // v1_host may be a temporary
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(project_kernel, dim3(D.nblocks), dim3(256), 0, ctx->stream, D.t, D.blocks,
+                     chi0_ss, X);
+  hipLaunchKernelGGL(induced_rows_kernel, dim3(D.nrows), dim3(256), 0, ctx->stream, D.t, D.rows,
+                     X, v1, l0, M);
+  hipLaunchKernelGGL(gauss_jordan_kernel, dim3(ctx->nsites), dim3(1024), 0, ctx->stream, D.t, M,
+                     l0 ? 2 : 1, y, D.w_out_off);
+  hipLaunchKernelGGL(induced_out_kernel, dim3(ctx->nsites), dim3(256), 0, ctx->stream, D.t, X, y,
+                     v1, l0, rho_out, v_out);
+  return hipGetLastError();
+}
+
 }  // namespace lrs
+
+using namespace lrs;
+
+extern "C" lrs_status lrs_induced_potential(lrs_ctx* ctx, const double* chi0_sitesite,
+                                            const double* v1_host, double q, double r_shell,
+                                            int l0_only, double* rho_out, double* v_out) {
+  if (!ctx) return LRS_EINVAL;
+  ctx->err.clear();
+  if (!ctx->have_sites) {
+    ctx->err = "sites must be set first";
+    return LRS_ESTATE;
+  }
+  if (!chi0_sitesite || !rho_out || !v_out) {
+    ctx->err = "missing argument";
+    return LRS_EINVAL;
+  }
+  std::vector<double> v1(ctx->radii.size());
+  if (v1_host) {
+    for (size_t i = 0; i < v1.size(); ++i) {
+      if (!std::isfinite(v1_host[i])) {
+        ctx->err = "v1 must be finite";
+        return LRS_ENONFINITE;
+      }
+      v1[i] = v1_host[i];
+    }
+  } else {
+    if (!std::isfinite(q) || !(r_shell > 0) || !std::isfinite(r_shell)) {
+      ctx->err = "q must be finite and r_shell positive";
+      return LRS_EINVAL;
+    }
+    // short-range part of q / r after the shell partition: q (1/r - 1/R_S) inside the shell
+    for (size_t i = 0; i < v1.size(); ++i) {
+      const double r = ctx->radii[i];
+      v1[i] = r < r_shell ? q * (1.0 / r - 1.0 / r_shell) : 0.0;
+    }
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipSetDevice(ctx->device) != hipSuccess ||
+      hipStreamIsCapturing(ctx->stream, &cs) != hipSuccess) {
+    ctx->err = "device";
+    return LRS_EDEVICE;
+  }
+  if (cs != hipStreamCaptureStatusNone) {
+    ctx->err = "the induced-potential solve copies host tables; it cannot be captured";
+    return LRS_ESTATE;
+  }
+  const hipError_t e = launch_induced(ctx, chi0_sitesite, v1.data(), l0_only != 0, rho_out, v_out);
+  if (e == hipErrorInvalidValue) {
+    ctx->err = "a site basis exceeds 288 functions or 256 directions";
+    return LRS_EUNSUPPORTED;
+  }
+  if (e == hipErrorOutOfMemory) {
+    ctx->err = "induced-potential workspace";
+    return LRS_ENOMEM;
+  }
+  if (e != hipSuccess) {
+    ctx->err = std::string("induced potential: ") + hipGetErrorString(e);
+    return LRS_EDEVICE;
+  }
+  return LRS_OK;
+}
