@@ -20,6 +20,8 @@ grads       reference gradients of that loss with respect to band energies and
             site orbitals (exact denominators or quadrature kernel).
 project     orbitals at arbitrary points from plane-wave coefficients by the phase
             matrix (Eq. bloch, the direct method of Sec. VI's projection step).
+alda        the ALDA vertex: LDA f_xc by a 5-point difference, its contact matrix in the
+            site basis, and W for the ALDA polarizability (Eq. chi-alda, Eq. kxc_alda).
 
 Parity status: every function here is pinned by tests in
 ``tests/test_oracle_*.py`` (closed forms, invariants, brute force, finite

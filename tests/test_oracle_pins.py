@@ -458,3 +458,64 @@ def test_induced_pins(tiny):
     assert np.abs(full[site.n_rad:]).max() < 1e-12 * np.abs(full).max()
     assert np.abs(full - l0).max() < 1e-12 * np.abs(full).max()
     assert np.abs(vf - vl0).max() < 1e-12 * np.abs(vf).max()
+
+
+# ------------------------------------------------------------------ ALDA vertex
+from oracle import alda as ax  # noqa: E402
+
+
+def test_lda_exchange_kernel_closed_form():
+    """The 5-point difference of the exchange energy n eps_x(n) against its closed-form
+    second derivative -(1/3) (3/pi)^(1/3) n^(-2/3)."""
+    n = np.array([0.2, 0.5, 1.0, 3.0])
+    fd = ax.fxc(n, energy=lambda m: m * ax.eps_x(m))
+    exact = -(1.0 / 3.0) * (3.0 / math.pi) ** (1 / 3) * n ** (-2 / 3)
+    assert np.abs(fd / exact - 1).max() < 1e-5
+
+
+def test_vwn_correlation_limits():
+    """eps_c < 0 and rising to 0 at low density; d eps_c / d ln r_s -> A at high density (the
+    form's logarithmic term)."""
+    rs = np.array([0.5, 1.0, 2.0, 5.0, 10.0, 100.0, 1e4])
+    n = 3.0 / (4.0 * math.pi * rs ** 3)
+    ec = ax.eps_c(n)
+    assert np.all(ec < 0) and np.all(np.diff(ec) > 0) and abs(ec[-1]) < 1e-3
+    r1, r2 = 1e-10, 1e-9
+    n1, n2 = 3.0 / (4.0 * math.pi * r1 ** 3), 3.0 / (4.0 * math.pi * r2 ** 3)
+    slope = (ax.eps_c(n2) - ax.eps_c(n1)) / math.log(r2 / r1)
+    assert abs(slope / ax.VWN_A - 1) < 1e-3
+
+
+def test_fxc_difference_step_and_contact_matrix():
+    """The 0.01 step agrees with a 0.001 step; for a constant f the contact matrix is f I
+    (the Lebedev rule integrates products of l <= 2 harmonics exactly)."""
+    n = np.array([0.2, 0.3, 1.0])
+    assert np.abs(ax.fxc(n) / ax.fxc(n, h=1e-3) - 1).max() < 1e-5
+    site = sx.make_site(np.zeros(3), 3, 26, r_max=2.0)
+    F = ax.contact_matrix(site, np.full(site.npts, -0.7))
+    assert np.abs(F + 0.7 * np.eye(F.shape[0])).max() < 1e-13
+
+
+def test_alda_W_pins(tiny):
+    """W~ through eps (I - (V D + F) X D) agrees with W~ through chi~; a zero kernel gives
+    the RPA W back, and the density's kernel changes it."""
+    w = tiny
+    ps = w.psi_site.numpy()
+    site = w.sites[0]
+    chi = cz.chi0_exact(ps, ps, w.energies, w.nocc)
+    from workloads import crystal as cx
+    dens = cx.valence_density(w.psi_site, w.nocc).numpy()
+    Wa = ax.screen_W_alda(chi, site, dens)
+    X = sc.project(chi, site)
+    V = sc.coulomb(site)
+    d = sc.radial_weights(site)
+    D = np.diag(d)
+    F = ax.contact_matrix(site, ax.fxc(dens))
+    n = V.shape[0]
+    Y = np.linalg.solve(np.eye(n) - (V @ D + F) @ X @ D, V)
+    Wb = V + V @ D @ X @ D @ Y
+    assert np.abs(Wa - Wb).max() < 1e-11 * np.abs(Wa).max()
+    W = sc.screen_W(chi, site)
+    W0 = ax.screen_W_alda(chi, site, dens, f_points=np.zeros_like(dens))
+    assert np.abs(W0 - W).max() < 1e-12 * np.abs(W).max()
+    assert np.abs(Wa - W).max() > 1e-6 * np.abs(W).max()

@@ -209,3 +209,9 @@ def random_cell(a: float, natom: int, rng: np.random.Generator) -> Crystal:
     frac = rng.uniform(0.0, 1.0, size=(natom, 3))
     depth = rng.uniform(1.0, 3.0, size=natom)
     return Crystal(a=a, frac=frac, depth=depth)
+
+
+def valence_density(psi: torch.Tensor, nocc: int, spin: int = 2) -> torch.Tensor:
+    """Electron density at the points of psi [nk, nb, npts]: (spin / nk) sum_k sum_{n < nocc}
+    |psi_nk|^2 (the density a plane-wave calculation hands over with its orbitals)."""
+    return spin / psi.shape[0] * (psi[:, :nocc].abs() ** 2).sum((0, 1))
