@@ -215,6 +215,20 @@ lrs_status lrs_induced_potential(lrs_ctx* ctx, const double* chi0_sitesite, cons
                                  double q, double r_shell, int l0_only, double* rho_out,
                                  double* v_out);
 
+/* W for the ALDA polarizability (App. ALDA, Eq. chi-alda: chi~ = (1 - chi0 (v + f_xc))^-1 chi0,
+ * with the contact kernel of Eq. kxc_alda, f_xc(r, r') = delta(r - r') dv_xc/dn at n(r)).
+ * f_xc is the second derivative of the LDA exchange-correlation energy (Slater exchange,
+ * Vosko-Wilk-Nusair correlation) by a 5-point difference with density steps of 0.01
+ * (n/4 where n < 0.04).  In the basis of lrs_screen_W, with
+ * F_{(L,i),(L',i)} = sum_a w_a Y_L(a) f_xc(r_i a) Y_L'(a):
+ *   W~ = V + V D chi~ D V = V + V D X D Y,   Y = (I - V D X D - F X D)^-1 V   (FP64).
+ *   chi0_sitesite  site blocks (layout of LRS_COLS_SITE, all sites), device
+ *   density        float64 [sum npts] electron density at the site points (e/bohr^3), device
+ *   W_out          float64 [nsites][n][n] as lrs_screen_W.
+ * Does not change the W kept for lrs_screen_W_backward.  LRS_ESTATE under stream capture. */
+lrs_status lrs_screen_W_alda(lrs_ctx* ctx, const double* chi0_sitesite, const double* density,
+                             double* W_out);
+
 /* Adjoint of lrs_screen_W.  dL_dW float64 [nsites][n][n], or NULL to differentiate
  * sum(loss_out) of the last lrs_screen_W call with rho_test.  Writes
  * dL_dchi0_sitesite (site-block layout) = P^T (D W^T Gbar W^T D) P per site.  Asynchronous. */

@@ -48,6 +48,7 @@ SIGNATURES = [
     ("lrs_tune", _I, [_P, _I]),
     ("lrs_project_orbitals", _I, [_P, _I, _I, _I, _P, _P, _P, _D, _I, _P, _P]),
     ("lrs_induced_potential", _I, [_P, _P, _P, _D, _D, _I, _P, _P]),
+    ("lrs_screen_W_alda", _I, [_P, _P, _P, _P]),
     ("lrs_last_kernel_ms", _D, [_P]),
 ]
 
@@ -241,6 +242,14 @@ class Context:
                                                   _ptr(dL_dchi0_ss.contiguous()), _ptr(dE),
                                                   _ptr(dpsi), None))
         return dE, dpsi
+
+    def screen_W_alda(self, chi0_ss, density):
+        """W [sum n^2] for the ALDA polarizability, from the site-block chi0 and the electron
+        density at the site points [sum npts] (App. ALDA)."""
+        W = torch.empty(sum(n * n for n in self.nbasis), dtype=torch.float64, device=self.device)
+        d = _dev(density, torch.float64, self.device)
+        self._check(lib.lrs_screen_W_alda(self.h, _ptr(chi0_ss.contiguous()), _ptr(d), _ptr(W)))
+        return W
 
     def induced_potential(self, chi0_ss, v1=None, q=1.0, r_shell=1.0, l0_only=False):
         """(rho_ind, v_ind) [sum n] of a spherical perturbation: `v1` [sum n_rad] radial

@@ -10,6 +10,9 @@
 //   y = (I - V D X D)^-1 v1 (the total potential),  rho = X D y,  v_ind = y - v1,
 // which equal rho = (I - X D V D)^-1 X D v1 = chi D v1 and v_ind = V D rho (push-through);
 // optionally with the 00;00 block alone (the l = 0 response).
+// ALDA vertex (App. ALDA, Eqs. chi-alda and kxc_alda): with the contact kernel f_xc(n(r)),
+// F_{(L,i),(L',i)} = sum_a w_a Y_L(a) f_xc(r_i a) Y_L'(a), the ALDA polarizability gives
+//   W~ = V + V D X D Y,  Y = (I - V D X D - F X D)^-1 V.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -209,6 +212,117 @@ __global__ void induced_out_kernel(ScreenTabs T, const double* X, const double* 
     }
     rho[m.h_off + r] = rr;
     vind[m.h_off + r] = vv;
+  }
+}
+
+// ---- ALDA: the LDA exchange-correlation energy per volume, e(n) = n (eps_x + eps_c), with
+// Slater exchange eps_x = -(3/4) (3n/pi)^(1/3) and the Vosko-Wilk-Nusair (1980) paramagnetic
+// correlation (fit to Ceperley-Alder; Hartree units), x = sqrt(r_s), X(x) = x^2 + b x + c
+__device__ double lda_energy(double n) {
+  const double pi = 3.14159265358979323846;
+  const double A = 0.0310907, x0 = -0.10498, b = 3.72744, c = 12.9352;
+  const double ex = -0.75 * cbrt(3.0 * n / pi);
+  const double rs = cbrt(3.0 / (4.0 * pi * n));
+  const double x = sqrt(rs);
+  const double Q = sqrt(4.0 * c - b * b);
+  const double X = x * x + b * x + c, X0 = x0 * x0 + b * x0 + c;
+  const double at = atan(Q / (2.0 * x + b));
+  const double ec = A * (log(x * x / X) + 2.0 * b / Q * at -
+                         b * x0 / X0 * (log((x - x0) * (x - x0) / X) + 2.0 * (b + 2.0 * x0) / Q * at));
+  return n * (ex + ec);
+}
+
+// f_xc = d^2 e / dn^2 at every site point: 5-point central difference with density steps of
+// 0.01, shrunk to n/4 where n < 0.04 so that every stencil density stays positive; 0 for n <= 0
+__global__ void fxc_kernel(const double* dens, long long npts, double* f) {
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npts;
+       p += (long long)gridDim.x * blockDim.x) {
+    const double n = dens[p];
+    double v = 0.0;
+    if (n > 0.0) {
+      const double h = fmin(0.01, 0.25 * n);
+      v = (-lda_energy(n + 2 * h) + 16.0 * lda_energy(n + h) - 30.0 * lda_energy(n) +
+           16.0 * lda_energy(n - h) - lda_energy(n - 2 * h)) / (12.0 * h * h);
+    }
+    f[p] = v;
+  }
+}
+
+// contact matrix F[(i, L, L')] = sum_a w_a Y_L(a) f(r_i a) Y_L'(a) of one (site, shell); the
+// unweighted Y_L'(a) is yw[L'][a] / w_a with w_a = 2 sqrt(pi) yw[0][a]
+__global__ void contact_kernel(ScreenTabs T, const double* f, double* F) {
+  const SiteMeta m = T.meta[blockIdx.y];
+  const int i = blockIdx.x;
+  if (i >= m.nrad) return;
+  const int nL = m.nL, A = m.nang;
+  const double* yw = T.yw + m.yw_off;
+  const double* fi = f + m.pt_off + (long long)i * A;
+  double* out = F + (long long)m.h_off * nL + (long long)i * nL * nL;
+  for (int it = threadIdx.x; it < nL * nL; it += blockDim.x) {
+    const int L = it / nL, Lp = it % nL;
+    double acc = 0;
+    for (int a = 0; a < A; ++a)
+      acc += yw[L * A + a] * yw[Lp * A + a] * fi[a] / (2.0 * sqrt(3.14159265358979323846) * yw[a]);
+    out[it] = acc;
+  }
+}
+
+// augmented [I - V D X D - F X D | V] rows: one workgroup per (site, row)
+__global__ void alda_rows_kernel(ScreenTabs T, const int2* rows, const double* X,
+                                 const double* F, double* M) {
+  const int2 rw = rows[blockIdx.x];
+  const SiteMeta m = T.meta[rw.x];
+  const int row = rw.y, n = m.n, R = m.nrad, nL = m.nL;
+  const int L = row / R, i = row % R, l = l_of(L);
+  const double* r = T.radii + m.rad_off;
+  const double* u = T.u + m.rad_off;
+  const double* x = X + m.w_off;
+  const double* fi = F + (long long)m.h_off * nL + (long long)i * nL * nL + L * nL;
+  double* out = M + 2 * m.w_off + (long long)row * 2 * n;
+  for (int c = threadIdx.x; c < 2 * n; c += blockDim.x) {
+    if (c < n) {
+      const int j = c % R;
+      double acc = 0;
+      for (int q = 0; q < R; ++q) acc += coulomb_l(l, r[i], r[q]) * u[q] * x[(long long)(L * R + q) * n + c];
+      for (int Lp = 0; Lp < nL; ++Lp) acc += fi[Lp] * x[(long long)(Lp * R + i) * n + c];
+      out[c] = (c == row ? 1.0 : 0.0) - acc * u[j];
+    } else {
+      const int cc = c - n, Lp = cc / R, j = cc % R;
+      out[c] = Lp == L ? coulomb_l(l, r[i], r[j]) : 0.0;
+    }
+  }
+}
+
+// T = X D Y (pass 1) and W~ = V + V D T (pass 2); grid (row, site), threads over columns
+__global__ void alda_pass1(ScreenTabs T, const double* X, const double* Y, double* Tm) {
+  const SiteMeta m = T.meta[blockIdx.y];
+  const int n = m.n, R = m.nrad, rr = blockIdx.x;
+  if (rr >= n) return;
+  const double* x = X + m.w_off + (long long)rr * n;
+  const double* y = Y + m.w_off;
+  const double* u = T.u + m.rad_off;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    double acc = 0;
+    for (int k = 0; k < n; ++k) acc += x[k] * u[k % R] * y[(long long)k * n + c];
+    Tm[m.w_off + (long long)rr * n + c] = acc;
+  }
+}
+
+__global__ void alda_pass2(ScreenTabs T, const double* Tm, double* W_out,
+                           const long long* w_out_off) {
+  const SiteMeta m = T.meta[blockIdx.y];
+  const int n = m.n, R = m.nrad, rr = blockIdx.x;
+  if (rr >= n) return;
+  const int L = rr / R, i = rr % R, l = l_of(L);
+  const double* r = T.radii + m.rad_off;
+  const double* u = T.u + m.rad_off;
+  const double* t = Tm + m.w_off;
+  double* W = W_out + w_out_off[blockIdx.y] + (long long)rr * n;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    const int Lp = c / R, j = c % R;
+    double acc = Lp == L ? coulomb_l(l, r[i], r[j]) : 0.0;
+    for (int q = 0; q < R; ++q) acc += coulomb_l(l, r[i], r[q]) * u[q] * t[(long long)(L * R + q) * n + c];
+    W[c] = acc;
   }
 }
 
@@ -563,9 +677,82 @@ static hipError_t launch_induced(lrs_ctx* ctx, const double* chi0_ss, const doub
   return hipGetLastError();
 }
 
+// work layout: X [w_total] | M [2 w_total] | Y [w_total] | T [w_total] | F [n_total nL] |
+// f [nrows]
+static hipError_t launch_alda(lrs_ctx* ctx, const double* chi0_ss, const double* dens,
+                              double* W_out) {
+  HostTabs H;
+  build_tabs(ctx, H);
+  if (H.max_n > 288) return hipErrorInvalidValue;
+  for (const auto& m : H.meta)
+    if (m.nang > 256) return hipErrorInvalidValue;
+  DevTabs D;
+  hipError_t e = upload_tabs(ctx, H, D);
+  if (e != hipSuccess) return e;
+  const int nL = (ctx->lmax + 1) * (ctx->lmax + 1);
+  e = ensure_dev(ctx, ctx->work,
+                 (size_t)(5 * H.w_total + H.n_total * nL + (long long)ctx->nrows) * 8);
+  if (e != hipSuccess) return e;
+  double* X = (double*)ctx->work.p;
+  double* M = X + H.w_total;
+  double* Y = M + 2 * H.w_total;
+  double* Tm = Y + H.w_total;
+  double* F = Tm + H.w_total;
+  double* f = F + H.n_total * nL;
+  hipStream_t st = ctx->stream;
+  hipLaunchKernelGGL(fxc_kernel, dim3(256), dim3(256), 0, st, dens, (long long)ctx->nrows, f);
+  hipLaunchKernelGGL(contact_kernel, dim3(H.max_n / nL, ctx->nsites), dim3(64), 0, st, D.t, f, F);
+  hipLaunchKernelGGL(project_kernel, dim3(D.nblocks), dim3(256), 0, st, D.t, D.blocks, chi0_ss, X);
+  hipLaunchKernelGGL(alda_rows_kernel, dim3(D.nrows), dim3(256), 0, st, D.t, D.rows, X, F, M);
+  hipLaunchKernelGGL(gauss_jordan_kernel, dim3(ctx->nsites), dim3(1024), 0, st, D.t, M, 0, Y,
+                     D.w_out_off);
+  dim3 grid(H.max_n, ctx->nsites);
+  hipLaunchKernelGGL(alda_pass1, grid, dim3(256), 0, st, D.t, X, Y, Tm);
+  hipLaunchKernelGGL(alda_pass2, grid, dim3(256), 0, st, D.t, Tm, W_out, D.w_out_off);
+  return hipGetLastError();
+}
+
 }  // namespace lrs
 
 using namespace lrs;
+
+extern "C" lrs_status lrs_screen_W_alda(lrs_ctx* ctx, const double* chi0_sitesite,
+                                        const double* density, double* W_out) {
+  if (!ctx) return LRS_EINVAL;
+  ctx->err.clear();
+  if (!ctx->have_sites) {
+    ctx->err = "sites must be set first";
+    return LRS_ESTATE;
+  }
+  if (!chi0_sitesite || !density || !W_out) {
+    ctx->err = "missing argument";
+    return LRS_EINVAL;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipSetDevice(ctx->device) != hipSuccess ||
+      hipStreamIsCapturing(ctx->stream, &cs) != hipSuccess) {
+    ctx->err = "device";
+    return LRS_EDEVICE;
+  }
+  if (cs != hipStreamCaptureStatusNone) {
+    ctx->err = "the ALDA solve copies host tables; it cannot be captured";
+    return LRS_ESTATE;
+  }
+  const hipError_t e = launch_alda(ctx, chi0_sitesite, density, W_out);
+  if (e == hipErrorInvalidValue) {
+    ctx->err = "a site basis exceeds 288 functions or 256 directions";
+    return LRS_EUNSUPPORTED;
+  }
+  if (e == hipErrorOutOfMemory) {
+    ctx->err = "ALDA workspace";
+    return LRS_ENOMEM;
+  }
+  if (e != hipSuccess) {
+    ctx->err = std::string("ALDA W: ") + hipGetErrorString(e);
+    return LRS_EDEVICE;
+  }
+  return LRS_OK;
+}
 
 extern "C" lrs_status lrs_induced_potential(lrs_ctx* ctx, const double* chi0_sitesite,
                                             const double* v1_host, double q, double r_shell,

@@ -1,0 +1,105 @@
+"""GPU parity of W for the ALDA polarizability (LDA contact kernel from the density at the
+site points) against the oracle.
+
+Error measure: max |gpu - ref| / max |ref|; bar 1e-10 with the library's FP64 chi0 against
+the oracle's chi0 of the same quadrature, 1e-11 from the same chi0 blocks.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import alda as ax
+from oracle import chi0 as cz
+from oracle import quadrature as q
+from tests.conftest import workload
+from workloads import crystal as cx
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2005_07834_amd as P
+    return P
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def scale_for(w, n):
+    mu = q.mid_gap(w.energies, w.nocc)
+    x, y = q.offsets(w.energies, w.nocc, mu)
+    return q.auto_scale(x, y, n)
+
+
+def make(P, w):
+    n = w.n_terms
+    s = scale_for(w, n)
+    ctx = P.Context(0)
+    ctx.set_orbitals(w.energies, w.nocc, None, w.grid_dV)
+    ctx.set_sites(w.sites, w.psi_site)
+    ctx.make_quadrature(P.QUAD_TIME, n, s)
+    return ctx, n, s
+
+
+@pytest.mark.parametrize("name", ["tiny", "production"])
+def test_alda_W_vs_oracle(P, name):
+    """Every site of the tiny and production workloads; the W kept for the backward pass is
+    the RPA one before and after."""
+    w = workload(name, with_grid=False)
+    ctx, n, s = make(P, w)
+    dens = cx.valence_density(w.psi_site, w.nocc)
+    chi = ctx.chi0(-1, P.COLS_SITE, P.FP64)
+    W, _ = ctx.screen_W(chi, rho=torch.as_tensor(w.rho_test, device="cuda"), want_loss=True)
+    lam0 = ctx.screen_W_backward()
+    Wa = ctx.screen_W_alda(chi, dens)
+    lam1 = ctx.screen_W_backward()
+    assert torch.equal(lam0, lam1)
+    ps = w.psi_site.numpy()
+    terms = cz.terms_for(w.energies, w.nocc, "time", n, s)
+    offs = w.site_offsets
+    dn = dens.numpy()
+    worst = 0.0
+    for k, (blk, site) in enumerate(zip(ctx.W_blocks(Wa), w.sites)):
+        sl = slice(offs[k], offs[k + 1])
+        ref_chi = cz.chi0_quad(ps[:, :, sl], ps[:, :, sl], w.nocc, 2, *terms)
+        ref = ax.screen_W_alda(ref_chi, site, dn[sl])
+        e = rel(blk.cpu().numpy(), ref)
+        d = rel(blk.cpu().numpy(), ctx.W_blocks(W)[k].cpu().numpy())
+        say(f"  {name} site {k}: ALDA W vs oracle {e:.2e} (differs from RPA W by {d:.2e})")
+        worst = max(worst, e)
+        assert d > 1e-6
+    assert worst < 1e-10
+    ctx.close()
+
+
+def test_alda_W_uneven_sites(P):
+    """Batching workload: the library's ALDA W on its own BF16X2 chi0 blocks against the
+    oracle's on the same blocks, at the largest, the smallest and one middle site."""
+    w = workload("batching", with_grid=False, device="cuda")
+    ctx, n, s = make(P, w)
+    chi = ctx.chi0(-1, P.COLS_SITE, P.BF16X2)
+    dens = cx.valence_density(w.psi_site, w.nocc)
+    Wa = ctx.screen_W_alda(chi, dens)
+    npts = [x.npts for x in w.sites]
+    cb = np.cumsum([0] + [m * m for m in npts])
+    offs = w.site_offsets
+    dn = dens.cpu().numpy()
+    for k in sorted({int(np.argmax(npts)), int(np.argmin(npts)), 31}):
+        blk = chi[cb[k]:cb[k + 1]].view(npts[k], npts[k]).cpu().numpy()
+        ref = ax.screen_W_alda(blk, w.sites[k], dn[offs[k]:offs[k + 1]])
+        e = rel(ctx.W_blocks(Wa)[k].cpu().numpy(), ref)
+        say(f"  site {k} ({npts[k]} points): {e:.2e}")
+        assert e < 1e-11
+    ctx.close()
