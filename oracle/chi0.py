@@ -43,6 +43,14 @@ def pair_sum(psi_rows, psi_cols, nocc, spin, kern, nblock=16):
     Also returns the largest |Im| of the same sum taken without the real part; it
     vanishes for time-reversal-symmetric orbitals on k-sets closed under k -> -k,
     where the full band sum is real before the real part is taken."""
+    acc = pair_acc(psi_rows, psi_cols, nocc, kern, nblock)
+    pref = -2.0 * spin / psi_rows.shape[0] ** 2
+    return pref * acc.real, float(np.abs(acc.imag).max() * abs(pref))
+
+
+def pair_acc(psi_rows, psi_cols, nocc, kern, nblock=16):
+    """sum_{k,k'} sum_{n occ, m unocc} P_nm(r, r') K_nm(k, k') (complex, no prefactor), with
+    P = psi_nk*(r) psi_mk'(r) psi_mk'*(r') psi_nk(r')."""
     nk = psi_rows.shape[0]
     nr, nc = psi_rows.shape[2], psi_cols.shape[2]
     acc = np.zeros((nr, nc), dtype=np.complex128)
@@ -57,8 +65,42 @@ def pair_sum(psi_rows, psi_cols, nocc, spin, kern, nblock=16):
                 rr = rr * Kmat[n0:n1, :, None]
                 nu = rr.shape[1]
                 acc += rr.reshape((n1 - n0) * nu, nr).T @ np.conj(rc.reshape((n1 - n0) * nu, nc))
-    pref = -2.0 * spin / nk ** 2
-    return pref * acc.real, float(np.abs(acc.imag).max() * abs(pref))
+    return acc
+
+
+def chi0_iw_exact(psi_rows, psi_cols, E, nocc, omega, spin=2, mu=None):
+    """chi0(r, r'; i omega): each occupied x unoccupied pair contributes
+    P / (i omega - Delta) - conj(P) / (i omega + Delta) (the two orderings of the pair), i.e.
+        chi0 = -(2 s / N_k^2) sum [Delta Re P - omega Im P] / (Delta^2 + omega^2),
+    Delta = e_mk' - e_nk.  The omega Im P part is odd in omega and vanishes for
+    time-reversal-symmetric orbital sets.  Returns (chi0, the largest |odd part|)."""
+    if mu is None:
+        mu = q.mid_gap(E, nocc)
+    x, y = q.offsets(E, nocc, mu)
+
+    def k_even(k, kp):
+        d = x[k][:, None] + y[kp][None, :]
+        return d / (d * d + omega * omega)
+
+    def k_odd(k, kp):
+        d = x[k][:, None] + y[kp][None, :]
+        return omega / (d * d + omega * omega)
+
+    pref = -2.0 * spin / psi_rows.shape[0] ** 2
+    ev = pair_acc(psi_rows, psi_cols, nocc, k_even)
+    od = pair_acc(psi_rows, psi_cols, nocc, k_odd)
+    odd = -pref * od.imag
+    return pref * ev.real + odd, float(np.abs(odd).max())
+
+
+def chi0_iw_quad(psi_rows, psi_cols, nocc, spin, cc, cs, alpha, beta):
+    """chi0(i omega) with the time rule: sum_l (cc_l + i cs_l) alpha_l beta_l approximates
+    (Delta + i omega) / (Delta^2 + omega^2) (cc = c cos(omega tau), cs = c sin(omega tau)),
+    and chi0 = -(2 s / N_k^2) sum Re[(K_e + i K_o) P] as in chi0_iw_exact."""
+    pref = -2.0 * spin / psi_rows.shape[0] ** 2
+    ev = pair_acc(psi_rows, psi_cols, nocc, quad_kernel(cc, alpha, beta))
+    od = pair_acc(psi_rows, psi_cols, nocc, quad_kernel(cs, alpha, beta))
+    return pref * (ev.real - od.imag)
 
 
 def chi0_exact(psi_rows, psi_cols, E, nocc, spin=2, mu=None, delta=0.0):
@@ -101,6 +143,13 @@ def terms_for(E, nocc, kind, n, scale=None, mu=None, delta=0.0):
             scale = q.auto_scale(x, y, n)
         c, al, be, _ = q.imag_time_terms(x, y, n, scale)
         return c, al, be
+    if kind.startswith("time_iw:"):        # "time_iw:<omega>": (c cos, c sin, alpha, beta)
+        omega = float(kind.split(":", 1)[1])
+        if scale is None or scale <= 0:
+            scale = q.auto_scale_iw(x, y, n, omega)
+        cc, al, be, tau = q.imag_time_terms_iw(x, y, n, scale, omega)
+        c0, _, _, _ = q.imag_time_terms(x, y, n, scale)
+        return cc, c0 * np.sin(omega * tau), al, be
     if kind == "freq":
         z = q.zeta(E, mu, metallic=delta > 0) if scale is None or scale <= 0 else scale
         c, al, be, _ = q.freq_terms(x, y, n, z)

@@ -86,6 +86,42 @@ def auto_scale(x, y, n: int) -> float:
     return best_s
 
 
+def imag_time_terms_iw(x, y, n: int, scale: float, omega: float):
+    """The same rule for the polarizability at imaginary frequency i omega, whose even part
+    needs Delta / (Delta^2 + omega^2) = int_0^inf cos(omega tau) exp(-Delta tau) d tau: the
+    coefficients take the factor cos(omega tau_l) (and may be negative)."""
+    c, alpha, beta, tau = imag_time_terms(x, y, n, scale)
+    return c * np.cos(omega * tau), alpha, beta, tau
+
+
+def imag_time_error_iw(scale: float, n: int, dmin: float, dmax: float, omega: float,
+                       nsample: int = 512) -> float:
+    """max over log-spaced Delta in [dmin, dmax] of |K(Delta) / k(Delta) - 1|, with
+    k = Delta / (Delta^2 + omega^2) and K the cos-weighted rule."""
+    a, w = gauss_legendre_01(n)
+    tau = scale * a / (1.0 - a)
+    c = scale * w / (1.0 - a) ** 2 * np.cos(omega * tau)
+    d = np.exp(np.linspace(math.log(dmin), math.log(dmax), nsample))
+    K = (c[None, :] * np.exp(-d[:, None] * tau[None, :])).sum(1)
+    return float(np.abs(K * (d * d + omega * omega) / d - 1.0).max())
+
+
+def auto_scale_iw(x, y, n: int, omega: float) -> float:
+    """auto_scale with the imaginary-frequency error model (the static scan at omega = 0)."""
+    if omega == 0.0:
+        return auto_scale(x, y, n)
+    dmin = float(x.min() + y.min())
+    dmax = float(x.max() + y.max())
+    g = math.sqrt(dmin * dmax)
+    best, best_s = None, None
+    for j in range(-80, 101):
+        s = 10.0 ** (j / 40.0) / g
+        e = imag_time_error_iw(s, n, dmin, dmax, omega)
+        if best is None or e < best:
+            best, best_s = e, s
+    return best_s
+
+
 def zeta(E: np.ndarray, mu: float, metallic: bool = False) -> float:
     """Geometric mean of the smallest and largest |mu - e| over all bands and k."""
     d = np.abs(mu - E)

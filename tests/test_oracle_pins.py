@@ -519,3 +519,61 @@ def test_alda_W_pins(tiny):
     W0 = ax.screen_W_alda(chi, site, dens, f_points=np.zeros_like(dens))
     assert np.abs(W0 - W).max() < 1e-12 * np.abs(W).max()
     assert np.abs(Wa - W).max() > 1e-6 * np.abs(W).max()
+
+
+# ------------------------------------------------------------------ chi0 at imaginary frequency
+@pytest.mark.parametrize("d,om", [(0.05, 0.02), (0.3, 0.3), (1.7, 0.8), (0.2, 3.0)])
+def test_iw_pair_identity(d, om):
+    """int_0^inf cos(omega tau) exp(-Delta tau) d tau = Delta / (Delta^2 + omega^2)."""
+    val, _ = integrate.quad(lambda t: math.cos(om * t) * math.exp(-d * t), 0, np.inf,
+                            limit=400, epsabs=1e-14, epsrel=1e-13)
+    assert abs(val - d / (d * d + om * om)) < 1e-11 * d / (d * d + om * om)
+
+
+def test_chi0_iw_limits_and_symmetry(tiny):
+    """omega = 0 gives the static chi0; omega^2 chi0(i omega) tends to the first-moment sum
+    -(2s/N_k^2) sum Delta Re P; the odd part vanishes for the Gamma-only tiny workload (a
+    real potential: a time-reversal-symmetric set with whole multiplets)."""
+    w = tiny
+    ps = w.psi_site.numpy()
+    E = w.energies
+    static = cz.chi0_exact(ps, ps, E, w.nocc)
+    z, odd0 = cz.chi0_iw_exact(ps, ps, E, w.nocc, 0.0)
+    assert np.abs(z - static).max() < 1e-13 * np.abs(static).max()
+    om = 1e4
+    big, _ = cz.chi0_iw_exact(ps, ps, E, w.nocc, om)
+    mu = q.mid_gap(E, w.nocc)
+    x, y = q.offsets(E, w.nocc, mu)
+    first = cz.pair_sum(ps, ps, w.nocc, 2, lambda k, kp: x[k][:, None] + y[kp][None, :])[0]
+    assert np.abs(om * om * big - first).max() < 1e-7 * np.abs(first).max()
+    _, odd = cz.chi0_iw_exact(ps, ps, E, w.nocc, 0.3)
+    assert odd < 1e-14 * np.abs(static).max()
+
+
+def test_iw_time_rule_converges(tiny):
+    """The cos-weighted imaginary-time rule approaches chi0(i omega) as nodes are added (its
+    accuracy falls as omega tau oscillates faster: small omega only)."""
+    w = tiny
+    ps = w.psi_site.numpy()
+    E = w.energies
+    ex, _ = cz.chi0_iw_exact(ps, ps, E, w.nocc, 0.2)
+    errs = []
+    for n in (16, 32, 48):
+        cc, cs, al, be = cz.terms_for(E, w.nocc, "time_iw:0.2", n)
+        got = cz.chi0_iw_quad(ps, ps, w.nocc, 2, cc, cs, al, be)
+        errs.append(np.abs(got - ex).max() / np.abs(ex).max())
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-6
+
+
+def test_iw_odd_part_with_split_band_sets():
+    """Where the band cut splits a degenerate multiplet (production cell, 2x2x2 k) the odd
+    part is not zero; the sin-weighted terms reproduce it: the quadrature chi0(i omega)
+    approaches the exact one, odd part included, and is not symmetric."""
+    p = workload("production", with_grid=False)
+    pp = p.psi_site.numpy()[:, :, :120]
+    ex, odd = cz.chi0_iw_exact(pp, pp, p.energies, p.nocc, 0.05)
+    assert odd > 1e-5 * np.abs(ex).max()
+    cc, cs, al, be = cz.terms_for(p.energies, p.nocc, "time_iw:0.05", 48)
+    got = cz.chi0_iw_quad(pp, pp, p.nocc, 2, cc, cs, al, be)
+    assert np.abs(got - ex).max() < 1e-6 * np.abs(ex).max()
+    assert np.abs(got - got.T).max() > 1e-6 * np.abs(got).max()
