@@ -125,6 +125,21 @@ def pair_sum_entries(psi_r, psi_c, nocc, spin, kern):
     return -2.0 * spin / nk ** 2 * out.real
 
 
+def chi0_iw_quad_entries(psi_r, psi_c, nocc, spin, cc, cs, alpha, beta):
+    """chi0_iw_quad at individual entries (psi_r, psi_c as in pair_sum_entries)."""
+    nk = psi_r.shape[0]
+    ev = np.zeros(psi_r.shape[2], dtype=np.complex128)
+    od = np.zeros(psi_r.shape[2], dtype=np.complex128)
+    Ke, Ko = quad_kernel(cc, alpha, beta), quad_kernel(cs, alpha, beta)
+    for k in range(nk):
+        a = np.conj(psi_r[k, :nocc]) * psi_c[k, :nocc]               # [nocc, E]
+        for kp in range(nk):
+            b = psi_r[kp, nocc:] * np.conj(psi_c[kp, nocc:])         # [nu, E]
+            ev += np.einsum("ne,ne->e", a, Ke(k, kp) @ b)
+            od += np.einsum("ne,ne->e", a, Ko(k, kp) @ b)
+    return -2.0 * spin / nk ** 2 * (ev.real - od.imag)
+
+
 def chi0_exact_entries(psi_r, psi_c, E, nocc, spin=2, mu=None, delta=0.0):
     return pair_sum_entries(psi_r, psi_c, nocc, spin, exact_kernel(E, nocc, mu, delta))
 

@@ -577,3 +577,16 @@ def test_iw_odd_part_with_split_band_sets():
     got = cz.chi0_iw_quad(pp, pp, p.nocc, 2, cc, cs, al, be)
     assert np.abs(got - ex).max() < 1e-6 * np.abs(ex).max()
     assert np.abs(got - got.T).max() > 1e-6 * np.abs(got).max()
+
+
+def test_iw_entries_match_blocks(tiny):
+    """The per-entry imaginary-frequency sum equals the block sum at those entries."""
+    w = tiny
+    ps = w.psi_site.numpy()
+    cc, cs, al, be = cz.terms_for(w.energies, w.nocc, "time_iw:0.3", 24)
+    blk = cz.chi0_iw_quad(ps, ps, w.nocc, 2, cc, cs, al, be)
+    rng = np.random.default_rng(5)
+    r = rng.integers(0, ps.shape[2], 40)
+    c = rng.integers(0, ps.shape[2], 40)
+    ent = cz.chi0_iw_quad_entries(ps[:, :, r], ps[:, :, c], w.nocc, 2, cc, cs, al, be)
+    assert np.abs(ent - blk[r, c]).max() < 1e-13 * np.abs(blk).max()
