@@ -148,6 +148,20 @@ lrs_status lrs_set_quadrature(lrs_ctx* ctx, int nterms, const double* c_host,
  * 1 <= nnodes <= 64.  Node positions and mu are constants under differentiation. */
 lrs_status lrs_make_quadrature(lrs_ctx* ctx, int kind, int nnodes, double scale);
 
+/* The imaginary-time rule for chi0 at imaginary frequency i omega (omega >= 0, Ha; the
+ * dynamic extension of Eq. chi1 on the same contour).  Each occupied x unoccupied pair then
+ * needs (Delta + i omega) / (Delta^2 + omega^2) = int_0^inf e^{i omega tau} e^{-Delta tau} dtau,
+ * so the terms of lrs_make_quadrature(LRS_QUAD_TIME) take complex coefficients
+ * c e^{i omega tau} and lrs_compute_chi0 accumulates Re[c e^{i omega tau} G_o o conj(G_u)]:
+ *   chi0(i omega) = -(2s/N_k^2) sum [Delta Re P - omega Im P] / (Delta^2 + omega^2).
+ * The scale (scale <= 0: automatic) minimises the rule's worst relative error on
+ * Delta / (Delta^2 + omega^2) over the gap range; the rule loses accuracy once omega tau
+ * oscillates within the decay of e^{-Delta tau} (omega well above the smallest gap).
+ * Site x site blocks of chi0(i omega) are not symmetric (the odd part); the adjoint
+ * (lrs_compute_chi0_backward) returns LRS_EUNSUPPORTED for these terms.  omega = 0 gives
+ * exactly lrs_make_quadrature(LRS_QUAD_TIME, ...). */
+lrs_status lrs_make_quadrature_iw(lrs_ctx* ctx, int nnodes, double scale, double omega);
+
 /* Reads back the terms in use: c_host [nterms], tau_host [nterms] (tau for LRS_QUAD_TIME,
  * t for LRS_QUAD_FREQ, 0 for generic), mu and the time scale C / zeta (may be NULL). */
 lrs_status lrs_get_quadrature(const lrs_ctx* ctx, int* nterms, double* c_host, double* tau_host,

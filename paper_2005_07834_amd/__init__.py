@@ -49,6 +49,7 @@ SIGNATURES = [
     ("lrs_project_orbitals", _I, [_P, _I, _I, _I, _P, _P, _P, _D, _I, _P, _P]),
     ("lrs_induced_potential", _I, [_P, _P, _P, _D, _D, _I, _P, _P]),
     ("lrs_screen_W_alda", _I, [_P, _P, _P, _P]),
+    ("lrs_make_quadrature_iw", _I, [_P, _I, _D, _D]),
     ("lrs_last_kernel_ms", _D, [_P]),
 ]
 
@@ -165,6 +166,11 @@ class Context:
     def make_quadrature(self, kind=QUAD_TIME, nnodes=16, scale=0.0):
         self.orb_version += 1
         self._check(lib.lrs_make_quadrature(self.h, kind, nnodes, scale))
+
+    def make_quadrature_iw(self, nnodes=32, scale=0.0, omega=0.0):
+        """Imaginary-time terms for chi0 at imaginary frequency i omega (Ha)."""
+        self.orb_version += 1
+        self._check(lib.lrs_make_quadrature_iw(self.h, nnodes, scale, omega))
 
     def set_quadrature(self, c, alpha, beta):
         c = _host(c, np.float64)

@@ -49,6 +49,7 @@ struct Chi0Params {
   int b_ncb;                    // column blocks in b
   int nch;                      // chunks per term (= K_pad / chunk)
   const double* c;              // [T]
+  const double* ci;             // [T] imaginary parts of the term coefficients, or null
   int T, nch_o;
   const TileDesc* tiles;
   int ntiles;
@@ -821,6 +822,7 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
             // and (c, r)): the host lists only tiles that reach the upper triangle, and each
             // element on or above the diagonal is stored at both places
             const double ct = P.c[t];
+            const double cti = P.ci ? P.ci[t] : 0.0;
             const double scale = t == P.T - 1 ? P.pref : 1.0;
             double old[ELEMS];
             if (t > 0) {
@@ -832,8 +834,11 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
             }
 #pragma unroll
             for (int e = 0; e < ELEMS; ++e) {
+              // Re[(c + i c_i) G_o conj(G_u)]; c_i is zero but for imaginary frequency
               const double v = ct * ((double)or_[e] * (double)gr[i][j][e] +
-                                     (double)oi_[e] * (double)gi[i][j][e]);
+                                     (double)oi_[e] * (double)gi[i][j][e]) -
+                               cti * ((double)oi_[e] * (double)gr[i][j][e] -
+                                      (double)or_[e] * (double)gi[i][j][e]);
               const double r = (v + old[e]) * scale;
               if (in[e] && (!P.sym || dg[e] >= 0)) {
                 P.out[obase + off[e]] = r;
@@ -1004,10 +1009,12 @@ hipError_t launch_prep_site(int prec, const double* site, int rows_pad, int K_pa
 }
 
 hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int a_nrb,
-                       const void* b_tiles, int b_ncb, int nch, const double* c, int T,
-                       int nch_o, const TileDesc* tiles, int ntiles, double* out, double pref,
-                       int sym, unsigned int* sync, void* park, hipStream_t s) {
+                       const void* b_tiles, int b_ncb, int nch, const double* c,
+                       const double* ci, int T, int nch_o, const TileDesc* tiles, int ntiles,
+                       double* out, double pref, int sym, unsigned int* sync, void* park,
+                       hipStream_t s) {
   Chi0Params P;
+  P.ci = ci;
   P.sym = sym;
   P.sync = sync;
   P.park = (unsigned char*)park;
@@ -1048,6 +1055,7 @@ hipError_t launch_green_adjoint(int prec, int grid, const void* a_tiles, int a_n
   P.b_ncb = b_ncb;
   P.nch = nch;
   P.c = c;
+  P.ci = nullptr;
   P.T = 1;
   P.nch_o = nch_o;
   P.tiles = tiles;

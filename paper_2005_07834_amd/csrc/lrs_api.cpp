@@ -166,12 +166,14 @@ lrs_status ensure_site_tiles(lrs_ctx* ctx, int prec) {
 // of two (largest weight in [1, 2)) and moves the factors into c.
 lrs_status install_terms(lrs_ctx* ctx, Quad& q, const std::vector<double>& c,
                          const std::vector<double>& alpha, const std::vector<double>& beta,
-                         const std::vector<double>* dalpha, const std::vector<double>* dbeta) {
+                         const std::vector<double>* dalpha, const std::vector<double>* dbeta,
+                         const std::vector<double>* ci = nullptr) {
   const int T = (int)c.size();
   const int Ko = ctx->Ko, Ku = ctx->Ku, Kp = ctx->K_pad;
   q.nterms = T;
   q.c_raw = c;
   q.c.assign(T, 0.0);
+  q.ci.assign(ci ? T : 0, 0.0);
   q.w.assign((size_t)T * Kp, 0.0);
   q.dw.assign((size_t)T * Kp, 0.0);
   q.has_deriv = dalpha != nullptr;
@@ -189,6 +191,7 @@ lrs_status install_terms(lrs_ctx* ctx, Quad& q, const std::vector<double>& c,
     double sa = std::ldexp(1.0, -(int)std::floor(std::log2(ma)));
     double sb = std::ldexp(1.0, -(int)std::floor(std::log2(mb)));
     q.c[t] = c[t] / (sa * sb);
+    if (ci) q.ci[t] = (*ci)[t] / (sa * sb);
     double* w = &q.w[(size_t)t * Kp];
     double* dw = &q.dw[(size_t)t * Kp];
     for (int i = 0; i < Ko; ++i) {
@@ -202,11 +205,14 @@ lrs_status install_terms(lrs_ctx* ctx, Quad& q, const std::vector<double>& c,
   }
   // device copies: weights in natural K order (FP64) and the coefficients
   CHECK(ensure_buf(ctx, ctx->w_nat, q.w.size() * 8, "weights"));
-  CHECK(ensure_buf(ctx, ctx->c_dev, (size_t)T * 8, "term coefficients"));
+  CHECK(ensure_buf(ctx, ctx->c_dev, (size_t)2 * T * 8, "term coefficients"));
   HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->w_nat.p, q.w.data(), q.w.size() * 8,
                                   hipMemcpyHostToDevice, ctx->stream));
   HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->c_dev.p, q.c.data(), (size_t)T * 8,
                                   hipMemcpyHostToDevice, ctx->stream));
+  if (ci)
+    HIP_OR_FAIL(ctx, hipMemcpyAsync((double*)ctx->c_dev.p + T, q.ci.data(), (size_t)T * 8,
+                                    hipMemcpyHostToDevice, ctx->stream));
   HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));   // host vectors are freed on return
   ctx->have_quad = true;
   ++ctx->quad_version;
@@ -351,8 +357,9 @@ lrs_status get_plan(lrs_ctx* ctx, int site, int cols, int prec, int variant, int
           const RowTile& x = rt[i + r];
           // chi0 (symmetric) and the adjoint's H (Hermitian) blocks are stored from their
           // upper triangle: tiles wholly below the diagonal are not needed, and pad carries
-          // (first row - first column)
-          if (c * sh.bn + sh.bn - 1 < x.m0) return;
+          // (first row - first column).  Mode 2 (chi0 at imaginary frequency, whose odd part
+          // is antisymmetric) lists every tile.
+          if (mode != 2 && c * sh.bn + sh.bn - 1 < x.m0) return;
           TileDesc t;
           t.a_row0 = x.slot_row - bt.rb0 * 16;
           t.b_col0 = slot0 + c * sh.bn;
@@ -438,7 +445,8 @@ int pick_variant(lrs_ctx* ctx, int prec) {
 lrs_status run_chi0(lrs_ctx* ctx, int site, int cols, int prec, int variant, double* out,
                     bool timed, int max_tiles = 0) {
   Plan* plan = nullptr;
-  CHECK(get_plan(ctx, site, cols, prec, variant, 0, &plan));
+  const bool odd = !ctx->quad.ci.empty();    // complex term coefficients (imaginary frequency)
+  CHECK(get_plan(ctx, site, cols, prec, variant, cols == LRS_COLS_SITE && odd ? 2 : 0, &plan));
   double bscale = 1.0;
   const void* b;
   const int b_ncb = (cols == LRS_COLS_GRID ? ctx->grid_cols_pad : ctx->site_cols_pad) / 16;
@@ -480,9 +488,11 @@ lrs_status run_chi0(lrs_ctx* ctx, int site, int cols, int prec, int variant, dou
     if (timed && first) HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev0, ctx->stream));
     first = false;
     HIP_OR_FAIL(ctx, launch_chi0(prec, variant, grid, ctx->a_tiles.p, bt.nrb, b, b_ncb, nch,
-                                 (const double*)ctx->c_dev.p, T, ctx->Ko_pad / KC,
-                                 (const TileDesc*)plan->tiles.p + bt.tile0, nt, out, pref,
-                                 cols == LRS_COLS_SITE, sync, ctx->park.p, ctx->stream));
+                                 (const double*)ctx->c_dev.p,
+                                 odd ? (const double*)ctx->c_dev.p + T : nullptr, T,
+                                 ctx->Ko_pad / KC, (const TileDesc*)plan->tiles.p + bt.tile0, nt,
+                                 out, pref, cols == LRS_COLS_SITE && !odd, sync, ctx->park.p,
+                                 ctx->stream));
     if (max_tiles > 0) break;
   }
   if (timed && !first) {
@@ -748,7 +758,23 @@ lrs_status lrs_set_quadrature(lrs_ctx* ctx, int nterms, const double* c, const d
   return LRS_OK;
 }
 
+static lrs_status make_quadrature(lrs_ctx* ctx, int kind, int nnodes, double scale,
+                                  double omega);
+
 lrs_status lrs_make_quadrature(lrs_ctx* ctx, int kind, int nnodes, double scale) {
+  return make_quadrature(ctx, kind, nnodes, scale, 0.0);
+}
+
+lrs_status lrs_make_quadrature_iw(lrs_ctx* ctx, int nnodes, double scale, double omega) {
+  if (ctx && !(std::isfinite(omega) && omega >= 0)) {
+    ctx->err.clear();
+    return fail(ctx, LRS_EINVAL, "omega must be finite and >= 0");
+  }
+  return make_quadrature(ctx, LRS_QUAD_TIME, nnodes, scale, omega);
+}
+
+static lrs_status make_quadrature(lrs_ctx* ctx, int kind, int nnodes, double scale,
+                                  double omega) {
   if (!ctx) return LRS_EINVAL;
   ctx->err.clear();
   if (!ctx->have_bands) return fail(ctx, LRS_ESTATE, "lrs_set_orbitals must come first");
@@ -762,7 +788,7 @@ lrs_status lrs_make_quadrature(lrs_ctx* ctx, int kind, int nnodes, double scale)
   const int Ko = ctx->Ko, Ku = ctx->Ku;
   Quad q;
   q.kind = kind;
-  std::vector<double> c, al, be, dal, dbe;
+  std::vector<double> c, ci, al, be, dal, dbe;
   // derivative of an offset with respect to its band energy (mu fixed):
   // x = mu - e -> -1, y = e - mu -> +1, times x/sqrt(x^2+delta^2) with regularisation
   auto dx_de = [&](double xr, double sign) {
@@ -778,12 +804,16 @@ lrs_status lrs_make_quadrature(lrs_ctx* ctx, int kind, int nnodes, double scale)
     double dmin = *std::min_element(x.begin(), x.end()) + *std::min_element(y.begin(), y.end());
     double dmax = *std::max_element(x.begin(), x.end()) + *std::max_element(y.begin(), y.end());
     if (!(dmin > 0)) return fail(ctx, LRS_ENOGAP, "smallest denominator is not positive");
-    double C = scale > 0 ? scale : time_auto_scale(dmin, dmax, nnodes);
+    double C = scale > 0 ? scale : time_auto_scale_iw(dmin, dmax, nnodes, omega);
     q.scale = C;
+    q.omega = omega;
     for (int j = 0; j < nnodes; ++j) {
       double tau = C * a[j] / (1.0 - a[j]);
       double cj = C * wgl[j] / ((1.0 - a[j]) * (1.0 - a[j]));
-      c.push_back(cj);
+      // imaginary frequency: complex coefficient c e^{i omega tau} (Laplace transform of
+      // cos and sin); omega = 0 leaves the static rule
+      if (omega != 0.0) ci.push_back(cj * std::sin(omega * tau));
+      c.push_back(omega != 0.0 ? cj * std::cos(omega * tau) : cj);
       q.tau.push_back(tau);
       for (int i = 0; i < Ko; ++i) {
         double v = std::exp(-x[i] * tau);
@@ -836,7 +866,7 @@ lrs_status lrs_make_quadrature(lrs_ctx* ctx, int kind, int nnodes, double scale)
   }
   if ((int)c.size() > kMaxTerms) return fail(ctx, LRS_EINVAL, "too many terms");
   drop_quad(ctx);
-  CHECK(install_terms(ctx, q, c, al, be, &dal, &dbe));
+  CHECK(install_terms(ctx, q, c, al, be, &dal, &dbe, ci.empty() ? nullptr : &ci));
   ctx->quad = q;
   return LRS_OK;
 }
@@ -992,6 +1022,8 @@ lrs_status lrs_compute_chi0_backward(lrs_ctx* ctx, int cols, int prec, const dou
   if (dL_dpsi_grid) return fail(ctx, LRS_EUNSUPPORTED, "site blocks do not depend on grid orbitals");
   if (!dL_dchi0 || !dL_dE || !dL_dpsi_site) return fail(ctx, LRS_EINVAL, "missing gradient buffers");
   if (!ctx->quad.has_deriv) return fail(ctx, LRS_EUNSUPPORTED, "generic terms carry no energy derivative");
+  if (!ctx->quad.ci.empty())
+    return fail(ctx, LRS_EUNSUPPORTED, "the adjoint covers the static polarizability only");
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   HIP_OR_FAIL(ctx, hipStreamIsCapturing(ctx->stream, &cs));

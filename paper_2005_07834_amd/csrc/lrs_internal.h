@@ -94,6 +94,8 @@ struct Quad {
   double scale = 0;       // C (time) or zeta (freq)
   std::vector<double> c;        // per-term coefficient after weight normalisation
   std::vector<double> c_raw;    // per-term coefficient as constructed
+  std::vector<double> ci;       // imaginary parts after normalisation (imaginary frequency)
+  double omega = 0;             // imaginary frequency of the rule (0: static)
   std::vector<double> tau;      // tau (time) or t (freq) per term
   std::vector<double> w;        // [T][K_pad] normalised alpha | beta (zero padded)
   std::vector<double> dw;       // [T][K_pad] d(weight)/d(energy) with mu fixed
@@ -150,6 +152,7 @@ struct lrs_ctx {
   bool have_quad = false;
   lrs::Quad quad;
   lrs::DevBuf w_nat, c_dev;       // weights [T][K_pad] (natural K order), coefficients [T]
+                                  // (then their imaginary parts [T] when the rule has them)
   int quad_version = 0;
 
   // plans
@@ -174,6 +177,7 @@ namespace lrs {
 void gauss_legendre_01(int n, std::vector<double>& a, std::vector<double>& w);
 double time_rule_error(double scale, int n, double dmin, double dmax);
 double time_auto_scale(double dmin, double dmax, int n);
+double time_auto_scale_iw(double dmin, double dmax, int n, double omega);
 
 // pack.hip
 hipError_t launch_pack_tiles(const double* psi, int nk, int nb, int nocc, int ncols, int ld_src,
@@ -202,10 +206,13 @@ hipError_t launch_prep_site(int prec, const double* site, int rows_pad, int K_pa
                             int nt, double a_scale, void* out, hipStream_t s);
 // sym: site x site blocks, listed from their upper triangle (TileDesc.pad set): each element
 // on or above the diagonal is also stored at its transposed place
+// ci: imaginary parts of the term coefficients (null: real); sym must be 0 then (the odd
+// part of chi0 at imaginary frequency is antisymmetric on a site block)
 hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int a_nrb,
-                       const void* b_tiles, int b_ncb, int nch, const double* c, int T,
-                       int nch_o, const TileDesc* tiles, int ntiles, double* out, double pref,
-                       int sym, unsigned int* sync, void* park, hipStream_t s);
+                       const void* b_tiles, int b_ncb, int nch, const double* c,
+                       const double* ci, int T, int nch_o, const TileDesc* tiles, int ntiles,
+                       double* out, double pref, int sym, unsigned int* sync, void* park,
+                       hipStream_t s);
 // adjoint Green's functions of one term on site blocks: prec LRS_FP64 writes Hu, Ho as FP64
 // planes (hu_re, hu_im, ho_re, ho_im; row stride ld); LRS_BF16X2 writes each at hs_u, hs_o
 // as bfloat16 hi/lo in the split adjoint GEMM's operand tiles (h_tile_offset)

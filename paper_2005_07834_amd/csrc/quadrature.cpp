@@ -75,6 +75,54 @@ double rule_error(double scale, const std::vector<double>& a, const std::vector<
   }
   return worst;
 }
+
+// The same for the even kernel Delta / (Delta^2 + omega^2) at imaginary frequency omega, with
+// the coefficients times cos(omega tau_j): the worst |K (Delta^2 + omega^2) / Delta - 1|.
+double rule_error_iw(double scale, const std::vector<double>& a, const std::vector<double>& w,
+                     double dmin, double dmax, double omega, double stop) {
+  const int n = (int)a.size();
+  std::vector<double> tau(n), c(n);
+  for (int j = 0; j < n; ++j) {
+    tau[j] = scale * a[j] / (1.0 - a[j]);
+    c[j] = scale * w[j] / ((1.0 - a[j]) * (1.0 - a[j])) * std::cos(omega * tau[j]);
+  }
+  double worst = 0;
+  for (int i = 0; i < kGapSamples; ++i) {
+    const int smp = i == 0 ? 0 : (i == 1 ? kGapSamples - 1 : i - 1);
+    const double d = std::exp(std::log(dmin) + (std::log(dmax) - std::log(dmin)) * smp /
+                                                   (kGapSamples - 1));
+    double k = 0;
+    for (int j = 0; j < n; ++j) k += c[j] * std::exp(-d * tau[j]);
+    worst = std::fmax(worst, std::fabs(k * (d * d + omega * omega) / d - 1.0));
+    if (worst >= stop) break;
+  }
+  return worst;
+}
+}  // namespace
+
+namespace {
+// candidate scan shared by the static and the imaginary-frequency rules (see time_auto_scale)
+template <class Err>
+double scan_scale(double dmin, double dmax, Err err) {
+  const double g = std::sqrt(dmin * dmax);
+  double best = HUGE_VAL;
+  int best_j = 0;
+  bool have = false;
+  auto consider = [&](int j) {
+    const double s = std::pow(10.0, j / 40.0) / g;
+    const double stop = !have ? HUGE_VAL : (j < best_j ? std::nextafter(best, HUGE_VAL) : best);
+    const double e = err(s, stop);
+    if (!have || e < best || (e == best && j < best_j)) {
+      best = e;
+      best_j = j;
+      have = true;
+    }
+  };
+  for (int j = -80; j <= 100; j += 10) consider(j);
+  for (int j = -80; j <= 100; ++j)
+    if ((j + 80) % 10 != 0) consider(j);
+  return std::pow(10.0, best_j / 40.0) / g;
+}
 }  // namespace
 
 double time_rule_error(double scale, int n, double dmin, double dmax) {
@@ -90,25 +138,19 @@ double time_rule_error(double scale, int n, double dmin, double dmax) {
 double time_auto_scale(double dmin, double dmax, int n) {
   std::vector<double> a, w;
   gauss_legendre_01(n, a, w);
-  const double g = std::sqrt(dmin * dmax);
-  double best = HUGE_VAL;
-  int best_j = 0;
-  bool have = false;
-  auto consider = [&](int j) {
-    const double s = std::pow(10.0, j / 40.0) / g;
-    // a smaller j wins a tie, so it is kept going until it exceeds the best
-    const double stop = !have ? HUGE_VAL : (j < best_j ? std::nextafter(best, HUGE_VAL) : best);
-    const double e = rule_error(s, a, w, dmin, dmax, stop);
-    if (!have || e < best || (e == best && j < best_j)) {
-      best = e;
-      best_j = j;
-      have = true;
-    }
-  };
-  for (int j = -80; j <= 100; j += 10) consider(j);
-  for (int j = -80; j <= 100; ++j)
-    if ((j + 80) % 10 != 0) consider(j);
-  return std::pow(10.0, best_j / 40.0) / g;
+  return scan_scale(dmin, dmax, [&](double s, double stop) {
+    return rule_error(s, a, w, dmin, dmax, stop);
+  });
+}
+
+// The same scan with the imaginary-frequency error model (the static scan at omega = 0).
+double time_auto_scale_iw(double dmin, double dmax, int n, double omega) {
+  if (omega == 0.0) return time_auto_scale(dmin, dmax, n);
+  std::vector<double> a, w;
+  gauss_legendre_01(n, a, w);
+  return scan_scale(dmin, dmax, [&](double s, double stop) {
+    return rule_error_iw(s, a, w, dmin, dmax, omega, stop);
+  });
 }
 
 }  // namespace lrs
