@@ -140,6 +140,27 @@ def chi0_iw_quad_entries(psi_r, psi_c, nocc, spin, cc, cs, alpha, beta):
     return -2.0 * spin / nk ** 2 * (ev.real - od.imag)
 
 
+def chi0_iw_exact_entries(psi_r, psi_c, E, nocc, omega, spin=2, mu=None):
+    """chi0_iw_exact at individual entries (psi_r, psi_c as in pair_sum_entries): the even
+    kernel Delta / (Delta^2 + omega^2) on Re P and the odd kernel omega / (Delta^2 + omega^2)
+    on Im P, per band pair."""
+    if mu is None:
+        mu = q.mid_gap(E, nocc)
+    x, y = q.offsets(E, nocc, mu)
+    nk = psi_r.shape[0]
+    ev = np.zeros(psi_r.shape[2], dtype=np.complex128)
+    od = np.zeros(psi_r.shape[2], dtype=np.complex128)
+    for k in range(nk):
+        a = np.conj(psi_r[k, :nocc]) * psi_c[k, :nocc]               # [nocc, E]
+        for kp in range(nk):
+            b = psi_r[kp, nocc:] * np.conj(psi_c[kp, nocc:])         # [nu, E]
+            d = x[k][:, None] + y[kp][None, :]
+            den = d * d + omega * omega
+            ev += np.einsum("ne,ne->e", a, (d / den) @ b)
+            od += np.einsum("ne,ne->e", a, (omega / den) @ b)
+    return -2.0 * spin / nk ** 2 * (ev.real - od.imag)
+
+
 def chi0_exact_entries(psi_r, psi_c, E, nocc, spin=2, mu=None, delta=0.0):
     return pair_sum_entries(psi_r, psi_c, nocc, spin, exact_kernel(E, nocc, mu, delta))
 

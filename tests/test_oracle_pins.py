@@ -590,3 +590,19 @@ def test_iw_entries_match_blocks(tiny):
     c = rng.integers(0, ps.shape[2], 40)
     ent = cz.chi0_iw_quad_entries(ps[:, :, r], ps[:, :, c], w.nocc, 2, cc, cs, al, be)
     assert np.abs(ent - blk[r, c]).max() < 1e-13 * np.abs(blk).max()
+
+
+def test_iw_exact_entries_match_blocks():
+    """The per-entry exact imaginary-frequency sum equals the block sum at those entries, on
+    the production cell where the odd part is not zero (entries and their transposes)."""
+    p = workload("production", with_grid=False)
+    pp = p.psi_site.numpy()[:, :, :120]
+    ex, odd = cz.chi0_iw_exact(pp, pp, p.energies, p.nocc, 0.05)
+    assert odd > 1e-5 * np.abs(ex).max()
+    rng = np.random.default_rng(6)
+    r = rng.integers(0, 120, 30)
+    c = rng.integers(0, 120, 30)
+    rr, cc = np.concatenate([r, c]), np.concatenate([c, r])
+    ent = cz.chi0_iw_exact_entries(pp[:, :, rr], pp[:, :, cc], p.energies, p.nocc, 0.05)
+    assert np.abs(ent - ex[rr, cc]).max() < 1e-13 * np.abs(ex).max()
+    assert np.abs(ent[:30] - ent[30:]).max() > 1e-6 * np.abs(ex).max()
