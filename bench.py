@@ -2,13 +2,18 @@
 
 One step = one pass of the hot path over one synthetic input:
   quadrature terms (host) -> chi0 site x grid (the headline) -> chi0 site x site ->
-  W solve with a test-charge loss -> adjoint of the solve -> adjoint of chi0 (FP64).
+  W solve with a test-charge loss -> adjoint of the solve -> adjoint of chi0 (split
+  products when chi0 runs split, else FP64).
 Inputs (orbitals on the grid and at the site points, packed into the library's layouts)
 are resident in HBM before the timed region.
 
 Prints one JSON line.  `value` = chi0 (site x grid) entries per second of step time.
 The FP64 path is timed once beside it (speedup), sampled entries of both are compared
-with the CPU oracle, and the oracle itself is timed on the host (cpu_baseline).
+with the CPU oracle, and the oracle itself is timed on the host (cpu_baseline).  After the
+steps, once each: the FP16 split launch, the FP64 adjoint (against the split one), the
+per-site solves beside W (ALDA W, induced potential), chi0 at imaginary frequency on the
+same launch (sampled entries against the oracle) and the projection of the plane-wave
+orbitals onto the site points.
 """
 from __future__ import annotations
 
@@ -85,12 +90,13 @@ def main():
     ap.add_argument("--no-fp16", action="store_true",
                     help="skip the one FP16X2 launch run beside a BF16X2 bench")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-projection", action="store_true",
                     help="skip the plane-wave -> site-point projection timed after the steps")
     ap.add_argument("--adjoint-prec", default="auto", choices=["auto", "fp64", "bf16x2"],
                     help="precision of the adjoint's products (auto: bf16x2 with --prec bf16x2, "
                          "else fp64)")
+    ap.add_argument("--omega", type=float, default=0.1,
+                    help="imaginary frequency (Ha) of the chi0(i omega) launch run after the steps")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
@@ -106,6 +112,7 @@ def main():
     import torch
     import paper_2005_07834_amd as P
     from workloads import configs
+    from workloads.crystal import valence_density
 
     dev = "cuda"
     t0 = time.time()
@@ -168,15 +175,13 @@ def main():
         kms = ctx.last_kernel_ms()
         chi_ss = ctx.chi0(-1, P.COLS_SITE, prec)
         W, loss = ctx.screen_W(chi_ss, rho=rho, want_loss=True)
-        if not args.no_adjoint:
-            lam = ctx.screen_W_backward()
-            dE, dpsi = ctx.chi0_backward(lam, adj_prec)
+        lam = ctx.screen_W_backward()
+        dE, dpsi = ctx.chi0_backward(lam, adj_prec)
         torch.cuda.synchronize()
         if record:
             comp.setdefault("kernel_ms", []).append(kms)
             comp.setdefault("step_ms", []).append((time.time() - tq) * 1e3)
-            if not args.no_adjoint:
-                comp["adjoint"] = (lam, dE, dpsi)
+            comp["adjoint"] = (lam, dE, dpsi)
         return loss
 
     for _ in range(args.warmup):
@@ -193,6 +198,7 @@ def main():
     kern_ms = float(np.mean(comp["kernel_ms"]))
     got_low = out_grid[torch.as_tensor(rows, device=dev), torch.as_tensor(cols, device=dev)].cpu().numpy()
     log(f"step {ms_per_step:.1f} ms; chi0 kernel ({prec}) {kern_ms:.1f} ms")
+    qd = ctx.get_quadrature()      # the static rule of the timed steps
 
     # FP64 path once, for the speedup and the error statement
     fp64 = {}
@@ -216,18 +222,49 @@ def main():
         fp16 = dict(kernel_ms=ms16, entries_per_s=entries / (ms16 / 1e3))
         log(f"fp16x2 chi0 kernel {ms16:.1f} ms")
     # the split adjoint against the FP64 adjoint on the last step's dL/dchi0
-    adjoint = None
-    if not args.no_adjoint:
-        adjoint = {"precision": adj_prec}
-        if adj_prec != "fp64" and not args.no_fp64:
-            lam, dE, dpsi = comp.pop("adjoint")
-            ctx.make_quadrature(P.QUAD_TIME, w.n_terms, 0.0)
-            dE64, dpsi64 = ctx.chi0_backward(lam, "fp64")
-            adjoint["dE_rel_vs_fp64"] = float((dE - dE64).abs().max() / dE64.abs().max())
-            adjoint["dpsi_rel_vs_fp64"] = float((dpsi - dpsi64).abs().max() / dpsi64.abs().max())
-            del dE64, dpsi64
-            log("adjoint", adjoint)
-        comp.pop("adjoint", None)
+    adjoint = {"precision": adj_prec}
+    if adj_prec != "fp64" and not args.no_fp64:
+        lam, dE, dpsi = comp.pop("adjoint")
+        ctx.make_quadrature(P.QUAD_TIME, w.n_terms, 0.0)
+        dE64, dpsi64 = ctx.chi0_backward(lam, "fp64")
+        adjoint["dE_rel_vs_fp64"] = float((dE - dE64).abs().max() / dE64.abs().max())
+        adjoint["dpsi_rel_vs_fp64"] = float((dpsi - dpsi64).abs().max() / dpsi64.abs().max())
+        del dE64, dpsi64
+        log("adjoint", adjoint)
+    comp.pop("adjoint", None)
+    # the per-site solves beside W (ALDA W, induced potential of a spherical perturbation) on
+    # this workload's site block, per call on the library stream
+    ctx.make_quadrature(P.QUAD_TIME, w.n_terms, 0.0)
+    chi_ss = ctx.chi0(-1, P.COLS_SITE, prec)
+    dens = valence_density(w.psi_site, w.nocc)
+
+    def per_call_ms(fn, reps=10):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    solves = {"sites": len(w.sites), "basis": [9 * st.n_rad for st in w.sites],
+              "screen_W_ms": per_call_ms(lambda: ctx.screen_W(chi_ss)),
+              "screen_W_alda_ms": per_call_ms(lambda: ctx.screen_W_alda(chi_ss, dens)),
+              "induced_ms": per_call_ms(lambda: ctx.induced_potential(chi_ss, q=1.0, r_shell=1.5)),
+              "induced_l0_ms": per_call_ms(lambda: ctx.induced_potential(chi_ss, q=1.0, r_shell=1.5,
+                                                                         l0_only=True))}
+    del chi_ss
+    log("site solves", solves)
+    # chi0 at imaginary frequency i omega: the same site x grid launch with complex term
+    # coefficients, once
+    ctx.make_quadrature_iw(w.n_terms, 0.0, args.omega)
+    ctx.chi0(-1, P.COLS_GRID, prec, out=out_grid)
+    iw = {"omega": args.omega, "terms": w.n_terms, "precision": prec,
+          "kernel_ms": ctx.last_kernel_ms(), "scale": ctx.get_quadrature()["scale"]}
+    iw["vs_static_kernel"] = iw["kernel_ms"] / kern_ms
+    got_iw = out_grid[torch.as_tensor(rows, device=dev), torch.as_tensor(cols, device=dev)].cpu().numpy()
+    log(f"chi0(i omega) kernel {iw['kernel_ms']:.1f} ms")
     # the projection of the plane-wave orbitals onto the site points (the step before the
     # packing), once, outside the timed steps
     proj = None
@@ -251,7 +288,6 @@ def main():
                     float((psi_p - w.psi_site).abs().max() / w.psi_site.abs().max())}
         del psi_p, coef
         log("projection", proj)
-    qd = ctx.get_quadrature()
     ctx.close()
     del out_grid
     torch.cuda.empty_cache()
@@ -300,6 +336,14 @@ def main():
         errs["quadrature_vs_exact"] = rel(qq, ex)
         errs["entries_compared"] = int(ns)
         log("errors", errs)
+        tiw = cz.terms_for(w.energies, w.nocc, f"time_iw:{args.omega}", w.n_terms, iw["scale"], mu)
+        qiw = cz.chi0_iw_quad_entries(ps_s, pg_s, w.nocc, 2, *tiw)
+        exiw = cz.chi0_iw_exact_entries(ps_s, pg_s, w.energies, w.nocc, args.omega, mu=mu)
+        iw["rel_err_vs_same_quadrature"] = rel(got_iw, qiw)
+        iw["rel_err_vs_exact"] = rel(got_iw, exiw)
+        iw["quadrature_vs_exact"] = rel(qiw, exiw)
+        iw["entries_compared"] = int(ns)
+        log("chi0(i omega)", iw)
 
     rec = {
         "metric": "chi0 entries/s + MFMA util: split-BF16 vs FP64 GPU path at stated rel. error",
@@ -318,8 +362,7 @@ def main():
                    "rows": nrows, "grid_columns": ncols, "kpoints": nk, "bands": nb,
                    "occupied": w.nocc, "terms": w.n_terms,
                    "step": "quadrature + chi0 site x grid + chi0 site x site + W + loss + "
-                           + (f"adjoints ({adj_prec} products)" if not args.no_adjoint
-                              else "no adjoint")},
+                           + f"adjoints ({adj_prec} products)"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "traffic_gb_per_s": traffic / (kern_ms / 1e3) / 1e9 if traffic else None,
@@ -336,6 +379,8 @@ def main():
         "rel_err": errs,
         "adjoint": adjoint,
         "projection": proj,
+        "imag_freq": iw,
+        "site_solves": solves,
         "pack_ms": pack_ms,
         "loss": float(loss.sum().item()),
     }
