@@ -83,88 +83,154 @@ __global__ void eps_kernel(ScreenTabs T, const int2* rows, const double* X, doub
   const double* r = T.radii + m.rad_off;
   const double* u = T.u + m.rad_off;
   const double* x = X + m.w_off;
-  double* out = M + 2 * m.w_off + (long long)row * 2 * n;
+  double* out = M + 2 * m.w_off + row;   // column-major: element (row, c) at c * n
   for (int c = threadIdx.x; c < 2 * n; c += blockDim.x) {
     if (c < n) {
       const int j = c % R;
       double s = 0;
       for (int q = 0; q < R; ++q) s += coulomb_l(l, r[i], r[q]) * u[q] * x[(long long)(L * R + q) * n + c];
-      out[c] = (c == row ? 1.0 : 0.0) - s * u[j];
+      out[(long long)c * n] = (c == row ? 1.0 : 0.0) - s * u[j];
     } else {
       const int cc = c - n, Lp = cc / R, j = cc % R;
-      out[c] = Lp == L ? coulomb_l(l, r[i], r[j]) : 0.0;
+      out[(long long)c * n] = Lp == L ? coulomb_l(l, r[i], r[j]) : 0.0;
     }
   }
 }
 
-// Gauss-Jordan with partial pivoting on the augmented matrix of one site (at M + 2 w_off):
-//   mode 0: [eps | V], n x 2n, the right block (W) goes to out + w_out_off[site]
-//   mode 1: [eps | v1], n x (n + 1), the last column (y) goes to out + h_off
-//   mode 2: as 1 on the 00;00 block, n_rad x (n_rad + 1)
+// Gauss-Jordan with partial pivoting on the augmented matrix of one site, stored column-major
+// at M + 2 w_off (column c at c * n, n rows):
+//   mode 0: [eps | V], 2n columns; the right block (W) goes to out + w_out_off[site], row-major
+//   mode 1: [eps | v1], n + 1 columns; the last column (y) goes to out + h_off
+//   mode 2: as 1 on the 00;00 block (n_rad rows)
+// One workgroup per site, blocked by panels of GJ_NB columns.  The panel is eliminated in LDS:
+// at each of its steps the pivot row is swapped into place across the whole panel (the
+// multipliers of earlier steps included, so that they end up in the final row order) and the
+// step's column keeps its multipliers.  Then every later column is read once, in the panel's
+// final row order, takes the panel's nb elimination steps in registers and is written back
+// (a wave updates four columns at a time, sharing the multipliers read from LDS).  The columns
+// left of the panel are unit vectors by then and are not touched again.
+constexpr int GJ_NB = 16, GJ_MAXN = 288, GJ_SLOTS = (GJ_MAXN + 63) / 64, GJ_COLS = 4;
+
+// a column spread over the lanes of a wave: row lane + 64 t in element t (t < GJ_SLOTS)
+typedef double gj_col __attribute__((ext_vector_type(8)));
+
+// value of row `row` (wave-uniform) of such a column: a register-indexed read of element
+// row / 64, then lane row % 64
+__device__ __forceinline__ double gj_row_value(const gj_col& x, int row) {
+  const double v = x[row >> 6];
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, row & 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), row & 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __global__ void __launch_bounds__(1024) gauss_jordan_kernel(ScreenTabs T, double* M, int mode,
                                                             double* out,
                                                             const long long* w_out_off) {
-  __shared__ double fac[288 + 32];
-  __shared__ double red_v[1024 / 64];
-  __shared__ int red_i[1024 / 64];
+  __shared__ double pan[GJ_NB][GJ_MAXN];
+  __shared__ int perm[GJ_MAXN];
+  __shared__ double inv_s[GJ_NB];
   __shared__ int piv_s;
   const SiteMeta m = T.meta[blockIdx.x];
   const int n = mode == 2 ? m.nrad : m.n, n2 = n + (mode == 0 ? n : 1);
   double* A = M + 2 * m.w_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-  for (int col = 0; col < n; ++col) {
-    // pivot: the largest |A[r][col]| for r >= col (lowest row on ties)
-    double best = -1.0;
-    int bi = col;
-    for (int r = col + tid; r < n; r += blockDim.x) {
-      double v = fabs(A[(long long)r * n2 + col]);
-      if (v > best) { best = v; bi = r; }
+  for (int j0 = 0; j0 < n; j0 += GJ_NB) {
+    const int nb = min(GJ_NB, n - j0);
+    for (int it = tid; it < nb * n; it += blockDim.x) {
+      const int k = it / n, r = it - k * n;
+      pan[k][r] = A[(long long)(j0 + k) * n + r];
     }
-    for (int o = 32; o > 0; o >>= 1) {
-      double ov = __shfl_xor(best, o);
-      int oi = __shfl_xor(bi, o);
-      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-    }
-    if (lane == 0) { red_v[wave] = best; red_i[wave] = bi; }
+    for (int r = tid; r < n; r += blockDim.x) perm[r] = r;
     __syncthreads();
-    if (tid == 0) {
-      double b = red_v[0];
-      int p = red_i[0];
-      for (int w = 1; w < nw; ++w)
-        if (red_v[w] > b || (red_v[w] == b && red_i[w] < p)) { b = red_v[w]; p = red_i[w]; }
-      piv_s = p;
-    }
-    __syncthreads();
-    const int p = piv_s;
-    if (p != col)
-      for (int c = tid; c < n2; c += blockDim.x) {
-        double a = A[(long long)col * n2 + c];
-        A[(long long)col * n2 + c] = A[(long long)p * n2 + c];
-        A[(long long)p * n2 + c] = a;
+    for (int k = 0; k < nb; ++k) {
+      const int col = j0 + k;
+      if (wave == 0) {
+        // pivot: the largest |pan[k][r]| for r >= col (lowest row on ties)
+        double best = -1.0;
+        int bi = col;
+        for (int r = col + lane; r < n; r += 64) {
+          const double v = fabs(pan[k][r]);
+          if (v > best) { best = v; bi = r; }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+          const double ov = __shfl_xor(best, o);
+          const int oi = __shfl_xor(bi, o);
+          if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+        }
+        if (lane == 0) piv_s = bi;
       }
+      __syncthreads();
+      const int p = piv_s;
+      if (p != col) {
+        if (tid < nb) {
+          const double t = pan[tid][col];
+          pan[tid][col] = pan[tid][p];
+          pan[tid][p] = t;
+        }
+        if (tid == 0) {
+          const int t = perm[col];
+          perm[col] = perm[p];
+          perm[p] = t;
+        }
+      }
+      __syncthreads();
+      // eliminate column col from the other rows of the later panel columns
+      const double inv = 1.0 / pan[k][col];
+      const int width = nb - k - 1;
+      for (int it = tid; it < width * n; it += blockDim.x) {
+        const int kk = k + 1 + it / n, r = it % n;
+        if (r != col) pan[kk][r] -= pan[k][r] * (pan[kk][col] * inv);
+      }
+      __syncthreads();
+      // scale the pivot row (read by no one until the next step's elimination)
+      if (tid < width) pan[k + 1 + tid][col] *= inv;
+      if (tid == 0) inv_s[k] = inv;
+    }
     __syncthreads();
-    const double inv = 1.0 / A[(long long)col * n2 + col];
-    for (int r = tid; r < n; r += blockDim.x) fac[r] = A[(long long)r * n2 + col];
-    __syncthreads();
-    for (int c = col + tid; c < n2; c += blockDim.x) A[(long long)col * n2 + c] *= inv;
-    __syncthreads();
-    // eliminate column col from every other row (columns > col of the left block, all of the right)
-    const int width = n2 - col - 1;
-    for (long long it = tid; it < (long long)n * width; it += blockDim.x) {
-      const int r = (int)(it / width);
-      const int c = col + 1 + (int)(it % width);
-      if (r != col) A[(long long)r * n2 + c] -= fac[r] * A[(long long)col * n2 + c];
+    // the later columns, GJ_COLS per wave at a time
+    const int c0 = j0 + nb;
+    for (int g = c0 + wave * GJ_COLS; g < n2; g += nw * GJ_COLS) {
+      gj_col x[GJ_COLS];
+#pragma unroll
+      for (int q = 0; q < GJ_COLS; ++q)
+#pragma unroll
+        for (int t = 0; t < GJ_SLOTS; ++t) {
+          const int r = lane + 64 * t;
+          x[q][t] = (g + q < n2 && r < n) ? A[(long long)(g + q) * n + perm[r]] : 0.0;
+        }
+      for (int k = 0; k < nb; ++k) {
+        const int col = j0 + k;
+        const double inv = inv_s[k];
+        double xp[GJ_COLS];
+#pragma unroll
+        for (int q = 0; q < GJ_COLS; ++q) xp[q] = gj_row_value(x[q], col) * inv;
+#pragma unroll
+        for (int t = 0; t < GJ_SLOTS; ++t) {
+          const int r = lane + 64 * t;
+          const double f = r < n ? pan[k][r] : 0.0;
+#pragma unroll
+          for (int q = 0; q < GJ_COLS; ++q) x[q][t] = r == col ? xp[q] : x[q][t] - f * xp[q];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < GJ_COLS; ++q)
+#pragma unroll
+        for (int t = 0; t < GJ_SLOTS; ++t) {
+          const int r = lane + 64 * t;
+          if (g + q < n2 && r < n) A[(long long)(g + q) * n + r] = x[q][t];
+        }
     }
     __syncthreads();
   }
   if (mode == 0) {
     double* W = out + w_out_off[blockIdx.x];
-    for (long long it = tid; it < (long long)n * n; it += blockDim.x) {
-      const int r = (int)(it / n), c = (int)(it % n);
-      W[it] = A[(long long)r * n2 + n + c];
+    for (int it = tid; it < n * n; it += blockDim.x) {
+      const int c = it / n, r = it - c * n;
+      W[(long long)r * n + c] = A[(long long)(n + c) * n + r];
     }
   } else {
-    for (int r = tid; r < n; r += blockDim.x) out[m.h_off + r] = A[(long long)r * n2 + n];
+    for (int r = tid; r < n; r += blockDim.x) out[m.h_off + r] = A[(long long)n * n + r];
   }
 }
 
@@ -181,16 +247,16 @@ __global__ void induced_rows_kernel(ScreenTabs T, const int2* rows, const double
   const double* r = T.radii + m.rad_off;
   const double* u = T.u + m.rad_off;
   const double* x = X + m.w_off;
-  double* out = M + 2 * m.w_off + (long long)row * (sz + 1);
+  double* out = M + 2 * m.w_off + row;   // column-major: element (row, c) at c * sz
   for (int c = threadIdx.x; c <= sz; c += blockDim.x) {
     if (c < sz) {
       const int j = c % R;
       double acc = 0;
       for (int q = 0; q < R; ++q) acc += coulomb_l(l, r[i], r[q]) * u[q] * x[(long long)(L * R + q) * n + c];
-      out[c] = (c == row ? 1.0 : 0.0) - acc * u[j];
+      out[(long long)c * sz] = (c == row ? 1.0 : 0.0) - acc * u[j];
     } else {
       // the Y_00 coefficient of the spherical v1
-      out[c] = L == 0 ? 2.0 * sqrt(3.14159265358979323846) * v1[m.rad_off + i] : 0.0;
+      out[(long long)c * sz] = L == 0 ? 2.0 * sqrt(3.14159265358979323846) * v1[m.rad_off + i] : 0.0;
     }
   }
 }
@@ -278,17 +344,17 @@ __global__ void alda_rows_kernel(ScreenTabs T, const int2* rows, const double* X
   const double* u = T.u + m.rad_off;
   const double* x = X + m.w_off;
   const double* fi = F + (long long)m.h_off * nL + (long long)i * nL * nL + L * nL;
-  double* out = M + 2 * m.w_off + (long long)row * 2 * n;
+  double* out = M + 2 * m.w_off + row;   // column-major: element (row, c) at c * n
   for (int c = threadIdx.x; c < 2 * n; c += blockDim.x) {
     if (c < n) {
       const int j = c % R;
       double acc = 0;
       for (int q = 0; q < R; ++q) acc += coulomb_l(l, r[i], r[q]) * u[q] * x[(long long)(L * R + q) * n + c];
       for (int Lp = 0; Lp < nL; ++Lp) acc += fi[Lp] * x[(long long)(Lp * R + i) * n + c];
-      out[c] = (c == row ? 1.0 : 0.0) - acc * u[j];
+      out[(long long)c * n] = (c == row ? 1.0 : 0.0) - acc * u[j];
     } else {
       const int cc = c - n, Lp = cc / R, j = cc % R;
-      out[c] = Lp == L ? coulomb_l(l, r[i], r[j]) : 0.0;
+      out[(long long)c * n] = Lp == L ? coulomb_l(l, r[i], r[j]) : 0.0;
     }
   }
 }
