@@ -16,6 +16,14 @@ the loss's dependence on chi0 is Q = P_f sum |M|^2 K_{nk,mk'} and
 (complex gradients as dL/dRe + i dL/dIm).  Exact denominators: K = 1/Delta,
 dK/de_n = 1/Delta^2, dK/de_m = -1/Delta^2.  Imaginary-time terms with mu and
 the nodes held fixed: dK/de_n = sum_l c_l tau_l alpha beta, dK/de_m = -that.
+
+At imaginary frequency (complex kernel z = K_e + i K_o per pair, chi0 = P_f sum
+Re[z rho(r) conj(rho(c))] with rho = psi_nk* psi_mk'), for a linear functional
+L = sum_{r,c} Lambda(r, c) chi0(r, c) with an arbitrary real Lambda per site block:
+    M = rho^T Lambda conj(rho),   L = P_f sum Re[z M],   dL/de = P_f sum Re[(dz/de) M]
+    grad psi_nk(p)  = P_f sum_{m,k'} psi_mk'(p) [z (Lambda conj(rho))(p) + conj(z) (Lambda^T conj(rho))(p)]
+    grad psi_mk'(p) = P_f sum_{n,k}  psi_nk(p)  [z (Lambda^T rho)(p) + conj(z) (Lambda rho)(p)]
+(``linear_grads_iw``; Wirtinger derivatives, gradients as dL/dRe + i dL/dIm).
 """
 from __future__ import annotations
 
@@ -102,4 +110,57 @@ def loss_and_grads(psi_site, E, nocc, spin, sites, rho, kind="exact", n_terms=No
                 dE[kp, nocc:] += Pf * (M2 * dKm).sum(0)
                 dpsi[k, :nocc, sl] += 2 * Pf * g[None, :] * ((np.conj(M) * Km) @ pu[kp])
                 dpsi[kp, nocc:, sl] += 2 * Pf * g[None, :] * ((M * Km).T @ po[k])
+    return L, dE, dpsi
+
+
+def iw_terms(E, nocc, n, scale, omega, mu=None):
+    """Imaginary-time terms at i omega: (cc, cs, alpha, beta, tau) with cc = c cos(omega tau),
+    cs = c sin(omega tau) (oracle.quadrature)."""
+    if mu is None:
+        mu = q.mid_gap(E, nocc)
+    x, y = q.offsets(E, nocc, mu)
+    c, al, be, tau = q.imag_time_terms(x, y, n, scale)
+    return c * np.cos(omega * tau), c * np.sin(omega * tau), al, be, tau
+
+
+def linear_loss_iw(psi_site, nocc, spin, sites, lam_blocks, cc, cs, al, be):
+    """L = sum_sites sum_{r,c} Lambda_s(r, c) chi0_iw(r, c) with the quadrature chi0."""
+    total = 0.0
+    for sl, lam in zip(site_slices(sites), lam_blocks):
+        ps = psi_site[:, :, sl]
+        total += float((lam * cz.chi0_iw_quad(ps, ps, nocc, spin, cc, cs, al, be)).sum())
+    return total
+
+
+def linear_grads_iw(psi_site, E, nocc, spin, sites, lam_blocks, n, scale, omega, mu=None):
+    """(L, dL/dE [nk, nb], dL/dpsi_site complex [nk, nb, npts]) for the linear functional of
+    chi0(i omega) above; mu and the nodes held fixed."""
+    cc, cs, al, be, tau = iw_terms(E, nocc, n, scale, omega, mu)
+    nk = E.shape[0]
+    Pf = -2.0 * spin / nk ** 2
+    dE = np.zeros_like(E)
+    dpsi = np.zeros_like(psi_site)
+    L = 0.0
+    for sl, lam in zip(site_slices(sites), lam_blocks):
+        po = psi_site[:, :nocc, sl]
+        pu = psi_site[:, nocc:, sl]
+        for k in range(nk):
+            for kp in range(nk):
+                z = (np.einsum("l,ln,lm->nm", cc, al[:, k], be[:, kp])
+                     + 1j * np.einsum("l,ln,lm->nm", cs, al[:, k], be[:, kp]))
+                dz = (np.einsum("l,ln,lm->nm", cc * tau, al[:, k], be[:, kp])
+                      + 1j * np.einsum("l,ln,lm->nm", cs * tau, al[:, k], be[:, kp]))
+                rho = np.conj(po[k])[:, None, :] * pu[kp][None, :, :]     # [nocc, nu, p]
+                lr_c = np.conj(rho) @ lam.T           # (Lambda conj(rho))(p)
+                ltr_c = np.conj(rho) @ lam            # (Lambda^T conj(rho))(p)
+                M = np.einsum("nmp,nmp->nm", rho, lr_c)
+                L += Pf * float((z * M).real.sum())
+                dE[k, :nocc] += Pf * (dz * M).real.sum(1)
+                dE[kp, nocc:] -= Pf * (dz * M).real.sum(0)
+                dpsi[k, :nocc, sl] += Pf * np.einsum(
+                    "mp,nmp->np", pu[kp], z[:, :, None] * lr_c + np.conj(z)[:, :, None] * ltr_c)
+                lt_r = rho @ lam                      # (Lambda^T rho)(p)
+                l_r = rho @ lam.T                     # (Lambda rho)(p)
+                dpsi[kp, nocc:, sl] += Pf * np.einsum(
+                    "np,nmp->mp", po[k], z[:, :, None] * lt_r + np.conj(z)[:, :, None] * l_r)
     return L, dE, dpsi

@@ -606,3 +606,40 @@ def test_iw_exact_entries_match_blocks():
     ent = cz.chi0_iw_exact_entries(pp[:, :, rr], pp[:, :, cc], p.energies, p.nocc, 0.05)
     assert np.abs(ent - ex[rr, cc]).max() < 1e-13 * np.abs(ex).max()
     assert np.abs(ent[:30] - ent[30:]).max() > 1e-6 * np.abs(ex).max()
+
+
+def test_iw_linear_gradient_central_differences():
+    """The reference gradient of L = sum Lambda chi0(i omega) (arbitrary, non-symmetric Lambda;
+    complex term coefficients) against central differences of the oracle's own chi0(i omega)
+    in the energies and along random complex orbital directions."""
+    from workloads import sites as sx
+    rng = np.random.default_rng(8)
+    nk, nb, nocc, n, omega = 2, 10, 3, 24, 0.3
+    sites = [sx.make_site(np.zeros(3), 2, 6), sx.make_site(np.ones(3), 1, 6)]
+    npts = sum(s.npts for s in sites)
+    ps = rng.standard_normal((nk, nb, npts)) + 1j * rng.standard_normal((nk, nb, npts))
+    E = np.sort(rng.uniform(-1, 1, (nk, nb)), axis=1)
+    E[:, nocc:] += 0.5
+    lam = [rng.standard_normal((s.npts, s.npts)) for s in sites]
+    mu = q.mid_gap(E, nocc)
+    x, y = q.offsets(E, nocc, mu)
+    scale = q.auto_scale_iw(x, y, n, omega)
+    L, dE, dpsi = gr.linear_grads_iw(ps, E, nocc, 2, sites, lam, n, scale, omega, mu)
+
+    def Lf(pp, EE):
+        cc, cs, al, be, _ = gr.iw_terms(EE, nocc, n, scale, omega, mu)
+        return gr.linear_loss_iw(pp, nocc, 2, sites, lam, cc, cs, al, be)
+    assert abs(L - Lf(ps, E)) < 1e-12 * abs(L)
+    h = 1e-6
+    for k in range(nk):
+        for b in range(nb):
+            Ep, Em = E.copy(), E.copy()
+            Ep[k, b] += h
+            Em[k, b] -= h
+            fd = (Lf(ps, Ep) - Lf(ps, Em)) / (2 * h)
+            assert abs(fd - dE[k, b]) < 1e-6 * np.abs(dE).max()
+    for _ in range(3):
+        V = rng.standard_normal(ps.shape) + 1j * rng.standard_normal(ps.shape)
+        fd = (Lf(ps + h * V, E) - Lf(ps - h * V, E)) / (2 * h)
+        an = float((np.conj(dpsi) * V).real.sum())
+        assert abs(fd - an) < 1e-6 * abs(an)
