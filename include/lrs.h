@@ -157,9 +157,10 @@ lrs_status lrs_make_quadrature(lrs_ctx* ctx, int kind, int nnodes, double scale)
  * The scale (scale <= 0: automatic) minimises the rule's worst relative error on
  * Delta / (Delta^2 + omega^2) over the gap range; the rule loses accuracy once omega tau
  * oscillates within the decay of e^{-Delta tau} (omega well above the smallest gap).
- * Site x site blocks of chi0(i omega) are not symmetric (the odd part); the adjoint
- * (lrs_compute_chi0_backward) returns LRS_EUNSUPPORTED for these terms.  omega = 0 gives
- * exactly lrs_make_quadrature(LRS_QUAD_TIME, ...). */
+ * Site x site blocks of chi0(i omega) are not symmetric (the odd part); they are computed
+ * tile by tile over the whole block, and lrs_compute_chi0_backward differentiates them (mu,
+ * omega and the nodes held fixed).  omega = 0 gives exactly
+ * lrs_make_quadrature(LRS_QUAD_TIME, ...). */
 lrs_status lrs_make_quadrature_iw(lrs_ctx* ctx, int nnodes, double scale, double omega);
 
 /* Reads back the terms in use: c_host [nterms], tau_host [nterms] (tau for LRS_QUAD_TIME,
@@ -254,7 +255,10 @@ lrs_status lrs_screen_W_backward(lrs_ctx* ctx, const double* dL_dW, double* dL_d
  * Each term's G_o, G_u are recomputed rather than stored.  prec LRS_FP64 runs every product
  * in FP64; LRS_BF16X2 recomputes G and forms the products with psi in split bfloat16 (hi + lo,
  * FP32 accumulation; relative error of order 1e-5), with the gradient accumulation in FP64.
- * Other precisions: LRS_EUNSUPPORTED.  Requires terms from lrs_make_quadrature.
+ * Other precisions: LRS_EUNSUPPORTED.  Requires terms from lrs_make_quadrature or
+ * lrs_make_quadrature_iw (generic terms carry no energy derivative: LRS_EUNSUPPORTED).  With
+ * the imaginary-frequency terms dL/dchi0 may be any real matrix per block; with the static
+ * terms only its symmetric part matters (chi0 is symmetric there).
  * dL_dpsi_grid must be NULL (site blocks do not use grid orbitals).  Synchronous; under stream
  * capture it returns LRS_ESTATE. */
 lrs_status lrs_compute_chi0_backward(lrs_ctx* ctx, int cols, int prec, const double* dL_dchi0,

@@ -5,7 +5,11 @@
 //   dL/dpsi_K (K occupied)   = 2 P_f sum_l c_l alpha_l(K) [ (Lambda o conj(G_u^l)) psi_K ]
 //   dL/dpsi_K (K unoccupied) = 2 P_f sum_l c_l beta_l(K)  [ (Lambda o conj(G_o^l)) psi_K ]
 //   dL/de_K = P_f sum_l c_l (d weight_l(K)/d e_K) Re[ psi_K^H (Lambda o conj(G^l)) psi_K ]
-// (complex gradients as dL/dRe + i dL/dIm; mu and the nodes held fixed).  Each term's G's are
+// (complex gradients as dL/dRe + i dL/dIm; mu and the nodes held fixed).  With complex term
+// coefficients c_l + i s_l (chi0 at imaginary frequency, whose site block is not symmetric)
+// Lambda splits into its symmetric part Ls and antisymmetric part La, and c_l Lambda becomes
+// the Hermitian c_l Ls + i s_l La next to conj(G_u) and c_l Ls - i s_l La next to conj(G_o);
+// the energy partials take the real part as before.  Each term's G's are
 // recomputed on the matrix cores (the chi0 kernel in an adjoint mode writes
 // Lambda o conj(G) directly); the products with psi run as a complex MFMA GEMM (FP64, or
 // bfloat16 hi + lo with FP32 accumulation) whose epilogue accumulates the orbital gradient and
@@ -407,9 +411,11 @@ __global__ void split_psi_kernel(const double* psi, int rows_pad, int K_pad, con
 
 // lam = (A + A^T) / 2 per site, from the caller's n x n blocks (offsets blk_off) into blocks
 // with row stride npad (offsets pblk_off); the padding rows and columns are zero
+// symmetric part of each site block of lam into the padded layout, and the antisymmetric part
+// too where out_a is given
 __global__ void symmetrise_kernel(const double* lam, const long long* blk_off,
                                   const long long* pblk_off, const int* blk_n, int nsites,
-                                  double* out) {
+                                  double* out, double* out_a) {
   const int s = blockIdx.y;
   if (s >= nsites) return;
   const int n = blk_n[s], np = (n + kAdjAlign - 1) / kAdjAlign * kAdjAlign;
@@ -418,7 +424,10 @@ __global__ void symmetrise_kernel(const double* lam, const long long* blk_off,
   for (long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x; it < (long long)np * np;
        it += (long long)gridDim.x * blockDim.x) {
     const int r = (int)(it / np), c = (int)(it % np);
-    o[it] = (r < n && c < n) ? 0.5 * (a[(long long)r * n + c] + a[(long long)c * n + r]) : 0.0;
+    const bool in = r < n && c < n;
+    const double x = in ? a[(long long)r * n + c] : 0.0, y = in ? a[(long long)c * n + r] : 0.0;
+    o[it] = 0.5 * (x + y);
+    if (out_a) out_a[pblk_off[s] + it] = 0.5 * (x - y);
   }
 }
 
@@ -520,8 +529,10 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
   // workspace: lam | H (FP64: hu_re | hu_im | ho_re | ho_im; split: hs_u | hs_o, four bfloat16
   // planes each) over the padded blocks | part | w | dw | tiles | blk_off | pblk_off | blk_n |
   // rowmap (split)
+  const bool odd = !ctx->quad.ci.empty();   // complex term coefficients
   const size_t hbytes = split ? (size_t)16 * ptot : (size_t)32 * ptot;
-  size_t bytes = (size_t)ptot * 8 + hbytes + (size_t)nparts * Kp * 8 + 2 * (size_t)T * Kp * 8 +
+  size_t bytes = (size_t)ptot * 8 * (odd ? 2 : 1) + hbytes + (size_t)nparts * Kp * 8 +
+                 2 * (size_t)T * Kp * 8 +
                  tiles.size() * sizeof(BwdTile) + S * 16 + S * 4 + rowmap.size() * 4 + 4096;
   e = ensure(ctx, ctx->adj_work, bytes);
   if (e != hipSuccess) return e;
@@ -536,6 +547,7 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
     return q;
   };
   double* lam = (double*)take(ptot * 8);
+  double* lam_a = odd ? (double*)take(ptot * 8) : nullptr;
   char* hbuf = take(hbytes);
   double* part = (double*)take((size_t)nparts * Kp * 8);
   double* wn = (double*)take((size_t)T * Kp * 8);
@@ -569,7 +581,7 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   hipLaunchKernelGGL(symmetrise_kernel, dim3(256, S), dim3(256), 0, st, dL_dchi0, dblk_off,
-                     dpblk_off, dblk_n, S, lam);
+                     dpblk_off, dblk_n, S, lam, lam_a);
   // the adjoint Green's-function launches write the blocks' valid entries only: the padding
   // of the H arrays must read as zero in the contraction
   if ((e = launch_fill_zero(hbuf, hbytes, st)) ||
@@ -611,13 +623,14 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
       e = launch_green_adjoint(prec, bt.grid, ctx->a_tiles.p, bt.nrb, ctx->site_tiles[prec].p,
                                ctx->site_cols_pad / 16, ctx->K_pad / chunk,
                                (const double*)ctx->c_dev.p + t, ctx->Ko_pad / chunk,
-                               (const TileDesc*)plan->tiles.p + bt.tile0, bt.ntiles, lam, hu_re,
+                               (const TileDesc*)plan->tiles.p + bt.tile0, bt.ntiles, lam, lam_a,
+                               odd ? ctx->quad.c[t] : 0.0, odd ? ctx->quad.ci[t] : 0.0, hu_re,
                                hu_im, ho_re, ho_im, hs_u, hs_o, ctx->park.p, st);
       if (e != hipSuccess) return e;
     }
     B.w = wn + (size_t)t * Kp;
     B.dw = dwn + (size_t)t * Kp;
-    B.ct = ctx->quad.c[t];
+    B.ct = odd ? 1.0 : ctx->quad.c[t];   // (complex coefficients are inside H)
     if (split)
       hipLaunchKernelGGL(bwd_split_kernel, dim3((unsigned)(8 * B.per)), dim3(256), 0, st, B);
     else

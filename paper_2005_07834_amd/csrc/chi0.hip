@@ -60,8 +60,12 @@ struct Chi0Params {
   unsigned char* park;          // per-workgroup space for G_o between the two phases
   // adjoint modes: with T = 1, write lam * conj(G_u) and lam * conj(G_o), as FP64 planes with
   // the block's row stride (mode 1) or as bfloat16 hi/lo in operand tiles (mode 2,
-  // h_tile_offset)
+  // h_tile_offset).  With lam_a (complex term coefficients, chi0 at imaginary frequency) the
+  // coefficient matrices are Hermitian: adj_c lam + i adj_s lam_a for G_u and
+  // adj_c lam - i adj_s lam_a for G_o (lam symmetric, lam_a antisymmetric).
   const double* lam;
+  const double* lam_a;
+  double adj_c, adj_s;
   double* hu_re;
   double* hu_im;
   double* ho_re;
@@ -772,19 +776,33 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
           }
           if constexpr (MODE >= 1) {
             // adjoint: Hu = lam * conj(G_u), Ho = lam * conj(G_o) on a site block.  lam is
-            // symmetric and G Hermitian there, so H(c, r) = conj(H(r, c)): the host lists only
-            // tiles that reach the upper triangle, each element on or above the diagonal is
-            // stored with its conjugate at the transposed place, and each place is written
-            // once.
-            double l[ELEMS];
+            // symmetric (or the coefficient matrix Hermitian) and G Hermitian there, so
+            // H(c, r) = conj(H(r, c)): the host lists only tiles that reach the upper
+            // triangle, each element on or above the diagonal is stored with its conjugate at
+            // the transposed place, and each place is written once.
+            double l[ELEMS], la[ELEMS];
 #pragma unroll
             for (int e = 0; e < ELEMS; ++e) l[e] = P.lam[obase + off[e]];
+            if (P.lam_a) {
+#pragma unroll
+              for (int e = 0; e < ELEMS; ++e) la[e] = P.lam_a[obase + off[e]];
+            }
 #pragma unroll
             for (int e = 0; e < ELEMS; ++e)
               if (in[e] && dg[e] >= 0) {
                 const long long o = obase + off[e];
-                const double hur = l[e] * (double)gr[i][j][e], hui = -l[e] * (double)gi[i][j][e];
-                const double hor = l[e] * (double)or_[e], hoi = -l[e] * (double)oi_[e];
+                double hur = l[e] * (double)gr[i][j][e], hui = -l[e] * (double)gi[i][j][e];
+                double hor = l[e] * (double)or_[e], hoi = -l[e] * (double)oi_[e];
+                if (P.lam_a) {
+                  // (a + i b) conj(g) with a = adj_c lam, b = +-adj_s lam_a
+                  const double a = P.adj_c * l[e], b = P.adj_s * la[e];
+                  const double ur = gr[i][j][e], ui = gi[i][j][e];
+                  const double vr = or_[e], vi = oi_[e];
+                  hur = a * ur + b * ui;
+                  hui = b * ur - a * ui;
+                  hor = a * vr - b * vi;
+                  hoi = -b * vr - a * vi;
+                }
                 if constexpr (MODE == 1) {
                   const long long ot = o + (long long)dg[e] * (td.ldo - 1);
                   P.hu_re[o] = hur;
@@ -1031,6 +1049,8 @@ hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int
   P.out = out;
   P.pref = pref;
   P.lam = nullptr;
+  P.lam_a = nullptr;
+  P.adj_c = P.adj_s = 0.0;
   P.hu_re = P.hu_im = P.ho_re = P.ho_im = nullptr;
   P.hs_u = P.hs_o = nullptr;
   switch (prec) {
@@ -1045,6 +1065,7 @@ hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int
 hipError_t launch_green_adjoint(int prec, int grid, const void* a_tiles, int a_nrb,
                                 const void* b_tiles, int b_ncb, int nch, const double* c,
                                 int nch_o, const TileDesc* tiles, int ntiles, const double* lam,
+                                const double* lam_a, double adj_c, double adj_s,
                                 double* hu_re, double* hu_im, double* ho_re, double* ho_im,
                                 void* hs_u, void* hs_o, void* park, hipStream_t s) {
   Chi0Params P;
@@ -1065,6 +1086,9 @@ hipError_t launch_green_adjoint(int prec, int grid, const void* a_tiles, int a_n
   P.sym = 0;
   P.sync = nullptr;
   P.lam = lam;
+  P.lam_a = lam_a;
+  P.adj_c = adj_c;
+  P.adj_s = adj_s;
   P.hu_re = hu_re;
   P.hu_im = hu_im;
   P.ho_re = ho_re;

@@ -1022,8 +1022,6 @@ lrs_status lrs_compute_chi0_backward(lrs_ctx* ctx, int cols, int prec, const dou
   if (dL_dpsi_grid) return fail(ctx, LRS_EUNSUPPORTED, "site blocks do not depend on grid orbitals");
   if (!dL_dchi0 || !dL_dE || !dL_dpsi_site) return fail(ctx, LRS_EINVAL, "missing gradient buffers");
   if (!ctx->quad.has_deriv) return fail(ctx, LRS_EUNSUPPORTED, "generic terms carry no energy derivative");
-  if (!ctx->quad.ci.empty())
-    return fail(ctx, LRS_EUNSUPPORTED, "the adjoint covers the static polarizability only");
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   HIP_OR_FAIL(ctx, hipStreamIsCapturing(ctx->stream, &cs));

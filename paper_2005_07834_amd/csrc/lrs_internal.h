@@ -219,6 +219,7 @@ hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int
 hipError_t launch_green_adjoint(int prec, int grid, const void* a_tiles, int a_nrb,
                                 const void* b_tiles, int b_ncb, int nch, const double* c,
                                 int nch_o, const TileDesc* tiles, int ntiles, const double* lam,
+                                const double* lam_a, double adj_c, double adj_s,
                                 double* hu_re, double* hu_im, double* ho_re, double* ho_im,
                                 void* hs_u, void* hs_o, void* park, hipStream_t s);
 

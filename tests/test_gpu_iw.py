@@ -12,6 +12,7 @@ import pytest
 import torch
 
 from oracle import chi0 as cz
+from oracle import grads as gr
 from oracle import quadrature as q
 from tests.conftest import workload
 
@@ -68,7 +69,7 @@ def test_iw_tiny_full(P, omega):
 def test_iw_zero_is_static_and_production_blocks(P):
     """omega = 0 reproduces the static rule bit for bit; on the production cell (2x2x2 k,
     where the odd part is not zero) sampled site-block entries and their transposes against
-    the oracle (FP64 and BF16X2); the adjoint refuses these terms."""
+    the oracle (FP64 and BF16X2)."""
     w = workload("production", with_grid=False)
     ctx = P.Context(0)
     ctx.set_orbitals(w.energies, w.nocc, None, w.grid_dV)
@@ -96,8 +97,75 @@ def test_iw_zero_is_static_and_production_blocks(P):
         say(f"  production omega {omega} {prec}: {e:.2e} (asymmetry {asym:.1e})")
         assert e < tol
     assert asym > 1e-6
-    with pytest.raises(P.LrsError) as ei:
-        ctx.chi0_backward(torch.zeros(sum(x.npts ** 2 for x in w.sites), dtype=torch.float64,
-                                      device="cuda"))
-    assert ei.value.status == P.LRS_EUNSUPPORTED
+    ctx.close()
+
+
+def test_iw_adjoint_tiny_vs_oracle(P):
+    """Adjoint of chi0(i omega) on the tiny workload for a seeded non-symmetric dL/dchi0:
+    FP64 and split products against the oracle's gradient."""
+    w = workload("tiny")
+    omega, n = 0.3, 32
+    ctx = P.Context(0)
+    ctx.set_orbitals(w.energies, w.nocc, None, w.grid_dV)
+    ctx.set_sites(w.sites, w.psi_site)
+    ctx.make_quadrature_iw(n, 0.0, omega)
+    sc = ctx.get_quadrature()["scale"]
+    npts = w.sites[0].npts
+    rng = np.random.default_rng(9)
+    lam = rng.standard_normal((npts, npts))
+    _, dE_ref, dp_ref = gr.linear_grads_iw(w.psi_site.numpy(), w.energies, w.nocc, 2, w.sites,
+                                           [lam], n, sc, omega)
+    lam_d = torch.as_tensor(lam.ravel(), device="cuda")
+    for prec, tol in [(P.FP64, 1e-10), (P.BF16X2, 1e-4)]:
+        dE, dp = ctx.chi0_backward(lam_d, prec)
+        eE, ep = rel(dE.cpu().numpy(), dE_ref), rel(dp.cpu().numpy(), dp_ref)
+        say(f"  tiny adjoint at i omega, prec {prec}: dE {eE:.2e} dpsi {ep:.2e}")
+        assert eE < tol and ep < tol
+    ctx.close()
+
+
+def test_iw_adjoint_production_central_differences(P):
+    """Production cell (2 sites, 2x2x2 k, where the odd part is not zero): the FP64 adjoint of
+    L = sum Lambda chi0(i omega) against central differences of the library's own FP64
+    forward, in two interior band energies and along a random orbital direction; the split
+    adjoint against the FP64 one."""
+    w = workload("production", with_grid=False)
+    omega, n = 0.05, 32
+    ctx = P.Context(0)
+    ctx.set_orbitals(w.energies, w.nocc, None, w.grid_dV)
+    ctx.set_sites(w.sites, w.psi_site)
+    ctx.make_quadrature_iw(n, 0.0, omega)
+    sc = ctx.get_quadrature()["scale"]
+    rng = np.random.default_rng(10)
+    lam = torch.as_tensor(rng.standard_normal(sum(x.npts ** 2 for x in w.sites)), device="cuda")
+    dE, dp = ctx.chi0_backward(lam, P.FP64)
+    dEs, dps = ctx.chi0_backward(lam, P.BF16X2)
+    es = float((dEs - dE).abs().max() / dE.abs().max())
+    ps_ = float((dps - dp).abs().max() / dp.abs().max())
+    say(f"  production split vs fp64: dE {es:.2e} dpsi {ps_:.2e}")
+    assert es < 1e-4 and ps_ < 1e-4
+
+    def L(E, psi):
+        ctx.set_orbitals(E, w.nocc, None, w.grid_dV)
+        ctx.set_sites(w.sites, psi)
+        ctx.make_quadrature_iw(n, sc, omega)
+        return float((ctx.chi0(-1, P.COLS_SITE, P.FP64) * lam).sum())
+
+    E0, psi0 = w.energies, w.psi_site
+    h = 1e-4
+    for k, b in [(1, 20), (6, 300)]:
+        Ep, Em = E0.copy(), E0.copy()
+        Ep[k, b] += h
+        Em[k, b] -= h
+        fd = (L(Ep, psi0) - L(Em, psi0)) / (2 * h)
+        an = float(dE[k, b])
+        say(f"  dL/de[{k},{b}]: adjoint {an:.10e} central difference {fd:.10e}")
+        assert abs(fd - an) < 1e-6 * dE.abs().max().item()
+    V = torch.complex(torch.randn(psi0.shape, dtype=torch.float64, generator=torch.Generator().manual_seed(3)),
+                      torch.randn(psi0.shape, dtype=torch.float64, generator=torch.Generator().manual_seed(4)))
+    hp = 1e-5
+    fd = (L(E0, psi0 + hp * V) - L(E0, psi0 - hp * V)) / (2 * hp)
+    an = float((torch.conj(dp.cpu()) * V).real.sum())
+    say(f"  along a random direction: adjoint {an:.10e} central difference {fd:.10e}")
+    assert abs(fd - an) < 1e-6 * abs(an)
     ctx.close()
