@@ -169,3 +169,84 @@ def test_iw_adjoint_production_central_differences(P):
     say(f"  along a random direction: adjoint {an:.10e} central difference {fd:.10e}")
     assert abs(fd - an) < 1e-6 * abs(an)
     ctx.close()
+
+
+def test_iw_batching_uneven_sites(P):
+    """64 uneven sites (2x2x2 k, 8 terms at omega = 0.05 Ha): the site blocks over every tile
+    (chi0(i omega) is not symmetric) sampled with their transposes against the oracle in
+    BF16X2 and FP64; the adjoint in split products against FP64, unchanged bit for bit when a
+    small operand budget cuts the launches into many batches, and the FP64 adjoint against
+    central differences of the FP64 forward along a random orbital direction."""
+    import os
+    w = workload("batching", with_grid=False, device="cuda")
+    omega, n = 0.05, 8
+    ctx = P.Context(0)
+    ctx.set_orbitals(w.energies, w.nocc, None, w.grid_dV)
+    ctx.set_sites(w.sites, w.psi_site)
+    ctx.make_quadrature_iw(n, 0.0, omega)
+    sc = ctx.get_quadrature()["scale"]
+    cc, cs, al, be = cz.terms_for(w.energies, w.nocc, f"time_iw:{omega}", n, sc)
+    rng = np.random.default_rng(12)
+    offs = w.site_offsets
+    blk0 = np.cumsum([0] + [x.npts ** 2 for x in w.sites])
+    rows, cols, flat, flat_t = [], [], [], []
+    for k, site in enumerate(w.sites):
+        m = site.npts
+        i, j = rng.integers(0, m, 3), rng.integers(0, m, 3)
+        rows += list(offs[k] + i)
+        cols += list(offs[k] + j)
+        flat += list(blk0[k] + i * m + j)
+        flat_t += list(blk0[k] + j * m + i)
+    rows, cols = np.array(rows), np.array(cols)
+    psr = w.psi_site[:, :, torch.as_tensor(rows, device="cuda")].cpu().numpy()
+    psc = w.psi_site[:, :, torch.as_tensor(cols, device="cuda")].cpu().numpy()
+    ref = cz.chi0_iw_quad_entries(psr, psc, w.nocc, 2, cc, cs, al, be)
+    ref_t = cz.chi0_iw_quad_entries(psc, psr, w.nocc, 2, cc, cs, al, be)
+    asym = np.abs(ref - ref_t).max() / np.abs(ref).max()
+    fi, ft = torch.as_tensor(flat, device="cuda"), torch.as_tensor(flat_t, device="cuda")
+    for prec, tol in [("bf16x2", 1e-4), ("fp64", 1e-12)]:
+        out = ctx.chi0(-1, P.COLS_SITE, prec)
+        e = max(rel(out[fi].cpu().numpy(), ref), rel(out[ft].cpu().numpy(), ref_t))
+        say(f"  batching at i omega, {prec}: {e:.2e} (asymmetry {asym:.1e})")
+        assert e < tol
+    assert asym > 1e-6
+    tot = int(blk0[-1])
+    g = torch.Generator(device="cuda").manual_seed(13)
+    lam = torch.randn(tot, generator=g, dtype=torch.float64, device="cuda")
+    dE, dp = ctx.chi0_backward(lam, P.FP64)
+    dEs, dps = ctx.chi0_backward(lam, P.BF16X2)
+    eE = (dEs - dE).abs().max().item() / dE.abs().max().item()
+    eP = (dps - dp).abs().max().item() / dp.abs().max().item()
+    say(f"  adjoint split vs FP64: dE {eE:.2e} dpsi {eP:.2e}")
+    assert eE < 1e-4 and eP < 1e-4
+    psi0 = w.psi_site
+    V = torch.complex(torch.randn(psi0.shape, dtype=torch.float64, device="cuda", generator=g),
+                      torch.randn(psi0.shape, dtype=torch.float64, device="cuda", generator=g))
+
+    def L(psi):
+        ctx.set_sites(w.sites, psi)
+        ctx.make_quadrature_iw(n, sc, omega)
+        return float((ctx.chi0(-1, P.COLS_SITE, P.FP64) * lam).sum())
+    h = 3e-6    # |V| ~ 1 against orbital values ~ 1e-2: a relative step of about 3e-4
+    fd = (L(psi0 + h * V) - L(psi0 - h * V)) / (2 * h)
+    an = float((torch.conj(dp) * V).real.sum())
+    say(f"  along a random direction: adjoint {an:.10e} central difference {fd:.10e}")
+    assert abs(fd - an) < 1e-6 * abs(an)
+    ctx.close()
+    old = os.environ.get("LRS_SITE_OPERAND_BYTES")
+    os.environ["LRS_SITE_OPERAND_BYTES"] = str(64 << 20)
+    try:
+        ctx2 = P.Context(0)
+        ctx2.set_orbitals(w.energies, w.nocc, None, w.grid_dV)
+        ctx2.set_sites(w.sites, w.psi_site)
+        ctx2.make_quadrature_iw(n, sc, omega)
+        dEb, dpb = ctx2.chi0_backward(lam, P.BF16X2)
+        say(f"  64 MiB operand budget: max diff dE {(dEb - dEs).abs().max().item():.1e} "
+            f"dpsi {(dpb - dps).abs().max().item():.1e}")
+        assert torch.equal(dEb, dEs) and torch.equal(dpb, dps)
+        ctx2.close()
+    finally:
+        if old is None:
+            os.environ.pop("LRS_SITE_OPERAND_BYTES")
+        else:
+            os.environ["LRS_SITE_OPERAND_BYTES"] = old
