@@ -580,7 +580,6 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
   const int bslot = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
   const int nch = P.nch;
   const int nseq = P.T * nch;
-  const size_t a_term = (size_t)P.a_nrb * nch * TB;
 
   // global -> LDS: the next chunk to load has its A tiles at `an` and its B tiles at `bn`; the
   // stage's A tiles and B tiles are each one contiguous run, and the wave's share of its 1 KiB
