@@ -298,9 +298,11 @@ class Chi0Fn(torch.autograd.Function):
     """chi0 on the site x site blocks as a differentiable function of the band energies and
     the site orbitals: Eq. chi1 with the imaginary-time quadrature.
 
-    ``Chi0Fn.apply(energies, psi_site, ctx, nocc, sites, nnodes, scale[, prec])`` sets the
-    context's orbitals (no grid), sites and quadrature, and returns the flat site-block layout
-    computed in ``prec`` (FP64 by default).  The backward pass runs the library's adjoint
+    ``Chi0Fn.apply(energies, psi_site, ctx, nocc, sites, nnodes, scale[, prec[, omega]])`` sets
+    the context's orbitals (no grid), sites and quadrature, and returns the flat site-block
+    layout computed in ``prec`` (FP64 by default); ``omega`` > 0 gives chi0 at imaginary
+    frequency i omega (the imaginary-time terms with complex coefficients).  The backward pass
+    runs the library's adjoint
     (Green's functions recomputed per term; split products when ``prec`` is BF16X2, FP64
     otherwise) and returns dL/de [nk, nb] and dL/dpsi_site (complex, dL/dRe + i dL/dIm).  The
     nodes and mu are held fixed: pass ``scale > 0`` so the node set does not depend on the
@@ -309,23 +311,27 @@ class Chi0Fn(torch.autograd.Function):
     """
 
     @staticmethod
-    def _setup(lctx, energies, psi_site, nocc, sites, nnodes, scale):
+    def _setup(lctx, energies, psi_site, nocc, sites, nnodes, scale, omega):
         lctx.set_orbitals(energies, nocc)
         lctx.set_sites(sites, psi_site)
-        lctx.make_quadrature(QUAD_TIME, nnodes, scale)
+        if omega:
+            lctx.make_quadrature_iw(nnodes, scale, omega)
+        else:
+            lctx.make_quadrature(QUAD_TIME, nnodes, scale)
 
     @staticmethod
-    def forward(fctx, energies, psi_site, lctx, nocc, sites, nnodes, scale, *prec):
-        p = prec[0] if prec else FP64
+    def forward(fctx, energies, psi_site, lctx, nocc, sites, nnodes, scale, *opt):
+        p = opt[0] if opt else FP64
         p = PREC_NAMES[p] if isinstance(p, str) else p
+        omega = float(opt[1]) if len(opt) > 1 else 0.0
         args = (energies.detach() if isinstance(energies, torch.Tensor) else energies,
-                psi_site.detach(), nocc, sites, nnodes, scale)
+                psi_site.detach(), nocc, sites, nnodes, scale, omega)
         Chi0Fn._setup(lctx, *args)
         out = lctx.chi0(-1, COLS_SITE, p)
         fctx.lctx = lctx
         fctx.args = args
         fctx.prec = BF16X2 if p == BF16X2 else FP64
-        fctx.nextra = len(prec)
+        fctx.nextra = len(opt)
         fctx.version = lctx.orb_version
         fctx.e_like = (energies.device, energies.dtype) if isinstance(energies, torch.Tensor) \
             else (torch.device("cpu"), torch.float64)

@@ -1,3 +1,4 @@
+import gc
 import os
 import sys
 
@@ -28,3 +29,14 @@ def workload(name, **kw):
 @pytest.fixture(scope="session")
 def tiny():
     return workload("tiny")
+
+
+@pytest.fixture(autouse=True)
+def _release_cached_device_memory():
+    """After each test, hand the memory torch's caching allocator keeps back to the device:
+    the library allocates its own buffers with hipMalloc, outside that cache."""
+    yield
+    torch = sys.modules.get("torch")
+    if torch is not None and torch.cuda.is_initialized():
+        gc.collect()
+        torch.cuda.empty_cache()

@@ -233,6 +233,8 @@ def test_iw_batching_uneven_sites(P):
     say(f"  along a random direction: adjoint {an:.10e} central difference {fd:.10e}")
     assert abs(fd - an) < 1e-6 * abs(an)
     ctx.close()
+    del V, dE, dp
+    torch.cuda.empty_cache()
     old = os.environ.get("LRS_SITE_OPERAND_BYTES")
     os.environ["LRS_SITE_OPERAND_BYTES"] = str(64 << 20)
     try:
@@ -250,3 +252,37 @@ def test_iw_batching_uneven_sites(P):
             os.environ.pop("LRS_SITE_OPERAND_BYTES")
         else:
             os.environ["LRS_SITE_OPERAND_BYTES"] = old
+
+
+def test_iw_autograd_tiny(P):
+    """Chi0Fn at imaginary frequency: gradients of sum(Lambda * chi0(i omega)) through
+    autograd against the oracle gradient, and torch's numerical Jacobian check (FP64)."""
+    w = workload("tiny")
+    omega, n = 0.3, 32
+    mu = q.mid_gap(w.energies, w.nocc)
+    x, y = q.offsets(w.energies, w.nocc, mu)
+    sc = q.auto_scale_iw(x, y, n, omega)
+    npts = w.sites[0].npts
+    rng = np.random.default_rng(14)
+    lam_np = rng.standard_normal((npts, npts))
+    lam = torch.as_tensor(lam_np.ravel(), device="cuda")
+    ctx = P.Context(0)
+    E = torch.tensor(w.energies, dtype=torch.float64, requires_grad=True)
+    psi = w.psi_site.to("cuda").clone().requires_grad_(True)
+
+    def f(E_, psi_):
+        return (P.Chi0Fn.apply(E_, psi_, ctx, w.nocc, w.sites, n, sc, P.FP64, omega) * lam).sum()
+
+    L = f(E, psi)
+    L.backward()
+    L_ref, dE_ref, dp_ref = gr.linear_grads_iw(w.psi_site.numpy(), w.energies, w.nocc, 2,
+                                               w.sites, [lam_np], n, sc, omega)
+    eL = abs(L.item() - L_ref) / abs(L_ref)
+    eE, ep = rel(E.grad.numpy(), dE_ref), rel(psi.grad.cpu().numpy(), dp_ref)
+    say(f"  autograd at i omega: loss {eL:.2e} dE {eE:.2e} dpsi {ep:.2e}")
+    assert eL < 1e-12 and eE < 1e-10 and ep < 1e-10
+    E2 = torch.tensor(w.energies, dtype=torch.float64, requires_grad=True)
+    psi2 = w.psi_site.to("cuda").clone().requires_grad_(True)
+    assert torch.autograd.gradcheck(f, (E2, psi2), eps=1e-6, atol=1e-7, rtol=1e-4,
+                                    fast_mode=True)
+    ctx.close()
