@@ -125,3 +125,4 @@ def test_grid_launch_imaginary_frequency(full):
     say(f"  grid bf16x2 at i omega = {omega}i: {ctx.last_kernel_ms():.0f} ms, vs same terms "
         f"{eq:.2e}, vs exact {ex:.2e}")
     assert eq < 1e-4 and ex < 1e-4
+
