@@ -140,12 +140,14 @@ __device__ __forceinline__ T zero_acc() {
 
 // ----------------------------------------------------------------------------- site prep
 // Weighted site operand for terms [t0, t0 + nt) and row blocks [rb0, rb0 + nrb) of the slot
-// layout, with p + i q = w_t(k) * psi_k(row) * a_scale.  One thread per (term, row block,
-// chunk, lane slot) writes that slot of every plane:
+// layout, with p + i q = w_t(k) * psi_k(row) * a_scale.  One thread per (row block, chunk,
+// lane slot) reads that slot's orbital values once and writes the slot of every plane for
+// each term in turn:
 //   FP64 (chunk 16, 64 slots):  slot l holds row l%16, k = 4 s + l/16, s = 0..3, planes p, q
 //   FP32 (chunk 32, 64 slots):  slot l holds row l%16, k = 4 s + l/16, s = 0..7, planes p, q
 //   split (chunk 16, 32 slots): slot l holds row l%16, k = 8 (l/16) + e, e = 0..7,
 //                               planes p_hi, p_lo, q_hi, q_lo
+// (a_scale is a power of two, so the product does not depend on the order of the factors)
 __device__ inline size_t site_pos(int r, int k, int K_pad) {
   int ch = k >> 4, kl = k & 15;
   return (size_t)r * K_pad + ch * 16 + (kl & 3) * 4 + (kl >> 2);
@@ -156,71 +158,72 @@ __global__ void prep_site_kernel(const double* site, int rows_pad, int K_pad, co
                                  int rb0, int nrb, const double* w, int t0, int nt, double a_scale,
                                  unsigned char* out) {
   constexpr int KC = Prec<PREC>::KC, TB = Prec<PREC>::TB;
-  constexpr int SLOTS = (PREC == LRS_BF16X2 || PREC == LRS_FP16X2) ? 32 : 64;
+  constexpr bool SPLIT = PREC == LRS_BF16X2 || PREC == LRS_FP16X2;
+  constexpr int SLOTS = SPLIT ? 32 : 64;
+  constexpr int NV = PREC == LRS_FP64 ? 4 : 8;     // values of the slot per plane
   const int nch = K_pad / KC;
   long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (long long)nt * nrb * nch * SLOTS) return;
+  if (gid >= (long long)nrb * nch * SLOTS) return;
   const int lane = (int)(gid % SLOTS);
-  long long tile = gid / SLOTS;              // ((t * nch + ch) * nrb + rb): chunk-major
+  const long long tile = gid / SLOTS;        // ch * nrb + rb
   const int rb = (int)(tile % nrb);
-  tile /= nrb;
-  const int ch = (int)(tile % nch);
-  const int t = (int)(tile / nch);
+  const int ch = (int)(tile / nrb);
   const int row = slot_row[(rb0 + rb) * 16 + (lane & 15)];
   const size_t plane = (size_t)rows_pad * K_pad;
-  const double* wt = w + (size_t)(t0 + t) * K_pad;
-  unsigned char* base = out + (((size_t)t * nch + ch) * nrb + rb) * TB;
-  auto val = [&](int k, double& p, double& q) {
+  int kv[NV];
+  double p0[NV], q0[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    kv[v] = SPLIT ? ch * 16 + 8 * (lane >> 4) + v : ch * KC + 4 * v + (lane >> 4);
     if (row < 0) {
-      p = 0.0;
-      q = 0.0;
-      return;
+      p0[v] = 0.0;
+      q0[v] = 0.0;
+    } else {
+      const size_t o = site_pos(row, kv[v], K_pad);
+      p0[v] = site[o] * a_scale;
+      q0[v] = site[plane + o] * a_scale;
     }
-    const size_t o = site_pos(row, k, K_pad);
-    const double f = wt[k] * a_scale;
-    p = site[o] * f;
-    q = site[plane + o] * f;
-  };
-  if constexpr (PREC == LRS_FP64) {
-    f64x4 vp, vq;
+  }
+  for (int t = 0; t < nt; ++t) {
+    const double* wt = w + (size_t)(t0 + t) * K_pad;
+    unsigned char* base = out + (((size_t)t * nch + ch) * nrb + rb) * TB;
+    if constexpr (PREC == LRS_FP64) {
+      f64x4 vp, vq;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      double p, q;
-      val(ch * 16 + 4 * s + (lane >> 4), p, q);
-      vp[s] = p;
-      vq[s] = q;
-    }
-    f64x4* d = (f64x4*)base;
-    d[lane] = vp;
-    d[64 + lane] = vq;
-  } else if constexpr (PREC == LRS_FP32) {
-    float* d = (float*)base;
-    for (int s = 0; s < 8; ++s) {
-      double p, q;
-      val(ch * 32 + 4 * s + (lane >> 4), p, q);
-      d[lane * 8 + s] = (float)p;
-      d[512 + lane * 8 + s] = (float)q;
-    }
-  } else {
-    using elem_t = typename std::conditional<PREC == LRS_BF16X2, __bf16, _Float16>::type;
-    using vec_t = typename std::conditional<PREC == LRS_BF16X2, bf16x8, f16x8>::type;
-    // the slot's 8 values of each plane are 16 contiguous bytes: one store per plane
-    vec_t vph, vpl, vqh, vql;
+      for (int v = 0; v < 4; ++v) {
+        vp[v] = p0[v] * wt[kv[v]];
+        vq[v] = q0[v] * wt[kv[v]];
+      }
+      f64x4* d = (f64x4*)base;
+      d[lane] = vp;
+      d[64 + lane] = vq;
+    } else if constexpr (PREC == LRS_FP32) {
+      float* d = (float*)base;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      double p, q;
-      val(ch * 16 + 8 * (lane >> 4) + e, p, q);
-      const elem_t ph = (elem_t)(float)p, qh = (elem_t)(float)q;
-      vph[e] = ph;
-      vpl[e] = (elem_t)(float)(p - (double)(float)ph);
-      vqh[e] = qh;
-      vql[e] = (elem_t)(float)(q - (double)(float)qh);
+      for (int v = 0; v < 8; ++v) {
+        d[lane * 8 + v] = (float)(p0[v] * wt[kv[v]]);
+        d[512 + lane * 8 + v] = (float)(q0[v] * wt[kv[v]]);
+      }
+    } else {
+      using elem_t = typename std::conditional<PREC == LRS_BF16X2, __bf16, _Float16>::type;
+      using vec_t = typename std::conditional<PREC == LRS_BF16X2, bf16x8, f16x8>::type;
+      // the slot's 8 values of each plane are 16 contiguous bytes: one store per plane
+      vec_t vph, vpl, vqh, vql;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const double p = p0[e] * wt[kv[e]], q = q0[e] * wt[kv[e]];
+        const elem_t ph = (elem_t)(float)p, qh = (elem_t)(float)q;
+        vph[e] = ph;
+        vpl[e] = (elem_t)(float)(p - (double)(float)ph);
+        vqh[e] = qh;
+        vql[e] = (elem_t)(float)(q - (double)(float)qh);
+      }
+      vec_t* d = (vec_t*)base;
+      d[lane] = vph;
+      d[32 + lane] = vpl;
+      d[64 + lane] = vqh;
+      d[96 + lane] = vql;
     }
-    vec_t* d = (vec_t*)base;
-    d[lane] = vph;
-    d[32 + lane] = vpl;
-    d[64 + lane] = vqh;
-    d[96 + lane] = vql;
   }
 }
 
@@ -981,7 +984,7 @@ hipError_t prep_p(const double* site, int rows_pad, int K_pad, const int* slot_r
                   hipStream_t s) {
   const int nch = K_pad / Prec<PREC>::KC;
   const int slots = (PREC == LRS_BF16X2 || PREC == LRS_FP16X2) ? 32 : 64;
-  const long long n = (long long)nt * nrb * nch * slots;
+  const long long n = (long long)nrb * nch * slots;
   hipLaunchKernelGGL(prep_site_kernel<PREC>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                      site, rows_pad, K_pad, slot_row, rb0, nrb, w, t0, nt, a_scale,
                      (unsigned char*)out);
