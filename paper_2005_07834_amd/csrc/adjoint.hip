@@ -618,9 +618,10 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
   for (int t = 0; t < T; ++t) {
     for (const Batch& bt : plan->batches) {
       if (bt.ntiles == 0) continue;
-      if (ensure_site_operand(ctx, prec, bt, t, 1) != LRS_OK) return hipErrorOutOfMemory;
+      const void* a_op = nullptr;
+      if (ensure_site_operand(ctx, prec, bt, t, 1, &a_op) != LRS_OK) return hipErrorOutOfMemory;
       if (ensure_park(ctx, prec, 0, bt.grid) != LRS_OK) return hipErrorOutOfMemory;
-      e = launch_green_adjoint(prec, bt.grid, ctx->a_tiles.p, bt.nrb, ctx->site_tiles[prec].p,
+      e = launch_green_adjoint(prec, bt.grid, a_op, bt.nrb, ctx->site_tiles[prec].p,
                                ctx->site_cols_pad / 16, ctx->K_pad / chunk,
                                (const double*)ctx->c_dev.p + t, ctx->Ko_pad / chunk,
                                (const TileDesc*)plan->tiles.p + bt.tile0, bt.ntiles, lam, lam_a,

@@ -406,10 +406,20 @@ lrs_status get_plan(lrs_ctx* ctx, int site, int cols, int prec, int variant, int
 }
 
 // Weighted site operand of terms [t0, t0+nt) for one batch (kept while nothing changes).
-lrs_status site_operand(lrs_ctx* ctx, int prec, const Batch& b, int t0, int nt) {
+// The weighted site operand of terms [t0, t0 + nt) for the rows of batch b; *a is the first
+// term's part.  The context keeps one operand: a request that the kept one covers (same
+// precision, terms, batch rows; terms are stored one after the other) uses it in place, so the
+// adjoint's one-term requests reuse the all-term operand of the forward launches.
+lrs_status site_operand(lrs_ctx* ctx, int prec, const Batch& b, int t0, int nt,
+                        const void** a = nullptr) {
   if (ctx->a_prec == prec && ctx->a_version == ctx->quad_version && ctx->a_rb0 == b.rb0 &&
-      ctx->a_nrb == b.nrb && ctx->a_t0 == t0 && ctx->a_nt == nt && ctx->a_tiles.p)
+      ctx->a_nrb == b.nrb && ctx->a_t0 <= t0 && t0 + nt <= ctx->a_t0 + ctx->a_nt &&
+      ctx->a_tiles.p) {
+    if (a)
+      *a = (const unsigned char*)ctx->a_tiles.p +
+           (size_t)(t0 - ctx->a_t0) * a_bytes_per_rb(ctx, prec, 1) * b.nrb;
     return LRS_OK;
+  }
   ctx->a_prec = -1;
   CHECK(ensure_buf(ctx, ctx->a_tiles, a_bytes_per_rb(ctx, prec, nt) * b.nrb, "weighted site operand"));
   const double a_scale = prec == LRS_FP16X2 ? ctx->site_scale_f16 : 1.0;
@@ -423,6 +433,7 @@ lrs_status site_operand(lrs_ctx* ctx, int prec, const Batch& b, int t0, int nt) 
   ctx->a_nrb = b.nrb;
   ctx->a_t0 = t0;
   ctx->a_nt = nt;
+  if (a) *a = ctx->a_tiles.p;
   return LRS_OK;
 }
 
@@ -469,7 +480,8 @@ lrs_status run_chi0(lrs_ctx* ctx, int site, int cols, int prec, int variant, dou
   bool first = true;
   for (const Batch& bt : plan->batches) {
     if (bt.ntiles == 0) continue;
-    CHECK(site_operand(ctx, prec, bt, 0, T));
+    const void* a_op = nullptr;
+    CHECK(site_operand(ctx, prec, bt, 0, T, &a_op));
     int nt = bt.ntiles, grid = bt.grid;
     if (max_tiles > 0) {
       nt = std::min(nt, max_tiles);
@@ -487,7 +499,7 @@ lrs_status run_chi0(lrs_ctx* ctx, int site, int cols, int prec, int variant, dou
     }
     if (timed && first) HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev0, ctx->stream));
     first = false;
-    HIP_OR_FAIL(ctx, launch_chi0(prec, variant, grid, ctx->a_tiles.p, bt.nrb, b, b_ncb, nch,
+    HIP_OR_FAIL(ctx, launch_chi0(prec, variant, grid, a_op, bt.nrb, b, b_ncb, nch,
                                  (const double*)ctx->c_dev.p,
                                  odd ? (const double*)ctx->c_dev.p + T : nullptr, T,
                                  ctx->Ko_pad / KC, (const TileDesc*)plan->tiles.p + bt.tile0, nt,
@@ -510,8 +522,9 @@ lrs_status plan_for(lrs_ctx* ctx, int site, int cols, int prec, int variant, int
   return get_plan(ctx, site, cols, prec, variant, mode, out);
 }
 lrs_status ensure_site_tiles_for(lrs_ctx* ctx, int prec) { return ensure_site_tiles(ctx, prec); }
-lrs_status ensure_site_operand(lrs_ctx* ctx, int prec, const Batch& b, int t0, int nt) {
-  return site_operand(ctx, prec, b, t0, nt);
+lrs_status ensure_site_operand(lrs_ctx* ctx, int prec, const Batch& b, int t0, int nt,
+                               const void** a) {
+  return site_operand(ctx, prec, b, t0, nt, a);
 }
 lrs_status ensure_park(lrs_ctx* ctx, int prec, int variant, int grid) {
   return park_for(ctx, prec, variant, grid);

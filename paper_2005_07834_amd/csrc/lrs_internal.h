@@ -227,7 +227,9 @@ hipError_t launch_green_adjoint(int prec, int grid, const void* a_tiles, int a_n
 lrs_status plan_for(lrs_ctx* ctx, int site, int cols, int prec, int variant, int mode,
                     Plan** out);
 lrs_status ensure_site_tiles_for(lrs_ctx* ctx, int prec);
-lrs_status ensure_site_operand(lrs_ctx* ctx, int prec, const Batch& b, int t0, int nt);
+// weighted site operand of terms [t0, t0 + nt) for batch b's rows; *a = the first term's part
+lrs_status ensure_site_operand(lrs_ctx* ctx, int prec, const Batch& b, int t0, int nt,
+                               const void** a);
 lrs_status ensure_park(lrs_ctx* ctx, int prec, int variant, int grid);
 
 // screen.hip
