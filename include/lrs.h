@@ -207,7 +207,8 @@ lrs_status lrs_compute_chi0(lrs_ctx* ctx, int site, int cols, int prec, double* 
  *   W_out      float64 [nsites][n][n] with n = (lmax+1)^2 * n_rad of each site, concatenated.
  *   rho_test   optional float64 [sum npts] test charge at the site points (NULL = none).
  *   loss_out   optional float64 [nsites]: rho_L^T D W D rho_L, rho_L = P rho (needs rho_test).
- * Keeps W (and rho_test) for lrs_screen_W_backward.  Asynchronous. */
+ * Keeps W (and rho_test) for lrs_screen_W_backward.  Asynchronous.  LRS_EUNSUPPORTED when a
+ * site has more than 288 basis functions (n_rad > 32) or 256 directions. */
 lrs_status lrs_screen_W(lrs_ctx* ctx, const double* chi0_sitesite, double* W_out,
                         const double* rho_test, double* loss_out);
 

@@ -1006,6 +1006,8 @@ lrs_status lrs_screen_W(lrs_ctx* ctx, const double* chi0_ss, double* W_out, cons
   if (loss_out && !rho) return fail(ctx, LRS_EINVAL, "loss_out needs rho_test");
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
   hipError_t e = launch_screen_forward(ctx, chi0_ss, W_out, rho, loss_out);
+  if (e == hipErrorInvalidValue)
+    return fail(ctx, LRS_EUNSUPPORTED, "a site basis exceeds 288 functions or 256 directions");
   if (e == hipErrorOutOfMemory) return fail(ctx, LRS_ENOMEM, "screening workspace");
   if (e != hipSuccess) return fail(ctx, LRS_EDEVICE, "screen_W: %s", hipGetErrorString(e));
   return LRS_OK;

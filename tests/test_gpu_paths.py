@@ -435,5 +435,21 @@ def test_size_limits_refused(P):
                              xyz.ctypes.data_as(C.c_void_p), one.ctypes.data_as(C.c_void_p),
                              C.c_void_p(psi.data_ptr()), 3)
     assert st == P.LRS_EINVAL                     # lmax above 2
+    # a site of 33 shells (297 basis functions) is accepted for chi0 but not by the solves
+    from workloads import sites as sx
+    big = sx.make_site(np.zeros(3), 33, 26)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    psi_big = torch.complex(torch.randn((1, w.energies.shape[1], big.npts), dtype=torch.float64,
+                                        device="cuda", generator=g),
+                            torch.randn((1, w.energies.shape[1], big.npts), dtype=torch.float64,
+                                        device="cuda", generator=g))
+    ctx.set_sites([big], psi_big)
+    chi = torch.zeros(big.npts ** 2, dtype=torch.float64, device="cuda")
+    for name, call in [("W", lambda: ctx.screen_W(chi)),
+                       ("ALDA W", lambda: ctx.screen_W_alda(chi, torch.ones(big.npts, dtype=torch.float64))),
+                       ("induced", lambda: ctx.induced_potential(chi))]:
+        with pytest.raises(P.LrsError) as e:
+            call()
+        assert e.value.status == P.LRS_EUNSUPPORTED, name
     say("  size limits refused")
     ctx.close()
