@@ -77,3 +77,41 @@ def test_binding_argument_counts_match_header():
         params = decls[name].strip()
         n = 0 if params in ("", "void") else params.count(",") + 1
         assert n == len(args), f"{name}: header {n} arguments, binding {len(args)}"
+
+
+def test_product_path_never_uses_the_oracle():
+    """The package (binding, build script, kernels) and the benchmark's timed path import
+    nothing from oracle/: only tests, smoke() and bench.py's CPU baseline and error legs may."""
+    pkg = os.path.join(ROOT, "paper_2005_07834_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(from|import)\s+oracle\b", src, flags=re.M), f
+                assert "oracle/" not in src and "oracle." not in src, f
+    bench = open(os.path.join(ROOT, "bench.py")).read()
+    step = bench[bench.index("    def step(record):"):bench.index("    for _ in range(args.warmup):")]
+    assert "cz." not in step and "oracle" not in step
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py --gpus N with N > 1 exits with a message, before touching any device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without liblrs.so the package does not import (no fallback path exists)."""
+    import shutil
+    import subprocess
+    import sys
+    dst = tmp_path / "paper_2005_07834_amd"
+    shutil.copytree(os.path.join(ROOT, "paper_2005_07834_amd"), dst,
+                    ignore=shutil.ignore_patterns("*.so", "*.o", "_build", "__pycache__"))
+    r = subprocess.run([sys.executable, "-c", "import paper_2005_07834_amd"], cwd=tmp_path,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0 and "ImportError" in r.stderr and "not built" in r.stderr
