@@ -58,7 +58,7 @@ typedef enum {
   LRS_ESTATE = 4,        /* call out of order (e.g. chi0 before orbitals) */
   LRS_ENOGAP = 5,        /* some occupied energy is not below every unoccupied one */
   LRS_ENONFINITE = 6,    /* NaN or Inf in an input */
-  LRS_EUNSUPPORTED = 7   /* valid request this build does not implement */
+  LRS_EUNSUPPORTED = 7   /* valid request the library does not implement */
 } lrs_status;
 
 typedef enum {
