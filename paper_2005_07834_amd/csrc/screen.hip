@@ -102,26 +102,50 @@ __global__ void eps_kernel(ScreenTabs T, const int2* rows, const double* X, doub
 //   mode 0: [eps | V], 2n columns; the right block (W) goes to out + w_out_off[site], row-major
 //   mode 1: [eps | v1], n + 1 columns; the last column (y) goes to out + h_off
 //   mode 2: as 1 on the 00;00 block (n_rad rows)
-// One workgroup per site, blocked by panels of GJ_NB columns.  The panel is eliminated in LDS:
-// at each of its steps the pivot row is swapped into place across the whole panel (the
+// One workgroup of 1024 threads per site, blocked by panels of GJ_NB columns.  The panel is
+// eliminated in LDS, wave w owning panel column w: at each step the owner of the step's column
+// finds and swaps in the pivot, then every other wave swaps the same rows in its column (the
 // multipliers of earlier steps included, so that they end up in the final row order) and the
-// step's column keeps its multipliers.  Then every later column is read once, in the panel's
+// later columns are eliminated; the step's column keeps its multipliers.  Then every later column is read once, in the panel's
 // final row order, takes the panel's nb elimination steps in registers and is written back
 // (a wave updates four columns at a time, sharing the multipliers read from LDS).  The columns
 // left of the panel are unit vectors by then and are not touched again.
 constexpr int GJ_NB = 16, GJ_MAXN = 288, GJ_SLOTS = (GJ_MAXN + 63) / 64, GJ_COLS = 4;
+static_assert(64 % GJ_NB == 0, "a panel's rows must lie in one 64-row slot");
+static_assert(1024 / 64 >= GJ_NB, "one wave per panel column");
 
-// a column spread over the lanes of a wave: row lane + 64 t in element t (t < GJ_SLOTS)
-typedef double gj_col __attribute__((ext_vector_type(8)));
-
-// value of row `row` (wave-uniform) of such a column: a register-indexed read of element
-// row / 64, then lane row % 64
-__device__ __forceinline__ double gj_row_value(const gj_col& x, int row) {
-  const double v = x[row >> 6];
+__device__ __forceinline__ double gj_readlane(double v, int l) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)b, row & 63);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), row & 63);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// The panel's nb elimination steps on GJ_COLS columns held in registers, row lane + 64 t in
+// x[.][t].  Panels start at multiples of GJ_NB, so the panel's rows lie in one slot S of every
+// column: the pivot-row value of step k is a read of lane (j0 + k) % 64 of x[.][S], and only
+// slot S needs the pivot-row case.
+template <int S>
+__device__ __forceinline__ void gj_panel_steps(double (&x)[GJ_COLS][GJ_SLOTS],
+                                               const double (*pan)[GJ_MAXN], const double* inv_s,
+                                               int j0, int nb, int n, int lane) {
+  for (int k = 0; k < nb; ++k) {
+    const int col = j0 + k, l = col & 63;
+    const double inv = inv_s[k];
+    double xp[GJ_COLS];
+#pragma unroll
+    for (int q = 0; q < GJ_COLS; ++q) xp[q] = gj_readlane(x[q][S], l) * inv;
+#pragma unroll
+    for (int t = 0; t < GJ_SLOTS; ++t) {
+      const int r = lane + 64 * t;
+      const double f = r < n ? pan[k][r] : 0.0;
+#pragma unroll
+      for (int q = 0; q < GJ_COLS; ++q) {
+        const double v = x[q][t] - f * xp[q];
+        x[q][t] = (t == S && lane == l) ? xp[q] : v;
+      }
+    }
+  }
 }
 
 __global__ void __launch_bounds__(1024) gauss_jordan_kernel(ScreenTabs T, double* M, int mode,
@@ -145,8 +169,8 @@ __global__ void __launch_bounds__(1024) gauss_jordan_kernel(ScreenTabs T, double
     __syncthreads();
     for (int k = 0; k < nb; ++k) {
       const int col = j0 + k;
-      if (wave == 0) {
-        // pivot: the largest |pan[k][r]| for r >= col (lowest row on ties)
+      if (wave == k) {
+        // pivot: the largest |pan[k][r]| for r >= col (lowest row on ties), swapped into place
         double best = -1.0;
         int bi = col;
         for (int r = col + lane; r < n; r += 64) {
@@ -158,40 +182,44 @@ __global__ void __launch_bounds__(1024) gauss_jordan_kernel(ScreenTabs T, double
           const int oi = __shfl_xor(bi, o);
           if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
         }
-        if (lane == 0) piv_s = bi;
-      }
-      __syncthreads();
-      const int p = piv_s;
-      if (p != col) {
-        if (tid < nb) {
-          const double t = pan[tid][col];
-          pan[tid][col] = pan[tid][p];
-          pan[tid][p] = t;
-        }
-        if (tid == 0) {
-          const int t = perm[col];
-          perm[col] = perm[p];
-          perm[p] = t;
+        if (lane == 0) {
+          if (bi != col) {
+            const double t = pan[k][col];
+            pan[k][col] = pan[k][bi];
+            pan[k][bi] = t;
+            const int pt = perm[col];
+            perm[col] = perm[bi];
+            perm[bi] = pt;
+          }
+          piv_s = bi;
+          inv_s[k] = 1.0 / pan[k][col];
         }
       }
       __syncthreads();
-      // eliminate column col from the other rows of the later panel columns
-      const double inv = 1.0 / pan[k][col];
-      const int width = nb - k - 1;
-      for (int it = tid; it < width * n; it += blockDim.x) {
-        const int kk = k + 1 + it / n, r = it % n;
-        if (r != col) pan[kk][r] -= pan[k][r] * (pan[kk][col] * inv);
+      // wave w owns panel column w: the same row swap (the multipliers of earlier steps
+      // included), then for later columns the elimination of column col and the scaling of
+      // the pivot-row entry.  Within a wave the LDS accesses keep program order.
+      if (wave < nb && wave != k) {
+        const int p = piv_s;
+        if (p != col && lane == 0) {
+          const double t = pan[wave][col];
+          pan[wave][col] = pan[wave][p];
+          pan[wave][p] = t;
+        }
+        if (wave > k) {
+          const double piv = pan[wave][col] * inv_s[k];
+          for (int r = lane; r < n; r += 64)
+            if (r != col) pan[wave][r] -= pan[k][r] * piv;
+          if (lane == 0) pan[wave][col] = piv;
+        }
       }
       __syncthreads();
-      // scale the pivot row (read by no one until the next step's elimination)
-      if (tid < width) pan[k + 1 + tid][col] *= inv;
-      if (tid == 0) inv_s[k] = inv;
     }
     __syncthreads();
     // the later columns, GJ_COLS per wave at a time
     const int c0 = j0 + nb;
     for (int g = c0 + wave * GJ_COLS; g < n2; g += nw * GJ_COLS) {
-      gj_col x[GJ_COLS];
+      double x[GJ_COLS][GJ_SLOTS];
 #pragma unroll
       for (int q = 0; q < GJ_COLS; ++q)
 #pragma unroll
@@ -199,19 +227,12 @@ __global__ void __launch_bounds__(1024) gauss_jordan_kernel(ScreenTabs T, double
           const int r = lane + 64 * t;
           x[q][t] = (g + q < n2 && r < n) ? A[(long long)(g + q) * n + perm[r]] : 0.0;
         }
-      for (int k = 0; k < nb; ++k) {
-        const int col = j0 + k;
-        const double inv = inv_s[k];
-        double xp[GJ_COLS];
-#pragma unroll
-        for (int q = 0; q < GJ_COLS; ++q) xp[q] = gj_row_value(x[q], col) * inv;
-#pragma unroll
-        for (int t = 0; t < GJ_SLOTS; ++t) {
-          const int r = lane + 64 * t;
-          const double f = r < n ? pan[k][r] : 0.0;
-#pragma unroll
-          for (int q = 0; q < GJ_COLS; ++q) x[q][t] = r == col ? xp[q] : x[q][t] - f * xp[q];
-        }
+      switch (j0 >> 6) {
+        case 0: gj_panel_steps<0>(x, pan, inv_s, j0, nb, n, lane); break;
+        case 1: gj_panel_steps<1>(x, pan, inv_s, j0, nb, n, lane); break;
+        case 2: gj_panel_steps<2>(x, pan, inv_s, j0, nb, n, lane); break;
+        case 3: gj_panel_steps<3>(x, pan, inv_s, j0, nb, n, lane); break;
+        default: gj_panel_steps<4>(x, pan, inv_s, j0, nb, n, lane); break;
       }
 #pragma unroll
       for (int q = 0; q < GJ_COLS; ++q)
