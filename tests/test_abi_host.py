@@ -115,3 +115,30 @@ def test_missing_library_fails_loudly(tmp_path):
     r = subprocess.run([sys.executable, "-c", "import paper_2005_07834_amd"], cwd=tmp_path,
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0 and "ImportError" in r.stderr and "not built" in r.stderr
+
+
+def test_profile_summaries(tmp_path):
+    """profsum groups dispatches by (kernel, grid size), lists them in dispatch order, and sums
+    a counter over the rows of one dispatch (the per-XCD or per-shader-engine rows)."""
+    from paper_2005_07834_amd import profsum
+    tr = tmp_path / "kernel_trace.csv"
+    tr.write_text(
+        "Kernel_Name,Dispatch_Id,Start_Timestamp,End_Timestamp,Grid_Size\n"
+        "k<1>(int),3,1000000,4000000,256\n"
+        "k<1>(int),1,0,2000000,256\n"
+        "k<1>(int),2,0,500000,512\n"
+        "other(int),4,0,100000000,256\n")
+    lines = profsum.trace(str(tr), r"k<")
+    assert len(lines) == 5 and "other" not in "".join(lines)
+    assert lines[1].split()[:4] == ["2", "2.500", "2.000", "3.000"] and "256" in lines[1]
+    assert lines[2].strip() == "each (ms): 2.000, 3.000"      # dispatch order, not row order
+    assert lines[3].split()[:4] == ["1", "0.500", "0.500", "0.500"] and "512" in lines[3]
+    pm = tmp_path / "counter_collection.csv"
+    pm.write_text(
+        "Kernel_Name,Dispatch_Id,Grid_Size,Counter_Name,Counter_Value\n"
+        "k(int),1,256,FETCH_SIZE,10\n"
+        "k(int),1,256,FETCH_SIZE,5\n"
+        "k(int),2,256,FETCH_SIZE,20\n")
+    lines = profsum.pmc(str(pm), ".")
+    assert lines[1].split()[:3] == ["2", "FETCH_SIZE", "1.750000e+01"]
+    assert lines[2].strip() == "each: 1.500000e+01, 2.000000e+01"
