@@ -199,7 +199,7 @@ __global__ __launch_bounds__(256) void bwd_split_kernel(BwdParams P) {
   __shared__ __attribute__((aligned(1024))) unsigned char s1[S_STAGE];
   __shared__ __attribute__((aligned(1024))) unsigned char s2[S_STAGE];
   __shared__ __attribute__((aligned(1024))) unsigned char s3[S_STAGE];
-  __shared__ double red[2][SN];
+  static_assert(S_STAGE == 64 * SM * 4, "a ring slot holds Y_re or Y_im of 64 K of the tile");
   const int ti = (blockIdx.x & 7) * P.per + (blockIdx.x >> 3);
   if (ti >= P.ntiles) return;
   const BwdTile tl = P.tiles[ti];
@@ -326,64 +326,88 @@ __global__ __launch_bounds__(256) void bwd_split_kernel(BwdParams P) {
     step(s0, s3, fb, fa);
   }
   ring_barrier<0>();
-  // epilogue: element e of a lane's 32 x 32 block is (row 8 (e/4) + 4 (lane/32) + e%4, column
-  // lane%32); per block every load is issued before the first use (the stores may alias
-  // the next block's loads, so each block costs one memory latency)
-  double colsum[2];
+  // epilogue.  Element e of a lane's 32 x 32 accumulator block is (row 8 (e/4) + 4 (lane/32) +
+  // e%4, column lane%32): the lanes of an instruction span 32 K, whose gradient and orbital
+  // rows lie far apart in memory.  So Y goes through the ring's LDS first, Y_re in s0 (K 0..63
+  // of the tile) and s1 (K 64..127), Y_im in s2 and s3, each [K][128 rows] in FP32 with the row
+  // index XOR-ed with K % 32 (the accumulator writes then fall in distinct banks).  Then wave w
+  // takes K = w, w + 4, ..., eight at a time, with the lanes along the tile's rows: the FP64
+  // gradient and the orbitals are read and written along contiguous site rows, and each K's
+  // energy partial is a sum within one wave.
+  {
+    float* yre_s = (float*)(wn ? s1 : s0);
+    float* yim_s = (float*)(wn ? s3 : s2);
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    colsum[j] = 0.0;
-    const int K = tl.k0 + wn * 64 + 32 * j + lr;
-    int kp = -1, band = 0;
-    if (occ && K < P.Ko) {
-      kp = K / P.nocc;
-      band = K - kp * P.nocc;
-    } else if (!occ && K - P.Ko_pad < P.Ku) {
-      const int qq = K - P.Ko_pad;
-      kp = qq / P.nu;
-      band = P.nocc + (qq - kp * P.nu);
-    }
-    const double gw = 2.0 * P.pf * P.ct * P.w[K];
-    const double ew = P.pf * P.ct * P.dw[K];
-    const size_t gbase = (size_t)(max(kp, 0) * P.nb + band) * P.nrows;
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      double gre[16], gim[16], pre[16], pim[16];
-      const int row0 = tl.r0 + wm * 64 + 32 * i + 4 * lh;
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int grow = tl.site_row0 + min(row0 + 8 * (e >> 2) + (e & 3), tl.ns - 1);
-        const size_t gidx = 2 * (gbase + grow), o = (size_t)K * P.rows_pad + grow;
-        gre[e] = P.grad[gidx];
-        gim[e] = P.grad[gidx + 1];
-        pre[e] = P.psi[o];
-        pim[e] = P.psi[plane + o];
-      }
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int row = row0 + 8 * (e >> 2) + (e & 3);
-        const int grow = tl.site_row0 + min(row, tl.ns - 1);
-        const size_t gidx = 2 * (gbase + grow);
-        const double vr = (double)yr[i][j][e], vi = (double)yi[i][j][e];
-        if (kp >= 0 && row < tl.ns) {
-          P.grad[gidx] = gre[e] + gw * vr;
-          P.grad[gidx + 1] = gim[e] + gw * vi;
-          colsum[j] += ew * (pre[e] * vr + pim[e] * vi);
+        for (int e = 0; e < 16; ++e) {
+          const int row = wm * 64 + 32 * i + 8 * (e >> 2) + 4 * lh + (e & 3);
+          const int o = (32 * j + lr) * SM + (row ^ lr);
+          yre_s[o] = yr[i][j][e];
+          yim_s[o] = yi[i][j][e];
         }
-      }
-    }
-  }
-  // reduce the energy partials over the tile's rows (lanes l and l + 32 share a column)
-#pragma unroll
-  for (int j = 0; j < 2; ++j) colsum[j] += __shfl_xor(colsum[j], 32);
-  if (lane < 32) {
-#pragma unroll
-    for (int j = 0; j < 2; ++j) red[wm][wn * 64 + 32 * j + lane] = colsum[j];
   }
   __syncthreads();
-  if (tid < SN) {
-    double* p = P.part + (size_t)tl.part_row * P.K_pad + tl.k0 + tid;
-    *p += red[0][tid] + red[1][tid];
+  constexpr int KB = 8;   // K per batch: every load of a batch is issued before the first use
+  for (int kb = 0; kb < SN / 4; kb += KB) {
+    int kk[KB], kpv[KB], bandv[KB];
+    double gre[KB][2], gim[KB][2], pre[KB][2], pim[KB][2];
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+      kk[u] = wave + 4 * (kb + u);
+      const int K = tl.k0 + kk[u];
+      int kp = -1, band = 0;
+      if (occ && K < P.Ko) {
+        kp = K / P.nocc;
+        band = K - kp * P.nocc;
+      } else if (!occ && K - P.Ko_pad < P.Ku) {
+        const int qq = K - P.Ko_pad;
+        kp = qq / P.nu;
+        band = P.nocc + (qq - kp * P.nu);
+      }
+      kpv[u] = kp;
+      bandv[u] = band;
+      const size_t gbase = (size_t)(max(kp, 0) * P.nb + band) * P.nrows;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        // rows past the site read its last row (their results are not stored)
+        const int grow = tl.site_row0 + min(tl.r0 + lane + 64 * h, tl.ns - 1);
+        const double2 g = *(const double2*)(P.grad + 2 * (gbase + grow));
+        const size_t o = (size_t)K * P.rows_pad + grow;
+        gre[u][h] = g.x;
+        gim[u][h] = g.y;
+        pre[u][h] = P.psi[o];
+        pim[u][h] = P.psi[plane + o];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+      if (kpv[u] < 0) continue;   // K padding (wave-uniform)
+      const int K = tl.k0 + kk[u];
+      const double gw = 2.0 * P.pf * P.ct * P.w[K];
+      const double ew = P.pf * P.ct * P.dw[K];
+      const size_t gbase = (size_t)(kpv[u] * P.nb + bandv[u]) * P.nrows;
+      const int kl = kk[u] & 63;
+      const float* yre_s = (const float*)(kk[u] < 64 ? s0 : s1);
+      const float* yim_s = (const float*)(kk[u] < 64 ? s2 : s3);
+      double sum = 0.0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int row = lane + 64 * h;
+        if (tl.r0 + row < tl.ns) {
+          const int o = kl * SM + (row ^ (kl & 31));
+          const double vr = (double)yre_s[o], vi = (double)yim_s[o];
+          const int grow = tl.site_row0 + tl.r0 + row;
+          *(double2*)(P.grad + 2 * (gbase + grow)) =
+              double2{gre[u][h] + gw * vr, gim[u][h] + gw * vi};
+          sum += ew * (pre[u][h] * vr + pim[u][h] * vi);
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+      if (lane == 0) P.part[(size_t)tl.part_row * P.K_pad + K] += sum;
+    }
   }
 }
 
