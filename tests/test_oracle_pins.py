@@ -643,3 +643,27 @@ def test_iw_linear_gradient_central_differences():
         fd = (Lf(ps + h * V, E) - Lf(ps - h * V, E)) / (2 * h)
         an = float((np.conj(dpsi) * V).real.sum())
         assert abs(fd - an) < 1e-6 * abs(an)
+
+
+def test_iw_gradient_at_zero_frequency_is_the_static_loss_gradient():
+    """Two independently written reference gradients agree: the imaginary-frequency gradient of
+    sum Lambda chi0 at omega = 0, with Lambda = g g^T the sensitivity of the test-charge loss,
+    equals the static test-charge-loss gradient (same nodes)."""
+    w = workload("tiny")
+    nb = 40
+    E = w.energies[:, :nb].copy()
+    ps = w.psi_site.numpy()[:, :nb, :].copy()
+    sites, rho, nocc = w.sites, w.rho_test, w.nocc
+    n, scale = 16, 4.0
+    _, dE, dpsi = gr.loss_and_grads(ps, E, nocc, 2, sites, rho, "time", n, scale)
+    c, al, be = cz.terms_for(E, nocc, "time", n, scale)
+    lams = []
+    for s, sl in zip(sites, gr.site_slices(sites)):
+        chi = cz.chi0_quad(ps[:, :, sl], ps[:, :, sl], nocc, 2, c, al, be)
+        W = sc.screen_W(chi, s)
+        d = sc.radial_weights(s)
+        g = sc.projector(s).T @ (d * (0.5 * (W + W.T) @ (d * sc.charge_moments(rho[sl], s))))
+        lams.append(np.outer(g, g))
+    _, dE0, dpsi0 = gr.linear_grads_iw(ps, E, nocc, 2, sites, lams, n, scale, 0.0)
+    assert np.abs(dE0 - dE).max() < 1e-12 * np.abs(dE).max()
+    assert np.abs(dpsi0 - dpsi).max() < 1e-12 * np.abs(dpsi).max()
