@@ -93,18 +93,23 @@ void lrs_destroy(lrs_ctx* ctx);
 const char* lrs_last_error(const lrs_ctx* ctx);
 
 /* Host-only validation of a band set, usable without a device: nk >= 1,
- * 1 <= nocc < nb, finite energies, and (delta == 0) a global gap:
- * min over k of e[k][nocc] > max over k of e[k][nocc-1].  Returns the status
- * lrs_set_orbitals would return for these energies. */
+ * 1 <= nocc < nb, finite energies, and a global gap:
+ * min over k of e[k][nocc] > max over k of e[k][nocc-1], with mu (if given) inside it.
+ * The side of mu decides occupation (Sec. VI.D) and the lowest nocc bands are the occupied
+ * ones at every k, so a set without such a gap is LRS_ENOGAP with delta == 0 and
+ * LRS_EUNSUPPORTED with delta > 0 (a metal whose occupied count changes with k).  Returns
+ * the status lrs_set_orbitals would return for these energies. */
 lrs_status lrs_check_bands(int nk, int nb, int nocc, const double* energies_host, double mu,
                            double delta);
 
 /* Band energies and the grid orbitals (Sec. VI.A-D).
  *   energies_host  [nk][nb] float64, Ha; the lowest nocc bands at every k are occupied.
  *   mu             chemical potential; NaN = middle of the global gap (Sec. VI.D).
- *                  With delta == 0 it must lie strictly inside the gap.
- *   delta          metallic regularisation of Sec. VI.D: |mu - e| -> sqrt((mu - e)^2 + delta^2)
- *                  in every energy offset (0 = off).
+ *                  It must lie strictly inside the gap.
+ *   delta          metallic regularisation of Sec. VI.D: every offset mu - e keeps its sign and
+ *                  takes delta in quadrature, mu - e -> +-sqrt((mu - e)^2 + delta^2) (0 = off).
+ *                  Every occupied band must still lie below mu and every other band above it
+ *                  (lrs_check_bands).
  *   spin_factor    s in the prefactor -2 s / N_k^2 (2 for a closed shell, 1 per spin channel).
  *   psi_grid       complex128 [nk][nb][ngrid] on the device, or NULL with ngrid = 0.
  *   grid_dV        volume element of the grid (kept for the caller; not used by chi0).

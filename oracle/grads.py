@@ -15,7 +15,8 @@ the loss's dependence on chi0 is Q = P_f sum |M|^2 K_{nk,mk'} and
     grad psi_mk'(p) = 2 P_f g(p) sum_{n,k}  M K psi_nk(p)
 (complex gradients as dL/dRe + i dL/dIm).  Exact denominators: K = 1/Delta,
 dK/de_n = 1/Delta^2, dK/de_m = -1/Delta^2.  Imaginary-time terms with mu and
-the nodes held fixed: dK/de_n = sum_l c_l tau_l alpha beta, dK/de_m = -that.
+the nodes held fixed: dK/de_n = sum_l c_l tau_l alpha beta, dK/de_m = -that.  With the
+metallic regularisation each offset's derivative carries the chain factor of its square root.
 
 At imaginary frequency (complex kernel z = K_e + i K_o per pair, chi0 = P_f sum
 Re[z rho(r) conj(rho(c))] with rho = psi_nk* psi_mk'), for a linear functional
@@ -54,38 +55,46 @@ def loss(psi_site, E, nocc, spin, sites, rho, kern, lmax=2):
     return total, Ws
 
 
+def _chain(E, nocc, mu, delta):
+    """Regularised offsets X, Y (Sec. VI.D) and their derivatives with respect to the band
+    energy, mu fixed: X = sqrt((mu - e)^2 + delta^2) gives dX/de = -(mu - e)/X, and
+    Y = sqrt((e - mu)^2 + delta^2) gives dY/de = (e - mu)/Y (-1 and +1 when delta = 0)."""
+    X, Y = q.offsets(E, nocc, mu, delta)
+    return X, Y, -(mu - E[:, :nocc]) / X, (E[:, nocc:] - mu) / Y
+
+
 def _kernels_exact(E, nocc, mu, delta):
-    x, y = q.offsets(E, nocc, mu, delta)
-    if delta > 0:
-        raise NotImplementedError("reference gradient with delta > 0")
+    x, y, dx, dy = _chain(E, nocc, mu, delta)
 
     def K(k, kp):
         d = x[k][:, None] + y[kp][None, :]
-        return 1.0 / d, 1.0 / d ** 2, -1.0 / d ** 2
+        return 1.0 / d, -dx[k][:, None] / d ** 2, -dy[kp][None, :] / d ** 2
     return K
 
 
-def _kernels_time(E, nocc, mu, n, scale):
-    x, y = q.offsets(E, nocc, mu)
+def _kernels_time(E, nocc, mu, n, scale, delta=0.0):
+    x, y, dx, dy = _chain(E, nocc, mu, delta)
     c, al, be, tau = q.imag_time_terms(x, y, n, scale)
 
     def K(k, kp):
         base = np.einsum("l,ln,lm->nm", c, al[:, k], be[:, kp])
+        # d exp(-x tau)/de = -tau exp(-x tau) dx/de, likewise for y
         d = np.einsum("l,ln,lm->nm", c * tau, al[:, k], be[:, kp])
-        return base, d, -d
+        return base, -d * dx[k][:, None], -d * dy[kp][None, :]
     return K
 
 
 def loss_and_grads(psi_site, E, nocc, spin, sites, rho, kind="exact", n_terms=None,
-                   scale=None, lmax=2):
-    """Returns (loss, dL/dE [nk, nb], dL/dpsi_site complex [nk, nb, npts])."""
+                   scale=None, lmax=2, delta=0.0):
+    """Returns (loss, dL/dE [nk, nb], dL/dpsi_site complex [nk, nb, npts]); delta is the
+    metallic regularisation of Sec. VI.D (mu mid-gap and fixed)."""
     mu = q.mid_gap(E, nocc)
     if kind == "exact":
-        kfun = _kernels_exact(E, nocc, mu, 0.0)
-        kern = cz.exact_kernel(E, nocc, mu)
+        kfun = _kernels_exact(E, nocc, mu, delta)
+        kern = cz.exact_kernel(E, nocc, mu, delta)
     elif kind == "time":
-        kfun = _kernels_time(E, nocc, mu, n_terms, scale)
-        c, al, be = cz.terms_for(E, nocc, "time", n_terms, scale, mu)
+        kfun = _kernels_time(E, nocc, mu, n_terms, scale, delta)
+        c, al, be = cz.terms_for(E, nocc, "time", n_terms, scale, mu, delta)
         kern = cz.quad_kernel(c, al, be)
     else:
         raise ValueError(kind)

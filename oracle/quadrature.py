@@ -40,15 +40,29 @@ def mid_gap(E: np.ndarray, nocc: int) -> float:
     return 0.5 * (E[:, :nocc].max() + E[:, nocc:].min())
 
 
+def regularised(d: np.ndarray, delta: float) -> np.ndarray:
+    """The metallic regularisation of Sec. VI.D applied to offsets d = mu - e: the offset keeps
+    its sign and takes delta in quadrature, d -> sign(d) sqrt(d^2 + delta^2); delta = 0 leaves
+    it unchanged."""
+    d = np.asarray(d, dtype=np.float64)
+    if delta <= 0:
+        return d
+    return np.sign(d) * np.sqrt(d * d + delta * delta)
+
+
 def offsets(E: np.ndarray, nocc: int, mu: float, delta: float = 0.0):
-    """x = mu - e_occ, y = e_unocc - mu; with the metallic regularisation of Sec. VI.D
-    each becomes sqrt(x^2 + delta^2) when delta > 0."""
+    """x = mu - e_occ > 0 and y = e_unocc - mu > 0, regularised by delta (Sec. VI.D).
+
+    Which side of mu a band lies on decides whether it is occupied.  Here the lowest nocc
+    bands at every k are the occupied ones, so every one of them must lie below mu and every
+    other band above it; a band on the other side would make the occupied count depend on k,
+    which this form does not express (ValueError)."""
     x = mu - E[:, :nocc]
     y = E[:, nocc:] - mu
-    if delta > 0:
-        x = np.sqrt(x * x + delta * delta)
-        y = np.sqrt(y * y + delta * delta)
-    return x, y
+    if not (x.min() > 0 and y.min() > 0):
+        raise ValueError("a band lies on the other side of mu than its occupation says")
+    # y = e - mu is minus the offset mu - e: regularise the offset, then flip the sign
+    return regularised(x, delta), -regularised(-y, delta)
 
 
 def imag_time_terms(x, y, n: int, scale: float):

@@ -220,18 +220,21 @@ lrs_status install_terms(lrs_ctx* ctx, Quad& q, const std::vector<double>& c,
   return LRS_OK;
 }
 
-// x = mu - e_occ, y = e_unocc - mu with the metallic regularisation
+// x = mu - e_occ > 0, y = e_unocc - mu > 0 (lrs_check_bands put every band on its label's
+// side of mu), with the metallic regularisation of Sec. VI.D: mu - e keeps its sign and takes
+// delta in quadrature, so x -> sqrt(x^2 + delta^2) and y -> sqrt(y^2 + delta^2)
 void offsets(const lrs_ctx* ctx, std::vector<double>& x, std::vector<double>& y) {
   x.resize(ctx->Ko);
   y.resize(ctx->Ku);
+  const double d2 = ctx->delta > 0 ? ctx->delta * ctx->delta : 0.0;
   for (int k = 0; k < ctx->nk; ++k) {
     for (int n = 0; n < ctx->nocc; ++n) {
-      double v = ctx->mu - ctx->energies[(size_t)k * ctx->nb + n];
-      x[(size_t)k * ctx->nocc + n] = ctx->delta > 0 ? std::sqrt(v * v + ctx->delta * ctx->delta) : v;
+      const double v = ctx->mu - ctx->energies[(size_t)k * ctx->nb + n];
+      x[(size_t)k * ctx->nocc + n] = d2 > 0 ? std::sqrt(v * v + d2) : v;
     }
     for (int m = 0; m < ctx->nu; ++m) {
-      double v = ctx->energies[(size_t)k * ctx->nb + ctx->nocc + m] - ctx->mu;
-      y[(size_t)k * ctx->nu + m] = ctx->delta > 0 ? std::sqrt(v * v + ctx->delta * ctx->delta) : v;
+      const double v = ctx->energies[(size_t)k * ctx->nb + ctx->nocc + m] - ctx->mu;
+      y[(size_t)k * ctx->nu + m] = d2 > 0 ? std::sqrt(v * v + d2) : v;
     }
   }
 }
@@ -594,10 +597,14 @@ lrs_status lrs_check_bands(int nk, int nb, int nocc, const double* e, double mu,
     for (int n = 0; n < nocc; ++n) top = std::max(top, e[(size_t)k * nb + n]);
     for (int m = nocc; m < nb; ++m) bottom = std::min(bottom, e[(size_t)k * nb + m]);
   }
-  if (delta == 0) {
-    if (!(bottom > top)) return LRS_ENOGAP;
-    if (!std::isnan(mu) && !(mu > top && mu < bottom)) return LRS_ENOGAP;
-  }
+  // The side of mu decides occupation (Sec. VI.D; the metallic regularisation keeps the sign
+  // of mu - e).  The lowest nocc bands are occupied at every k, so every one of them must lie
+  // below mu and every other band above it.  Without regularisation a band set that allows no
+  // such mu has no gap; with it, such a set (a metal whose occupied count changes with k) is
+  // a case this library does not implement.
+  const lrs_status side = delta > 0 ? LRS_EUNSUPPORTED : LRS_ENOGAP;
+  if (!(bottom > top)) return side;
+  if (!std::isnan(mu) && !(mu > top && mu < bottom)) return side;
   return LRS_OK;
 }
 
@@ -610,6 +617,9 @@ lrs_status lrs_set_orbitals(lrs_ctx* ctx, int nk, int nb, int nocc, int spin_fac
   if (st == LRS_EINVAL) return fail(ctx, st, "invalid band set (nk=%d nb=%d nocc=%d delta=%g)", nk, nb, nocc, delta);
   if (st == LRS_ENONFINITE) return fail(ctx, st, "non-finite band energy or mu");
   if (st == LRS_ENOGAP) return fail(ctx, st, "no global gap between occupied and unoccupied bands (or mu outside it)");
+  if (st == LRS_EUNSUPPORTED)
+    return fail(ctx, st, "with delta > 0 a band labelled occupied lies above mu or an unoccupied "
+                "one below it: occupied counts that change with k are not supported");
   if (spin_factor != 1 && spin_factor != 2) return fail(ctx, LRS_EINVAL, "spin_factor must be 1 or 2");
   if (ngrid < 0 || (ngrid > 0 && !psi_grid) || (ngrid == 0 && psi_grid))
     return fail(ctx, LRS_EINVAL, "psi_grid and ngrid must be given together");

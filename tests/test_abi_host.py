@@ -39,7 +39,11 @@ def test_check_bands_status_codes():
     ov = E.copy()
     ov[1, 1] = 0.25          # occupied at k=1 above the unoccupied bottom at k=0
     assert P.check_bands(ov, 2) == P.LRS_ENOGAP
-    assert P.check_bands(ov, 2, delta=0.01) == P.LRS_OK   # metallic regularisation needs no gap
+    # with the metallic regularisation the side of mu still decides occupation: a band set
+    # that needs k-dependent occupied counts is refused, one with a gap is accepted
+    assert P.check_bands(ov, 2, delta=0.01) == P.LRS_EUNSUPPORTED
+    assert P.check_bands(E, 2, delta=0.01) == P.LRS_OK
+    assert P.check_bands(E, 2, mu=-0.45, delta=0.01) == P.LRS_EUNSUPPORTED
     assert P.check_bands(E, 2, mu=0.1) == P.LRS_OK
     assert P.check_bands(E, 2, mu=-0.45) == P.LRS_ENOGAP  # mu below the valence top
     assert P.check_bands(E, 2, delta=-1.0) == P.LRS_EINVAL

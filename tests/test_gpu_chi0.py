@@ -253,3 +253,54 @@ def test_chi0_backward_vs_oracle(P, tiny_ref, prec, tol):
         with pytest.raises(P.LrsError) as e:
             ctx.chi0_backward(lam, bad)
         assert e.value.status == P.LRS_EUNSUPPORTED
+
+
+def test_metallic_regularisation_tiny(P, tiny_ref):
+    """delta > 0 (Sec. VI.D, each offset keeps its sign and takes delta in quadrature): chi0
+    with both rules and the FP64 adjoint against the oracle with the same regularised offsets;
+    a band set that would need k-dependent occupation is refused."""
+    w = tiny_ref["w"]
+    ps, pg = tiny_ref["ps"], tiny_ref["pg"]
+    delta, n = 0.02, 24
+    say("tiny metallic delta", delta)
+    ctx = P.Context(0)
+    ctx.set_orbitals(w.energies, w.nocc, w.psi_grid, w.grid_dV, delta=delta)
+    ctx.set_sites(w.sites, w.psi_site)
+    ctx.make_quadrature(P.QUAD_TIME, n, 0.0)
+    mu = q.mid_gap(w.energies, w.nocc)
+    terms = cz.terms_for(w.energies, w.nocc, "time", n, None, mu, delta)
+    x, y = q.offsets(w.energies, w.nocc, mu, delta)
+    assert abs(ctx.get_quadrature()["scale"] / q.auto_scale(x, y, n) - 1) < 1e-12
+    g = ctx.chi0(-1, P.COLS_GRID, P.FP64).cpu().numpy()
+    s = ctx.site_blocks(ctx.chi0(-1, P.COLS_SITE, P.FP64))[0].cpu().numpy()
+    qg = cz.chi0_quad(ps, pg, w.nocc, 2, *terms)
+    qs = cz.chi0_quad(ps, ps, w.nocc, 2, *terms)
+    eg = cz.chi0_exact(ps, pg, w.energies, w.nocc, mu=mu, delta=delta)
+    say(f"  grid vs quad {rel(g, qg):.3e} vs exact {rel(g, eg):.3e}; site {rel(s, qs):.3e}")
+    assert rel(g, qg) < 1e-12 and rel(s, qs) < 1e-12 and rel(g, eg) < 1e-6
+    # the regularisation changes the result (so the comparison above is not vacuous)
+    assert rel(g, tiny_ref["exact_grid"]) > 1e-3
+    # adjoint of the test-charge loss, mu and the nodes fixed
+    scale = ctx.get_quadrature()["scale"]
+    chi = ctx.chi0(-1, P.COLS_SITE, P.FP64)
+    ctx.screen_W(chi, rho=w.rho_test, want_loss=True)
+    lam = ctx.screen_W_backward()
+    dE, dpsi = ctx.chi0_backward(lam, P.FP64)
+    _, dE_ref, dpsi_ref = gr.loss_and_grads(ps, w.energies, w.nocc, 2, w.sites, w.rho_test,
+                                            "time", n, scale, delta=delta)
+    say(f"  dE {rel(dE.cpu().numpy(), dE_ref):.3e} dpsi {rel(dpsi.cpu().numpy(), dpsi_ref):.3e}")
+    assert rel(dE.cpu().numpy(), dE_ref) < 1e-9 and rel(dpsi.cpu().numpy(), dpsi_ref) < 1e-9
+    # the paper's frequency rule with delta: zeta takes 0.5 eV in quadrature
+    ctx.make_quadrature(P.QUAD_FREQ, 16, 0.0)
+    assert abs(ctx.get_quadrature()["scale"] / q.zeta(w.energies, mu, metallic=True) - 1) < 1e-13
+    sf = ctx.site_blocks(ctx.chi0(-1, P.COLS_SITE, P.FP64))[0].cpu().numpy()
+    rf = cz.chi0_quad(ps, ps, w.nocc, 2, *cz.terms_for(w.energies, w.nocc, "freq", 16, None, mu,
+                                                       delta))
+    assert rel(sf, rf) < 1e-12
+    # an occupied band pushed above the bottom of the unoccupied ones at another k
+    bad = w.energies.copy()
+    bad[0, w.nocc - 1] = bad[0, w.nocc:].min() + 0.01
+    with pytest.raises(P.LrsError) as e:
+        ctx.set_orbitals(bad, w.nocc, None, 0.0, delta=delta)
+    assert e.value.status == P.LRS_EUNSUPPORTED
+    ctx.close()

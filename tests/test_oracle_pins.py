@@ -254,7 +254,7 @@ def test_W_special_cases(tiny):
     v00 = 4 * math.pi / 1.5
     u = one.rad_w[0]
     assert abs(W[0, 0] - v00 / (1 - v00 * u * x00 * u)) < 1e-13 * v00
-    assert np.abs(W[1:, 1:] - V[1:, 1:] if False else W[1:, 1:] - sc.coulomb(one)[1:, 1:]).max() < 1e-13
+    assert np.abs(W[1:, 1:] - sc.coulomb(one)[1:, 1:]).max() < 1e-13
 
 
 def test_W_push_through_and_screening_bound(tiny):
