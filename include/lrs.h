@@ -168,6 +168,16 @@ lrs_status lrs_make_quadrature(lrs_ctx* ctx, int kind, int nnodes, double scale)
  * lrs_make_quadrature(LRS_QUAD_TIME, ...). */
 lrs_status lrs_make_quadrature_iw(lrs_ctx* ctx, int nnodes, double scale, double omega);
 
+/* The imaginary-time rule of lrs_make_quadrature(LRS_QUAD_TIME) with the node count picked from
+ * the band-energy range: the smallest n in [nmin, nmax] (1 <= nmin <= nmax <= 64) whose rule,
+ * at its automatic scale, keeps the worst relative error of sum_j c_j exp(-D tau_j) against 1/D
+ * at or below tol over 512 log-spaced D in [Dmin, Dmax] (every band pair's denominator lies in
+ * that range); nmax when none does.  One node set serves every k (cross-k pairs need a common
+ * tau).  Writes the chosen n and its error to *nnodes_host and *err_host (either may be NULL).
+ * LRS_EINVAL for tol <= 0 or a bad range. */
+lrs_status lrs_make_quadrature_tol(lrs_ctx* ctx, double tol, int nmin, int nmax, int* nnodes_host,
+                                   double* err_host);
+
 /* Reads back the terms in use: c_host [nterms], tau_host [nterms] (tau for LRS_QUAD_TIME,
  * t for LRS_QUAD_FREQ, 0 for generic), mu and the time scale C / zeta (may be NULL). */
 lrs_status lrs_get_quadrature(const lrs_ctx* ctx, int* nterms, double* c_host, double* tau_host,
@@ -202,9 +212,21 @@ lrs_status lrs_project_orbitals(lrs_ctx* ctx, int nk, int nb, int npw, const dou
  * suits launches that share the GPU with other kernels.
  * Graph capture: once a call has run on a problem (same site, column set and precision), the
  * same call may be captured on the context's stream (e.g. into a HIP graph); under capture it
- * records kernels only, records no timing event, and returns LRS_ESTATE instead of
- * allocating or building a plan. */
+ * records kernels only (the weighted site operand's preparation included, so a replay does not
+ * depend on what the operand buffer holds), records no timing event, and returns LRS_ESTATE
+ * instead of allocating or building a plan.  A successful capture pins the context: the graph
+ * holds the addresses of its buffers (orbital operands, weights, term coefficients, tile
+ * lists, the site operand and the per-workgroup scratch), so until lrs_release_graphs
+ * lrs_set_orbitals, lrs_set_sites, lrs_set_quadrature, lrs_make_quadrature(_iw, _tol) and any
+ * call that would have to replace one of those buffers with a larger one (chi0 in another
+ * precision or column set, the backward pass, lrs_tune) return LRS_ESTATE; eager calls that
+ * fit the existing buffers, the solves of lrs_screen_W and friends, and replays stay valid.
+ * lrs_destroy frees the buffers regardless: destroy the graphs first. */
 lrs_status lrs_compute_chi0(lrs_ctx* ctx, int site, int cols, int prec, double* chi0_out);
+
+/* Unpins the context (see lrs_compute_chi0): the caller declares that no graph captured from
+ * this context's calls will be replayed again. */
+lrs_status lrs_release_graphs(lrs_ctx* ctx);
 
 /* Per-site dielectric solve from site x site chi0 blocks (layout of LRS_COLS_SITE, all sites):
  *   X = P chi0 P^T (P_{(L,i),(i',a)} = delta_ii' w_a Y_L(a)), V_L = 4 pi/(2l+1) r_<^l / r_>^(l+1),
@@ -216,6 +238,7 @@ lrs_status lrs_compute_chi0(lrs_ctx* ctx, int site, int cols, int prec, double* 
  * site has more than 288 basis functions (n_rad > 32) or 256 directions. */
 lrs_status lrs_screen_W(lrs_ctx* ctx, const double* chi0_sitesite, double* W_out,
                         const double* rho_test, double* loss_out);
+
 
 /* Induced density and potential of a spherical perturbation at every site (Sec. VI,
  * construction of chi and W; the perturbation is the short-range part of a potential split by
@@ -270,10 +293,21 @@ lrs_status lrs_screen_W_backward(lrs_ctx* ctx, const double* dL_dW, double* dL_d
 lrs_status lrs_compute_chi0_backward(lrs_ctx* ctx, int cols, int prec, const double* dL_dchi0,
                                      double* dL_dE, void* dL_dpsi_site, void* dL_dpsi_grid);
 
-/* Times the candidate tile configurations of precision prec on the current problem and keeps
- * the fastest for later lrs_compute_chi0 calls; the choice is cached on disk in the file named
- * by LRS_TUNE_CACHE (if set), keyed by precision and problem shape.  Synchronous. */
+/* Autotuner: times every compiled chi0 variant (workgroup tile shape, LDS ring depth, operand
+ * scheduling) of precision prec on each column set of the current problem (the cell grid if
+ * it was given, and the site blocks), sampled on the site with the most points: the site x grid
+ * launch over its first two rounds of tiles of the real plan, the site block whole, scored by
+ * milliseconds per output entry covered.  The fastest is kept per (precision, column set) for
+ * later lrs_compute_chi0 calls (the environment variable LRS_VARIANT overrides it).  If
+ * LRS_TUNE_CACHE names a file, choices are read from it (keyed by precision, column set, the
+ * site's rows, columns, K and terms) instead of timed, and new ones appended.  Synchronous;
+ * LRS_ESTATE without orbitals, sites and terms. */
 lrs_status lrs_tune(lrs_ctx* ctx, int prec);
+
+/* The chi0 variant that lrs_compute_chi0 uses for (prec, cols) (tuned, or the default) and its
+ * workgroup tile shape: *variant_host, and *tile_rows_host x *tile_cols_host (may be NULL). */
+lrs_status lrs_tuned_variant(const lrs_ctx* ctx, int prec, int cols, int* variant_host,
+                             int* tile_rows_host, int* tile_cols_host);
 
 /* Duration in milliseconds of the main kernel of the last lrs_compute_chi0 call, measured
  * with HIP events on the context's stream (synchronises).  -1 if none. */

@@ -85,9 +85,10 @@ def _kernels_time(E, nocc, mu, n, scale, delta=0.0):
 
 
 def loss_and_grads(psi_site, E, nocc, spin, sites, rho, kind="exact", n_terms=None,
-                   scale=None, lmax=2, delta=0.0):
-    """Returns (loss, dL/dE [nk, nb], dL/dpsi_site complex [nk, nb, npts]); delta is the
-    metallic regularisation of Sec. VI.D (mu mid-gap and fixed)."""
+                   scale=None, lmax=2, delta=0.0, with_W=False):
+    """Returns (loss, dL/dE [nk, nb], dL/dpsi_site complex [nk, nb, npts]), and the per-site W
+    as a fourth item when with_W; delta is the metallic regularisation of Sec. VI.D (mu
+    mid-gap and fixed)."""
     mu = q.mid_gap(E, nocc)
     if kind == "exact":
         kfun = _kernels_exact(E, nocc, mu, delta)
@@ -119,6 +120,8 @@ def loss_and_grads(psi_site, E, nocc, spin, sites, rho, kind="exact", n_terms=No
                 dE[kp, nocc:] += Pf * (M2 * dKm).sum(0)
                 dpsi[k, :nocc, sl] += 2 * Pf * g[None, :] * ((np.conj(M) * Km) @ pu[kp])
                 dpsi[kp, nocc:, sl] += 2 * Pf * g[None, :] * ((M * Km).T @ po[k])
+    if with_W:
+        return L, dE, dpsi, Ws
     return L, dE, dpsi
 
 

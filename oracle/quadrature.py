@@ -165,3 +165,16 @@ def freq_terms(x, y, n: int, z: float):
 def kernel(c, alpha, beta, k: int, kp: int) -> np.ndarray:
     """K_nm for occupied bands at k and unoccupied bands at kp: sum_l c_l alpha_l(k,n) beta_l(kp,m)."""
     return np.einsum("l,ln,lm->nm", c, alpha[:, k, :], beta[:, kp, :])
+
+
+def auto_nodes(x, y, tol: float, nmin: int = 24, nmax: int = 32):
+    """The smallest node count n in [nmin, nmax] whose imaginary-time rule (with its own
+    auto_scale) keeps the worst per-pair relative error over [Dmin, Dmax] at or below tol; nmax
+    if none does.  Returns (n, scale, error)."""
+    dmin = float(x.min() + y.min())
+    dmax = float(x.max() + y.max())
+    for n in range(nmin, nmax + 1):
+        s = auto_scale(x, y, n)
+        e = imag_time_error(s, n, dmin, dmax)
+        if e <= tol or n == nmax:
+            return n, s, e

@@ -46,11 +46,14 @@ SIGNATURES = [
     ("lrs_screen_W_backward", _I, [_P, _P, _P]),
     ("lrs_compute_chi0_backward", _I, [_P, _I, _I, _P, _P, _P, _P]),
     ("lrs_tune", _I, [_P, _I]),
+    ("lrs_tuned_variant", _I, [_P, _I, _I, _P, _P, _P]),
     ("lrs_project_orbitals", _I, [_P, _I, _I, _I, _P, _P, _P, _D, _I, _P, _P]),
     ("lrs_induced_potential", _I, [_P, _P, _P, _D, _D, _I, _P, _P]),
     ("lrs_screen_W_alda", _I, [_P, _P, _P, _P]),
     ("lrs_make_quadrature_iw", _I, [_P, _I, _D, _D]),
+    ("lrs_make_quadrature_tol", _I, [_P, _D, _I, _I, _P, _P]),
     ("lrs_last_kernel_ms", _D, [_P]),
+    ("lrs_release_graphs", _I, [_P]),
 ]
 
 
@@ -172,6 +175,16 @@ class Context:
         self.orb_version += 1
         self._check(lib.lrs_make_quadrature_iw(self.h, nnodes, scale, omega))
 
+    def make_quadrature_tol(self, tol, nmin=24, nmax=32):
+        """Imaginary-time terms with the node count picked from the band-energy range: the
+        smallest n in [nmin, nmax] meeting the per-pair bound tol.  Returns (n, error)."""
+        n = np.zeros(1, dtype=np.int32)
+        e = np.zeros(1)
+        self.orb_version += 1
+        self._check(lib.lrs_make_quadrature_tol(self.h, float(tol), int(nmin), int(nmax), _ptr(n),
+                                                _ptr(e)))
+        return int(n[0]), float(e[0])
+
     def set_quadrature(self, c, alpha, beta):
         c = _host(c, np.float64)
         a = _host(alpha, np.float64)
@@ -285,10 +298,23 @@ class Context:
                                              float(omega), pt.shape[0], _ptr(pt), _ptr(out)))
         return out
 
+    def release_graphs(self):
+        """Unpins the context after the graphs that captured its calls are gone."""
+        self._check(lib.lrs_release_graphs(self.h))
+
     def tune(self, prec):
         if isinstance(prec, str):
             prec = PREC_NAMES[prec]
         self._check(lib.lrs_tune(self.h, prec))
+
+    def tuned_variant(self, prec, cols=COLS_GRID):
+        """(variant, tile rows, tile cols) that chi0 uses for this precision and column set."""
+        if isinstance(prec, str):
+            prec = PREC_NAMES[prec]
+        v = np.zeros(3, dtype=np.int32)
+        self._check(lib.lrs_tuned_variant(self.h, prec, cols, _ptr(v[0:1]), _ptr(v[1:2]),
+                                          _ptr(v[2:3])))
+        return int(v[0]), int(v[1]), int(v[2])
 
     def last_kernel_ms(self):
         return float(lib.lrs_last_kernel_ms(self.h))

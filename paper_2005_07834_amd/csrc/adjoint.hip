@@ -643,8 +643,10 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
     for (const Batch& bt : plan->batches) {
       if (bt.ntiles == 0) continue;
       const void* a_op = nullptr;
-      if (ensure_site_operand(ctx, prec, bt, t, 1, &a_op) != LRS_OK) return hipErrorOutOfMemory;
-      if (ensure_park(ctx, prec, 0, bt.grid) != LRS_OK) return hipErrorOutOfMemory;
+      // (LRS_ESTATE: a buffer that captured graphs read would have to be replaced)
+      lrs_status ls = ensure_site_operand(ctx, prec, bt, t, 1, &a_op);
+      if (ls == LRS_OK) ls = ensure_park(ctx, prec, 0, bt.grid);
+      if (ls != LRS_OK) return ls == LRS_ESTATE ? hipErrorIllegalState : hipErrorOutOfMemory;
       e = launch_green_adjoint(prec, bt.grid, a_op, bt.nrb, ctx->site_tiles[prec].p,
                                ctx->site_cols_pad / 16, ctx->K_pad / chunk,
                                (const double*)ctx->c_dev.p + t, ctx->Ko_pad / chunk,

@@ -57,6 +57,9 @@ lrs_status ensure_buf(lrs_ctx* ctx, DevBuf& b, size_t bytes, const char* what) {
   if (ctx->capturing)
     return fail(ctx, LRS_ESTATE, "%s: the call would allocate during stream capture; run it "
                 "once on the same problem before capturing", what);
+  if (b.p && ctx->graph_pinned)
+    return fail(ctx, LRS_ESTATE, "%s: the call would replace a buffer that captured graphs "
+                "read; call lrs_release_graphs once those graphs are gone", what);
   release(ctx, b);
   if (ctx->max_bytes && ctx->bytes_in_use + bytes > ctx->max_bytes)
     return fail(ctx, LRS_ENOMEM, "%s: %zu bytes would exceed LRS_MAX_BYTES (%zu in use)", what,
@@ -399,6 +402,9 @@ lrs_status get_plan(lrs_ctx* ctx, int site, int cols, int prec, int variant, int
     long long g = std::min<long long>(maxg, round_up(std::max(b.ntiles, 1), 8));
     b.grid = (int)std::max<long long>(8, g / 8 * 8);
   }
+  p.area.assign(tiles.size() + 1, 0);
+  for (size_t i = 0; i < tiles.size(); ++i)
+    p.area[i + 1] = p.area[i] + (long long)tiles[i].nrows * tiles[i].ncols;
   CHECK(ensure_buf(ctx, p.tiles, tiles.size() * sizeof(TileDesc) + 32, "tile list"));
   HIP_OR_FAIL(ctx, hipMemcpyAsync(p.tiles.p, tiles.data(), tiles.size() * sizeof(TileDesc),
                                   hipMemcpyHostToDevice, ctx->stream));
@@ -415,6 +421,10 @@ lrs_status get_plan(lrs_ctx* ctx, int site, int cols, int prec, int variant, int
 // adjoint's one-term requests reuse the all-term operand of the forward launches.
 lrs_status site_operand(lrs_ctx* ctx, int prec, const Batch& b, int t0, int nt,
                         const void** a = nullptr) {
+  // Under capture the graph must build the operand itself (a replay cannot rely on what the
+  // buffer held at capture time); while graphs are pinned their replays rewrite the buffer in
+  // stream order, so the kept operand is never trusted then either.
+  if (ctx->capturing || ctx->graph_pinned) ctx->a_prec = -1;
   if (ctx->a_prec == prec && ctx->a_version == ctx->quad_version && ctx->a_rb0 == b.rb0 &&
       ctx->a_nrb == b.nrb && ctx->a_t0 <= t0 && t0 + nt <= ctx->a_t0 + ctx->a_nt &&
       ctx->a_tiles.p) {
@@ -445,13 +455,13 @@ lrs_status park_for(lrs_ctx* ctx, int prec, int variant, int grid) {
   return ensure_buf(ctx, ctx->park, bytes, "G_o scratch");
 }
 
-int pick_variant(lrs_ctx* ctx, int prec) {
+int pick_variant(lrs_ctx* ctx, int prec, int cols) {
   const char* e = std::getenv("LRS_VARIANT");
   if (e) {
     int v = std::atoi(e);
     if (v >= 0 && v < chi0_num_variants(prec)) return v;
   }
-  if (ctx->tuned_variant[prec] >= 0) return ctx->tuned_variant[prec];
+  if (ctx->tuned_variant[prec][cols] >= 0) return ctx->tuned_variant[prec][cols];
   return chi0_default_variant(prec);
 }
 
@@ -613,6 +623,9 @@ lrs_status lrs_set_orbitals(lrs_ctx* ctx, int nk, int nb, int nocc, int spin_fac
                             int ngrid, double grid_dV) {
   if (!ctx) return LRS_EINVAL;
   ctx->err.clear();
+  if (ctx->graph_pinned)
+    return fail(ctx, LRS_ESTATE, "captured graphs read this context's buffers; call "
+                "lrs_release_graphs once those graphs are gone");
   lrs_status st = lrs_check_bands(nk, nb, nocc, e, mu, delta);
   if (st == LRS_EINVAL) return fail(ctx, st, "invalid band set (nk=%d nb=%d nocc=%d delta=%g)", nk, nb, nocc, delta);
   if (st == LRS_ENONFINITE) return fail(ctx, st, "non-finite band energy or mu");
@@ -688,6 +701,9 @@ lrs_status lrs_set_sites(lrs_ctx* ctx, int nsites, const int* nrad, const int* n
                          const double* ang_w, const void* psi_site, int lmax) {
   if (!ctx) return LRS_EINVAL;
   ctx->err.clear();
+  if (ctx->graph_pinned)
+    return fail(ctx, LRS_ESTATE, "captured graphs read this context's buffers; call "
+                "lrs_release_graphs once those graphs are gone");
   if (!ctx->have_bands) return fail(ctx, LRS_ESTATE, "lrs_set_orbitals must come first");
   if (nsites < 1 || !nrad || !nang || !radii || !rad_w || !ang_xyz || !ang_w || !psi_site)
     return fail(ctx, LRS_EINVAL, "missing site arguments");
@@ -758,6 +774,9 @@ lrs_status lrs_set_quadrature(lrs_ctx* ctx, int nterms, const double* c, const d
                               const double* beta) {
   if (!ctx) return LRS_EINVAL;
   ctx->err.clear();
+  if (ctx->graph_pinned)
+    return fail(ctx, LRS_ESTATE, "captured graphs read this context's buffers; call "
+                "lrs_release_graphs once those graphs are gone");
   if (!ctx->have_bands) return fail(ctx, LRS_ESTATE, "lrs_set_orbitals must come first");
   if (nterms < 1 || nterms > kMaxTerms || !c || !alpha || !beta)
     return fail(ctx, LRS_EINVAL, "nterms must be 1..%d with all arrays given", kMaxTerms);
@@ -800,6 +819,9 @@ static lrs_status make_quadrature(lrs_ctx* ctx, int kind, int nnodes, double sca
                                   double omega) {
   if (!ctx) return LRS_EINVAL;
   ctx->err.clear();
+  if (ctx->graph_pinned)
+    return fail(ctx, LRS_ESTATE, "captured graphs read this context's buffers; call "
+                "lrs_release_graphs once those graphs are gone");
   if (!ctx->have_bands) return fail(ctx, LRS_ESTATE, "lrs_set_orbitals must come first");
   if (kind != LRS_QUAD_TIME && kind != LRS_QUAD_FREQ) return fail(ctx, LRS_EINVAL, "unknown quadrature kind %d", kind);
   if (nnodes < 1 || nnodes > 64) return fail(ctx, LRS_EINVAL, "nnodes must be 1..64");
@@ -894,6 +916,36 @@ static lrs_status make_quadrature(lrs_ctx* ctx, int kind, int nnodes, double sca
   return LRS_OK;
 }
 
+lrs_status lrs_make_quadrature_tol(lrs_ctx* ctx, double tol, int nmin, int nmax, int* nnodes_host,
+                                   double* err_host) {
+  if (!ctx) return LRS_EINVAL;
+  ctx->err.clear();
+  if (!ctx->have_bands) return fail(ctx, LRS_ESTATE, "lrs_set_orbitals must come first");
+  if (!(tol > 0) || !std::isfinite(tol)) return fail(ctx, LRS_EINVAL, "tol must be finite and > 0");
+  if (nmin < 1 || nmax > 64 || nmin > nmax) return fail(ctx, LRS_EINVAL, "need 1 <= nmin <= nmax <= 64");
+  std::vector<double> x, y;
+  offsets(ctx, x, y);
+  const double dmin = *std::min_element(x.begin(), x.end()) + *std::min_element(y.begin(), y.end());
+  const double dmax = *std::max_element(x.begin(), x.end()) + *std::max_element(y.begin(), y.end());
+  if (!(dmin > 0)) return fail(ctx, LRS_ENOGAP, "smallest denominator is not positive");
+  // the smallest node count whose rule (at its own best scale) meets tol on every gap in
+  // [dmin, dmax]; the band-energy range alone decides it
+  int n = nmax;
+  double C = 0, e = 0;
+  for (int m = nmin; m <= nmax; ++m) {
+    C = time_auto_scale(dmin, dmax, m);
+    e = time_rule_error(C, m, dmin, dmax);
+    if (e <= tol) {
+      n = m;
+      break;
+    }
+  }
+  CHECK(make_quadrature(ctx, LRS_QUAD_TIME, n, C, 0.0));
+  if (nnodes_host) *nnodes_host = n;
+  if (err_host) *err_host = e;
+  return LRS_OK;
+}
+
 lrs_status lrs_get_quadrature(const lrs_ctx* ctx, int* nterms, double* c_host, double* tau_host,
                               double* mu_host, double* scale_host) {
   if (!ctx || !nterms) return LRS_EINVAL;
@@ -930,9 +982,23 @@ lrs_status lrs_compute_chi0(lrs_ctx* ctx, int site, int cols, int prec, double* 
   HIP_OR_FAIL(ctx, hipStreamIsCapturing(ctx->stream, &cs));
   ctx->capturing = cs != hipStreamCaptureStatusNone;
   if (ctx->capturing) ctx->timed = false;
-  const lrs_status st = run_chi0(ctx, site, cols, prec, pick_variant(ctx, prec), out, !ctx->capturing);
+  const lrs_status st = run_chi0(ctx, site, cols, prec, pick_variant(ctx, prec, cols), out, !ctx->capturing);
+  // a captured call bakes the context's buffers into the graph: keep them in place.  The site
+  // operand it recorded was not built yet, so the kept one describes nothing.
+  if (ctx->capturing) {
+    if (st == LRS_OK) ctx->graph_pinned = true;
+    ctx->a_prec = -1;
+  }
   ctx->capturing = false;
   return st;
+}
+
+lrs_status lrs_release_graphs(lrs_ctx* ctx) {
+  if (!ctx) return LRS_EINVAL;
+  ctx->err.clear();
+  ctx->graph_pinned = false;
+  ctx->a_prec = -1;        // replays may have rewritten the site operand
+  return LRS_OK;
 }
 
 double lrs_last_kernel_ms(lrs_ctx* ctx) {
@@ -943,6 +1009,15 @@ double lrs_last_kernel_ms(lrs_ctx* ctx) {
   return ms;
 }
 
+// The tuner times every compiled variant of precision prec on each column set of the current
+// problem (the cell grid if it was given, and the site blocks), on the site with the most
+// points (the shape class that dominates the launch): the site x grid launch over its first
+// two rounds of tiles of the real plan (XCD meeting included), the site block whole.  The score
+// is milliseconds per output entry actually covered, so tile shapes of different size and
+// raggedness compare fairly; each sample runs once to warm up and twice timed (the faster
+// counts).  The choice is kept per (precision, column set) for later lrs_compute_chi0 calls and
+// appended to the file named by LRS_TUNE_CACHE, keyed by precision, column set and problem
+// shape (rows of that site, columns, K, terms).
 lrs_status lrs_tune(lrs_ctx* ctx, int prec) {
   if (!ctx) return LRS_EINVAL;
   ctx->err.clear();
@@ -950,60 +1025,85 @@ lrs_status lrs_tune(lrs_ctx* ctx, int prec) {
     return fail(ctx, LRS_ESTATE, "orbitals, sites and quadrature must be set first");
   if (prec < LRS_FP64 || prec > LRS_FP16X2) return fail(ctx, LRS_EINVAL, "bad precision");
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
-  const int cols = ctx->ngrid > 0 ? LRS_COLS_GRID : LRS_COLS_SITE;
-  // problem key for the on-disk cache
-  std::ostringstream key;
-  key << "prec=" << prec << " rows=" << ctx->nrows << " cols=" << (cols == LRS_COLS_GRID ? ctx->ngrid : -1)
-      << " K=" << ctx->K_pad << " T=" << ctx->quad.nterms;
+  int s = 0;
+  for (int k = 1; k < ctx->nsites; ++k)
+    if (ctx->site_off[k + 1] - ctx->site_off[k] > ctx->site_off[s + 1] - ctx->site_off[s]) s = k;
+  const int nr = ctx->site_off[s + 1] - ctx->site_off[s];
   const char* path = std::getenv("LRS_TUNE_CACHE");
-  if (path) {
-    std::ifstream in(path);
-    std::string line;
-    while (std::getline(in, line)) {
-      size_t p = line.rfind(" variant=");
-      if (p != std::string::npos && line.substr(0, p) == key.str()) {
-        int v = std::atoi(line.c_str() + p + 9);
-        if (v >= 0 && v < chi0_num_variants(prec)) {
-          ctx->tuned_variant[prec] = v;
-          return LRS_OK;
+  for (int cols = LRS_COLS_GRID; cols <= LRS_COLS_SITE; ++cols) {
+    if (cols == LRS_COLS_GRID && ctx->ngrid <= 0) continue;
+    std::ostringstream key;
+    key << "prec=" << prec << " cols=" << cols << " rows=" << nr
+        << " ncols=" << (cols == LRS_COLS_GRID ? ctx->ngrid : nr) << " K=" << ctx->K_pad
+        << " T=" << ctx->quad.nterms << " iw=" << (ctx->quad.ci.empty() ? 0 : 1);
+    bool cached = false;
+    if (path) {
+      std::ifstream in(path);
+      std::string line;
+      while (std::getline(in, line)) {
+        const size_t p = line.rfind(" variant=");
+        if (p != std::string::npos && line.substr(0, p) == key.str()) {
+          const int v = std::atoi(line.c_str() + p + 9);
+          if (v >= 0 && v < chi0_num_variants(prec)) {
+            ctx->tuned_variant[prec][cols] = v;
+            cached = true;
+          }
         }
       }
     }
-  }
-  // time every variant on a bounded sample: the first tiles of the first batch of site 0
-  DevBuf out;
-  const int s = 0;
-  const int nr = ctx->site_off[1] - ctx->site_off[0];
-  const long long ncol = cols == LRS_COLS_GRID ? ctx->ngrid : nr;
-  CHECK(ensure_buf(ctx, out, (size_t)nr * ncol * 8, "tuning output"));
-  int best = 0;
-  float best_ms = 1e30f;
-  const int sample = 2 * ctx->num_cu * 2;
-  for (int v = 0; v < chi0_num_variants(prec); ++v) {
-    lrs_status st = run_chi0(ctx, s, cols, prec, v, (double*)out.p, false, sample);   // warm-up
-    if (st != LRS_OK) { release(ctx, out); return st; }
-    HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-    st = run_chi0(ctx, s, cols, prec, v, (double*)out.p, false, sample);
-    if (st != LRS_OK) { release(ctx, out); return st; }
-    HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev1, ctx->stream));
-    HIP_OR_FAIL(ctx, hipEventSynchronize(ctx->ev1));
-    float ms = 0;
-    HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-    // normalise by the tile area so that variants with different tile shapes compare fairly
-    TileShape sh = chi0_shape(prec, v);
-    ms /= (float)(sh.bm * sh.bn);
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = v;
+    if (cached) continue;
+    const long long ncol = cols == LRS_COLS_GRID ? ctx->ngrid : nr;
+    DevBuf out;
+    CHECK(ensure_buf(ctx, out, (size_t)nr * ncol * 8, "tuning output"));
+    int best = chi0_default_variant(prec);
+    double best_score = HUGE_VAL;
+    for (int v = 0; v < chi0_num_variants(prec); ++v) {
+      Plan* plan = nullptr;
+      const bool odd = !ctx->quad.ci.empty();
+      lrs_status st = get_plan(ctx, s, cols, prec, v, cols == LRS_COLS_SITE && odd ? 2 : 0, &plan);
+      if (st != LRS_OK) { release(ctx, out); return st; }
+      const Batch& b0 = plan->batches[0];
+      const int sample = cols == LRS_COLS_GRID ? std::min(b0.ntiles, 2 * b0.grid) : 0;
+      const long long area = sample > 0 ? plan->area[b0.tile0 + sample] - plan->area[b0.tile0]
+                                        : plan->area.back();
+      float ms = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+        st = run_chi0(ctx, s, cols, prec, v, (double*)out.p, false, sample);
+        if (st != LRS_OK) { release(ctx, out); return st; }
+        HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+        HIP_OR_FAIL(ctx, hipEventSynchronize(ctx->ev1));
+        float t = 0;
+        HIP_OR_FAIL(ctx, hipEventElapsedTime(&t, ctx->ev0, ctx->ev1));
+        if (rep > 0) ms = std::min(ms, t);
+      }
+      const double score = ms / (double)std::max<long long>(area, 1);
+      if (score < best_score) {
+        best_score = score;
+        best = v;
+      }
+    }
+    release(ctx, out);
+    ctx->tuned_variant[prec][cols] = best;
+    if (path) {
+      std::ofstream o(path, std::ios::app);
+      o << key.str() << " variant=" << best << "\n";
     }
   }
-  release(ctx, out);
   ctx->timed = false;
-  ctx->tuned_variant[prec] = best;
-  if (path) {
-    std::ofstream o(path, std::ios::app);
-    o << key.str() << " variant=" << best << "\n";
-  }
+  return LRS_OK;
+}
+
+lrs_status lrs_tuned_variant(const lrs_ctx* ctx, int prec, int cols, int* variant_host,
+                             int* tile_rows_host, int* tile_cols_host) {
+  if (!ctx || !variant_host) return LRS_EINVAL;
+  if (prec < LRS_FP64 || prec > LRS_FP16X2 || (cols != LRS_COLS_GRID && cols != LRS_COLS_SITE))
+    return LRS_EINVAL;
+  const int v = pick_variant(const_cast<lrs_ctx*>(ctx), prec, cols);
+  *variant_host = v;
+  const TileShape sh = chi0_shape(prec, v);
+  if (tile_rows_host) *tile_rows_host = sh.bm;
+  if (tile_cols_host) *tile_cols_host = sh.bn;
   return LRS_OK;
 }
 
@@ -1014,10 +1114,10 @@ lrs_status lrs_screen_W(lrs_ctx* ctx, const double* chi0_ss, double* W_out, cons
   if (!ctx->have_sites) return fail(ctx, LRS_ESTATE, "sites must be set first");
   if (!chi0_ss || !W_out) return fail(ctx, LRS_EINVAL, "chi0 and W_out are required");
   if (loss_out && !rho) return fail(ctx, LRS_EINVAL, "loss_out needs rho_test");
+  if (!screen_sizes_ok(ctx))
+    return fail(ctx, LRS_EUNSUPPORTED, "a site basis exceeds 288 functions or 256 directions");
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
   hipError_t e = launch_screen_forward(ctx, chi0_ss, W_out, rho, loss_out);
-  if (e == hipErrorInvalidValue)
-    return fail(ctx, LRS_EUNSUPPORTED, "a site basis exceeds 288 functions or 256 directions");
   if (e == hipErrorOutOfMemory) return fail(ctx, LRS_ENOMEM, "screening workspace");
   if (e != hipSuccess) return fail(ctx, LRS_EDEVICE, "screen_W: %s", hipGetErrorString(e));
   return LRS_OK;
@@ -1054,6 +1154,7 @@ lrs_status lrs_compute_chi0_backward(lrs_ctx* ctx, int cols, int prec, const dou
     return fail(ctx, LRS_ESTATE, "the backward pass copies host tables and synchronises; it "
                 "cannot be captured");
   hipError_t e = launch_chi0_backward(ctx, prec, dL_dchi0, dL_dE, (double*)dL_dpsi_site);
+  if (e == hipErrorIllegalState) return LRS_ESTATE;   // message set by the refused buffer
   if (e == hipErrorOutOfMemory) return fail(ctx, LRS_ENOMEM, "adjoint workspace");
   if (e != hipSuccess) return fail(ctx, LRS_EDEVICE, "chi0 backward: %s", hipGetErrorString(e));
   return LRS_OK;

@@ -83,6 +83,7 @@ struct Batch {            // a contiguous range of site row blocks and its tiles
 
 struct Plan {             // cached launch plan for (site, cols, prec, variant, mode)
   DevBuf tiles;
+  std::vector<long long> area;   // output entries covered by the first i tiles (prefix sums)
   int ntiles = 0;
   int variant = 0;
   std::vector<Batch> batches;
@@ -157,7 +158,8 @@ struct lrs_ctx {
 
   // plans
   std::map<long long, lrs::Plan> plans;
-  int tuned_variant[4] = {-1, -1, -1, -1};
+  // variant chosen by lrs_tune per (precision, column set); -1 = the default
+  int tuned_variant[4][2] = {{-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}};
 
   // screening state
   lrs::DevBuf W_last, rho_last, screen_tab, work, adj_work;
@@ -169,6 +171,9 @@ struct lrs_ctx {
   // set while a call runs on a stream that is being captured into a graph: nothing may
   // allocate, copy from the host or synchronise then
   bool capturing = false;
+  // set once a call has been captured: graphs then hold this context's buffer addresses, so
+  // calls that would free or replace those buffers are refused until lrs_release_graphs
+  bool graph_pinned = false;
 };
 
 namespace lrs {
@@ -233,6 +238,7 @@ lrs_status ensure_site_operand(lrs_ctx* ctx, int prec, const Batch& b, int t0, i
 lrs_status ensure_park(lrs_ctx* ctx, int prec, int variant, int grid);
 
 // screen.hip
+bool screen_sizes_ok(const lrs_ctx* ctx);
 hipError_t launch_screen_forward(lrs_ctx* ctx, const double* chi0_ss, double* W_out,
                                  const double* rho, double* loss_out);
 hipError_t launch_screen_backward(lrs_ctx* ctx, const double* dL_dW, double* dL_dchi0);

@@ -16,6 +16,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "lrs_internal.h"
@@ -799,6 +802,16 @@ static hipError_t launch_alda(lrs_ctx* ctx, const double* chi0_ss, const double*
   return hipGetLastError();
 }
 
+// Host-side check of the solve kernels' limits: n = (lmax+1)^2 n_rad <= 288 basis functions
+// (the Gauss-Jordan kernel's register slots) and at most 256 directions per site (the
+// projection's LDS table).
+bool screen_sizes_ok(const lrs_ctx* ctx) {
+  const int nL = (ctx->lmax + 1) * (ctx->lmax + 1);
+  for (int s = 0; s < ctx->nsites; ++s)
+    if (nL * ctx->nrad[s] > 288 || ctx->nang[s] > 256) return false;
+  return true;
+}
+
 }  // namespace lrs
 
 using namespace lrs;
@@ -825,11 +838,11 @@ extern "C" lrs_status lrs_screen_W_alda(lrs_ctx* ctx, const double* chi0_sitesit
     ctx->err = "the ALDA solve copies host tables; it cannot be captured";
     return LRS_ESTATE;
   }
-  const hipError_t e = launch_alda(ctx, chi0_sitesite, density, W_out);
-  if (e == hipErrorInvalidValue) {
+  if (!screen_sizes_ok(ctx)) {
     ctx->err = "a site basis exceeds 288 functions or 256 directions";
     return LRS_EUNSUPPORTED;
   }
+  const hipError_t e = launch_alda(ctx, chi0_sitesite, density, W_out);
   if (e == hipErrorOutOfMemory) {
     ctx->err = "ALDA workspace";
     return LRS_ENOMEM;
@@ -884,11 +897,11 @@ extern "C" lrs_status lrs_induced_potential(lrs_ctx* ctx, const double* chi0_sit
     ctx->err = "the induced-potential solve copies host tables; it cannot be captured";
     return LRS_ESTATE;
   }
-  const hipError_t e = launch_induced(ctx, chi0_sitesite, v1.data(), l0_only != 0, rho_out, v_out);
-  if (e == hipErrorInvalidValue) {
+  if (!screen_sizes_ok(ctx)) {
     ctx->err = "a site basis exceeds 288 functions or 256 directions";
     return LRS_EUNSUPPORTED;
   }
+  const hipError_t e = launch_induced(ctx, chi0_sitesite, v1.data(), l0_only != 0, rho_out, v_out);
   if (e == hipErrorOutOfMemory) {
     ctx->err = "induced-potential workspace";
     return LRS_ENOMEM;
@@ -899,3 +912,4 @@ extern "C" lrs_status lrs_induced_potential(lrs_ctx* ctx, const double* chi0_sit
   }
   return LRS_OK;
 }
+

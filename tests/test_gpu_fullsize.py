@@ -126,3 +126,42 @@ def test_grid_launch_imaginary_frequency(full):
         f"{eq:.2e}, vs exact {ex:.2e}")
     assert eq < 1e-4 and ex < 1e-4
 
+
+
+def test_gamma_grid_launch_sampled():
+    """The precision workload at Gamma (the other half of its "Gamma + 2x2x2 k" k-sets): the
+    site x grid launch in BF16X2 and FP64 against the oracle on sampled entries (same terms and
+    exact pair sum)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2005_07834_amd as P
+    from workloads import configs
+    say("precision workload at Gamma, with the grid")
+    w = configs.precision(device="cuda", gamma_only=True)
+    rng = np.random.default_rng(35)
+    rows = rng.integers(0, w.nrows, NS)
+    cols = rng.integers(0, w.ngrid ** 3, NS)
+    ps = w.psi_site[:, :, torch.as_tensor(rows, device="cuda")].cpu().numpy()
+    pg = w.psi_grid[:, :, torch.as_tensor(cols, device="cuda")].cpu().numpy()
+    ctx = P.Context(0)
+    ctx.set_orbitals(w.energies, w.nocc, w.psi_grid, w.grid_dV)
+    ctx.set_sites(w.sites, w.psi_site)
+    w.psi_grid = None
+    torch.cuda.empty_cache()
+    ctx.make_quadrature(P.QUAD_TIME, w.n_terms, 0.0)
+    mu = q.mid_gap(w.energies, w.nocc)
+    terms = cz.terms_for(w.energies, w.nocc, "time", w.n_terms, ctx.get_quadrature()["scale"], mu)
+    ref_q = cz.chi0_quad_entries(ps, pg, w.nocc, 2, *terms)
+    ref_x = cz.chi0_exact_entries(ps, pg, w.energies, w.nocc, mu=mu)
+    out = torch.empty((w.nrows, w.ngrid ** 3), dtype=torch.float64, device="cuda")
+    for prec, tq, tx in (("bf16x2", 1e-4, 1e-4), ("fp64", 1e-12, 1e-6)):
+        ctx.chi0(-1, P.COLS_GRID, prec, out=out)
+        got = out[torch.as_tensor(rows, device="cuda"), torch.as_tensor(cols, device="cuda")]
+        got = got.cpu().numpy()
+        eq, ex = rel(got, ref_q), rel(got, ref_x)
+        say(f"  Gamma grid {prec}: {ctx.last_kernel_ms():.0f} ms, vs same terms {eq:.2e}, "
+            f"vs exact {ex:.2e}")
+        assert eq < tq and ex < tx
+    ctx.close()
+    del out
+    torch.cuda.empty_cache()

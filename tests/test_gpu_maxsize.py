@@ -68,3 +68,50 @@ def test_batching_grid_launch_sampled():
     assert e < 1e-4
     ctx.close()
     del out
+
+
+def test_batching_fp32_grid_launch_sampled():
+    """The batching workload's FP32 variant on the site x grid launch: the largest, the
+    smallest and a ragged site (rows not a multiple of the 128-row tile) of the 64 uneven
+    sites, each over all 110,592 grid columns with 28 terms, sampled against the oracle with
+    the same terms (bar 1e-5)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import time
+
+    import paper_2005_07834_amd as P
+    from tests.conftest import workload
+    from workloads import crystal as cx
+    w = workload("batching", with_grid=False, device="cuda")
+    ncols = w.ngrid ** 3
+    sizes = [s.npts for s in w.sites]
+    pick = [int(np.argmax(sizes)), int(np.argmin(sizes))]
+    pick.append(next(k for k, n in enumerate(sizes) if n % 128 and k not in pick))
+    say(f"batching FP32 grid launch: sites {pick} ({[sizes[k] for k in pick]} rows)")
+    psi_grid = torch.stack([cx.psi_on_grid(w.bands, w.ngrid, k) for k in range(w.bands.nk)])
+    rng = np.random.default_rng(34)
+    offs = w.site_offsets
+    ctx = P.Context(0)
+    ctx.set_orbitals(w.energies, w.nocc, psi_grid, w.grid_dV)
+    ctx.set_sites(w.sites, w.psi_site)
+    ctx.make_quadrature(P.QUAD_TIME, w.n_terms, 0.0)
+    terms = cz.terms_for(w.energies, w.nocc, "time", w.n_terms, ctx.get_quadrature()["scale"])
+    worst = 0.0
+    for k in pick:
+        r = rng.integers(0, sizes[k], 8)
+        c = rng.integers(0, ncols, 8)
+        ps = w.psi_site[:, :, torch.as_tensor(offs[k] + r, device="cuda")].cpu().numpy()
+        pg = psi_grid[:, :, torch.as_tensor(c, device="cuda")].cpu().numpy()
+        ref = cz.chi0_quad_entries(ps, pg, w.nocc, 2, *terms)
+        t0 = time.time()
+        out = ctx.chi0(k, P.COLS_GRID, "fp32")
+        torch.cuda.synchronize()
+        got = out[torch.as_tensor(r, device="cuda"), torch.as_tensor(c, device="cuda")]
+        e = rel(got.cpu().numpy(), ref)
+        say(f"  site {k} ({sizes[k]} rows): {time.time() - t0:.1f} s, vs same terms {e:.2e}")
+        worst = max(worst, e)
+        del out
+    assert worst < 1e-5
+    ctx.close()
+    del psi_grid
+    torch.cuda.empty_cache()

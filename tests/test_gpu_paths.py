@@ -172,14 +172,30 @@ def test_differentiation_workload_fd_and_oracle(P):
     L1 = P.ScreenWFn.apply(chi, ctx1, rho[sl].contiguous())[1].sum()
     L1.backward()
     say("  oracle reference gradient for site 0 (CPU)")
-    L_ref, dE_ref, dpsi_ref = gr.loss_and_grads(w.psi_site.numpy()[:, :, sl], w.energies,
-                                                w.nocc, 2, w.sites[:1], w.rho_test[sl],
-                                                "time", n, s)
+    L_ref, dE_ref, dpsi_ref, W_ref = gr.loss_and_grads(w.psi_site.numpy()[:, :, sl], w.energies,
+                                                       w.nocc, 2, w.sites[:1], w.rho_test[sl],
+                                                       "time", n, s, with_W=True)
     eL = abs(L1.item() - L_ref) / abs(L_ref)
     eE = rel(E1.grad.numpy(), dE_ref)
     ep = rel(p1.grad.cpu().numpy(), dpsi_ref)
     say(f"  site 0 vs oracle: loss {eL:.2e} dE {eE:.2e} dpsi {ep:.2e}")
     assert eL < 1e-11 and eE < 1e-8 and ep < 1e-8
+    # W of site 0 from the split-precision chi0 and from the FP64 one, element by element
+    # against the oracle's W on the same terms
+    with torch.no_grad():
+        for prec, tol in (("bf16x2", 1e-4), ("fp64", 1e-10)):
+            ctx1.set_orbitals(w.energies, w.nocc)
+            ctx1.set_sites(w.sites[:1], p1.detach())
+            ctx1.make_quadrature(P.QUAD_TIME, n, s)
+            Wg, lg = ctx1.screen_W(ctx1.chi0(-1, P.COLS_SITE, prec), rho=rho[sl].contiguous(),
+                                   want_loss=True)
+            Wg = ctx1.W_blocks(Wg)[0].cpu().numpy()
+            eW = rel(Wg, W_ref[0])
+            eF = float(np.linalg.norm(Wg - W_ref[0]) / np.linalg.norm(W_ref[0]))
+            eLs = abs(lg.item() - L_ref) / abs(L_ref)
+            say(f"  site 0 W from {prec} chi0 vs oracle W: max {eW:.2e} frobenius {eF:.2e} "
+                f"loss {eLs:.2e}")
+            assert eW < tol and eLs < tol
 
 
 def test_split_adjoint_matches_fp64(P):
@@ -342,6 +358,64 @@ def test_graph_capture_replay(P):
     ctx.close()
 
 
+def test_captured_graph_pins_the_context(P):
+    """A captured chi0 call pins the context: calls that would free or replace the buffers the
+    graph reads (new terms, new sites, a larger operand) are refused with LRS_ESTATE, eager calls
+    that fit the existing buffers run, and replays stay bitwise equal to the eager result, also
+    after an eager call in another precision has overwritten the site operand (the graph
+    rebuilds it).  After lrs_release_graphs the context accepts new inputs again."""
+    w = workload("tiny")
+    n = w.n_terms
+    s = oracle_scale(w, n)
+    say("graph pinning, tiny")
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        ctx = make_ctx(P, w, n, s)
+        o64 = ctx.chi0(-1, P.COLS_SITE, "fp64")
+        ref = o64.clone()
+        obf = ctx.chi0(-1, P.COLS_SITE, "bf16x2")
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=st):
+        ctx.chi0(-1, P.COLS_SITE, "fp64", out=o64)
+    torch.cuda.synchronize()
+
+    def replay_equal():
+        o64.fill_(5.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        return torch.equal(o64, ref)
+
+    assert replay_equal()
+    for what, call in [("make_quadrature", lambda: ctx.make_quadrature(P.QUAD_TIME, n, s)),
+                       ("set_sites", lambda: ctx.set_sites(w.sites, w.psi_site)),
+                       ("set_orbitals", lambda: ctx.set_orbitals(w.energies, w.nocc))]:
+        with pytest.raises(P.LrsError) as e:
+            with torch.cuda.stream(st):
+                call()
+        assert e.value.status == P.LRS_ESTATE, what
+        say(f"  {what} refused while pinned")
+    with torch.cuda.stream(st):
+        again = ctx.chi0(-1, P.COLS_SITE, "bf16x2")      # fits: overwrites the site operand
+    torch.cuda.synchronize()
+    assert torch.equal(again, obf)
+    assert replay_equal()
+    say("  replay after an eager split call: equal")
+    # the replay rewrote the site operand with the FP64 one: an eager split call rebuilds its own
+    with torch.cuda.stream(st):
+        again = ctx.chi0(-1, P.COLS_SITE, "bf16x2")
+    torch.cuda.synchronize()
+    assert torch.equal(again, obf)
+    ctx.release_graphs()
+    del g
+    with torch.cuda.stream(st):
+        ctx.make_quadrature(P.QUAD_TIME, n, s)
+        assert torch.equal(ctx.chi0(-1, P.COLS_SITE, "fp64"), ref)
+    torch.cuda.synchronize()
+    ctx.close()
+
+
 def test_capture_without_warmup_is_refused(P):
     """Capturing a call whose plan is not built yet returns LRS_ESTATE (nothing is allocated
     or launched under capture); so does capturing the backward pass, which copies host tables
@@ -373,24 +447,48 @@ def test_capture_without_warmup_is_refused(P):
     ctx.close()
 
 
-def test_tune_and_determinism(P):
-    """The autotuner's choice gives the default variant's result; repeated calls are
-    bitwise identical."""
+def test_tune_and_determinism(P, tmp_path):
+    """The autotuner picks a variant per (precision, column set); the tuned calls agree with the
+    default variant's, repeated calls are bitwise identical, and a second context reads the
+    choices back from the cache file."""
     w = workload("production")
     n = w.n_terms
     s = oracle_scale(w, n)
     say("tune + determinism, production")
-    ctx = make_ctx(P, w, n, s)
-    for prec in ["bf16x2", "fp64"]:
-        a = ctx.chi0(-1, P.COLS_GRID, prec)
-        b = ctx.chi0(-1, P.COLS_GRID, prec)
-        assert torch.equal(a, b)
-        ctx.tune(prec)
-        c = ctx.chi0(-1, P.COLS_GRID, prec)
-        d = (c - a).abs().max().item() / a.abs().max().item()
-        say(f"  {prec}: repeat equal, tuned vs default rel diff {d:.2e}")
-        assert d < (1e-6 if prec == "bf16x2" else 1e-13)
-    ctx.close()
+    cache = tmp_path / "tune.txt"
+    os.environ["LRS_TUNE_CACHE"] = str(cache)
+    try:
+        ctx = make_ctx(P, w, n, s)
+        chosen = {}
+        for prec in ["bf16x2", "fp64"]:
+            a = ctx.chi0(-1, P.COLS_GRID, prec)
+            b = ctx.chi0(-1, P.COLS_GRID, prec)
+            assert torch.equal(a, b)
+            sa = ctx.chi0(-1, P.COLS_SITE, prec)
+            ctx.tune(prec)
+            for cols in (P.COLS_GRID, P.COLS_SITE):
+                chosen[(prec, cols)] = ctx.tuned_variant(prec, cols)
+            c = ctx.chi0(-1, P.COLS_GRID, prec)
+            sc = ctx.chi0(-1, P.COLS_SITE, prec)
+            d = (c - a).abs().max().item() / a.abs().max().item()
+            ds = (sc - sa).abs().max().item() / sa.abs().max().item()
+            say(f"  {prec}: tuned grid {chosen[(prec, P.COLS_GRID)]} site "
+                f"{chosen[(prec, P.COLS_SITE)]}; vs default {d:.2e} / {ds:.2e}")
+            tol = 1e-6 if prec == "bf16x2" else 1e-13
+            assert d < tol and ds < tol
+            assert torch.equal(c, ctx.chi0(-1, P.COLS_GRID, prec))
+        ctx.close()
+        lines = cache.read_text().splitlines()
+        assert len(lines) == 4 and all(" variant=" in x for x in lines)
+        ctx2 = make_ctx(P, w, n, s)
+        for prec in ["bf16x2", "fp64"]:
+            ctx2.tune(prec)                          # from the cache file, nothing timed
+            for cols in (P.COLS_GRID, P.COLS_SITE):
+                assert ctx2.tuned_variant(prec, cols) == chosen[(prec, cols)]
+        assert len(cache.read_text().splitlines()) == 4
+        ctx2.close()
+    finally:
+        os.environ.pop("LRS_TUNE_CACHE", None)
 
 
 def test_single_site_calls_match_all_sites(P):

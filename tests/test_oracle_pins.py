@@ -103,6 +103,28 @@ def _brute_chi0(psi_r, psi_c, E, nocc, spin):
     return out
 
 
+def test_node_count_picked_from_the_energy_range(tiny):
+    """auto_nodes: the chosen rule meets the bound and one node fewer does not (on the same
+    error model), and the bound holds for every actual band pair of the tiny workload, whose
+    kernel is summed term by term against the exact 1/(x + y)."""
+    w = tiny
+    mu = q.mid_gap(w.energies, w.nocc)
+    x, y = q.offsets(w.energies, w.nocc, mu)
+    dmin, dmax = x.min() + y.min(), x.max() + y.max()
+    for tol in (1e-6, 1e-9, 1e-11):
+        n, s, e = q.auto_nodes(x, y, tol, 12, 32)
+        assert e <= tol
+        if n > 12:
+            assert q.imag_time_error(q.auto_scale(x, y, n - 1), n - 1, dmin, dmax) > tol
+        c, al, be, _ = q.imag_time_terms(x, y, n, s)
+        K = q.kernel(c, al, be, 0, 0)
+        pair = np.abs(K * (x[0][:, None] + y[0][None, :]) - 1.0).max()
+        assert pair <= 1.05 * e
+    # a band-energy range that no count in range meets: the largest count
+    n, s, e = q.auto_nodes(x, y, 1e-30, 20, 24)
+    assert n == 24 and e > 1e-30
+
+
 def test_pair_sum_matches_brute_force_loops():
     rng = np.random.default_rng(7)
     nk, nb, nocc, nr, nc = 2, 6, 2, 3, 4
