@@ -239,6 +239,19 @@ lrs_status lrs_release_graphs(lrs_ctx* ctx);
 lrs_status lrs_screen_W(lrs_ctx* ctx, const double* chi0_sitesite, double* W_out,
                         const double* rho_test, double* loss_out);
 
+/* lrs_screen_W for callers that cannot allocate device memory (code under graph capture
+ * elsewhere in the process, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and results (W_out, and loss_out when rho_test is given), with the solve's tables and
+ * workspace in a fixed device array of 64 MiB that each GPU holds until the process ends, so the
+ * call allocates and frees nothing.  The caller passes inputs and outputs as for lrs_screen_W.
+ * LRS_ENOMEM when the sites need more scratch than the array holds (3 n^2 + n doubles per site
+ * plus the tables, so up to about 100 sites of 288 basis functions), LRS_EUNSUPPORTED beyond
+ * the solve's limits as lrs_screen_W.  It keeps no state for lrs_screen_W_backward.  It copies
+ * host tables into the array and synchronises the stream: LRS_ESTATE under stream capture.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's contents: calls
+ * that overlap on one GPU (other streams, other contexts, other threads) race. */
+lrs_status lrs_screen_W_noalloc(lrs_ctx* ctx, const double* chi0_sitesite, double* W_out,
+                                const double* rho_test, double* loss_out);
 
 /* Induced density and potential of a spherical perturbation at every site (Sec. VI,
  * construction of chi and W; the perturbation is the short-range part of a potential split by

@@ -44,6 +44,7 @@ SIGNATURES = [
     ("lrs_compute_chi0", _I, [_P, _I, _I, _I, _P]),
     ("lrs_screen_W", _I, [_P, _P, _P, _P, _P]),
     ("lrs_screen_W_backward", _I, [_P, _P, _P]),
+    ("lrs_screen_W_noalloc", _I, [_P, _P, _P, _P, _P]),
     ("lrs_compute_chi0_backward", _I, [_P, _I, _I, _P, _P, _P, _P]),
     ("lrs_tune", _I, [_P, _I]),
     ("lrs_tuned_variant", _I, [_P, _I, _I, _P, _P, _P]),
@@ -234,6 +235,17 @@ class Context:
         self.screen_version += 1
         self._check(lib.lrs_screen_W(self.h, _ptr(chi0_ss.contiguous()), _ptr(W), _ptr(r),
                                      _ptr(loss)))
+        return W, loss
+
+    def screen_W_noalloc(self, chi0_ss, rho=None, want_loss=False, out=None):
+        """lrs_screen_W_noalloc: W (and the loss) with the library's fixed scratch array; `out`
+        (float64 [sum n^2] on this device) may be given so that nothing is allocated here."""
+        W = out if out is not None else torch.empty(sum(n * n for n in self.nbasis),
+                                                    dtype=torch.float64, device=self.device)
+        r = None if rho is None else _dev(rho, torch.float64, self.device)
+        loss = torch.empty(self.nsites, dtype=torch.float64, device=self.device) if want_loss else None
+        self._check(lib.lrs_screen_W_noalloc(self.h, _ptr(chi0_ss.contiguous()), _ptr(W), _ptr(r),
+                                             _ptr(loss)))
         return W, loss
 
     def W_blocks(self, flat):

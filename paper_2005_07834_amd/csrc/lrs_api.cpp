@@ -562,6 +562,11 @@ lrs_status lrs_create(lrs_ctx** out, int device, void* hip_stream) {
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) return LRS_EDEVICE;
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return LRS_EDEVICE;
   if (hipSetDevice(device) != hipSuccess) return LRS_EDEVICE;
+  // the allocation-free solve's fixed scratch array: its address on this device, once
+  if (scratch_setup(device) != hipSuccess) {
+    (void)hipGetLastError();
+    return LRS_EDEVICE;
+  }
   lrs_ctx* ctx = new lrs_ctx();
   ctx->device = device;
   ctx->stream = (hipStream_t)hip_stream;

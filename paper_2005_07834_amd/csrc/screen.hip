@@ -913,3 +913,161 @@ extern "C" lrs_status lrs_induced_potential(lrs_ctx* ctx, const double* chi0_sit
   return LRS_OK;
 }
 
+// ------------------------------------------------------------------ allocation-free W solve
+// lrs_screen_W_noalloc runs the kernels of lrs_screen_W with its tables and workspace in this
+// fixed device array instead of context buffers.  Every GPU the library runs on holds its own
+// copy until the process ends.  Host code must never pass the array's name to a kernel or a
+// copy (in host code it is a stand-in, not a device address): it uses the address that
+// hipGetSymbolAddress returned for the current device, kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[lrs::kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+namespace lrs {
+
+// Looks up the scratch array's address on `device` (which must be current); once per device.
+hipError_t scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = p;
+  return hipSuccess;
+}
+
+namespace {
+
+// Scratch layout of one call: meta | radii | u | yw | blocks | rows | w_out_off, then
+// X [w_total] | M [2 w_total] | h [n_total] (the workspace of lrs_screen_W).  Returns the bytes
+// needed; with base != null also fills D and the workspace pointers.
+size_t noalloc_layout(const HostTabs& H, unsigned char* base, DevTabs* D, double** X,
+                      double** M, double** h, size_t* offs) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  offs[0] = take(H.meta.size() * sizeof(SiteMeta));
+  offs[1] = take(H.radii.size() * 8);
+  offs[2] = take(H.u.size() * 8);
+  offs[3] = take(H.yw.size() * 8);
+  offs[4] = take(H.blocks.size() * sizeof(int4));
+  offs[5] = take(H.rows.size() * sizeof(int2));
+  offs[6] = take(H.w_out_off.size() * 8);
+  const size_t o_x = take((size_t)H.w_total * 8);
+  const size_t o_m = take((size_t)2 * H.w_total * 8);
+  const size_t o_h = take((size_t)H.n_total * 8);
+  if (base) {
+    D->t.meta = (const SiteMeta*)(base + offs[0]);
+    D->t.radii = (const double*)(base + offs[1]);
+    D->t.u = (const double*)(base + offs[2]);
+    D->t.yw = (const double*)(base + offs[3]);
+    D->blocks = (const int4*)(base + offs[4]);
+    D->rows = (const int2*)(base + offs[5]);
+    D->w_out_off = (const long long*)(base + offs[6]);
+    D->nblocks = (int)H.blocks.size();
+    D->nrows = (int)H.rows.size();
+    *X = (double*)(base + o_x);
+    *M = (double*)(base + o_m);
+    *h = (double*)(base + o_h);
+  }
+  return off;
+}
+
+}  // namespace
+}  // namespace lrs
+
+extern "C" lrs_status lrs_screen_W_noalloc(lrs_ctx* ctx, const double* chi0_sitesite,
+                                           double* W_out, const double* rho_test,
+                                           double* loss_out) {
+  if (!ctx) return LRS_EINVAL;
+  ctx->err.clear();
+  if (!ctx->have_sites) {
+    ctx->err = "sites must be set first";
+    return LRS_ESTATE;
+  }
+  if (!chi0_sitesite || !W_out) {
+    ctx->err = "chi0 and W_out are required";
+    return LRS_EINVAL;
+  }
+  if (loss_out && !rho_test) {
+    ctx->err = "loss_out needs rho_test";
+    return LRS_EINVAL;
+  }
+  if (!screen_sizes_ok(ctx)) {
+    ctx->err = "a site basis exceeds 288 functions or 256 directions";
+    return LRS_EUNSUPPORTED;
+  }
+  HostTabs H;
+  build_tabs(ctx, H);
+  size_t offs[7];
+  const size_t need = noalloc_layout(H, nullptr, nullptr, nullptr, nullptr, nullptr, offs);
+  if (need > kScratchBytes) {
+    char buf[160];
+    snprintf(buf, sizeof(buf), "the solve needs %zu bytes of scratch; the fixed array holds %zu",
+             need, kScratchBytes);
+    ctx->err = buf;
+    return LRS_ENOMEM;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipSetDevice(ctx->device) != hipSuccess ||
+      hipStreamIsCapturing(ctx->stream, &cs) != hipSuccess) {
+    ctx->err = "device";
+    return LRS_EDEVICE;
+  }
+  if (cs != hipStreamCaptureStatusNone) {
+    ctx->err = "the solve copies host tables into its scratch; it cannot be captured";
+    return LRS_ESTATE;
+  }
+  unsigned char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (ctx->device >= 0 && ctx->device < kMaxDevices)
+      base = (unsigned char*)g_scratch_ptr[ctx->device];
+  }
+  if (!base) {
+    ctx->err = "the scratch array's address on this device was not set up";
+    return LRS_EDEVICE;
+  }
+  DevTabs D;
+  double *X = nullptr, *M = nullptr, *h = nullptr;
+  noalloc_layout(H, base, &D, &X, &M, &h, offs);
+  hipStream_t st = ctx->stream;
+  hipError_t e = hipSuccess;
+  auto put = [&](size_t o, const void* src, size_t bytes) {
+    if (e == hipSuccess && bytes) e = hipMemcpyAsync(base + o, src, bytes, hipMemcpyHostToDevice, st);
+  };
+  put(offs[0], H.meta.data(), H.meta.size() * sizeof(SiteMeta));
+  put(offs[1], H.radii.data(), H.radii.size() * 8);
+  put(offs[2], H.u.data(), H.u.size() * 8);
+  put(offs[3], H.yw.data(), H.yw.size() * 8);
+  put(offs[4], H.blocks.data(), H.blocks.size() * sizeof(int4));
+  put(offs[5], H.rows.data(), H.rows.size() * sizeof(int2));
+  put(offs[6], H.w_out_off.data(), H.w_out_off.size() * 8);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);   // the host tables die on return
+  if (e == hipSuccess) {
+    // X, M and h are written in full by the kernels before they are read: nothing to clear
+    hipLaunchKernelGGL(project_kernel, dim3(D.nblocks), dim3(256), 0, st, D.t, D.blocks,
+                       chi0_sitesite, X);
+    hipLaunchKernelGGL(eps_kernel, dim3(D.nrows), dim3(256), 0, st, D.t, D.rows, X, M);
+    hipLaunchKernelGGL(gauss_jordan_kernel, dim3(ctx->nsites), dim3(1024), 0, st, D.t, M, 0,
+                       W_out, D.w_out_off);
+    if (rho_test)
+      hipLaunchKernelGGL(charge_kernel, dim3(ctx->nsites), dim3(256), 0, st, D.t, rho_test,
+                         W_out, D.w_out_off, h, loss_out);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) {
+    ctx->err = std::string("screen_W_noalloc: ") + hipGetErrorString(e);
+    return LRS_EDEVICE;
+  }
+  return LRS_OK;
+}
