@@ -1,19 +1,21 @@
 """Benchmark of the screening hot path on one MI355X.
 
-One step = one pass of the hot path over one synthetic input:
+One step = one pass of the hot path over one synthetic input (the precision workload, 2x2x2 k):
   quadrature terms (host) -> chi0 site x grid (the headline) -> chi0 site x site ->
   W solve with a test-charge loss -> adjoint of the solve -> adjoint of chi0 (split
   products when chi0 runs split, else FP64).
 Inputs (orbitals on the grid and at the site points, packed into the library's layouts)
-are resident in HBM before the timed region.
+are resident in HBM before the timed region.  The autotuner picks the chi0 variant first.
 
-Prints one JSON line.  `value` = chi0 (site x grid) entries per second of step time.
-The FP64 path is timed once beside it (speedup), sampled entries of both are compared
-with the CPU oracle, and the oracle itself is timed on the host (cpu_baseline).  After the
-steps, once each: the FP16 split launch, the FP64 adjoint (against the split one), the
-per-site solves beside W (ALDA W, induced potential), chi0 at imaginary frequency on the
-same launch (sampled entries against the oracle) and the projection of the plane-wave
-orbitals onto the site points.
+Prints one JSON line.  `value` = chi0 (site x grid) entries per second of step time in the
+bench precision (default F16F8: fp16 hi products with fp8 cross terms; --prec bf16x2 for the
+split-BF16 path).  After the steps, once each: the same launch in every other precision (FP64
+for the speedup; the split BF16 and FP16 paths; FP32), W from the step's site blocks against W
+from the FP64 ones, the FP64 adjoint against the split one, the per-site solves beside W (ALDA
+W, induced potential), chi0 at imaginary frequency, the projection of the plane-wave orbitals
+onto the site points, and the batching workload's site x grid call (64 uneven sites).  Sampled
+entries of every path are compared with the CPU oracle; the oracle's exact pair sum is timed on
+the host (cpu_baseline), beside the same factorised algorithm in NumPy (cpu_factorised).
 """
 from __future__ import annotations
 
@@ -30,8 +32,55 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAKS_TFLOPS = {"bf16x2": 2500.0, "fp16x2": 2500.0, "fp32": 157.3, "fp64": 78.6}
-DTYPE = {"bf16x2": "bf16", "fp16x2": "f16", "fp32": "f32", "fp64": "f64"}
+PEAKS_TFLOPS = {"bf16x2": 2500.0, "fp16x2": 2500.0, "f16f8": 2500.0, "fp32": 157.3, "fp64": 78.6}
+DTYPE = {"bf16x2": "bf16", "fp16x2": "f16", "f16f8": "f16+f8", "fp32": "f32", "fp64": "f64"}
+# matrix-core time per algorithmic product, in units of one product at the 2.5 PF/s dense
+# 16-bit rate: the split paths run hi*hi + hi*lo + lo*hi (3); F16F8 runs hi*hi on fp16 (1) and
+# both cross terms on one fp8 instruction of twice the K at twice the rate (1)
+EXEC_FACTOR = {"bf16x2": 3.0, "fp16x2": 3.0, "f16f8": 2.0, "fp32": 1.0, "fp64": 1.0}
+SPLIT = ("bf16x2", "fp16x2", "f16f8")
+
+
+def host_info():
+    """CPU model, logical CPUs and the BLAS NumPy calls (after a BLAS call has loaded it)."""
+    import platform
+    model = platform.processor()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = None
+    try:
+        import threadpoolctl
+        info = [i for i in threadpoolctl.threadpool_info() if i.get("user_api") == "blas"]
+        if info:
+            blas = {"library": info[0].get("internal_api"), "version": info[0].get("version"),
+                    "threads": info[0].get("num_threads")}
+    except Exception:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "blas": blas}
+
+
+def cpu_factorised(ps_rows, pg_cols, nocc, c, alpha, beta, spin=2):
+    """chi0 on a block of rows x columns by the same factorised imaginary-time algorithm as the
+    GPU path, in NumPy (one complex GEMM per Green's function and term): G_o^l = sum over
+    occupied (k, n) of conj(psi(r)) alpha_l psi(r'), G_u^l likewise, and
+    chi0 = -(2 s / N_k^2) sum_l c_l Re[G_o^l conj(G_u^l)].  A CPU baseline, not the oracle."""
+    nk = ps_rows.shape[0]
+    a_o = np.conj(ps_rows[:, :nocc]).reshape(-1, ps_rows.shape[2])     # [K_o, rows]
+    a_u = np.conj(ps_rows[:, nocc:]).reshape(-1, ps_rows.shape[2])
+    b_o = pg_cols[:, :nocc].reshape(-1, pg_cols.shape[2])               # [K_o, cols]
+    b_u = pg_cols[:, nocc:].reshape(-1, pg_cols.shape[2])
+    out = np.zeros((ps_rows.shape[2], pg_cols.shape[2]))
+    for l in range(len(c)):
+        go = (a_o * alpha[l].reshape(-1, 1)).T @ b_o
+        gu = (a_u * beta[l].reshape(-1, 1)).T @ b_u
+        out += c[l] * (go.real * gu.real + go.imag * gu.imag)
+    return -2.0 * spin / nk ** 2 * out
 
 
 def log(*a):
@@ -85,16 +134,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="precision", choices=["precision", "production", "tiny"])
     ap.add_argument("--gamma", action="store_true", help="Gamma-only k-set (precision workload)")
-    ap.add_argument("--prec", default="bf16x2", choices=list(PEAKS_TFLOPS))
+    ap.add_argument("--prec", default="f16f8", choices=list(PEAKS_TFLOPS))
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-fp16", action="store_true",
                     help="skip the one FP16X2 launch run beside a BF16X2 bench")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-projection", action="store_true",
                     help="skip the plane-wave -> site-point projection timed after the steps")
+    ap.add_argument("--no-batching", action="store_true",
+                    help="skip the batching workload's site x grid launch timed at the end")
+    ap.add_argument("--no-tune", action="store_true", help="use the default chi0 variant")
     ap.add_argument("--adjoint-prec", default="auto", choices=["auto", "fp64", "bf16x2"],
-                    help="precision of the adjoint's products (auto: bf16x2 with --prec bf16x2, "
-                         "else fp64)")
+                    help="precision of the adjoint's products (auto: bf16x2 with a split "
+                         "--prec, else fp64)")
     ap.add_argument("--omega", type=float, default=0.1,
                     help="imaginary frequency (Ha) of the chi0(i omega) launch run after the steps")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -149,6 +201,10 @@ def main():
         bcol = rng.integers(0, ncols, size=bc)
         cpu_block = (w.psi_site[:, :, torch.as_tensor(brow, device=dev)].cpu().numpy(),
                      w.psi_grid[:, :, torch.as_tensor(bcol, device=dev)].cpu().numpy())
+        fcol = rng.integers(0, ncols, size=min(ncols, 4096))
+        fact_cols = w.psi_grid[:, :, torch.as_tensor(fcol, device=dev)].cpu().numpy()
+        frow = rng.integers(0, nrows, size=min(nrows, 128))
+        fact_rows = w.psi_site[:, :, torch.as_tensor(frow, device=dev)].cpu().numpy()
         log(f"oracle ~{per * 1e3:.3f} ms/entry; baseline block {br} x {bc}")
 
     ctx = P.Context(0)
@@ -164,9 +220,20 @@ def main():
     prec = args.prec
     adj_prec = args.adjoint_prec
     if adj_prec == "auto":
-        adj_prec = "bf16x2" if prec == "bf16x2" else "fp64"
+        adj_prec = "bf16x2" if prec in SPLIT else "fp64"
+    # the autotuner's choice for this problem (both column sets), before the timed steps
+    ctx.make_quadrature(P.QUAD_TIME, w.n_terms, 0.0)
+    tq = time.time()
+    if not args.no_tune:
+        ctx.tune(prec)
+    tuned = {"tune_s": time.time() - tq}
+    for name, cset in (("grid", P.COLS_GRID), ("site", P.COLS_SITE)):
+        v, bm, bn = ctx.tuned_variant(prec, cset)
+        tuned[name] = {"variant": v, "tile": [bm, bn]}
+    log("tuned", tuned)
 
     comp = {}
+    W_step = {}
 
     def step(record):
         tq = time.time()
@@ -182,6 +249,7 @@ def main():
             comp.setdefault("kernel_ms", []).append(kms)
             comp.setdefault("step_ms", []).append((time.time() - tq) * 1e3)
             comp["adjoint"] = (lam, dE, dpsi)
+            W_step["W"] = W
         return loss
 
     for _ in range(args.warmup):
@@ -200,27 +268,36 @@ def main():
     log(f"step {ms_per_step:.1f} ms; chi0 kernel ({prec}) {kern_ms:.1f} ms")
     qd = ctx.get_quadrature()      # the static rule of the timed steps
 
-    # FP64 path once, for the speedup and the error statement
-    fp64 = {}
-    if not args.no_fp64 and prec != "fp64":
+    # every other precision once on the same launch: FP64 (the speedup and the error
+    # statement), the split BF16 and FP16 paths, FP32
+    paths, got_p = {}, {}
+    others = [x for x in ("fp64", "bf16x2", "fp16x2", "f16f8", "fp32") if x != prec]
+    if args.no_fp64:
+        others.remove("fp64")
+    if args.no_fp16 and "fp16x2" in others:
+        others.remove("fp16x2")
+    for p in others:
         ctx.make_quadrature(P.QUAD_TIME, w.n_terms, 0.0)
-        ctx.chi0(-1, P.COLS_GRID, "fp64", out=out_grid)
-        ms64 = ctx.last_kernel_ms()
-        got64 = out_grid[torch.as_tensor(rows, device=dev), torch.as_tensor(cols, device=dev)].cpu().numpy()
-        fp64 = dict(kernel_ms=ms64, entries_per_s=entries / (ms64 / 1e3))
-        log(f"fp64 chi0 kernel {ms64:.1f} ms")
-    else:
-        got64 = got_low if prec == "fp64" else None
-    # the FP16 split variant once on the same launch, for comparison with BF16
-    fp16 = {}
-    got16 = None
-    if prec == "bf16x2" and not args.no_fp16:
+        ctx.chi0(-1, P.COLS_GRID, p, out=out_grid)
+        ms = ctx.last_kernel_ms()
+        got_p[p] = out_grid[torch.as_tensor(rows, device=dev),
+                            torch.as_tensor(cols, device=dev)].cpu().numpy()
+        paths[p] = dict(kernel_ms=ms, entries_per_s=entries / (ms / 1e3),
+                        vs_headline=ms / kern_ms)
+        log(f"{p} chi0 kernel {ms:.1f} ms")
+    got64 = got_low if prec == "fp64" else got_p.get("fp64")
+    # W from this precision's site blocks (the last step's) against W from the FP64 blocks:
+    # transitive parity, the FP64 path being pinned to the oracle at the smaller workloads
+    w_err = None
+    if prec != "fp64" and not args.no_fp64:
         ctx.make_quadrature(P.QUAD_TIME, w.n_terms, 0.0)
-        ctx.chi0(-1, P.COLS_GRID, "fp16x2", out=out_grid)
-        ms16 = ctx.last_kernel_ms()
-        got16 = out_grid[torch.as_tensor(rows, device=dev), torch.as_tensor(cols, device=dev)].cpu().numpy()
-        fp16 = dict(kernel_ms=ms16, entries_per_s=entries / (ms16 / 1e3))
-        log(f"fp16x2 chi0 kernel {ms16:.1f} ms")
+        W64, _ = ctx.screen_W(ctx.chi0(-1, P.COLS_SITE, "fp64"))
+        Wp = W_step["W"]
+        w_err = {"precision": prec, "vs": "W from the FP64 GPU site blocks (transitive)",
+                 "max_rel": float((Wp - W64).abs().max() / W64.abs().max()),
+                 "frobenius_rel": float(torch.linalg.norm(Wp - W64) / torch.linalg.norm(W64))}
+        log("W", w_err)
+        del W64
     # the split adjoint against the FP64 adjoint on the last step's dL/dchi0
     adjoint = {"precision": adj_prec}
     if adj_prec != "fp64" and not args.no_fp64:
@@ -308,15 +385,18 @@ def main():
     flop_per_entry = w.n_terms * (8.0 * K + 4.0)
     achieved = entries * flop_per_entry / (kern_ms / 1e3) / 1e12
     peak = PEAKS_TFLOPS[prec]
-    exec_factor = 3.0 if prec in ("bf16x2", "fp16x2") else 1.0
+    exec_factor = EXEC_FACTOR[prec]
     ctr = counters_for(w.name + ("_gamma" if args.gamma else ""), prec)
     traffic = ctr.get("hbm_bytes_per_launch") if ctr else None
 
     # oracle: timed exact pair sum on the baseline block (cpu_baseline), and the sampled
     # entries of the GPU results against the exact sum and against the same quadrature
     from oracle import quadrature as q
-    cpu = None
+    cpu, cpu_fact = None, None
     errs = {}
+
+    def rel(a, b):
+        return float(np.abs(a - b).max() / np.abs(b).max())
     if not args.no_cpu:
         import threadpoolctl
         info = threadpoolctl.threadpool_info()
@@ -327,22 +407,31 @@ def main():
         cpu = {"value": blk.size / tcpu, "unit": "chi0 entries/s", "cores": int(threads),
                "kind": "oracle",
                "sample": f"{blk.shape[0]} site rows x {blk.shape[1]} grid columns (seeded) of "
-                         f"the same workload, exact band-pair sum, {tcpu:.1f} s"}
-        ex = cz.chi0_exact_entries(ps_s, pg_s, w.energies, w.nocc)
+                         f"the same workload, exact band-pair sum, {tcpu:.1f} s",
+               "host": host_info()}
         mu = q.mid_gap(w.energies, w.nocc)
         terms = cz.terms_for(w.energies, w.nocc, "time", w.n_terms, qd["scale"], mu)
+        # the same factorised algorithm as the GPU path in NumPy on the host (context, not the
+        # oracle): calibrated on 64 columns, then a block sized for about --cpu-seconds / 2
+        tc = time.time()
+        cpu_factorised(fact_rows, fact_cols[:, :, :256], w.nocc, *terms)
+        per_col = (time.time() - tc) / 256
+        mcol = int(max(256, min(fact_cols.shape[2], 0.5 * args.cpu_seconds / max(per_col, 1e-9))))
+        tc = time.time()
+        fb = cpu_factorised(fact_rows, fact_cols[:, :, :mcol], w.nocc, *terms)
+        tf = time.time() - tc
+        cpu_fact = {"value": fb.size / tf, "unit": "chi0 entries/s", "cores": int(threads),
+                    "kind": "factorised imaginary-time algorithm (NumPy complex GEMM per term)",
+                    "sample": f"{fb.shape[0]} site rows x {fb.shape[1]} grid columns (seeded) of "
+                              f"the same workload, {w.n_terms} terms, {tf:.1f} s"}
+        ex = cz.chi0_exact_entries(ps_s, pg_s, w.energies, w.nocc)
         qq = cz.chi0_quad_entries(ps_s, pg_s, w.nocc, 2, *terms)
-
-        def rel(a, b):
-            return float(np.abs(a - b).max() / np.abs(b).max())
         errs[f"{prec}_vs_exact"] = rel(got_low, ex)
         errs[f"{prec}_vs_same_quadrature"] = rel(got_low, qq)
         errs[f"{prec}_vs_exact_frobenius"] = float(np.linalg.norm(got_low - ex) / np.linalg.norm(ex))
-        if got64 is not None:
-            errs["fp64_vs_exact"] = rel(got64, ex)
-            errs["fp64_vs_same_quadrature"] = rel(got64, qq)
-        if got16 is not None:
-            errs["fp16x2_vs_exact"] = rel(got16, ex)
+        for p, g in got_p.items():
+            errs[f"{p}_vs_exact"] = rel(g, ex)
+            errs[f"{p}_vs_same_quadrature"] = rel(g, qq)
         errs["quadrature_vs_exact"] = rel(qq, ex)
         errs["entries_compared"] = int(ns)
         log("errors", errs)
@@ -355,6 +444,61 @@ def main():
         iw["entries_compared"] = int(ns)
         log("chi0(i omega)", iw)
 
+    # the batching workload (64 uneven sites, 87,960 rows x 110,592 columns): its site x grid
+    # chi0 in one call (persistent launches over operand batches), node count picked from the
+    # band-energy range, three sampled entries per site against the oracle
+    batching = None
+    if not args.no_batching and args.workload == "precision" and not args.gamma:
+        tb = time.time()
+        wb = configs.batching(device=dev)
+        nrb, ncb = wb.nrows, wb.ngrid ** 3
+        offs = wb.site_offsets
+        brows = np.array([offs[k] + rng.integers(0, st.npts) for k, st in enumerate(wb.sites)
+                          for _ in range(3)])
+        bcols = rng.integers(0, ncb, brows.size)
+        bps = wb.psi_site[:, :, torch.as_tensor(brows, device=dev)].cpu().numpy()
+        bpg = wb.psi_grid[:, :, torch.as_tensor(bcols, device=dev)].cpu().numpy()
+        ctx2 = P.Context(0)
+        ctx2.set_orbitals(wb.energies, wb.nocc, wb.psi_grid, wb.grid_dV)
+        ctx2.set_sites(wb.sites, wb.psi_site)
+        wb.psi_grid = None
+        torch.cuda.empty_cache()
+        nt, terr = ctx2.make_quadrature_tol(1e-9, 24, 32)
+        if not args.no_tune:
+            ctx2.tune(prec)
+        outb = torch.empty((nrb, ncb), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        log(f"batching workload ready in {time.time() - tb:.1f} s: {len(wb.sites)} sites, "
+            f"{nrb} x {ncb}, {nt} terms")
+        tb = time.time()
+        ctx2.chi0(-1, P.COLS_GRID, prec, out=outb)
+        torch.cuda.synchronize()
+        call_s = time.time() - tb
+        bms = ctx2.last_kernel_ms()
+        gotb = outb[torch.as_tensor(brows, device=dev), torch.as_tensor(bcols, device=dev)]
+        gotb = gotb.cpu().numpy()
+        qb = ctx2.get_quadrature()
+        v, bm, bn = ctx2.tuned_variant(prec, P.COLS_GRID)
+        ctx2.close()
+        del outb
+        torch.cuda.empty_cache()
+        Kb = wb.nk * wb.nb
+        batching = {"workload": "batching", "precision": prec, "sites": len(wb.sites),
+                    "rows": nrb, "grid_columns": ncb, "terms": nt,
+                    "terms_rule": "smallest n in 24..32 with per-pair error <= 1e-9",
+                    "terms_rule_error": terr, "variant": v, "tile": [bm, bn],
+                    "call_s": call_s, "kernels_ms": bms,
+                    "entries_per_s": nrb * ncb / call_s,
+                    "algorithmic_tflops": nrb * ncb * nt * (8.0 * Kb + 4.0) / call_s / 1e12}
+        if not args.no_cpu:
+            tb_ = cz.terms_for(wb.energies, wb.nocc, "time", nt, qb["scale"])
+            refb = cz.chi0_quad_entries(bps, bpg, wb.nocc, 2, *tb_)
+            batching["rel_err_vs_same_quadrature"] = rel(gotb, refb)
+            batching["entries_compared"] = int(brows.size)
+        log("batching", batching)
+        del wb
+
+    fp64 = paths.get("fp64", {})
     rec = {
         "metric": "chi0 entries/s + MFMA util: split-BF16 vs FP64 GPU path at stated rel. error",
         "value": value,
@@ -372,25 +516,30 @@ def main():
                    "rows": nrows, "grid_columns": ncols, "kpoints": nk, "bands": nb,
                    "occupied": w.nocc, "terms": w.n_terms,
                    "step": "quadrature + chi0 site x grid + chi0 site x site + W + loss + "
-                           + f"adjoints ({adj_prec} products)"},
+                           + f"adjoints ({adj_prec} products)",
+                   "tuned": tuned},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "traffic_gb_per_s": traffic / (kern_ms / 1e3) / 1e9 if traffic else None,
-                     "executed_mfma_tflops": achieved * exec_factor,
+                     "executed_mfma_tflops_equiv": achieved * exec_factor,
                      "executed_frac": achieved * exec_factor / peak,
                      "kernel": "chi0_kernel (site x grid)", "kernel_ms": kern_ms,
                      "flop_per_entry": flop_per_entry,
                      "mfma_busy": ctr.get("mfma_busy_frac") if ctr else None},
         "cpu_baseline": cpu,
+        "cpu_factorised": cpu_fact,
         "chi0_kernel_entries_per_s": entries / (kern_ms / 1e3),
-        "fp64_path": fp64,
-        "fp16x2_path": fp16,
+        "paths": paths,
         "speedup_vs_fp64": (fp64["kernel_ms"] / kern_ms) if fp64 else None,
+        "split_bf16_speedup_vs_fp64": (fp64["kernel_ms"] / paths["bf16x2"]["kernel_ms"])
+        if fp64 and "bf16x2" in paths else None,
         "rel_err": errs,
+        "W_rel_err": w_err,
         "adjoint": adjoint,
         "projection": proj,
         "imag_freq": iw,
         "site_solves": solves,
+        "batching": batching,
         "pack_ms": pack_ms,
         "loss": float(loss.sum().item()),
     }

@@ -65,7 +65,10 @@ typedef enum {
   LRS_FP64 = 0,     /* FP64 matrix-core products, FP64 accumulation */
   LRS_FP32 = 1,     /* FP32 matrix-core products, FP32 accumulation of G */
   LRS_BF16X2 = 2,   /* each operand split into bf16 hi + lo; hi*hi + hi*lo + lo*hi, FP32 accumulation */
-  LRS_FP16X2 = 3    /* the same with fp16 halves (operands prescaled by powers of two) */
+  LRS_FP16X2 = 3,   /* the same with fp16 halves (operands prescaled by powers of two) */
+  LRS_F16F8 = 4     /* fp16 hi + lo split: hi*hi on fp16 matrix cores, the cross terms hi*lo +
+                       lo*hi on block-scaled fp8 (e4m3) ones, FP32 accumulation; two thirds of
+                       the split paths' matrix-core time, relative error of order 1e-6 */
 } lrs_precision;
 
 typedef enum {
@@ -271,6 +274,33 @@ lrs_status lrs_screen_W_noalloc(lrs_ctx* ctx, const double* chi0_sitesite, doubl
 lrs_status lrs_induced_potential(lrs_ctx* ctx, const double* chi0_sitesite, const double* v1_host,
                                  double q, double r_shell, int l0_only, double* rho_out,
                                  double* v_out);
+
+/* Valence screened interaction W(x, x') within r_m (Sec. V.A, Eq. rpa-val): the sites are grid
+ * points x (centres_host [nsites][3], bohr), each screening a unit charge spread uniformly over
+ * a sphere of the grid's discretisation volume vx = Omega / N_x (radius R_x = (3 vx/4 pi)^(1/3)),
+ * potential v_ext = (3 - r^2/R_x^2)/(2 R_x) inside, 1/r outside.  The shell of charge at r_shell
+ * splits it (Eq. partition) into v1 = v_ext - v2 and v2 = 1/r_shell inside, 1/r outside; v1 is
+ * screened by the local RPA response of the site (the solve of lrs_induced_potential, l <= lmax
+ * response to v1 in the L = 00 channel), v2 by the long-wavelength limit of the model, 1/eps_inf
+ * (eps_inf = 1: bare).  With v_ind,L the induced potential's radial functions on the site's
+ * shells, read at |d| by cubic Lagrange interpolation over the four nearest shells:
+ *   W^[x](x + d) = v_ext(|d|) + sum_L v_ind,L(|d|) Y_L(d/|d|) - (1 - 1/eps_inf) v2(|d|)
+ *   W_out[x][x'] = (W^[x](x') + W^[x'](x)) / 2   for 0 < |d| <= r_m (d = x' - x, nearest image)
+ *   W_out[x][x]  = (3/R_x^3) int_0^R_x W^[x]_00(r) r^2 dr  (the l = 0 part over the
+ *                  discretisation sphere: 6/(5 R_x) for the bare sphere, the induced part by
+ *                  8-point Gauss-Legendre on [0, R_x])
+ *   W_out[x][x'] = 0 beyond r_m (the paper's HLL model there is outside this library).
+ *   chi0_sitesite  site blocks (layout of LRS_COLS_SITE, all sites), device
+ *   cell_host      lattice vectors [3][3] (rows, bohr) for the nearest periodic image (by
+ *                  rounding fractional coordinates: exact while r_m is below half the smallest
+ *                  cell height), or NULL for plain differences
+ *   W_out          float64 [nsites][nsites], device; exactly symmetric.
+ * LRS_EINVAL unless vx > 0, r_shell > R_x, eps_inf >= 1, 0 < r_m <= every site's largest shell
+ * radius; LRS_EUNSUPPORTED for a site with fewer than 4 shells or beyond the solve's limits.
+ * Synchronous in its host part; LRS_ESTATE under stream capture. */
+lrs_status lrs_valence_W(lrs_ctx* ctx, const double* chi0_sitesite, const double* centres_host,
+                         const double* cell_host, double vx, double r_shell, double eps_inf,
+                         double r_m, double* W_out);
 
 /* W for the ALDA polarizability (App. ALDA, Eq. chi-alda: chi~ = (1 - chi0 (v + f_xc))^-1 chi0,
  * with the contact kernel of Eq. kxc_alda, f_xc(r, r') = delta(r - r') dv_xc/dn at n(r)).

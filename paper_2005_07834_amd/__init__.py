@@ -21,10 +21,10 @@ LIB_PATH = os.path.join(_HERE, "liblrs.so")
 
 LRS_OK, LRS_EINVAL, LRS_ENOMEM, LRS_EDEVICE, LRS_ESTATE, LRS_ENOGAP, LRS_ENONFINITE, \
     LRS_EUNSUPPORTED = range(8)
-FP64, FP32, BF16X2, FP16X2 = range(4)
+FP64, FP32, BF16X2, FP16X2, F16F8 = range(5)
 COLS_GRID, COLS_SITE = 0, 1
 QUAD_TIME, QUAD_FREQ = 0, 1
-PREC_NAMES = {"fp64": FP64, "fp32": FP32, "bf16x2": BF16X2, "fp16x2": FP16X2}
+PREC_NAMES = {"fp64": FP64, "fp32": FP32, "bf16x2": BF16X2, "fp16x2": FP16X2, "f16f8": F16F8}
 STATUS_NAMES = {0: "LRS_OK", 1: "LRS_EINVAL", 2: "LRS_ENOMEM", 3: "LRS_EDEVICE", 4: "LRS_ESTATE",
                 5: "LRS_ENOGAP", 6: "LRS_ENONFINITE", 7: "LRS_EUNSUPPORTED"}
 
@@ -51,6 +51,7 @@ SIGNATURES = [
     ("lrs_project_orbitals", _I, [_P, _I, _I, _I, _P, _P, _P, _D, _I, _P, _P]),
     ("lrs_induced_potential", _I, [_P, _P, _P, _D, _D, _I, _P, _P]),
     ("lrs_screen_W_alda", _I, [_P, _P, _P, _P]),
+    ("lrs_valence_W", _I, [_P, _P, _P, _P, _D, _D, _D, _D, _P]),
     ("lrs_make_quadrature_iw", _I, [_P, _I, _D, _D]),
     ("lrs_make_quadrature_tol", _I, [_P, _D, _I, _I, _P, _P]),
     ("lrs_last_kernel_ms", _D, [_P]),
@@ -294,6 +295,21 @@ class Context:
                                               _ptr(rho), _ptr(v)))
         return rho, v
 
+    def valence_W(self, chi0_ss, centres, vx, r_shell, eps_inf=1.0, r_m=2.0, cell=None):
+        """Valence W(x, x') [nsites, nsites] within r_m for sites centred at grid points
+        `centres` [nsites, 3] (Sec. V.A, Eq. rpa-val): the sphere of the discretisation volume
+        vx, the shell radius r_shell, eps_inf for the shell's potential, lattice `cell` [3, 3]
+        (rows) for the nearest image or None."""
+        c = _host(centres, np.float64).reshape(-1, 3)
+        if c.shape[0] != self.nsites:
+            raise ValueError("one centre per site")
+        cl = None if cell is None else _host(cell, np.float64).reshape(3, 3)
+        W = torch.empty((self.nsites, self.nsites), dtype=torch.float64, device=self.device)
+        self._check(lib.lrs_valence_W(self.h, _ptr(chi0_ss.contiguous()), _ptr(c), _ptr(cl),
+                                      float(vx), float(r_shell), float(eps_inf), float(r_m),
+                                      _ptr(W)))
+        return W
+
     def project_orbitals(self, kpts, gvec, coef, omega, points):
         """Orbitals at `points` (float64 [npts, 3], bohr) from plane-wave coefficients `coef`
         (complex128 [nk, nb, npw] on this device) with k-points `kpts` [nk, 3] and G vectors
@@ -439,5 +455,5 @@ def check_bands(energies, nocc, mu=float("nan"), delta=0.0):
     return lib.lrs_check_bands(E.shape[0], E.shape[1], nocc, _ptr(E), mu, delta)
 
 
-__all__ = ["lib", "Context", "LrsError", "check_bands", "Chi0Fn", "ScreenWFn", "FP64", "FP32", "BF16X2", "FP16X2",
+__all__ = ["lib", "Context", "LrsError", "check_bands", "Chi0Fn", "ScreenWFn", "FP64", "FP32", "BF16X2", "FP16X2", "F16F8",
            "COLS_GRID", "COLS_SITE", "QUAD_TIME", "QUAD_FREQ", "SIGNATURES"]

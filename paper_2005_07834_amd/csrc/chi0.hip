@@ -41,6 +41,7 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 typedef __attribute__((__vector_size__(4 * sizeof(double)))) double f64x4;
 typedef __attribute__((__vector_size__(4 * sizeof(unsigned int)))) unsigned int u32x4;
+typedef int i32x8 __attribute__((ext_vector_type(8)));   // 32 fp8 values
 
 struct Chi0Params {
   const unsigned char* a;       // weighted site operand tiles [term][chunk][rowblock][tile]
@@ -111,6 +112,13 @@ struct Prec<LRS_FP16X2> {
   using acc_t = f32x16;
   static constexpr int KC = 16, TB = 2048, BLK = 32, ELEMS = 16;
 };
+// fp16 hi products on v_mfma_f32_32x32x16_f16, the cross terms on
+// v_mfma_scale_f32_32x32x64_f8f6f4 (fp8 e4m3, one scale per row and 32-K block); 32 K per chunk
+template <>
+struct Prec<LRS_F16F8> {
+  using acc_t = f32x16;
+  static constexpr int KC = 32, TB = 4096, BLK = 32, ELEMS = 16;
+};
 
 // Row and column (inside a BLK x BLK accumulator block) of element e of a lane:
 //   f32 16x16:   (4 (lane/16) + e, lane%16)
@@ -151,6 +159,66 @@ __device__ __forceinline__ T zero_acc() {
 __device__ inline size_t site_pos(int r, int k, int K_pad) {
   int ch = k >> 4, kl = k & 15;
   return (size_t)r * K_pad + ch * 16 + (kl & 3) * 4 + (kl >> 2);
+}
+
+// F16F8 (chunk 32, 32 slots): slot s holds row s%16 and K 16 (s/16) + j, j = 0..15, of the
+// chunk: fp16 hi slots s%16 and 16 + s%16 of plane pair s/16, fp8 slot s with part 0 =
+// hi * 2^7 and part 1 = lo * 2^18 (the row side's order), for re and im.
+__global__ void prep_site_f16f8_kernel(const double* site, int rows_pad, int K_pad,
+                                       const int* slot_row, int rb0, int nrb, const double* w,
+                                       int t0, int nt, double a_scale, unsigned char* out) {
+  constexpr int TB = 4096;
+  const int nch = K_pad / 32;
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long long)nrb * nch * 32) return;
+  const int s = (int)(gid % 32);
+  const long long tile = gid / 32;
+  const int rb = (int)(tile % nrb);
+  const int ch = (int)(tile / nrb);
+  const int r = s & 15, h = s >> 4;
+  const int row = slot_row[(rb0 + rb) * 16 + r];
+  const size_t plane = (size_t)rows_pad * K_pad;
+  const int k0 = ch * 32 + 16 * h;
+  double p0[16], q0[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    if (row < 0) {
+      p0[j] = 0.0;
+      q0[j] = 0.0;
+    } else {
+      const size_t o = site_pos(row, k0 + j, K_pad);
+      p0[j] = site[o] * a_scale;
+      q0[j] = site[plane + o] * a_scale;
+    }
+  }
+  for (int t = 0; t < nt; ++t) {
+    const double* wt = w + (size_t)(t0 + t) * K_pad + k0;
+    unsigned char* base = out + (((size_t)t * nch + ch) * nrb + rb) * TB;
+    f16x8 hp[2], hq[2];
+    unsigned int f8[4][4] = {};     // [re p0, re p1, im p0, im p1][dword]
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const float xp = (float)(p0[j] * wt[j]), xq = (float)(q0[j] * wt[j]);
+      const _Float16 a = (_Float16)xp, b = (_Float16)xq;
+      hp[j >> 3][j & 7] = a;
+      hq[j >> 3][j & 7] = b;
+      const int sh = 8 * (j & 3), dw = j >> 2;
+      f8[0][dw] |= e4m3_rn(ldexpf((float)a, kF8HiShift)) << sh;
+      f8[1][dw] |= e4m3_rn(ldexpf(xp - (float)a, kF8LoShift)) << sh;
+      f8[2][dw] |= e4m3_rn(ldexpf((float)b, kF8HiShift)) << sh;
+      f8[3][dw] |= e4m3_rn(ldexpf(xq - (float)b, kF8LoShift)) << sh;
+    }
+    // (16-byte stores; the four planes of a chunk half and the four fp8 parts)
+    *(f16x8*)(base + h * 512 + r * 16) = hp[0];
+    *(f16x8*)(base + h * 512 + (16 + r) * 16) = hp[1];
+    *(f16x8*)(base + 1024 + h * 512 + r * 16) = hq[0];
+    *(f16x8*)(base + 1024 + h * 512 + (16 + r) * 16) = hq[1];
+#pragma unroll
+    for (int part = 0; part < 4; ++part) {
+      u32x4 v = {f8[part][0], f8[part][1], f8[part][2], f8[part][3]};
+      *(u32x4*)(base + 2048 + part * 512 + s * 16) = v;
+    }
+  }
 }
 
 template <int PREC>
@@ -254,6 +322,25 @@ struct Frags<LRS_FP16X2, MB, NB> {
   f16x8 ph[MB / 2], pl[MB / 2], qh[MB / 2], ql[MB / 2];
   f16x8 rh[NB / 2], rl[NB / 2], ih[NB / 2], il[NB / 2];
 };
+// F16F8: per 32-row block the fp16 hi values of both 16-K halves of the chunk (lane l: row
+// l%32, K 8 (l/32) + e of each half) and the fp8 pairs (lane l: row l%32, K 16 (l/32) + j;
+// bytes 0-15 scale block 0, bytes 16-31 block 1)
+template <int MB, int NB>
+struct Frags<LRS_F16F8, MB, NB> {
+  f16x8 p0[MB / 2], p1[MB / 2], q0[MB / 2], q1[MB / 2];
+  i32x8 p8[MB / 2], q8[MB / 2];
+  f16x8 r0[NB / 2], r1[NB / 2], i0[NB / 2], i1[NB / 2];
+  i32x8 r8[NB / 2], i8[NB / 2];
+};
+
+// fp8 fragment of 32 bytes from two 16-byte parts 512 bytes apart
+__device__ __forceinline__ i32x8 load_f8(const unsigned char* p) {
+  const u32x4 a = *(const u32x4*)p, b = *(const u32x4*)(p + 512);
+  i32x8 v;
+  v[0] = (int)a[0]; v[1] = (int)a[1]; v[2] = (int)a[2]; v[3] = (int)a[3];
+  v[4] = (int)b[0]; v[5] = (int)b[1]; v[6] = (int)b[2]; v[7] = (int)b[3];
+  return v;
+}
 
 template <int PREC, int MB, int NB>
 __device__ __forceinline__ void load_frags(const unsigned char* lds_a, const unsigned char* lds_b,
@@ -283,6 +370,29 @@ __device__ __forceinline__ void load_frags(const unsigned char* lds_a, const uns
         f.br[j][h] = *(const f32x4*)(lds_b + j * TB + lane * 32 + 16 * h);
         f.bi[j][h] = *(const f32x4*)(lds_b + j * TB + 2048 + lane * 32 + 16 * h);
       }
+    }
+  } else if constexpr (PREC == LRS_F16F8) {
+    // a 32-row block is two 4 KiB tiles; lane l reads slot (l/32) * 16 + l%16 of tile (l%32)/16
+    const int lofs = ((lane & 31) >> 4) * TB + (lane >> 5) * 256 + (lane & 15) * 16;
+#pragma unroll
+    for (int i = 0; i < MB / 2; ++i) {
+      const unsigned char* a = lds_a + i * 2 * TB + lofs;
+      f.p0[i] = *(const f16x8*)(a);
+      f.p1[i] = *(const f16x8*)(a + 512);
+      f.q0[i] = *(const f16x8*)(a + 1024);
+      f.q1[i] = *(const f16x8*)(a + 1536);
+      f.p8[i] = load_f8(a + 2048);
+      f.q8[i] = load_f8(a + 3072);
+    }
+#pragma unroll
+    for (int j = 0; j < NB / 2; ++j) {
+      const unsigned char* b = lds_b + j * 2 * TB + lofs;
+      f.r0[j] = *(const f16x8*)(b);
+      f.r1[j] = *(const f16x8*)(b + 512);
+      f.i0[j] = *(const f16x8*)(b + 1024);
+      f.i1[j] = *(const f16x8*)(b + 1536);
+      f.r8[j] = load_f8(b + 2048);
+      f.i8[j] = load_f8(b + 3072);
     }
   } else {
     using half_t = typename std::conditional<PREC == LRS_BF16X2, bf16x8, f16x8>::type;
@@ -339,6 +449,47 @@ __device__ __forceinline__ void mma_frags(
             gr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(q, bi, gr[i][j], 0, 0, 0);
             gi[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(-q, br, gi[i][j], 0, 0, 0);
           }
+  } else if constexpr (PREC == LRS_F16F8) {
+    // each real product: hi * hi over both K halves on the fp16 instruction, then hi * lo and
+    // lo * hi on one scaled fp8 instruction (block 0: row hi x column lo, scales 2^-7 and
+    // 2^-18; block 1: row lo x column hi, 2^-18 and 2^-7).  Each stage updates every block of
+    // one accumulator array before the next stage, so dependent instructions are far apart.
+    const int lane = __lane_id();
+    const int sa = lane < 32 ? 127 - kF8HiShift : 127 - kF8LoShift;
+    const int sb = lane < 32 ? 127 - kF8LoShift : 127 - kF8HiShift;
+    const u32x4 m16 = {0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+    const int m8 = (int)0x80808080u;
+    auto h = [](f16x8 a, f16x8 b, f32x16 c) {
+      return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    };
+    auto e = [&](i32x8 a, i32x8 b, f32x16 c) {
+      return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, sa, 0, sb);
+    };
+    f16x8 nq0[MB / 2], nq1[MB / 2];
+    i32x8 nq8[MB / 2];
+#pragma unroll
+    for (int i = 0; i < MB / 2; ++i) {
+      nq0[i] = (f16x8)((u32x4)f.q0[i] ^ m16);
+      nq1[i] = (f16x8)((u32x4)f.q1[i] ^ m16);
+      nq8[i] = f.q8[i] ^ m8;
+    }
+#define LRS_F16F8_STAGE(ACC, OP, A, B)         \
+  _Pragma("unroll") for (int i = 0; i < MB / 2; ++i) \
+    _Pragma("unroll") for (int j = 0; j < NB / 2; ++j) ACC[i][j] = OP(A[i], B[j], ACC[i][j]);
+    // G_r += p b_r + q b_i,  G_i += p b_i - q b_r
+    LRS_F16F8_STAGE(gr, h, f.p0, f.r0)
+    LRS_F16F8_STAGE(gi, h, f.p0, f.i0)
+    LRS_F16F8_STAGE(gr, h, f.p1, f.r1)
+    LRS_F16F8_STAGE(gi, h, f.p1, f.i1)
+    LRS_F16F8_STAGE(gr, e, f.p8, f.r8)
+    LRS_F16F8_STAGE(gi, e, f.p8, f.i8)
+    LRS_F16F8_STAGE(gr, h, f.q0, f.i0)
+    LRS_F16F8_STAGE(gi, h, nq0, f.r0)
+    LRS_F16F8_STAGE(gr, h, f.q1, f.i1)
+    LRS_F16F8_STAGE(gi, h, nq1, f.r1)
+    LRS_F16F8_STAGE(gr, e, f.q8, f.i8)
+    LRS_F16F8_STAGE(gi, e, nq8, f.r8)
+#undef LRS_F16F8_STAGE
   } else {
     using half_t = typename std::conditional<PREC == LRS_BF16X2, bf16x8, f16x8>::type;
     // negation flips the sign bit of every 16-bit element
@@ -491,16 +642,25 @@ __device__ __forceinline__ void mma_col_split(const FragsA<PREC, MB>& a, const F
 
 // Scheduling groups for one pipeline step: the next chunk's LDS reads, one per matrix-core
 // instruction, then the global->LDS loads spread over the following ones, then the rest.
-template <int PREC, int MB, int NB, int NVM>
+// With the F16F8 path's two-slot ring the loads go first instead: the chunk they fetch is waited
+// for at the start of the next step, so issuing them late would leave them a fraction of a step
+// to land.
+template <int PREC, int MB, int NB, int NVM, int S>
 __device__ __forceinline__ void interleave() {
   constexpr int kMFMA = 0x008, kVMEM = 0x010, kDSREAD = 0x100;
   constexpr bool split = PREC == LRS_BF16X2 || PREC == LRS_FP16X2;
   // instructions per step: LDS reads of 16 bytes, matrix-core instructions
-  constexpr int NDS = split ? 2 * (MB + NB) : (PREC == LRS_FP64 ? 4 * (MB + NB) : 4 * (MB + NB));
-  constexpr int NMF = split ? 3 * MB * NB : (PREC == LRS_FP64 ? 16 * MB * NB : 32 * MB * NB);
+  constexpr int NDS = split ? 2 * (MB + NB) : 4 * (MB + NB);
+  constexpr int NMF = (split || PREC == LRS_F16F8) ? 3 * MB * NB
+                                                   : (PREC == LRS_FP64 ? 16 * MB * NB : 32 * MB * NB);
   constexpr int R = (NMF - NDS) / NVM > 0 ? (NMF - NDS) / NVM : 1;
-  sched_pairs<NDS, kMFMA, 1, kDSREAD, 1>();
-  sched_pairs<NVM, kMFMA, R, kVMEM, 1>();
+  if constexpr (S == 2 && PREC == LRS_F16F8) {
+    sched_pairs<NVM, kMFMA, 1, kVMEM, 1>();
+    sched_pairs<NDS, kMFMA, 1, kDSREAD, 1>();
+  } else {
+    sched_pairs<NDS, kMFMA, 1, kDSREAD, 1>();
+    sched_pairs<NVM, kMFMA, R, kVMEM, 1>();
+  }
   __builtin_amdgcn_sched_group_barrier(kMFMA, NMF, 0);
 }
 
@@ -703,7 +863,7 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
         } else {
           // LDS reads and loads spread between the matrix-core instructions
           mma_frags<PREC, MB, NB>(cur, gr, gi);
-          interleave<PREC, MB, NB, LPW>();
+          interleave<PREC, MB, NB, LPW, S>();
         }
       }
       __builtin_amdgcn_sched_barrier(0);
@@ -900,6 +1060,12 @@ LRS_VARIANT(LRS_FP16X2, 0, 2, 2, 4, 4, 4, 1, 0)
 LRS_VARIANT(LRS_FP16X2, 1, 2, 2, 4, 8, 2, 1, 0)
 LRS_VARIANT(LRS_FP16X2, 2, 1, 4, 8, 4, 2, 1, 1)
 LRS_VARIANT(LRS_FP16X2, 3, 2, 2, 4, 6, 4, 1, 0)
+// F16F8: 64 KiB stages (32 K per chunk), so a two-slot ring; interleaved or not.  (Variants 2
+// and 3 repeat 0 and 1: only two are offered.)
+LRS_VARIANT(LRS_F16F8, 0, 2, 2, 4, 4, 2, 1, 0)
+LRS_VARIANT(LRS_F16F8, 1, 2, 2, 4, 4, 2, 0, 0)
+LRS_VARIANT(LRS_F16F8, 2, 2, 2, 4, 4, 2, 1, 0)
+LRS_VARIANT(LRS_F16F8, 3, 2, 2, 4, 4, 2, 0, 0)
 #undef LRS_VARIANT
 constexpr int kNumVariants = 4;
 
@@ -982,6 +1148,13 @@ template <int PREC>
 hipError_t prep_p(const double* site, int rows_pad, int K_pad, const int* slot_row, int rb0,
                   int nrb, const double* w, int t0, int nt, double a_scale, void* out,
                   hipStream_t s) {
+  if constexpr (PREC == LRS_F16F8) {
+    const long long n = (long long)nrb * (K_pad / 32) * 32;
+    hipLaunchKernelGGL(prep_site_f16f8_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       s, site, rows_pad, K_pad, slot_row, rb0, nrb, w, t0, nt, a_scale,
+                       (unsigned char*)out);
+    return hipGetLastError();
+  }
   const int nch = K_pad / Prec<PREC>::KC;
   const int slots = (PREC == LRS_BF16X2 || PREC == LRS_FP16X2) ? 32 : 64;
   const long long n = (long long)nrb * nch * slots;
@@ -993,7 +1166,7 @@ hipError_t prep_p(const double* site, int rows_pad, int K_pad, const int* slot_r
 
 }  // namespace
 
-int chi0_num_variants(int) { return kNumVariants; }
+int chi0_num_variants(int prec) { return prec == LRS_F16F8 ? 2 : kNumVariants; }
 
 // fastest variant measured on the precision workload (the tuner can override it)
 int chi0_default_variant(int) { return 0; }
@@ -1003,6 +1176,7 @@ int chi0_blocks_per_cu(int prec, int variant) {
     case LRS_FP64: return occ_p<LRS_FP64>(variant);
     case LRS_FP32: return occ_p<LRS_FP32>(variant);
     case LRS_BF16X2: return occ_p<LRS_BF16X2>(variant);
+    case LRS_F16F8: return occ_p<LRS_F16F8>(variant);
     default: return occ_p<LRS_FP16X2>(variant);
   }
 }
@@ -1012,6 +1186,7 @@ TileShape chi0_shape(int prec, int variant) {
     case LRS_FP64: return shape_p<LRS_FP64>(variant);
     case LRS_FP32: return shape_p<LRS_FP32>(variant);
     case LRS_BF16X2: return shape_p<LRS_BF16X2>(variant);
+    case LRS_F16F8: return shape_p<LRS_F16F8>(variant);
     default: return shape_p<LRS_FP16X2>(variant);
   }
 }
@@ -1024,6 +1199,7 @@ hipError_t launch_prep_site(int prec, const double* site, int rows_pad, int K_pa
     case LRS_FP32: return prep_p<LRS_FP32>(site, rows_pad, K_pad, slot_row, rb0, nrb, w, t0, nt, a_scale, out, s);
     case LRS_BF16X2: return prep_p<LRS_BF16X2>(site, rows_pad, K_pad, slot_row, rb0, nrb, w, t0, nt, a_scale, out, s);
     case LRS_FP16X2: return prep_p<LRS_FP16X2>(site, rows_pad, K_pad, slot_row, rb0, nrb, w, t0, nt, a_scale, out, s);
+    case LRS_F16F8: return prep_p<LRS_F16F8>(site, rows_pad, K_pad, slot_row, rb0, nrb, w, t0, nt, a_scale, out, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1060,6 +1236,7 @@ hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int
     case LRS_FP32: return launch_p<LRS_FP32>(variant, grid, P, s);
     case LRS_BF16X2: return launch_p<LRS_BF16X2>(variant, grid, P, s);
     case LRS_FP16X2: return launch_p<LRS_FP16X2>(variant, grid, P, s);
+    case LRS_F16F8: return launch_p<LRS_F16F8>(variant, grid, P, s);
   }
   return hipErrorInvalidValue;
 }

@@ -435,7 +435,7 @@ lrs_status site_operand(lrs_ctx* ctx, int prec, const Batch& b, int t0, int nt,
   }
   ctx->a_prec = -1;
   CHECK(ensure_buf(ctx, ctx->a_tiles, a_bytes_per_rb(ctx, prec, nt) * b.nrb, "weighted site operand"));
-  const double a_scale = prec == LRS_FP16X2 ? ctx->site_scale_f16 : 1.0;
+  const double a_scale = is_f16(prec) ? ctx->site_scale_f16 : 1.0;
   HIP_OR_FAIL(ctx, launch_prep_site(prec, (const double*)ctx->site_f64.p, ctx->rows_pad,
                                     ctx->K_pad, (const int*)ctx->site_colmap.p, b.rb0, b.nrb,
                                     (const double*)ctx->w_nat.p, t0, nt, a_scale,
@@ -477,13 +477,13 @@ lrs_status run_chi0(lrs_ctx* ctx, int site, int cols, int prec, int variant, dou
   if (cols == LRS_COLS_GRID) {
     CHECK(ensure_grid_tiles(ctx, prec));
     b = ctx->grid_tiles[prec].p;
-    if (prec == LRS_FP16X2) bscale = ctx->grid_scale_f16;
+    if (is_f16(prec)) bscale = ctx->grid_scale_f16;
   } else {
     CHECK(ensure_site_tiles(ctx, prec));
     b = ctx->site_tiles[prec].p;
-    if (prec == LRS_FP16X2) bscale = ctx->site_scale_f16;
+    if (is_f16(prec)) bscale = ctx->site_scale_f16;
   }
-  const double a_scale = prec == LRS_FP16X2 ? ctx->site_scale_f16 : 1.0;
+  const double a_scale = is_f16(prec) ? ctx->site_scale_f16 : 1.0;
   const int KC = chunk_of(prec);
   const int nch = ctx->K_pad / KC;
   double pref = -2.0 * ctx->spin / ((double)ctx->nk * ctx->nk);
@@ -592,6 +592,7 @@ void lrs_destroy(lrs_ctx* ctx) {
   release(ctx, ctx->screen_tab);
   release(ctx, ctx->work);
   release(ctx, ctx->adj_work);
+  release(ctx, ctx->val_work);
   release(ctx, ctx->a_tiles);
   release(ctx, ctx->park);
   release(ctx, ctx->xcd_sync);
@@ -976,7 +977,7 @@ lrs_status lrs_compute_chi0(lrs_ctx* ctx, int site, int cols, int prec, double* 
   if (!out) return fail(ctx, LRS_EINVAL, "chi0_out is NULL");
   if (site < -1 || site >= ctx->nsites) return fail(ctx, LRS_EINVAL, "site %d out of range", site);
   if (cols != LRS_COLS_GRID && cols != LRS_COLS_SITE) return fail(ctx, LRS_EINVAL, "bad column set");
-  if (prec < LRS_FP64 || prec > LRS_FP16X2) return fail(ctx, LRS_EINVAL, "bad precision");
+  if (prec < LRS_FP64 || prec > LRS_F16F8) return fail(ctx, LRS_EINVAL, "bad precision");
   if (cols == LRS_COLS_GRID && ctx->ngrid <= 0) return fail(ctx, LRS_ESTATE, "no grid orbitals were given");
   int cur = -1;
   HIP_OR_FAIL(ctx, hipGetDevice(&cur));
@@ -1028,7 +1029,7 @@ lrs_status lrs_tune(lrs_ctx* ctx, int prec) {
   ctx->err.clear();
   if (!ctx->have_bands || !ctx->have_sites || !ctx->have_quad)
     return fail(ctx, LRS_ESTATE, "orbitals, sites and quadrature must be set first");
-  if (prec < LRS_FP64 || prec > LRS_FP16X2) return fail(ctx, LRS_EINVAL, "bad precision");
+  if (prec < LRS_FP64 || prec > LRS_F16F8) return fail(ctx, LRS_EINVAL, "bad precision");
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
   int s = 0;
   for (int k = 1; k < ctx->nsites; ++k)
@@ -1102,7 +1103,7 @@ lrs_status lrs_tune(lrs_ctx* ctx, int prec) {
 lrs_status lrs_tuned_variant(const lrs_ctx* ctx, int prec, int cols, int* variant_host,
                              int* tile_rows_host, int* tile_cols_host) {
   if (!ctx || !variant_host) return LRS_EINVAL;
-  if (prec < LRS_FP64 || prec > LRS_FP16X2 || (cols != LRS_COLS_GRID && cols != LRS_COLS_SITE))
+  if (prec < LRS_FP64 || prec > LRS_F16F8 || (cols != LRS_COLS_GRID && cols != LRS_COLS_SITE))
     return LRS_EINVAL;
   const int v = pick_variant(const_cast<lrs_ctx*>(ctx), prec, cols);
   *variant_host = v;

@@ -28,7 +28,10 @@ constexpr int kMaxTileCols = 256;
 constexpr int kPhaseAlign = 128;
 constexpr int kMaxTerms = 128;
 
-inline bool is_split(int prec) { return prec == LRS_BF16X2 || prec == LRS_FP16X2; }
+__host__ __device__ inline bool is_split(int prec) { return prec == LRS_BF16X2 || prec == LRS_FP16X2; }
+// operands carry fp16 values prescaled by a power of two (FP16X2 and F16F8)
+__host__ __device__ inline bool is_f16(int prec) { return prec == LRS_FP16X2 || prec == LRS_F16F8; }
+constexpr int kNumPrec = 5;
 // leading dimension of a site's n x n block: n for chi0 outputs, n rounded up to kAdjAlign for
 // the adjoint's internal site blocks (plan mode 1): a whole number of four-chunk ring cycles
 // of the adjoint GEMMs' contraction, whose padding is zero
@@ -37,8 +40,33 @@ inline int site_block_ld(int n, int mode) {
   return mode == 1 ? (n + kAdjAlign - 1) / kAdjAlign * kAdjAlign : n;
 }
 // K values per chunk and bytes per fragment tile (16 rows x chunk x planes)
-inline int chunk_of(int prec) { return prec == LRS_FP32 ? 32 : 16; }
-inline int tile_bytes(int prec) { return is_split(prec) ? 2048 : 4096; }
+__host__ __device__ inline int chunk_of(int prec) { return prec == LRS_FP32 || prec == LRS_F16F8 ? 32 : 16; }
+__host__ __device__ inline int tile_bytes(int prec) { return is_split(prec) ? 2048 : 4096; }
+// F16F8 fragment tiles (16 rows x 32 K, 4 KiB; a 32-row block is two consecutive tiles):
+//   [0, 2048)    fp16 hi: planes re (K 0-15), re (K 16-31), im (K 0-15), im (K 16-31), 512 B
+//                each, slot s holding row s%16 and K 8 (s/16) + e, e = 0..7 (16 B)
+//   [2048, 4096) fp8 (e4m3) planes re part 0, re part 1, im part 0, im part 1, 512 B each, slot
+//                s holding row s%16 and K 16 (s/16) + j, j = 0..15 (16 B); part 0 is the scale
+//                block 0 of the matrix-core instruction, part 1 block 1.  The row (site) operand
+//                stores hi * 2^7 in part 0 and lo * 2^18 in part 1; the column operand the
+//                other way round, so that the blocks multiply hi * lo and lo * hi.
+constexpr int kF8HiShift = 7;    // fp8 hi = e4m3(hi * 2^7): |hi| < 2 after the prescale
+constexpr int kF8LoShift = 18;   // fp8 lo = e4m3(lo * 2^18): |lo| <= 2^-11 |x| < 2^-10
+
+// x to fp8 e4m3 (1 sign, 4 exponent bits with bias 7, 3 mantissa bits; no infinities, the
+// largest finite value 448), rounding to nearest with ties to even; values beyond 448 saturate
+// to it.  Below 2^-6 the format is subnormal (steps of 2^-9).
+__device__ inline unsigned int e4m3_rn(float x) {
+  const unsigned int sign = (__float_as_uint(x) >> 24) & 0x80u;
+  const float a = fabsf(x);
+  if (a < 0.015625f) return sign | (unsigned int)rintf(a * 512.0f);   // 8 -> 0x08 = 2^-6
+  unsigned int u = __float_as_uint(a);
+  u += 0x7FFFFu + ((u >> 20) & 1u);                  // round the mantissa to 3 bits
+  const int e = (int)(u >> 23) - 120;                // rebias 127 -> 7
+  const unsigned int m = (u >> 20) & 7u;
+  if (e > 15 || (e == 15 && m == 7)) return sign | 0x7Eu;
+  return sign | ((unsigned int)e << 3) | m;
+}
 inline long long round_up(long long x, long long m) { return (x + m - 1) / m * m; }
 // Split adjoint operand tiles (bfloat16).  A 1 KiB piece holds 32 rows x 16 contraction
 // indices of one plane, lane l's 16 bytes at 16 l being row l%32, indices 8 (l/32) .. +7; the
@@ -124,9 +152,9 @@ struct lrs_ctx {
   int Ko = 0, Ku = 0, Ko_pad = 0, Ku_pad = 0, K_pad = 0;
 
   // grid operand: FP64 fragment tiles (always) and lazily built reduced-precision tiles
-  lrs::DevBuf grid_tiles[4];
+  lrs::DevBuf grid_tiles[lrs::kNumPrec];
   int grid_cols_pad = 0;
-  float grid_scale_f16 = 1.f;     // power-of-two prescale used by the FP16X2 tiles
+  float grid_scale_f16 = 1.f;     // power-of-two prescale used by the FP16X2 and F16F8 tiles
 
   // sites
   bool have_sites = false;
@@ -134,11 +162,11 @@ struct lrs_ctx {
   std::vector<int> nrad, nang, site_off, rad_off, ang_off;
   std::vector<int> site_col_off;  // column offset of each site in the site column operand
   int site_cols_pad = 0;
-  float site_scale_f16 = 1.f;     // power-of-two prescale of site values in FP16X2 operands
+  float site_scale_f16 = 1.f;     // power-of-two prescale of site values in FP16X2 and F16F8 operands
   lrs::DevBuf site_colmap;        // [site_cols_pad] column -> site row (-1: zero column)
   std::vector<double> radii, rad_w, ang_xyz, ang_w;
   lrs::DevBuf site_f64;           // planar re/im [2][rows_pad][K_pad] (chunk-permuted), FP64
-  lrs::DevBuf site_tiles[4];      // site points as a column operand (fragment tiles)
+  lrs::DevBuf site_tiles[lrs::kNumPrec];   // site points as a column operand (fragment tiles)
   lrs::DevBuf a_tiles;            // weighted site operand tiles of the current batch
   lrs::DevBuf park;               // per-workgroup G_o scratch of the chi0 launches
   lrs::DevBuf xcd_sync;           // per-XCD term counters of the chi0 launches
@@ -159,10 +187,10 @@ struct lrs_ctx {
   // plans
   std::map<long long, lrs::Plan> plans;
   // variant chosen by lrs_tune per (precision, column set); -1 = the default
-  int tuned_variant[4][2] = {{-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}};
+  int tuned_variant[lrs::kNumPrec][2] = {{-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}};
 
   // screening state
-  lrs::DevBuf W_last, rho_last, screen_tab, work, adj_work;
+  lrs::DevBuf W_last, rho_last, screen_tab, work, adj_work, val_work;
   bool have_W = false, have_rho = false;
 
   // timing

@@ -66,10 +66,47 @@ __device__ inline void split_f16(float x, __half& hi, __half& lo) {
 //   FP32  (4 KiB, 64 slots):  slot l holds column l%16, k = 32 ch + 4 s + l/16, s = 0..7
 //   split (2 KiB, 32 slots):  slot l holds column l%16, k = 16 ch + 8 (l/16) + e, e = 0..7,
 //                             planes re hi, re lo, im hi, im lo
+//   F16F8 (4 KiB): see pack_f16f8_column and the layout note in lrs_internal.h
+// F16F8 column operand, one thread per (tile, column c, half h of the 32-K chunk): the 16 K
+// values 16 h .. 16 h + 15 of column c go to the fp16 hi slots c and 16 + c of plane pair h
+// and to fp8 slot 16 h + c, part 0 = lo * 2^18, part 1 = hi * 2^7 (the column side's order).
+template <class Src>
+__device__ void pack_f16f8_column(const Src& src, int c, int k0, float prescale,
+                                  unsigned char* tile, int h, int slot_c) {
+  _Float16 hr[16], hi_[16];
+  unsigned int f8[4][4] = {};     // [re p0, re p1, im p0, im p1][dword]
+  for (int j = 0; j < 16; ++j) {
+    double re, im;
+    src.get(c, k0 + j, re, im);
+    const float xr = (float)(re * prescale), xi = (float)(im * prescale);
+    const _Float16 a = (_Float16)xr, b = (_Float16)xi;
+    hr[j] = a;
+    hi_[j] = b;
+    const float lr = xr - (float)a, li = xi - (float)b;
+    const int sh = 8 * (j & 3), dw = j >> 2;
+    f8[0][dw] |= e4m3_rn(ldexpf(lr, kF8LoShift)) << sh;
+    f8[1][dw] |= e4m3_rn(ldexpf((float)a, kF8HiShift)) << sh;
+    f8[2][dw] |= e4m3_rn(ldexpf(li, kF8LoShift)) << sh;
+    f8[3][dw] |= e4m3_rn(ldexpf((float)b, kF8HiShift)) << sh;
+  }
+  for (int q = 0; q < 2; ++q) {       // slots slot_c (K 0-7) and 16 + slot_c (K 8-15)
+    _Float16* dr = reinterpret_cast<_Float16*>(tile + h * 512 + (q * 16 + slot_c) * 16);
+    _Float16* di = reinterpret_cast<_Float16*>(tile + 1024 + h * 512 + (q * 16 + slot_c) * 16);
+    for (int e = 0; e < 8; ++e) {
+      dr[e] = hr[8 * q + e];
+      di[e] = hi_[8 * q + e];
+    }
+  }
+  for (int part = 0; part < 4; ++part) {
+    uint4* d = reinterpret_cast<uint4*>(tile + 2048 + part * 512 + (16 * h + slot_c) * 16);
+    *d = make_uint4(f8[part][0], f8[part][1], f8[part][2], f8[part][3]);
+  }
+}
+
 template <class Src>
 __global__ void pack_tiles_kernel(Src src, long long ntiles, int ncb, int prec,
                                   float prescale, unsigned char* out) {
-  const bool split = prec == LRS_BF16X2 || prec == LRS_FP16X2;
+  const bool split = prec == LRS_BF16X2 || prec == LRS_FP16X2 || prec == LRS_F16F8;
   const int slots = split ? 32 : 64;
   long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= ntiles * slots) return;
@@ -78,8 +115,10 @@ __global__ void pack_tiles_kernel(Src src, long long ntiles, int ncb, int prec,
   int ch = (int)(tile / ncb);
   int cb = (int)(tile - (long long)ch * ncb);
   int c = cb * 16 + (lane & 15);
-  unsigned char* base = out + tile * (split ? 2048 : 4096);
-  if (prec == LRS_FP64) {
+  unsigned char* base = out + tile * (long long)tile_bytes(prec);
+  if (prec == LRS_F16F8) {
+    pack_f16f8_column(src, c, ch * 32 + 16 * (lane >> 4), prescale, base, lane >> 4, lane & 15);
+  } else if (prec == LRS_FP64) {
     double* t = reinterpret_cast<double*>(base);
     for (int s = 0; s < 4; ++s) {
       double re, im;

@@ -305,6 +305,113 @@ __global__ void induced_out_kernel(ScreenTabs T, const double* X, const double* 
   }
 }
 
+// ---- valence W(x, x') inside r_m (Sec. V.A, Eq. rpa-val): every site is a grid point x with the
+// induced potential v_ind of a uniformly charged sphere of radius R_x (unit charge) on its shells.
+struct ValenceArgs {
+  const double* vind;    // [sum n] induced potential, (L, i) L-major per site (at h_off)
+  const double* centre;  // [nsites][3]
+  double cell[9], inv[9];   // lattice vectors (rows) and the inverse transpose; has_cell = 0: none
+  int has_cell, nsites, nL;
+  double R_x, r_shell, eps_inf, r_m;
+  double* W;             // [nsites][nsites]
+};
+
+__device__ inline void real_ylm_dev(double x, double y, double z, double* Y) {
+  const double pi = 3.14159265358979323846;
+  const double c1 = sqrt(3.0 / (4.0 * pi)), c2 = sqrt(15.0 / (4.0 * pi));
+  const double c20 = sqrt(5.0 / (16.0 * pi));
+  Y[0] = 0.5 / sqrt(pi);
+  Y[1] = c1 * y;
+  Y[2] = c1 * z;
+  Y[3] = c1 * x;
+  Y[4] = c2 * x * y;
+  Y[5] = c2 * y * z;
+  Y[6] = c20 * (3.0 * z * z - 1.0);
+  Y[7] = c2 * x * z;
+  Y[8] = 0.5 * c2 * (x * x - y * y);
+}
+
+// cubic Lagrange interpolation of f (stride `stride`, nr samples at radii r) at x: the four
+// shells nearest to x, clamped at the ends of the grid
+__device__ inline double lagrange4_dev(const double* r, const double* f, int nr, double x) {
+  int i = 0;
+  while (i < nr && r[i] < x) ++i;
+  i = min(max(i - 2, 0), nr - 4);
+  double out = 0.0;
+  for (int a = 0; a < 4; ++a) {
+    double w = 1.0;
+    for (int b = 0; b < 4; ++b)
+      if (b != a) w *= (x - r[i + b]) / (r[i + a] - r[i + b]);
+    out += w * f[i + a];
+  }
+  return out;
+}
+
+__device__ inline double sphere_pot(double r, double R) {
+  return r < R ? (3.0 - r * r / (R * R)) / (2.0 * R) : 1.0 / r;
+}
+
+// W^[a](centre_a + d)
+__device__ double valence_one_way(const ScreenTabs& T, const ValenceArgs& A, int a, double dx,
+                                  double dy, double dz) {
+  const SiteMeta m = T.meta[a];
+  const double r = sqrt(dx * dx + dy * dy + dz * dz);
+  double Y[9];
+  real_ylm_dev(dx / r, dy / r, dz / r, Y);
+  const double* rad = T.radii + m.rad_off;
+  double v = sphere_pot(r, A.R_x);
+  for (int L = 0; L < A.nL; ++L)
+    v += Y[L] * lagrange4_dev(rad, A.vind + m.h_off + (long long)L * m.nrad, m.nrad, r);
+  const double v2 = r < A.r_shell ? 1.0 / A.r_shell : 1.0 / r;
+  return v - (1.0 - 1.0 / A.eps_inf) * v2;
+}
+
+// one thread per (a, b): W[a][b] = (W^[a](x_b) + W^[b](x_a)) / 2 within r_m (the same two terms
+// in both orders, so W is exactly symmetric), the discretisation-sphere average on the
+// diagonal, zero beyond r_m
+__global__ void valence_pairs_kernel(ScreenTabs T, ValenceArgs A) {
+  const int a = blockIdx.y * blockDim.y + threadIdx.y;
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= A.nsites || b >= A.nsites) return;
+  double* out = A.W + (long long)a * A.nsites + b;
+  if (a == b) {
+    // (3 / R^3) int_0^R W_00(r) r^2 dr: the bare sphere 6 / (5 R), the shell's v2 (constant
+    // inside R_S > R), the induced l = 0 part by 8-point Gauss-Legendre on [0, R]
+    const double gx[8] = {-0.9602898564975363, -0.7966664774136267, -0.5255324099163290,
+                          -0.1834346424956498, 0.1834346424956498, 0.5255324099163290,
+                          0.7966664774136267, 0.9602898564975363};
+    const double gw[8] = {0.1012285362903763, 0.2223810344533745, 0.3137066458778873,
+                          0.3626837833783620, 0.3626837833783620, 0.3137066458778873,
+                          0.2223810344533745, 0.1012285362903763};
+    const SiteMeta m = T.meta[a];
+    const double* rad = T.radii + m.rad_off;
+    const double R = A.R_x;
+    double s = 0.0;
+    for (int q = 0; q < 8; ++q) {
+      const double r = 0.5 * R * (gx[q] + 1.0);
+      s += 0.5 * R * gw[q] * r * r * lagrange4_dev(rad, A.vind + m.h_off, m.nrad, r);
+    }
+    const double y00 = 0.5 / sqrt(3.14159265358979323846);
+    *out = 6.0 / (5.0 * R) + 3.0 / (R * R * R) * y00 * s - (1.0 - 1.0 / A.eps_inf) / A.r_shell;
+    return;
+  }
+  double d[3];
+  for (int c = 0; c < 3; ++c) d[c] = A.centre[3 * b + c] - A.centre[3 * a + c];
+  if (A.has_cell) {
+    // nearest periodic image: subtract the rounded fractional coordinates
+    double f[3];
+    for (int c = 0; c < 3; ++c) f[c] = rint(A.inv[3 * c] * d[0] + A.inv[3 * c + 1] * d[1] + A.inv[3 * c + 2] * d[2]);
+    for (int c = 0; c < 3; ++c) d[c] -= f[0] * A.cell[c] + f[1] * A.cell[3 + c] + f[2] * A.cell[6 + c];
+  }
+  const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  if (r > A.r_m) {
+    *out = 0.0;
+    return;
+  }
+  *out = 0.5 * (valence_one_way(T, A, a, d[0], d[1], d[2]) +
+                valence_one_way(T, A, b, -d[0], -d[1], -d[2]));
+}
+
 // ---- ALDA: the LDA exchange-correlation energy per volume, e(n) = n (eps_x + eps_c), with
 // Slater exchange eps_x = -(3/4) (3n/pi)^(1/3) and the Vosko-Wilk-Nusair (1980) paramagnetic
 // correlation (fit to Ceperley-Alder; Hartree units), x = sqrt(r_s), X(x) = x^2 + b x + c
@@ -802,6 +909,70 @@ static hipError_t launch_alda(lrs_ctx* ctx, const double* chi0_ss, const double*
   return hipGetLastError();
 }
 
+// Valence W of the sites as grid points: the induced potential of the sphere's v1 at every site
+// (the induced-potential solve, full response), then the pair kernel.
+// val_work layout: rho [n_total] | v_ind [n_total] | centres [3 nsites]
+static hipError_t launch_valence(lrs_ctx* ctx, const double* chi0_ss, const double* centres,
+                                 const double* cell, double vx, double r_shell, double eps_inf,
+                                 double r_m, double* W_out) {
+  const double pi = 3.14159265358979323846;
+  const double R_x = std::cbrt(3.0 * vx / (4.0 * pi));
+  std::vector<double> v1(ctx->radii.size());
+  for (size_t i = 0; i < v1.size(); ++i) {
+    const double r = ctx->radii[i];
+    const double ve = r < R_x ? (3.0 - r * r / (R_x * R_x)) / (2.0 * R_x) : 1.0 / r;
+    v1[i] = r < r_shell ? ve - 1.0 / r_shell : 0.0;     // v_ext - v2 (zero beyond the shell)
+  }
+  HostTabs H;
+  build_tabs(ctx, H);
+  hipError_t e = ensure_dev(ctx, ctx->val_work, (size_t)(2 * H.n_total + 3 * ctx->nsites) * 8);
+  if (e != hipSuccess) return e;
+  double* rho = (double*)ctx->val_work.p;
+  double* vind = rho + H.n_total;
+  double* cen = vind + H.n_total;
+  e = hipMemcpyAsync(cen, centres, (size_t)3 * ctx->nsites * 8, hipMemcpyHostToDevice, ctx->stream);
+  if (e != hipSuccess) return e;
+  e = launch_induced(ctx, chi0_ss, v1.data(), 0, rho, vind);   // synchronises (host tables)
+  if (e != hipSuccess) return e;
+  DevTabs D;
+  e = upload_tabs(ctx, H, D);
+  if (e != hipSuccess) return e;
+  ValenceArgs A;
+  A.vind = vind;
+  A.centre = cen;
+  A.has_cell = cell != nullptr;
+  for (int i = 0; i < 9; ++i) A.cell[i] = cell ? cell[i] : 0.0;
+  if (cell) {
+    // inverse of the transpose: fractional coordinates f = A^-T d, row c of `inv` gives f_c
+    const double* a = cell;
+    const double det = a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+                       a[2] * (a[3] * a[7] - a[4] * a[6]);
+    // adjugate of A (rows a1, a2, a3): (A^-1)_{ij}; f_c = sum_j (A^-T)_{cj} d_j = sum_j (A^-1)_{jc} d_j
+    double ai[9];
+    ai[0] = (a[4] * a[8] - a[5] * a[7]) / det;
+    ai[1] = (a[2] * a[7] - a[1] * a[8]) / det;
+    ai[2] = (a[1] * a[5] - a[2] * a[4]) / det;
+    ai[3] = (a[5] * a[6] - a[3] * a[8]) / det;
+    ai[4] = (a[0] * a[8] - a[2] * a[6]) / det;
+    ai[5] = (a[2] * a[3] - a[0] * a[5]) / det;
+    ai[6] = (a[3] * a[7] - a[4] * a[6]) / det;
+    ai[7] = (a[1] * a[6] - a[0] * a[7]) / det;
+    ai[8] = (a[0] * a[4] - a[1] * a[3]) / det;
+    for (int c = 0; c < 3; ++c)
+      for (int j = 0; j < 3; ++j) A.inv[3 * c + j] = ai[3 * j + c];
+  }
+  A.nsites = ctx->nsites;
+  A.nL = (ctx->lmax + 1) * (ctx->lmax + 1);
+  A.R_x = R_x;
+  A.r_shell = r_shell;
+  A.eps_inf = eps_inf;
+  A.r_m = r_m;
+  A.W = W_out;
+  const dim3 blk(16, 16), grd((ctx->nsites + 15) / 16, (ctx->nsites + 15) / 16);
+  hipLaunchKernelGGL(valence_pairs_kernel, grd, blk, 0, ctx->stream, D.t, A);
+  return hipGetLastError();
+}
+
 // Host-side check of the solve kernels' limits: n = (lmax+1)^2 n_rad <= 288 basis functions
 // (the Gauss-Jordan kernel's register slots) and at most 256 directions per site (the
 // projection's LDS table).
@@ -908,6 +1079,83 @@ extern "C" lrs_status lrs_induced_potential(lrs_ctx* ctx, const double* chi0_sit
   }
   if (e != hipSuccess) {
     ctx->err = std::string("induced potential: ") + hipGetErrorString(e);
+    return LRS_EDEVICE;
+  }
+  return LRS_OK;
+}
+
+extern "C" lrs_status lrs_valence_W(lrs_ctx* ctx, const double* chi0_sitesite,
+                                    const double* centres_host, const double* cell_host, double vx,
+                                    double r_shell, double eps_inf, double r_m, double* W_out) {
+  if (!ctx) return LRS_EINVAL;
+  ctx->err.clear();
+  if (!ctx->have_sites) {
+    ctx->err = "sites must be set first";
+    return LRS_ESTATE;
+  }
+  if (!chi0_sitesite || !centres_host || !W_out) {
+    ctx->err = "missing argument";
+    return LRS_EINVAL;
+  }
+  for (int i = 0; i < 3 * ctx->nsites; ++i)
+    if (!std::isfinite(centres_host[i])) {
+      ctx->err = "non-finite site centre";
+      return LRS_ENONFINITE;
+    }
+  if (cell_host)
+    for (int i = 0; i < 9; ++i)
+      if (!std::isfinite(cell_host[i])) {
+        ctx->err = "non-finite lattice vector";
+        return LRS_ENONFINITE;
+      }
+  const double R_x = std::cbrt(3.0 * vx / (4.0 * 3.14159265358979323846));
+  if (!(vx > 0) || !std::isfinite(vx) || !(r_shell > R_x) || !std::isfinite(r_shell) ||
+      !(eps_inf >= 1.0) || !std::isfinite(eps_inf) || !(r_m > 0) || !std::isfinite(r_m)) {
+    ctx->err = "need vx > 0, r_shell > R_x = (3 vx / 4 pi)^(1/3), eps_inf >= 1 and r_m > 0";
+    return LRS_EINVAL;
+  }
+  if (cell_host) {
+    const double* a = cell_host;
+    const double det = a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+                       a[2] * (a[3] * a[7] - a[4] * a[6]);
+    if (!(std::fabs(det) > 0)) {
+      ctx->err = "singular lattice";
+      return LRS_EINVAL;
+    }
+  }
+  for (int s = 0; s < ctx->nsites; ++s) {
+    const int nr = ctx->nrad[s];
+    if (nr < 4) {
+      ctx->err = "every site needs at least 4 shells (cubic radial interpolation)";
+      return LRS_EUNSUPPORTED;
+    }
+    if (ctx->radii[ctx->rad_off[s] + nr - 1] < r_m) {
+      ctx->err = "r_m exceeds a site's largest shell radius";
+      return LRS_EINVAL;
+    }
+  }
+  if (!screen_sizes_ok(ctx)) {
+    ctx->err = "a site basis exceeds 288 functions or 256 directions";
+    return LRS_EUNSUPPORTED;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipSetDevice(ctx->device) != hipSuccess ||
+      hipStreamIsCapturing(ctx->stream, &cs) != hipSuccess) {
+    ctx->err = "device";
+    return LRS_EDEVICE;
+  }
+  if (cs != hipStreamCaptureStatusNone) {
+    ctx->err = "the valence assembly copies host tables; it cannot be captured";
+    return LRS_ESTATE;
+  }
+  const hipError_t e = launch_valence(ctx, chi0_sitesite, centres_host, cell_host, vx, r_shell,
+                                      eps_inf, r_m, W_out);
+  if (e == hipErrorOutOfMemory) {
+    ctx->err = "valence workspace";
+    return LRS_ENOMEM;
+  }
+  if (e != hipSuccess) {
+    ctx->err = std::string("valence W: ") + hipGetErrorString(e);
     return LRS_EDEVICE;
   }
   return LRS_OK;

@@ -96,7 +96,8 @@ def test_tiny_fp64_parity(P, tiny_ref):
     assert np.array_equal(g2, g)
 
 
-@pytest.mark.parametrize("prec,tol", [("bf16x2", 1e-4), ("fp32", 1e-5), ("fp16x2", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("bf16x2", 1e-4), ("fp32", 1e-5), ("fp16x2", 1e-5),
+                                      ("f16f8", 1e-4)])
 def test_tiny_reduced_precision(P, tiny_ref, prec, tol):
     w = tiny_ref["w"]
     say("tiny", prec)
@@ -171,7 +172,7 @@ def test_production_fp64_and_bf16_sampled(P, prod):
     cols = _sample(w.ngrid ** 3, 300, rng)
     ref_q = cz.chi0_quad_entries(ps[:, :, rows], pg[:, :, cols], w.nocc, 2, *terms)
     ref_x = cz.chi0_exact_entries(ps[:, :, rows], pg[:, :, cols], w.energies, w.nocc)
-    for prec, tq, tx in [("fp64", 1e-12, 1e-6), ("bf16x2", 1e-4, 1e-4)]:
+    for prec, tq, tx in [("fp64", 1e-12, 1e-6), ("bf16x2", 1e-4, 1e-4), ("f16f8", 1e-4, 1e-4)]:
         g = ctx.chi0(-1, P.COLS_GRID, prec)
         got = g[torch.as_tensor(rows), torch.as_tensor(cols)].cpu().numpy()
         say(f"  grid {prec}: vs quad {rel(got, ref_q):.3e} vs exact {rel(got, ref_x):.3e}")

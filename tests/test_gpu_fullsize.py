@@ -70,7 +70,7 @@ def sampled(F, out):
 
 
 @pytest.mark.parametrize("prec,tq,tx", [("bf16x2", 1e-4, 1e-4), ("fp16x2", 1e-4, 1e-4),
-                                        ("fp64", 1e-12, 1e-6)])
+                                        ("f16f8", 1e-4, 1e-4), ("fp64", 1e-12, 1e-6)])
 def test_grid_launch_sampled(full, prec, tq, tx):
     """The site x grid launch (the benchmark's headline launch), every precision of the
     bench line, with the library's own scale choice equal to the oracle's."""

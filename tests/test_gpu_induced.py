@@ -114,3 +114,49 @@ def test_induced_uneven_sites(P):
         ctx.induced_potential(chi, q=1.0, r_shell=0.0)
     assert e.value.status == P.LRS_EINVAL
     ctx.close()
+
+
+def test_valence_W_vs_oracle(P):
+    """Valence W(x, x') within r_m (Sec. V.A, Eq. rpa-val) on 27 grid-point sites of a 3 x 3 x 3
+    patch of the tiny cell's 16^3 grid (16 shells x 26 directions each, seeded chi0-like
+    blocks), periodic images on: against the oracle element by element (bar 1e-11), for
+    eps_inf 1 and 4; the bare limit (chi0 = 0) gives 1/|x - x'| and 6/(5 R_x) on the diagonal."""
+    from oracle import valence as va
+    from workloads import blocks as bx
+    from workloads import sites as sx
+    a, ng = 10.0, 16
+    h = a / ng
+    idx = np.array([[i, j, k] for i in (15, 0, 1) for j in (15, 0, 1) for k in (15, 0, 1)])
+    centres = idx * h
+    sites = [sx.make_site(c, 16, 26, r_max=2.0, r_min=0.05) for c in centres]
+    blocks, flat = bx.chi0_like_blocks(sites, seed=13)
+    cell = np.eye(3) * a
+    vx = a ** 3 / ng ** 3
+    R_S, r_m = 1.5, 1.5
+    rng = np.random.default_rng(2)
+    psi = torch.as_tensor(rng.normal(size=(1, 4, sum(s.npts for s in sites)))
+                          + 1j * rng.normal(size=(1, 4, sum(s.npts for s in sites))))
+    ctx = P.Context(0)
+    ctx.set_orbitals(np.array([[-1.0, 0.5, 0.9, 1.4]]), 1)
+    ctx.set_sites(sites, psi)
+    chi = torch.as_tensor(flat, device="cuda")
+    for eps_inf in (1.0, 4.0):
+        say(f"valence W: 27 sites, eps_inf {eps_inf}")
+        got = ctx.valence_W(chi, centres, vx, R_S, eps_inf, r_m, cell).cpu().numpy()
+        ref = va.valence_W(blocks, sites, centres, vx, R_S, eps_inf, r_m, cell)
+        e = rel(got, ref)
+        npairs = int((ref != 0).sum()) - len(sites)
+        say(f"  vs oracle {e:.2e} ({npairs} pairs within r_m)")
+        assert e < 1e-11 and np.array_equal(got, got.T) and npairs > 100
+        assert np.array_equal(got == 0, ref == 0)
+    zero = torch.zeros_like(chi)
+    W0 = ctx.valence_W(zero, centres, vx, R_S, 1.0, r_m, cell).cpu().numpy()
+    R_x = (3 * vx / (4 * np.pi)) ** (1 / 3)
+    assert np.abs(np.diag(W0) - 6 / (5 * R_x)).max() < 1e-13 * 6 / (5 * R_x)
+    # sites 0 and 1 (grid indices (15, 15, 15) and (15, 15, 0)) are neighbours through the
+    # cell boundary, one grid step apart
+    assert abs(W0[0, 1] - 1 / h) < 1e-13
+    with pytest.raises(P.LrsError) as e:
+        ctx.valence_W(chi, centres, vx, R_S, 1.0, 2.5, cell)      # r_m beyond the shells
+    assert e.value.status == P.LRS_EINVAL
+    ctx.close()

@@ -257,3 +257,84 @@ def test_regularised_gradients_finite_differences():
             Em[k, b] -= h
             fd = (L_of(Ep, kind) - L_of(Em, kind)) / (2 * h)
             assert abs(fd - dE[k, b]) < 1e-6 * np.abs(dE).max(), (kind, k, b)
+
+
+# ---------------------------------------------------------------- valence W(x, x') in r_m
+from oracle import valence as va  # noqa: E402
+
+
+def test_sphere_potential_and_self_term_by_quadrature():
+    """The uniformly charged sphere's potential against the radial Coulomb integral of its
+    density (adaptive quadrature), and its average over the sphere against 6 / (5 R)."""
+    R = 0.4
+    rho = 3.0 / (4.0 * math.pi * R ** 3)
+    for r in (0.05, 0.2, 0.39, 0.41, 1.3):
+        ref = integrate.quad(lambda s: 4 * math.pi * s * s * rho / max(r, s), 0, R,
+                             points=[min(r, R)], epsabs=0, epsrel=1e-12)[0]
+        assert float(va.sphere_potential(np.array(r), R)) == pytest.approx(ref, rel=1e-10)
+    avg = 3 / R ** 3 * integrate.quad(lambda s: float(va.sphere_potential(np.array(s), R)) * s * s,
+                                      0, R, epsabs=0, epsrel=1e-13)[0]
+    assert avg == pytest.approx(6 / (5 * R), rel=1e-12)
+
+
+def test_lagrange4_exact_for_cubics():
+    rng = np.random.default_rng(3)
+    xs = np.sort(rng.uniform(0.1, 3.0, 12))
+    c = rng.normal(size=4)
+    f = lambda x: c[0] + c[1] * x + c[2] * x ** 2 + c[3] * x ** 3
+    for x in (0.0, 0.05, 0.7, 1.9, 2.999, 3.4):        # inside and extrapolated at both ends
+        assert va.lagrange4(xs, f(xs), x) == pytest.approx(f(x), rel=1e-10, abs=1e-10)
+
+
+def _valence_sites(nsites=8, spacing=0.625, n_rad=16, n_ang=26, seed=2):
+    rng = np.random.default_rng(seed)
+    base = np.array([[i, j, k] for i in range(2) for j in range(2) for k in range(2)], float)
+    centres = base[:nsites] * spacing + rng.uniform(-0.01, 0.01, (nsites, 3))
+    sites = [sx.make_site(c, n_rad, n_ang, r_max=2.0, r_min=0.05) for c in centres]
+    return centres, sites
+
+
+def test_valence_W_bare_limits():
+    """chi0 = 0: W(x, x') is the bare potential of the neighbouring sphere's unit charge,
+    1/|x - x'| (|x - x'| > R_x), reduced by (1 - 1/eps_inf) times the shell's v2 (1/R_S inside
+    the shell); the diagonal is 6/(5 R_x) less the same constant; zero beyond r_m; symmetric."""
+    centres, sites = _valence_sites()
+    zero = [np.zeros((s.npts, s.npts)) for s in sites]
+    vx, R_S = 0.244, 1.5
+    R_x = (3 * vx / (4 * math.pi)) ** (1 / 3)
+    for eps_inf in (1.0, 2.5):
+        W = va.valence_W(zero, sites, centres, vx, R_S, eps_inf, r_m=1.0)
+        c = (1 - 1 / eps_inf) / R_S
+        for a in range(len(sites)):
+            assert W[a, a] == pytest.approx(6 / (5 * R_x) - c, rel=1e-12)
+            for b in range(len(sites)):
+                if a == b:
+                    continue
+                d = np.linalg.norm(centres[b] - centres[a])
+                ref = 1 / d - c if d <= 1.0 else 0.0
+                assert W[a, b] == pytest.approx(ref, rel=1e-12, abs=1e-15)
+        assert np.array_equal(W, W.T)
+
+
+def test_valence_W_periodic_images_and_screening():
+    """Sites across the cell boundary meet through the nearest image; with NSD chi0-like blocks
+    the induced potential lowers W(x, x') below the bare value at every pair within r_m (a
+    positive charge attracts the responding electrons), and the diagonal below 6/(5 R_x)."""
+    from workloads import blocks as bx
+    a = 4.0
+    centres = np.array([[0.2, 0.2, 0.2], [3.8, 0.2, 0.2], [0.2, 3.9, 0.3], [0.9, 0.3, 0.2]])
+    sites = [sx.make_site(c, 16, 26, r_max=2.0, r_min=0.05) for c in centres]
+    blocks, _ = bx.chi0_like_blocks(sites, seed=5)
+    cell = np.eye(3) * a
+    vx, R_S = 0.05, 1.5                 # R_x = 0.23 bohr, below every pair distance
+    R_x = (3 * vx / (4 * math.pi)) ** (1 / 3)
+    W = va.valence_W(blocks, sites, centres, vx, R_S, 1.0, r_m=1.0, cell=cell)
+    zero = [np.zeros_like(b) for b in blocks]
+    W0 = va.valence_W(zero, sites, centres, vx, R_S, 1.0, r_m=1.0, cell=cell)
+    assert W0[0, 1] == pytest.approx(1 / 0.4, rel=1e-12)          # through the x boundary
+    assert W0[0, 2] == pytest.approx(1 / math.sqrt(0.3 ** 2 + 0.1 ** 2), rel=1e-12)
+    assert W0[1, 3] == 0.0                                       # 1.10 bohr > r_m apart
+    pairs = W0 != 0
+    assert np.all(W[pairs] < W0[pairs])
+    assert np.all(np.diag(W) < 6 / (5 * R_x))
+    assert np.array_equal(W, W.T)
