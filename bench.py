@@ -83,6 +83,41 @@ def cpu_factorised(ps_rows, pg_cols, nocc, c, alpha, beta, spin=2):
     return -2.0 * spin / nk ** 2 * out
 
 
+def fft_grid_size(m, over=4):
+    """Smallest 2^a 3^b 5^c >= over * (2 m + 1): the oversampled grid of the FFT route."""
+    n = over * (2 * m + 1)
+    while True:
+        k = n
+        for f in (2, 3, 5):
+            while k % f == 0:
+                k //= f
+        if k == 1:
+            return n
+        n += 1
+
+
+def fft_projection(ctx, bd, coef, pts, psi_direct):
+    """The FFT route of the projection (the same orbitals from an oversampled FFT grid and
+    cubic interpolation) timed once after a warm-up, beside the direct method's result."""
+    import torch
+    cell = np.eye(3) * bd.crystal.a
+    n = fft_grid_size(int(np.abs(bd.gvec).max()))
+    args = (bd.kpts, cell, bd.gvec, coef, bd.crystal.omega, pts, (n, n, n))
+    ctx.project_orbitals_fft(*args)
+    torch.cuda.synchronize()
+    t = time.time()
+    psi = ctx.project_orbitals_fft(*args)
+    torch.cuda.synchronize()
+    ms = (time.time() - t) * 1e3
+    nk_, nb_ = coef.shape[:2]
+    # each axis pass reads and writes the box once (16 bytes per value)
+    moved = 3.0 * 2.0 * 16.0 * n ** 3 * nk_ * nb_
+    return {"call_ms": ms, "grid": [n, n, n], "interpolation": "cubic Lagrange, 4x4x4 nodes",
+            "fft_pass_bytes": moved, "fft_pass_gb_per_s": moved / (ms / 1e3) / 1e9,
+            "max_rel_diff_vs_direct": float((psi - psi_direct).abs().max()
+                                            / psi_direct.abs().max())}
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -373,6 +408,7 @@ def main():
                 "frac_of_fp64_peak": fl / (pms / 1e3) / 1e12 / PEAKS_TFLOPS["fp64"],
                 "rel_err_vs_workload_orbitals":
                     float((psi_p - w.psi_site).abs().max() / w.psi_site.abs().max())}
+        proj["fft"] = fft_projection(ctx, bd, coef, pts, psi_p)
         del psi_p, coef
         log("projection", proj)
     ctx.close()
@@ -479,9 +515,25 @@ def main():
         gotb = gotb.cpu().numpy()
         qb = ctx2.get_quadrature()
         v, bm, bn = ctx2.tuned_variant(prec, P.COLS_GRID)
-        ctx2.close()
         del outb
         torch.cuda.empty_cache()
+        # the projection onto all 87,960 site points, direct and by FFT
+        bproj = None
+        if not args.no_projection:
+            bd = wb.bands
+            coef = torch.stack([c.T for c in bd.coef]).contiguous()
+            gcart = bd.gvec * (2.0 * np.pi / bd.crystal.a)
+            pts = np.concatenate([st.points() for st in wb.sites])
+            ctx2.project_orbitals(bd.kpts, gcart, coef, bd.crystal.omega, pts[:64])
+            torch.cuda.synchronize()
+            tp = time.time()
+            psi_d = ctx2.project_orbitals(bd.kpts, gcart, coef, bd.crystal.omega, pts)
+            torch.cuda.synchronize()
+            bproj = {"points": len(pts), "direct_call_ms": (time.time() - tp) * 1e3,
+                     "fft": fft_projection(ctx2, bd, coef, pts, psi_d)}
+            del psi_d, coef
+            torch.cuda.empty_cache()
+        ctx2.close()
         Kb = wb.nk * wb.nb
         batching = {"workload": "batching", "precision": prec, "sites": len(wb.sites),
                     "rows": nrb, "grid_columns": ncb, "terms": nt,
@@ -489,7 +541,8 @@ def main():
                     "terms_rule_error": terr, "variant": v, "tile": [bm, bn],
                     "call_s": call_s, "kernels_ms": bms,
                     "entries_per_s": nrb * ncb / call_s,
-                    "algorithmic_tflops": nrb * ncb * nt * (8.0 * Kb + 4.0) / call_s / 1e12}
+                    "algorithmic_tflops": nrb * ncb * nt * (8.0 * Kb + 4.0) / call_s / 1e12,
+                    "projection": bproj}
         if not args.no_cpu:
             tb_ = cz.terms_for(wb.energies, wb.nocc, "time", nt, qb["scale"])
             refb = cz.chi0_quad_entries(bps, bpg, wb.nocc, 2, *tb_)

@@ -204,6 +204,38 @@ lrs_status lrs_project_orbitals(lrs_ctx* ctx, int nk, int nb, int npw, const dou
                                 const double* gvec_host, const void* coef, double omega,
                                 int npts, const double* points_host, void* psi_out);
 
+/* The same orbitals by the FFT route of that section: per band, C_bk(G) placed at its Miller
+ * indices m mod N in a zeroed N0 x N1 x N2 box and inverse-transformed (unnormalised, a
+ * hand-written mixed-radix FFT), u_bk(x_j) = sum_G C exp(i G.x_j) on the grid
+ * x_j = sum_d (j_d / N_d) a_d; then cubic Lagrange interpolation at each point over the 4 x 4 x 4
+ * grid nodes around it (the interpolants computed once per point, reused for every band and k)
+ * and the Bloch phase: psi_bk(r) = exp(i k.r) u_bk(r) / sqrt(Omega).  The interpolation error of
+ * a plane wave with phase step theta per grid spacing is of order theta^4 / 40 per dimension, so
+ * the grid should oversample the plane-wave sphere (N_d of about 4 (2 max|m_d| + 1) for 10^-3 on
+ * the largest G).
+ *   cell_host   float64 [3][3], lattice vectors a_d as rows (bohr); |det| must equal omega
+ *   gidx_host   int32 [npw][3], Miller indices m of the plane waves (G = sum_d m_d b_d)
+ *   nfft_host   int32 [3], the FFT grid N_d: 2^a 3^b 5^c, at most 128, N_d > 2 max |m_d|
+ *   the other arguments as lrs_project_orbitals.
+ * LRS_EUNSUPPORTED for a grid size outside those; synchronises (host tables); LRS_ESTATE under
+ * stream capture. */
+lrs_status lrs_project_orbitals_fft(lrs_ctx* ctx, int nk, int nb, int npw, const double* kpts_host,
+                                   const double* cell_host, const int* gidx_host, const void* coef,
+                                   double omega, const int* nfft_host, int npts,
+                                   const double* points_host, void* psi_out);
+
+/* lrs_set_orbitals from plane-wave coefficients: the grid orbitals are made on the device by
+ * the FFT of lrs_project_orbitals_fft on the ngrid_host[0] x [1] x [2] grid (C order, j2
+ * fastest; x_j = sum_d (j_d / N_d) a_d) with the Bloch phase, then packed as by
+ * lrs_set_orbitals with grid_dV = omega / (N0 N1 N2).  coef complex128 [nk][nb][npw] on the
+ * device; the other arguments as lrs_set_orbitals and lrs_project_orbitals_fft.  Allocates the
+ * grid orbitals for the call (nk nb N0 N1 N2 x 16 bytes) and synchronises. */
+lrs_status lrs_set_orbitals_pw(lrs_ctx* ctx, int nk, int nb, int nocc, int spin_factor,
+                               const double* energies_host, double mu, double delta,
+                               const double* kpts_host, const double* cell_host,
+                               const int* gidx_host, const void* coef, int npw, double omega,
+                               const int* ngrid_host);
+
 /* chi0 for one site (site >= 0) or all sites concatenated (site = -1), in precision prec.
  *   LRS_COLS_GRID: chi0_out float64 [rows][ngrid], rows = npts of the site (or all sites).
  *   LRS_COLS_SITE: chi0_out float64 site blocks [npts_s][npts_s], concatenated over sites.

@@ -54,6 +54,8 @@ SIGNATURES = [
     ("lrs_valence_W", _I, [_P, _P, _P, _P, _D, _D, _D, _D, _P]),
     ("lrs_make_quadrature_iw", _I, [_P, _I, _D, _D]),
     ("lrs_make_quadrature_tol", _I, [_P, _D, _I, _I, _P, _P]),
+    ("lrs_project_orbitals_fft", _I, [_P, _I, _I, _I, _P, _P, _P, _P, _D, _P, _I, _P, _P]),
+    ("lrs_set_orbitals_pw", _I, [_P, _I, _I, _I, _I, _P, _D, _D, _P, _P, _P, _P, _I, _D, _P]),
     ("lrs_last_kernel_ms", _D, [_P]),
     ("lrs_release_graphs", _I, [_P]),
 ]
@@ -329,6 +331,39 @@ class Context:
     def release_graphs(self):
         """Unpins the context after the graphs that captured its calls are gone."""
         self._check(lib.lrs_release_graphs(self.h))
+
+    def project_orbitals_fft(self, kpts, cell, gidx, coef, omega, points, nfft):
+        """Orbitals at `points` by the FFT route: `cell` [3, 3] lattice vectors (rows), `gidx`
+        [npw, 3] Miller indices, `coef` complex128 [nk, nb, npw], FFT grid `nfft` (3 sizes);
+        complex128 [nk, nb, npts]."""
+        kp = _host(kpts, np.float64).reshape(-1, 3)
+        cl = _host(cell, np.float64).reshape(3, 3)
+        gi = _host(gidx, np.int32).reshape(-1, 3)
+        pt = _host(points, np.float64).reshape(-1, 3)
+        nf = _host(nfft, np.int32).reshape(3)
+        c = _dev(coef, torch.complex128, self.device)
+        nk, nb, npw = c.shape
+        out = torch.empty((nk, nb, pt.shape[0]), dtype=torch.complex128, device=self.device)
+        self._check(lib.lrs_project_orbitals_fft(self.h, nk, nb, npw, _ptr(kp), _ptr(cl), _ptr(gi),
+                                                 _ptr(c), float(omega), _ptr(nf), pt.shape[0],
+                                                 _ptr(pt), _ptr(out)))
+        return out
+
+    def set_orbitals_pw(self, energies, nocc, kpts, cell, gidx, coef, omega, ngrid, spin=2,
+                        mu=float("nan"), delta=0.0):
+        """set_orbitals with the grid orbitals made by FFT from plane-wave coefficients `coef`
+        complex128 [nk, nb, npw] on the ngrid[0] x ngrid[1] x ngrid[2] grid."""
+        E = _host(energies, np.float64)
+        kp = _host(kpts, np.float64).reshape(-1, 3)
+        cl = _host(cell, np.float64).reshape(3, 3)
+        gi = _host(gidx, np.int32).reshape(-1, 3)
+        ng = _host(ngrid, np.int32).reshape(3)
+        c = _dev(coef, torch.complex128, self.device)
+        nk, nb, npw = c.shape
+        self.orb_version += 1
+        self._check(lib.lrs_set_orbitals_pw(self.h, nk, nb, nocc, spin, _ptr(E), mu, delta, _ptr(kp),
+                                            _ptr(cl), _ptr(gi), _ptr(c), npw, float(omega), _ptr(ng)))
+        self.nk, self.nb, self.nocc, self.ngrid = nk, nb, nocc, int(np.prod(ng))
 
     def tune(self, prec):
         if isinstance(prec, str):

@@ -593,6 +593,7 @@ void lrs_destroy(lrs_ctx* ctx) {
   release(ctx, ctx->work);
   release(ctx, ctx->adj_work);
   release(ctx, ctx->val_work);
+  release(ctx, ctx->fft_work);
   release(ctx, ctx->a_tiles);
   release(ctx, ctx->park);
   release(ctx, ctx->xcd_sync);

@@ -190,7 +190,7 @@ struct lrs_ctx {
   int tuned_variant[lrs::kNumPrec][2] = {{-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}};
 
   // screening state
-  lrs::DevBuf W_last, rho_last, screen_tab, work, adj_work, val_work;
+  lrs::DevBuf W_last, rho_last, screen_tab, work, adj_work, val_work, fft_work;
   bool have_W = false, have_rho = false;
 
   // timing

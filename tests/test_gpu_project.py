@@ -116,3 +116,88 @@ def test_projection_edge_cases_and_errors(P):
         ctx.project_orbitals(k, g, coef, 1.0, np.full((1, 3), np.nan))
     assert e.value.status == P.LRS_ENONFINITE
     ctx.close()
+
+
+# ------------------------------------------------------------------------- the FFT route
+def _fft_size(m, over=4):
+    """Smallest 2^a 3^b 5^c >= over * (2 m + 1) (the oversampled grid of the FFT route)."""
+    n = over * (2 * m + 1)
+    while True:
+        k = n
+        for f in (2, 3, 5):
+            while k % f == 0:
+                k //= f
+        if k == 1:
+            return n
+        n += 1
+
+
+def test_fft_projection_tiny_vs_oracle(P):
+    """Tiny workload (Gamma, 128 bands, 251 plane waves, 208 site points) on a 32^3 grid: the
+    library's FFT route against the oracle's (same grid, numpy FFT, the same cubic
+    interpolation) element by element (1e-12), and against the direct sum within the derived
+    interpolation bound of each band; at the grid's own points it is exact (1e-12)."""
+    w = workload("tiny", with_grid=False)
+    coef, kpts, gcart, omega = pw_inputs(w)
+    bd = w.bands
+    cell = np.eye(3) * bd.crystal.a
+    gidx = bd.gvec
+    N = _fft_size(int(np.abs(gidx).max()))
+    pts = np.concatenate([s.points() for s in w.sites])
+    say(f"FFT projection tiny: grid {N}^3, {coef.shape[1]} bands, {len(pts)} points")
+    ctx = P.Context(0)
+    got = ctx.project_orbitals_fft(kpts, cell, gidx, coef.cuda(), omega, pts, (N, N, N)).cpu().numpy()
+    ref = pj.project_fft(coef.numpy()[:, :16], kpts, cell, gidx, pts, omega, (N, N, N))
+    e = rel(got[:, :16], ref)
+    direct = pj.project(coef.numpy(), kpts, gcart, pts, omega)
+    bound = pj.interpolation_bound(coef.numpy()[0], gidx, (N, N, N), omega)
+    err_b = np.abs(got[0] - direct[0]).max(1)
+    say(f"  vs oracle FFT route {e:.2e}; vs direct max {err_b.max():.2e} "
+        f"(bound {bound.max():.2e}); worst ratio {(err_b / bound).max():.2f}")
+    assert e < 1e-12 and np.all(err_b <= bound)
+    gp = (np.random.default_rng(3).integers(0, N, size=(40, 3)) / N) @ cell
+    g_fft = ctx.project_orbitals_fft(kpts, cell, gidx, coef.cuda(), omega, gp, (N, N, N))
+    g_dir = pj.project(coef.numpy(), kpts, gcart, gp, omega)
+    assert rel(g_fft.cpu().numpy(), g_dir) < 1e-12
+    ctx.close()
+
+
+def test_fft_projection_production_within_bound(P):
+    """Production workload (2x2x2 k, 576 bands, 2007 plane waves, 2 sites of 800 points): the
+    FFT route against the direct sum within each band's derived interpolation bound, and the
+    FFT of the grid itself (lrs_set_orbitals_pw) against the workload's grid orbitals (numpy
+    FFT) with chi0 on the grid from either equal to rounding."""
+    w = workload("production")
+    coef, kpts, gcart, omega = pw_inputs(w)
+    bd = w.bands
+    cell = np.eye(3) * bd.crystal.a
+    gidx = bd.gvec
+    N = _fft_size(int(np.abs(gidx).max()))
+    pts = np.concatenate([s.points() for s in w.sites])
+    say(f"FFT projection production: grid {N}^3, {len(pts)} points")
+    ctx = P.Context(0)
+    got = ctx.project_orbitals_fft(kpts, cell, gidx, coef.cuda(), omega, pts, (N, N, N)).cpu().numpy()
+    direct = pj.project(coef.numpy(), kpts, gcart, pts, omega)
+    worst = 0.0
+    for k in range(coef.shape[0]):
+        bound = pj.interpolation_bound(coef.numpy()[k], gidx, (N, N, N), omega)
+        err_b = np.abs(got[k] - direct[k]).max(1)
+        assert np.all(err_b <= bound)
+        worst = max(worst, (err_b / bound).max())
+    say(f"  vs direct {rel(got, direct):.2e}; worst error / bound {worst:.2f}")
+    # the grid orbitals by FFT in the library, then chi0 on the grid both ways
+    n = w.n_terms
+    ng = w.ngrid
+    ctx.set_orbitals_pw(w.energies, w.nocc, kpts, cell, gidx, coef.cuda(), omega, (ng, ng, ng))
+    ctx.set_sites(w.sites, w.psi_site)
+    ctx.make_quadrature(P.QUAD_TIME, n, 0.0)
+    a = ctx.chi0(-1, P.COLS_GRID, P.FP64).cpu().numpy()
+    ctx2 = P.Context(0)
+    ctx2.set_orbitals(w.energies, w.nocc, w.psi_grid, w.grid_dV)
+    ctx2.set_sites(w.sites, w.psi_site)
+    ctx2.make_quadrature(P.QUAD_TIME, n, 0.0)
+    b = ctx2.chi0(-1, P.COLS_GRID, P.FP64).cpu().numpy()
+    say(f"  chi0 from PW-coefficient grid orbitals vs the workload's: {rel(a, b):.2e}")
+    assert rel(a, b) < 1e-12
+    ctx.close()
+    ctx2.close()

@@ -410,6 +410,54 @@ def test_projection_bloch_and_parseval():
     assert np.abs(norm - 1.0).max() < 1e-12
 
 
+def test_fft_route_exact_at_grid_points_and_cubic_weights():
+    """The FFT route at the FFT grid's own points (weights 0, 1, 0, 0) equals the direct phase
+    matrix sum to rounding, on a sheared (non-orthogonal) cell and off Gamma; the Lagrange
+    weights sum to one and reproduce t, t^2, t^3."""
+    rng = np.random.default_rng(41)
+    cell = np.array([[6.0, 0.0, 0.0], [1.5, 5.5, 0.0], [0.5, -1.0, 6.5]])
+    B = 2 * np.pi * np.linalg.inv(cell).T                      # reciprocal vectors (rows)
+    n = np.stack(np.meshgrid(*[np.arange(-2, 3)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    gvec = n @ B
+    coef = rng.normal(size=(2, 2, len(n))) + 1j * rng.normal(size=(2, 2, len(n)))
+    kpts = np.array([[0.0, 0.0, 0.0], [0.25, -0.5, 0.125]]) @ B
+    N = (10, 12, 9)
+    j = rng.integers(0, 40, size=(15, 3))
+    pts = (j / np.array(N)) @ cell
+    omega = abs(np.linalg.det(cell))
+    f = pj.project_fft(coef, kpts, cell, n, pts, omega, N)
+    d = pj.project(coef, kpts, gvec, pts, omega)
+    assert np.abs(f - d).max() < 1e-12 * np.abs(d).max()
+    for t in (0.0, 0.3, 0.77):
+        w = pj.lagrange_cubic(t)
+        nodes = np.array([-1.0, 0.0, 1.0, 2.0])
+        for p in range(4):
+            assert abs((w * nodes ** p).sum() - t ** p) < 1e-14
+
+
+def test_fft_route_within_derived_interpolation_bound():
+    """At random points the FFT route differs from the direct sum by no more than the derived
+    bound of the cubic tensor-product interpolation (oracle.project.interpolation_bound), the
+    bound is tight within a factor of 30, and the error falls at least tenfold when the grid
+    is oversampled twice as much (fourth-order interpolation)."""
+    rng = np.random.default_rng(42)
+    a, nmax = 7.0, 3
+    n, gvec, coef = _random_pw(rng, a, nmax, nb=2, nk=1)
+    cell = np.eye(3) * a
+    k = np.array([[0.1, 0.2, -0.3]])
+    pts = rng.uniform(-2, 9, size=(24, 3))
+    d = pj.project(coef, k, gvec, pts, a ** 3)
+    errs = []
+    for N in (28, 56):
+        f = pj.project_fft(coef, k, cell, n, pts, a ** 3, (N, N, N))
+        for b in range(2):
+            e = np.abs(f[0, b] - d[0, b]).max()
+            bound = pj.interpolation_bound(coef[0, b], n, (N, N, N), a ** 3)
+            assert e <= bound and bound < 30 * e
+        errs.append(np.abs(f - d).max())
+    assert errs[1] < errs[0] / 10
+
+
 def test_projection_explicit_loops():
     """Two bands, a handful of plane waves and points, by explicit loops over G."""
     import cmath
