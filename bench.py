@@ -185,6 +185,9 @@ def main():
     ap.add_argument("--omega", type=float, default=0.1,
                     help="imaginary frequency (Ha) of the chi0(i omega) launch run after the steps")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--steps-only", action="store_true",
+                    help="only the warm-up and timed steps and the JSON line: no CPU legs, other "
+                         "precisions, checks or side workloads (for profiler runs)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -195,6 +198,9 @@ def main():
         return 2
     if args.copy_mib:
         return copy_calibration(args.copy_mib)
+    if args.steps_only:
+        args.no_cpu = args.no_fp64 = args.no_fp16 = True
+        args.no_projection = args.no_batching = True
 
     import torch
     import paper_2005_07834_amd as P
@@ -307,10 +313,12 @@ def main():
     # statement), the split BF16 and FP16 paths, FP32
     paths, got_p = {}, {}
     others = [x for x in ("fp64", "bf16x2", "fp16x2", "f16f8", "fp32") if x != prec]
-    if args.no_fp64:
+    if args.no_fp64 and "fp64" in others:
         others.remove("fp64")
     if args.no_fp16 and "fp16x2" in others:
         others.remove("fp16x2")
+    if args.steps_only:
+        others = []
     for p in others:
         ctx.make_quadrature(P.QUAD_TIME, w.n_terms, 0.0)
         ctx.chi0(-1, P.COLS_GRID, p, out=out_grid)
@@ -354,39 +362,43 @@ def main():
         del dE64, dpsi64
         log("adjoint", adjoint)
     comp.pop("adjoint", None)
-    # the per-site solves beside W (ALDA W, induced potential of a spherical perturbation) on
-    # this workload's site block, per call on the library stream
-    ctx.make_quadrature(P.QUAD_TIME, w.n_terms, 0.0)
-    chi_ss = ctx.chi0(-1, P.COLS_SITE, prec)
-    dens = valence_density(w.psi_site, w.nocc)
+    solves, iw, got_iw = None, None, None
+    if not args.steps_only:
+        # the per-site solves beside W (ALDA W, induced potential of a spherical perturbation) on
+        # this workload's site block, per call on the library stream
+        ctx.make_quadrature(P.QUAD_TIME, w.n_terms, 0.0)
+        chi_ss = ctx.chi0(-1, P.COLS_SITE, prec)
+        dens = valence_density(w.psi_site, w.nocc)
 
-    def per_call_ms(fn, reps=10):
-        fn()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
+        def per_call_ms(fn, reps=10):
             fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
 
-    solves = {"sites": len(w.sites), "basis": [9 * st.n_rad for st in w.sites],
-              "screen_W_ms": per_call_ms(lambda: ctx.screen_W(chi_ss)),
-              "screen_W_alda_ms": per_call_ms(lambda: ctx.screen_W_alda(chi_ss, dens)),
-              "induced_ms": per_call_ms(lambda: ctx.induced_potential(chi_ss, q=1.0, r_shell=1.5)),
-              "induced_l0_ms": per_call_ms(lambda: ctx.induced_potential(chi_ss, q=1.0, r_shell=1.5,
-                                                                         l0_only=True))}
-    del chi_ss
-    log("site solves", solves)
-    # chi0 at imaginary frequency i omega: the same site x grid launch with complex term
-    # coefficients, once
-    ctx.make_quadrature_iw(w.n_terms, 0.0, args.omega)
-    ctx.chi0(-1, P.COLS_GRID, prec, out=out_grid)
-    iw = {"omega": args.omega, "terms": w.n_terms, "precision": prec,
-          "kernel_ms": ctx.last_kernel_ms(), "scale": ctx.get_quadrature()["scale"]}
-    iw["vs_static_kernel"] = iw["kernel_ms"] / kern_ms
-    got_iw = out_grid[torch.as_tensor(rows, device=dev), torch.as_tensor(cols, device=dev)].cpu().numpy()
-    log(f"chi0(i omega) kernel {iw['kernel_ms']:.1f} ms")
+        def induced(l0):
+            return ctx.induced_potential(chi_ss, q=1.0, r_shell=1.5, l0_only=l0)
+        solves = {"sites": len(w.sites), "basis": [9 * st.n_rad for st in w.sites],
+                  "screen_W_ms": per_call_ms(lambda: ctx.screen_W(chi_ss)),
+                  "screen_W_alda_ms": per_call_ms(lambda: ctx.screen_W_alda(chi_ss, dens)),
+                  "induced_ms": per_call_ms(lambda: induced(False)),
+                  "induced_l0_ms": per_call_ms(lambda: induced(True))}
+        del chi_ss
+        log("site solves", solves)
+        # chi0 at imaginary frequency i omega: the same site x grid launch with complex term
+        # coefficients, once
+        ctx.make_quadrature_iw(w.n_terms, 0.0, args.omega)
+        ctx.chi0(-1, P.COLS_GRID, prec, out=out_grid)
+        iw = {"omega": args.omega, "terms": w.n_terms, "precision": prec,
+              "kernel_ms": ctx.last_kernel_ms(), "scale": ctx.get_quadrature()["scale"]}
+        iw["vs_static_kernel"] = iw["kernel_ms"] / kern_ms
+        got_iw = out_grid[torch.as_tensor(rows, device=dev),
+                          torch.as_tensor(cols, device=dev)].cpu().numpy()
+        log(f"chi0(i omega) kernel {iw['kernel_ms']:.1f} ms")
     # the projection of the plane-wave orbitals onto the site points (the step before the
     # packing), once, outside the timed steps
     proj = None
@@ -411,6 +423,11 @@ def main():
         proj["fft"] = fft_projection(ctx, bd, coef, pts, psi_p)
         del psi_p, coef
         log("projection", proj)
+    # the sustained matrix-core rate of this precision's instruction mix (no memory traffic):
+    # the measured denominator of the executed rate, beside the datasheet peak
+    _, ms0 = ctx.mfma_rate(prec, 2000)
+    sustained, sus_ms = ctx.mfma_rate(prec, max(2000, int(2000 * 300.0 / max(ms0, 1e-3))))
+    log(f"sustained matrix-core rate ({prec} mix): {sustained:.0f} TFLOP/s over {sus_ms:.0f} ms")
     ctx.close()
     del out_grid
     torch.cuda.empty_cache()
@@ -576,6 +593,8 @@ def main():
                      "traffic_gb_per_s": traffic / (kern_ms / 1e3) / 1e9 if traffic else None,
                      "executed_mfma_tflops_equiv": achieved * exec_factor,
                      "executed_frac": achieved * exec_factor / peak,
+                     "sustained_mfma_tflops_equiv": sustained,
+                     "executed_frac_of_sustained": achieved * exec_factor / sustained,
                      "kernel": "chi0_kernel (site x grid)", "kernel_ms": kern_ms,
                      "flop_per_entry": flop_per_entry,
                      "mfma_busy": ctr.get("mfma_busy_frac") if ctr else None},

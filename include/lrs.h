@@ -86,7 +86,10 @@ const char* lrs_version(void);
 
 /* Creates a context on HIP device `device`, enqueuing on `hip_stream` (a hipStream_t;
  * NULL = the legacy default stream).  Fails with LRS_EDEVICE if the device is not
- * gfx950 or cannot be initialised.  *ctx is set to NULL on failure. */
+ * gfx950 or cannot be initialised.  *ctx is set to NULL on failure.  If the environment
+ * variable LRS_MAX_BYTES holds a byte count when the context is created, the context's own
+ * device allocations are kept at or below it: a call that would pass it fails with
+ * LRS_ENOMEM and leaves the context usable (caller-owned buffers do not count). */
 lrs_status lrs_create(lrs_ctx** ctx, int device, void* hip_stream);
 
 /* Synchronises the context's stream and frees every device buffer the context owns. */
@@ -387,6 +390,20 @@ lrs_status lrs_tuned_variant(const lrs_ctx* ctx, int prec, int cols, int* varian
 /* Duration in milliseconds of the main kernel of the last lrs_compute_chi0 call, measured
  * with HIP events on the context's stream (synchronises).  -1 if none. */
 double lrs_last_kernel_ms(lrs_ctx* ctx);
+
+/* Sustained matrix-core rate of the instruction mix the chi0 kernel of precision `prec`
+ * issues (FP64 and FP32: 16x16x4 instructions; BF16X2 and FP16X2: 32x32x16; F16F8: two
+ * 32x32x16 fp16 instructions per scaled 32x32x64 fp8 instruction), measured by one launch of
+ * one 256-thread workgroup per CU (one wave per SIMD, as the chi0 kernel runs) that issues
+ * `iters` rounds of independent instructions and touches memory only to store one value per
+ * thread.  *tflops_host: flops per second / 1e12 at the instruction's own rate, an fp8
+ * instruction counted as the two fp16 instructions of equal matrix-core time (the unit of
+ * the 2.5 PFLOP/s dense 16-bit peak); *ms_host (may be NULL): the launch's duration.  This
+ * is the measured denominator for the chi0 kernel's executed rate; it is not part of the
+ * method.  Synchronises the stream; LRS_ESTATE under capture; LRS_EINVAL for iters <= 0 or
+ * a bad precision. */
+lrs_status lrs_mfma_rate(lrs_ctx* ctx, int prec, long long iters, double* tflops_host,
+                         double* ms_host);
 
 #ifdef __cplusplus
 }

@@ -58,6 +58,7 @@ SIGNATURES = [
     ("lrs_set_orbitals_pw", _I, [_P, _I, _I, _I, _I, _P, _D, _D, _P, _P, _P, _P, _I, _D, _P]),
     ("lrs_last_kernel_ms", _D, [_P]),
     ("lrs_release_graphs", _I, [_P]),
+    ("lrs_mfma_rate", _I, [_P, _I, C.c_longlong, _P, _P]),
 ]
 
 
@@ -382,6 +383,14 @@ class Context:
     def last_kernel_ms(self):
         return float(lib.lrs_last_kernel_ms(self.h))
 
+    def mfma_rate(self, prec, iters):
+        """Sustained matrix-core rate of prec's chi0 instruction mix: (TFLOP/s, ms)."""
+        p = PREC_NAMES[prec] if isinstance(prec, str) else prec
+        t = np.zeros(1)
+        ms = np.zeros(1)
+        self._check(lib.lrs_mfma_rate(self.h, p, int(iters), _ptr(t), _ptr(ms)))
+        return float(t[0]), float(ms[0])
+
 
 class Chi0Fn(torch.autograd.Function):
     """chi0 on the site x site blocks as a differentiable function of the band energies and
@@ -393,10 +402,13 @@ class Chi0Fn(torch.autograd.Function):
     frequency i omega (the imaginary-time terms with complex coefficients).  The backward pass
     runs the library's adjoint
     (Green's functions recomputed per term; split products when ``prec`` is BF16X2, FP64
-    otherwise) and returns dL/de [nk, nb] and dL/dpsi_site (complex, dL/dRe + i dL/dIm).  The
-    nodes and mu are held fixed: pass ``scale > 0`` so the node set does not depend on the
-    energies.  If the context was given other inputs since the forward pass, the backward pass
-    sets the forward's inputs again first.
+    otherwise) and returns dL/de [nk, nb] and dL/dpsi_site (complex, dL/dRe + i dL/dIm); dL/de
+    is None when the energies were not a tensor or do not require a gradient.  The nodes are held
+    fixed: pass ``scale > 0`` so the node set does not depend on the energies.  mu is the
+    mid-gap value of the energies given to each forward pass; it cancels in the imaginary-time
+    rule (and its frequency-rule counterpart), so no gradient flows through it.  If the context
+    was given other inputs since the forward pass, the backward pass sets the forward's inputs
+    again first.
     """
 
     @staticmethod
@@ -422,8 +434,8 @@ class Chi0Fn(torch.autograd.Function):
         fctx.prec = BF16X2 if p == BF16X2 else FP64
         fctx.nextra = len(opt)
         fctx.version = lctx.orb_version
-        fctx.e_like = (energies.device, energies.dtype) if isinstance(energies, torch.Tensor) \
-            else (torch.device("cpu"), torch.float64)
+        fctx.e_like = (energies.device, energies.dtype) \
+            if isinstance(energies, torch.Tensor) else None
         return out
 
     @staticmethod
@@ -433,7 +445,13 @@ class Chi0Fn(torch.autograd.Function):
             Chi0Fn._setup(lctx, *fctx.args)
             fctx.version = lctx.orb_version
         dE, dpsi = lctx.chi0_backward(g, fctx.prec)
-        return (dE.to(device=fctx.e_like[0], dtype=fctx.e_like[1]), dpsi,
+        if fctx.e_like is None or not fctx.needs_input_grad[0]:
+            dE = None
+        else:
+            dE = dE.to(device=fctx.e_like[0], dtype=fctx.e_like[1])
+        if not fctx.needs_input_grad[1]:
+            dpsi = None
+        return (dE, dpsi,
                 None, None, None, None, None) + (None,) * fctx.nextra
 
 

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(os.path.dirname(HERE), "_build", "obj")
 LIB = os.path.join(HERE, "liblrs.so")
 SOURCES = ["lrs_api.cpp", "quadrature.cpp", "pack.hip", "chi0.hip", "screen.hip", "adjoint.hip",
-           "project.hip", "fft.hip"]
+           "project.hip", "fft.hip", "peak.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -307,12 +307,20 @@ lrs_status get_plan(lrs_ctx* ctx, int site, int cols, int prec, int variant, int
   p.batches.push_back(cur);
   // 2. tiles in 2-D blocks: the workgroups of one XCD run 32 consecutive tiles of the list
   //    at a time and the whole grid runs 256, so the list goes in 16 x 16 blocks of
-  //    (row tile, column tile), each made of eight 4 x 8 blocks: the concurrent tiles of an
-  //    XCD then share 4 A and 8 B panels in its L2, and those of the grid 16 + 16 in the
-  //    memory-side cache, instead of one row against hundreds of columns.
+  //    (row tile, column tile), each made of eight BR x BC blocks (BR BC = 32): the
+  //    concurrent tiles of an XCD then share BR A and BC B panels in its L2, and those of
+  //    the grid 16 + 16 in the memory-side cache, instead of one row against hundreds of
+  //    columns.  A panel chunk is bm rows and a B one bn columns, so BR is the power of two
+  //    that minimises the bytes BR bm + BC bn an XCD fetches per chunk step (4 x 8 for square
+  //    tiles, 8 x 4 for 128 x 192).
   std::vector<TileDesc> tiles;
+  int BR = 4;
+  for (int br = 1; br <= 32; br *= 2)
+    if ((long long)br * sh.bm + (32 / br) * sh.bn < (long long)BR * sh.bm + (32 / BR) * sh.bn)
+      BR = br;
+  const int BC = 32 / BR;
   auto emit_blocked = [&](int nr, int nc, auto&& make) {
-    constexpr int SR = 16, SC = 16, BR = 4, BC = 8;
+    constexpr int SR = 16, SC = 16;
     for (int R0 = 0; R0 < nr; R0 += SR)
       for (int C0 = 0; C0 < nc; C0 += SC) {
         const int R1 = std::min(nr, R0 + SR), C1 = std::min(nc, C0 + SC);
@@ -594,6 +602,7 @@ void lrs_destroy(lrs_ctx* ctx) {
   release(ctx, ctx->adj_work);
   release(ctx, ctx->val_work);
   release(ctx, ctx->fft_work);
+  release(ctx, ctx->probe);
   release(ctx, ctx->a_tiles);
   release(ctx, ctx->park);
   release(ctx, ctx->xcd_sync);

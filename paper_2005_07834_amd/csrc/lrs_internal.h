@@ -40,16 +40,20 @@ inline int site_block_ld(int n, int mode) {
   return mode == 1 ? (n + kAdjAlign - 1) / kAdjAlign * kAdjAlign : n;
 }
 // K values per chunk and bytes per fragment tile (16 rows x chunk x planes)
-__host__ __device__ inline int chunk_of(int prec) { return prec == LRS_FP32 || prec == LRS_F16F8 ? 32 : 16; }
-__host__ __device__ inline int tile_bytes(int prec) { return is_split(prec) ? 2048 : 4096; }
-// F16F8 fragment tiles (16 rows x 32 K, 4 KiB; a 32-row block is two consecutive tiles):
-//   [0, 2048)    fp16 hi: planes re (K 0-15), re (K 16-31), im (K 0-15), im (K 16-31), 512 B
-//                each, slot s holding row s%16 and K 8 (s/16) + e, e = 0..7 (16 B)
-//   [2048, 4096) fp8 (e4m3) planes re part 0, re part 1, im part 0, im part 1, 512 B each, slot
-//                s holding row s%16 and K 16 (s/16) + j, j = 0..15 (16 B); part 0 is the scale
-//                block 0 of the matrix-core instruction, part 1 block 1.  The row (site) operand
-//                stores hi * 2^7 in part 0 and lo * 2^18 in part 1; the column operand the
-//                other way round, so that the blocks multiply hi * lo and lo * hi.
+__host__ __device__ inline int chunk_of(int prec) { return prec == LRS_FP32 ? 32 : 16; }
+__host__ __device__ inline int tile_bytes(int prec) {
+  return is_split(prec) || prec == LRS_F16F8 ? 2048 : 4096;
+}
+// F16F8 fragment tiles (16 rows x 16 K, 2 KiB; a 32-row block is two consecutive tiles):
+//   [0, 1024)    fp16 hi: planes re, im, 512 B each, slot s holding row s%16 and
+//                K 8 (s/16) + e, e = 0..7 (16 B)
+//   [1024, 2048) fp8 (e4m3) planes re part 0, re part 1, im part 0, im part 1, 256 B each,
+//                row r at 16 r holding K 0..15 (16 B).  The fp8 fragment of a lane is one
+//                component's part 0 (its scale block 0 of the matrix-core instruction) and
+//                part 1 (block 1): re in lanes 0-31, im in lanes 32-63, so that one instruction
+//                takes the cross terms of both products of a complex multiply-add.  The row
+//                (site) operand stores hi * 2^7 in part 0 and lo * 2^18 in part 1; the column
+//                operand the other way round, so that the blocks multiply hi * lo and lo * hi.
 constexpr int kF8HiShift = 7;    // fp8 hi = e4m3(hi * 2^7): |hi| < 2 after the prescale
 constexpr int kF8LoShift = 18;   // fp8 lo = e4m3(lo * 2^18): |lo| <= 2^-11 |x| < 2^-10
 
@@ -191,6 +195,7 @@ struct lrs_ctx {
 
   // screening state
   lrs::DevBuf W_last, rho_last, screen_tab, work, adj_work, val_work, fft_work;
+  lrs::DevBuf probe;              // output of the matrix-core rate probe
   bool have_W = false, have_rho = false;
 
   // timing

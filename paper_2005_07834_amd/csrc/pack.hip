@@ -66,16 +66,18 @@ __device__ inline void split_f16(float x, __half& hi, __half& lo) {
 //   FP32  (4 KiB, 64 slots):  slot l holds column l%16, k = 32 ch + 4 s + l/16, s = 0..7
 //   split (2 KiB, 32 slots):  slot l holds column l%16, k = 16 ch + 8 (l/16) + e, e = 0..7,
 //                             planes re hi, re lo, im hi, im lo
-//   F16F8 (4 KiB): see pack_f16f8_column and the layout note in lrs_internal.h
-// F16F8 column operand, one thread per (tile, column c, half h of the 32-K chunk): the 16 K
-// values 16 h .. 16 h + 15 of column c go to the fp16 hi slots c and 16 + c of plane pair h
-// and to fp8 slot 16 h + c, part 0 = lo * 2^18, part 1 = hi * 2^7 (the column side's order).
+//   F16F8 (2 KiB, 32 slots): slot l holds column l%16, k = 16 ch + 8 (l/16) + e, e = 0..7:
+//                             the fp16 hi slot of planes re and im and 8 bytes of each fp8
+//                             plane (layout note in lrs_internal.h)
+// F16F8 column operand: the 8 K values k0 .. k0 + 7 of column c (K half h of the chunk) go to
+// fp16 hi slot 16 h + c of the re and im planes and to bytes 8 h .. 8 h + 7 of row c of the
+// fp8 planes, part 0 = lo * 2^18 and part 1 = hi * 2^7 (the column side's order).
 template <class Src>
 __device__ void pack_f16f8_column(const Src& src, int c, int k0, float prescale,
-                                  unsigned char* tile, int h, int slot_c) {
-  _Float16 hr[16], hi_[16];
-  unsigned int f8[4][4] = {};     // [re p0, re p1, im p0, im p1][dword]
-  for (int j = 0; j < 16; ++j) {
+                                  unsigned char* tile, int h) {
+  _Float16 hr[8], hi_[8];
+  unsigned int f8[4][2] = {};     // [re p0, re p1, im p0, im p1][dword]
+  for (int j = 0; j < 8; ++j) {
     double re, im;
     src.get(c, k0 + j, re, im);
     const float xr = (float)(re * prescale), xi = (float)(im * prescale);
@@ -89,17 +91,15 @@ __device__ void pack_f16f8_column(const Src& src, int c, int k0, float prescale,
     f8[2][dw] |= e4m3_rn(ldexpf(li, kF8LoShift)) << sh;
     f8[3][dw] |= e4m3_rn(ldexpf((float)b, kF8HiShift)) << sh;
   }
-  for (int q = 0; q < 2; ++q) {       // slots slot_c (K 0-7) and 16 + slot_c (K 8-15)
-    _Float16* dr = reinterpret_cast<_Float16*>(tile + h * 512 + (q * 16 + slot_c) * 16);
-    _Float16* di = reinterpret_cast<_Float16*>(tile + 1024 + h * 512 + (q * 16 + slot_c) * 16);
-    for (int e = 0; e < 8; ++e) {
-      dr[e] = hr[8 * q + e];
-      di[e] = hi_[8 * q + e];
-    }
+  _Float16* dr = reinterpret_cast<_Float16*>(tile + (16 * h + c % 16) * 16);
+  _Float16* di = reinterpret_cast<_Float16*>(tile + 512 + (16 * h + c % 16) * 16);
+  for (int e = 0; e < 8; ++e) {
+    dr[e] = hr[e];
+    di[e] = hi_[e];
   }
   for (int part = 0; part < 4; ++part) {
-    uint4* d = reinterpret_cast<uint4*>(tile + 2048 + part * 512 + (16 * h + slot_c) * 16);
-    *d = make_uint4(f8[part][0], f8[part][1], f8[part][2], f8[part][3]);
+    uint2* d = reinterpret_cast<uint2*>(tile + 1024 + part * 256 + (c % 16) * 16 + 8 * h);
+    *d = make_uint2(f8[part][0], f8[part][1]);
   }
 }
 
@@ -117,7 +117,7 @@ __global__ void pack_tiles_kernel(Src src, long long ntiles, int ncb, int prec,
   int c = cb * 16 + (lane & 15);
   unsigned char* base = out + tile * (long long)tile_bytes(prec);
   if (prec == LRS_F16F8) {
-    pack_f16f8_column(src, c, ch * 32 + 16 * (lane >> 4), prescale, base, lane >> 4, lane & 15);
+    pack_f16f8_column(src, c, ch * 16 + 8 * (lane >> 4), prescale, base, lane >> 4);
   } else if (prec == LRS_FP64) {
     double* t = reinterpret_cast<double*>(base);
     for (int s = 0; s < 4; ++s) {

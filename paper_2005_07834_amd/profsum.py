@@ -4,7 +4,8 @@
         per (kernel, grid size): dispatch count and mean / min / max duration in ms
     python -m paper_2005_07834_amd.profsum pmc <counter_collection.csv> [--match REGEX]
         per (kernel, grid size, counter): dispatch count and the mean value per dispatch
-Groups of at most 8 dispatches also list every dispatch's own value, in dispatch order.
+Groups of at most 8 dispatches (or --each N) also list every dispatch's own value, in dispatch
+order; with --each N above 8, larger groups list their first N dispatches.
 
 Launches of one kernel template on different column sets (site x grid, site x site) share a
 name; the grid size (workgroups x threads) tells them apart, so both summaries group on it.
@@ -36,7 +37,7 @@ def _grid(row) -> str:
     return "x".join(row.get(f"Grid_Size_{a}", "1") for a in "XYZ")
 
 
-def trace(path: str, match: str) -> list[str]:
+def trace(path: str, match: str, each: int = 8) -> list[str]:
     groups = collections.defaultdict(list)
     with open(path, newline="") as fh:
         for r in csv.DictReader(fh):
@@ -51,12 +52,14 @@ def trace(path: str, match: str) -> list[str]:
         ts = [t for _, t in sorted(dts)]
         out.append(f"{len(ts):4d} {sum(ts) / len(ts):11.3f} {min(ts):11.3f} {max(ts):11.3f}  "
                    f"{grid}  {name}")
-        if len(ts) <= 8:
+        if len(ts) <= each:
             out.append("       each (ms): " + ", ".join(f"{t:.3f}" for t in ts))
+        elif each > 8:
+            out.append(f"       first {each} (ms): " + ", ".join(f"{t:.3f}" for t in ts[:each]))
     return out
 
 
-def pmc(path: str, match: str) -> list[str]:
+def pmc(path: str, match: str, each: int = 8) -> list[str]:
     # (kernel, grid) -> counter -> dispatch -> value (summed over the rows of one dispatch)
     groups = collections.defaultdict(
         lambda: collections.defaultdict(lambda: collections.defaultdict(float)))
@@ -74,8 +77,10 @@ def pmc(path: str, match: str) -> list[str]:
             vals = [v for _, v in sorted(per.items())]
             out.append(f"{len(vals):4d} {cname:>28} {sum(vals) / len(vals):18.6e}  "
                        f"{key[1]}  {key[0]}")
-            if len(vals) <= 8:
+            if len(vals) <= each:
                 out.append("       each: " + ", ".join(f"{v:.6e}" for v in vals))
+            elif each > 8:
+                out.append(f"       first {each}: " + ", ".join(f"{v:.6e}" for v in vals[:each]))
     return out
 
 
@@ -84,8 +89,11 @@ def main(argv=None) -> int:
     ap.add_argument("kind", choices=["trace", "pmc"])
     ap.add_argument("csv")
     ap.add_argument("--match", default=".")
+    ap.add_argument("--each", type=int, default=8,
+                    help="list every dispatch of groups up to this size, and the first this many "
+                         "(in dispatch order) of larger groups when above 8")
     a = ap.parse_args(argv)
-    lines = (trace if a.kind == "trace" else pmc)(a.csv, a.match)
+    lines = (trace if a.kind == "trace" else pmc)(a.csv, a.match, a.each)
     print("\n".join(lines))
     return 0
 

@@ -149,6 +149,29 @@ def test_generic_terms_and_errors(P, tiny_ref):
     assert e.value.status == P.LRS_ENONFINITE
 
 
+def test_device_memory_cap(P, tiny_ref, monkeypatch):
+    """LRS_MAX_BYTES (read when a context is created) caps the context's device allocations:
+    a call that would pass it fails with LRS_ENOMEM and the context stays usable; a context
+    created without the cap runs the same calls."""
+    w = tiny_ref["w"]
+    say("device memory cap (LRS_MAX_BYTES)")
+    monkeypatch.setenv("LRS_MAX_BYTES", str(64 << 10))
+    ctx = P.Context(0)
+    monkeypatch.delenv("LRS_MAX_BYTES")
+    with pytest.raises(P.LrsError) as e:
+        ctx.set_orbitals(w.energies, w.nocc, w.psi_grid, w.grid_dV)
+    assert e.value.status == P.LRS_ENOMEM
+    assert b"LRS_MAX_BYTES" in P.lib.lrs_last_error(ctx.h)
+    ctx.close()
+    ctx = P.Context(0)
+    ctx.set_orbitals(w.energies, w.nocc, w.psi_grid, w.grid_dV)
+    ctx.set_sites(w.sites, w.psi_site)
+    ctx.set_quadrature(*tiny_ref["terms"])
+    s = ctx.site_blocks(ctx.chi0(-1, P.COLS_SITE, P.FP64))[0].cpu().numpy()
+    assert rel(s, tiny_ref["quad_site"]) < 1e-12
+    ctx.close()
+
+
 @pytest.fixture(scope="module")
 def prod():
     return workload("production")

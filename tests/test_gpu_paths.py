@@ -69,6 +69,34 @@ def site_pairs(w, n_per_site, rng, sites=None):
 
 
 # ------------------------------------------------------------------ differentiation
+def test_chi0fn_energies_without_gradient(P):
+    """Energies given as an array (or a tensor without requires_grad): the backward pass returns
+    no energy gradient, and the orbital gradient equals the one taken with differentiable
+    energies."""
+    w = workload("tiny")
+    n = w.n_terms
+    s = oracle_scale(w, n)
+    say("Chi0Fn with energies that take no gradient, tiny")
+    ctx = P.Context(0)
+    lam = None
+    grads = []
+    for E in (np.asarray(w.energies), torch.tensor(w.energies, dtype=torch.float64),
+              torch.tensor(w.energies, dtype=torch.float64, requires_grad=True)):
+        psi = w.psi_site.to("cuda").clone().requires_grad_(True)
+        chi = P.Chi0Fn.apply(E, psi, ctx, w.nocc, w.sites, n, s)
+        if lam is None:
+            lam = torch.randn(chi.shape, dtype=torch.float64, device="cuda",
+                              generator=torch.Generator("cuda").manual_seed(5))
+        (chi * lam).sum().backward()
+        grads.append(psi.grad.clone())
+        if isinstance(E, torch.Tensor) and E.requires_grad:
+            assert E.grad is not None and torch.isfinite(E.grad).all()
+    e = max(float((g - grads[2]).abs().max() / grads[2].abs().max()) for g in grads[:2])
+    say(f"  dpsi with and without an energy gradient: {e:.2e}")
+    assert e == 0.0
+    ctx.close()
+
+
 def test_autograd_gradcheck_tiny(P):
     """Chi0Fn -> ScreenWFn -> sum of losses against torch's numerical Jacobian (FP64 path)."""
     w = workload("tiny")
@@ -550,4 +578,24 @@ def test_size_limits_refused(P):
             call()
         assert e.value.status == P.LRS_EUNSUPPORTED, name
     say("  size limits refused")
+    ctx.close()
+
+
+def test_mfma_rate_probe(P):
+    """The sustained matrix-core rate probe: positive and below the datasheet peak of each
+    precision's unit (FP64 78.6, FP32 157.3, 16-bit 2500 TFLOP/s), a longer run takes longer,
+    and bad arguments are refused."""
+    say("matrix-core rate probe")
+    ctx = P.Context(0)
+    peak = {"fp64": 78.6, "fp32": 157.3, "bf16x2": 2500.0, "fp16x2": 2500.0, "f16f8": 2500.0}
+    for prec, top in peak.items():
+        ctx.mfma_rate(prec, 200)
+        r1, ms1 = ctx.mfma_rate(prec, 2000)
+        r2, ms2 = ctx.mfma_rate(prec, 8000)
+        say(f"  {prec}: {r2:.1f} TFLOP/s ({ms2:.1f} ms for 8000 rounds, {ms1:.1f} ms for 2000)")
+        assert 0 < r2 <= 1.02 * top and ms2 > 2 * ms1
+    with pytest.raises(P.LrsError) as e:
+        ctx.mfma_rate("fp64", 0)
+    assert e.value.status == P.LRS_EINVAL
+    assert P.lib.lrs_mfma_rate(ctx.h, 9, 10, None, None) == P.LRS_EINVAL
     ctx.close()
