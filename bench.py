@@ -179,7 +179,7 @@ def main():
     ap.add_argument("--no-batching", action="store_true",
                     help="skip the batching workload's site x grid launch timed at the end")
     ap.add_argument("--no-tune", action="store_true", help="use the default chi0 variant")
-    ap.add_argument("--adjoint-prec", default="auto", choices=["auto", "fp64", "bf16x2"],
+    ap.add_argument("--adjoint-prec", default="auto", choices=["auto", "fp64", "bf16x2", "f16f8"],
                     help="precision of the adjoint's products (auto: bf16x2 with a split "
                          "--prec, else fp64)")
     ap.add_argument("--omega", type=float, default=0.1,
@@ -261,7 +261,7 @@ def main():
     prec = args.prec
     adj_prec = args.adjoint_prec
     if adj_prec == "auto":
-        adj_prec = "bf16x2" if prec in SPLIT else "fp64"
+        adj_prec = prec if prec in ("bf16x2", "f16f8") else ("bf16x2" if prec in SPLIT else "fp64")
     # the autotuner's choice for this problem (both column sets), before the timed steps
     ctx.make_quadrature(P.QUAD_TIME, w.n_terms, 0.0)
     tq = time.time()

@@ -361,7 +361,9 @@ lrs_status lrs_screen_W_backward(lrs_ctx* ctx, const double* dL_dW, double* dL_d
  * dL_dpsi_site complex128 [nk][nb][sum npts] (complex gradients as dL/dRe + i dL/dIm).
  * Each term's G_o, G_u are recomputed rather than stored.  prec LRS_FP64 runs every product
  * in FP64; LRS_BF16X2 recomputes G and forms the products with psi in split bfloat16 (hi + lo,
- * FP32 accumulation; relative error of order 1e-5), with the gradient accumulation in FP64.
+ * FP32 accumulation; relative error of order 1e-5), with the gradient accumulation in FP64;
+ * LRS_F16F8 recomputes G as the forward F16F8 path does (and so reads the site operand a
+ * forward F16F8 call prepared) and forms the products with psi as LRS_BF16X2 does.
  * Other precisions: LRS_EUNSUPPORTED.  Requires terms from lrs_make_quadrature or
  * lrs_make_quadrature_iw (generic terms carry no energy derivative: LRS_EUNSUPPORTED).  With
  * the imaginary-frequency terms dL/dchi0 may be any real matrix per block; with the static

@@ -267,7 +267,8 @@ class Context:
 
     def chi0_backward(self, dL_dchi0_ss, prec=FP64):
         """dL/dE [nk, nb] and dL/dpsi_site (complex) from dL/dchi0 on the site blocks; prec
-        FP64 or BF16X2 (split products, relative error of order 1e-5)."""
+        FP64, BF16X2 (split products, relative error of order 1e-5) or F16F8 (Green's
+        functions as the forward F16F8 path, split products)."""
         if isinstance(prec, str):
             prec = PREC_NAMES[prec]
         dE = torch.empty((self.nk, self.nb), dtype=torch.float64, device=self.device)
@@ -401,8 +402,8 @@ class Chi0Fn(torch.autograd.Function):
     layout computed in ``prec`` (FP64 by default); ``omega`` > 0 gives chi0 at imaginary
     frequency i omega (the imaginary-time terms with complex coefficients).  The backward pass
     runs the library's adjoint
-    (Green's functions recomputed per term; split products when ``prec`` is BF16X2, FP64
-    otherwise) and returns dL/de [nk, nb] and dL/dpsi_site (complex, dL/dRe + i dL/dIm); dL/de
+    (Green's functions recomputed per term, in ``prec`` when it is BF16X2 or F16F8 with split
+    products, FP64 otherwise) and returns dL/de [nk, nb] and dL/dpsi_site (complex, dL/dRe + i dL/dIm); dL/de
     is None when the energies were not a tensor or do not require a gradient.  The nodes are held
     fixed: pass ``scale > 0`` so the node set does not depend on the energies.  mu is the
     mid-gap value of the energies given to each forward pass; it cancels in the imaginary-time
@@ -431,7 +432,7 @@ class Chi0Fn(torch.autograd.Function):
         out = lctx.chi0(-1, COLS_SITE, p)
         fctx.lctx = lctx
         fctx.args = args
-        fctx.prec = BF16X2 if p == BF16X2 else FP64
+        fctx.prec = p if p in (BF16X2, F16F8) else FP64
         fctx.nextra = len(opt)
         fctx.version = lctx.orb_version
         fctx.e_like = (energies.device, energies.dtype) \

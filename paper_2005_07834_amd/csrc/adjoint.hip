@@ -498,11 +498,15 @@ hipError_t ensure(lrs_ctx* ctx, DevBuf& b, size_t bytes) {
 hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, double* dL_dE,
                                 double* dL_dpsi) {
   hipStream_t st = ctx->stream;
-  const bool split = prec == LRS_BF16X2;
+  // the Green's functions in `prec` (F16F8: the 128 x 128 tile, whose site block has more
+  // tiles to spread over the workgroups than the 128 x 192 one); the products with psi in
+  // split bfloat16 for both reduced precisions, else FP64
+  const bool split = prec == LRS_BF16X2 || prec == LRS_F16F8;
+  const int gvar = prec == LRS_F16F8 ? 1 : 0;
   // operands: site rows and site columns of the precision, k-major orbitals (FP64, and split)
   if (ensure_site_tiles_for(ctx, prec) != LRS_OK) return hipErrorOutOfMemory;
   Plan* plan = nullptr;
-  if (plan_for(ctx, -1, LRS_COLS_SITE, prec, 0, 1, &plan) != LRS_OK) return hipErrorOutOfMemory;
+  if (plan_for(ctx, -1, LRS_COLS_SITE, prec, gvar, 1, &plan) != LRS_OK) return hipErrorOutOfMemory;
   hipError_t e = ensure(ctx, ctx->psi_site_f64, (size_t)2 * ctx->K_pad * ctx->rows_pad * 8);
   if (e != hipSuccess) return e;
   e = launch_derive_site_kmajor((const double*)ctx->site_f64.p, ctx->rows_pad, ctx->K_pad,
@@ -639,13 +643,14 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
   B.ntiles = (int)tiles.size();
   B.per = (B.ntiles + 7) / 8;
   const int chunk = chunk_of(prec);
+  const double g_scale = is_f16(prec) ? (double)ctx->site_scale_f16 * ctx->site_scale_f16 : 1.0;
   for (int t = 0; t < T; ++t) {
     for (const Batch& bt : plan->batches) {
       if (bt.ntiles == 0) continue;
       const void* a_op = nullptr;
       // (LRS_ESTATE: a buffer that captured graphs read would have to be replaced)
       lrs_status ls = ensure_site_operand(ctx, prec, bt, t, 1, &a_op);
-      if (ls == LRS_OK) ls = ensure_park(ctx, prec, 0, bt.grid);
+      if (ls == LRS_OK) ls = ensure_park(ctx, prec, gvar, bt.grid);
       if (ls != LRS_OK) return ls == LRS_ESTATE ? hipErrorIllegalState : hipErrorOutOfMemory;
       e = launch_green_adjoint(prec, bt.grid, a_op, bt.nrb, ctx->site_tiles[prec].p,
                                ctx->site_cols_pad / 16, ctx->K_pad / chunk,
@@ -657,7 +662,9 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
     }
     B.w = wn + (size_t)t * Kp;
     B.dw = dwn + (size_t)t * Kp;
-    B.ct = odd ? 1.0 : ctx->quad.c[t];   // (complex coefficients are inside H)
+    // (complex coefficients are inside H; fp16-prescaled operands scale each G, and so H, by
+    // the square of the site prescale, a power of two taken out here)
+    B.ct = (odd ? 1.0 : ctx->quad.c[t]) / g_scale;
     if (split)
       hipLaunchKernelGGL(bwd_split_kernel, dim3((unsigned)(8 * B.per)), dim3(256), 0, st, B);
     else

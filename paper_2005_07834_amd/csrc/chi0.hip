@@ -635,8 +635,9 @@ __device__ __forceinline__ void mma_col_split(const FragsA<PREC, MB>& a, const F
 // Scheduling groups for one pipeline step: the next chunk's LDS reads, one per matrix-core
 // instruction, then the global->LDS loads spread over the following ones, then the rest.
 // The F16F8 path has fewer, longer matrix-core instructions per step than LDS reads and loads
-// together: two reads per instruction, then one load per instruction.
-template <int PREC, int MB, int NB, int NVM, int S>
+// together: two reads per instruction, then one load per instruction (LOADS_FIRST: the loads
+// go first, which gives them the most time to land before the step that waits for them).
+template <int PREC, int MB, int NB, int NVM, int S, bool LOADS_FIRST = false>
 __device__ __forceinline__ void interleave() {
   constexpr int kMFMA = 0x008, kVMEM = 0x010, kDSREAD = 0x100;
   constexpr bool split = PREC == LRS_BF16X2 || PREC == LRS_FP16X2;
@@ -646,7 +647,11 @@ __device__ __forceinline__ void interleave() {
   constexpr int NMF = f8 ? 3 * MB * NB / 2
                          : (split ? 3 * MB * NB : (PREC == LRS_FP64 ? 16 * MB * NB : 32 * MB * NB));
   constexpr int R = (NMF - NDS) / NVM > 0 ? (NMF - NDS) / NVM : 1;
-  if constexpr (f8) {
+  if constexpr (f8 && LOADS_FIRST) {
+    static_assert(NDS % 2 == 0 && NDS / 2 + NVM <= NMF, "F16F8 step groups");
+    sched_pairs<NVM, kMFMA, 1, kVMEM, 1>();
+    sched_pairs<NDS / 2, kMFMA, 1, kDSREAD, 2>();
+  } else if constexpr (f8) {
     static_assert(NDS % 2 == 0 && NDS / 2 + NVM <= NMF, "F16F8 step groups");
     sched_pairs<NDS / 2, kMFMA, 1, kDSREAD, 2>();
     sched_pairs<NVM, kMFMA, 1, kVMEM, 1>();
@@ -856,7 +861,7 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
         } else {
           // LDS reads and loads spread between the matrix-core instructions
           mma_frags<PREC, MB, NB>(cur, gr, gi);
-          interleave<PREC, MB, NB, LPW, S>();
+          interleave<PREC, MB, NB, LPW, S, IL == 2>();
         }
       }
       __builtin_amdgcn_sched_barrier(0);
@@ -1058,7 +1063,7 @@ LRS_VARIANT(LRS_FP16X2, 3, 2, 2, 4, 6, 4, 1, 0)
 // faster one on the precision workload (2.55 s against 2.94 s for its site x grid launch).
 LRS_VARIANT(LRS_F16F8, 0, 2, 2, 4, 6, 4, 1, 0)
 LRS_VARIANT(LRS_F16F8, 1, 2, 2, 4, 4, 4, 1, 0)
-LRS_VARIANT(LRS_F16F8, 2, 2, 2, 4, 6, 4, 0, 0)
+LRS_VARIANT(LRS_F16F8, 2, 2, 2, 4, 6, 4, 2, 0)
 LRS_VARIANT(LRS_F16F8, 3, 2, 2, 4, 4, 4, 0, 0)
 #undef LRS_VARIANT
 constexpr int kNumVariants = 4;
@@ -1271,6 +1276,7 @@ hipError_t launch_green_adjoint(int prec, int grid, const void* a_tiles, int a_n
   switch (prec) {
     case LRS_FP64: return launch_v<LRS_FP64, 0, 1>(grid, P, s);
     case LRS_BF16X2: return launch_v<LRS_BF16X2, 0, 2>(grid, P, s);
+    case LRS_F16F8: return launch_v<LRS_F16F8, 1, 2>(grid, P, s);
   }
   return hipErrorInvalidValue;
 }

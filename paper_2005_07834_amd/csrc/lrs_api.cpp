@@ -1158,8 +1158,9 @@ lrs_status lrs_compute_chi0_backward(lrs_ctx* ctx, int cols, int prec, const dou
   if (!ctx->have_bands || !ctx->have_sites || !ctx->have_quad)
     return fail(ctx, LRS_ESTATE, "orbitals, sites and quadrature must be set first");
   if (cols != LRS_COLS_SITE) return fail(ctx, LRS_EUNSUPPORTED, "backward supports site x site blocks only");
-  if (prec != LRS_FP64 && prec != LRS_BF16X2)
-    return fail(ctx, LRS_EUNSUPPORTED, "backward precision must be LRS_FP64 or LRS_BF16X2");
+  if (prec != LRS_FP64 && prec != LRS_BF16X2 && prec != LRS_F16F8)
+    return fail(ctx, LRS_EUNSUPPORTED, "backward precision must be LRS_FP64, LRS_BF16X2 or "
+                "LRS_F16F8");
   if (dL_dpsi_grid) return fail(ctx, LRS_EUNSUPPORTED, "site blocks do not depend on grid orbitals");
   if (!dL_dchi0 || !dL_dE || !dL_dpsi_site) return fail(ctx, LRS_EINVAL, "missing gradient buffers");
   if (!ctx->quad.has_deriv) return fail(ctx, LRS_EUNSUPPORTED, "generic terms carry no energy derivative");

@@ -252,8 +252,9 @@ hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int
                        double* out, double pref, int sym, unsigned int* sync, void* park,
                        hipStream_t s);
 // adjoint Green's functions of one term on site blocks: prec LRS_FP64 writes Hu, Ho as FP64
-// planes (hu_re, hu_im, ho_re, ho_im; row stride ld); LRS_BF16X2 writes each at hs_u, hs_o
-// as bfloat16 hi/lo in the split adjoint GEMM's operand tiles (h_tile_offset)
+// planes (hu_re, hu_im, ho_re, ho_im; row stride ld); LRS_BF16X2 and LRS_F16F8 (variant 1)
+// write each at hs_u, hs_o as bfloat16 hi/lo in the split adjoint GEMM's operand tiles
+// (h_tile_offset)
 hipError_t launch_green_adjoint(int prec, int grid, const void* a_tiles, int a_nrb,
                                 const void* b_tiles, int b_ncb, int nch, const double* c,
                                 int nch_o, const TileDesc* tiles, int ntiles, const double* lam,

@@ -254,7 +254,7 @@ def test_screen_backward_matches_rank_one_sensitivity(P, tiny_ref):
     assert rel(lam2.reshape(lam.shape), lam) < 1e-12
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("bf16x2", 1e-4)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("bf16x2", 1e-4), ("f16f8", 1e-4)])
 def test_chi0_backward_vs_oracle(P, tiny_ref, prec, tol):
     """The adjoint (FP64, or with the split products) against the oracle's gradient of the
     test-charge loss; a second call gives the same bits."""

@@ -117,7 +117,8 @@ def test_autograd_gradcheck_tiny(P):
                                     fast_mode=True)
 
 
-@pytest.mark.parametrize("prec,tol_l,tol_g", [(None, 1e-12, 1e-9), ("bf16x2", 1e-4, 1e-4)])
+@pytest.mark.parametrize("prec,tol_l,tol_g", [(None, 1e-12, 1e-9), ("bf16x2", 1e-4, 1e-4),
+                                              ("f16f8", 1e-4, 1e-4)])
 def test_autograd_matches_oracle_tiny(P, prec, tol_l, tol_g):
     """Loss and gradients through Chi0Fn and ScreenWFn against the oracle: the FP64 path (the
     default), and the split path (BF16X2 forward and adjoint products)."""
@@ -228,8 +229,8 @@ def test_differentiation_workload_fd_and_oracle(P):
 
 def test_split_adjoint_matches_fp64(P):
     """Differentiation workload (4 sites of 800 points, 2x2x2 k, 24 terms): the adjoint with
-    split-precision products against the FP64 adjoint on the same dL/dchi0, per site; the
-    split result is bitwise reproducible."""
+    split-precision products (Green's functions in BF16X2, then in F16F8) against the FP64
+    adjoint on the same dL/dchi0, per site; each result is bitwise reproducible."""
     w = workload("differentiation")
     n = w.n_terms
     s = oracle_scale(w, n)
@@ -239,16 +240,19 @@ def test_split_adjoint_matches_fp64(P):
     ctx.screen_W(chi, rho=torch.as_tensor(w.rho_test, device="cuda"), want_loss=True)
     lam = ctx.screen_W_backward()
     dE64, dp64 = ctx.chi0_backward(lam, P.FP64)
-    dEs, dps = ctx.chi0_backward(lam, P.BF16X2)
-    eE = rel(dEs.cpu().numpy(), dE64.cpu().numpy())
-    say(f"  dE {eE:.2e}")
-    assert eE < 1e-4
-    for k, sl in enumerate(gr.site_slices(w.sites)):
-        ep = rel(dps[:, :, sl].cpu().numpy(), dp64[:, :, sl].cpu().numpy())
-        say(f"  dpsi site {k}: {ep:.2e}")
-        assert ep < 1e-4
-    dEs2, dps2 = ctx.chi0_backward(lam, P.BF16X2)
-    assert torch.equal(dEs, dEs2) and torch.equal(dps, dps2)
+    for prec in (P.BF16X2, P.F16F8):
+        if prec == P.F16F8:
+            ctx.chi0(-1, P.COLS_SITE, prec)      # (the forward call whose operand it reads)
+        dEs, dps = ctx.chi0_backward(lam, prec)
+        eE = rel(dEs.cpu().numpy(), dE64.cpu().numpy())
+        say(f"  precision {prec}: dE {eE:.2e}")
+        assert eE < 1e-4
+        for k, sl in enumerate(gr.site_slices(w.sites)):
+            ep = rel(dps[:, :, sl].cpu().numpy(), dp64[:, :, sl].cpu().numpy())
+            say(f"  dpsi site {k}: {ep:.2e}")
+            assert ep < 1e-4
+        dEs2, dps2 = ctx.chi0_backward(lam, prec)
+        assert torch.equal(dEs, dEs2) and torch.equal(dps, dps2)
     ctx.close()
 
 
