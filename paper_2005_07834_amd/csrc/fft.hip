@@ -4,12 +4,17 @@
 //   u_bk(r)   = cubic Lagrange interpolation of u_bk(x) at the points r (cached stencils),
 //   psi_bk(r) = exp(i k.r) u_bk(r) / sqrt(Omega).
 // With Miller indices m (G = sum_d m_d b_d), G.x_j = 2 pi sum_d m_d j_d / N_d, so u on the grid is
-// the unnormalised inverse DFT of C placed at m mod N: a zeroed box per band, the coefficients
-// scattered into it, then one pass of a mixed-radix Stockham FFT along each axis, the lines of a
-// pass held in LDS (16 lines per workgroup, radices 4, 2, 3, 5, sizes up to 128).  The grid
-// values times the Bloch phase are the grid orbitals (lrs_set_orbitals_pw); interpolated at
-// arbitrary points they are lrs_project_orbitals_fft.  Everything is FP64 and HBM-bound: each
-// pass reads and writes the box once.
+// the unnormalised inverse DFT of C placed at m mod N: the coefficients scattered into a box per
+// band, then one pass of a mixed-radix Stockham FFT along each axis, the lines of a pass held in
+// LDS (16 lines per workgroup, radices 4, 2, 3, 5, sizes up to 128, roots from a table).  The
+// coefficients fill only the sub-box S_0 x S_1 x S_2 of the indices m mod N with |m_d| <= M_d
+// (S_d = {0..M_d} and {N_d - M_d..N_d - 1}), so the passes are pruned: axis 2 runs on the lines
+// of S_0 x S_1 only, axis 1 on the slabs of S_0 only, axis 0 on every line, and each pass reads
+// only the support of its axis (the rest of a line is zero), so nothing but the sub-box is
+// cleared.  The grid values times the Bloch phase are the grid orbitals
+// (lrs_set_orbitals_pw); interpolated at arbitrary points they are lrs_project_orbitals_fft.
+// Everything is FP64 and HBM-bound: with four-fold oversampling the passes move about 1.6 box
+// volumes per band instead of 6.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -56,35 +61,48 @@ __device__ inline double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-__device__ inline double2 expi_turns(double t) {   // exp(2 pi i t)
-  double s, c;
-  sincospi(2.0 * t, &s, &c);
-  return make_double2(c, s);
+// The support {0..m} and {n - m..n - 1} of an axis (m < 0: the whole axis): its a-th index,
+// its size, and whether index i lies in it.
+__host__ __device__ inline int sup_at(int a, int m, int n) {
+  return (m < 0 || a <= m) ? a : a + n - 2 * m - 1;
+}
+__host__ __device__ inline int sup_count(int m, int n) { return m < 0 ? n : 2 * m + 1; }
+__device__ inline bool in_sup(int i, int m, int n) { return m < 0 || i <= m || i >= n - m; }
+
+// tw[m] = exp(2 pi i m / n), m < n: every root a stage needs is one of these (its order Ns R
+// divides n), so a workgroup fills the table once instead of evaluating sines per butterfly
+__device__ inline void fill_twiddles(double2* tw, int n) {
+  for (int m = threadIdx.x; m < n; m += blockDim.x) {
+    double s, c;
+    sincospi(2.0 * (double)m / (double)n, &s, &c);
+    tw[m] = make_double2(c, s);
+  }
 }
 
 // Inverse (exp(+2 pi i ...)) Stockham stages on `nl` lines held in a[line][*]; returns the buffer
 // that holds the result.  Stage with radix R after sub-transforms of size Ns: butterfly j of a
 // line takes x[j + r n/R] (r < R), twiddles them by exp(2 pi i r (j mod Ns)/(Ns R)), takes their
-// R-point DFT and stores it at (j / Ns) Ns R + (j mod Ns) + r Ns.
-__device__ double2 (*fft_lines(double2 (*a)[kMaxFFT], double2 (*b)[kMaxFFT], const FftPlan& P,
-                               int nl))[kMaxFFT] {
+// R-point DFT and stores it at (j / Ns) Ns R + (j mod Ns) + r Ns.  Roots come from tw.
+__device__ double2 (*fft_lines(double2 (*a)[kMaxFFT], double2 (*b)[kMaxFFT], const double2* tw,
+                               const FftPlan& P, int nl))[kMaxFFT] {
   int Ns = 1;
+  const int n = P.n;
   for (int s = 0; s < P.nf; ++s) {
     const int R = P.rad[s];
-    const int nbf = P.n / R;
+    const int nbf = n / R;
+    const int tstep = n / (Ns * R);     // exp(2 pi i r k / (Ns R)) = tw[r k tstep]
     for (int it = threadIdx.x; it < nl * nbf; it += blockDim.x) {
       const int line = it / nbf, j = it - line * nbf;
       const int k = j % Ns;
       double2 v[5], V[5];
       for (int r = 0; r < R; ++r) {
         v[r] = a[line][j + r * nbf];
-        if (r > 0 && k > 0) v[r] = cmul(v[r], expi_turns((double)(r * k) / (double)(Ns * R)));
+        if (r > 0 && k > 0) v[r] = cmul(v[r], tw[r * k * tstep]);
       }
       for (int q = 0; q < R; ++q) {
         double2 acc = v[0];
         for (int r = 1; r < R; ++r) {
-          const double2 w = expi_turns((double)((r * q) % R) / (double)R);
-          const double2 t = cmul(v[r], w);
+          const double2 t = cmul(v[r], tw[((r * q) % R) * nbf]);
           acc.x += t.x;
           acc.y += t.y;
         }
@@ -102,45 +120,105 @@ __device__ double2 (*fft_lines(double2 (*a)[kMaxFFT], double2 (*b)[kMaxFFT], con
   return a;
 }
 
-// The contiguous axis (the last): lines of P.n consecutive values, 16 per workgroup; one band
-// per blockIdx.y (box stride `vol`).
-__global__ void __launch_bounds__(256) fft_contig_kernel(double2* box, long long vol,
-                                                         long long nlines, FftPlan P) {
+// The contiguous axis (the last): the lines (i0, i1) of S_0 x S_1 (supports m0, m1 of axes of
+// n0, n1), P.n consecutive values each, 16 per workgroup, reading the support m2 of the line
+// only; one band per blockIdx.y (box stride `vol`).
+__global__ void __launch_bounds__(256) fft_contig_kernel(double2* box, long long vol, int m0,
+                                                         int n0, int m1, int n1, int m2,
+                                                         FftPlan P) {
   __shared__ double2 s0[kLines][kMaxFFT];
   __shared__ double2 s1[kLines][kMaxFFT];
+  __shared__ double2 tw[kMaxFFT];
+  __shared__ long long start[kLines];
   double2* data = box + (long long)blockIdx.y * vol;
+  const int c1 = sup_count(m1, n1);
+  const long long nlines = (long long)sup_count(m0, n0) * c1;
   const long long l0 = (long long)blockIdx.x * kLines;
   const int nl = (int)min((long long)kLines, nlines - l0);
   const int n = P.n;
-  for (int it = threadIdx.x; it < nl * n; it += blockDim.x) s0[it / n][it % n] = data[l0 * n + it];
+  if (threadIdx.x < nl) {
+    const long long l = l0 + threadIdx.x;
+    const int i0 = sup_at((int)(l / c1), m0, n0), i1 = sup_at((int)(l % c1), m1, n1);
+    start[threadIdx.x] = ((long long)i0 * n1 + i1) * n;
+  }
+  fill_twiddles(tw, n);
   __syncthreads();
-  double2 (*res)[kMaxFFT] = fft_lines(s0, s1, P, nl);
-  for (int it = threadIdx.x; it < nl * n; it += blockDim.x) data[l0 * n + it] = res[it / n][it % n];
+  for (int it = threadIdx.x; it < nl * n; it += blockDim.x) {
+    const int line = it / n, i = it % n;
+    s0[line][i] = in_sup(i, m2, n) ? data[start[line] + i] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  double2 (*res)[kMaxFFT] = fft_lines(s0, s1, tw, P, nl);
+  for (int it = threadIdx.x; it < nl * n; it += blockDim.x)
+    data[start[it / n] + it % n] = res[it / n][it % n];
 }
 
-// A strided axis: the box as [outer][n][inner] with inner contiguous; a workgroup takes the 16
-// lines (o, c0 .. c0 + 15), so that every load and store moves 16 neighbouring values.
-__global__ void __launch_bounds__(256) fft_strided_kernel(double2* box, long long vol, int outer,
-                                                          long long inner, FftPlan P) {
+// A strided axis: the box as [outer][n][inner] with inner contiguous, outer restricted to the
+// support mo of an axis of no values; a workgroup takes the 16 lines (o, c0 .. c0 + 15), so that
+// every load and store moves 16 neighbouring values, and reads the support ml of its axis only.
+__global__ void __launch_bounds__(256) fft_strided_kernel(double2* box, long long vol, int mo,
+                                                          int no, long long inner, int ml,
+                                                          FftPlan P) {
   __shared__ double2 s0[kLines][kMaxFFT];
   __shared__ double2 s1[kLines][kMaxFFT];
+  __shared__ double2 tw[kMaxFFT];
   double2* data = box + (long long)blockIdx.y * vol;
   const long long nblk = (inner + kLines - 1) / kLines;
-  const long long o = blockIdx.x / nblk;
-  const long long c0 = (blockIdx.x - o * nblk) * kLines;
+  const long long o = sup_at((int)(blockIdx.x / nblk), mo, no);
+  const long long c0 = (blockIdx.x % nblk) * kLines;
   const int nl = (int)min((long long)kLines, inner - c0);
   const int n = P.n;
   const long long base = o * n * inner + c0;
+  fill_twiddles(tw, n);
   for (int it = threadIdx.x; it < kLines * n; it += blockDim.x) {
     const int i = it / kLines, c = it % kLines;
-    if (c < nl) s0[c][i] = data[base + (long long)i * inner + c];
+    if (c < nl)
+      s0[c][i] = in_sup(i, ml, n) ? data[base + (long long)i * inner + c] : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  double2 (*res)[kMaxFFT] = fft_lines(s0, s1, P, nl);
+  double2 (*res)[kMaxFFT] = fft_lines(s0, s1, tw, P, nl);
   for (int it = threadIdx.x; it < kLines * n; it += blockDim.x) {
     const int i = it / kLines, c = it % kLines;
     if (c < nl) data[base + (long long)i * inner + c] = res[c][i];
   }
+}
+
+// clears the sub-box S_0 x S_1 x S_2 of nbb boxes; one thread per value
+__global__ void zero_sub_kernel(double2* box, long long vol, int m0, int n0, int m1, int n1,
+                                int m2, int n2, int nbb) {
+  const int c0 = sup_count(m0, n0), c1 = sup_count(m1, n1), c2 = sup_count(m2, n2);
+  const long long per = (long long)c0 * c1 * c2;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= per * nbb) return;
+  const long long bb = t / per, r = t - bb * per;
+  const int a2 = (int)(r % c2), a1 = (int)((r / c2) % c1), a0 = (int)(r / ((long long)c1 * c2));
+  box[bb * vol + ((long long)sup_at(a0, m0, n0) * n1 + sup_at(a1, m1, n1)) * n2 +
+      sup_at(a2, m2, n2)] = make_double2(0.0, 0.0);
+}
+
+// exp(i k.r) / sqrt(Omega) at each point (the Bloch phase of the interpolated values)
+__global__ void point_phase_kernel(const double* pts, int npts, double kx, double ky, double kz,
+                                   double inv_sqrt_omega, double2* ph) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npts) return;
+  double s, c;
+  sincos(kx * pts[3 * p] + ky * pts[3 * p + 1] + kz * pts[3 * p + 2], &s, &c);
+  ph[p] = make_double2(c * inv_sqrt_omega, s * inv_sqrt_omega);
+}
+
+// exp(i k.(j / N_d) a_d) per axis d and index j (tables of n0, n1, n2 values one after the
+// other); their product over the axes, over sqrt(Omega), is the grid point's Bloch phase
+__global__ void axis_phase_kernel(const double* cell, double kx, double ky, double kz, int n0,
+                                  int n1, int n2, double2* ph) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n0 + n1 + n2) return;
+  const int d = t < n0 ? 0 : (t < n0 + n1 ? 1 : 2);
+  const int j = t - (d == 0 ? 0 : (d == 1 ? n0 : n0 + n1));
+  const int nd = d == 0 ? n0 : (d == 1 ? n1 : n2);
+  const double f = (double)j / nd;
+  double s, c;
+  sincos(f * (kx * cell[3 * d] + ky * cell[3 * d + 1] + kz * cell[3 * d + 2]), &s, &c);
+  ph[t] = make_double2(c, s);
 }
 
 // C_bk(G) of bands [b0, b0 + nbb) at k into the zeroed boxes: one thread per (band, G)
@@ -159,9 +237,8 @@ __global__ void scatter_kernel(const double2* coef, int nb, int npw, int b0, int
 // psi at the points: 4 x 4 x 4 stencil (first nodes base[p], weights w[p][3][4]) times the Bloch
 // phase; one thread per (band, point)
 __global__ void interp_kernel(const double2* box, long long vol, int n0, int n1, int n2,
-                              const int* base, const double* w, const double* pts, int npts,
-                              double kx, double ky, double kz, double inv_sqrt_omega, int nbb,
-                              double2* out) {
+                              const int* base, const double* w, const double2* ph, int npts,
+                              int nbb, double2* out) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (long long)nbb * npts) return;
   const int bb = (int)(t / npts), p = (int)(t - (long long)bb * npts);
@@ -182,28 +259,22 @@ __global__ void interp_kernel(const double2* box, long long vol, int n0, int n1,
       }
     }
   }
-  double s, c;
-  sincos(kx * pts[3 * p] + ky * pts[3 * p + 1] + kz * pts[3 * p + 2], &s, &c);
-  const double2 ph = make_double2(c * inv_sqrt_omega, s * inv_sqrt_omega);
-  out[(long long)bb * npts + p] = cmul(acc, ph);
+  out[(long long)bb * npts + p] = cmul(acc, ph[p]);
 }
 
 // grid orbitals: the box values times exp(i k.x_j) / sqrt(Omega), x_j = sum_d (j_d / N_d) a_d;
 // one thread per (band, grid point), output in the box's own order
 __global__ void grid_out_kernel(const double2* box, long long vol, int n0, int n1, int n2,
-                                const double* cell, double kx, double ky, double kz,
-                                double inv_sqrt_omega, int nbb, double2* out) {
+                                const double2* aph, double inv_sqrt_omega, int nbb,
+                                double2* out) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (long long)nbb * vol) return;
-  const long long bb = t / vol, idx = t - bb * vol;
+  const long long idx = t % vol;
   const int j2 = (int)(idx % n2), j1 = (int)((idx / n2) % n1), j0 = (int)(idx / ((long long)n1 * n2));
-  const double f0 = (double)j0 / n0, f1 = (double)j1 / n1, f2 = (double)j2 / n2;
-  const double x = f0 * cell[0] + f1 * cell[3] + f2 * cell[6];
-  const double y = f0 * cell[1] + f1 * cell[4] + f2 * cell[7];
-  const double z = f0 * cell[2] + f1 * cell[5] + f2 * cell[8];
-  double s, c;
-  sincos(kx * x + ky * y + kz * z, &s, &c);
-  out[t] = cmul(box[t], make_double2(c * inv_sqrt_omega, s * inv_sqrt_omega));
+  double2 ph = cmul(cmul(aph[j0], aph[n0 + j1]), aph[n0 + n1 + j2]);
+  ph.x *= inv_sqrt_omega;
+  ph.y *= inv_sqrt_omega;
+  out[t] = cmul(box[t], ph);
 }
 
 lrs_status set_err(lrs_ctx* ctx, lrs_status st, const char* msg) {
@@ -248,6 +319,10 @@ lrs_status fft_route(lrs_ctx* ctx, int nk, int nb, int npw, const double* kpts,
         return set_err(ctx, LRS_EINVAL, "the FFT grid must hold every plane wave: N_d > 2 |m_d|");
   const int n0 = nfft[0], n1 = nfft[1], n2 = nfft[2];
   const long long vol = (long long)n0 * n1 * n2;
+  // the coefficients' support per axis: |m_d| <= M_d (2 M_d + 1 <= N_d, checked above)
+  int M[3] = {0, 0, 0};
+  for (int g = 0; g < npw; ++g)
+    for (int d = 0; d < 3; ++d) M[d] = std::max(M[d], std::abs(gidx[3 * g + d]));
   // interpolation stencils, once for all bands and k: first node and the cubic weights of the
   // nodes at offsets -1, 0, 1, 2 from floor(grid coordinate)
   std::vector<int> base;
@@ -286,8 +361,9 @@ lrs_status fft_route(lrs_ctx* ctx, int nk, int nb, int npw, const double* kpts,
       }
     }
   }
-  // workspace: gidx | cell | stencils | points | boxes of a band batch (at most 1 GiB)
-  const size_t b_small = 256 + (size_t)npw * 12 + 9 * 8 + (size_t)npts * (12 + 96 + 24) + 1024;
+  // workspace: gidx | cell | stencils | points | phases | boxes of a band batch (at most 1 GiB)
+  const size_t b_small = 256 + (size_t)npw * 12 + 9 * 8 + (size_t)npts * (12 + 96 + 24 + 16) +
+                         (size_t)(n0 + n1 + n2) * 16 + 1536;
   const int nbb = (int)std::max<long long>(1, std::min<long long>(nb, (1LL << 30) / (vol * 16)));
   hipError_t e = ensure_fft(ctx, ctx->fft_work, b_small + (size_t)nbb * vol * 16 + 256);
   if (e == hipErrorIllegalState)
@@ -305,6 +381,7 @@ lrs_status fft_route(lrs_ctx* ctx, int nk, int nb, int npw, const double* kpts,
   int* d_base = (int*)take((size_t)npts * 12 + 1);
   double* d_w = (double*)take((size_t)npts * 96 + 1);
   double* d_pts = (double*)take((size_t)npts * 24 + 1);
+  double2* d_ph = (double2*)take((size_t)std::max(npts, n0 + n1 + n2) * 16);
   double2* box = (double2*)take((size_t)nbb * vol * 16);
   hipStream_t st = ctx->stream;
   e = hipMemcpyAsync(d_gidx, gidx, (size_t)npw * 12, hipMemcpyHostToDevice, st);
@@ -315,35 +392,45 @@ lrs_status fft_route(lrs_ctx* ctx, int nk, int nb, int npw, const double* kpts,
     if (e == hipSuccess) e = hipMemcpyAsync(d_pts, points, (size_t)npts * 24, hipMemcpyHostToDevice, st);
   }
   const double iso = 1.0 / std::sqrt(omega);
+  const int c0 = sup_count(M[0], n0), c1 = sup_count(M[1], n1), c2 = sup_count(M[2], n2);
   for (int k = 0; k < nk && e == hipSuccess; ++k) {
     const double* kv = kpts + 3 * k;
+    if (psi_pts)
+      hipLaunchKernelGGL(point_phase_kernel, dim3((npts + 255) / 256), dim3(256), 0, st, d_pts,
+                         npts, kv[0], kv[1], kv[2], iso, d_ph);
+    else
+      hipLaunchKernelGGL(axis_phase_kernel, dim3((n0 + n1 + n2 + 255) / 256), dim3(256), 0, st,
+                         d_cell, kv[0], kv[1], kv[2], n0, n1, n2, d_ph);
     for (int b0 = 0; b0 < nb && e == hipSuccess; b0 += nbb) {
       const int nbt = std::min(nbb, nb - b0);
-      e = launch_fill_zero(box, (size_t)nbt * vol * 16, st);
-      if (e != hipSuccess) break;
+      const long long nz = (long long)c0 * c1 * c2 * nbt;
+      hipLaunchKernelGGL(zero_sub_kernel, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, st,
+                         box, vol, M[0], n0, M[1], n1, M[2], n2, nbt);
       const long long ns = (long long)nbt * npw;
       hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st,
                          coef + (size_t)k * nb * npw, nb, npw, b0, nbt, d_gidx, n0, n1, n2, vol,
                          box);
-      // last axis (contiguous lines), then the middle axis, then the first
-      hipLaunchKernelGGL(fft_contig_kernel, dim3((unsigned)((vol / n2 + kLines - 1) / kLines), nbt),
-                         dim3(256), 0, st, box, vol, vol / n2, plan[2]);
+      // last axis on the lines of S_0 x S_1, the middle axis on the slabs of S_0, the first
+      // axis everywhere
+      const long long l2 = (long long)c0 * c1;
+      hipLaunchKernelGGL(fft_contig_kernel, dim3((unsigned)((l2 + kLines - 1) / kLines), nbt),
+                         dim3(256), 0, st, box, vol, M[0], n0, M[1], n1, M[2], plan[2]);
       const long long nb1 = (n2 + kLines - 1) / kLines;
-      hipLaunchKernelGGL(fft_strided_kernel, dim3((unsigned)(n0 * nb1), nbt), dim3(256), 0, st,
-                         box, vol, n0, (long long)n2, plan[1]);
+      hipLaunchKernelGGL(fft_strided_kernel, dim3((unsigned)(c0 * nb1), nbt), dim3(256), 0, st,
+                         box, vol, M[0], n0, (long long)n2, M[1], plan[1]);
       const long long inner0 = (long long)n1 * n2;
       hipLaunchKernelGGL(fft_strided_kernel,
                          dim3((unsigned)((inner0 + kLines - 1) / kLines), nbt), dim3(256), 0, st,
-                         box, vol, 1, inner0, plan[0]);
+                         box, vol, -1, 1, inner0, M[0], plan[0]);
       if (psi_pts) {
         const long long nt = (long long)nbt * npts;
         hipLaunchKernelGGL(interp_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st,
-                           box, vol, n0, n1, n2, d_base, d_w, d_pts, npts, kv[0], kv[1], kv[2],
-                           iso, nbt, psi_pts + ((size_t)k * nb + b0) * npts);
+                           box, vol, n0, n1, n2, d_base, d_w, d_ph, npts, nbt,
+                           psi_pts + ((size_t)k * nb + b0) * npts);
       } else {
         const long long nt = (long long)nbt * vol;
         hipLaunchKernelGGL(grid_out_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st,
-                           box, vol, n0, n1, n2, d_cell, kv[0], kv[1], kv[2], iso, nbt,
+                           box, vol, n0, n1, n2, d_ph, iso, nbt,
                            psi_grid + ((size_t)k * nb + b0) * vol);
       }
       e = hipGetLastError();

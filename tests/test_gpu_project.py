@@ -159,6 +159,14 @@ def test_fft_projection_tiny_vs_oracle(P):
     g_fft = ctx.project_orbitals_fft(kpts, cell, gidx, coef.cuda(), omega, gp, (N, N, N))
     g_dir = pj.project(coef.numpy(), kpts, gcart, gp, omega)
     assert rel(g_fft.cpu().numpy(), g_dir) < 1e-12
+    # a different size per axis (each pass prunes to its own axis's support)
+    M = int(np.abs(gidx).max())
+    nf = (_fft_size(M, 3), _fft_size(M, 4), _fft_size(M, 5))
+    got3 = ctx.project_orbitals_fft(kpts, cell, gidx, coef.cuda(), omega, pts, nf).cpu().numpy()
+    ref3 = pj.project_fft(coef.numpy()[:, :16], kpts, cell, gidx, pts, omega, nf)
+    e3 = rel(got3[:, :16], ref3)
+    say(f"  grid {nf}: vs oracle FFT route {e3:.2e}")
+    assert e3 < 1e-12
     ctx.close()
 
 
