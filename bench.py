@@ -109,11 +109,18 @@ def fft_projection(ctx, bd, coef, pts, psi_direct):
     psi = ctx.project_orbitals_fft(*args)
     torch.cuda.synchronize()
     ms = (time.time() - t) * 1e3
-    nk_, nb_ = coef.shape[:2]
-    # each axis pass reads and writes the box once (16 bytes per value)
-    moved = 3.0 * 2.0 * 16.0 * n ** 3 * nk_ * nb_
+    nk_, nb_, npw_ = coef.shape
+    # least traffic of the pruned route per band (16 bytes per value): the coefficient
+    # sub-box c^3 cleared, read and the coefficients scattered; axis 2 on c^2 lines (writes
+    # c^2 n), axis 1 on c slabs (reads c^2 n, writes c n^2), axis 0 everywhere (reads c n^2,
+    # writes n^3); the interpolation reads at most every grid value once and writes the points
+    c = 2 * int(np.abs(bd.gvec).max()) + 1
+    per_band = (2 * c ** 3 + npw_ + 2 * c * c * n + 2 * c * n * n + n ** 3
+                + min(64 * len(pts), n ** 3) + len(pts))
+    moved = 16.0 * per_band * nk_ * nb_
     return {"call_ms": ms, "grid": [n, n, n], "interpolation": "cubic Lagrange, 4x4x4 nodes",
-            "fft_pass_bytes": moved, "fft_pass_gb_per_s": moved / (ms / 1e3) / 1e9,
+            "pruned_route_bytes": moved, "pruned_route_gb_per_s": moved / (ms / 1e3) / 1e9,
+            "frac_of_hbm": moved / (ms / 1e3) / 8e12,
             "max_rel_diff_vs_direct": float((psi - psi_direct).abs().max()
                                             / psi_direct.abs().max())}
 

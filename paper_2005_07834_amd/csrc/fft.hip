@@ -28,7 +28,7 @@
 namespace lrs {
 namespace {
 
-constexpr int kMaxFFT = 128;   // longest axis (LDS: two buffers of 16 lines)
+constexpr int kMaxFFT = 128;   // longest axis (LDS: two buffers of 16 lines, 66 KiB at most)
 constexpr int kLines = 16;     // lines per workgroup
 
 struct FftPlan {
@@ -79,12 +79,13 @@ __device__ inline void fill_twiddles(double2* tw, int n) {
   }
 }
 
-// Inverse (exp(+2 pi i ...)) Stockham stages on `nl` lines held in a[line][*]; returns the buffer
-// that holds the result.  Stage with radix R after sub-transforms of size Ns: butterfly j of a
+// Inverse (exp(+2 pi i ...)) Stockham stages on `nl` lines held in a[line * ld + *] (ld = n | 1:
+// an odd stride, so that the 16 lines' values at one index fall in different LDS banks); returns
+// the buffer that holds the result.  Stage with radix R after sub-transforms of size Ns: butterfly j of a
 // line takes x[j + r n/R] (r < R), twiddles them by exp(2 pi i r (j mod Ns)/(Ns R)), takes their
 // R-point DFT and stores it at (j / Ns) Ns R + (j mod Ns) + r Ns.  Roots come from tw.
-__device__ double2 (*fft_lines(double2 (*a)[kMaxFFT], double2 (*b)[kMaxFFT], const double2* tw,
-                               const FftPlan& P, int nl))[kMaxFFT] {
+__device__ double2* fft_lines(double2* a, double2* b, const double2* tw, const FftPlan& P,
+                              int nl, int ld) {
   int Ns = 1;
   const int n = P.n;
   for (int s = 0; s < P.nf; ++s) {
@@ -96,7 +97,7 @@ __device__ double2 (*fft_lines(double2 (*a)[kMaxFFT], double2 (*b)[kMaxFFT], con
       const int k = j % Ns;
       double2 v[5], V[5];
       for (int r = 0; r < R; ++r) {
-        v[r] = a[line][j + r * nbf];
+        v[r] = a[line * ld + j + r * nbf];
         if (r > 0 && k > 0) v[r] = cmul(v[r], tw[r * k * tstep]);
       }
       for (int q = 0; q < R; ++q) {
@@ -109,10 +110,10 @@ __device__ double2 (*fft_lines(double2 (*a)[kMaxFFT], double2 (*b)[kMaxFFT], con
         V[q] = acc;
       }
       const int d = (j / Ns) * Ns * R + k;
-      for (int r = 0; r < R; ++r) b[line][d + r * Ns] = V[r];
+      for (int r = 0; r < R; ++r) b[line * ld + d + r * Ns] = V[r];
     }
     __syncthreads();
-    double2 (*t)[kMaxFFT] = a;
+    double2* t = a;
     a = b;
     b = t;
     Ns *= R;
@@ -126,16 +127,18 @@ __device__ double2 (*fft_lines(double2 (*a)[kMaxFFT], double2 (*b)[kMaxFFT], con
 __global__ void __launch_bounds__(256) fft_contig_kernel(double2* box, long long vol, int m0,
                                                          int n0, int m1, int n1, int m2,
                                                          FftPlan P) {
-  __shared__ double2 s0[kLines][kMaxFFT];
-  __shared__ double2 s1[kLines][kMaxFFT];
-  __shared__ double2 tw[kMaxFFT];
+  // dynamic LDS: two buffers of kLines lines of P.n values, then the twiddle table
+  extern __shared__ double2 smem[];
   __shared__ long long start[kLines];
   double2* data = box + (long long)blockIdx.y * vol;
   const int c1 = sup_count(m1, n1);
   const long long nlines = (long long)sup_count(m0, n0) * c1;
   const long long l0 = (long long)blockIdx.x * kLines;
   const int nl = (int)min((long long)kLines, nlines - l0);
-  const int n = P.n;
+  const int n = P.n, ld = n | 1;
+  double2* s0 = smem;
+  double2* s1 = smem + kLines * ld;
+  double2* tw = smem + 2 * kLines * ld;
   if (threadIdx.x < nl) {
     const long long l = l0 + threadIdx.x;
     const int i0 = sup_at((int)(l / c1), m0, n0), i1 = sup_at((int)(l % c1), m1, n1);
@@ -145,12 +148,12 @@ __global__ void __launch_bounds__(256) fft_contig_kernel(double2* box, long long
   __syncthreads();
   for (int it = threadIdx.x; it < nl * n; it += blockDim.x) {
     const int line = it / n, i = it % n;
-    s0[line][i] = in_sup(i, m2, n) ? data[start[line] + i] : make_double2(0.0, 0.0);
+    s0[line * ld + i] = in_sup(i, m2, n) ? data[start[line] + i] : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  double2 (*res)[kMaxFFT] = fft_lines(s0, s1, tw, P, nl);
+  const double2* res = fft_lines(s0, s1, tw, P, nl, ld);
   for (int it = threadIdx.x; it < nl * n; it += blockDim.x)
-    data[start[it / n] + it % n] = res[it / n][it % n];
+    data[start[it / n] + it % n] = res[(it / n) * ld + it % n];
 }
 
 // A strided axis: the box as [outer][n][inner] with inner contiguous, outer restricted to the
@@ -159,9 +162,7 @@ __global__ void __launch_bounds__(256) fft_contig_kernel(double2* box, long long
 __global__ void __launch_bounds__(256) fft_strided_kernel(double2* box, long long vol, int mo,
                                                           int no, long long inner, int ml,
                                                           FftPlan P) {
-  __shared__ double2 s0[kLines][kMaxFFT];
-  __shared__ double2 s1[kLines][kMaxFFT];
-  __shared__ double2 tw[kMaxFFT];
+  extern __shared__ double2 smem[];   // as in fft_contig_kernel
   double2* data = box + (long long)blockIdx.y * vol;
   const long long nblk = (inner + kLines - 1) / kLines;
   const long long o = sup_at((int)(blockIdx.x / nblk), mo, no);
@@ -169,17 +170,68 @@ __global__ void __launch_bounds__(256) fft_strided_kernel(double2* box, long lon
   const int nl = (int)min((long long)kLines, inner - c0);
   const int n = P.n;
   const long long base = o * n * inner + c0;
+  const int ld = n | 1;
+  double2* s0 = smem;
+  double2* s1 = smem + kLines * ld;
+  double2* tw = smem + 2 * kLines * ld;
   fill_twiddles(tw, n);
   for (int it = threadIdx.x; it < kLines * n; it += blockDim.x) {
     const int i = it / kLines, c = it % kLines;
     if (c < nl)
-      s0[c][i] = in_sup(i, ml, n) ? data[base + (long long)i * inner + c] : make_double2(0.0, 0.0);
+      s0[c * ld + i] =
+          in_sup(i, ml, n) ? data[base + (long long)i * inner + c] : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  double2 (*res)[kMaxFFT] = fft_lines(s0, s1, tw, P, nl);
+  const double2* res = fft_lines(s0, s1, tw, P, nl, ld);
   for (int it = threadIdx.x; it < kLines * n; it += blockDim.x) {
     const int i = it / kLines, c = it % kLines;
-    if (c < nl) data[base + (long long)i * inner + c] = res[c][i];
+    if (c < nl) data[base + (long long)i * inner + c] = res[c * ld + i];
+  }
+}
+
+// An axis as a direct sum over its support: the box as [outer][n][inner] (outer restricted to
+// the support mo of an axis of no values), each output j of a column (o, c) is the sum over the
+// c_l <= kMaxSup indices m of the axis's support ml of u(m) exp(2 pi i m j / n).  One thread
+// per (band, o, c): it reads its c_l values (a wave reads 64 neighbouring columns of a row) and
+// writes all n outputs the same way, so the pass streams the box in long runs; the root index
+// m j mod n is the same across the workgroup, so the table read is a broadcast.  Where the
+// support is short (four-fold oversampling: a quarter of the axis) this costs fewer memory
+// passes than staging lines through LDS, and the arithmetic stays far below the memory time.
+constexpr int kMaxSup = 32;
+__global__ void __launch_bounds__(256) axis_dft_kernel(double2* box, long long vol, int mo,
+                                                       int no, int n, long long inner, int ml,
+                                                       int nbb) {
+  __shared__ double2 tw[kMaxFFT];
+  fill_twiddles(tw, n);
+  __syncthreads();
+  const long long per = (long long)sup_count(mo, no) * inner;   // columns per band
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)nbb * per) return;
+  const long long r = t % per;
+  const long long o = sup_at((int)(r / inner), mo, no);
+  double2* u = box + (t / per) * vol + o * n * inner + r % inner;
+  const int cl = sup_count(ml, n);
+  double2 x[kMaxSup];
+  int m[kMaxSup], idx[kMaxSup];
+#pragma unroll
+  for (int a = 0; a < kMaxSup; ++a) {
+    m[a] = a < cl ? sup_at(a, ml, n) : 0;
+    x[a] = a < cl ? u[(long long)m[a] * inner] : make_double2(0.0, 0.0);
+    idx[a] = 0;
+  }
+  for (int j = 0; j < n; ++j) {
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int a = 0; a < kMaxSup; ++a) {
+      if (a < cl) {
+        const double2 w = tw[idx[a]];
+        acc.x += x[a].x * w.x - x[a].y * w.y;
+        acc.y += x[a].x * w.y + x[a].y * w.x;
+        idx[a] += m[a];
+        idx[a] -= idx[a] >= n ? n : 0;
+      }
+    }
+    u[(long long)j * inner] = acc;
   }
 }
 
@@ -234,32 +286,48 @@ __global__ void scatter_kernel(const double2* coef, int nb, int npw, int b0, int
   box[bb * vol + ((long long)m0 * n1 + m1) * n2 + m2] = coef[(long long)(b0 + bb) * npw + g];
 }
 
-// psi at the points: 4 x 4 x 4 stencil (first nodes base[p], weights w[p][3][4]) times the Bloch
-// phase; one thread per (band, point)
+// psi at the points: 4 x 4 x 4 stencil (first nodes base[p] in [0, n), weights w[p][3][4]) times
+// the Bloch phase ph[p]; one thread per (band, point).  The points come sorted by their first
+// node (neighbouring threads gather neighbouring grid values); order[p] is the caller's index.
 __global__ void interp_kernel(const double2* box, long long vol, int n0, int n1, int n2,
-                              const int* base, const double* w, const double2* ph, int npts,
-                              int nbb, double2* out) {
+                              const int* base, const double* w, const double2* ph,
+                              const int* order, int npts, int nbb, double2* out) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (long long)nbb * npts) return;
   const int bb = (int)(t / npts), p = (int)(t - (long long)bb * npts);
   const double2* u = box + bb * vol;
   const double* wp = w + 12 * (long long)p;
-  double2 acc = make_double2(0.0, 0.0);
+  // the four node indices per axis, wrapped into the box (first nodes lie in [0, n), so
+  // three subtractions cover any n >= 1)
+  auto wrap = [](int x, int n) {
+    x -= x >= n ? n : 0;
+    x -= x >= n ? n : 0;
+    return x - (x >= n ? n : 0);
+  };
+  int i0[4], i1[4], i2[4];
+#pragma unroll
   for (int a = 0; a < 4; ++a) {
-    const int i0 = ((base[3 * p] + a) % n0 + n0) % n0;
+    i0[a] = wrap(base[3 * p] + a, n0);
+    i1[a] = wrap(base[3 * p + 1] + a, n1);
+    i2[a] = wrap(base[3 * p + 2] + a, n2);
+  }
+  double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+#pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const int i1 = ((base[3 * p + 1] + c) % n1 + n1) % n1;
       const double wac = wp[a] * wp[4 + c];
-      const double2* row = u + ((long long)i0 * n1 + i1) * n2;
+      const double2* row = u + ((long long)i0[a] * n1 + i1[c]) * n2;
+#pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int i2 = ((base[3 * p + 2] + e) % n2 + n2) % n2;
         const double we = wac * wp[8 + e];
-        acc.x += we * row[i2].x;
-        acc.y += we * row[i2].y;
+        const double2 v = row[i2[e]];
+        acc.x += we * v.x;
+        acc.y += we * v.y;
       }
     }
   }
-  out[(long long)bb * npts + p] = cmul(acc, ph[p]);
+  out[(long long)bb * npts + order[p]] = cmul(acc, ph[p]);
 }
 
 // grid orbitals: the box values times exp(i k.x_j) / sqrt(Omega), x_j = sum_d (j_d / N_d) a_d;
@@ -351,7 +419,9 @@ lrs_status fft_route(lrs_ctx* ctx, int nk, int nb, int npw, const double* kpts,
         const double g = f * nfft[d];
         const double fl = std::floor(g);
         const double t = g - fl;
-        base[3 * (size_t)p + d] = (int)fl - 1;
+        // first node, reduced into [0, N_d) (the grid is periodic)
+        const long long b = ((long long)fl - 1) % nfft[d];
+        base[3 * (size_t)p + d] = (int)(b < 0 ? b + nfft[d] : b);
         for (int q = 0; q < 4; ++q) {
           double v = 1.0;
           for (int s = 0; s < 4; ++s)
@@ -361,9 +431,33 @@ lrs_status fft_route(lrs_ctx* ctx, int nk, int nb, int npw, const double* kpts,
       }
     }
   }
+  // points in the order of their first node (lexicographic), stencils and coordinates with them
+  std::vector<int> order, base_s;
+  std::vector<double> wts_s, pts_s;
+  if (psi_pts) {
+    order.resize(npts);
+    for (int p = 0; p < npts; ++p) order[p] = p;
+    std::sort(order.begin(), order.end(), [&](int x, int y) {
+      for (int d = 0; d < 3; ++d)
+        if (base[3 * (size_t)x + d] != base[3 * (size_t)y + d])
+          return base[3 * (size_t)x + d] < base[3 * (size_t)y + d];
+      return x < y;
+    });
+    base_s.resize(base.size());
+    wts_s.resize(wts.size());
+    pts_s.resize((size_t)3 * npts);
+    for (int q = 0; q < npts; ++q) {
+      const size_t p = order[q];
+      for (int d = 0; d < 3; ++d) {
+        base_s[3 * (size_t)q + d] = base[3 * p + d];
+        pts_s[3 * (size_t)q + d] = points[3 * p + d];
+      }
+      for (int i = 0; i < 12; ++i) wts_s[12 * (size_t)q + i] = wts[12 * p + i];
+    }
+  }
   // workspace: gidx | cell | stencils | points | phases | boxes of a band batch (at most 1 GiB)
-  const size_t b_small = 256 + (size_t)npw * 12 + 9 * 8 + (size_t)npts * (12 + 96 + 24 + 16) +
-                         (size_t)(n0 + n1 + n2) * 16 + 1536;
+  const size_t b_small = 256 + (size_t)npw * 12 + 9 * 8 + (size_t)npts * (12 + 96 + 24 + 16 + 4) +
+                         (size_t)(n0 + n1 + n2) * 16 + 1792;
   const int nbb = (int)std::max<long long>(1, std::min<long long>(nb, (1LL << 30) / (vol * 16)));
   hipError_t e = ensure_fft(ctx, ctx->fft_work, b_small + (size_t)nbb * vol * 16 + 256);
   if (e == hipErrorIllegalState)
@@ -381,18 +475,37 @@ lrs_status fft_route(lrs_ctx* ctx, int nk, int nb, int npw, const double* kpts,
   int* d_base = (int*)take((size_t)npts * 12 + 1);
   double* d_w = (double*)take((size_t)npts * 96 + 1);
   double* d_pts = (double*)take((size_t)npts * 24 + 1);
+  int* d_order = (int*)take((size_t)npts * 4 + 1);
   double2* d_ph = (double2*)take((size_t)std::max(npts, n0 + n1 + n2) * 16);
   double2* box = (double2*)take((size_t)nbb * vol * 16);
   hipStream_t st = ctx->stream;
   e = hipMemcpyAsync(d_gidx, gidx, (size_t)npw * 12, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(d_cell, cell, 72, hipMemcpyHostToDevice, st);
   if (e == hipSuccess && psi_pts) {
-    e = hipMemcpyAsync(d_base, base.data(), (size_t)npts * 12, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(d_w, wts.data(), (size_t)npts * 96, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(d_pts, points, (size_t)npts * 24, hipMemcpyHostToDevice, st);
+    e = hipMemcpyAsync(d_base, base_s.data(), (size_t)npts * 12, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_w, wts_s.data(), (size_t)npts * 96, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_pts, pts_s.data(), (size_t)npts * 24, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_order, order.data(), (size_t)npts * 4, hipMemcpyHostToDevice, st);
   }
   const double iso = 1.0 / std::sqrt(omega);
   const int c0 = sup_count(M[0], n0), c1 = sup_count(M[1], n1), c2 = sup_count(M[2], n2);
+  // two line buffers and the twiddle table of a pass along an axis of n values
+  auto lds_bytes = [](int n) {
+    return (unsigned)((2 * kLines * (n | 1) + n) * sizeof(double2));
+  };
+  {
+    // (above 64 KiB of dynamic LDS, that is for axes longer than 123, a kernel must ask)
+    const int most = (int)lds_bytes(kMaxFFT);
+    hipError_t ea = hipFuncSetAttribute((const void*)fft_contig_kernel,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, most);
+    if (ea == hipSuccess)
+      ea = hipFuncSetAttribute((const void*)fft_strided_kernel,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, most);
+    if (ea != hipSuccess) {
+      ctx->err = std::string("FFT projection: ") + hipGetErrorString(ea);
+      return LRS_EDEVICE;
+    }
+  }
   for (int k = 0; k < nk && e == hipSuccess; ++k) {
     const double* kv = kpts + 3 * k;
     if (psi_pts)
@@ -414,18 +527,31 @@ lrs_status fft_route(lrs_ctx* ctx, int nk, int nb, int npw, const double* kpts,
       // axis everywhere
       const long long l2 = (long long)c0 * c1;
       hipLaunchKernelGGL(fft_contig_kernel, dim3((unsigned)((l2 + kLines - 1) / kLines), nbt),
-                         dim3(256), 0, st, box, vol, M[0], n0, M[1], n1, M[2], plan[2]);
-      const long long nb1 = (n2 + kLines - 1) / kLines;
-      hipLaunchKernelGGL(fft_strided_kernel, dim3((unsigned)(c0 * nb1), nbt), dim3(256), 0, st,
-                         box, vol, M[0], n0, (long long)n2, M[1], plan[1]);
+                         dim3(256), lds_bytes(n2), st, box, vol, M[0], n0, M[1], n1, M[2],
+                         plan[2]);
+      if (c1 <= kMaxSup) {
+        const long long nc = (long long)nbt * c0 * n2;
+        hipLaunchKernelGGL(axis_dft_kernel, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st,
+                           box, vol, M[0], n0, n1, (long long)n2, M[1], nbt);
+      } else {
+        const long long nb1 = (n2 + kLines - 1) / kLines;
+        hipLaunchKernelGGL(fft_strided_kernel, dim3((unsigned)(c0 * nb1), nbt), dim3(256),
+                           lds_bytes(n1), st, box, vol, M[0], n0, (long long)n2, M[1], plan[1]);
+      }
       const long long inner0 = (long long)n1 * n2;
-      hipLaunchKernelGGL(fft_strided_kernel,
-                         dim3((unsigned)((inner0 + kLines - 1) / kLines), nbt), dim3(256), 0, st,
-                         box, vol, -1, 1, inner0, M[0], plan[0]);
+      if (c0 <= kMaxSup) {
+        const long long nc = (long long)nbt * inner0;
+        hipLaunchKernelGGL(axis_dft_kernel, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st,
+                           box, vol, -1, 1, n0, inner0, M[0], nbt);
+      } else {
+        hipLaunchKernelGGL(fft_strided_kernel,
+                           dim3((unsigned)((inner0 + kLines - 1) / kLines), nbt), dim3(256),
+                           lds_bytes(n0), st, box, vol, -1, 1, inner0, M[0], plan[0]);
+      }
       if (psi_pts) {
         const long long nt = (long long)nbt * npts;
         hipLaunchKernelGGL(interp_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st,
-                           box, vol, n0, n1, n2, d_base, d_w, d_ph, npts, nbt,
+                           box, vol, n0, n1, n2, d_base, d_w, d_ph, d_order, npts, nbt,
                            psi_pts + ((size_t)k * nb + b0) * npts);
       } else {
         const long long nt = (long long)nbt * vol;

@@ -170,6 +170,72 @@ def test_fft_projection_tiny_vs_oracle(P):
     ctx.close()
 
 
+def test_fft_projection_long_support_and_set_orbitals_pw(P):
+    """Random coefficients on every G with |m| <= 17 (a support of 35 values per axis, beyond
+    what the direct-sum axis passes take, so the LDS passes run) in a sheared cell, two k-points,
+    on a (36, 40, 45) grid: the library's FFT route against the oracle's element by element
+    (1e-12), at random points and at points outside the cell (the grid is periodic); and the
+    grid orbitals of lrs_set_orbitals_pw on a short support against the oracle's FFT grid times
+    the Bloch phase at every grid point (1e-12)."""
+    rng = np.random.default_rng(17)
+    cell = np.array([[7.0, 0.0, 0.0], [1.5, 6.5, 0.0], [0.5, -1.0, 8.0]])
+    omega = abs(np.linalg.det(cell))
+    r = np.arange(-17, 18)
+    m = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3)
+    gidx = m[(m ** 2).sum(1) <= 17 ** 2].astype(np.int32)
+    nk, nb = 2, 3
+    coef = torch.complex(torch.randn((nk, nb, len(gidx)), dtype=torch.float64,
+                                     generator=torch.Generator().manual_seed(4)),
+                         torch.randn((nk, nb, len(gidx)), dtype=torch.float64,
+                                     generator=torch.Generator().manual_seed(5)))
+    kpts = rng.normal(size=(nk, 3)) * 0.2
+    frac = np.concatenate([rng.random((30, 3)), rng.random((10, 3)) * 3.0 - 1.0])
+    pts = frac @ cell
+    nf = (36, 40, 45)
+    say(f"FFT route, long support: {len(gidx)} plane waves, grid {nf}")
+    ctx = P.Context(0)
+    got = ctx.project_orbitals_fft(kpts, cell, gidx, coef.cuda(), omega, pts, nf).cpu().numpy()
+    ref = pj.project_fft(coef.numpy(), kpts, cell, gidx, pts, omega, nf)
+    e = rel(got, ref)
+    say(f"  vs oracle FFT route {e:.2e}")
+    assert e < 1e-12
+    ctx.close()
+    # grid orbitals on a short support (direct-sum passes), the sheared cell and a non-cubic
+    # grid: chi0 on the grid from lrs_set_orbitals_pw against chi0 from the oracle's FFT grid
+    # times the Bloch phase, given to lrs_set_orbitals (the same site and site orbitals)
+    from workloads import sites as sx
+    small = gidx[(np.abs(gidx) <= 4).all(1)]
+    cs = coef[:, :, :len(small)].contiguous()
+    nfs = (20, 24, 27)
+    E = np.array([[-1.0, 0.5, 0.9], [-0.8, 0.6, 1.1]])
+    j = np.stack(np.meshgrid(*[np.arange(n) for n in nfs], indexing="ij"), -1).reshape(-1, 3)
+    x = (j / np.array(nfs)) @ cell
+    ref_grid = np.empty((nk, nb, len(j)), dtype=np.complex128)
+    for ik in range(nk):
+        ph = np.exp(1j * (x @ kpts[ik])) / np.sqrt(omega)
+        for b in range(nb):
+            ref_grid[ik, b] = pj.fft_grid(cs.numpy()[ik, b], small, nfs).reshape(-1) * ph
+    site = sx.make_site(np.array([2.0, 2.0, 2.0]), 4, 26)
+    psi_site = torch.complex(torch.randn((nk, nb, site.npts), dtype=torch.float64,
+                                         generator=torch.Generator().manual_seed(6)),
+                             torch.randn((nk, nb, site.npts), dtype=torch.float64,
+                                         generator=torch.Generator().manual_seed(7)))
+    out = []
+    for use_pw in (True, False):
+        c2 = P.Context(0)
+        if use_pw:
+            c2.set_orbitals_pw(E, 1, kpts, cell, small, cs.cuda(), omega, nfs)
+        else:
+            c2.set_orbitals(E, 1, torch.as_tensor(ref_grid), omega / np.prod(nfs))
+        c2.set_sites([site], psi_site)
+        c2.make_quadrature(P.QUAD_TIME, 16, 0.0)
+        out.append(c2.chi0(-1, P.COLS_GRID, P.FP64).cpu().numpy())
+        c2.close()
+    eg = rel(out[0], out[1])
+    say(f"  chi0 from lrs_set_orbitals_pw grid orbitals {nfs} vs the oracle's: {eg:.2e}")
+    assert eg < 1e-12
+
+
 def test_fft_projection_production_within_bound(P):
     """Production workload (2x2x2 k, 576 bands, 2007 plane waves, 2 sites of 800 points): the
     FFT route against the direct sum within each band's derived interpolation bound, and the
