@@ -32,12 +32,16 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAKS_TFLOPS = {"bf16x2": 2500.0, "fp16x2": 2500.0, "f16f8": 2500.0, "fp32": 157.3, "fp64": 78.6}
-DTYPE = {"bf16x2": "bf16", "fp16x2": "f16", "f16f8": "f16+f8", "fp32": "f32", "fp64": "f64"}
+PEAKS_TFLOPS = {"bf16x2": 2500.0, "fp16x2": 2500.0, "f16f8": 2500.0, "fp32": 157.3, "fp64": 78.6,
+                "fp64m3": 78.6}
+DTYPE = {"bf16x2": "bf16", "fp16x2": "f16", "f16f8": "f16+f8", "fp32": "f32", "fp64": "f64",
+         "fp64m3": "f64"}
 # matrix-core time per algorithmic product, in units of one product at the 2.5 PF/s dense
 # 16-bit rate: the split paths run hi*hi + hi*lo + lo*hi (3); F16F8 runs hi*hi on fp16 (1) and
-# both cross terms on one fp8 instruction of twice the K at twice the rate (1)
-EXEC_FACTOR = {"bf16x2": 3.0, "fp16x2": 3.0, "f16f8": 2.0, "fp32": 1.0, "fp64": 1.0}
+# both cross terms on one fp8 instruction of twice the K at twice the rate (1); the FP64 3M form
+# three real products for four
+EXEC_FACTOR = {"bf16x2": 3.0, "fp16x2": 3.0, "f16f8": 2.0, "fp32": 1.0, "fp64": 1.0,
+               "fp64m3": 0.75}
 SPLIT = ("bf16x2", "fp16x2", "f16f8")
 
 
@@ -319,9 +323,9 @@ def main():
     # every other precision once on the same launch: FP64 (the speedup and the error
     # statement), the split BF16 and FP16 paths, FP32
     paths, got_p = {}, {}
-    others = [x for x in ("fp64", "bf16x2", "fp16x2", "f16f8", "fp32") if x != prec]
-    if args.no_fp64 and "fp64" in others:
-        others.remove("fp64")
+    others = [x for x in ("fp64", "fp64m3", "bf16x2", "fp16x2", "f16f8", "fp32") if x != prec]
+    if args.no_fp64:
+        others = [x for x in others if x not in ("fp64", "fp64m3")]
     if args.no_fp16 and "fp16x2" in others:
         others.remove("fp16x2")
     if args.steps_only:

@@ -66,9 +66,12 @@ typedef enum {
   LRS_FP32 = 1,     /* FP32 matrix-core products, FP32 accumulation of G */
   LRS_BF16X2 = 2,   /* each operand split into bf16 hi + lo; hi*hi + hi*lo + lo*hi, FP32 accumulation */
   LRS_FP16X2 = 3,   /* the same with fp16 halves (operands prescaled by powers of two) */
-  LRS_F16F8 = 4     /* fp16 hi + lo split: hi*hi on fp16 matrix cores, the cross terms hi*lo +
+  LRS_F16F8 = 4,    /* fp16 hi + lo split: hi*hi on fp16 matrix cores, the cross terms hi*lo +
                        lo*hi on block-scaled fp8 (e4m3) ones, FP32 accumulation; two thirds of
                        the split paths' matrix-core time, relative error of order 1e-6 */
+  LRS_FP64_3M = 5   /* FP64 with three real products per complex one (the 3M form:
+                       p b_r, q b_i and (p - q)(b_r + b_i) give G_r and G_i) instead of four;
+                       forward chi0 only (lrs_compute_chi0) */
 } lrs_precision;
 
 typedef enum {

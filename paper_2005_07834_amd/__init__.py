@@ -21,10 +21,11 @@ LIB_PATH = os.path.join(_HERE, "liblrs.so")
 
 LRS_OK, LRS_EINVAL, LRS_ENOMEM, LRS_EDEVICE, LRS_ESTATE, LRS_ENOGAP, LRS_ENONFINITE, \
     LRS_EUNSUPPORTED = range(8)
-FP64, FP32, BF16X2, FP16X2, F16F8 = range(5)
+FP64, FP32, BF16X2, FP16X2, F16F8, FP64_3M = range(6)
 COLS_GRID, COLS_SITE = 0, 1
 QUAD_TIME, QUAD_FREQ = 0, 1
-PREC_NAMES = {"fp64": FP64, "fp32": FP32, "bf16x2": BF16X2, "fp16x2": FP16X2, "f16f8": F16F8}
+PREC_NAMES = {"fp64": FP64, "fp32": FP32, "bf16x2": BF16X2, "fp16x2": FP16X2, "f16f8": F16F8,
+              "fp64m3": FP64_3M}
 STATUS_NAMES = {0: "LRS_OK", 1: "LRS_EINVAL", 2: "LRS_ENOMEM", 3: "LRS_EDEVICE", 4: "LRS_ESTATE",
                 5: "LRS_ENOGAP", 6: "LRS_ENONFINITE", 7: "LRS_EUNSUPPORTED"}
 
@@ -509,5 +510,5 @@ def check_bands(energies, nocc, mu=float("nan"), delta=0.0):
     return lib.lrs_check_bands(E.shape[0], E.shape[1], nocc, _ptr(E), mu, delta)
 
 
-__all__ = ["lib", "Context", "LrsError", "check_bands", "Chi0Fn", "ScreenWFn", "FP64", "FP32", "BF16X2", "FP16X2", "F16F8",
+__all__ = ["lib", "Context", "LrsError", "check_bands", "Chi0Fn", "ScreenWFn", "FP64", "FP32", "BF16X2", "FP16X2", "F16F8", "FP64_3M",
            "COLS_GRID", "COLS_SITE", "QUAD_TIME", "QUAD_FREQ", "SIGNATURES"]

@@ -98,6 +98,12 @@ struct Prec<LRS_FP64> {
   using acc_t = f64x4;
   static constexpr int KC = 16, TB = 4096, BLK = 16, ELEMS = 4;
 };
+// three planes per operand tile: p, q, p - q (rows); b_r, b_i, b_r + b_i (columns)
+template <>
+struct Prec<LRS_FP64_3M> {
+  using acc_t = f64x4;
+  static constexpr int KC = 16, TB = 6144, BLK = 16, ELEMS = 4;
+};
 template <>
 struct Prec<LRS_FP32> {
   using acc_t = f32x4;
@@ -127,7 +133,7 @@ struct Prec<LRS_F16F8> {
 //   f32 32x32:   (8 (e/4) + 4 (lane/32) + e%4, lane%32)
 template <int PREC>
 __device__ __forceinline__ void elem_rc(int lane, int e, int& r, int& c) {
-  if constexpr (PREC == LRS_FP64) {
+  if constexpr (PREC == LRS_FP64 || PREC == LRS_FP64_3M) {
     r = 4 * e + (lane >> 4);
     c = lane & 15;
   } else if constexpr (PREC == LRS_FP32) {
@@ -153,6 +159,7 @@ __device__ __forceinline__ T zero_acc() {
 // lane slot) reads that slot's orbital values once and writes the slot of every plane for
 // each term in turn:
 //   FP64 (chunk 16, 64 slots):  slot l holds row l%16, k = 4 s + l/16, s = 0..3, planes p, q
+//                               (FP64 3M: a third plane p - q)
 //   FP32 (chunk 32, 64 slots):  slot l holds row l%16, k = 4 s + l/16, s = 0..7, planes p, q
 //   split (chunk 16, 32 slots): slot l holds row l%16, k = 8 (l/16) + e, e = 0..7,
 //                               planes p_hi, p_lo, q_hi, q_lo
@@ -226,7 +233,8 @@ __global__ void prep_site_kernel(const double* site, int rows_pad, int K_pad, co
   constexpr int KC = Prec<PREC>::KC, TB = Prec<PREC>::TB;
   constexpr bool SPLIT = PREC == LRS_BF16X2 || PREC == LRS_FP16X2;
   constexpr int SLOTS = SPLIT ? 32 : 64;
-  constexpr int NV = PREC == LRS_FP64 ? 4 : 8;     // values of the slot per plane
+  constexpr bool F64 = PREC == LRS_FP64 || PREC == LRS_FP64_3M;
+  constexpr int NV = F64 ? 4 : 8;     // values of the slot per plane
   const int nch = K_pad / KC;
   long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (long long)nrb * nch * SLOTS) return;
@@ -253,7 +261,7 @@ __global__ void prep_site_kernel(const double* site, int rows_pad, int K_pad, co
   for (int t = 0; t < nt; ++t) {
     const double* wt = w + (size_t)(t0 + t) * K_pad;
     unsigned char* base = out + (((size_t)t * nch + ch) * nrb + rb) * TB;
-    if constexpr (PREC == LRS_FP64) {
+    if constexpr (F64) {
       f64x4 vp, vq;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -263,6 +271,7 @@ __global__ void prep_site_kernel(const double* site, int rows_pad, int K_pad, co
       f64x4* d = (f64x4*)base;
       d[lane] = vp;
       d[64 + lane] = vq;
+      if constexpr (PREC == LRS_FP64_3M) d[128 + lane] = vp - vq;
     } else if constexpr (PREC == LRS_FP32) {
       float* d = (float*)base;
 #pragma unroll
@@ -303,6 +312,10 @@ struct Frags;
 template <int MB, int NB>
 struct Frags<LRS_FP64, MB, NB> {
   f64x4 p[MB], q[MB], br[NB], bi[NB];   // element s <-> k = 4 s + lane/16
+};
+template <int MB, int NB>
+struct Frags<LRS_FP64_3M, MB, NB> {
+  f64x4 p[MB], q[MB], d[MB], br[NB], bi[NB], bs[NB];
 };
 template <int MB, int NB>
 struct Frags<LRS_FP32, MB, NB> {
@@ -356,6 +369,19 @@ __device__ __forceinline__ void load_frags(const unsigned char* lds_a, const uns
     for (int j = 0; j < NB; ++j) {
       f.br[j] = *(const f64x4*)(lds_b + j * TB + lane * 32);
       f.bi[j] = *(const f64x4*)(lds_b + j * TB + 2048 + lane * 32);
+    }
+  } else if constexpr (PREC == LRS_FP64_3M) {
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+      f.p[i] = *(const f64x4*)(lds_a + i * TB + lane * 32);
+      f.q[i] = *(const f64x4*)(lds_a + i * TB + 2048 + lane * 32);
+      f.d[i] = *(const f64x4*)(lds_a + i * TB + 4096 + lane * 32);
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      f.br[j] = *(const f64x4*)(lds_b + j * TB + lane * 32);
+      f.bi[j] = *(const f64x4*)(lds_b + j * TB + 2048 + lane * 32);
+      f.bs[j] = *(const f64x4*)(lds_b + j * TB + 4096 + lane * 32);
     }
   } else if constexpr (PREC == LRS_FP32) {
 #pragma unroll
@@ -533,6 +559,36 @@ __device__ __forceinline__ void mma_frags(
   }
 }
 
+// FP64 3M: T1 = p b_r into gr, T2 = q b_i into gi, T3 = (p - q)(b_r + b_i) into gx, per
+// k-step of the chunk; combine_3m turns them into G_r = T1 + T2 and G_i = T3 - T1 + T2.
+template <int MB, int NB>
+__device__ __forceinline__ void mma_frags_3m(const Frags<LRS_FP64_3M, MB, NB>& f,
+                                             f64x4 (&gr)[MB][NB], f64x4 (&gi)[MB][NB],
+                                             f64x4 (&gx)[MB][NB]) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        gr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.p[i][s], f.br[j][s], gr[i][j], 0, 0, 0);
+        gi[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.q[i][s], f.bi[j][s], gi[i][j], 0, 0, 0);
+        gx[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.d[i][s], f.bs[j][s], gx[i][j], 0, 0, 0);
+      }
+}
+template <int MB, int NB>
+__device__ __forceinline__ void combine_3m(f64x4 (&gr)[MB][NB], f64x4 (&gi)[MB][NB],
+                                           const f64x4 (&gx)[MB][NB]) {
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const f64x4 t2 = gi[i][j];
+      gi[i][j] = gx[i][j] - gr[i][j] + t2;
+      gr[i][j] = gr[i][j] + t2;
+    }
+}
+
 // Split paths with rotating B fragments: the A fragments of a chunk are double-buffered, the B
 // fragments are single-buffered and refilled block column by block column: once the matrix-core
 // instructions of B block j have issued, block j is read again from the next chunk's slot.  This
@@ -643,9 +699,12 @@ __device__ __forceinline__ void interleave() {
   constexpr bool split = PREC == LRS_BF16X2 || PREC == LRS_FP16X2;
   constexpr bool f8 = PREC == LRS_F16F8;
   // instructions per step: LDS reads of 16 bytes, matrix-core instructions
-  constexpr int NDS = f8 ? 2 * MB + 3 * NB : (split ? 2 * (MB + NB) : 4 * (MB + NB));
+  constexpr bool m3 = PREC == LRS_FP64_3M;
+  constexpr int NDS = f8 ? 2 * MB + 3 * NB
+                         : (split ? 2 * (MB + NB) : (m3 ? 6 * (MB + NB) : 4 * (MB + NB)));
   constexpr int NMF = f8 ? 3 * MB * NB / 2
-                         : (split ? 3 * MB * NB : (PREC == LRS_FP64 ? 16 * MB * NB : 32 * MB * NB));
+                         : (split ? 3 * MB * NB
+                                  : (PREC == LRS_FP64 ? 16 * MB * NB : (m3 ? 12 * MB * NB : 32 * MB * NB)));
   constexpr int R = (NMF - NDS) / NVM > 0 ? (NMF - NDS) / NVM : 1;
   if constexpr (f8 && LOADS_FIRST) {
     static_assert(NDS % 2 == 0 && NDS / 2 + NVM <= NMF, "F16F8 step groups");
@@ -803,6 +862,8 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
     const long long base = tau - (blockIdx.x >> 3);   // the group's first tile this round
     const unsigned int members = (unsigned int)max(0LL, min((long long)gsz, P.ntiles - base));
     acc_t gr[AM][AN], gi[AM][AN];
+    // the third product of the 3M form (FP64 3M only; a placeholder otherwise)
+    acc_t gx[PREC == LRS_FP64_3M ? AM : 1][PREC == LRS_FP64_3M ? AN : 1];
     frag_t fa, fb;
     FragsB<PREC, NB> bfr;
 
@@ -857,10 +918,12 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
         if constexpr (IL == 0) {
           // LDS reads and loads first, then the matrix-core block
           __builtin_amdgcn_sched_barrier(0);
-          mma_frags<PREC, MB, NB>(cur, gr, gi);
+          if constexpr (PREC == LRS_FP64_3M) mma_frags_3m<MB, NB>(cur, gr, gi, gx);
+          else mma_frags<PREC, MB, NB>(cur, gr, gi);
         } else {
           // LDS reads and loads spread between the matrix-core instructions
-          mma_frags<PREC, MB, NB>(cur, gr, gi);
+          if constexpr (PREC == LRS_FP64_3M) mma_frags_3m<MB, NB>(cur, gr, gi, gx);
+          else mma_frags<PREC, MB, NB>(cur, gr, gi);
           interleave<PREC, MB, NB, LPW, S, IL == 2>();
         }
       }
@@ -883,6 +946,7 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
         for (int j = 0; j < AN; ++j) {
           gr[i][j] = zero_acc<acc_t>();
           gi[i][j] = zero_acc<acc_t>();
+          if constexpr (PREC == LRS_FP64_3M) gx[i][j] = zero_acc<acc_t>();
         }
     };
     for (int t = 0; t < P.T; ++t) {
@@ -900,6 +964,7 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
       }
       zero();
       for (int ch = 0; ch < P.nch_o; ch += S) cycle(ch == 0);
+      if constexpr (PREC == LRS_FP64_3M) combine_3m<MB, NB>(gr, gi, gx);
       {
         const int ln = opaque(lane);
 #pragma unroll
@@ -912,6 +977,7 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
       }
       zero();
       for (int ch = P.nch_o; ch < nch; ch += S) cycle(ch == P.nch_o);
+      if constexpr (PREC == LRS_FP64_3M) combine_3m<MB, NB>(gr, gi, gx);
       // here gr, gi hold G_u; G_o comes back block by block.  Per accumulator block every
       // global load is issued before the first use (elements outside the output take the
       // tile origin's address and skip the store), so the block costs one memory latency.
@@ -1065,6 +1131,12 @@ LRS_VARIANT(LRS_F16F8, 0, 2, 2, 4, 6, 4, 1, 0)
 LRS_VARIANT(LRS_F16F8, 1, 2, 2, 4, 4, 4, 1, 0)
 LRS_VARIANT(LRS_F16F8, 2, 2, 2, 4, 6, 4, 2, 0)
 LRS_VARIANT(LRS_F16F8, 3, 2, 2, 4, 4, 4, 0, 0)
+// FP64 3M: a third accumulator and operand plane per block, so 32 x 32 or 32 x 48 wave tiles
+// (stages of 48 KiB for 64 x 64, 60 KiB for 64 x 96: two slots)
+LRS_VARIANT(LRS_FP64_3M, 0, 2, 2, 2, 3, 2, 1, 0)
+LRS_VARIANT(LRS_FP64_3M, 1, 2, 2, 2, 2, 2, 1, 0)
+LRS_VARIANT(LRS_FP64_3M, 2, 2, 2, 2, 3, 2, 0, 0)
+LRS_VARIANT(LRS_FP64_3M, 3, 2, 2, 2, 2, 2, 0, 0)
 #undef LRS_VARIANT
 constexpr int kNumVariants = 4;
 
@@ -1176,6 +1248,7 @@ int chi0_blocks_per_cu(int prec, int variant) {
     case LRS_FP32: return occ_p<LRS_FP32>(variant);
     case LRS_BF16X2: return occ_p<LRS_BF16X2>(variant);
     case LRS_F16F8: return occ_p<LRS_F16F8>(variant);
+    case LRS_FP64_3M: return occ_p<LRS_FP64_3M>(variant);
     default: return occ_p<LRS_FP16X2>(variant);
   }
 }
@@ -1186,6 +1259,7 @@ TileShape chi0_shape(int prec, int variant) {
     case LRS_FP32: return shape_p<LRS_FP32>(variant);
     case LRS_BF16X2: return shape_p<LRS_BF16X2>(variant);
     case LRS_F16F8: return shape_p<LRS_F16F8>(variant);
+    case LRS_FP64_3M: return shape_p<LRS_FP64_3M>(variant);
     default: return shape_p<LRS_FP16X2>(variant);
   }
 }
@@ -1199,6 +1273,7 @@ hipError_t launch_prep_site(int prec, const double* site, int rows_pad, int K_pa
     case LRS_BF16X2: return prep_p<LRS_BF16X2>(site, rows_pad, K_pad, slot_row, rb0, nrb, w, t0, nt, a_scale, out, s);
     case LRS_FP16X2: return prep_p<LRS_FP16X2>(site, rows_pad, K_pad, slot_row, rb0, nrb, w, t0, nt, a_scale, out, s);
     case LRS_F16F8: return prep_p<LRS_F16F8>(site, rows_pad, K_pad, slot_row, rb0, nrb, w, t0, nt, a_scale, out, s);
+    case LRS_FP64_3M: return prep_p<LRS_FP64_3M>(site, rows_pad, K_pad, slot_row, rb0, nrb, w, t0, nt, a_scale, out, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1236,6 +1311,7 @@ hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int
     case LRS_BF16X2: return launch_p<LRS_BF16X2>(variant, grid, P, s);
     case LRS_FP16X2: return launch_p<LRS_FP16X2>(variant, grid, P, s);
     case LRS_F16F8: return launch_p<LRS_F16F8>(variant, grid, P, s);
+    case LRS_FP64_3M: return launch_p<LRS_FP64_3M>(variant, grid, P, s);
   }
   return hipErrorInvalidValue;
 }

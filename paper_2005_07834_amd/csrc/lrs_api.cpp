@@ -987,7 +987,7 @@ lrs_status lrs_compute_chi0(lrs_ctx* ctx, int site, int cols, int prec, double* 
   if (!out) return fail(ctx, LRS_EINVAL, "chi0_out is NULL");
   if (site < -1 || site >= ctx->nsites) return fail(ctx, LRS_EINVAL, "site %d out of range", site);
   if (cols != LRS_COLS_GRID && cols != LRS_COLS_SITE) return fail(ctx, LRS_EINVAL, "bad column set");
-  if (prec < LRS_FP64 || prec > LRS_F16F8) return fail(ctx, LRS_EINVAL, "bad precision");
+  if (prec < LRS_FP64 || prec > LRS_FP64_3M) return fail(ctx, LRS_EINVAL, "bad precision");
   if (cols == LRS_COLS_GRID && ctx->ngrid <= 0) return fail(ctx, LRS_ESTATE, "no grid orbitals were given");
   int cur = -1;
   HIP_OR_FAIL(ctx, hipGetDevice(&cur));
@@ -1039,7 +1039,7 @@ lrs_status lrs_tune(lrs_ctx* ctx, int prec) {
   ctx->err.clear();
   if (!ctx->have_bands || !ctx->have_sites || !ctx->have_quad)
     return fail(ctx, LRS_ESTATE, "orbitals, sites and quadrature must be set first");
-  if (prec < LRS_FP64 || prec > LRS_F16F8) return fail(ctx, LRS_EINVAL, "bad precision");
+  if (prec < LRS_FP64 || prec > LRS_FP64_3M) return fail(ctx, LRS_EINVAL, "bad precision");
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
   int s = 0;
   for (int k = 1; k < ctx->nsites; ++k)
@@ -1113,7 +1113,7 @@ lrs_status lrs_tune(lrs_ctx* ctx, int prec) {
 lrs_status lrs_tuned_variant(const lrs_ctx* ctx, int prec, int cols, int* variant_host,
                              int* tile_rows_host, int* tile_cols_host) {
   if (!ctx || !variant_host) return LRS_EINVAL;
-  if (prec < LRS_FP64 || prec > LRS_F16F8 || (cols != LRS_COLS_GRID && cols != LRS_COLS_SITE))
+  if (prec < LRS_FP64 || prec > LRS_FP64_3M || (cols != LRS_COLS_GRID && cols != LRS_COLS_SITE))
     return LRS_EINVAL;
   const int v = pick_variant(const_cast<lrs_ctx*>(ctx), prec, cols);
   *variant_host = v;

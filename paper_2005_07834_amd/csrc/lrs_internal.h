@@ -31,7 +31,7 @@ constexpr int kMaxTerms = 128;
 __host__ __device__ inline bool is_split(int prec) { return prec == LRS_BF16X2 || prec == LRS_FP16X2; }
 // operands carry fp16 values prescaled by a power of two (FP16X2 and F16F8)
 __host__ __device__ inline bool is_f16(int prec) { return prec == LRS_FP16X2 || prec == LRS_F16F8; }
-constexpr int kNumPrec = 5;
+constexpr int kNumPrec = 6;
 // leading dimension of a site's n x n block: n for chi0 outputs, n rounded up to kAdjAlign for
 // the adjoint's internal site blocks (plan mode 1): a whole number of four-chunk ring cycles
 // of the adjoint GEMMs' contraction, whose padding is zero
@@ -42,7 +42,7 @@ inline int site_block_ld(int n, int mode) {
 // K values per chunk and bytes per fragment tile (16 rows x chunk x planes)
 __host__ __device__ inline int chunk_of(int prec) { return prec == LRS_FP32 ? 32 : 16; }
 __host__ __device__ inline int tile_bytes(int prec) {
-  return is_split(prec) || prec == LRS_F16F8 ? 2048 : 4096;
+  return is_split(prec) || prec == LRS_F16F8 ? 2048 : (prec == LRS_FP64_3M ? 6144 : 4096);
 }
 // F16F8 fragment tiles (16 rows x 16 K, 2 KiB; a 32-row block is two consecutive tiles):
 //   [0, 1024)    fp16 hi: planes re, im, 512 B each, slot s holding row s%16 and
@@ -191,7 +191,8 @@ struct lrs_ctx {
   // plans
   std::map<long long, lrs::Plan> plans;
   // variant chosen by lrs_tune per (precision, column set); -1 = the default
-  int tuned_variant[lrs::kNumPrec][2] = {{-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}};
+  int tuned_variant[lrs::kNumPrec][2] = {{-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1},
+                                         {-1, -1}};
 
   // screening state
   lrs::DevBuf W_last, rho_last, screen_tab, work, adj_work, val_work, fft_work;

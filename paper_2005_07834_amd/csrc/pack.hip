@@ -118,13 +118,15 @@ __global__ void pack_tiles_kernel(Src src, long long ntiles, int ncb, int prec,
   unsigned char* base = out + tile * (long long)tile_bytes(prec);
   if (prec == LRS_F16F8) {
     pack_f16f8_column(src, c, ch * 16 + 8 * (lane >> 4), prescale, base, lane >> 4);
-  } else if (prec == LRS_FP64) {
+  } else if (prec == LRS_FP64 || prec == LRS_FP64_3M) {
+    // (3M: a third plane b_r + b_i, the column side's factor of the third product)
     double* t = reinterpret_cast<double*>(base);
     for (int s = 0; s < 4; ++s) {
       double re, im;
       src.get(c, ch * 16 + 4 * s + (lane >> 4), re, im);
       t[lane * 4 + s] = re;
       t[256 + lane * 4 + s] = im;
+      if (prec == LRS_FP64_3M) t[512 + lane * 4 + s] = re + im;
     }
   } else if (prec == LRS_FP32) {
     float* t = reinterpret_cast<float*>(base);

@@ -97,7 +97,7 @@ def test_tiny_fp64_parity(P, tiny_ref):
 
 
 @pytest.mark.parametrize("prec,tol", [("bf16x2", 1e-4), ("fp32", 1e-5), ("fp16x2", 1e-5),
-                                      ("f16f8", 1e-4)])
+                                      ("f16f8", 1e-4), ("fp64m3", 1e-12)])
 def test_tiny_reduced_precision(P, tiny_ref, prec, tol):
     w = tiny_ref["w"]
     say("tiny", prec)

@@ -70,7 +70,8 @@ def sampled(F, out):
 
 
 @pytest.mark.parametrize("prec,tq,tx", [("bf16x2", 1e-4, 1e-4), ("fp16x2", 1e-4, 1e-4),
-                                        ("f16f8", 1e-4, 1e-4), ("fp64", 1e-12, 1e-6)])
+                                        ("f16f8", 1e-4, 1e-4), ("fp64", 1e-12, 1e-6),
+                                        ("fp64m3", 1e-12, 1e-6)])
 def test_grid_launch_sampled(full, prec, tq, tx):
     """The site x grid launch (the benchmark's headline launch), every precision of the
     bench line, with the library's own scale choice equal to the oracle's."""
@@ -87,7 +88,8 @@ def test_grid_launch_sampled(full, prec, tq, tx):
 
 def test_site_block_sampled_and_symmetric(full):
     """The site x site launch (upper-triangle tiles, mirrored): sampled entries and their
-    transposes against the oracle (BF16X2 and FP64), and the block exactly symmetric."""
+    transposes against the oracle (BF16X2, FP64 and FP64 3M), and the block exactly
+    symmetric."""
     F = full
     P, ctx, w = F["P"], F["ctx"], F["w"]
     ctx.make_quadrature(P.QUAD_TIME, w.n_terms, 0.0)
@@ -97,7 +99,7 @@ def test_site_block_sampled_and_symmetric(full):
     rr, cc = np.concatenate([r, c]), np.concatenate([c, r])
     ps_all = w.psi_site.cpu().numpy()
     ref = cz.chi0_quad_entries(ps_all[:, :, rr], ps_all[:, :, cc], w.nocc, 2, *F["terms"])
-    for prec, tol in [("bf16x2", 1e-4), ("fp64", 1e-12)]:
+    for prec, tol in [("bf16x2", 1e-4), ("fp64", 1e-12), ("fp64m3", 1e-12)]:
         blk = ctx.site_blocks(ctx.chi0(-1, P.COLS_SITE, prec))[0]
         e = rel(blk[torch.as_tensor(rr, device="cuda"), torch.as_tensor(cc, device="cuda")]
                 .cpu().numpy(), ref)
