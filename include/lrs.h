@@ -276,7 +276,7 @@ lrs_status lrs_release_graphs(lrs_ctx* ctx);
  *   rho_test   optional float64 [sum npts] test charge at the site points (NULL = none).
  *   loss_out   optional float64 [nsites]: rho_L^T D W D rho_L, rho_L = P rho (needs rho_test).
  * Keeps W (and rho_test) for lrs_screen_W_backward.  Asynchronous.  LRS_EUNSUPPORTED when a
- * site has more than 288 basis functions (n_rad > 32) or 256 directions. */
+ * site has more than 448 basis functions (n_rad > 49 at lmax 2) or 256 directions. */
 lrs_status lrs_screen_W(lrs_ctx* ctx, const double* chi0_sitesite, double* W_out,
                         const double* rho_test, double* loss_out);
 
@@ -286,7 +286,8 @@ lrs_status lrs_screen_W(lrs_ctx* ctx, const double* chi0_sitesite, double* W_out
  * workspace in a fixed device array of 64 MiB that each GPU holds until the process ends, so the
  * call allocates and frees nothing.  The caller passes inputs and outputs as for lrs_screen_W.
  * LRS_ENOMEM when the sites need more scratch than the array holds (3 n^2 + n doubles per site
- * plus the tables, so up to about 100 sites of 288 basis functions), LRS_EUNSUPPORTED beyond
+ * plus the tables, so up to about 100 sites of 288 basis functions or 40 of 448),
+ * LRS_EUNSUPPORTED beyond
  * the solve's limits as lrs_screen_W.  It keeps no state for lrs_screen_W_backward.  It copies
  * host tables into the array and synchronises the stream: LRS_ESTATE under stream capture.
  * Every call on one GPU shares that GPU's array, which keeps the last call's contents: calls
@@ -308,7 +309,7 @@ lrs_status lrs_screen_W_noalloc(lrs_ctx* ctx, const double* chi0_sitesite, doubl
  *                  q (1/r - 1/r_shell) for r < r_shell, 0 beyond
  *   rho_out, v_out float64 [sum n], n = (lmax+1)^2 n_rad per site, L-major, device.
  * Requires lrs_set_sites.  Synchronous in its host part; LRS_ESTATE under stream capture,
- * LRS_EUNSUPPORTED when a site has more than 288 basis functions or 256 directions. */
+ * LRS_EUNSUPPORTED when a site has more than 448 basis functions or 256 directions. */
 lrs_status lrs_induced_potential(lrs_ctx* ctx, const double* chi0_sitesite, const double* v1_host,
                                  double q, double r_shell, int l0_only, double* rho_out,
                                  double* v_out);

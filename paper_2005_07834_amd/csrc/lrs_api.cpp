@@ -1131,7 +1131,7 @@ lrs_status lrs_screen_W(lrs_ctx* ctx, const double* chi0_ss, double* W_out, cons
   if (!chi0_ss || !W_out) return fail(ctx, LRS_EINVAL, "chi0 and W_out are required");
   if (loss_out && !rho) return fail(ctx, LRS_EINVAL, "loss_out needs rho_test");
   if (!screen_sizes_ok(ctx))
-    return fail(ctx, LRS_EUNSUPPORTED, "a site basis exceeds 288 functions or 256 directions");
+    return fail(ctx, LRS_EUNSUPPORTED, "a site basis exceeds 448 functions or 256 directions");
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
   hipError_t e = launch_screen_forward(ctx, chi0_ss, W_out, rho, loss_out);
   if (e == hipErrorOutOfMemory) return fail(ctx, LRS_ENOMEM, "screening workspace");

@@ -275,6 +275,9 @@ lrs_status ensure_park(lrs_ctx* ctx, int prec, int variant, int grid);
 // screen.hip
 // size of the fixed device array that holds the tables and workspace of lrs_screen_W_noalloc
 constexpr size_t kScratchBytes = (size_t)64 << 20;
+// the per-site solves' limits: basis functions n = (lmax + 1)^2 n_rad (49 shells at lmax 2) and
+// directions per shell
+constexpr int kMaxBasis = 448, kMaxDirections = 256;
 hipError_t scratch_setup(int device);
 bool screen_sizes_ok(const lrs_ctx* ctx);
 hipError_t launch_screen_forward(lrs_ctx* ctx, const double* chi0_ss, double* W_out,

@@ -55,7 +55,7 @@ __device__ inline int l_of(int L) { return L == 0 ? 0 : (L < 4 ? 1 : 2); }
 // X block (i, j) of one site: one workgroup per (site, i, j)
 __global__ void project_kernel(ScreenTabs T, const int4* blocks, const double* chi0,
                                double* X) {
-  __shared__ double t1[9 * 4096 / 16];   // nL x nang, nang <= 256
+  __shared__ double t1[9 * kMaxDirections];   // nL x nang
   const int4 bk = blocks[blockIdx.x];
   const SiteMeta m = T.meta[bk.x];
   const int i = bk.y, j = bk.z, A = m.nang, nL = m.nL;
@@ -113,7 +113,10 @@ __global__ void eps_kernel(ScreenTabs T, const int2* rows, const double* X, doub
 // final row order, takes the panel's nb elimination steps in registers and is written back
 // (a wave updates four columns at a time, sharing the multipliers read from LDS).  The columns
 // left of the panel are unit vectors by then and are not touched again.
-constexpr int GJ_NB = 16, GJ_MAXN = 288, GJ_SLOTS = (GJ_MAXN + 63) / 64, GJ_COLS = 4;
+// SLOTS 64-row slots of each column in registers: 5 (n <= 320) or 7 (n <= kMaxBasis; a few
+// registers then spill, so sites that fit take the smaller form)
+constexpr int GJ_NB = 16, GJ_COLS = 4;
+static_assert(7 * 64 >= kMaxBasis, "the larger form holds every basis");
 static_assert(64 % GJ_NB == 0, "a panel's rows must lie in one 64-row slot");
 static_assert(1024 / 64 >= GJ_NB, "one wave per panel column");
 
@@ -128,9 +131,9 @@ __device__ __forceinline__ double gj_readlane(double v, int l) {
 // x[.][t].  Panels start at multiples of GJ_NB, so the panel's rows lie in one slot S of every
 // column: the pivot-row value of step k is a read of lane (j0 + k) % 64 of x[.][S], and only
 // slot S needs the pivot-row case.
-template <int S>
-__device__ __forceinline__ void gj_panel_steps(double (&x)[GJ_COLS][GJ_SLOTS],
-                                               const double (*pan)[GJ_MAXN], const double* inv_s,
+template <int S, int SLOTS>
+__device__ __forceinline__ void gj_panel_steps(double (&x)[GJ_COLS][SLOTS],
+                                               const double (*pan)[SLOTS * 64], const double* inv_s,
                                                int j0, int nb, int n, int lane) {
   for (int k = 0; k < nb; ++k) {
     const int col = j0 + k, l = col & 63;
@@ -139,7 +142,7 @@ __device__ __forceinline__ void gj_panel_steps(double (&x)[GJ_COLS][GJ_SLOTS],
 #pragma unroll
     for (int q = 0; q < GJ_COLS; ++q) xp[q] = gj_readlane(x[q][S], l) * inv;
 #pragma unroll
-    for (int t = 0; t < GJ_SLOTS; ++t) {
+    for (int t = 0; t < SLOTS; ++t) {
       const int r = lane + 64 * t;
       const double f = r < n ? pan[k][r] : 0.0;
 #pragma unroll
@@ -151,9 +154,11 @@ __device__ __forceinline__ void gj_panel_steps(double (&x)[GJ_COLS][GJ_SLOTS],
   }
 }
 
+template <int SLOTS>
 __global__ void __launch_bounds__(1024) gauss_jordan_kernel(ScreenTabs T, double* M, int mode,
                                                             double* out,
                                                             const long long* w_out_off) {
+  constexpr int GJ_MAXN = SLOTS * 64;
   __shared__ double pan[GJ_NB][GJ_MAXN];
   __shared__ int perm[GJ_MAXN];
   __shared__ double inv_s[GJ_NB];
@@ -222,25 +227,31 @@ __global__ void __launch_bounds__(1024) gauss_jordan_kernel(ScreenTabs T, double
     // the later columns, GJ_COLS per wave at a time
     const int c0 = j0 + nb;
     for (int g = c0 + wave * GJ_COLS; g < n2; g += nw * GJ_COLS) {
-      double x[GJ_COLS][GJ_SLOTS];
+      double x[GJ_COLS][SLOTS];
 #pragma unroll
       for (int q = 0; q < GJ_COLS; ++q)
 #pragma unroll
-        for (int t = 0; t < GJ_SLOTS; ++t) {
+        for (int t = 0; t < SLOTS; ++t) {
           const int r = lane + 64 * t;
           x[q][t] = (g + q < n2 && r < n) ? A[(long long)(g + q) * n + perm[r]] : 0.0;
         }
       switch (j0 >> 6) {
-        case 0: gj_panel_steps<0>(x, pan, inv_s, j0, nb, n, lane); break;
-        case 1: gj_panel_steps<1>(x, pan, inv_s, j0, nb, n, lane); break;
-        case 2: gj_panel_steps<2>(x, pan, inv_s, j0, nb, n, lane); break;
-        case 3: gj_panel_steps<3>(x, pan, inv_s, j0, nb, n, lane); break;
-        default: gj_panel_steps<4>(x, pan, inv_s, j0, nb, n, lane); break;
+        case 0: gj_panel_steps<0, SLOTS>(x, pan, inv_s, j0, nb, n, lane); break;
+        case 1: gj_panel_steps<1, SLOTS>(x, pan, inv_s, j0, nb, n, lane); break;
+        case 2: gj_panel_steps<2, SLOTS>(x, pan, inv_s, j0, nb, n, lane); break;
+        case 3: gj_panel_steps<3, SLOTS>(x, pan, inv_s, j0, nb, n, lane); break;
+        case 4: gj_panel_steps<4, SLOTS>(x, pan, inv_s, j0, nb, n, lane); break;
+        case 5:
+          if constexpr (SLOTS > 5) gj_panel_steps<5, SLOTS>(x, pan, inv_s, j0, nb, n, lane);
+          break;
+        default:
+          if constexpr (SLOTS > 6) gj_panel_steps<6, SLOTS>(x, pan, inv_s, j0, nb, n, lane);
+          break;
       }
 #pragma unroll
       for (int q = 0; q < GJ_COLS; ++q)
 #pragma unroll
-        for (int t = 0; t < GJ_SLOTS; ++t) {
+        for (int t = 0; t < SLOTS; ++t) {
           const int r = lane + 64 * t;
           if (g + q < n2 && r < n) A[(long long)(g + q) * n + r] = x[q][t];
         }
@@ -526,7 +537,7 @@ __global__ void alda_pass2(ScreenTabs T, const double* Tm, double* W_out,
 // rho_L = P rho and h = D rho_L for one site; optional loss h^T W h
 __global__ void charge_kernel(ScreenTabs T, const double* rho, const double* W,
                               const long long* w_out_off, double* h_out, double* loss) {
-  __shared__ double h[288 + 32];
+  __shared__ double h[kMaxBasis + 32];
   __shared__ double part[1024 / 64];
   const SiteMeta m = T.meta[blockIdx.x];
   const int R = m.nrad, A = m.nang, n = m.n;
@@ -601,7 +612,7 @@ __global__ void wtgw_pass2(ScreenTabs T, const double* W, const long long* w_out
 
 // dL/dchi0 block (i, j) = sum_{L,L'} yw[L][a] dX[(L,i),(L',j)] yw[L'][b]
 __global__ void lambda_kernel(ScreenTabs T, const int4* blocks, const double* dX, double* out) {
-  __shared__ double u1[9 * 256];
+  __shared__ double u1[9 * kMaxDirections];
   __shared__ double dxb[81];
   const int4 bk = blocks[blockIdx.x];
   const SiteMeta m = T.meta[bk.x];
@@ -781,9 +792,9 @@ hipError_t launch_screen_forward(lrs_ctx* ctx, const double* chi0_ss, double* W_
                                  const double* rho, double* loss_out) {
   HostTabs H;
   build_tabs(ctx, H);
-  if (H.max_n > 288) return hipErrorInvalidValue;
+  if (H.max_n > kMaxBasis) return hipErrorInvalidValue;
   for (const auto& m : H.meta)
-    if (m.nang > 256) return hipErrorInvalidValue;
+    if (m.nang > kMaxDirections) return hipErrorInvalidValue;
   DevTabs D;
   hipError_t e = upload_tabs(ctx, H, D);
   if (e != hipSuccess) return e;
@@ -797,7 +808,8 @@ hipError_t launch_screen_forward(lrs_ctx* ctx, const double* chi0_ss, double* W_
   hipLaunchKernelGGL(project_kernel, dim3(D.nblocks), dim3(256), 0, ctx->stream, D.t, D.blocks,
                      chi0_ss, X);
   hipLaunchKernelGGL(eps_kernel, dim3(D.nrows), dim3(256), 0, ctx->stream, D.t, D.rows, X, M);
-  hipLaunchKernelGGL(gauss_jordan_kernel, dim3(ctx->nsites), dim3(1024), 0, ctx->stream, D.t, M,
+  hipLaunchKernelGGL(H.max_n <= 320 ? gauss_jordan_kernel<5> : gauss_jordan_kernel<7>,
+                     dim3(ctx->nsites), dim3(1024), 0, ctx->stream, D.t, M,
                      0, W_out, D.w_out_off);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -847,9 +859,9 @@ static hipError_t launch_induced(lrs_ctx* ctx, const double* chi0_ss, const doub
                           double* rho_out, double* v_out) {
   HostTabs H;
   build_tabs(ctx, H);
-  if (H.max_n > 288) return hipErrorInvalidValue;
+  if (H.max_n > kMaxBasis) return hipErrorInvalidValue;
   for (const auto& m : H.meta)
-    if (m.nang > 256) return hipErrorInvalidValue;
+    if (m.nang > kMaxDirections) return hipErrorInvalidValue;
   DevTabs D;
   hipError_t e = upload_tabs(ctx, H, D);
   if (e != hipSuccess) return e;
@@ -867,7 +879,8 @@ static hipError_t launch_induced(lrs_ctx* ctx, const double* chi0_ss, const doub
                      chi0_ss, X);
   hipLaunchKernelGGL(induced_rows_kernel, dim3(D.nrows), dim3(256), 0, ctx->stream, D.t, D.rows,
                      X, v1, l0, M);
-  hipLaunchKernelGGL(gauss_jordan_kernel, dim3(ctx->nsites), dim3(1024), 0, ctx->stream, D.t, M,
+  hipLaunchKernelGGL(H.max_n <= 320 ? gauss_jordan_kernel<5> : gauss_jordan_kernel<7>,
+                     dim3(ctx->nsites), dim3(1024), 0, ctx->stream, D.t, M,
                      l0 ? 2 : 1, y, D.w_out_off);
   hipLaunchKernelGGL(induced_out_kernel, dim3(ctx->nsites), dim3(256), 0, ctx->stream, D.t, X, y,
                      v1, l0, rho_out, v_out);
@@ -880,9 +893,9 @@ static hipError_t launch_alda(lrs_ctx* ctx, const double* chi0_ss, const double*
                               double* W_out) {
   HostTabs H;
   build_tabs(ctx, H);
-  if (H.max_n > 288) return hipErrorInvalidValue;
+  if (H.max_n > kMaxBasis) return hipErrorInvalidValue;
   for (const auto& m : H.meta)
-    if (m.nang > 256) return hipErrorInvalidValue;
+    if (m.nang > kMaxDirections) return hipErrorInvalidValue;
   DevTabs D;
   hipError_t e = upload_tabs(ctx, H, D);
   if (e != hipSuccess) return e;
@@ -901,7 +914,8 @@ static hipError_t launch_alda(lrs_ctx* ctx, const double* chi0_ss, const double*
   hipLaunchKernelGGL(contact_kernel, dim3(H.max_n / nL, ctx->nsites), dim3(64), 0, st, D.t, f, F);
   hipLaunchKernelGGL(project_kernel, dim3(D.nblocks), dim3(256), 0, st, D.t, D.blocks, chi0_ss, X);
   hipLaunchKernelGGL(alda_rows_kernel, dim3(D.nrows), dim3(256), 0, st, D.t, D.rows, X, F, M);
-  hipLaunchKernelGGL(gauss_jordan_kernel, dim3(ctx->nsites), dim3(1024), 0, st, D.t, M, 0, Y,
+  hipLaunchKernelGGL(H.max_n <= 320 ? gauss_jordan_kernel<5> : gauss_jordan_kernel<7>,
+                     dim3(ctx->nsites), dim3(1024), 0, st, D.t, M, 0, Y,
                      D.w_out_off);
   dim3 grid(H.max_n, ctx->nsites);
   hipLaunchKernelGGL(alda_pass1, grid, dim3(256), 0, st, D.t, X, Y, Tm);
@@ -973,13 +987,13 @@ static hipError_t launch_valence(lrs_ctx* ctx, const double* chi0_ss, const doub
   return hipGetLastError();
 }
 
-// Host-side check of the solve kernels' limits: n = (lmax+1)^2 n_rad <= 288 basis functions
-// (the Gauss-Jordan kernel's register slots) and at most 256 directions per site (the
-// projection's LDS table).
+// Host-side check of the solve kernels' limits: n = (lmax+1)^2 n_rad <= kMaxBasis basis
+// functions (the Gauss-Jordan kernel's register slots) and at most kMaxDirections directions
+// per site (the projection's LDS table).
 bool screen_sizes_ok(const lrs_ctx* ctx) {
   const int nL = (ctx->lmax + 1) * (ctx->lmax + 1);
   for (int s = 0; s < ctx->nsites; ++s)
-    if (nL * ctx->nrad[s] > 288 || ctx->nang[s] > 256) return false;
+    if (nL * ctx->nrad[s] > kMaxBasis || ctx->nang[s] > kMaxDirections) return false;
   return true;
 }
 
@@ -1010,7 +1024,7 @@ extern "C" lrs_status lrs_screen_W_alda(lrs_ctx* ctx, const double* chi0_sitesit
     return LRS_ESTATE;
   }
   if (!screen_sizes_ok(ctx)) {
-    ctx->err = "a site basis exceeds 288 functions or 256 directions";
+    ctx->err = "a site basis exceeds 448 functions or 256 directions";
     return LRS_EUNSUPPORTED;
   }
   const hipError_t e = launch_alda(ctx, chi0_sitesite, density, W_out);
@@ -1069,7 +1083,7 @@ extern "C" lrs_status lrs_induced_potential(lrs_ctx* ctx, const double* chi0_sit
     return LRS_ESTATE;
   }
   if (!screen_sizes_ok(ctx)) {
-    ctx->err = "a site basis exceeds 288 functions or 256 directions";
+    ctx->err = "a site basis exceeds 448 functions or 256 directions";
     return LRS_EUNSUPPORTED;
   }
   const hipError_t e = launch_induced(ctx, chi0_sitesite, v1.data(), l0_only != 0, rho_out, v_out);
@@ -1135,7 +1149,7 @@ extern "C" lrs_status lrs_valence_W(lrs_ctx* ctx, const double* chi0_sitesite,
     }
   }
   if (!screen_sizes_ok(ctx)) {
-    ctx->err = "a site basis exceeds 288 functions or 256 directions";
+    ctx->err = "a site basis exceeds 448 functions or 256 directions";
     return LRS_EUNSUPPORTED;
   }
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -1251,7 +1265,7 @@ extern "C" lrs_status lrs_screen_W_noalloc(lrs_ctx* ctx, const double* chi0_site
     return LRS_EINVAL;
   }
   if (!screen_sizes_ok(ctx)) {
-    ctx->err = "a site basis exceeds 288 functions or 256 directions";
+    ctx->err = "a site basis exceeds 448 functions or 256 directions";
     return LRS_EUNSUPPORTED;
   }
   HostTabs H;
@@ -1306,7 +1320,8 @@ extern "C" lrs_status lrs_screen_W_noalloc(lrs_ctx* ctx, const double* chi0_site
     hipLaunchKernelGGL(project_kernel, dim3(D.nblocks), dim3(256), 0, st, D.t, D.blocks,
                        chi0_sitesite, X);
     hipLaunchKernelGGL(eps_kernel, dim3(D.nrows), dim3(256), 0, st, D.t, D.rows, X, M);
-    hipLaunchKernelGGL(gauss_jordan_kernel, dim3(ctx->nsites), dim3(1024), 0, st, D.t, M, 0,
+    hipLaunchKernelGGL(H.max_n <= 320 ? gauss_jordan_kernel<5> : gauss_jordan_kernel<7>,
+                     dim3(ctx->nsites), dim3(1024), 0, st, D.t, M, 0,
                        W_out, D.w_out_off);
     if (rho_test)
       hipLaunchKernelGGL(charge_kernel, dim3(ctx->nsites), dim3(256), 0, st, D.t, rho_test,

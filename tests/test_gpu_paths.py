@@ -565,9 +565,9 @@ def test_size_limits_refused(P):
                              xyz.ctypes.data_as(C.c_void_p), one.ctypes.data_as(C.c_void_p),
                              C.c_void_p(psi.data_ptr()), 3)
     assert st == P.LRS_EINVAL                     # lmax above 2
-    # a site of 33 shells (297 basis functions) is accepted for chi0 but not by the solves
+    # a site of 50 shells (450 basis functions) is accepted for chi0 but not by the solves
     from workloads import sites as sx
-    big = sx.make_site(np.zeros(3), 33, 26)
+    big = sx.make_site(np.zeros(3), 50, 26)
     g = torch.Generator(device="cuda").manual_seed(5)
     psi_big = torch.complex(torch.randn((1, w.energies.shape[1], big.npts), dtype=torch.float64,
                                         device="cuda", generator=g),
@@ -582,6 +582,45 @@ def test_size_limits_refused(P):
             call()
         assert e.value.status == P.LRS_EUNSUPPORTED, name
     say("  size limits refused")
+    ctx.close()
+
+
+@pytest.mark.parametrize("nrad", [36, 48])
+def test_solves_large_sites(P, nrad):
+    """Sites of 36 and 48 shells x 26 directions (n = 324 and 432 basis functions: the larger
+    Gauss-Jordan form, the paper's 48-shell sites) with a seeded negative semidefinite chi0
+    block: W and its test-charge loss, and the induced potential (full and l = 0), against the
+    oracle's solves on the same block (1e-10)."""
+    from oracle import screen as sc
+    from workloads import sites as sx
+    site = sx.make_site(np.zeros(3), nrad, 26, r_max=6.0)
+    n = site.npts
+    rng = np.random.default_rng(nrad)
+    B = rng.normal(size=(n, 96)) * 0.03
+    chi = -(B @ B.T)
+    rho = rng.normal(size=n)
+    say(f"solves at {nrad} shells ({9 * nrad} basis functions, {n} points)")
+    ctx = P.Context(0)
+    nb = 4
+    ctx.set_orbitals(np.array([[-1.0, -0.5, 0.5, 1.0]]), 2)
+    psi = torch.zeros((1, nb, n), dtype=torch.complex128, device="cuda")
+    ctx.set_sites([site], psi)
+    chi_d = torch.as_tensor(chi.ravel(), device="cuda")
+    W, loss = ctx.screen_W(chi_d, rho=torch.as_tensor(rho, device="cuda"), want_loss=True)
+    Wref = sc.screen_W(chi, site)
+    Lref = sc.test_charge_loss(Wref, rho, site)
+    eW = rel(ctx.W_blocks(W)[0].cpu().numpy(), Wref)
+    eL = abs(loss.item() / Lref - 1)
+    say(f"  W {eW:.2e}, loss {eL:.2e}")
+    assert eW < 1e-10 and eL < 1e-10
+    for l0 in (False, True):
+        rho_i, v_i = ctx.induced_potential(chi_d, q=1.0, r_shell=1.5, l0_only=l0)
+        v1 = np.where(site.radii < 1.5, 1.0 / site.radii - 1.0 / 1.5, 0.0)
+        rref, vref = sc.induced(chi, site, v1, 2, l0_only=l0)
+        er = rel(rho_i.cpu().numpy(), rref)
+        ev = rel(v_i.cpu().numpy(), vref)
+        say(f"  induced (l0 {l0}): rho {er:.2e} v {ev:.2e}")
+        assert er < 1e-10 and ev < 1e-10
     ctx.close()
 
 
