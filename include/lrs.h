@@ -203,7 +203,8 @@ lrs_status lrs_get_quadrature(const lrs_ctx* ctx, int* nterms, double* c_host, d
  *   points_host  float64 [npts][3], Cartesian (bohr)
  *   psi_out      complex128 [nk][nb][npts] on the device, the layout lrs_set_sites takes.
  * Uses only the context's device and stream (no orbitals, sites or terms need be set).
- * Allocates its workspace for the call and synchronises: LRS_ESTATE under stream capture.
+ * Its workspace stays with the context (allocated or grown only when a call needs more); it
+ * copies its host tables once and synchronises at the end: LRS_ESTATE under stream capture.
  * LRS_EINVAL for non-positive sizes or omega, LRS_ENONFINITE for non-finite k, G or points,
  * LRS_ENOMEM if the workspace (16 B x (nb + npts) x npw, padded) does not fit. */
 lrs_status lrs_project_orbitals(lrs_ctx* ctx, int nk, int nb, int npw, const double* kpts_host,

@@ -603,6 +603,7 @@ void lrs_destroy(lrs_ctx* ctx) {
   release(ctx, ctx->val_work);
   release(ctx, ctx->fft_work);
   release(ctx, ctx->probe);
+  release(ctx, ctx->proj_work);
   release(ctx, ctx->a_tiles);
   release(ctx, ctx->park);
   release(ctx, ctx->xcd_sync);

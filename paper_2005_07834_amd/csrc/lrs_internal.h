@@ -197,6 +197,7 @@ struct lrs_ctx {
   // screening state
   lrs::DevBuf W_last, rho_last, screen_tab, work, adj_work, val_work, fft_work;
   lrs::DevBuf probe;              // output of the matrix-core rate probe
+  lrs::DevBuf proj_work;          // workspace of the direct projection
   bool have_W = false, have_rho = false;
 
   // timing

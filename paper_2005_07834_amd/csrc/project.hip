@@ -148,20 +148,45 @@ extern "C" lrs_status lrs_project_orbitals(lrs_ctx* ctx, int nk, int nb, int npw
   const int rows = (int)round_up(nb, CG_BM);
   const int prow = (int)round_up(npts, CG_BN);
   const size_t bytes = (size_t)(2 * (size_t)rows * ld + 2 * (size_t)prow * ld) * 8 +
-                       (size_t)(3 * npw + 3 * npts) * 8;
-  if (ctx->max_bytes && ctx->bytes_in_use + bytes > ctx->max_bytes)
-    return set_err(ctx, LRS_ENOMEM, "projection workspace (%zu bytes) exceeds the limit", bytes);
-  char* w = nullptr;
-  if (hipMalloc(&w, bytes) != hipSuccess) return set_err(ctx, LRS_ENOMEM, "projection workspace");
+                       (size_t)(3 * (size_t)nk * npw + 3 * npts) * 8;
+  // the workspace stays with the context (grown when a call needs more), so repeated calls
+  // allocate nothing
+  DevBuf& wb = ctx->proj_work;
+  if (!wb.p || wb.bytes < bytes) {
+    if (wb.p && ctx->graph_pinned)
+      return set_err(ctx, LRS_ESTATE, "captured graphs read this context's buffers");
+    if (wb.p) {
+      (void)hipFree(wb.p);
+      ctx->bytes_in_use -= wb.bytes;
+      wb.p = nullptr;
+      wb.bytes = 0;
+    }
+    if (ctx->max_bytes && ctx->bytes_in_use + bytes > ctx->max_bytes)
+      return set_err(ctx, LRS_ENOMEM, "projection workspace (%zu bytes) exceeds the limit", bytes);
+    if (hipMalloc(&wb.p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      wb.p = nullptr;
+      return set_err(ctx, LRS_ENOMEM, "projection workspace");
+    }
+    wb.bytes = bytes;
+    ctx->bytes_in_use += bytes;
+  }
+  char* w = (char*)wb.p;
   double* a_re = (double*)w;
   double* a_im = a_re + (size_t)rows * ld;
   double* p_re = a_im + (size_t)rows * ld;
   double* p_im = p_re + (size_t)prow * ld;
-  double* kg = p_im + (size_t)prow * ld;
-  double* pts = kg + 3 * (size_t)npw;
+  double* kg = p_im + (size_t)prow * ld;        // k + G for every k, [nk][npw][3]
+  double* pts = kg + 3 * (size_t)nk * npw;
   hipStream_t st = ctx->stream;
+  std::vector<double> kgh(3 * (size_t)nk * npw);
+  for (int k = 0; k < nk; ++k)
+    for (int g = 0; g < npw; ++g)
+      for (int d = 0; d < 3; ++d)
+        kgh[3 * ((size_t)k * npw + g) + d] = gvec_host[3 * g + d] + kpts_host[3 * k + d];
   hipError_t e = hipMemcpyAsync(pts, points_host, 3 * (size_t)npts * 8, hipMemcpyHostToDevice, st);
-  std::vector<double> kgh(3 * (size_t)npw);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(kg, kgh.data(), kgh.size() * 8, hipMemcpyHostToDevice, st);
   ProjParams P;
   P.a_re = a_re;
   P.a_im = a_im;
@@ -172,14 +197,8 @@ extern "C" lrs_status lrs_project_orbitals(lrs_ctx* ctx, int nk, int nb, int npw
   P.npts = npts;
   P.scale = 1.0 / std::sqrt(omega);
   for (int k = 0; k < nk && e == hipSuccess; ++k) {
-    for (int g = 0; g < npw; ++g)
-      for (int d = 0; d < 3; ++d) kgh[3 * g + d] = gvec_host[3 * g + d] + kpts_host[3 * k + d];
-    // (pageable source: the copy is done before the call returns, so kgh may change next)
-    e = hipMemcpyAsync(kg, kgh.data(), kgh.size() * 8, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) break;
-    hipLaunchKernelGGL(phase_kernel, dim3(2048), dim3(256), 0, st, kg, pts, npts, npw, prow, ld,
-                       p_re, p_im);
+    hipLaunchKernelGGL(phase_kernel, dim3(2048), dim3(256), 0, st, kg + 3 * (size_t)k * npw, pts,
+                       npts, npw, prow, ld, p_re, p_im);
     hipLaunchKernelGGL(coef_planes_kernel, dim3(2048), dim3(256), 0, st,
                        (const double*)coef + 2 * (size_t)k * nb * npw, nb, npw, rows, ld, a_re,
                        a_im);
@@ -187,8 +206,7 @@ extern "C" lrs_status lrs_project_orbitals(lrs_ctx* ctx, int nk, int nb, int npw
     hipLaunchKernelGGL(project_gemm_kernel, dim3(prow / CG_BN, rows / CG_BM), dim3(256), 0, st, P);
     e = hipGetLastError();
   }
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  (void)hipFree(w);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);   // (the host tables are freed on return)
   if (e != hipSuccess) return set_err(ctx, LRS_EDEVICE, "projection: %s", hipGetErrorString(e));
   return LRS_OK;
 }
