@@ -129,6 +129,21 @@ lrs_status lrs_set_orbitals(lrs_ctx* ctx, int nk, int nb, int nocc, int spin_fac
                             const double* energies_host, double mu, double delta,
                             const void* psi_grid, int ngrid, double grid_dV);
 
+/* lrs_set_orbitals for real orbitals at the Gamma point (Sec. VI.F): with a real potential the
+ * Gamma orbitals can be chosen real (a phase per band, a real basis of each degenerate set),
+ * and then each Green's function is a real contraction, G = sum_K w_K psi_K(r) psi_K(r'), one
+ * real product where the complex form takes four.  Arguments as lrs_set_orbitals with nk = 1:
+ * energies_host [nb], psi_grid complex128 [nb][ngrid] whose imaginary parts vanish (at most
+ * 1e-12 of the largest real part, else LRS_EINVAL; only the real parts are read).  The
+ * operands hold two real orbitals per slot, so they take half the memory.  lrs_set_sites then
+ * requires real psi_site the same way.  lrs_compute_chi0 supports LRS_FP64 and LRS_F16F8 on
+ * real orbitals (others: LRS_EUNSUPPORTED), every column set and both rules; the W solves
+ * are unchanged; lrs_compute_chi0_backward returns LRS_EUNSUPPORTED.  A later
+ * lrs_set_orbitals returns the context to complex orbitals. */
+lrs_status lrs_set_orbitals_real(lrs_ctx* ctx, int nb, int nocc, int spin_factor,
+                                 const double* energies_host, double mu, double delta,
+                                 const void* psi_grid, int ngrid, double grid_dV);
+
 /* Site geometry and the orbitals at the site points.
  *   nrad_host, nang_host  [nsites] shell and angular-point counts; npts_s = nrad * nang.
  *   radii_host, rad_w_host [sum nrad]  radii r_i and radial weights u_i (~ r_i^2 dr).

@@ -174,7 +174,8 @@ __device__ inline size_t site_pos(int r, int k, int K_pad) {
 // fp8 planes, part 0 = hi * 2^7 and part 1 = lo * 2^18 (the row side's order).
 __global__ void prep_site_f16f8_kernel(const double* site, int rows_pad, int K_pad,
                                        const int* slot_row, int rb0, int nrb, const double* w,
-                                       int t0, int nt, double a_scale, unsigned char* out) {
+                                       int w_stride, int q_woff, int t0, int nt, double a_scale,
+                                       unsigned char* out) {
   constexpr int TB = 2048;
   const int nch = K_pad / 16;
   const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -200,13 +201,13 @@ __global__ void prep_site_f16f8_kernel(const double* site, int rows_pad, int K_p
     }
   }
   for (int t = 0; t < nt; ++t) {
-    const double* wt = w + (size_t)(t0 + t) * K_pad + k0;
+    const double* wt = w + (size_t)(t0 + t) * w_stride + k0;
     unsigned char* base = out + (((size_t)t * nch + ch) * nrb + rb) * TB;
     f16x8 hp, hq;
     unsigned int f8[4][2] = {};     // [re p0, re p1, im p0, im p1][dword]
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const float xp = (float)(p0[j] * wt[j]), xq = (float)(q0[j] * wt[j]);
+      const float xp = (float)(p0[j] * wt[j]), xq = (float)(q0[j] * wt[q_woff + j]);
       const _Float16 a = (_Float16)xp, b = (_Float16)xq;
       hp[j] = a;
       hq[j] = b;
@@ -228,8 +229,8 @@ __global__ void prep_site_f16f8_kernel(const double* site, int rows_pad, int K_p
 
 template <int PREC>
 __global__ void prep_site_kernel(const double* site, int rows_pad, int K_pad, const int* slot_row,
-                                 int rb0, int nrb, const double* w, int t0, int nt, double a_scale,
-                                 unsigned char* out) {
+                                 int rb0, int nrb, const double* w, int w_stride, int q_woff,
+                                 int t0, int nt, double a_scale, unsigned char* out) {
   constexpr int KC = Prec<PREC>::KC, TB = Prec<PREC>::TB;
   constexpr bool SPLIT = PREC == LRS_BF16X2 || PREC == LRS_FP16X2;
   constexpr int SLOTS = SPLIT ? 32 : 64;
@@ -259,14 +260,15 @@ __global__ void prep_site_kernel(const double* site, int rows_pad, int K_pad, co
     }
   }
   for (int t = 0; t < nt; ++t) {
-    const double* wt = w + (size_t)(t0 + t) * K_pad;
+    const double* wt = w + (size_t)(t0 + t) * w_stride;
+    const double* wq = wt + q_woff;
     unsigned char* base = out + (((size_t)t * nch + ch) * nrb + rb) * TB;
     if constexpr (F64) {
       f64x4 vp, vq;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         vp[v] = p0[v] * wt[kv[v]];
-        vq[v] = q0[v] * wt[kv[v]];
+        vq[v] = q0[v] * wq[kv[v]];
       }
       f64x4* d = (f64x4*)base;
       d[lane] = vp;
@@ -277,7 +279,7 @@ __global__ void prep_site_kernel(const double* site, int rows_pad, int K_pad, co
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
         d[lane * 8 + v] = (float)(p0[v] * wt[kv[v]]);
-        d[512 + lane * 8 + v] = (float)(q0[v] * wt[kv[v]]);
+        d[512 + lane * 8 + v] = (float)(q0[v] * wq[kv[v]]);
       }
     } else {
       using elem_t = typename std::conditional<PREC == LRS_BF16X2, __bf16, _Float16>::type;
@@ -286,7 +288,7 @@ __global__ void prep_site_kernel(const double* site, int rows_pad, int K_pad, co
       vec_t vph, vpl, vqh, vql;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const double p = p0[e] * wt[kv[e]], q = q0[e] * wt[kv[e]];
+        const double p = p0[e] * wt[kv[e]], q = q0[e] * wq[kv[e]];
         const elem_t ph = (elem_t)(float)p, qh = (elem_t)(float)q;
         vph[e] = ph;
         vpl[e] = (elem_t)(float)(p - (double)(float)ph);
@@ -355,7 +357,7 @@ __device__ __forceinline__ i32x8 load_f8(const unsigned char* p) {
   return v;
 }
 
-template <int PREC, int MB, int NB>
+template <int PREC, int MB, int NB, bool RE = false>
 __device__ __forceinline__ void load_frags(const unsigned char* lds_a, const unsigned char* lds_b,
                                            int lane, Frags<PREC, MB, NB>& f) {
   constexpr int TB = Prec<PREC>::TB;
@@ -416,7 +418,7 @@ __device__ __forceinline__ void load_frags(const unsigned char* lds_a, const uns
       f.r[j] = *(const f16x8*)(b + lofs);
       f.i[j] = *(const f16x8*)(b + lofs + 512);
       f.br8[j] = load_f8(b + own);
-      f.bi8[j] = load_f8(b + other);
+      if constexpr (!RE) f.bi8[j] = load_f8(b + other);
     }
   } else {
     using half_t = typename std::conditional<PREC == LRS_BF16X2, bf16x8, f16x8>::type;
@@ -556,6 +558,47 @@ __device__ __forceinline__ void mma_frags(
         gi[i][j] = mf(nql, f.rh[j], gi[i][j]);
       }
     }
+  }
+}
+
+// Real orbitals (kernel mode 3): each operand slot carries two real orbitals, the first in the
+// "re" plane and the second in the "im" plane (two K values per slot), so G = sum over both
+// planes of p b, which is the real-part update of the complex product; G_i stays zero.
+template <int PREC, int MB, int NB>
+__device__ __forceinline__ void mma_frags_re(
+    const Frags<PREC, MB, NB>& f,
+    typename Prec<PREC>::acc_t (&gr)[MB * 16 / Prec<PREC>::BLK][NB * 16 / Prec<PREC>::BLK]) {
+  static_assert(PREC == LRS_FP64 || PREC == LRS_F16F8, "real orbitals: FP64 and F16F8");
+  if constexpr (PREC == LRS_FP64) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          gr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.p[i][s], f.br[j][s], gr[i][j], 0, 0, 0);
+          gr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.q[i][s], f.bi[j][s], gr[i][j], 0, 0, 0);
+        }
+  } else {
+    const int lane = __lane_id();
+    const int sa = lane < 32 ? 127 - kF8HiShift : 127 - kF8LoShift;
+    const int sb = lane < 32 ? 127 - kF8LoShift : 127 - kF8HiShift;
+#pragma unroll
+    for (int i = 0; i < MB / 2; ++i)
+#pragma unroll
+      for (int j = 0; j < NB / 2; ++j)
+        gr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(f.p[i], f.r[j], gr[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < MB / 2; ++i)
+#pragma unroll
+      for (int j = 0; j < NB / 2; ++j)
+        gr[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(f.a8[i], f.br8[j], gr[i][j], 0,
+                                                                  0, 0, sa, 0, sb);
+#pragma unroll
+    for (int i = 0; i < MB / 2; ++i)
+#pragma unroll
+      for (int j = 0; j < NB / 2; ++j)
+        gr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(f.q[i], f.i[j], gr[i][j], 0, 0, 0);
   }
 }
 
@@ -888,7 +931,7 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
         for (int j = 0; j < NB / 2; ++j)
           load_b_split<PREC, NB>(s0 + A_BYTES + wn * NB * TB, lane, j, bfr);
       } else {
-        load_frags<PREC, MB, NB>(s0 + wm * MB * TB, s0 + A_BYTES + wn * NB * TB, lane, fa);
+        load_frags<PREC, MB, NB, MODE == 3>(s0 + wm * MB * TB, s0 + A_BYTES + wn * NB * TB, lane, fa);
       }
     }
     int q = 0;
@@ -913,16 +956,19 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
         }
         interleave_rot<MB, NB, LPW>();
       } else {
-        load_frags<PREC, MB, NB>(sn + wm * MB * TB, sn + A_BYTES + wn * NB * TB, lane, nxt);
+        load_frags<PREC, MB, NB, MODE == 3>(sn + wm * MB * TB, sn + A_BYTES + wn * NB * TB, lane, nxt);
         issue_next(slot(I), q + S < nseq);
-        if constexpr (IL == 0) {
-          // LDS reads and loads first, then the matrix-core block
+        if constexpr (IL == 0 || MODE == 3) {
+          // LDS reads and loads first, then the matrix-core block (real orbitals: a third of
+          // the complex step's instructions, too few to spread the reads and loads over)
           __builtin_amdgcn_sched_barrier(0);
           if constexpr (PREC == LRS_FP64_3M) mma_frags_3m<MB, NB>(cur, gr, gi, gx);
+          else if constexpr (MODE == 3) mma_frags_re<PREC, MB, NB>(cur, gr);
           else mma_frags<PREC, MB, NB>(cur, gr, gi);
         } else {
           // LDS reads and loads spread between the matrix-core instructions
           if constexpr (PREC == LRS_FP64_3M) mma_frags_3m<MB, NB>(cur, gr, gi, gx);
+          else if constexpr (MODE == 3) mma_frags_re<PREC, MB, NB>(cur, gr);
           else mma_frags<PREC, MB, NB>(cur, gr, gi);
           interleave<PREC, MB, NB, LPW, S, IL == 2>();
         }
@@ -1000,7 +1046,7 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
             off[e] = in[e] ? row * td.ldo + col : 0;
             dg[e] = col - row - td.pad;   // (site column) - (site row), adjoint mode
           }
-          if constexpr (MODE >= 1) {
+          if constexpr (MODE == 1 || MODE == 2) {
             // adjoint: Hu = lam * conj(G_u), Ho = lam * conj(G_o) on a site block.  lam is
             // symmetric (or the coefficient matrix Hermitian) and G Hermitian there, so
             // H(c, r) = conj(H(r, c)): the host lists only tiles that reach the upper
@@ -1168,13 +1214,13 @@ hipError_t launch_v(int grid, const Chi0Params& P, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int PREC>
+template <int PREC, int MODE = 0>
 hipError_t launch_p(int variant, int grid, const Chi0Params& P, hipStream_t s) {
   switch (variant) {
-    case 0: return launch_v<PREC, 0, 0>(grid, P, s);
-    case 1: return launch_v<PREC, 1, 0>(grid, P, s);
-    case 2: return launch_v<PREC, 2, 0>(grid, P, s);
-    case 3: return launch_v<PREC, 3, 0>(grid, P, s);
+    case 0: return launch_v<PREC, 0, MODE>(grid, P, s);
+    case 1: return launch_v<PREC, 1, MODE>(grid, P, s);
+    case 2: return launch_v<PREC, 2, MODE>(grid, P, s);
+    case 3: return launch_v<PREC, 3, MODE>(grid, P, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1217,21 +1263,21 @@ int occ_p(int v) {
 
 template <int PREC>
 hipError_t prep_p(const double* site, int rows_pad, int K_pad, const int* slot_row, int rb0,
-                  int nrb, const double* w, int t0, int nt, double a_scale, void* out,
-                  hipStream_t s) {
+                  int nrb, const double* w, int w_stride, int q_woff, int t0, int nt,
+                  double a_scale, void* out, hipStream_t s) {
   if constexpr (PREC == LRS_F16F8) {
     const long long n = (long long)nrb * (K_pad / 16) * 32;
     hipLaunchKernelGGL(prep_site_f16f8_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                       s, site, rows_pad, K_pad, slot_row, rb0, nrb, w, t0, nt, a_scale,
-                       (unsigned char*)out);
+                       s, site, rows_pad, K_pad, slot_row, rb0, nrb, w, w_stride, q_woff, t0,
+                       nt, a_scale, (unsigned char*)out);
     return hipGetLastError();
   }
   const int nch = K_pad / Prec<PREC>::KC;
   const int slots = (PREC == LRS_BF16X2 || PREC == LRS_FP16X2) ? 32 : 64;
   const long long n = (long long)nrb * nch * slots;
   hipLaunchKernelGGL(prep_site_kernel<PREC>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                     site, rows_pad, K_pad, slot_row, rb0, nrb, w, t0, nt, a_scale,
-                     (unsigned char*)out);
+                     site, rows_pad, K_pad, slot_row, rb0, nrb, w, w_stride, q_woff, t0, nt,
+                     a_scale, (unsigned char*)out);
   return hipGetLastError();
 }
 
@@ -1265,16 +1311,20 @@ TileShape chi0_shape(int prec, int variant) {
 }
 
 hipError_t launch_prep_site(int prec, const double* site, int rows_pad, int K_pad,
-                            const int* slot_row, int rb0, int nrb, const double* w, int t0,
-                            int nt, double a_scale, void* out, hipStream_t s) {
+                            const int* slot_row, int rb0, int nrb, const double* w,
+                            int w_stride, int q_woff, int t0, int nt, double a_scale, void* out,
+                            hipStream_t s) {
+#define LRS_PREP(PR) \
+  prep_p<PR>(site, rows_pad, K_pad, slot_row, rb0, nrb, w, w_stride, q_woff, t0, nt, a_scale, out, s)
   switch (prec) {
-    case LRS_FP64: return prep_p<LRS_FP64>(site, rows_pad, K_pad, slot_row, rb0, nrb, w, t0, nt, a_scale, out, s);
-    case LRS_FP32: return prep_p<LRS_FP32>(site, rows_pad, K_pad, slot_row, rb0, nrb, w, t0, nt, a_scale, out, s);
-    case LRS_BF16X2: return prep_p<LRS_BF16X2>(site, rows_pad, K_pad, slot_row, rb0, nrb, w, t0, nt, a_scale, out, s);
-    case LRS_FP16X2: return prep_p<LRS_FP16X2>(site, rows_pad, K_pad, slot_row, rb0, nrb, w, t0, nt, a_scale, out, s);
-    case LRS_F16F8: return prep_p<LRS_F16F8>(site, rows_pad, K_pad, slot_row, rb0, nrb, w, t0, nt, a_scale, out, s);
-    case LRS_FP64_3M: return prep_p<LRS_FP64_3M>(site, rows_pad, K_pad, slot_row, rb0, nrb, w, t0, nt, a_scale, out, s);
+    case LRS_FP64: return LRS_PREP(LRS_FP64);
+    case LRS_FP32: return LRS_PREP(LRS_FP32);
+    case LRS_BF16X2: return LRS_PREP(LRS_BF16X2);
+    case LRS_FP16X2: return LRS_PREP(LRS_FP16X2);
+    case LRS_F16F8: return LRS_PREP(LRS_F16F8);
+    case LRS_FP64_3M: return LRS_PREP(LRS_FP64_3M);
   }
+#undef LRS_PREP
   return hipErrorInvalidValue;
 }
 
@@ -1282,7 +1332,7 @@ hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int
                        const void* b_tiles, int b_ncb, int nch, const double* c,
                        const double* ci, int T, int nch_o, const TileDesc* tiles, int ntiles,
                        double* out, double pref, int sym, unsigned int* sync, void* park,
-                       hipStream_t s) {
+                       int real, hipStream_t s) {
   Chi0Params P;
   P.ci = ci;
   P.sym = sym;
@@ -1305,6 +1355,13 @@ hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int
   P.adj_c = P.adj_s = 0.0;
   P.hu_re = P.hu_im = P.ho_re = P.ho_im = nullptr;
   P.hs_u = P.hs_o = nullptr;
+  if (real) {
+    switch (prec) {
+      case LRS_FP64: return launch_p<LRS_FP64, 3>(variant, grid, P, s);
+      case LRS_F16F8: return launch_p<LRS_F16F8, 3>(variant, grid, P, s);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (prec) {
     case LRS_FP64: return launch_p<LRS_FP64>(variant, grid, P, s);
     case LRS_FP32: return launch_p<LRS_FP32>(variant, grid, P, s);

@@ -114,6 +114,22 @@ void drop_quad(lrs_ctx* ctx) {
   ctx->quad = Quad();
 }
 
+// max |Im psi| over n complex values on the device (synchronises)
+lrs_status device_max_abs_im(lrs_ctx* ctx, const double* psi, long long n, float* out) {
+  DevBuf tmp;
+  CHECK(ensure_buf(ctx, tmp, 256, "max|Im| scratch"));
+  lrs_status st = LRS_OK;
+  unsigned int h = 0;
+  if (launch_fill_zero(tmp.p, 256, ctx->stream) != hipSuccess ||
+      launch_max_abs_im(psi, n, (unsigned int*)tmp.p, ctx->stream) != hipSuccess ||
+      hipMemcpyAsync(&h, tmp.p, 4, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess)
+    st = fail(ctx, LRS_EDEVICE, "max|Im| reduction failed");
+  release(ctx, tmp);
+  std::memcpy(out, &h, 4);
+  return st;
+}
+
 // max |x| over a device array of doubles, and whether any entry is not finite (synchronises)
 lrs_status device_max_abs(lrs_ctx* ctx, const double* x, long long n, float* out, bool* bad) {
   DevBuf tmp;
@@ -172,7 +188,11 @@ lrs_status install_terms(lrs_ctx* ctx, Quad& q, const std::vector<double>& c,
                          const std::vector<double>* dalpha, const std::vector<double>* dbeta,
                          const std::vector<double>* ci = nullptr) {
   const int T = (int)c.size();
-  const int Ko = ctx->Ko, Ku = ctx->Ku, Kp = ctx->K_pad;
+  // real orbitals: weights per orbital (Kp = 2 K_pad of them, the unoccupied from 2 Ko_pad),
+  // rearranged below into the slot layout
+  const bool real = ctx->real_mode;
+  const int Ko = ctx->Ko, Ku = ctx->Ku, Kp = real ? 2 * ctx->K_pad : ctx->K_pad;
+  const int Ko_pad = real ? 2 * ctx->Ko_pad : ctx->Ko_pad;
   q.nterms = T;
   q.c_raw = c;
   q.c.assign(T, 0.0);
@@ -202,9 +222,25 @@ lrs_status install_terms(lrs_ctx* ctx, Quad& q, const std::vector<double>& c,
       if (dalpha) dw[i] = (*dalpha)[(size_t)t * Ko + i] * sa;
     }
     for (int i = 0; i < Ku; ++i) {
-      w[ctx->Ko_pad + i] = beta[(size_t)t * Ku + i] * sb;
-      if (dbeta) dw[ctx->Ko_pad + i] = (*dbeta)[(size_t)t * Ku + i] * sb;
+      w[Ko_pad + i] = beta[(size_t)t * Ku + i] * sb;
+      if (dbeta) dw[Ko_pad + i] = (*dbeta)[(size_t)t * Ku + i] * sb;
     }
+  }
+  if (real) {
+    // slot k of chunk k / 16 holds orbitals 32 (k / 16) + k % 16 (re) and that + 16 (im): per
+    // term the re orbitals' weights [K_pad], then the im orbitals' [K_pad]
+    const int Ks = ctx->K_pad;
+    std::vector<double> w2(q.w.size()), dw2(q.dw.size());
+    for (int t = 0; t < T; ++t)
+      for (int k = 0; k < Ks; ++k) {
+        const int K = 32 * (k >> 4) + (k & 15);
+        w2[(size_t)t * Kp + k] = q.w[(size_t)t * Kp + K];
+        w2[(size_t)t * Kp + Ks + k] = q.w[(size_t)t * Kp + K + 16];
+        dw2[(size_t)t * Kp + k] = q.dw[(size_t)t * Kp + K];
+        dw2[(size_t)t * Kp + Ks + k] = q.dw[(size_t)t * Kp + K + 16];
+      }
+    q.w.swap(w2);
+    q.dw.swap(dw2);
   }
   // device copies: weights in natural K order (FP64) and the coefficients
   CHECK(ensure_buf(ctx, ctx->w_nat, q.w.size() * 8, "weights"));
@@ -444,10 +480,13 @@ lrs_status site_operand(lrs_ctx* ctx, int prec, const Batch& b, int t0, int nt,
   ctx->a_prec = -1;
   CHECK(ensure_buf(ctx, ctx->a_tiles, a_bytes_per_rb(ctx, prec, nt) * b.nrb, "weighted site operand"));
   const double a_scale = is_f16(prec) ? ctx->site_scale_f16 : 1.0;
+  // (real orbitals: the weights of a slot's second orbital follow those of the first)
+  const int w_stride = ctx->real_mode ? 2 * ctx->K_pad : ctx->K_pad;
+  const int q_woff = ctx->real_mode ? ctx->K_pad : 0;
   HIP_OR_FAIL(ctx, launch_prep_site(prec, (const double*)ctx->site_f64.p, ctx->rows_pad,
                                     ctx->K_pad, (const int*)ctx->site_colmap.p, b.rb0, b.nrb,
-                                    (const double*)ctx->w_nat.p, t0, nt, a_scale,
-                                    ctx->a_tiles.p, ctx->stream));
+                                    (const double*)ctx->w_nat.p, w_stride, q_woff, t0, nt,
+                                    a_scale, ctx->a_tiles.p, ctx->stream));
   ctx->a_prec = prec;
   ctx->a_version = ctx->quad_version;
   ctx->a_rb0 = b.rb0;
@@ -525,7 +564,7 @@ lrs_status run_chi0(lrs_ctx* ctx, int site, int cols, int prec, int variant, dou
                                  odd ? (const double*)ctx->c_dev.p + T : nullptr, T,
                                  ctx->Ko_pad / KC, (const TileDesc*)plan->tiles.p + bt.tile0, nt,
                                  out, pref, cols == LRS_COLS_SITE && !odd, sync, ctx->park.p,
-                                 ctx->stream));
+                                 ctx->real_mode ? 1 : 0, ctx->stream));
     if (max_tiles > 0) break;
   }
   if (timed && !first) {
@@ -635,9 +674,11 @@ lrs_status lrs_check_bands(int nk, int nb, int nocc, const double* e, double mu,
   return LRS_OK;
 }
 
-lrs_status lrs_set_orbitals(lrs_ctx* ctx, int nk, int nb, int nocc, int spin_factor,
-                            const double* e, double mu, double delta, const void* psi_grid,
-                            int ngrid, double grid_dV) {
+namespace {
+// lrs_set_orbitals, and with real != 0 lrs_set_orbitals_real (nk = 1)
+lrs_status set_orbitals_impl(lrs_ctx* ctx, int nk, int nb, int nocc, int spin_factor,
+                             const double* e, double mu, double delta, const void* psi_grid,
+                             int ngrid, double grid_dV, int real) {
   if (!ctx) return LRS_EINVAL;
   ctx->err.clear();
   if (ctx->graph_pinned)
@@ -660,7 +701,10 @@ lrs_status lrs_set_orbitals(lrs_ctx* ctx, int nk, int nb, int nocc, int spin_fac
 
   // sizes and storage for the new state, validated before the old state is dropped
   const int Ko = nk * nocc, Ku = nk * (nb - nocc);
-  const int Ko_pad = (int)round_up(Ko, kPhaseAlign), Ku_pad = (int)round_up(Ku, kPhaseAlign);
+  // (real orbitals: two per slot, so the orbital counts are padded to twice the alignment)
+  const int align = real ? 2 * kPhaseAlign : kPhaseAlign;
+  const int Ko_pad = (int)round_up(Ko, align) / (real ? 2 : 1);
+  const int Ku_pad = (int)round_up(Ku, align) / (real ? 2 : 1);
   const int K_pad = Ko_pad + Ku_pad;
   const int cols_pad = ngrid > 0 ? (int)round_up(ngrid, kRowAlign) + kMaxTileCols : 0;
   DevBuf tiles;
@@ -674,9 +718,18 @@ lrs_status lrs_set_orbitals(lrs_ctx* ctx, int nk, int nb, int nocc, int spin_fac
       release(ctx, tiles);
       return s2 != LRS_OK ? s2 : fail(ctx, LRS_ENONFINITE, "non-finite value in psi_grid");
     }
+    if (real) {
+      float mi = 0;
+      lrs_status s3 = device_max_abs_im(ctx, (const double*)psi_grid, K * ngrid, &mi);
+      if (s3 != LRS_OK || !(mi <= 1e-12f * m)) {
+        release(ctx, tiles);
+        return s3 != LRS_OK ? s3 : fail(ctx, LRS_EINVAL, "psi_grid is not real: max|Im| %g "
+                                        "against max|Re| %g", mi, m);
+      }
+    }
     ctx->grid_max_abs = m;
     hipError_t he = launch_pack_tiles((const double*)psi_grid, nk, nb, nocc, ngrid, ngrid, cols_pad,
-                                      Ko_pad, K_pad, LRS_FP64, 1.f, tiles.p, ctx->stream);
+                                      Ko_pad, K_pad, LRS_FP64, 1.f, real, tiles.p, ctx->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
     if (he != hipSuccess) {
       release(ctx, tiles);
@@ -709,8 +762,24 @@ lrs_status lrs_set_orbitals(lrs_ctx* ctx, int nk, int nb, int nocc, int spin_fac
   ctx->grid_dV = grid_dV;
   ctx->grid_cols_pad = cols_pad;
   ctx->grid_scale_f16 = pow2_prescale(ctx->grid_max_abs);
+  ctx->real_mode = real != 0;
   ctx->have_bands = true;
   return LRS_OK;
+}
+}  // namespace
+
+lrs_status lrs_set_orbitals(lrs_ctx* ctx, int nk, int nb, int nocc, int spin_factor,
+                            const double* e, double mu, double delta, const void* psi_grid,
+                            int ngrid, double grid_dV) {
+  return set_orbitals_impl(ctx, nk, nb, nocc, spin_factor, e, mu, delta, psi_grid, ngrid,
+                           grid_dV, 0);
+}
+
+lrs_status lrs_set_orbitals_real(lrs_ctx* ctx, int nb, int nocc, int spin_factor,
+                                 const double* e, double mu, double delta, const void* psi_grid,
+                                 int ngrid, double grid_dV) {
+  return set_orbitals_impl(ctx, 1, nb, nocc, spin_factor, e, mu, delta, psi_grid, ngrid,
+                           grid_dV, 1);
 }
 
 lrs_status lrs_set_sites(lrs_ctx* ctx, int nsites, const int* nrad, const int* nang,
@@ -744,6 +813,13 @@ lrs_status lrs_set_sites(lrs_ctx* ctx, int nsites, const int* nrad, const int* n
   bool bad = false;
   CHECK(device_max_abs(ctx, (const double*)psi_site, 2LL * ctx->nk * ctx->nb * nrows, &m, &bad));
   if (bad) return fail(ctx, LRS_ENONFINITE, "non-finite value in psi_site");
+  if (ctx->real_mode) {
+    float mi = 0;
+    CHECK(device_max_abs_im(ctx, (const double*)psi_site, (long long)ctx->nb * nrows, &mi));
+    if (!(mi <= 1e-12f * m))
+      return fail(ctx, LRS_EINVAL, "psi_site is not real (the orbitals were set real): max|Im| "
+                  "%g against max|Re| %g", mi, m);
+  }
 
   drop_sites(ctx);
   ctx->nsites = nsites;
@@ -781,7 +857,8 @@ lrs_status lrs_set_sites(lrs_ctx* ctx, int nsites, const int* nrad, const int* n
                                   hipMemcpyHostToDevice, ctx->stream));
   HIP_OR_FAIL(ctx, launch_pack_site_rows((const double*)psi_site, ctx->nk, ctx->nb, ctx->nocc,
                                          ctx->nrows, ctx->rows_pad, ctx->Ko_pad, ctx->K_pad,
-                                         (double*)ctx->site_f64.p, ctx->stream));
+                                         ctx->real_mode ? 1 : 0, (double*)ctx->site_f64.p,
+                                         ctx->stream));
   HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
   ctx->have_sites = true;
   return LRS_OK;
@@ -989,6 +1066,8 @@ lrs_status lrs_compute_chi0(lrs_ctx* ctx, int site, int cols, int prec, double* 
   if (site < -1 || site >= ctx->nsites) return fail(ctx, LRS_EINVAL, "site %d out of range", site);
   if (cols != LRS_COLS_GRID && cols != LRS_COLS_SITE) return fail(ctx, LRS_EINVAL, "bad column set");
   if (prec < LRS_FP64 || prec > LRS_FP64_3M) return fail(ctx, LRS_EINVAL, "bad precision");
+  if (ctx->real_mode && prec != LRS_FP64 && prec != LRS_F16F8)
+    return fail(ctx, LRS_EUNSUPPORTED, "real orbitals: LRS_FP64 or LRS_F16F8 only");
   if (cols == LRS_COLS_GRID && ctx->ngrid <= 0) return fail(ctx, LRS_ESTATE, "no grid orbitals were given");
   int cur = -1;
   HIP_OR_FAIL(ctx, hipGetDevice(&cur));
@@ -1041,6 +1120,8 @@ lrs_status lrs_tune(lrs_ctx* ctx, int prec) {
   if (!ctx->have_bands || !ctx->have_sites || !ctx->have_quad)
     return fail(ctx, LRS_ESTATE, "orbitals, sites and quadrature must be set first");
   if (prec < LRS_FP64 || prec > LRS_FP64_3M) return fail(ctx, LRS_EINVAL, "bad precision");
+  if (ctx->real_mode && prec != LRS_FP64 && prec != LRS_F16F8)
+    return fail(ctx, LRS_EUNSUPPORTED, "real orbitals: LRS_FP64 or LRS_F16F8 only");
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
   int s = 0;
   for (int k = 1; k < ctx->nsites; ++k)
@@ -1163,6 +1244,7 @@ lrs_status lrs_compute_chi0_backward(lrs_ctx* ctx, int cols, int prec, const dou
     return fail(ctx, LRS_EUNSUPPORTED, "backward precision must be LRS_FP64, LRS_BF16X2 or "
                 "LRS_F16F8");
   if (dL_dpsi_grid) return fail(ctx, LRS_EUNSUPPORTED, "site blocks do not depend on grid orbitals");
+  if (ctx->real_mode) return fail(ctx, LRS_EUNSUPPORTED, "no adjoint for real orbitals");
   if (!dL_dchi0 || !dL_dE || !dL_dpsi_site) return fail(ctx, LRS_EINVAL, "missing gradient buffers");
   if (!ctx->quad.has_deriv) return fail(ctx, LRS_EUNSUPPORTED, "generic terms carry no energy derivative");
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));

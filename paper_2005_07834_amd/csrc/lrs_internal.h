@@ -154,6 +154,9 @@ struct lrs_ctx {
   double grid_dV = 0;
   // K layout: [0, Ko) occupied (k-major), zeros to Ko_pad, then [Ko_pad, Ko_pad+Ku) unoccupied
   int Ko = 0, Ku = 0, Ko_pad = 0, Ku_pad = 0, K_pad = 0;
+  // real orbitals at one k (lrs_set_orbitals_real): Ko and Ku count orbitals, Ko_pad, Ku_pad
+  // and K_pad count operand slots, two orbitals each
+  bool real_mode = false;
 
   // grid operand: FP64 fragment tiles (always) and lazily built reduced-precision tiles
   lrs::DevBuf grid_tiles[lrs::kNumPrec];
@@ -220,12 +223,17 @@ double time_auto_scale(double dmin, double dmax, int n);
 double time_auto_scale_iw(double dmin, double dmax, int n, double omega);
 
 // pack.hip
+// real != 0: one k of real orbitals (the real parts of psi), two to a slot (Ko_pad and K_pad
+// count slots)
 hipError_t launch_pack_tiles(const double* psi, int nk, int nb, int nocc, int ncols, int ld_src,
                              int ncols_pad, int Ko_pad, int K_pad, int prec, float prescale,
-                             void* out, hipStream_t s);
+                             int real, void* out, hipStream_t s);
 hipError_t launch_pack_site_rows(const double* psi, int nk, int nb, int nocc, int nrows,
-                                 int rows_pad, int Ko_pad, int K_pad, double* out_f64,
+                                 int rows_pad, int Ko_pad, int K_pad, int real, double* out_f64,
                                  hipStream_t s);
+// largest |Im psi| over n complex values, as float bits (0 if all vanish)
+hipError_t launch_max_abs_im(const double* psi, long long n, unsigned int* out_bits,
+                             hipStream_t s);
 hipError_t launch_derive_site_kmajor(const double* site_f64, int rows_pad, int K_pad, double* out,
                                      hipStream_t s);
 hipError_t launch_site_col_tiles(const double* site_f64, int rows_pad, int K_pad, int ncols_pad,
@@ -241,18 +249,22 @@ int chi0_num_variants(int prec);
 int chi0_blocks_per_cu(int prec, int variant);
 int chi0_default_variant(int prec);
 TileShape chi0_shape(int prec, int variant);
+// w: weights [T][w_stride]; a slot's im-plane value takes the weight at q_woff + k (0 for
+// complex orbitals; K_pad for real orbitals, whose second orbital of a slot has its own)
 hipError_t launch_prep_site(int prec, const double* site, int rows_pad, int K_pad,
-                            const int* slot_row, int rb0, int nrb, const double* w, int t0,
-                            int nt, double a_scale, void* out, hipStream_t s);
+                            const int* slot_row, int rb0, int nrb, const double* w,
+                            int w_stride, int q_woff, int t0, int nt, double a_scale, void* out,
+                            hipStream_t s);
 // sym: site x site blocks, listed from their upper triangle (TileDesc.pad set): each element
 // on or above the diagonal is also stored at its transposed place
 // ci: imaginary parts of the term coefficients (null: real); sym must be 0 then (the odd
 // part of chi0 at imaginary frequency is antisymmetric on a site block)
+// real: the operands hold real orbitals two to a slot (FP64 and F16F8 only)
 hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int a_nrb,
                        const void* b_tiles, int b_ncb, int nch, const double* c,
                        const double* ci, int T, int nch_o, const TileDesc* tiles, int ntiles,
                        double* out, double pref, int sym, unsigned int* sync, void* park,
-                       hipStream_t s);
+                       int real, hipStream_t s);
 // adjoint Green's functions of one term on site blocks: prec LRS_FP64 writes Hu, Ho as FP64
 // planes (hu_re, hu_im, ho_re, ho_im; row stride ld); LRS_BF16X2 and LRS_F16F8 (variant 1)
 // write each at hs_u, hs_o as bfloat16 hi/lo in the split adjoint GEMM's operand tiles

@@ -16,10 +16,11 @@ namespace {
 struct SrcPsi {           // complex128 [nk][nb][ld] orbitals on a point set
   const double* psi;
   int nb, nocc, nu, ncols, ld, Ko, Ko_pad, Ku;
-  __device__ void get(int c, int k, double& re, double& im) const {
-    re = 0.0;
-    im = 0.0;
-    if (c >= ncols) return;
+  // real orbitals (one k): slot k of a 16-slot chunk c holds orbital K = 32 c + k%16 as its
+  // re value and K + 16 as its im value, each orbital's real part (Ko_pad then counts
+  // orbitals, twice the slots)
+  int real;
+  __device__ const double* at(int c, int k) const {   // orbital k's value at c, or null
     int kp, band;
     if (k < Ko) {
       kp = k / nocc;
@@ -29,9 +30,24 @@ struct SrcPsi {           // complex128 [nk][nb][ld] orbitals on a point set
       kp = j / nu;
       band = nocc + (j - kp * nu);
     } else {
+      return nullptr;
+    }
+    return psi + 2 * ((size_t)(kp * nb + band) * ld + c);
+  }
+  __device__ void get(int c, int k, double& re, double& im) const {
+    re = 0.0;
+    im = 0.0;
+    if (c >= ncols) return;
+    if (real) {
+      const int K = 32 * (k >> 4) + (k & 15);
+      const double* a = at(c, K);
+      const double* b = at(c, K + 16);
+      re = a ? a[0] : 0.0;
+      im = b ? b[0] : 0.0;
       return;
     }
-    const double* p = psi + 2 * ((size_t)(kp * nb + band) * ld + c);
+    const double* p = at(c, k);
+    if (!p) return;
     re = p[0];
     im = p[1];
   }
@@ -208,6 +224,16 @@ __global__ void derive_site_kmajor_kernel(SrcSite64 src, double* out) {
   out[n + gid] = im;
 }
 
+// largest |Im| of n complex values (the odd doubles)
+__global__ void max_abs_im_kernel(const double* x, long long n, unsigned int* out_bits) {
+  float m = 0.f;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    m = fmaxf(m, (float)fabs(x[2 * i + 1]));
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) atomicMax(out_bits, __float_as_uint(m));
+}
+
 __global__ void max_abs_kernel(const double* x, long long n, unsigned int* out_bits) {
   float m = 0.f;
   bool bad = false;
@@ -237,9 +263,10 @@ inline int blocks_for(long long n, int tpb) { return (int)((n + tpb - 1) / tpb);
 
 hipError_t launch_pack_tiles(const double* psi, int nk, int nb, int nocc, int ncols, int ld_src,
                              int ncols_pad, int Ko_pad, int K_pad, int prec, float prescale,
-                             void* out, hipStream_t s) {
+                             int real, void* out, hipStream_t s) {
   int nu = nb - nocc;
-  SrcPsi src{psi, nb, nocc, nu, ncols, ld_src, nk * nocc, Ko_pad, nk * nu};
+  SrcPsi src{psi, nb, nocc, nu, ncols, ld_src, nk * nocc, real ? 2 * Ko_pad : Ko_pad, nk * nu,
+             real};
   int nchunks = K_pad / chunk_of(prec);
   long long ntiles = (long long)(ncols_pad / 16) * nchunks;
   hipLaunchKernelGGL(pack_tiles_kernel<SrcPsi>, dim3(blocks_for(ntiles * 64, 256)), dim3(256), 0,
@@ -258,10 +285,11 @@ hipError_t launch_repack_from_f64(const void* tiles64, int ncols_pad, int K_pad,
 }
 
 hipError_t launch_pack_site_rows(const double* psi, int nk, int nb, int nocc, int nrows,
-                                 int rows_pad, int Ko_pad, int K_pad, double* out_f64,
+                                 int rows_pad, int Ko_pad, int K_pad, int real, double* out_f64,
                                  hipStream_t s) {
   int nu = nb - nocc;
-  SrcPsi src{psi, nb, nocc, nu, nrows, nrows, nk * nocc, Ko_pad, nk * nu};
+  SrcPsi src{psi, nb, nocc, nu, nrows, nrows, nk * nocc, real ? 2 * Ko_pad : Ko_pad, nk * nu,
+             real};
   long long n = (long long)rows_pad * K_pad;
   hipLaunchKernelGGL(pack_site_rows_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, src,
                      rows_pad, K_pad, out_f64);
@@ -291,6 +319,13 @@ hipError_t launch_site_col_tiles(const double* site_f64, int rows_pad, int K_pad
 hipError_t launch_max_abs(const double* x, long long n, unsigned int* out_bits, hipStream_t s) {
   int blocks = (int)std::min<long long>(4096, std::max<long long>(1, (n + 255) / 256));
   hipLaunchKernelGGL(max_abs_kernel, dim3(blocks), dim3(256), 0, s, x, n, out_bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_max_abs_im(const double* psi, long long n, unsigned int* out_bits,
+                             hipStream_t s) {
+  int blocks = (int)std::min<long long>(4096, std::max<long long>(1, (n + 255) / 256));
+  hipLaunchKernelGGL(max_abs_im_kernel, dim3(blocks), dim3(256), 0, s, psi, n, out_bits);
   return hipGetLastError();
 }
 
