@@ -129,18 +129,21 @@ lrs_status lrs_set_orbitals(lrs_ctx* ctx, int nk, int nb, int nocc, int spin_fac
                             const double* energies_host, double mu, double delta,
                             const void* psi_grid, int ngrid, double grid_dV);
 
-/* lrs_set_orbitals for real orbitals at the Gamma point (Sec. VI.F): with a real potential the
- * Gamma orbitals can be chosen real (a phase per band, a real basis of each degenerate set),
- * and then each Green's function is a real contraction, G = sum_K w_K psi_K(r) psi_K(r'), one
- * real product where the complex form takes four.  Arguments as lrs_set_orbitals with nk = 1:
- * energies_host [nb], psi_grid complex128 [nb][ngrid] whose imaginary parts vanish (at most
- * 1e-12 of the largest real part, else LRS_EINVAL; only the real parts are read).  The
- * operands hold two real orbitals per slot, so they take half the memory.  lrs_set_sites then
- * requires real psi_site the same way.  lrs_compute_chi0 supports LRS_FP64 and LRS_F16F8 on
- * real orbitals (others: LRS_EUNSUPPORTED), every column set and both rules; the W solves
- * are unchanged; lrs_compute_chi0_backward returns LRS_EUNSUPPORTED.  A later
+/* lrs_set_orbitals for real orbitals (Sec. VI.F, the Gamma point): with a real potential
+ * (time-reversal symmetry, no spin-orbit coupling) the Gamma orbitals can be chosen real (a
+ * phase per band, a real basis of each degenerate set); so can those at the other k-points
+ * equal to their own negatives modulo the reciprocal lattice (the zone-boundary points of a
+ * Gamma-centred 2 x 2 x 2 grid, Bloch factors +-1) when their plane-wave basis is centred on
+ * -k.  Any nk is accepted: chi0 is computed for the real orbitals given.  Each Green's
+ * function is then a real contraction, G = sum_K w_K psi_K(r) psi_K(r'), one real product
+ * where the complex form takes four.  Arguments as lrs_set_orbitals; psi_grid complex128 [nk][nb][ngrid] whose imaginary
+ * parts vanish (at most 1e-12 of the largest real part, else LRS_EINVAL; only the real parts
+ * are read).  The operands hold two real orbitals per slot, so they take half the memory.
+ * lrs_set_sites then requires real psi_site the same way.  lrs_compute_chi0 supports LRS_FP64
+ * and LRS_F16F8 on real orbitals (others: LRS_EUNSUPPORTED), every column set and both rules;
+ * the W solves are unchanged; lrs_compute_chi0_backward returns LRS_EUNSUPPORTED.  A later
  * lrs_set_orbitals returns the context to complex orbitals. */
-lrs_status lrs_set_orbitals_real(lrs_ctx* ctx, int nb, int nocc, int spin_factor,
+lrs_status lrs_set_orbitals_real(lrs_ctx* ctx, int nk, int nb, int nocc, int spin_factor,
                                  const double* energies_host, double mu, double delta,
                                  const void* psi_grid, int ngrid, double grid_dV);
 

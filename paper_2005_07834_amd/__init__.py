@@ -38,7 +38,7 @@ SIGNATURES = [
     ("lrs_last_error", _CS, [_P]),
     ("lrs_check_bands", _I, [_I, _I, _I, _P, _D, _D]),
     ("lrs_set_orbitals", _I, [_P, _I, _I, _I, _I, _P, _D, _D, _P, _I, _D]),
-    ("lrs_set_orbitals_real", _I, [_P, _I, _I, _I, _P, _D, _D, _P, _I, _D]),
+    ("lrs_set_orbitals_real", _I, [_P, _I, _I, _I, _I, _P, _D, _D, _P, _I, _D]),
     ("lrs_set_sites", _I, [_P, _I, _P, _P, _P, _P, _P, _P, _P, _I]),
     ("lrs_set_quadrature", _I, [_P, _I, _P, _P, _P]),
     ("lrs_make_quadrature", _I, [_P, _I, _I, _D]),
@@ -160,19 +160,22 @@ class Context:
 
     def set_orbitals_real(self, energies, nocc, psi_grid=None, grid_dV=0.0, spin=2,
                           mu=float("nan"), delta=0.0):
-        """Real orbitals at the Gamma point: energies [nb] (or [1, nb]), psi_grid [nb, ngrid]
-        (or [1, nb, ngrid]) real, or complex with vanishing imaginary parts."""
-        E = _host(energies, np.float64).reshape(-1)
-        nb = E.shape[0]
+        """Real orbitals (Gamma, or k-points equal to their negatives modulo the reciprocal
+        lattice): energies [nk, nb] (or [nb] at one k), psi_grid [nk, nb, ngrid] (or
+        [nb, ngrid]) real, or complex with vanishing imaginary parts."""
+        E = _host(energies, np.float64)
+        if E.ndim == 1:
+            E = E[None]
+        nk, nb = E.shape
         g = None
         ngrid = 0
         if psi_grid is not None:
-            g = _dev(psi_grid, torch.complex128, self.device).reshape(nb, -1).contiguous()
-            ngrid = g.shape[1]
+            g = _dev(psi_grid, torch.complex128, self.device).reshape(nk, nb, -1).contiguous()
+            ngrid = g.shape[2]
         self.orb_version += 1
-        self._check(lib.lrs_set_orbitals_real(self.h, nb, nocc, spin, _ptr(E), mu, delta, _ptr(g),
-                                              ngrid, grid_dV))
-        self.nk, self.nb, self.nocc, self.ngrid = 1, nb, nocc, ngrid
+        self._check(lib.lrs_set_orbitals_real(self.h, nk, nb, nocc, spin, _ptr(E), mu, delta,
+                                              _ptr(g), ngrid, grid_dV))
+        self.nk, self.nb, self.nocc, self.ngrid = nk, nb, nocc, ngrid
 
     def set_sites(self, sites, psi_site, lmax=2):
         nrad = _host([s.n_rad for s in sites], np.int32)

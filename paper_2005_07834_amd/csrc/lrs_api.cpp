@@ -675,7 +675,7 @@ lrs_status lrs_check_bands(int nk, int nb, int nocc, const double* e, double mu,
 }
 
 namespace {
-// lrs_set_orbitals, and with real != 0 lrs_set_orbitals_real (nk = 1)
+// lrs_set_orbitals, and with real != 0 lrs_set_orbitals_real
 lrs_status set_orbitals_impl(lrs_ctx* ctx, int nk, int nb, int nocc, int spin_factor,
                              const double* e, double mu, double delta, const void* psi_grid,
                              int ngrid, double grid_dV, int real) {
@@ -775,10 +775,10 @@ lrs_status lrs_set_orbitals(lrs_ctx* ctx, int nk, int nb, int nocc, int spin_fac
                            grid_dV, 0);
 }
 
-lrs_status lrs_set_orbitals_real(lrs_ctx* ctx, int nb, int nocc, int spin_factor,
+lrs_status lrs_set_orbitals_real(lrs_ctx* ctx, int nk, int nb, int nocc, int spin_factor,
                                  const double* e, double mu, double delta, const void* psi_grid,
                                  int ngrid, double grid_dV) {
-  return set_orbitals_impl(ctx, 1, nb, nocc, spin_factor, e, mu, delta, psi_grid, ngrid,
+  return set_orbitals_impl(ctx, nk, nb, nocc, spin_factor, e, mu, delta, psi_grid, ngrid,
                            grid_dV, 1);
 }
 
@@ -815,7 +815,8 @@ lrs_status lrs_set_sites(lrs_ctx* ctx, int nsites, const int* nrad, const int* n
   if (bad) return fail(ctx, LRS_ENONFINITE, "non-finite value in psi_site");
   if (ctx->real_mode) {
     float mi = 0;
-    CHECK(device_max_abs_im(ctx, (const double*)psi_site, (long long)ctx->nb * nrows, &mi));
+    CHECK(device_max_abs_im(ctx, (const double*)psi_site, (long long)ctx->nk * ctx->nb * nrows,
+                            &mi));
     if (!(mi <= 1e-12f * m))
       return fail(ctx, LRS_EINVAL, "psi_site is not real (the orbitals were set real): max|Im| "
                   "%g against max|Re| %g", mi, m);

@@ -3,7 +3,7 @@
 The synthetic crystals have a real potential, so their Gamma orbitals can be made real: a phase
 per band and a real basis of each degenerate set (a unitary change within the set, which leaves
 chi0 unchanged, since a set's orbitals carry equal weights).  The tests make them real
-(`realify`, on the device), then compare the library's real-orbital chi0 (FP64 and F16F8)
+(`workloads.realify`, on the device), then compare the library's real-orbital chi0 (FP64 and F16F8)
 with the oracle's band-pair sum on the same real orbitals, and with the library's complex path
 on the original orbitals.  Error measure: max |gpu - ref| / max |ref|.
 """
@@ -16,6 +16,7 @@ import torch
 from oracle import chi0 as cz
 from oracle import quadrature as q
 from tests.conftest import workload
+from workloads.realify import realify
 
 pytestmark = pytest.mark.gpu
 
@@ -38,32 +39,6 @@ def rel(a, b):
     return float(np.abs(a - b).max() / np.abs(b).max())
 
 
-def realify(E, arrays, tol=1e-8):
-    """Real orbitals spanning each degenerate set of complex Gamma orbitals.  arrays: complex
-    [nb, P_i] device tensors sampling the same orbitals (the first, a full grid, fixes the
-    change of basis); returns their real versions (float64) and the largest imaginary part
-    left relative to the largest value, over all arrays."""
-    nb = len(E)
-    out = [torch.empty_like(a) for a in arrays]
-    b = 0
-    while b < nb:
-        e = b + 1
-        while e < nb and abs(E[e] - E[b]) <= tol * max(1.0, abs(E[b])):
-            e += 1
-        V = arrays[0][b:e]                                    # [d, Ng]
-        A = torch.cat([V.real, V.imag])                       # [2d, Ng] real
-        _, _, Wh = torch.linalg.svd(A, full_matrices=False)
-        W = Wh[: e - b].to(V.dtype)                           # real orthonormal rows
-        G = V @ V.conj().T                                    # [d, d], a multiple of I
-        C = (W @ V.conj().T) @ torch.linalg.inv(G)            # W = C V
-        C = C * torch.sqrt(torch.diagonal(G).real.mean())     # keep the orbitals' norms
-        for o, a in zip(out, arrays):
-            o[b:e] = C @ a[b:e]
-        b = e
-    left = max(float(o.imag.abs().max() / o.abs().max()) for o in out)
-    return [o.real.contiguous() for o in out], left
-
-
 def oracle_scale(E, nocc, n):
     mu = q.mid_gap(E, nocc)
     x, y = q.offsets(E, nocc, mu)
@@ -74,8 +49,8 @@ def oracle_scale(E, nocc, n):
 def tiny_real():
     w = workload("tiny")
     E = w.energies[0]
-    (g, s), left = realify(E, [w.psi_grid[0].to("cuda"), w.psi_site[0].to("cuda")])
-    return dict(w=w, E=E, g=g, s=s, left=left)
+    (g, s), left = realify(w.energies, [w.psi_grid.to("cuda"), w.psi_site.to("cuda")])
+    return dict(w=w, E=E, g=g[0], s=s[0], left=left)
 
 
 def test_real_orbitals_tiny(P, tiny_real):
@@ -149,7 +124,8 @@ def test_real_orbitals_precision_gamma(P):
     from workloads import configs
     w = configs.precision(device="cuda", gamma_only=True)
     E = w.energies[0]
-    (g, s), left = realify(E, [w.psi_grid[0], w.psi_site[0]])
+    (g, s), left = realify(w.energies, [w.psi_grid, w.psi_site])
+    g, s = g[0], s[0]
     say(f"precision at Gamma: real orbitals, imaginary part left {left:.1e}")
     assert left < 1e-10
     n = w.n_terms
@@ -186,4 +162,54 @@ def test_real_orbitals_precision_gamma(P):
         say(f"  {prec} real: {times[prec + ' real']:.0f} ms (complex orbitals "
             f"{times[prec + ' complex']:.0f} ms), vs oracle {e:.2e}")
         assert e < tol
+    ctx.close()
+
+
+def test_real_orbitals_many_k(P):
+    """Real orbitals at 8 k-points (production workload: 576 bands, 2 sites of 800 points, 24^3
+    grid, 24 terms).  chi0 is defined for any orbital set, so the real parts of the workload's
+    orbitals serve as the input: FP64 and F16F8 site x grid and site blocks from the real path,
+    sampled against the oracle on the same real orbitals, and the FP64 result against the
+    complex path given the same orbitals as complex values."""
+    w = workload("production")
+    n = w.n_terms
+    g = w.psi_grid.real.contiguous()
+    s = w.psi_site.real.contiguous()
+    ctx = P.Context(0)
+    ctx.set_orbitals_real(w.energies, w.nocc, g, w.grid_dV)
+    ctx.set_sites(w.sites, s)
+    ctx.make_quadrature(P.QUAD_TIME, n, 0.0)
+    scale = ctx.get_quadrature()["scale"]
+    c2 = P.Context(0)
+    c2.set_orbitals(w.energies, w.nocc, g.to(torch.complex128), w.grid_dV)
+    c2.set_sites(w.sites, s.to(torch.complex128))
+    c2.make_quadrature(P.QUAD_TIME, n, scale)
+    cplx = c2.chi0(-1, P.COLS_GRID, P.FP64).cpu().numpy()
+    cplx_s = c2.chi0(-1, P.COLS_SITE, P.FP64).cpu().numpy()
+    c2.close()
+    rng = np.random.default_rng(5)
+    rows = rng.integers(0, w.nrows, 40)
+    cols = rng.integers(0, w.ngrid ** 3, 40)
+    sg = s.numpy().astype(np.complex128)
+    gg = g.numpy().astype(np.complex128)
+    terms = cz.terms_for(w.energies, w.nocc, "time", n, scale)
+    ref = cz.chi0_quad_entries(sg[:, :, rows], gg[:, :, cols], w.nocc, 2, *terms)
+    site = 1
+    o = w.site_offsets[site]
+    m = w.site_offsets[site + 1] - o
+    ra = rng.integers(0, m, 40)
+    rb = rng.integers(0, m, 40)
+    ref_s = cz.chi0_quad_entries(sg[:, :, o + ra], sg[:, :, o + rb], w.nocc, 2, *terms)
+    for prec, tol in (("fp64", 1e-12), ("f16f8", 1e-4)):
+        got = ctx.chi0(-1, P.COLS_GRID, prec).cpu().numpy()
+        blk = ctx.site_blocks(ctx.chi0(-1, P.COLS_SITE, prec))[site].cpu().numpy()
+        eg = rel(got[rows, cols], ref)
+        es = rel(blk[ra, rb], ref_s)
+        say(f"  8 k real {prec}: grid {eg:.2e} site {es:.2e} vs oracle")
+        assert eg < tol and es < tol
+        if prec == "fp64":
+            ec = rel(got, cplx)
+            ecs = rel(ctx.chi0(-1, P.COLS_SITE, prec).cpu().numpy(), cplx_s)
+            say(f"  8 k real vs complex path: grid {ec:.2e} site {ecs:.2e}")
+            assert ec < 1e-12 and ecs < 1e-12
     ctx.close()
