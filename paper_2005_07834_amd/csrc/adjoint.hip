@@ -644,9 +644,20 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
   B.per = (B.ntiles + 7) / 8;
   const int chunk = chunk_of(prec);
   const double g_scale = is_f16(prec) ? (double)ctx->site_scale_f16 * ctx->site_scale_f16 : 1.0;
+  // the Green's functions an F16F8 launch over every site block kept (same quadrature, sites
+  // and orbitals; any change of those drops them): H from them instead of recomputing G
+  const bool kept = prec == LRS_F16F8 && ctx->g_keep_prec == LRS_F16F8 && ctx->g_keep.p &&
+                    ctx->g_keep.bytes >= (size_t)2 * T * tot * 8;
   for (int t = 0; t < T; ++t) {
+    if (kept) {
+      const char* ko = (const char*)ctx->g_keep.p + (size_t)t * tot * 8;
+      e = launch_h_from_kept(ko, ko + (size_t)T * tot * 8, S, dblk_off, dpblk_off, dblk_n, lam,
+                             lam_a, odd ? ctx->quad.c[t] : 0.0, odd ? ctx->quad.ci[t] : 0.0,
+                             hs_u, hs_o, st);
+      if (e != hipSuccess) return e;
+    }
     for (const Batch& bt : plan->batches) {
-      if (bt.ntiles == 0) continue;
+      if (kept || bt.ntiles == 0) continue;
       const void* a_op = nullptr;
       // (LRS_ESTATE: a buffer that captured graphs read would have to be replaced)
       lrs_status ls = ensure_site_operand(ctx, prec, bt, t, 1, &a_op);

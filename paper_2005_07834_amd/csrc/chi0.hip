@@ -74,6 +74,11 @@ struct Chi0Params {
   double* ho_im;
   __bf16* hs_u;
   __bf16* hs_o;
+  // mode 0 on site blocks: keep each term's G_o and G_u (FP32 complex, the output's element
+  // offsets, term stride keep_stride) on and above the diagonal for the adjoint, or null
+  float2* keep_o;
+  float2* keep_u;
+  long long keep_stride;
 };
 
 // x = hi + lo in bfloat16 (hi rounded from x, lo from the remainder), re and im of one
@@ -1135,6 +1140,15 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
                 if (P.sym && dg[e] > 0) P.out[obase + off[e] + (long long)dg[e] * (td.ldo - 1)] = r;
               }
             }
+            if (P.keep_o) {
+              const long long kb = (long long)t * P.keep_stride + obase;
+#pragma unroll
+              for (int e = 0; e < ELEMS; ++e)
+                if (in[e] && dg[e] >= 0) {
+                  P.keep_o[kb + off[e]] = float2{(float)or_[e], (float)oi_[e]};
+                  P.keep_u[kb + off[e]] = float2{(float)gr[i][j][e], (float)gi[i][j][e]};
+                }
+            }
           }
         }
     }
@@ -1332,8 +1346,12 @@ hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int
                        const void* b_tiles, int b_ncb, int nch, const double* c,
                        const double* ci, int T, int nch_o, const TileDesc* tiles, int ntiles,
                        double* out, double pref, int sym, unsigned int* sync, void* park,
-                       int real, hipStream_t s) {
+                       int real, void* keep_o, void* keep_u, long long keep_stride,
+                       hipStream_t s) {
   Chi0Params P;
+  P.keep_o = (float2*)keep_o;
+  P.keep_u = (float2*)keep_u;
+  P.keep_stride = keep_stride;
   P.ci = ci;
   P.sym = sym;
   P.sync = sync;
@@ -1380,6 +1398,8 @@ hipError_t launch_green_adjoint(int prec, int grid, const void* a_tiles, int a_n
                                 double* hu_re, double* hu_im, double* ho_re, double* ho_im,
                                 void* hs_u, void* hs_o, void* park, hipStream_t s) {
   Chi0Params P;
+  P.keep_o = P.keep_u = nullptr;
+  P.keep_stride = 0;
   P.park = (unsigned char*)park;
   P.a = (const unsigned char*)a_tiles;
   P.a_nrb = a_nrb;
@@ -1412,6 +1432,59 @@ hipError_t launch_green_adjoint(int prec, int grid, const void* a_tiles, int a_n
     case LRS_F16F8: return launch_v<LRS_F16F8, 1, 2>(grid, P, s);
   }
   return hipErrorInvalidValue;
+}
+
+namespace {
+// The adjoint's H = (coefficient matrix) o conj(G) from one term's kept Green's functions, the
+// same arithmetic and layout as the mode-2 epilogue: per site block element (r, c) on or above
+// the diagonal, H at (r, c) and its conjugate at (c, r), bfloat16 hi/lo in operand tiles.
+__global__ __launch_bounds__(256) void h_from_kept_kernel(
+    const float2* keep_o, const float2* keep_u, const long long* blk_off,
+    const long long* pblk_off, const int* blk_n, const double* lam, const double* lam_a,
+    double adj_c, double adj_s, __bf16* hs_u, __bf16* hs_o) {
+  const int st = blockIdx.y;
+  const int n = blk_n[st];
+  const int np = site_block_ld(n, 1);
+  const long long kb = blk_off[st], pb = pblk_off[st];
+  const long long hb = 4 * pb;
+  const long long nn = (long long)n * n;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < nn;
+       q += (long long)gridDim.x * blockDim.x) {
+    const int r = (int)(q / n), c = (int)(q - (long long)r * n);
+    if (c < r) continue;
+    const float2 go = keep_o[kb + q], gu = keep_u[kb + q];
+    const double l = lam[pb + (long long)r * np + c];
+    double hur = l * (double)gu.x, hui = -l * (double)gu.y;
+    double hor = l * (double)go.x, hoi = -l * (double)go.y;
+    if (lam_a) {
+      const double a = adj_c * l, b = adj_s * lam_a[pb + (long long)r * np + c];
+      const double ur = gu.x, ui = gu.y, vr = go.x, vi = go.y;
+      hur = a * ur + b * ui;
+      hui = b * ur - a * ui;
+      hor = a * vr - b * vi;
+      hoi = -b * vr - a * vi;
+    }
+    const long long ht = hb + h_tile_offset(r, c, np);
+    put_split(hs_u, 512, ht, hur, hui);
+    put_split(hs_o, 512, ht, hor, hoi);
+    if (c > r) {
+      const long long htt = hb + h_tile_offset(c, r, np);
+      put_split(hs_u, 512, htt, hur, -hui);
+      put_split(hs_o, 512, htt, hor, -hoi);
+    }
+  }
+}
+}  // namespace
+
+hipError_t launch_h_from_kept(const void* keep_o, const void* keep_u, int nsites,
+                              const long long* blk_off, const long long* pblk_off,
+                              const int* blk_n, const double* lam, const double* lam_a,
+                              double adj_c, double adj_s, void* hs_u, void* hs_o,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(h_from_kept_kernel, dim3(2048, nsites), dim3(256), 0, s,
+                     (const float2*)keep_o, (const float2*)keep_u, blk_off, pblk_off, blk_n, lam,
+                     lam_a, adj_c, adj_s, (__bf16*)hs_u, (__bf16*)hs_o);
+  return hipGetLastError();
 }
 
 }  // namespace lrs

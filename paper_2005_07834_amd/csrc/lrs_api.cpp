@@ -100,6 +100,8 @@ void drop_sites(lrs_ctx* ctx) {
   release(ctx, ctx->psi_site_bf16);
   for (auto& b : ctx->site_tiles) release(ctx, b);
   release(ctx, ctx->site_colmap);
+  release(ctx, ctx->g_keep);
+  ctx->g_keep_prec = -1;
   ctx->have_sites = false;
   ctx->have_W = false;
   ctx->have_rho = false;
@@ -110,6 +112,7 @@ void drop_quad(lrs_ctx* ctx) {
   release(ctx, ctx->w_nat);
   release(ctx, ctx->c_dev);
   ctx->a_prec = -1;
+  ctx->g_keep_prec = -1;
   ctx->have_quad = false;
   ctx->quad = Quad();
 }
@@ -537,6 +540,26 @@ lrs_status run_chi0(lrs_ctx* ctx, int site, int cols, int prec, int variant, dou
   const double g_scale = a_scale * bscale;   // each G carries a_scale * b_scale
   pref /= g_scale * g_scale;
   const int T = ctx->quad.nterms;
+  // an F16F8 launch over every site block keeps each term's Green's functions for the adjoint
+  // (which would otherwise recompute them) when they fit in kKeepMaxBytes
+  void* keep_o = nullptr;
+  void* keep_u = nullptr;
+  long long keep_stride = 0;
+  if (cols == LRS_COLS_SITE && site < 0 && prec == LRS_F16F8 && !ctx->real_mode &&
+      max_tiles == 0 && !ctx->capturing) {
+    for (int s = 0; s < ctx->nsites; ++s) {
+      const long long n = ctx->site_off[s + 1] - ctx->site_off[s];
+      keep_stride += n * n;
+    }
+    const size_t bytes = (size_t)2 * T * keep_stride * 8;
+    ctx->g_keep_prec = -1;
+    if (bytes <= kKeepMaxBytes && ensure_buf(ctx, ctx->g_keep, bytes, "kept G") == LRS_OK) {
+      keep_o = ctx->g_keep.p;
+      keep_u = (char*)ctx->g_keep.p + (size_t)T * keep_stride * 8;
+    } else {
+      ctx->err.clear();     // (not kept: the adjoint recomputes them)
+    }
+  }
   bool first = true;
   for (const Batch& bt : plan->batches) {
     if (bt.ntiles == 0) continue;
@@ -564,13 +587,15 @@ lrs_status run_chi0(lrs_ctx* ctx, int site, int cols, int prec, int variant, dou
                                  odd ? (const double*)ctx->c_dev.p + T : nullptr, T,
                                  ctx->Ko_pad / KC, (const TileDesc*)plan->tiles.p + bt.tile0, nt,
                                  out, pref, cols == LRS_COLS_SITE && !odd, sync, ctx->park.p,
-                                 ctx->real_mode ? 1 : 0, ctx->stream));
+                                 ctx->real_mode ? 1 : 0, keep_o, keep_u, keep_stride,
+                                 ctx->stream));
     if (max_tiles > 0) break;
   }
   if (timed && !first) {
     HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev1, ctx->stream));
     ctx->timed = true;
   }
+  if (keep_o) ctx->g_keep_prec = prec;
   return LRS_OK;
 }
 
@@ -645,6 +670,7 @@ void lrs_destroy(lrs_ctx* ctx) {
   release(ctx, ctx->proj_work);
   release(ctx, ctx->a_tiles);
   release(ctx, ctx->park);
+  release(ctx, ctx->g_keep);
   release(ctx, ctx->xcd_sync);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);

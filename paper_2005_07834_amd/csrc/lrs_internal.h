@@ -26,6 +26,8 @@ constexpr int kMaxTileCols = 256;
 // each K phase (occupied, unoccupied) is padded to this: a multiple of four chunks of every
 // precision, so the kernel's four-slot LDS ring starts every phase at slot 0
 constexpr int kPhaseAlign = 128;
+// largest set of Green's functions an F16F8 site-block launch keeps for the adjoint
+constexpr size_t kKeepMaxBytes = (size_t)16 << 30;
 constexpr int kMaxTerms = 128;
 
 __host__ __device__ inline bool is_split(int prec) { return prec == LRS_BF16X2 || prec == LRS_FP16X2; }
@@ -36,7 +38,7 @@ constexpr int kNumPrec = 6;
 // the adjoint's internal site blocks (plan mode 1): a whole number of four-chunk ring cycles
 // of the adjoint GEMMs' contraction, whose padding is zero
 constexpr int kAdjAlign = 64;
-inline int site_block_ld(int n, int mode) {
+__host__ __device__ inline int site_block_ld(int n, int mode) {
   return mode == 1 ? (n + kAdjAlign - 1) / kAdjAlign * kAdjAlign : n;
 }
 // K values per chunk and bytes per fragment tile (16 rows x chunk x planes)
@@ -176,6 +178,11 @@ struct lrs_ctx {
   lrs::DevBuf site_tiles[lrs::kNumPrec];   // site points as a column operand (fragment tiles)
   lrs::DevBuf a_tiles;            // weighted site operand tiles of the current batch
   lrs::DevBuf park;               // per-workgroup G_o scratch of the chi0 launches
+  // Green's functions of every term on the site blocks, kept by an F16F8 chi0 launch over all
+  // sites for the adjoint (G_o then G_u, FP32 complex [T][sum n^2] each); g_keep_prec is the
+  // precision they hold, -1 when they are absent or stale
+  lrs::DevBuf g_keep;
+  int g_keep_prec = -1;
   lrs::DevBuf xcd_sync;           // per-XCD term counters of the chi0 launches
   int a_prec = -1, a_version = -1, a_rb0 = -1, a_nrb = -1, a_t0 = -1, a_nt = -1;
   lrs::DevBuf psi_site_f64;       // planar [2][K_pad][rows_pad] (k-major rows) for the adjoint
@@ -260,11 +267,14 @@ hipError_t launch_prep_site(int prec, const double* site, int rows_pad, int K_pa
 // ci: imaginary parts of the term coefficients (null: real); sym must be 0 then (the odd
 // part of chi0 at imaginary frequency is antisymmetric on a site block)
 // real: the operands hold real orbitals two to a slot (FP64 and F16F8 only)
+// keep_o, keep_u (site blocks, or null): each term's G_o and G_u as FP32 complex at the
+// output's element offsets plus t * keep_stride, on and above the diagonal
 hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int a_nrb,
                        const void* b_tiles, int b_ncb, int nch, const double* c,
                        const double* ci, int T, int nch_o, const TileDesc* tiles, int ntiles,
                        double* out, double pref, int sym, unsigned int* sync, void* park,
-                       int real, hipStream_t s);
+                       int real, void* keep_o, void* keep_u, long long keep_stride,
+                       hipStream_t s);
 // adjoint Green's functions of one term on site blocks: prec LRS_FP64 writes Hu, Ho as FP64
 // planes (hu_re, hu_im, ho_re, ho_im; row stride ld); LRS_BF16X2 and LRS_F16F8 (variant 1)
 // write each at hs_u, hs_o as bfloat16 hi/lo in the split adjoint GEMM's operand tiles
@@ -275,6 +285,13 @@ hipError_t launch_green_adjoint(int prec, int grid, const void* a_tiles, int a_n
                                 const double* lam_a, double adj_c, double adj_s,
                                 double* hu_re, double* hu_im, double* ho_re, double* ho_im,
                                 void* hs_u, void* hs_o, void* park, hipStream_t s);
+// the same split H (hs_u, hs_o) of one term from its kept G_o, G_u (keep_o, keep_u at the
+// caller's site-block offsets blk_off; lam, lam_a and H at the padded offsets pblk_off)
+hipError_t launch_h_from_kept(const void* keep_o, const void* keep_u, int nsites,
+                              const long long* blk_off, const long long* pblk_off,
+                              const int* blk_n, const double* lam, const double* lam_a,
+                              double adj_c, double adj_s, void* hs_u, void* hs_o,
+                              hipStream_t s);
 
 // lrs_api.cpp (shared with the adjoint)
 lrs_status plan_for(lrs_ctx* ctx, int site, int cols, int prec, int variant, int mode,

@@ -256,6 +256,31 @@ def test_split_adjoint_matches_fp64(P):
     ctx.close()
 
 
+def test_kept_green_functions_match_recompute(P):
+    """The F16F8 adjoint built from the Green's functions that the forward site-block launch
+    keeps equals, bit for bit, the adjoint that recomputes them (differentiation workload, 4
+    sites of 800 points; the static rule and chi0 at imaginary frequency); a new quadrature
+    drops the kept ones, so the second call recomputes."""
+    w = workload("differentiation")
+    n = w.n_terms
+    s = oracle_scale(w, n)
+    ctx = make_ctx(P, w, n, s, grid=False)
+    rng = np.random.default_rng(31)
+    lam = torch.as_tensor(rng.standard_normal(sum(x.npts ** 2 for x in w.sites)), device="cuda")
+    rules = (("static", lambda: ctx.make_quadrature(P.QUAD_TIME, n, s)),
+             ("i omega", lambda: ctx.make_quadrature_iw(n, 0.0, 0.3)))
+    for name, rule in rules:
+        rule()
+        ctx.chi0(-1, P.COLS_SITE, P.F16F8)           # keeps every term's G_o, G_u
+        dE1, dp1 = ctx.chi0_backward(lam, P.F16F8)
+        rule()                                        # drops them
+        dE2, dp2 = ctx.chi0_backward(lam, P.F16F8)    # recomputes them
+        say(f"kept vs recomputed Green's functions ({name}): dE equal "
+            f"{torch.equal(dE1, dE2)}, dpsi equal {torch.equal(dp1, dp2)}")
+        assert torch.equal(dE1, dE2) and torch.equal(dp1, dp2)
+    ctx.close()
+
+
 # ------------------------------------------------------------------ batching
 def test_batching_uneven_sites(P):
     """64 sites with uneven radial x angular grids, 2x2x2 k, 28 terms: all site x site blocks
