@@ -507,11 +507,17 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
   if (ensure_site_tiles_for(ctx, prec) != LRS_OK) return hipErrorOutOfMemory;
   Plan* plan = nullptr;
   if (plan_for(ctx, -1, LRS_COLS_SITE, prec, gvar, 1, &plan) != LRS_OK) return hipErrorOutOfMemory;
-  hipError_t e = ensure(ctx, ctx->psi_site_f64, (size_t)2 * ctx->K_pad * ctx->rows_pad * 8);
-  if (e != hipSuccess) return e;
-  e = launch_derive_site_kmajor((const double*)ctx->site_f64.p, ctx->rows_pad, ctx->K_pad,
-                                (double*)ctx->psi_site_f64.p, st);
-  if (e != hipSuccess) return e;
+  // (the k-major orbitals and their split copy depend on the orbitals and sites only: built
+  // once, dropped with the sites)
+  hipError_t e = hipSuccess;
+  if (!ctx->psi_kmajor_ok) {
+    e = ensure(ctx, ctx->psi_site_f64, (size_t)2 * ctx->K_pad * ctx->rows_pad * 8);
+    if (e != hipSuccess) return e;
+    e = launch_derive_site_kmajor((const double*)ctx->site_f64.p, ctx->rows_pad, ctx->K_pad,
+                                  (double*)ctx->psi_site_f64.p, st);
+    if (e != hipSuccess) return e;
+    ctx->psi_kmajor_ok = true;
+  }
 
   // site blocks (the caller's n x n layout, and the padded one of the H arrays), the split
   // orbital rows (64-row slot per site) and the GEMM tile list
@@ -565,8 +571,10 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
   e = ensure(ctx, ctx->adj_work, bytes);
   if (e != hipSuccess) return e;
   if (split) {
+    const void* had = ctx->psi_site_bf16.p;
     e = ensure(ctx, ctx->psi_site_bf16, (size_t)8 * Kp * srows);
     if (e != hipSuccess) return e;
+    if (ctx->psi_site_bf16.p != had) ctx->psi_split_ok = false;
   }
   char* p = (char*)ctx->adj_work.p;
   auto take = [&](size_t b) {
@@ -600,13 +608,14 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
       (e = hipMemcpyAsync(dpblk_off, pblk_off.data(), S * 8, hipMemcpyHostToDevice, st)) ||
       (e = hipMemcpyAsync(dblk_n, blk_n.data(), S * 4, hipMemcpyHostToDevice, st)))
     return e;
-  if (split) {
+  if (split && !ctx->psi_split_ok) {
     if ((e = hipMemcpyAsync(drowmap, rowmap.data(), rowmap.size() * 4, hipMemcpyHostToDevice, st)))
       return e;
     hipLaunchKernelGGL(split_psi_kernel, dim3(4096), dim3(256), 0, st,
                        (const double*)ctx->psi_site_f64.p, ctx->rows_pad, ctx->K_pad, drowmap,
                        srows, (__bf16*)ctx->psi_site_bf16.p);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    ctx->psi_split_ok = true;
   }
   hipLaunchKernelGGL(symmetrise_kernel, dim3(256, S), dim3(256), 0, st, dL_dchi0, dblk_off,
                      dpblk_off, dblk_n, S, lam, lam_a);
@@ -651,7 +660,8 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
   for (int t = 0; t < T; ++t) {
     if (kept) {
       const char* ko = (const char*)ctx->g_keep.p + (size_t)t * tot * 8;
-      e = launch_h_from_kept(ko, ko + (size_t)T * tot * 8, S, dblk_off, dpblk_off, dblk_n, lam,
+      e = launch_h_from_kept(ko, ko + (size_t)T * tot * 8, S, dblk_off, dpblk_off, dblk_n,
+                             blk_n.data(), lam,
                              lam_a, odd ? ctx->quad.c[t] : 0.0, odd ? ctx->quad.ci[t] : 0.0,
                              hs_u, hs_o, st);
       if (e != hipSuccess) return e;

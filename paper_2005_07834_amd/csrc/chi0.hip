@@ -1436,52 +1436,64 @@ hipError_t launch_green_adjoint(int prec, int grid, const void* a_tiles, int a_n
 
 namespace {
 // The adjoint's H = (coefficient matrix) o conj(G) from one term's kept Green's functions, the
-// same arithmetic and layout as the mode-2 epilogue: per site block element (r, c) on or above
-// the diagonal, H at (r, c) and its conjugate at (c, r), bfloat16 hi/lo in operand tiles.
-__global__ __launch_bounds__(256) void h_from_kept_kernel(
+// same arithmetic and values as the mode-2 epilogue.  One workgroup per operand-tile piece (32
+// block rows p x 16 block columns r, four planes of 512 values), element e of each plane at
+// p = 32 (piece row) + (e / 8) % 32, r = 16 (piece column) + 8 (e / 256) + e % 8, so each wave
+// writes whole runs of a plane.  G, lam and lam_a are kept on and above the diagonal only:
+// below it H(p, r) = conj(H(r, p)), formed from the transposed element.
+__global__ __launch_bounds__(512) void h_from_kept_kernel(
     const float2* keep_o, const float2* keep_u, const long long* blk_off,
     const long long* pblk_off, const int* blk_n, const double* lam, const double* lam_a,
     double adj_c, double adj_s, __bf16* hs_u, __bf16* hs_o) {
   const int st = blockIdx.y;
   const int n = blk_n[st];
   const int np = site_block_ld(n, 1);
-  const long long kb = blk_off[st], pb = pblk_off[st];
-  const long long hb = 4 * pb;
-  const long long nn = (long long)n * n;
-  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < nn;
-       q += (long long)gridDim.x * blockDim.x) {
-    const int r = (int)(q / n), c = (int)(q - (long long)r * n);
-    if (c < r) continue;
-    const float2 go = keep_o[kb + q], gu = keep_u[kb + q];
-    const double l = lam[pb + (long long)r * np + c];
-    double hur = l * (double)gu.x, hui = -l * (double)gu.y;
-    double hor = l * (double)go.x, hoi = -l * (double)go.y;
-    if (lam_a) {
-      const double a = adj_c * l, b = adj_s * lam_a[pb + (long long)r * np + c];
-      const double ur = gu.x, ui = gu.y, vr = go.x, vi = go.y;
-      hur = a * ur + b * ui;
-      hui = b * ur - a * ui;
-      hor = a * vr - b * vi;
-      hoi = -b * vr - a * vi;
-    }
-    const long long ht = hb + h_tile_offset(r, c, np);
-    put_split(hs_u, 512, ht, hur, hui);
-    put_split(hs_o, 512, ht, hor, hoi);
-    if (c > r) {
-      const long long htt = hb + h_tile_offset(c, r, np);
-      put_split(hs_u, 512, htt, hur, -hui);
-      put_split(hs_o, 512, htt, hor, -hoi);
-    }
+  const int npr = np >> 5, npc = np >> 4;            // pieces along p and along r
+  const int piece = blockIdx.x;
+  if (piece >= npr * npc) return;
+  const int pb = piece % npr, rb = piece / npr;
+  const int e = threadIdx.x;
+  const int p = pb * 32 + ((e >> 3) & 31), r = rb * 16 + ((e >> 8) << 3) + (e & 7);
+  if (p >= n || r >= n) return;                     // padding stays zero
+  const bool up = r >= p;
+  const int a = up ? p : r, b = up ? r : p;         // the kept element (a <= b)
+  const long long kk = blk_off[st] + (long long)a * n + b;
+  const long long lk = pblk_off[st] + (long long)a * np + b;
+  const float2 go = keep_o[kk], gu = keep_u[kk];
+  const double l = lam[lk];
+  double hur = l * (double)gu.x, hui = -l * (double)gu.y;
+  double hor = l * (double)go.x, hoi = -l * (double)go.y;
+  if (lam_a) {
+    const double ac = adj_c * l, bs = adj_s * lam_a[lk];
+    const double ur = gu.x, ui = gu.y, vr = go.x, vi = go.y;
+    hur = ac * ur + bs * ui;
+    hui = bs * ur - ac * ui;
+    hor = ac * vr - bs * vi;
+    hoi = -bs * vr - ac * vi;
   }
+  if (!up) {
+    hui = -hui;
+    hoi = -hoi;
+  }
+  const long long ht = 4 * pblk_off[st] + ((long long)(rb * npr + pb) << 11) + e;
+  put_split(hs_u, 512, ht, hur, hui);
+  put_split(hs_o, 512, ht, hor, hoi);
 }
 }  // namespace
 
 hipError_t launch_h_from_kept(const void* keep_o, const void* keep_u, int nsites,
                               const long long* blk_off, const long long* pblk_off,
-                              const int* blk_n, const double* lam, const double* lam_a,
+                              const int* blk_n, const int* blk_n_host, const double* lam,
+                              const double* lam_a,
                               double adj_c, double adj_s, void* hs_u, void* hs_o,
                               hipStream_t s) {
-  hipLaunchKernelGGL(h_from_kept_kernel, dim3(2048, nsites), dim3(256), 0, s,
+  int npmax = 0;
+  for (int i = 0; i < nsites; ++i) {
+    const int np = site_block_ld(blk_n_host[i], 1);
+    npmax = np > npmax ? np : npmax;
+  }
+  const int pieces = (npmax >> 5) * (npmax >> 4);
+  hipLaunchKernelGGL(h_from_kept_kernel, dim3(pieces, nsites), dim3(512), 0, s,
                      (const float2*)keep_o, (const float2*)keep_u, blk_off, pblk_off, blk_n, lam,
                      lam_a, adj_c, adj_s, (__bf16*)hs_u, (__bf16*)hs_o);
   return hipGetLastError();

@@ -98,6 +98,7 @@ void drop_sites(lrs_ctx* ctx) {
   ctx->a_prec = -1;
   release(ctx, ctx->psi_site_f64);
   release(ctx, ctx->psi_site_bf16);
+  ctx->psi_kmajor_ok = ctx->psi_split_ok = false;
   for (auto& b : ctx->site_tiles) release(ctx, b);
   release(ctx, ctx->site_colmap);
   release(ctx, ctx->g_keep);

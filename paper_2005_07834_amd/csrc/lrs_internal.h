@@ -188,6 +188,7 @@ struct lrs_ctx {
   lrs::DevBuf psi_site_f64;       // planar [2][K_pad][rows_pad] (k-major rows) for the adjoint
   lrs::DevBuf psi_site_bf16;      // the same split: bfloat16 [4][K_pad][rows_pad] (re hi, re lo,
                                   // im hi, im lo) for the split adjoint
+  bool psi_kmajor_ok = false, psi_split_ok = false;   // the two above are current
   float site_max_abs = 0.f;
   float grid_max_abs = 0.f;
 
@@ -286,10 +287,12 @@ hipError_t launch_green_adjoint(int prec, int grid, const void* a_tiles, int a_n
                                 double* hu_re, double* hu_im, double* ho_re, double* ho_im,
                                 void* hs_u, void* hs_o, void* park, hipStream_t s);
 // the same split H (hs_u, hs_o) of one term from its kept G_o, G_u (keep_o, keep_u at the
-// caller's site-block offsets blk_off; lam, lam_a and H at the padded offsets pblk_off)
+// caller's site-block offsets blk_off; lam, lam_a and H at the padded offsets pblk_off;
+// blk_n on the device, blk_n_host its host copy)
 hipError_t launch_h_from_kept(const void* keep_o, const void* keep_u, int nsites,
                               const long long* blk_off, const long long* pblk_off,
-                              const int* blk_n, const double* lam, const double* lam_a,
+                              const int* blk_n, const int* blk_n_host, const double* lam,
+                              const double* lam_a,
                               double adj_c, double adj_s, void* hs_u, void* hs_o,
                               hipStream_t s);
 
