@@ -190,6 +190,8 @@ def main():
     ap.add_argument("--no-batching", action="store_true",
                     help="skip the batching workload's site x grid launch timed at the end")
     ap.add_argument("--no-tune", action="store_true", help="use the default chi0 variant")
+    ap.add_argument("--no-gamma-real", action="store_true",
+                    help="skip the real-orbital launches at Gamma timed at the end")
     ap.add_argument("--adjoint-prec", default="auto", choices=["auto", "fp64", "bf16x2", "f16f8"],
                     help="precision of the adjoint's products (auto: bf16x2 with a split "
                          "--prec, else fp64)")
@@ -211,7 +213,7 @@ def main():
         return copy_calibration(args.copy_mib)
     if args.steps_only:
         args.no_cpu = args.no_fp64 = args.no_fp16 = True
-        args.no_projection = args.no_batching = True
+        args.no_projection = args.no_batching = args.no_gamma_real = True
 
     import torch
     import paper_2005_07834_amd as P
@@ -579,6 +581,58 @@ def main():
         log("batching", batching)
         del wb
 
+    # real orbitals at Gamma: the precision cell at one k-point, its orbitals made real
+    # (workloads/realify.py); the F16F8 and FP64 site x grid launches from the real orbitals
+    # beside the same launches from the complex ones, sampled against the oracle
+    gamma_real = None
+    if not args.no_gamma_real and args.workload == "precision" and not args.gamma:
+        from workloads.realify import realify
+        tg = time.time()
+        wg = configs.precision(device=dev, gamma_only=True)
+        (gre, sre), left = realify(wg.energies, [wg.psi_grid, wg.psi_site])
+        ngc = wg.ngrid ** 3
+        grows = rng.integers(0, wg.nrows, 64)
+        gcols = rng.integers(0, ngc, 64)
+        gr_t, gc_t = torch.as_tensor(grows, device=dev), torch.as_tensor(gcols, device=dev)
+        outg = torch.empty((wg.nrows, ngc), dtype=torch.float64, device=dev)
+        gamma_real = {"workload": "precision at Gamma", "rows": wg.nrows, "grid_columns": ngc,
+                      "bands": wg.nb, "terms": wg.n_terms, "imag_left_after_realify": left}
+        ctx3 = P.Context(0)
+        ctx3.set_orbitals(wg.energies, wg.nocc, wg.psi_grid, wg.grid_dV)
+        ctx3.set_sites(wg.sites, wg.psi_site)
+        ctx3.make_quadrature(P.QUAD_TIME, wg.n_terms, 0.0)
+        gscale = ctx3.get_quadrature()["scale"]
+        for p in ("f16f8", "fp64"):
+            ctx3.chi0(-1, P.COLS_GRID, p, out=outg)       # (the second call is the one timed)
+            ctx3.chi0(-1, P.COLS_GRID, p, out=outg)
+            gamma_real[p + "_complex_orbitals_ms"] = ctx3.last_kernel_ms()
+        ctx3.close()
+        wg.psi_grid = None
+        torch.cuda.empty_cache()
+        ctx3 = P.Context(0)
+        ctx3.set_orbitals_real(wg.energies, wg.nocc, gre, wg.grid_dV)
+        ctx3.set_sites(wg.sites, sre)
+        ctx3.make_quadrature(P.QUAD_TIME, wg.n_terms, gscale)
+        got_g = {}
+        for p in ("f16f8", "fp64"):
+            ctx3.chi0(-1, P.COLS_GRID, p, out=outg)
+            ctx3.chi0(-1, P.COLS_GRID, p, out=outg)
+            gamma_real[p + "_real_orbitals_ms"] = ctx3.last_kernel_ms()
+            got_g[p] = outg[gr_t, gc_t].cpu().numpy()
+        ctx3.close()
+        if not args.no_cpu:
+            tg_ = cz.terms_for(wg.energies, wg.nocc, "time", wg.n_terms, gscale)
+            refg = cz.chi0_quad_entries(sre[:, :, gr_t].cpu().numpy().astype(np.complex128),
+                                        gre[:, :, gc_t].cpu().numpy().astype(np.complex128),
+                                        wg.nocc, 2, *tg_)
+            for p in got_g:
+                gamma_real[p + "_rel_err_vs_same_quadrature"] = rel(got_g[p], refg)
+            gamma_real["entries_compared"] = int(grows.size)
+        gamma_real["leg_s"] = time.time() - tg
+        log("gamma real", gamma_real)
+        del wg, gre, sre, outg
+        torch.cuda.empty_cache()
+
     fp64 = paths.get("fp64", {})
     rec = {
         "metric": "chi0 entries/s + MFMA util: split-BF16 vs FP64 GPU path at stated rel. error",
@@ -623,6 +677,7 @@ def main():
         "imag_freq": iw,
         "site_solves": solves,
         "batching": batching,
+        "gamma_real": gamma_real,
         "pack_ms": pack_ms,
         "loss": float(loss.sum().item()),
     }
