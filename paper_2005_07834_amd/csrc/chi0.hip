@@ -741,20 +741,39 @@ __device__ __forceinline__ void mma_col_split(const FragsA<PREC, MB>& a, const F
 // The F16F8 path has fewer, longer matrix-core instructions per step than LDS reads and loads
 // together: two reads per instruction, then one load per instruction (LOADS_FIRST: the loads
 // go first, which gives them the most time to land before the step that waits for them).
-template <int PREC, int MB, int NB, int NVM, int S, bool LOADS_FIRST = false>
+// N times: one matrix-core instruction, two LDS reads, one global->LDS load
+template <int N>
+__device__ __forceinline__ void sched_read_load() {
+  if constexpr (N > 0) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+    __builtin_amdgcn_sched_group_barrier(0x010, 1, 0);
+    sched_read_load<N - 1>();
+  }
+}
+
+template <int PREC, int MB, int NB, int NVM, int S, bool LOADS_FIRST = false, bool RE = false>
 __device__ __forceinline__ void interleave() {
   constexpr int kMFMA = 0x008, kVMEM = 0x010, kDSREAD = 0x100;
   constexpr bool split = PREC == LRS_BF16X2 || PREC == LRS_FP16X2;
   constexpr bool f8 = PREC == LRS_F16F8;
-  // instructions per step: LDS reads of 16 bytes, matrix-core instructions
+  // instructions per step: LDS reads of 16 bytes, matrix-core instructions (real orbitals:
+  // no second fp8 column fragment, and only the products that feed Re G)
   constexpr bool m3 = PREC == LRS_FP64_3M;
-  constexpr int NDS = f8 ? 2 * MB + 3 * NB
+  constexpr int NDS = f8 ? (RE ? 2 * MB + 2 * NB : 2 * MB + 3 * NB)
                          : (split ? 2 * (MB + NB) : (m3 ? 6 * (MB + NB) : 4 * (MB + NB)));
-  constexpr int NMF = f8 ? 3 * MB * NB / 2
-                         : (split ? 3 * MB * NB
-                                  : (PREC == LRS_FP64 ? 16 * MB * NB : (m3 ? 12 * MB * NB : 32 * MB * NB)));
+  constexpr int NMF0 = f8 ? 3 * MB * NB / 2
+                          : (split ? 3 * MB * NB
+                                   : (PREC == LRS_FP64 ? 16 * MB * NB : (m3 ? 12 * MB * NB : 32 * MB * NB)));
+  constexpr int NMF = RE ? NMF0 / 2 : NMF0;
   constexpr int R = (NMF - NDS) / NVM > 0 ? (NMF - NDS) / NVM : 1;
-  if constexpr (f8 && LOADS_FIRST) {
+  if constexpr (f8 && RE) {
+    // too few matrix-core instructions for the read pairs and the loads one after the other:
+    // a load with each read pair, then the rest
+    static_assert(NDS % 2 == 0 && NVM <= NDS / 2 && NDS / 2 <= NMF, "F16F8 real step groups");
+    sched_read_load<NVM>();
+    sched_pairs<NDS / 2 - NVM, kMFMA, 1, kDSREAD, 2>();
+  } else if constexpr (f8 && LOADS_FIRST) {
     static_assert(NDS % 2 == 0 && NDS / 2 + NVM <= NMF, "F16F8 step groups");
     sched_pairs<NVM, kMFMA, 1, kVMEM, 1>();
     sched_pairs<NDS / 2, kMFMA, 1, kDSREAD, 2>();
@@ -963,9 +982,8 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
       } else {
         load_frags<PREC, MB, NB, MODE == 3>(sn + wm * MB * TB, sn + A_BYTES + wn * NB * TB, lane, nxt);
         issue_next(slot(I), q + S < nseq);
-        if constexpr (IL == 0 || MODE == 3) {
-          // LDS reads and loads first, then the matrix-core block (real orbitals: a third of
-          // the complex step's instructions, too few to spread the reads and loads over)
+        if constexpr (IL == 0) {
+          // LDS reads and loads first, then the matrix-core block
           __builtin_amdgcn_sched_barrier(0);
           if constexpr (PREC == LRS_FP64_3M) mma_frags_3m<MB, NB>(cur, gr, gi, gx);
           else if constexpr (MODE == 3) mma_frags_re<PREC, MB, NB>(cur, gr);
@@ -975,7 +993,7 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
           if constexpr (PREC == LRS_FP64_3M) mma_frags_3m<MB, NB>(cur, gr, gi, gx);
           else if constexpr (MODE == 3) mma_frags_re<PREC, MB, NB>(cur, gr);
           else mma_frags<PREC, MB, NB>(cur, gr, gi);
-          interleave<PREC, MB, NB, LPW, S, IL == 2>();
+          interleave<PREC, MB, NB, LPW, S, IL == 2, MODE == 3>();
         }
       }
       __builtin_amdgcn_sched_barrier(0);
