@@ -141,8 +141,12 @@ lrs_status lrs_set_orbitals(lrs_ctx* ctx, int nk, int nb, int nocc, int spin_fac
  * are read).  The operands hold two real orbitals per slot, so they take half the memory.
  * lrs_set_sites then requires real psi_site the same way.  lrs_compute_chi0 supports LRS_FP64
  * and LRS_F16F8 on real orbitals (others: LRS_EUNSUPPORTED), every column set and both rules;
- * the W solves are unchanged; lrs_compute_chi0_backward returns LRS_EUNSUPPORTED.  A later
- * lrs_set_orbitals returns the context to complex orbitals. */
+ * the W solves are unchanged.  lrs_compute_chi0_backward runs in LRS_F16F8 only, from the
+ * Green's functions an LRS_F16F8 lrs_compute_chi0 over every site block kept (else
+ * LRS_EUNSUPPORTED); the real parts of dL_dpsi_site are then the gradient with respect to the
+ * real orbitals (the imaginary parts, zero for the static terms, are the derivatives with
+ * respect to imaginary parts of the orbitals).  A later lrs_set_orbitals returns the context to
+ * complex orbitals. */
 lrs_status lrs_set_orbitals_real(lrs_ctx* ctx, int nk, int nb, int nocc, int spin_factor,
                                  const double* energies_host, double mu, double delta,
                                  const void* psi_grid, int ngrid, double grid_dV);

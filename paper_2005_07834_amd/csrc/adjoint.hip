@@ -503,6 +503,12 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
   // split bfloat16 for both reduced precisions, else FP64
   const bool split = prec == LRS_BF16X2 || prec == LRS_F16F8;
   const int gvar = prec == LRS_F16F8 ? 1 : 0;
+  // real orbitals (two per operand slot): the products with psi run over the 2 K_pad orbitals
+  // in their own order, with zero imaginary parts, and H comes from the kept Green's functions
+  const bool real = ctx->real_mode;
+  const int Kb = real ? 2 * ctx->K_pad : ctx->K_pad;
+  const int Kob = real ? 2 * ctx->Ko_pad : ctx->Ko_pad;
+  if (real && !(prec == LRS_F16F8 && ctx->g_keep_prec == LRS_F16F8)) return hipErrorInvalidValue;
   // operands: site rows and site columns of the precision, k-major orbitals (FP64, and split)
   if (ensure_site_tiles_for(ctx, prec) != LRS_OK) return hipErrorOutOfMemory;
   Plan* plan = nullptr;
@@ -511,10 +517,10 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
   // once, dropped with the sites)
   hipError_t e = hipSuccess;
   if (!ctx->psi_kmajor_ok) {
-    e = ensure(ctx, ctx->psi_site_f64, (size_t)2 * ctx->K_pad * ctx->rows_pad * 8);
+    e = ensure(ctx, ctx->psi_site_f64, (size_t)2 * Kb * ctx->rows_pad * 8);
     if (e != hipSuccess) return e;
     e = launch_derive_site_kmajor((const double*)ctx->site_f64.p, ctx->rows_pad, ctx->K_pad,
-                                  (double*)ctx->psi_site_f64.p, st);
+                                  real ? 1 : 0, (double*)ctx->psi_site_f64.p, st);
     if (e != hipSuccess) return e;
     ctx->psi_kmajor_ok = true;
   }
@@ -528,8 +534,8 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
   std::vector<BwdTile> tiles;
   long long tot = 0, ptot = 0;
   int nparts = 0, srows = 0;
-  if (ctx->K_pad % tn) return hipErrorInvalidValue;
-  const int nkt = ctx->K_pad / tn;
+  if (Kb % tn) return hipErrorInvalidValue;
+  const int nkt = Kb / tn;
   for (int s = 0; s < S; ++s) {
     const int n = ctx->site_off[s + 1] - ctx->site_off[s];
     const int np = site_block_ld(n, 1);
@@ -559,7 +565,7 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
     ptot += (long long)np * np;
   }
   const int T = ctx->quad.nterms;
-  const size_t Kp = ctx->K_pad;
+  const size_t Kp = Kb;
   // workspace: lam | H (FP64: hu_re | hu_im | ho_re | ho_im; split: hs_u | hs_o, four bfloat16
   // planes each) over the padded blocks | part | w | dw | tiles | blk_off | pblk_off | blk_n |
   // rowmap (split)
@@ -601,8 +607,11 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
   __bf16* hs_u = split ? (__bf16*)hbuf : nullptr;
   __bf16* hs_o = split ? hs_u + 4 * ptot : nullptr;
 
-  if ((e = hipMemcpyAsync(wn, ctx->quad.w.data(), (size_t)T * Kp * 8, hipMemcpyHostToDevice, st)) ||
-      (e = hipMemcpyAsync(dwn, ctx->quad.dw.data(), (size_t)T * Kp * 8, hipMemcpyHostToDevice, st)) ||
+  const std::vector<double>& wsrc = real ? ctx->quad.w_orb : ctx->quad.w;
+  const std::vector<double>& dwsrc = real ? ctx->quad.dw_orb : ctx->quad.dw;
+  if (wsrc.size() < (size_t)T * Kp || dwsrc.size() < (size_t)T * Kp) return hipErrorInvalidValue;
+  if ((e = hipMemcpyAsync(wn, wsrc.data(), (size_t)T * Kp * 8, hipMemcpyHostToDevice, st)) ||
+      (e = hipMemcpyAsync(dwn, dwsrc.data(), (size_t)T * Kp * 8, hipMemcpyHostToDevice, st)) ||
       (e = hipMemcpyAsync(dtiles, tiles.data(), tiles.size() * sizeof(BwdTile), hipMemcpyHostToDevice, st)) ||
       (e = hipMemcpyAsync(dblk_off, blk_off.data(), S * 8, hipMemcpyHostToDevice, st)) ||
       (e = hipMemcpyAsync(dpblk_off, pblk_off.data(), S * 8, hipMemcpyHostToDevice, st)) ||
@@ -612,7 +621,7 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
     if ((e = hipMemcpyAsync(drowmap, rowmap.data(), rowmap.size() * 4, hipMemcpyHostToDevice, st)))
       return e;
     hipLaunchKernelGGL(split_psi_kernel, dim3(4096), dim3(256), 0, st,
-                       (const double*)ctx->psi_site_f64.p, ctx->rows_pad, ctx->K_pad, drowmap,
+                       (const double*)ctx->psi_site_f64.p, ctx->rows_pad, Kb, drowmap,
                        srows, (__bf16*)ctx->psi_site_bf16.p);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     ctx->psi_split_ok = true;
@@ -633,8 +642,8 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
   B.ho_im = ho_im;
   B.psi = (const double*)ctx->psi_site_f64.p;
   B.rows_pad = ctx->rows_pad;
-  B.K_pad = ctx->K_pad;
-  B.Ko_pad = ctx->Ko_pad;
+  B.K_pad = Kb;
+  B.Ko_pad = Kob;
   B.Ko = ctx->Ko;
   B.Ku = ctx->Ku;
   B.nocc = ctx->nocc;
@@ -657,6 +666,7 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
   // and orbitals; any change of those drops them): H from them instead of recomputing G
   const bool kept = prec == LRS_F16F8 && ctx->g_keep_prec == LRS_F16F8 && ctx->g_keep.p &&
                     ctx->g_keep.bytes >= (size_t)2 * T * tot * 8;
+  if (real && !kept) return hipErrorInvalidValue;    // (the entry point checks this first)
   for (int t = 0; t < T; ++t) {
     if (kept) {
       const char* ko = (const char*)ctx->g_keep.p + (size_t)t * tot * 8;
@@ -692,8 +702,8 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
       hipLaunchKernelGGL(bwd_gemm_kernel, dim3((unsigned)tiles.size()), dim3(256), 0, st, B);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(reduce_energy_kernel, dim3((ctx->K_pad + 255) / 256), dim3(256), 0, st, part,
-                     nparts, ctx->K_pad, ctx->Ko, ctx->Ko_pad, ctx->Ku, ctx->nocc, ctx->nu, ctx->nb,
+  hipLaunchKernelGGL(reduce_energy_kernel, dim3((Kb + 255) / 256), dim3(256), 0, st, part,
+                     nparts, Kb, ctx->Ko, Kob, ctx->Ku, ctx->nocc, ctx->nu, ctx->nb,
                      dL_dE);
   e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(st);   // host tables are freed on return

@@ -243,6 +243,8 @@ lrs_status install_terms(lrs_ctx* ctx, Quad& q, const std::vector<double>& c,
         dw2[(size_t)t * Kp + k] = q.dw[(size_t)t * Kp + K];
         dw2[(size_t)t * Kp + Ks + k] = q.dw[(size_t)t * Kp + K + 16];
       }
+    q.w_orb.swap(q.w);
+    q.dw_orb.swap(q.dw);
     q.w.swap(w2);
     q.dw.swap(dw2);
   }
@@ -546,8 +548,8 @@ lrs_status run_chi0(lrs_ctx* ctx, int site, int cols, int prec, int variant, dou
   void* keep_o = nullptr;
   void* keep_u = nullptr;
   long long keep_stride = 0;
-  if (cols == LRS_COLS_SITE && site < 0 && prec == LRS_F16F8 && !ctx->real_mode &&
-      max_tiles == 0 && !ctx->capturing) {
+  if (cols == LRS_COLS_SITE && site < 0 && prec == LRS_F16F8 && max_tiles == 0 &&
+      !ctx->capturing) {
     for (int s = 0; s < ctx->nsites; ++s) {
       const long long n = ctx->site_off[s + 1] - ctx->site_off[s];
       keep_stride += n * n;
@@ -1272,7 +1274,10 @@ lrs_status lrs_compute_chi0_backward(lrs_ctx* ctx, int cols, int prec, const dou
     return fail(ctx, LRS_EUNSUPPORTED, "backward precision must be LRS_FP64, LRS_BF16X2 or "
                 "LRS_F16F8");
   if (dL_dpsi_grid) return fail(ctx, LRS_EUNSUPPORTED, "site blocks do not depend on grid orbitals");
-  if (ctx->real_mode) return fail(ctx, LRS_EUNSUPPORTED, "no adjoint for real orbitals");
+  if (ctx->real_mode && (prec != LRS_F16F8 || ctx->g_keep_prec != LRS_F16F8))
+    return fail(ctx, LRS_EUNSUPPORTED, "real orbitals: the adjoint runs in LRS_F16F8 from the "
+                "Green's functions an LRS_F16F8 chi0 call over every site block keeps (none kept "
+                "for the current terms)");
   if (!dL_dchi0 || !dL_dE || !dL_dpsi_site) return fail(ctx, LRS_EINVAL, "missing gradient buffers");
   if (!ctx->quad.has_deriv) return fail(ctx, LRS_EUNSUPPORTED, "generic terms carry no energy derivative");
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));

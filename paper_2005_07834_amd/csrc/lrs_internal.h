@@ -134,6 +134,8 @@ struct Quad {
   std::vector<double> tau;      // tau (time) or t (freq) per term
   std::vector<double> w;        // [T][K_pad] normalised alpha | beta (zero padded)
   std::vector<double> dw;       // [T][K_pad] d(weight)/d(energy) with mu fixed
+  // real orbitals: w and dw hold the slot layout; these the orbital order [T][2 K_pad]
+  std::vector<double> w_orb, dw_orb;
   bool has_deriv = false;
 };
 
@@ -242,8 +244,11 @@ hipError_t launch_pack_site_rows(const double* psi, int nk, int nb, int nocc, in
 // largest |Im psi| over n complex values, as float bits (0 if all vanish)
 hipError_t launch_max_abs_im(const double* psi, long long n, unsigned int* out_bits,
                              hipStream_t s);
-hipError_t launch_derive_site_kmajor(const double* site_f64, int rows_pad, int K_pad, double* out,
-                                     hipStream_t s);
+// planar [2][K][rows_pad] site orbitals in natural K order from the FP64 row operand; real: the
+// operand holds two real orbitals per slot, and out gets the 2 K_pad orbitals with zero
+// imaginary parts
+hipError_t launch_derive_site_kmajor(const double* site_f64, int rows_pad, int K_pad, int real,
+                                     double* out, hipStream_t s);
 hipError_t launch_site_col_tiles(const double* site_f64, int rows_pad, int K_pad, int ncols_pad,
                                  const int* colmap, int prec, float prescale, void* dst,
                                  hipStream_t s);

@@ -16,9 +16,9 @@ namespace {
 struct SrcPsi {           // complex128 [nk][nb][ld] orbitals on a point set
   const double* psi;
   int nb, nocc, nu, ncols, ld, Ko, Ko_pad, Ku;
-  // real orbitals (one k): slot k of a 16-slot chunk c holds orbital K = 32 c + k%16 as its
-  // re value and K + 16 as its im value, each orbital's real part (Ko_pad then counts
-  // orbitals, twice the slots)
+  // real orbitals: slot k of a 16-slot chunk c holds orbital K = 32 c + k%16 as its re value
+  // and K + 16 as its im value, each orbital's real part (Ko_pad then counts orbitals, twice
+  // the slots)
   int real;
   __device__ const double* at(int c, int k) const {   // orbital k's value at c, or null
     int kp, band;
@@ -224,6 +224,19 @@ __global__ void derive_site_kmajor_kernel(SrcSite64 src, double* out) {
   out[n + gid] = im;
 }
 
+// real orbitals: orbital K (of 2 K_pad) is component (K / 16) % 2 of slot 16 (K / 32) + K % 16
+__global__ void derive_site_kmajor_real_kernel(SrcSite64 src, double* out) {
+  long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long n = 2LL * src.rows_pad * src.K_pad;
+  if (gid >= n) return;
+  int K = (int)(gid / src.rows_pad);
+  int r = (int)(gid - (long long)K * src.rows_pad);
+  double re, im;
+  src.get(r, 16 * (K >> 5) + (K & 15), re, im);
+  out[gid] = (K >> 4) & 1 ? im : re;
+  out[n + gid] = 0.0;
+}
+
 // largest |Im| of n complex values (the odd doubles)
 __global__ void max_abs_im_kernel(const double* x, long long n, unsigned int* out_bits) {
   float m = 0.f;
@@ -296,12 +309,16 @@ hipError_t launch_pack_site_rows(const double* psi, int nk, int nb, int nocc, in
   return hipGetLastError();
 }
 
-hipError_t launch_derive_site_kmajor(const double* site_f64, int rows_pad, int K_pad, double* out,
-                                     hipStream_t s) {
+hipError_t launch_derive_site_kmajor(const double* site_f64, int rows_pad, int K_pad, int real,
+                                     double* out, hipStream_t s) {
   SrcSite64 src{site_f64, rows_pad, K_pad, nullptr};
-  long long n = (long long)rows_pad * K_pad;
-  hipLaunchKernelGGL(derive_site_kmajor_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, src,
-                     out);
+  long long n = (long long)rows_pad * K_pad * (real ? 2 : 1);
+  if (real)
+    hipLaunchKernelGGL(derive_site_kmajor_real_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s,
+                       src, out);
+  else
+    hipLaunchKernelGGL(derive_site_kmajor_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, src,
+                       out);
   return hipGetLastError();
 }
 

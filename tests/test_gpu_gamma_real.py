@@ -14,6 +14,7 @@ import pytest
 import torch
 
 from oracle import chi0 as cz
+from oracle import grads as gr
 from oracle import quadrature as q
 from tests.conftest import workload
 from workloads.realify import realify
@@ -117,6 +118,39 @@ def test_real_orbitals_tiny(P, tiny_real):
     ctx.close()
 
 
+def test_real_orbitals_adjoint_tiny(P, tiny_real):
+    """The adjoint with real orbitals (tiny workload, Gamma): dL/dE and dL/dpsi of the
+    test-charge loss from the F16F8 path, which takes its Green's functions from the forward
+    site-block call, against the oracle's gradient on the same real orbitals (whose imaginary
+    parts vanish, as the library's do); refused before any Green's functions were kept."""
+    T = tiny_real
+    w = T["w"]
+    n = w.n_terms
+    s = oracle_scale(w.energies, w.nocc, n)
+    ctx = P.Context(0)
+    ctx.set_orbitals_real(T["E"], w.nocc, T["g"], w.grid_dV)
+    ctx.set_sites(w.sites, T["s"][None])
+    ctx.make_quadrature(P.QUAD_TIME, n, s)
+    with pytest.raises(P.LrsError) as e:
+        ctx.chi0_backward(torch.zeros(w.nrows ** 2, dtype=torch.float64, device="cuda"),
+                          P.F16F8)
+    assert e.value.status == P.LRS_EUNSUPPORTED
+    chi = ctx.chi0(-1, P.COLS_SITE, P.F16F8)
+    ctx.screen_W(chi, rho=torch.as_tensor(w.rho_test, device="cuda"), want_loss=True)
+    lam = ctx.screen_W_backward()
+    dE, dpsi = ctx.chi0_backward(lam, P.F16F8)
+    sr = T["s"].cpu().numpy()[None].astype(np.complex128)
+    _, dE_ref, dp_ref = gr.loss_and_grads(sr, w.energies, w.nocc, 2, w.sites, w.rho_test,
+                                          "time", n, s)
+    eE = rel(dE.cpu().numpy(), dE_ref)
+    ep = rel(dpsi.real.cpu().numpy(), dp_ref.real)
+    say(f"real-orbital adjoint (f16f8): dE {eE:.2e} dpsi {ep:.2e} vs oracle; max |Im| "
+        f"{float(dpsi.imag.abs().max()):.1e} (oracle {np.abs(dp_ref.imag).max():.1e})")
+    assert eE < 1e-4 and ep < 1e-4
+    assert float(dpsi.imag.abs().max()) == 0.0 and np.abs(dp_ref.imag).max() == 0.0
+    ctx.close()
+
+
 def test_real_orbitals_precision_gamma(P):
     """Precision workload at Gamma (2304 bands, 3520 site rows x 110,592 grid columns, 32
     terms): the site x grid launch from real orbitals in FP64 and F16F8, sampled against the
@@ -186,6 +220,10 @@ def test_real_orbitals_many_k(P):
     c2.make_quadrature(P.QUAD_TIME, n, scale)
     cplx = c2.chi0(-1, P.COLS_GRID, P.FP64).cpu().numpy()
     cplx_s = c2.chi0(-1, P.COLS_SITE, P.FP64).cpu().numpy()
+    # the adjoint on a seeded dL/dchi0: complex path (F16F8) on the same orbitals
+    lam = torch.as_tensor(np.random.default_rng(6).standard_normal(cplx_s.size), device="cuda")
+    c2.chi0(-1, P.COLS_SITE, P.F16F8)
+    dE_c, dp_c = c2.chi0_backward(lam, P.F16F8)
     c2.close()
     rng = np.random.default_rng(5)
     rows = rng.integers(0, w.nrows, 40)
@@ -212,4 +250,11 @@ def test_real_orbitals_many_k(P):
             ecs = rel(ctx.chi0(-1, P.COLS_SITE, prec).cpu().numpy(), cplx_s)
             say(f"  8 k real vs complex path: grid {ec:.2e} site {ecs:.2e}")
             assert ec < 1e-12 and ecs < 1e-12
+    # (the last forward call above is the F16F8 site-block one, so its Green's functions are
+    # kept) the real-orbital adjoint against the complex path's
+    dE_r, dp_r = ctx.chi0_backward(lam, P.F16F8)
+    eE = rel(dE_r.cpu().numpy(), dE_c.cpu().numpy())
+    ep = rel(dp_r.real.cpu().numpy(), dp_c.real.cpu().numpy())
+    say(f"  8 k real-orbital adjoint vs complex path: dE {eE:.2e} dpsi {ep:.2e}")
+    assert eE < 1e-4 and ep < 1e-4
     ctx.close()
