@@ -1457,7 +1457,7 @@ namespace {
 // same arithmetic and values as the mode-2 epilogue.  One workgroup per operand-tile piece (32
 // block rows p x 16 block columns r, four planes of 512 values), element e of each plane at
 // p = 32 (piece row) + (e / 8) % 32, r = 16 (piece column) + 8 (e / 256) + e % 8, so each wave
-// writes whole runs of a plane.  G, lam and lam_a are kept on and above the diagonal only:
+// writes whole runs of a plane.  G is kept on and above the diagonal only; H is Hermitian, so
 // below it H(p, r) = conj(H(r, p)), formed from the transposed element.
 __global__ __launch_bounds__(512) void h_from_kept_kernel(
     const float2* keep_o, const float2* keep_u, const long long* blk_off,

@@ -248,7 +248,8 @@ lrs_status install_terms(lrs_ctx* ctx, Quad& q, const std::vector<double>& c,
     q.w.swap(w2);
     q.dw.swap(dw2);
   }
-  // device copies: weights in natural K order (FP64) and the coefficients
+  // device copies: weights in natural K order (real orbitals: the slot layout above; FP64) and
+  // the coefficients
   CHECK(ensure_buf(ctx, ctx->w_nat, q.w.size() * 8, "weights"));
   CHECK(ensure_buf(ctx, ctx->c_dev, (size_t)2 * T * 8, "term coefficients"));
   HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->w_nat.p, q.w.data(), q.w.size() * 8,
