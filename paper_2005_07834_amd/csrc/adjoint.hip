@@ -662,10 +662,11 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
   B.per = (B.ntiles + 7) / 8;
   const int chunk = chunk_of(prec);
   const double g_scale = is_f16(prec) ? (double)ctx->site_scale_f16 * ctx->site_scale_f16 : 1.0;
-  // the Green's functions an F16F8 launch over every site block kept (same quadrature, sites
-  // and orbitals; any change of those drops them): H from them instead of recomputing G
-  const bool kept = prec == LRS_F16F8 && ctx->g_keep_prec == LRS_F16F8 && ctx->g_keep.p &&
-                    ctx->g_keep.bytes >= (size_t)2 * T * tot * 8;
+  // the Green's functions an F16F8 or BF16X2 launch over every site block kept (same
+  // quadrature, sites and orbitals; any change of those drops them): H from them instead of
+  // recomputing G
+  const bool kept = (prec == LRS_F16F8 || prec == LRS_BF16X2) && ctx->g_keep_prec == prec &&
+                    ctx->g_keep.p && ctx->g_keep.bytes >= (size_t)2 * T * tot * 8;
   if (real && !kept) return hipErrorInvalidValue;    // (the entry point checks this first)
   for (int t = 0; t < T; ++t) {
     if (kept) {

@@ -1273,6 +1273,16 @@ TileShape shape_p(int v) {
   }
 }
 
+template <int PREC>
+bool rot_p(int v) {
+  switch (v) {
+    case 0: return Variant<PREC, 0>::ROT != 0;
+    case 1: return Variant<PREC, 1>::ROT != 0;
+    case 2: return Variant<PREC, 2>::ROT != 0;
+    default: return Variant<PREC, 3>::ROT != 0;
+  }
+}
+
 template <int PREC, int V>
 int occ_v() {
   using Vt = Variant<PREC, V>;
@@ -1328,6 +1338,14 @@ int chi0_blocks_per_cu(int prec, int variant) {
     case LRS_F16F8: return occ_p<LRS_F16F8>(variant);
     case LRS_FP64_3M: return occ_p<LRS_FP64_3M>(variant);
     default: return occ_p<LRS_FP16X2>(variant);
+  }
+}
+
+bool chi0_variant_rotates(int prec, int variant) {
+  switch (prec) {
+    case LRS_BF16X2: return rot_p<LRS_BF16X2>(variant);
+    case LRS_FP16X2: return rot_p<LRS_FP16X2>(variant);
+    default: return false;
   }
 }
 

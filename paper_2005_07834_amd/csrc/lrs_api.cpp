@@ -544,13 +544,15 @@ lrs_status run_chi0(lrs_ctx* ctx, int site, int cols, int prec, int variant, dou
   const double g_scale = a_scale * bscale;   // each G carries a_scale * b_scale
   pref /= g_scale * g_scale;
   const int T = ctx->quad.nterms;
-  // an F16F8 launch over every site block keeps each term's Green's functions for the adjoint
-  // (which would otherwise recompute them) when they fit in kKeepMaxBytes
+  // an F16F8 or BF16X2 launch over every site block keeps each term's Green's functions for
+  // the adjoint (which would otherwise recompute them) when they fit in kKeepMaxBytes; the
+  // adjoint's own launch would form them in the same order (not so a rotating-B variant's)
   void* keep_o = nullptr;
   void* keep_u = nullptr;
   long long keep_stride = 0;
-  if (cols == LRS_COLS_SITE && site < 0 && prec == LRS_F16F8 && max_tiles == 0 &&
-      !ctx->capturing) {
+  const bool keeps = prec == LRS_F16F8 ||
+                     (prec == LRS_BF16X2 && !chi0_variant_rotates(prec, variant));
+  if (cols == LRS_COLS_SITE && site < 0 && keeps && max_tiles == 0 && !ctx->capturing) {
     for (int s = 0; s < ctx->nsites; ++s) {
       const long long n = ctx->site_off[s + 1] - ctx->site_off[s];
       keep_stride += n * n;

@@ -26,7 +26,7 @@ constexpr int kMaxTileCols = 256;
 // each K phase (occupied, unoccupied) is padded to this: a multiple of four chunks of every
 // precision, so the kernel's four-slot LDS ring starts every phase at slot 0
 constexpr int kPhaseAlign = 128;
-// largest set of Green's functions an F16F8 site-block launch keeps for the adjoint
+// largest set of Green's functions an F16F8 or BF16X2 site-block launch keeps for the adjoint
 constexpr size_t kKeepMaxBytes = (size_t)16 << 30;
 constexpr int kMaxTerms = 128;
 
@@ -180,9 +180,9 @@ struct lrs_ctx {
   lrs::DevBuf site_tiles[lrs::kNumPrec];   // site points as a column operand (fragment tiles)
   lrs::DevBuf a_tiles;            // weighted site operand tiles of the current batch
   lrs::DevBuf park;               // per-workgroup G_o scratch of the chi0 launches
-  // Green's functions of every term on the site blocks, kept by an F16F8 chi0 launch over all
-  // sites for the adjoint (G_o then G_u, FP32 complex [T][sum n^2] each); g_keep_prec is the
-  // precision they hold, -1 when they are absent or stale
+  // Green's functions of every term on the site blocks, kept by an F16F8 or BF16X2 chi0 launch
+  // over all sites for the adjoint (G_o then G_u, FP32 complex [T][sum n^2] each); g_keep_prec
+  // is the precision they hold, -1 when they are absent or stale
   lrs::DevBuf g_keep;
   int g_keep_prec = -1;
   lrs::DevBuf xcd_sync;           // per-XCD term counters of the chi0 launches
@@ -262,6 +262,9 @@ int chi0_num_variants(int prec);
 int chi0_blocks_per_cu(int prec, int variant);
 int chi0_default_variant(int prec);
 TileShape chi0_shape(int prec, int variant);
+// the variant keeps its B fragments rotating through registers (split paths): its products
+// reach each element in another order than the other variants'
+bool chi0_variant_rotates(int prec, int variant);
 // w: weights [T][w_stride]; a slot's im-plane value takes the weight at q_woff + k (0 for
 // complex orbitals; K_pad for real orbitals, whose second orbital of a slot has its own)
 hipError_t launch_prep_site(int prec, const double* site, int rows_pad, int K_pad,

@@ -256,8 +256,9 @@ def test_split_adjoint_matches_fp64(P):
     ctx.close()
 
 
-def test_kept_green_functions_match_recompute(P):
-    """The F16F8 adjoint built from the Green's functions that the forward site-block launch
+@pytest.mark.parametrize("prec", ["f16f8", "bf16x2"])
+def test_kept_green_functions_match_recompute(P, prec):
+    """The split adjoint built from the Green's functions that the forward site-block launch
     keeps equals, bit for bit, the adjoint that recomputes them (differentiation workload, 4
     sites of 800 points; the static rule and chi0 at imaginary frequency); a new quadrature
     drops the kept ones, so the second call recomputes."""
@@ -271,11 +272,11 @@ def test_kept_green_functions_match_recompute(P):
              ("i omega", lambda: ctx.make_quadrature_iw(n, 0.0, 0.3)))
     for name, rule in rules:
         rule()
-        ctx.chi0(-1, P.COLS_SITE, P.F16F8)           # keeps every term's G_o, G_u
-        dE1, dp1 = ctx.chi0_backward(lam, P.F16F8)
+        ctx.chi0(-1, P.COLS_SITE, prec)               # keeps every term's G_o, G_u
+        dE1, dp1 = ctx.chi0_backward(lam, prec)
         rule()                                        # drops them
-        dE2, dp2 = ctx.chi0_backward(lam, P.F16F8)    # recomputes them
-        say(f"kept vs recomputed Green's functions ({name}): dE equal "
+        dE2, dp2 = ctx.chi0_backward(lam, prec)       # recomputes them
+        say(f"kept vs recomputed Green's functions ({prec}, {name}): dE equal "
             f"{torch.equal(dE1, dE2)}, dpsi equal {torch.equal(dp1, dp2)}")
         assert torch.equal(dE1, dE2) and torch.equal(dp1, dp2)
     ctx.close()
