@@ -370,6 +370,17 @@ def main():
         dE64, dpsi64 = ctx.chi0_backward(lam, "fp64")
         torch.cuda.synchronize()
         adjoint["fp64_call_ms"] = (time.time() - ta) * 1e3
+        # the FP64 adjoint again after an FP64 site-block call, from the Green's functions it
+        # kept (bit for bit the same gradients)
+        ctx.chi0(-1, P.COLS_SITE, "fp64")
+        torch.cuda.synchronize()
+        ta = time.time()
+        dE64k, dpsi64k = ctx.chi0_backward(lam, "fp64")
+        torch.cuda.synchronize()
+        adjoint["fp64_kept_call_ms"] = (time.time() - ta) * 1e3
+        adjoint["fp64_kept_bitwise_equal"] = bool(torch.equal(dE64k, dE64) and
+                                                  torch.equal(dpsi64k, dpsi64))
+        del dE64k, dpsi64k
         adjoint["dE_rel_vs_fp64"] = float((dE - dE64).abs().max() / dE64.abs().max())
         adjoint["dpsi_rel_vs_fp64"] = float((dpsi - dpsi64).abs().max() / dpsi64.abs().max())
         del dE64, dpsi64

@@ -391,12 +391,12 @@ lrs_status lrs_screen_W_backward(lrs_ctx* ctx, const double* dL_dW, double* dL_d
  * FP32 accumulation; relative error of order 1e-5), with the gradient accumulation in FP64;
  * LRS_F16F8 recomputes G as the forward F16F8 path does (and so reads the site operand a
  * forward F16F8 call prepared) and forms the products with psi as LRS_BF16X2 does.  An
- * LRS_F16F8 or LRS_BF16X2 lrs_compute_chi0 over every site block (site -1, LRS_COLS_SITE;
- * BF16X2: a tuned variant without rotating B fragments) keeps each term's G_o and G_u instead
- * (FP32 complex, 16 * nterms * sum n^2 bytes, when that is at most 16 GiB and within
- * LRS_MAX_BYTES; not under stream capture); backward calls in the same precision then form H
- * from them, bit for bit as from recomputed ones, until new orbitals, sites or terms drop
- * them.
+ * LRS_F16F8, LRS_BF16X2 or LRS_FP64 lrs_compute_chi0 over every site block (site -1,
+ * LRS_COLS_SITE; BF16X2: a tuned variant without rotating B fragments) keeps each term's G_o
+ * and G_u instead (FP32 complex, FP64 for LRS_FP64: 16 or 32 * nterms * sum n^2 bytes, when
+ * that is at most 16 GiB and within LRS_MAX_BYTES; not under stream capture); backward calls
+ * in the same precision then form H from them, bit for bit as from recomputed ones, until new
+ * orbitals, sites or terms drop them.
  * Other precisions: LRS_EUNSUPPORTED.  Requires terms from lrs_make_quadrature or
  * lrs_make_quadrature_iw (generic terms carry no energy derivative: LRS_EUNSUPPORTED).  With
  * the imaginary-frequency terms dL/dchi0 may be any real matrix per block; with the static

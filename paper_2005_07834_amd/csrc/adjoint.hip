@@ -665,16 +665,22 @@ hipError_t launch_chi0_backward(lrs_ctx* ctx, int prec, const double* dL_dchi0, 
   // the Green's functions an F16F8 or BF16X2 launch over every site block kept (same
   // quadrature, sites and orbitals; any change of those drops them): H from them instead of
   // recomputing G
-  const bool kept = (prec == LRS_F16F8 || prec == LRS_BF16X2) && ctx->g_keep_prec == prec &&
-                    ctx->g_keep.p && ctx->g_keep.bytes >= (size_t)2 * T * tot * 8;
+  const size_t kelem = prec == LRS_FP64 ? 16 : 8;
+  const bool kept = (prec == LRS_F16F8 || prec == LRS_BF16X2 || prec == LRS_FP64) &&
+                    ctx->g_keep_prec == prec && ctx->g_keep.p &&
+                    ctx->g_keep.bytes >= (size_t)2 * T * tot * kelem;
   if (real && !kept) return hipErrorInvalidValue;    // (the entry point checks this first)
   for (int t = 0; t < T; ++t) {
     if (kept) {
-      const char* ko = (const char*)ctx->g_keep.p + (size_t)t * tot * 8;
-      e = launch_h_from_kept(ko, ko + (size_t)T * tot * 8, S, dblk_off, dpblk_off, dblk_n,
-                             blk_n.data(), lam,
-                             lam_a, odd ? ctx->quad.c[t] : 0.0, odd ? ctx->quad.ci[t] : 0.0,
-                             hs_u, hs_o, st);
+      const char* ko = (const char*)ctx->g_keep.p + (size_t)t * tot * kelem;
+      const char* ku = ko + (size_t)T * tot * kelem;
+      const double ac = odd ? ctx->quad.c[t] : 0.0, as = odd ? ctx->quad.ci[t] : 0.0;
+      if (split)
+        e = launch_h_from_kept(ko, ku, S, dblk_off, dpblk_off, dblk_n, blk_n.data(), lam, lam_a,
+                               ac, as, hs_u, hs_o, st);
+      else
+        e = launch_h_from_kept_f64(ko, ku, S, dblk_off, dpblk_off, dblk_n, lam, lam_a, ac, as,
+                                   hu_re, hu_im, ho_re, ho_im, st);
       if (e != hipSuccess) return e;
     }
     for (const Batch& bt : plan->batches) {

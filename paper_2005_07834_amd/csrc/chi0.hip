@@ -74,10 +74,11 @@ struct Chi0Params {
   double* ho_im;
   __bf16* hs_u;
   __bf16* hs_o;
-  // mode 0 on site blocks: keep each term's G_o and G_u (FP32 complex, the output's element
-  // offsets, term stride keep_stride) on and above the diagonal for the adjoint, or null
-  float2* keep_o;
-  float2* keep_u;
+  // mode 0 on site blocks: keep each term's G_o and G_u (complex: FP64 for the FP64 path, else
+  // FP32; the output's element offsets, term stride keep_stride) on and above the diagonal for
+  // the adjoint, or null
+  void* keep_o;
+  void* keep_u;
   long long keep_stride;
 };
 
@@ -1163,8 +1164,15 @@ __global__ __launch_bounds__(WMW * WNW * 64) void chi0_kernel(Chi0Params P) {
 #pragma unroll
               for (int e = 0; e < ELEMS; ++e)
                 if (in[e] && dg[e] >= 0) {
-                  P.keep_o[kb + off[e]] = float2{(float)or_[e], (float)oi_[e]};
-                  P.keep_u[kb + off[e]] = float2{(float)gr[i][j][e], (float)gi[i][j][e]};
+                  if constexpr (PREC == LRS_FP64 || PREC == LRS_FP64_3M) {
+                    ((double2*)P.keep_o)[kb + off[e]] = double2{(double)or_[e], (double)oi_[e]};
+                    ((double2*)P.keep_u)[kb + off[e]] =
+                        double2{(double)gr[i][j][e], (double)gi[i][j][e]};
+                  } else {
+                    ((float2*)P.keep_o)[kb + off[e]] = float2{(float)or_[e], (float)oi_[e]};
+                    ((float2*)P.keep_u)[kb + off[e]] =
+                        float2{(float)gr[i][j][e], (float)gi[i][j][e]};
+                  }
                 }
             }
           }
@@ -1385,8 +1393,8 @@ hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int
                        int real, void* keep_o, void* keep_u, long long keep_stride,
                        hipStream_t s) {
   Chi0Params P;
-  P.keep_o = (float2*)keep_o;
-  P.keep_u = (float2*)keep_u;
+  P.keep_o = keep_o;
+  P.keep_u = keep_u;
   P.keep_stride = keep_stride;
   P.ci = ci;
   P.sym = sym;
@@ -1532,6 +1540,61 @@ hipError_t launch_h_from_kept(const void* keep_o, const void* keep_u, int nsites
   hipLaunchKernelGGL(h_from_kept_kernel, dim3(pieces, nsites), dim3(512), 0, s,
                      (const float2*)keep_o, (const float2*)keep_u, blk_off, pblk_off, blk_n, lam,
                      lam_a, adj_c, adj_s, (__bf16*)hs_u, (__bf16*)hs_o);
+  return hipGetLastError();
+}
+
+namespace {
+// The FP64 adjoint's H planes (hu_re, hu_im, ho_re, ho_im, each site block row-major with the
+// padded row stride) from one term's kept FP64 Green's functions, the same values as the
+// mode-1 epilogue: one thread per block element, the element on or above the diagonal from
+// the kept G, the one below as the conjugate of its transpose (H is Hermitian).
+__global__ __launch_bounds__(256) void h_from_kept_f64_kernel(
+    const double2* keep_o, const double2* keep_u, const long long* blk_off,
+    const long long* pblk_off, const int* blk_n, const double* lam, const double* lam_a,
+    double adj_c, double adj_s, double* hu_re, double* hu_im, double* ho_re, double* ho_im) {
+  const int st = blockIdx.y;
+  const int n = blk_n[st];
+  const int np = site_block_ld(n, 1);
+  const long long nn = (long long)n * n;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < nn;
+       q += (long long)gridDim.x * blockDim.x) {
+    const int p = (int)(q / n), r = (int)(q - (long long)p * n);
+    const bool up = r >= p;
+    const int a = up ? p : r, b = up ? r : p;
+    const long long kk = blk_off[st] + (long long)a * n + b;
+    const long long lk = pblk_off[st] + (long long)a * np + b;
+    const double2 go = keep_o[kk], gu = keep_u[kk];
+    const double l = lam[lk];
+    double hur = l * gu.x, hui = -l * gu.y;
+    double hor = l * go.x, hoi = -l * go.y;
+    if (lam_a) {
+      const double ac = adj_c * l, bs = adj_s * lam_a[lk];
+      hur = ac * gu.x + bs * gu.y;
+      hui = bs * gu.x - ac * gu.y;
+      hor = ac * go.x - bs * go.y;
+      hoi = -bs * go.x - ac * go.y;
+    }
+    if (!up) {
+      hui = -hui;
+      hoi = -hoi;
+    }
+    const long long o = pblk_off[st] + (long long)p * np + r;
+    hu_re[o] = hur;
+    hu_im[o] = hui;
+    ho_re[o] = hor;
+    ho_im[o] = hoi;
+  }
+}
+}  // namespace
+
+hipError_t launch_h_from_kept_f64(const void* keep_o, const void* keep_u, int nsites,
+                                  const long long* blk_off, const long long* pblk_off,
+                                  const int* blk_n, const double* lam, const double* lam_a,
+                                  double adj_c, double adj_s, double* hu_re, double* hu_im,
+                                  double* ho_re, double* ho_im, hipStream_t s) {
+  hipLaunchKernelGGL(h_from_kept_f64_kernel, dim3(4096, nsites), dim3(256), 0, s,
+                     (const double2*)keep_o, (const double2*)keep_u, blk_off, pblk_off, blk_n,
+                     lam, lam_a, adj_c, adj_s, hu_re, hu_im, ho_re, ho_im);
   return hipGetLastError();
 }
 

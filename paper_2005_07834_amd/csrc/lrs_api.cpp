@@ -544,24 +544,25 @@ lrs_status run_chi0(lrs_ctx* ctx, int site, int cols, int prec, int variant, dou
   const double g_scale = a_scale * bscale;   // each G carries a_scale * b_scale
   pref /= g_scale * g_scale;
   const int T = ctx->quad.nterms;
-  // an F16F8 or BF16X2 launch over every site block keeps each term's Green's functions for
-  // the adjoint (which would otherwise recompute them) when they fit in kKeepMaxBytes; the
+  // an F16F8, BF16X2 or FP64 launch over every site block keeps each term's Green's functions
+  // for the adjoint (which would otherwise recompute them) when they fit in kKeepMaxBytes; the
   // adjoint's own launch would form them in the same order (not so a rotating-B variant's)
   void* keep_o = nullptr;
   void* keep_u = nullptr;
   long long keep_stride = 0;
-  const bool keeps = prec == LRS_F16F8 ||
+  const bool keeps = prec == LRS_F16F8 || prec == LRS_FP64 ||
                      (prec == LRS_BF16X2 && !chi0_variant_rotates(prec, variant));
+  const size_t keep_elem = prec == LRS_FP64 ? 16 : 8;
   if (cols == LRS_COLS_SITE && site < 0 && keeps && max_tiles == 0 && !ctx->capturing) {
     for (int s = 0; s < ctx->nsites; ++s) {
       const long long n = ctx->site_off[s + 1] - ctx->site_off[s];
       keep_stride += n * n;
     }
-    const size_t bytes = (size_t)2 * T * keep_stride * 8;
+    const size_t bytes = (size_t)2 * T * keep_stride * keep_elem;
     ctx->g_keep_prec = -1;
     if (bytes <= kKeepMaxBytes && ensure_buf(ctx, ctx->g_keep, bytes, "kept G") == LRS_OK) {
       keep_o = ctx->g_keep.p;
-      keep_u = (char*)ctx->g_keep.p + (size_t)T * keep_stride * 8;
+      keep_u = (char*)ctx->g_keep.p + (size_t)T * keep_stride * keep_elem;
     } else {
       ctx->err.clear();     // (not kept: the adjoint recomputes them)
     }

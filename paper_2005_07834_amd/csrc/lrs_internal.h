@@ -26,7 +26,8 @@ constexpr int kMaxTileCols = 256;
 // each K phase (occupied, unoccupied) is padded to this: a multiple of four chunks of every
 // precision, so the kernel's four-slot LDS ring starts every phase at slot 0
 constexpr int kPhaseAlign = 128;
-// largest set of Green's functions an F16F8 or BF16X2 site-block launch keeps for the adjoint
+// largest set of Green's functions an F16F8, BF16X2 or FP64 site-block launch keeps for the
+// adjoint
 constexpr size_t kKeepMaxBytes = (size_t)16 << 30;
 constexpr int kMaxTerms = 128;
 
@@ -180,9 +181,9 @@ struct lrs_ctx {
   lrs::DevBuf site_tiles[lrs::kNumPrec];   // site points as a column operand (fragment tiles)
   lrs::DevBuf a_tiles;            // weighted site operand tiles of the current batch
   lrs::DevBuf park;               // per-workgroup G_o scratch of the chi0 launches
-  // Green's functions of every term on the site blocks, kept by an F16F8 or BF16X2 chi0 launch
-  // over all sites for the adjoint (G_o then G_u, FP32 complex [T][sum n^2] each); g_keep_prec
-  // is the precision they hold, -1 when they are absent or stale
+  // Green's functions of every term on the site blocks, kept by an F16F8, BF16X2 or FP64 chi0
+  // launch over all sites for the adjoint (G_o then G_u, complex [T][sum n^2] each: FP64 for
+  // the FP64 path, else FP32); g_keep_prec is the precision they hold, -1 when absent or stale
   lrs::DevBuf g_keep;
   int g_keep_prec = -1;
   lrs::DevBuf xcd_sync;           // per-XCD term counters of the chi0 launches
@@ -276,8 +277,9 @@ hipError_t launch_prep_site(int prec, const double* site, int rows_pad, int K_pa
 // ci: imaginary parts of the term coefficients (null: real); sym must be 0 then (the odd
 // part of chi0 at imaginary frequency is antisymmetric on a site block)
 // real: the operands hold real orbitals two to a slot (FP64 and F16F8 only)
-// keep_o, keep_u (site blocks, or null): each term's G_o and G_u as FP32 complex at the
-// output's element offsets plus t * keep_stride, on and above the diagonal
+// keep_o, keep_u (site blocks, or null): each term's G_o and G_u as complex (FP64 for the FP64
+// paths, else FP32) at the output's element offsets plus t * keep_stride, on and above the
+// diagonal
 hipError_t launch_chi0(int prec, int variant, int grid, const void* a_tiles, int a_nrb,
                        const void* b_tiles, int b_ncb, int nch, const double* c,
                        const double* ci, int T, int nch_o, const TileDesc* tiles, int ntiles,
@@ -297,6 +299,13 @@ hipError_t launch_green_adjoint(int prec, int grid, const void* a_tiles, int a_n
 // the same split H (hs_u, hs_o) of one term from its kept G_o, G_u (keep_o, keep_u at the
 // caller's site-block offsets blk_off; lam, lam_a and H at the padded offsets pblk_off;
 // blk_n on the device, blk_n_host its host copy)
+// the FP64 H planes (hu_re, hu_im, ho_re, ho_im, padded row stride) of one term from its kept
+// FP64 G_o, G_u, as the mode-1 epilogue writes them
+hipError_t launch_h_from_kept_f64(const void* keep_o, const void* keep_u, int nsites,
+                                  const long long* blk_off, const long long* pblk_off,
+                                  const int* blk_n, const double* lam, const double* lam_a,
+                                  double adj_c, double adj_s, double* hu_re, double* hu_im,
+                                  double* ho_re, double* ho_im, hipStream_t s);
 hipError_t launch_h_from_kept(const void* keep_o, const void* keep_u, int nsites,
                               const long long* blk_off, const long long* pblk_off,
                               const int* blk_n, const int* blk_n_host, const double* lam,

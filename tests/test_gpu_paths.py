@@ -256,9 +256,9 @@ def test_split_adjoint_matches_fp64(P):
     ctx.close()
 
 
-@pytest.mark.parametrize("prec", ["f16f8", "bf16x2"])
+@pytest.mark.parametrize("prec", ["f16f8", "bf16x2", "fp64"])
 def test_kept_green_functions_match_recompute(P, prec):
-    """The split adjoint built from the Green's functions that the forward site-block launch
+    """The adjoint built from the Green's functions that the forward site-block launch
     keeps equals, bit for bit, the adjoint that recomputes them (differentiation workload, 4
     sites of 800 points; the static rule and chi0 at imaginary frequency); a new quadrature
     drops the kept ones, so the second call recomputes."""
